@@ -1,0 +1,212 @@
+/*
+ * phoebe_gpu.h -- C ABI of the MI355X (gfx950) electron-phonon interpolation
+ * and scattering-rate library.
+ *
+ * The operations follow the Phoebe paper (arXiv:2111.14999):
+ *   - electron bands by Wannier interpolation: H^W(k) = sum_R e^{ik.R} H(R)
+ *     and its diagonalisation U_k^dagger H^W(k) U_k = diag(eps_k)
+ *     (Electron Properties);
+ *   - phonons: D(q) = sum_R V2(0|R) e^{iq.R}, D z = (hbar omega)^2 z
+ *     (Phonon Properties, dynamical matrix and its eigenvalue equation);
+ *   - the Wannier-to-Bloch interpolation of the el-ph coupling with the
+ *     (1/2 m omega)^{1/2} factor (Electron Properties, definition of g and its
+ *     interpolation from g(Re, Rp)), computed as the two phase sums of the
+ *     Kokkos (Interaction) section;
+ *   - the electron lifetime 1/tau_kb (Transport Methods, electron BTE) with
+ *     Gaussian smearing (Dirac delta and Smearing) and an energy window
+ *     (Band structure classes).
+ *
+ * Conventions (every entry point):
+ *   - simple-cubic lattice, a = 1 A: k, q and R in crystal coordinates;
+ *     phases are e^{+i 2 pi k.R};
+ *   - units: energies eV, masses amu, force constants eV/A^2, g(Re,Rp) eV/A,
+ *     hbar omega = 0.0646541513 sqrt(lambda) eV, phonon length
+ *     l_{s,q nu} = sqrt(4.18015928e-3 / (2 M_s hbar omega)) A, Gamma in eV;
+ *   - arrays are C order; complex numbers are interleaved (re, im) doubles;
+ *   - "device" pointers are HIP device memory of the handle's device, "host"
+ *     pointers are ordinary host memory read before the call returns;
+ *   - the caller owns every input and output buffer; the handle owns its
+ *     workspace (device memory grown on demand up to the budget given at
+ *     creation);
+ *   - every call validates its arguments before launching anything and
+ *     returns a status; after an error no output is defined and
+ *     phoebe_gpu_last_error() describes it;
+ *   - work is enqueued on the given HIP stream (hipStream_t passed as void*,
+ *     NULL = default stream).  Calls return after enqueueing except where a
+ *     host-visible result (a count) is documented as synchronising;
+ *   - a handle is used by one host thread at a time.
+ */
+#ifndef PHOEBE_GPU_H
+#define PHOEBE_GPU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PHOEBE_GPU_ABI_VERSION 1
+
+typedef struct {
+    double re, im;
+} phoebe_c128;
+
+typedef enum {
+    PHOEBE_OK = 0,
+    PHOEBE_E_INVALID = -1,     /* bad argument: null pointer, size, enum, mesh */
+    PHOEBE_E_NOMEM = -2,       /* workspace budget or device allocation exhausted */
+    PHOEBE_E_DEVICE = -3,      /* a HIP runtime call failed */
+    PHOEBE_E_UNSUPPORTED = -4, /* valid request outside what the kernels implement */
+    PHOEBE_E_NUMERIC = -5      /* non-finite value met where a finite one is required */
+} phoebe_status;
+
+/* Arithmetic of the phase and rotation contractions.  Band structure,
+ * occupations, smearing and the rate accumulation are FP64 in every mode. */
+typedef enum {
+    PHOEBE_FP64 = 0,   /* FP64 MFMA, FP64 accumulation */
+    PHOEBE_FP32 = 1,   /* operands rounded to FP32, FP32 MFMA, FP32 accumulation */
+    PHOEBE_BF16X3 = 2, /* FP32 operands split hi+lo in BF16, 3 products, FP32 accumulation */
+    PHOEBE_BF16X6 = 3  /* FP32 operands split in 3 BF16 pieces, 6 products, FP32 accumulation */
+} phoebe_precision;
+
+/* One crystal.  Integer lattice-vector lists are HOST pointers; the tensors
+ * are DEVICE pointers. */
+typedef struct {
+    int32_t n_wannier;          /* nW >= 1 */
+    int32_t n_atoms;            /* nat >= 1; nModes = 3 nat, phonon index s*3+alpha */
+    int32_t n_rh;               /* number of Hamiltonian lattice vectors */
+    const int32_t *rh;          /* host   [n_rh, 3] */
+    const phoebe_c128 *h_r;     /* device [n_rh, nW, nW]  <0 n|H|R m>, eV */
+    int32_t n_rd;               /* number of force-constant lattice vectors */
+    const int32_t *rd;          /* host   [n_rd, 3] */
+    const double *phi_r;        /* device [n_rd, nModes, nModes]  V2(0 s a|R s' b), eV/A^2 */
+    const double *mass;         /* device [nat] amu */
+    int32_t n_re;               /* electron lattice vectors of g */
+    const int32_t *re;          /* host   [n_re, 3] */
+    int32_t n_rp;               /* phonon lattice vectors of g */
+    const int32_t *rp;          /* host   [n_rp, 3] */
+    const phoebe_c128 *g_rr;    /* device [n_re, n_rp, nModes, nW, nW] g(Re,Rp), eV/A;
+                                   first Wannier index pairs with k, second with k+q */
+} phoebe_system;
+
+/* Parameters of the rate sum.  States with win_lo < eps < win_hi are kept;
+ * modes with hbar omega < omega_min are left out (and get l = 0). */
+typedef struct {
+    double mu;        /* chemical potential, eV */
+    double kT;        /* k_B T, eV (> 0) */
+    double sigma;     /* Gaussian smearing: delta(x) = exp(-x^2/sigma^2)/(sqrt(pi) sigma), > 0 */
+    double win_lo;    /* energy window, eV */
+    double win_hi;
+    double omega_min; /* eV, >= 0 */
+} phoebe_rate_params;
+
+/* ABI version of the loaded library (PHOEBE_GPU_ABI_VERSION it was built with). */
+int32_t phoebe_gpu_abi_version(void);
+
+/* Create a handle on HIP device `device`; the workspace may grow to
+ * workspace_budget_bytes (0 = 90% of the device's free memory at creation).
+ * Errors: PHOEBE_E_INVALID (null out-pointer, bad device), PHOEBE_E_DEVICE. */
+phoebe_status phoebe_gpu_create(int device, size_t workspace_budget_bytes, void **handle);
+
+/* Release the handle and its workspace (synchronises the device first).
+ * NULL is accepted and ignored. */
+phoebe_status phoebe_gpu_destroy(void *handle);
+
+/* Text of the last error on this handle ("" if none); valid until the next
+ * call on the handle.  handle may be NULL (then: last error of create). */
+const char *phoebe_gpu_last_error(void *handle);
+
+/* Electron bands at arbitrary wavevectors (Electron Properties: back Fourier
+ * transform of H(R) and its diagonalisation).
+ *   k_frac    device [nk, 3] crystal coordinates
+ *   eps_out   device [nk, nW] ascending eigenvalues, eV
+ *   u_out     device [nk, nW, nW] eigenvectors as columns (nullable)
+ * Only sys->n_wannier, n_rh, rh, h_r are read.  nk = 0 is a no-op. */
+phoebe_status phoebe_gpu_electron_bands(void *handle, const phoebe_system *sys,
+                                        const double *k_frac, int64_t nk,
+                                        double *eps_out, phoebe_c128 *u_out, void *stream);
+
+/* Phonon modes at arbitrary wavevectors (Phonon Properties: dynamical matrix,
+ * mass-weighted as D/sqrt(M_s M_s'), and its eigenvalue equation).
+ *   q_frac    device [nq, 3]
+ *   omega_out device [nq, nModes] hbar omega = 0.0646541513 sqrt(max(lambda, 0)), eV,
+ *             in ascending lambda
+ *   z_out     device [nq, nModes, nModes] orthonormal eigenvectors as columns (nullable)
+ * Only n_atoms, n_rd, rd, phi_r, mass are read.  nq = 0 is a no-op. */
+phoebe_status phoebe_gpu_phonon_modes(void *handle, const phoebe_system *sys,
+                                      const double *q_frac, int64_t nq,
+                                      double *omega_out, phoebe_c128 *z_out, void *stream);
+
+/* Interpolated el-ph coupling for every pair of a k list and a q list
+ * (Electron Properties, definition of g and its Wannier interpolation; the
+ * two phase sums of the Kokkos section):
+ *   g_{nu n m}(k, q) = sum_{s alpha} [U_k^dagger G_{s alpha}(k,q) U_{k+q}]_{n m}
+ *                      z_{s alpha, nu}(q) l_{s, q nu},
+ *   G(k, q) = sum_{Re, Rp} e^{i 2 pi (k.Re + q.Rp)} g(Re, Rp),
+ * with l = 0 for hbar omega < omega_min.
+ *   k_frac  device [nk, 3];  q_frac device [nq, 3]
+ *   g_out   device [nk, nq, nModes, nW, nW]  index (i, j, nu, n at k, m at k+q)
+ *   eps_k   device [nk, nW] (nullable); eps_kq device [nk, nq, nW] (nullable);
+ *   omega_q device [nq, nModes] (nullable)
+ * Eigenvector phases are those of the library's eigensolver, so g itself is
+ * defined up to a phase per band and per mode (|g|^2 summed over degenerate
+ * states is gauge-free).  nk = 0 or nq = 0 is a no-op.
+ * Errors: PHOEBE_E_INVALID, PHOEBE_E_NOMEM, PHOEBE_E_UNSUPPORTED (nW > 32 or
+ * nModes > 32), PHOEBE_E_DEVICE. */
+phoebe_status phoebe_gpu_interp_g(void *handle, const phoebe_system *sys,
+                                  const double *k_frac, int64_t nk,
+                                  const double *q_frac, int64_t nq,
+                                  double omega_min, phoebe_precision prec,
+                                  phoebe_c128 *g_out, double *eps_k, double *eps_kq,
+                                  double *omega_q, void *stream);
+
+/* Scattering rates Gamma_nk = hbar/tau_nk on a uniform mesh (Transport
+ * Methods, electron lifetime; Gaussian smearing; energy window):
+ *   Gamma_nk = 2 pi sum_q w_q sum_m sum_nu |g_{nu n m}(k,q)|^2
+ *       [(n_{q nu}+1-f_{m,k+q}) delta(eps_nk-eps_{m,k+q}-hbar omega_{q nu})
+ *      + (n_{q nu}+f_{m,k+q})   delta(eps_nk-eps_{m,k+q}+hbar omega_{q nu})],
+ * f Fermi-Dirac(mu, kT), n Bose-Einstein(kT), k+q folded onto the mesh.
+ *   mesh      host [3], the k and the q mesh; point (i0,i1,i2) has linear
+ *             index (i0 N1 + i1) N2 + i2 (third coordinate fastest)
+ *   k_idx     device [nk] mesh linear indices of the k points to evaluate, or
+ *             NULL: every mesh k with a state in the window, ascending
+ *   q_off, q_idx, q_w: NULL for the full q mesh with w_q = 1/N_q; otherwise
+ *             explicit weighted q lists per evaluated k in CSR form:
+ *             q_off device int64 [nk+1], q_idx device int32 [q_off[nk]],
+ *             q_w device double [q_off[nk]] (only with k_idx != NULL)
+ *   gamma_out device [rows, nW]; row a belongs to the a-th evaluated k; bands
+ *             outside the window get 0.  rows = nk, or N_k (= N0 N1 N2)
+ *             capacity when k_idx is NULL
+ *   band_mask device uint8 [rows, nW], 1 = in window (nullable)
+ *   kept_k_out device int32 [rows] mesh index of each row (nullable)
+ *   n_kept_out host int64 (nullable): number of rows written.  When k_idx is
+ *             NULL the call synchronises the stream once, after the window
+ *             step, to learn this count.
+ * Errors: PHOEBE_E_INVALID (mesh < 1, sigma <= 0, kT <= 0, enum, pointers),
+ * PHOEBE_E_NOMEM, PHOEBE_E_UNSUPPORTED (nW > 32, nModes > 32), PHOEBE_E_DEVICE. */
+phoebe_status phoebe_gpu_scatter_rates(void *handle, const phoebe_system *sys,
+                                       const int32_t mesh[3],
+                                       const int32_t *k_idx, int64_t nk,
+                                       const int64_t *q_off, const int32_t *q_idx,
+                                       const double *q_w,
+                                       const phoebe_rate_params *par, phoebe_precision prec,
+                                       double *gamma_out, uint8_t *band_mask,
+                                       int32_t *kept_k_out, int64_t *n_kept_out,
+                                       void *stream);
+
+/* Kernel timing for measurement: when enabled, the named hot kernels are
+ * bracketed by HIP events on the stream they run on; phoebe_gpu_kernel_time
+ * returns the number of timed launches and their summed duration since the
+ * last reset.  Names: "stage2_rates", "stage1_phase", "bands_fft",
+ * "eig_jacobi".  Timing synchronises the stream at the end of each call. */
+phoebe_status phoebe_gpu_set_timing(void *handle, int enable);
+phoebe_status phoebe_gpu_kernel_time(void *handle, const char *name,
+                                     int64_t *launches, double *total_ms);
+phoebe_status phoebe_gpu_reset_timing(void *handle);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PHOEBE_GPU_H */

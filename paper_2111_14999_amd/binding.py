@@ -1,0 +1,237 @@
+"""ctypes binding of ``libphoebe_gpu.so`` (argument marshalling only).
+
+Every computation happens in the HIP library; this module converts torch
+tensors (device memory, streams) and numpy arrays (host lattice-vector lists)
+into the C ABI's plain pointers and sizes.  The functions raise ``PhoebeError``
+on any non-OK status, and loading fails loudly if the library has not been
+built.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libphoebe_gpu.so")
+
+PHOEBE_FP64, PHOEBE_FP32, PHOEBE_BF16X3, PHOEBE_BF16X6 = 0, 1, 2, 3
+PRECISIONS = {"fp64": PHOEBE_FP64, "fp32": PHOEBE_FP32, "bf16x3": PHOEBE_BF16X3,
+              "bf16x6": PHOEBE_BF16X6}
+STATUS = {0: "PHOEBE_OK", -1: "PHOEBE_E_INVALID", -2: "PHOEBE_E_NOMEM", -3: "PHOEBE_E_DEVICE",
+          -4: "PHOEBE_E_UNSUPPORTED", -5: "PHOEBE_E_NUMERIC"}
+
+#: every symbol the header declares
+EXPORTS = (
+    "phoebe_gpu_abi_version", "phoebe_gpu_create", "phoebe_gpu_destroy",
+    "phoebe_gpu_last_error", "phoebe_gpu_electron_bands", "phoebe_gpu_phonon_modes",
+    "phoebe_gpu_interp_g", "phoebe_gpu_scatter_rates", "phoebe_gpu_set_timing",
+    "phoebe_gpu_kernel_time", "phoebe_gpu_reset_timing",
+)
+
+
+class PhoebeError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class CSystem(ctypes.Structure):
+    _fields_ = [
+        ("n_wannier", ctypes.c_int32), ("n_atoms", ctypes.c_int32),
+        ("n_rh", ctypes.c_int32), ("rh", ctypes.c_void_p), ("h_r", ctypes.c_void_p),
+        ("n_rd", ctypes.c_int32), ("rd", ctypes.c_void_p), ("phi_r", ctypes.c_void_p),
+        ("mass", ctypes.c_void_p),
+        ("n_re", ctypes.c_int32), ("re", ctypes.c_void_p),
+        ("n_rp", ctypes.c_int32), ("rp", ctypes.c_void_p),
+        ("g_rr", ctypes.c_void_p),
+    ]
+
+
+class CRateParams(ctypes.Structure):
+    _fields_ = [("mu", ctypes.c_double), ("kT", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("win_lo", ctypes.c_double), ("win_hi", ctypes.c_double),
+                ("omega_min", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the shared library (raises if it was never built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2111_14999_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.phoebe_gpu_abi_version.restype = i32
+    lib.phoebe_gpu_create.argtypes = [ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(vp)]
+    lib.phoebe_gpu_destroy.argtypes = [vp]
+    lib.phoebe_gpu_last_error.argtypes = [vp]
+    lib.phoebe_gpu_last_error.restype = ctypes.c_char_p
+    lib.phoebe_gpu_electron_bands.argtypes = [vp, ctypes.POINTER(CSystem), vp, i64, vp, vp, vp]
+    lib.phoebe_gpu_phonon_modes.argtypes = [vp, ctypes.POINTER(CSystem), vp, i64, vp, vp, vp]
+    lib.phoebe_gpu_interp_g.argtypes = [vp, ctypes.POINTER(CSystem), vp, i64, vp, i64,
+                                        ctypes.c_double, ctypes.c_int, vp, vp, vp, vp, vp]
+    lib.phoebe_gpu_scatter_rates.argtypes = [vp, ctypes.POINTER(CSystem),
+                                             ctypes.POINTER(i32), vp, i64, vp, vp, vp,
+                                             ctypes.POINTER(CRateParams), ctypes.c_int,
+                                             vp, vp, vp, ctypes.POINTER(i64), vp]
+    lib.phoebe_gpu_set_timing.argtypes = [vp, ctypes.c_int]
+    lib.phoebe_gpu_reset_timing.argtypes = [vp]
+    lib.phoebe_gpu_kernel_time.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(i64),
+                                           ctypes.POINTER(ctypes.c_double)]
+    for name in EXPORTS:
+        if name not in ("phoebe_gpu_abi_version", "phoebe_gpu_last_error"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    return int(t.data_ptr())
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream) or None
+
+
+@dataclass
+class DeviceSystem:
+    """A system whose tensors live on the GPU (torch) and lattice lists on the host."""
+
+    n_wannier: int
+    n_atoms: int
+    rh: np.ndarray
+    h_r: object
+    rd: np.ndarray
+    phi_r: object
+    mass: object
+    re: np.ndarray
+    rp: np.ndarray
+    g_rr: object
+
+    @staticmethod
+    def from_host(system, device="cuda:0", with_coupling=True) -> "DeviceSystem":
+        """Copy a host system (numpy arrays) to the device."""
+        import torch
+
+        def dev(a):
+            return torch.from_numpy(np.ascontiguousarray(a)).to(device)
+
+        def ivec(a):
+            return np.ascontiguousarray(a, dtype=np.int32)
+
+        g = dev(system.g_rr) if (with_coupling and system.g_rr is not None) else None
+        return DeviceSystem(system.n_wannier, system.n_atoms, ivec(system.rh), dev(system.h_r),
+                            ivec(system.rd), dev(system.phi_r), dev(system.mass),
+                            ivec(system.re), ivec(system.rp), g)
+
+    def c_struct(self) -> CSystem:
+        c = CSystem()
+        c.n_wannier, c.n_atoms = self.n_wannier, self.n_atoms
+        c.n_rh, c.rh, c.h_r = self.rh.shape[0], self.rh.ctypes.data, _ptr(self.h_r)
+        c.n_rd, c.rd, c.phi_r = self.rd.shape[0], self.rd.ctypes.data, _ptr(self.phi_r)
+        c.mass = _ptr(self.mass)
+        c.n_re, c.re = self.re.shape[0], self.re.ctypes.data
+        c.n_rp, c.rp = self.rp.shape[0], self.rp.ctypes.data
+        c.g_rr = _ptr(self.g_rr)
+        return c
+
+
+class Library:
+    """One handle of the HIP library on one device."""
+
+    def __init__(self, device: int = 0, workspace_budget: int = 0):
+        self.lib = load()
+        h = ctypes.c_void_p()
+        st = self.lib.phoebe_gpu_create(device, workspace_budget, ctypes.byref(h))
+        if st != 0:
+            raise PhoebeError(st, self.lib.phoebe_gpu_last_error(None).decode())
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.phoebe_gpu_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != 0:
+            raise PhoebeError(st, self.lib.phoebe_gpu_last_error(self.handle).decode())
+
+    @staticmethod
+    def abi_version() -> int:
+        return int(load().phoebe_gpu_abi_version())
+
+    # -- band structure -----------------------------------------------------
+    def electron_bands(self, sys: DeviceSystem, k_frac, eps_out, u_out=None, stream=None):
+        c = sys.c_struct()
+        self._check(self.lib.phoebe_gpu_electron_bands(
+            self.handle, ctypes.byref(c), _ptr(k_frac), k_frac.shape[0], _ptr(eps_out),
+            _ptr(u_out), _stream(stream)))
+
+    def phonon_modes(self, sys: DeviceSystem, q_frac, omega_out, z_out=None, stream=None):
+        c = sys.c_struct()
+        self._check(self.lib.phoebe_gpu_phonon_modes(
+            self.handle, ctypes.byref(c), _ptr(q_frac), q_frac.shape[0], _ptr(omega_out),
+            _ptr(z_out), _stream(stream)))
+
+    # -- coupling -----------------------------------------------------------
+    def interp_g(self, sys: DeviceSystem, k_frac, q_frac, g_out, omega_min=1e-4,
+                 precision="fp64", eps_k=None, eps_kq=None, omega_q=None, stream=None):
+        c = sys.c_struct()
+        self._check(self.lib.phoebe_gpu_interp_g(
+            self.handle, ctypes.byref(c), _ptr(k_frac), k_frac.shape[0], _ptr(q_frac),
+            q_frac.shape[0], float(omega_min), PRECISIONS[precision], _ptr(g_out),
+            _ptr(eps_k), _ptr(eps_kq), _ptr(omega_q), _stream(stream)))
+
+    # -- rates --------------------------------------------------------------
+    def scatter_rates(self, sys: DeviceSystem, mesh, params: dict, gamma_out, k_idx=None,
+                      q_lists=None, precision="fp64", band_mask=None, kept_k_out=None,
+                      stream=None) -> int:
+        c = sys.c_struct()
+        m = (ctypes.c_int32 * 3)(*[int(x) for x in mesh])
+        p = CRateParams(params["mu"], params["kT"], params["sigma"], params["win_lo"],
+                        params["win_hi"], params.get("omega_min", 1e-4))
+        nk = 0 if k_idx is None else int(k_idx.shape[0])
+        q_off = q_idx = q_w = None
+        if q_lists is not None:
+            q_off, q_idx, q_w = q_lists
+        n_kept = ctypes.c_int64(0)
+        self._check(self.lib.phoebe_gpu_scatter_rates(
+            self.handle, ctypes.byref(c), m, _ptr(k_idx), nk, _ptr(q_off), _ptr(q_idx), _ptr(q_w),
+            ctypes.byref(p), PRECISIONS[precision], _ptr(gamma_out), _ptr(band_mask),
+            _ptr(kept_k_out), ctypes.byref(n_kept), _stream(stream)))
+        return int(n_kept.value)
+
+    # -- timing -------------------------------------------------------------
+    def set_timing(self, on: bool):
+        self._check(self.lib.phoebe_gpu_set_timing(self.handle, 1 if on else 0))
+
+    def reset_timing(self):
+        self._check(self.lib.phoebe_gpu_reset_timing(self.handle))
+
+    def kernel_time(self, name: str):
+        n = ctypes.c_int64(0)
+        ms = ctypes.c_double(0.0)
+        self._check(self.lib.phoebe_gpu_kernel_time(self.handle, name.encode(), ctypes.byref(n),
+                                                    ctypes.byref(ms)))
+        return int(n.value), float(ms.value)

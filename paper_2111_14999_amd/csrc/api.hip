@@ -1,0 +1,747 @@
+// C ABI of the library: argument validation, workspace, orchestration of the
+// kernels for the band structure, the coupling interpolation and the rates.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+
+using namespace phx;
+
+namespace {
+
+std::string g_create_error;
+
+struct TimedLaunch {
+    std::string name;
+    hipEvent_t start, stop;
+};
+
+struct KernelStat {
+    std::string name;
+    int64_t launches = 0;
+    double total_ms = 0.0;
+};
+
+struct Handle {
+    int device = 0;
+    size_t budget = 0;
+    char* ws = nullptr;
+    size_t ws_cap = 0;
+    std::string err;
+    bool timing = false;
+    std::vector<TimedLaunch> pending;
+    std::vector<KernelStat> stats;
+};
+
+struct Fail {
+    phoebe_status st;
+};
+
+// Bump allocation over the handle's workspace.  A first pass with base ==
+// nullptr only sizes the request.
+struct Arena {
+    char* base;
+    size_t used = 0;
+    explicit Arena(char* b) : base(b) {}
+    template <class T>
+    T* take(size_t count) {
+        used = (used + 255) & ~(size_t)255;
+        T* p = base ? reinterpret_cast<T*>(base + used) : nullptr;
+        used += count * sizeof(T);
+        return p;
+    }
+};
+
+void set_err(Handle* h, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+void set_err(Handle* h, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    h->err = buf;
+}
+
+#define REQUIRE(h, cond, ...)                    \
+    do {                                         \
+        if (!(cond)) {                           \
+            set_err((h), __VA_ARGS__);           \
+            throw Fail{PHOEBE_E_INVALID};        \
+        }                                        \
+    } while (0)
+
+#define HIPCHK(h, expr)                                                                   \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess) {                                                           \
+            set_err((h), "HIP error %s at %s:%d", hipGetErrorString(e_), __FILE__, __LINE__); \
+            throw Fail{PHOEBE_E_DEVICE};                                                  \
+        }                                                                                 \
+    } while (0)
+
+void ensure_ws(Handle* h, size_t bytes) {
+    if (bytes <= h->ws_cap) return;
+    if (bytes > h->budget) {
+        set_err(h, "workspace of %zu bytes exceeds the budget of %zu bytes", bytes, h->budget);
+        throw Fail{PHOEBE_E_NOMEM};
+    }
+    if (h->ws) {
+        HIPCHK(h, hipDeviceSynchronize());
+        HIPCHK(h, hipFree(h->ws));
+        h->ws = nullptr;
+        h->ws_cap = 0;
+    }
+    hipError_t e = hipMalloc(&h->ws, bytes);
+    if (e != hipSuccess) {
+        h->ws = nullptr;
+        set_err(h, "hipMalloc of %zu workspace bytes failed: %s", bytes, hipGetErrorString(e));
+        throw Fail{PHOEBE_E_NOMEM};
+    }
+    h->ws_cap = bytes;
+}
+
+// Timing brackets on the launch stream.
+struct Timer {
+    Handle* h;
+    hipStream_t s;
+    TimedLaunch t;
+    bool on;
+    Timer(Handle* h_, hipStream_t s_, const char* name) : h(h_), s(s_), on(h_->timing) {
+        if (!on) return;
+        t.name = name;
+        HIPCHK(h, hipEventCreate(&t.start));
+        HIPCHK(h, hipEventCreate(&t.stop));
+        HIPCHK(h, hipEventRecord(t.start, s));
+    }
+    void done() {
+        if (!on) return;
+        HIPCHK(h, hipEventRecord(t.stop, s));
+        h->pending.push_back(t);
+        on = false;
+    }
+};
+
+void flush_timing(Handle* h, hipStream_t s) {
+    if (h->pending.empty()) return;
+    HIPCHK(h, hipStreamSynchronize(s));
+    for (auto& t : h->pending) {
+        float ms = 0.f;
+        HIPCHK(h, hipEventElapsedTime(&ms, t.start, t.stop));
+        KernelStat* ks = nullptr;
+        for (auto& k : h->stats)
+            if (k.name == t.name) ks = &k;
+        if (!ks) {
+            h->stats.push_back(KernelStat{t.name, 0, 0.0});
+            ks = &h->stats.back();
+        }
+        ks->launches += 1;
+        ks->total_ms += ms;
+        (void)hipEventDestroy(t.start);
+        (void)hipEventDestroy(t.stop);
+    }
+    h->pending.clear();
+}
+
+void check_system(Handle* h, const phoebe_system* sys, bool need_h, bool need_ph, bool need_g) {
+    REQUIRE(h, sys != nullptr, "system is NULL");
+    REQUIRE(h, sys->n_wannier >= 1, "n_wannier must be >= 1 (got %d)", sys->n_wannier);
+    REQUIRE(h, sys->n_atoms >= 1, "n_atoms must be >= 1 (got %d)", sys->n_atoms);
+    if (need_h) {
+        REQUIRE(h, sys->n_rh >= 1 && sys->rh && sys->h_r, "H(R) arrays missing");
+    }
+    if (need_ph) {
+        REQUIRE(h, sys->n_rd >= 1 && sys->rd && sys->phi_r && sys->mass, "force constants missing");
+    }
+    if (need_g) {
+        REQUIRE(h, sys->n_re >= 1 && sys->re && sys->n_rp >= 1 && sys->rp && sys->g_rr,
+                "g(Re,Rp) arrays missing");
+    }
+}
+
+int32_t* upload_r(Handle* h, Arena& ar, const int32_t* host, int n, hipStream_t s) {
+    int32_t* d = ar.take<int32_t>((size_t)3 * n);
+    if (d) HIPCHK(h, hipMemcpyAsync(d, host, sizeof(int32_t) * 3 * n, hipMemcpyHostToDevice, s));
+    return d;
+}
+
+int rmax_of(const int32_t* r, int n) {
+    int m = 0;
+    for (int i = 0; i < 3 * n; ++i) m = std::max(m, std::abs(r[i]));
+    return m;
+}
+
+// ---------------------------------------------------------------------------
+// band structure on a set of points (fractional coordinates or mesh indices)
+// ---------------------------------------------------------------------------
+struct BandBufs {
+    double* eps;
+    cd* U;
+};
+
+void electron_bands_dev(Handle* h, Arena& ar, const phoebe_system* sys, const int32_t* rh_d,
+                        const double* frac, const int32_t* idx, Mesh m, int64_t np, double* eps,
+                        cd* U, hipStream_t s) {
+    const int nW = sys->n_wannier, nR = sys->n_rh;
+    cd* P = ar.take<cd>((size_t)np * nR);
+    cd* H = ar.take<cd>((size_t)np * nW * nW);
+    if (!ar.base) return;
+    HIPCHK(h, launch_phase_table(frac, idx, m, np, rh_d, nR, P, nR, s));
+    Timer t(h, s, "bands_fft");
+    HIPCHK(h, launch_zgemm(P, nR, reinterpret_cast<const cd*>(sys->h_r), (int64_t)nW * nW, H,
+                           (int64_t)nW * nW, np, (int64_t)nW * nW, nR, s));
+    t.done();
+    Timer te(h, s, "eig_jacobi");
+    HIPCHK(h, launch_eig_herm(H, nW, np, eps, U, s));
+    te.done();
+}
+
+void phonon_dev(Handle* h, Arena& ar, const phoebe_system* sys, const int32_t* rd_d,
+                const double* frac, const int32_t* idx, Mesh m, int64_t np, double omega_min,
+                double kT, double* omega, cd* E, double* nb, cd* z_out, hipStream_t s) {
+    const int nm = 3 * sys->n_atoms, nR = sys->n_rd;
+    cd* P = ar.take<cd>((size_t)np * nR);
+    cd* phic = ar.take<cd>((size_t)nR * nm * nm);
+    cd* D = ar.take<cd>((size_t)np * nm * nm);
+    double* lam = ar.take<double>((size_t)np * nm);
+    cd* z = z_out ? z_out : ar.take<cd>((size_t)np * nm * nm);
+    if (!ar.base) return;
+    HIPCHK(h, launch_phase_table(frac, idx, m, np, rd_d, nR, P, nR, s));
+    HIPCHK(h, launch_mass_weight(sys->phi_r, sys->mass, nR, nm, phic, s));
+    HIPCHK(h, launch_zgemm(P, nR, phic, (int64_t)nm * nm, D, (int64_t)nm * nm, np,
+                           (int64_t)nm * nm, nR, s));
+    HIPCHK(h, launch_eig_herm(D, nm, np, lam, z, s));
+    HIPCHK(h, launch_phonon_post(lam, z, sys->mass, sys->n_atoms, np, omega_min, kT, omega, E, nb,
+                                 s));
+}
+
+phoebe_status run(Handle* h, const std::function<void()>& body) {
+    try {
+        h->err.clear();
+        body();
+        return PHOEBE_OK;
+    } catch (const Fail& f) {
+        return f.st;
+    } catch (const std::bad_alloc&) {
+        set_err(h, "host allocation failed");
+        return PHOEBE_E_NOMEM;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t phoebe_gpu_abi_version(void) { return PHOEBE_GPU_ABI_VERSION; }
+
+phoebe_status phoebe_gpu_create(int device, size_t budget, void** handle) {
+    if (!handle) {
+        g_create_error = "handle out-pointer is NULL";
+        return PHOEBE_E_INVALID;
+    }
+    *handle = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess) {
+        g_create_error = std::string("hipGetDeviceCount failed: ") + hipGetErrorString(e);
+        return PHOEBE_E_DEVICE;
+    }
+    if (device < 0 || device >= count) {
+        g_create_error = "device index out of range";
+        return PHOEBE_E_INVALID;
+    }
+    e = hipSetDevice(device);
+    if (e != hipSuccess) {
+        g_create_error = std::string("hipSetDevice failed: ") + hipGetErrorString(e);
+        return PHOEBE_E_DEVICE;
+    }
+    if (budget == 0) {
+        size_t fr = 0, tot = 0;
+        e = hipMemGetInfo(&fr, &tot);
+        if (e != hipSuccess) {
+            g_create_error = std::string("hipMemGetInfo failed: ") + hipGetErrorString(e);
+            return PHOEBE_E_DEVICE;
+        }
+        budget = (size_t)(0.9 * (double)fr);
+    }
+    Handle* h = new (std::nothrow) Handle();
+    if (!h) {
+        g_create_error = "host allocation failed";
+        return PHOEBE_E_NOMEM;
+    }
+    h->device = device;
+    h->budget = budget;
+    *handle = h;
+    g_create_error.clear();
+    return PHOEBE_OK;
+}
+
+phoebe_status phoebe_gpu_destroy(void* handle) {
+    if (!handle) return PHOEBE_OK;
+    Handle* h = static_cast<Handle*>(handle);
+    (void)hipSetDevice(h->device);
+    (void)hipDeviceSynchronize();
+    for (auto& t : h->pending) {
+        (void)hipEventDestroy(t.start);
+        (void)hipEventDestroy(t.stop);
+    }
+    if (h->ws) (void)hipFree(h->ws);
+    delete h;
+    return PHOEBE_OK;
+}
+
+const char* phoebe_gpu_last_error(void* handle) {
+    if (!handle) return g_create_error.c_str();
+    return static_cast<Handle*>(handle)->err.c_str();
+}
+
+phoebe_status phoebe_gpu_set_timing(void* handle, int enable) {
+    if (!handle) return PHOEBE_E_INVALID;
+    static_cast<Handle*>(handle)->timing = enable != 0;
+    return PHOEBE_OK;
+}
+
+phoebe_status phoebe_gpu_reset_timing(void* handle) {
+    if (!handle) return PHOEBE_E_INVALID;
+    static_cast<Handle*>(handle)->stats.clear();
+    return PHOEBE_OK;
+}
+
+phoebe_status phoebe_gpu_kernel_time(void* handle, const char* name, int64_t* launches,
+                                     double* total_ms) {
+    if (!handle || !name || !launches || !total_ms) return PHOEBE_E_INVALID;
+    Handle* h = static_cast<Handle*>(handle);
+    *launches = 0;
+    *total_ms = 0.0;
+    for (auto& k : h->stats)
+        if (k.name == name) {
+            *launches = k.launches;
+            *total_ms = k.total_ms;
+        }
+    return PHOEBE_OK;
+}
+
+phoebe_status phoebe_gpu_electron_bands(void* handle, const phoebe_system* sys,
+                                        const double* k_frac, int64_t nk, double* eps_out,
+                                        phoebe_c128* u_out, void* stream) {
+    if (!handle) return PHOEBE_E_INVALID;
+    Handle* h = static_cast<Handle*>(handle);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return run(h, [&] {
+        check_system(h, sys, true, false, false);
+        REQUIRE(h, nk >= 0, "nk < 0");
+        if (nk == 0) return;
+        REQUIRE(h, k_frac && eps_out, "k_frac/eps_out is NULL");
+        REQUIRE(h, sys->n_wannier <= 32, "n_wannier > 32 is not supported");
+        HIPCHK(h, hipSetDevice(h->device));
+        const int nW = sys->n_wannier;
+        auto plan = [&](Arena& ar) {
+            int32_t* rh = upload_r(h, ar, sys->rh, sys->n_rh, s);
+            cd* U = u_out ? reinterpret_cast<cd*>(u_out) : ar.take<cd>((size_t)nk * nW * nW);
+            electron_bands_dev(h, ar, sys, rh, k_frac, nullptr, Mesh{1, 1, 1}, nk, eps_out, U, s);
+        };
+        Arena dry(nullptr);
+        plan(dry);
+        ensure_ws(h, dry.used);
+        Arena ar(h->ws);
+        plan(ar);
+        HIPCHK(h, hipGetLastError());
+        HIPCHK(h, hipStreamSynchronize(s));  // host lattice lists are read before return
+        flush_timing(h, s);
+    });
+}
+
+phoebe_status phoebe_gpu_phonon_modes(void* handle, const phoebe_system* sys,
+                                      const double* q_frac, int64_t nq, double* omega_out,
+                                      phoebe_c128* z_out, void* stream) {
+    if (!handle) return PHOEBE_E_INVALID;
+    Handle* h = static_cast<Handle*>(handle);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return run(h, [&] {
+        check_system(h, sys, false, true, false);
+        REQUIRE(h, nq >= 0, "nq < 0");
+        if (nq == 0) return;
+        REQUIRE(h, q_frac && omega_out, "q_frac/omega_out is NULL");
+        REQUIRE(h, sys->n_atoms <= 10, "more than 10 atoms (30 modes) is not supported");
+        HIPCHK(h, hipSetDevice(h->device));
+        auto plan = [&](Arena& ar) {
+            int32_t* rd = upload_r(h, ar, sys->rd, sys->n_rd, s);
+            phonon_dev(h, ar, sys, rd, q_frac, nullptr, Mesh{1, 1, 1}, nq, 0.0, 0.0, omega_out,
+                       nullptr, nullptr, reinterpret_cast<cd*>(z_out), s);
+        };
+        Arena dry(nullptr);
+        plan(dry);
+        ensure_ws(h, dry.used);
+        Arena ar(h->ws);
+        plan(ar);
+        HIPCHK(h, hipGetLastError());
+        HIPCHK(h, hipStreamSynchronize(s));  // host lattice lists are read before return
+    });
+}
+
+phoebe_status phoebe_gpu_interp_g(void* handle, const phoebe_system* sys, const double* k_frac,
+                                  int64_t nk, const double* q_frac, int64_t nq, double omega_min,
+                                  phoebe_precision prec, phoebe_c128* g_out, double* eps_k,
+                                  double* eps_kq, double* omega_q, void* stream) {
+    if (!handle) return PHOEBE_E_INVALID;
+    Handle* h = static_cast<Handle*>(handle);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return run(h, [&] {
+        check_system(h, sys, true, true, true);
+        REQUIRE(h, nk >= 0 && nq >= 0, "negative nk or nq");
+        REQUIRE(h, prec >= PHOEBE_FP64 && prec <= PHOEBE_BF16X6, "precision enum out of range");
+        REQUIRE(h, std::isfinite(omega_min) && omega_min >= 0.0, "omega_min must be >= 0");
+        if (nk == 0 || nq == 0) return;
+        REQUIRE(h, k_frac && q_frac && g_out, "k_frac/q_frac/g_out is NULL");
+        REQUIRE(h, nk * nq <= 4000000, "nk * nq above 4e6 pairs: split the call");
+        const int nW = sys->n_wannier, nm = 3 * sys->n_atoms;
+        if (nW > 32 || nm > 32) {
+            set_err(h, "nW > 32 or nModes > 32 is not supported");
+            throw Fail{PHOEBE_E_UNSUPPORTED};
+        }
+        if (prec != PHOEBE_FP64) {
+            set_err(h, "interp_g implements the FP64 contractions only");
+            throw Fail{PHOEBE_E_UNSUPPORTED};
+        }
+        HIPCHK(h, hipSetDevice(h->device));
+        const int n_re = sys->n_re, n_rp = sys->n_rp;
+        const int64_t NC3 = (int64_t)nm * nW * nW;
+        const int64_t npair = nk * nq;
+        const int64_t qchunk = std::min<int64_t>(nq, 65536);
+        const int64_t kb = std::min<int64_t>(nk, 64);
+        auto plan = [&](Arena& ar) {
+            int32_t* rh = upload_r(h, ar, sys->rh, sys->n_rh, s);
+            int32_t* rd = upload_r(h, ar, sys->rd, sys->n_rd, s);
+            int32_t* re = upload_r(h, ar, sys->re, n_re, s);
+            int32_t* rp = upload_r(h, ar, sys->rp, n_rp, s);
+            double* ek = eps_k ? eps_k : ar.take<double>((size_t)nk * nW);
+            cd* Uk = ar.take<cd>((size_t)nk * nW * nW);
+            double* ekq = eps_kq ? eps_kq : ar.take<double>((size_t)npair * nW);
+            cd* Ukq = ar.take<cd>((size_t)npair * nW * nW);
+            double* kqf = ar.take<double>((size_t)npair * 3);
+            double* om = omega_q ? omega_q : ar.take<double>((size_t)nq * nm);
+            cd* E = ar.take<cd>((size_t)nq * nm * nm);
+            cd* Pe = ar.take<cd>((size_t)kb * n_re);
+            cd* G1 = ar.take<cd>((size_t)kb * n_rp * NC3);
+            cd* Pp = ar.take<cd>((size_t)nq * n_rp);
+            cd* F = ar.take<cd>((size_t)n_rp * NC3);
+            cd* X = ar.take<cd>((size_t)qchunk * NC3);
+            {
+                Arena sub = ar;  // band scratch, reused after the tables are built
+                electron_bands_dev(h, sub, sys, rh, k_frac, nullptr, Mesh{1, 1, 1}, nk, ek, Uk, s);
+                Arena sub2 = ar;
+                if (ar.base) HIPCHK(h, launch_kq_points(k_frac, nk, q_frac, nq, kqf, s));
+                electron_bands_dev(h, sub2, sys, rh, kqf, nullptr, Mesh{1, 1, 1}, npair, ekq, Ukq,
+                                   s);
+                Arena sub3 = ar;
+                phonon_dev(h, sub3, sys, rd, q_frac, nullptr, Mesh{1, 1, 1}, nq, omega_min, 0.0,
+                           om, E, nullptr, nullptr, s);
+                ar.used = std::max(std::max(sub.used, sub2.used), sub3.used);
+            }
+            if (!ar.base) return;
+            HIPCHK(h, launch_phase_table(q_frac, nullptr, Mesh{1, 1, 1}, nq, rp, n_rp, Pp, n_rp, s));
+            for (int64_t k0 = 0; k0 < nk; k0 += kb) {
+                const int64_t nb = std::min(kb, nk - k0);
+                HIPCHK(h, launch_phase_table(k_frac + 3 * k0, nullptr, Mesh{1, 1, 1}, nb, re, n_re,
+                                             Pe, n_re, s));
+                Timer t1(h, s, "stage1_phase");
+                HIPCHK(h, launch_zgemm(Pe, n_re, reinterpret_cast<const cd*>(sys->g_rr),
+                                       (int64_t)n_rp * NC3, G1, (int64_t)n_rp * NC3, nb,
+                                       (int64_t)n_rp * NC3, n_re, s));
+                t1.done();
+                for (int64_t i = 0; i < nb; ++i) {
+                    const int64_t k = k0 + i;
+                    HIPCHK(h, launch_fold_all(G1 + i * n_rp * NC3, Uk + k * nW * nW, n_rp, nm, nW,
+                                              F, s));
+                    for (int64_t q0 = 0; q0 < nq; q0 += qchunk) {
+                        const int64_t nqc = std::min(qchunk, nq - q0);
+                        HIPCHK(h, launch_zgemm(Pp + q0 * n_rp, n_rp, F, NC3, X, NC3, nqc, NC3, n_rp,
+                                               s));
+                        HIPCHK(h, launch_rotate_g(X, nqc, Uk + k * nW * nW,
+                                                  Ukq + (k * nq + q0) * nW * nW, E + q0 * nm * nm,
+                                                  nW, nm,
+                                                  reinterpret_cast<cd*>(g_out) + (k * nq + q0) * NC3,
+                                                  s));
+                    }
+                }
+            }
+        };
+        Arena dry(nullptr);
+        plan(dry);
+        ensure_ws(h, dry.used);
+        Arena ar(h->ws);
+        plan(ar);
+        HIPCHK(h, hipGetLastError());
+        HIPCHK(h, hipStreamSynchronize(s));  // host lattice lists are read before return
+        flush_timing(h, s);
+    });
+}
+
+phoebe_status phoebe_gpu_scatter_rates(void* handle, const phoebe_system* sys,
+                                       const int32_t mesh_in[3], const int32_t* k_idx, int64_t nk,
+                                       const int64_t* q_off, const int32_t* q_idx,
+                                       const double* q_w, const phoebe_rate_params* par,
+                                       phoebe_precision prec, double* gamma_out,
+                                       uint8_t* band_mask, int32_t* kept_k_out,
+                                       int64_t* n_kept_out, void* stream) {
+    if (!handle) return PHOEBE_E_INVALID;
+    Handle* h = static_cast<Handle*>(handle);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return run(h, [&] {
+        check_system(h, sys, true, true, true);
+        REQUIRE(h, mesh_in != nullptr, "mesh is NULL");
+        REQUIRE(h, mesh_in[0] >= 1 && mesh_in[1] >= 1 && mesh_in[2] >= 1, "mesh must be >= 1");
+        REQUIRE(h, par != nullptr, "rate parameters are NULL");
+        REQUIRE(h, std::isfinite(par->sigma) && par->sigma > 0.0, "sigma must be > 0");
+        REQUIRE(h, std::isfinite(par->kT) && par->kT > 0.0, "kT must be > 0");
+        REQUIRE(h, std::isfinite(par->mu), "mu must be finite");
+        REQUIRE(h, !std::isnan(par->win_lo) && !std::isnan(par->win_hi), "window is NaN");
+        REQUIRE(h, std::isfinite(par->omega_min) && par->omega_min >= 0.0, "omega_min must be >= 0");
+        REQUIRE(h, prec >= PHOEBE_FP64 && prec <= PHOEBE_BF16X6, "precision enum out of range");
+        REQUIRE(h, gamma_out != nullptr, "gamma_out is NULL");
+        REQUIRE(h, k_idx != nullptr || nk == 0, "nk must be 0 when k_idx is NULL");
+        REQUIRE(h, nk >= 0, "nk < 0");
+        REQUIRE(h, (q_off == nullptr) == (q_idx == nullptr) && (q_off == nullptr) == (q_w == nullptr),
+                "q_off, q_idx and q_w must be all NULL or all set");
+        REQUIRE(h, q_off == nullptr || k_idx != nullptr, "explicit q lists need explicit k_idx");
+        const Mesh mesh{mesh_in[0], mesh_in[1], mesh_in[2]};
+        const int64_t N = (int64_t)mesh.n0 * mesh.n1 * mesh.n2;
+        REQUIRE(h, N <= (int64_t)1 << 30, "mesh too large");
+        const int nW = sys->n_wannier, nm = 3 * sys->n_atoms;
+        if (nW > 32 || nm > 32) {
+            set_err(h, "nW > 32 or nModes > 32 is not supported");
+            throw Fail{PHOEBE_E_UNSUPPORTED};
+        }
+        if (prec != PHOEBE_FP64) {
+            set_err(h, "this build implements the FP64 contractions only");
+            throw Fail{PHOEBE_E_UNSUPPORTED};
+        }
+        int wq = 0, tnw = 0;
+        const int nc_pad = stage2_config(nm, nW, &wq, &tnw);
+        if (nc_pad < 0) {
+            set_err(h, "no stage-2 tiling for nModes*nW = %d", nm * nW);
+            throw Fail{PHOEBE_E_UNSUPPORTED};
+        }
+        const int rmax_p = rmax_of(sys->rp, sys->n_rp);
+        REQUIRE(h, rmax_p <= 100, "|Rp| components above 100 are not supported");
+        HIPCHK(h, hipSetDevice(h->device));
+        const int n_re = sys->n_re, n_rp = sys->n_rp;
+        const int rp_pad = (n_rp + 3) & ~3;
+        const int64_t NC2 = (int64_t)n_rp * nm * nW * nW;
+        // kept k points per stage-1 batch: G and F of a batch stay under 8 GB each
+        int BK = 64;
+        while (BK > 16 && ((double)BK * NC2 * sizeof(cd) > 8e9 ||
+                           (double)BK * nW * rp_pad * NC2 / n_rp * sizeof(cd) > 8e9))
+            BK /= 2;
+        const int BQ = 16 * wq;
+
+        // q-list lengths (host) for the tile count
+        int64_t max_list = N;
+        std::vector<int64_t> qoff_h;
+        if (q_off) {
+            qoff_h.resize(nk + 1);
+            HIPCHK(h, hipMemcpyAsync(qoff_h.data(), q_off, sizeof(int64_t) * (nk + 1),
+                                     hipMemcpyDeviceToHost, s));
+            HIPCHK(h, hipStreamSynchronize(s));
+            max_list = 0;
+            REQUIRE(h, qoff_h[0] >= 0, "q_off[0] < 0");
+            for (int64_t i = 0; i < nk; ++i) {
+                REQUIRE(h, qoff_h[i + 1] >= qoff_h[i], "q_off is not non-decreasing");
+                max_list = std::max(max_list, qoff_h[i + 1] - qoff_h[i]);
+            }
+            const int64_t total = qoff_h[nk];
+            if (total > 0) {
+                std::vector<int32_t> qh(total);
+                HIPCHK(h, hipMemcpyAsync(qh.data(), q_idx, sizeof(int32_t) * total,
+                                         hipMemcpyDeviceToHost, s));
+                HIPCHK(h, hipStreamSynchronize(s));
+                for (int64_t i = 0; i < total; ++i)
+                    REQUIRE(h, qh[i] >= 0 && qh[i] < N, "q_idx[%lld] = %d is not a mesh index",
+                            (long long)i, qh[i]);
+            }
+        }
+        const int n_qtiles = (int)std::max<int64_t>(1, (max_list + BQ - 1) / BQ);
+
+        // ---- phase A: tables, window, states (sized for the whole mesh) ----
+        struct Tables {
+            int32_t *rh, *rd, *re, *rp, *rp_packed;
+            double *eps, *focc, *omega, *nb, *bmin, *bmax, *wmax;
+            cd *U, *E;
+            uint8_t* mask;
+            int32_t *flag, *kept, *cnt, *rowflag, *ids;
+            int32_t *st_row, *st_band, *st_kmesh, *st_mlo, *st_mhi;
+        } T{};
+        const int64_t rows_cap = k_idx ? nk : N;
+        auto plan_tables = [&](Arena& ar) {
+            T.rh = upload_r(h, ar, sys->rh, sys->n_rh, s);
+            T.rd = upload_r(h, ar, sys->rd, sys->n_rd, s);
+            T.re = upload_r(h, ar, sys->re, n_re, s);
+            T.rp = upload_r(h, ar, sys->rp, n_rp, s);
+            T.rp_packed = ar.take<int32_t>(n_rp);
+            T.eps = ar.take<double>((size_t)N * nW);
+            T.focc = ar.take<double>((size_t)N * nW);
+            T.U = ar.take<cd>((size_t)N * nW * nW);
+            T.omega = ar.take<double>((size_t)N * nm);
+            T.nb = ar.take<double>((size_t)N * nm);
+            T.E = ar.take<cd>((size_t)N * nm * nm);
+            T.bmin = ar.take<double>(nW);
+            T.bmax = ar.take<double>(nW);
+            T.wmax = ar.take<double>(1);
+            T.mask = ar.take<uint8_t>((size_t)N * nW);
+            T.flag = ar.take<int32_t>(N);
+            T.kept = ar.take<int32_t>(N);
+            T.cnt = ar.take<int32_t>(2);
+            T.rowflag = ar.take<int32_t>((size_t)rows_cap * nW);
+            T.ids = ar.take<int32_t>((size_t)rows_cap * nW);
+            T.st_row = ar.take<int32_t>((size_t)rows_cap * nW);
+            T.st_band = ar.take<int32_t>((size_t)rows_cap * nW);
+            T.st_kmesh = ar.take<int32_t>((size_t)rows_cap * nW);
+            T.st_mlo = ar.take<int32_t>((size_t)rows_cap * nW);
+            T.st_mhi = ar.take<int32_t>((size_t)rows_cap * nW);
+        };
+        // band scratch is carved after the tables and reused by the batches
+        size_t tables_end = 0, scratch_bands = 0;
+        {
+            Arena dry(nullptr);
+            plan_tables(dry);
+            tables_end = dry.used;
+            Arena d1 = dry, d2 = dry;
+            electron_bands_dev(h, d1, sys, nullptr, nullptr, nullptr, mesh, N, nullptr, nullptr, s);
+            phonon_dev(h, d2, sys, nullptr, nullptr, nullptr, mesh, N, 0, 0, nullptr, nullptr,
+                       nullptr, nullptr, s);
+            scratch_bands = std::max(d1.used, d2.used) - tables_end;
+        }
+        // batch buffers (upper bound on the states of a batch: BK * nW)
+        const int max_states = BK * nW;
+        const size_t batch_bytes = 4 * 256 + (size_t)BK * n_re * sizeof(cd) +
+                                   (size_t)BK * NC2 * sizeof(cd) +
+                                   (size_t)max_states * rp_pad * nc_pad * sizeof(cd) +
+                                   (size_t)max_states * n_qtiles * sizeof(double);
+        ensure_ws(h, tables_end + std::max(scratch_bands, batch_bytes) + 256);
+        Arena ar(h->ws);
+        plan_tables(ar);
+        {
+            std::vector<int32_t> packed(n_rp);
+            for (int i = 0; i < n_rp; ++i)
+                packed[i] = (sys->rp[3 * i] + rmax_p) | ((sys->rp[3 * i + 1] + rmax_p) << 8) |
+                            ((sys->rp[3 * i + 2] + rmax_p) << 16);
+            HIPCHK(h, hipMemcpyAsync(T.rp_packed, packed.data(), sizeof(int32_t) * n_rp,
+                                     hipMemcpyHostToDevice, s));
+            // the host vector must outlive the copy
+            HIPCHK(h, hipStreamSynchronize(s));
+        }
+        {
+            Arena b1 = ar, b2 = ar;
+            electron_bands_dev(h, b1, sys, T.rh, nullptr, nullptr, mesh, N, T.eps, T.U, s);
+            phonon_dev(h, b2, sys, T.rd, nullptr, nullptr, mesh, N, par->omega_min, par->kT,
+                       T.omega, T.E, T.nb, nullptr, s);
+        }
+        HIPCHK(h, launch_fermi(T.eps, N * nW, par->mu, par->kT, T.focc, s));
+        HIPCHK(h, launch_band_extrema(T.eps, N, nW, T.omega, N, nm, T.bmin, T.bmax, T.wmax, s));
+        HIPCHK(h, launch_window(T.eps, N, nW, par->win_lo, par->win_hi, T.mask, T.flag, s));
+        int64_t rows = nk;
+        const int32_t* kept = k_idx;
+        if (!k_idx) {
+            HIPCHK(h, launch_compact(T.flag, N, T.kept, T.cnt, s));
+            int32_t c = 0;
+            HIPCHK(h, hipMemcpyAsync(&c, T.cnt, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            HIPCHK(h, hipStreamSynchronize(s));
+            rows = c;
+            kept = T.kept;
+        } else {
+            std::vector<int32_t> kh(nk);
+            HIPCHK(h, hipMemcpyAsync(kh.data(), k_idx, sizeof(int32_t) * nk, hipMemcpyDeviceToHost, s));
+            HIPCHK(h, hipStreamSynchronize(s));
+            for (int64_t i = 0; i < nk; ++i)
+                REQUIRE(h, kh[i] >= 0 && kh[i] < N, "k_idx[%lld] = %d is not a mesh index",
+                        (long long)i, kh[i]);
+        }
+        if (n_kept_out) *n_kept_out = rows;
+        HIPCHK(h, launch_zero(gamma_out, (size_t)rows * nW * sizeof(double), s));
+        if (rows == 0) return;
+        HIPCHK(h, launch_gather_rows(T.mask, kept, rows, nW, T.rowflag, band_mask, kept_k_out, s));
+        HIPCHK(h, launch_compact(T.rowflag, rows * nW, T.ids, T.cnt + 1, s));
+        int32_t nst_i = 0;
+        HIPCHK(h, hipMemcpyAsync(&nst_i, T.cnt + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(h, hipStreamSynchronize(s));
+        const int nst = nst_i;
+        if (nst == 0) {
+            flush_timing(h, s);
+            return;
+        }
+        const double cut = 27.5 * par->sigma;  // exp(-27.5^2) underflows to 0 in FP64
+        HIPCHK(h, launch_build_states(T.ids, nst, nW, kept, T.eps, T.bmin, T.bmax, T.wmax, cut,
+                                      T.st_row, T.st_band, T.st_kmesh, T.st_mlo, T.st_mhi, s));
+        std::vector<int32_t> strow(nst);
+        HIPCHK(h, hipMemcpyAsync(strow.data(), T.st_row, sizeof(int32_t) * nst,
+                                 hipMemcpyDeviceToHost, s));
+        HIPCHK(h, hipStreamSynchronize(s));
+
+        // ---- phase B: batches of BK rows ----
+        cd* P1 = ar.take<cd>((size_t)BK * n_re);
+        cd* G = ar.take<cd>((size_t)BK * NC2);
+        cd* F = ar.take<cd>((size_t)max_states * rp_pad * nc_pad);
+        double* partial = ar.take<double>((size_t)max_states * n_qtiles);
+
+        const double inv_sqrtpi_sigma = 1.0 / (std::sqrt(kPi) * par->sigma);
+        const double scale = 2.0 * kPi * inv_sqrtpi_sigma * (q_off ? 1.0 : 1.0 / (double)N);
+        int sbeg = 0;
+        for (int64_t r0 = 0; r0 < rows; r0 += BK) {
+            const int64_t nb = std::min<int64_t>(BK, rows - r0);
+            int send = sbeg;
+            while (send < nst && strow[send] < r0 + nb) ++send;
+            const int ns = send - sbeg;
+            if (ns == 0) continue;
+            HIPCHK(h, launch_phase_table(nullptr, kept + r0, mesh, nb, T.re, n_re, P1, n_re, s));
+            Timer t1(h, s, "stage1_phase");
+            HIPCHK(h, launch_zgemm(P1, n_re, reinterpret_cast<const cd*>(sys->g_rr), NC2, G, NC2, nb,
+                                   NC2, n_re, s));
+            t1.done();
+            HIPCHK(h, launch_fold_uk(G, NC2, T.U, T.st_row + sbeg, (int)r0, T.st_kmesh + sbeg,
+                                     T.st_band + sbeg, ns, n_rp, nm, nW, rp_pad, nc_pad, F, s));
+            RateArgs ra{};
+            ra.F = F;
+            ra.rp_pad = rp_pad;
+            ra.nc_pad = nc_pad;
+            ra.n_rp = n_rp;
+            ra.rp_packed = T.rp_packed;
+            ra.rmax = rmax_p;
+            ra.mesh = mesh;
+            ra.nq_mesh = N;
+            ra.st_kmesh = T.st_kmesh + sbeg;
+            ra.st_band = T.st_band + sbeg;
+            ra.st_row = T.st_row + sbeg;
+            ra.st_mlo = T.st_mlo + sbeg;
+            ra.st_mhi = T.st_mhi + sbeg;
+            ra.q_off = q_off;
+            ra.q_idx = q_idx;
+            ra.q_w = q_w;
+            ra.eps = T.eps;
+            ra.focc = T.focc;
+            ra.U = T.U;
+            ra.omega = T.omega;
+            ra.nb = T.nb;
+            ra.E = T.E;
+            ra.nW = nW;
+            ra.nm = nm;
+            ra.sigma = par->sigma;
+            ra.partial = partial;
+            ra.n_qtiles = n_qtiles;
+            Timer t2(h, s, "stage2_rates");
+            HIPCHK(h, launch_stage2_rates(ra, ns, s));
+            t2.done();
+            HIPCHK(h, launch_reduce_partials(partial, ns, n_qtiles, T.st_row + sbeg,
+                                             T.st_band + sbeg, nW, scale, gamma_out, s));
+            sbeg = send;
+        }
+        HIPCHK(h, hipGetLastError());
+        flush_timing(h, s);
+    });
+}
+
+}  // extern "C"

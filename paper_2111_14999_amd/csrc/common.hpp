@@ -1,0 +1,69 @@
+// Shared device/host definitions of the gfx950 el-ph library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/phoebe_gpu.h"
+
+namespace phx {
+
+// ---------------------------------------------------------------------------
+// Units (CODATA 2018).  Energies eV, lengths A, masses amu.
+//   hbar omega = C_OMEGA sqrt(lambda), lambda in eV/(A^2 amu)
+//   l^2 = C_PH / (2 M hbar omega) in A^2
+// ---------------------------------------------------------------------------
+constexpr double kHbar = 1.054571817e-34;      // J s
+constexpr double kEv = 1.602176634e-19;        // J
+constexpr double kAmu = 1.66053906660e-27;     // kg
+constexpr double kAng = 1.0e-10;               // m
+// C_OMEGA = hbar sqrt(eV / (A^2 amu)) / eV ; C_PH = hbar^2 / (amu A^2) / eV
+constexpr double kCPh = kHbar * kHbar / (kAmu * kAng * kAng) / kEv;
+// sqrt is not constexpr: C_OMEGA^2 = C_PH (same combination), so C_OMEGA = sqrt(C_PH)
+inline double c_omega() { return __builtin_sqrt(kCPh); }
+
+constexpr double kPi = 3.14159265358979323846;
+
+struct cd {
+    double x, y;
+};
+
+__host__ __device__ inline cd cmul(cd a, cd b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+__host__ __device__ inline cd cmulc(cd a, cd b) {  // conj(a) * b
+    return {a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x};
+}
+__host__ __device__ inline cd cadd(cd a, cd b) { return {a.x + b.x, a.y + b.y}; }
+__host__ __device__ inline cd cfma(cd a, cd b, cd c) {  // a*b + c
+    return {fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y))};
+}
+__host__ __device__ inline cd cfmac(cd a, cd b, cd c) {  // conj(a)*b + c
+    return {fma(a.x, b.x, fma(a.y, b.y, c.x)), fma(a.x, b.y, fma(-a.y, b.x, c.y))};
+}
+__host__ __device__ inline double cabs2(cd a) { return a.x * a.x + a.y * a.y; }
+
+// e^{i 2 pi t} for t already reduced to [-1, 1)
+__device__ inline cd expi2pi(double t) {
+    double s, c;
+    sincospi(2.0 * t, &s, &c);
+    return {c, s};
+}
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Mesh helpers: linear index (i0 N1 + i1) N2 + i2
+struct Mesh {
+    int n0, n1, n2;
+};
+__host__ __device__ inline void mesh_triple(int64_t idx, Mesh m, int& i0, int& i1, int& i2) {
+    i2 = (int)(idx % m.n2);
+    idx /= m.n2;
+    i1 = (int)(idx % m.n1);
+    i0 = (int)(idx / m.n1);
+}
+__host__ __device__ inline int64_t mesh_linear(int i0, int i1, int i2, Mesh m) {
+    return ((int64_t)i0 * m.n1 + i1) * m.n2 + i2;
+}
+
+}  // namespace phx

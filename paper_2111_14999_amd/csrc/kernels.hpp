@@ -1,0 +1,117 @@
+// Launchers of the library's HIP kernels (host side).  All return hipError_t of
+// the launch; shapes are validated by the caller before any launch.
+#pragma once
+
+#include "common.hpp"
+
+namespace phx {
+
+// P[p, r] = e^{i 2 pi x_p . R_r}.  Points are either fractional coordinates
+// (frac != nullptr, [np, 3]) or mesh points given by linear index (idx, or
+// 0..np-1 when idx == nullptr) of mesh m.  R packed as int3 on device.
+hipError_t launch_phase_table(const double* frac, const int32_t* idx, Mesh m, int64_t np,
+                              const int32_t* R, int nR, cd* P, int64_t ldp, hipStream_t s);
+
+// C[M, N] = A[M, K] * B[K, N], complex FP64 on MFMA.  Row-major with leading
+// dimensions (in complex elements).
+hipError_t launch_zgemm(const cd* A, int64_t lda, const cd* B, int64_t ldb, cd* C, int64_t ldc,
+                        int64_t M, int64_t N, int K, hipStream_t s);
+
+// Real force constants -> complex mass-weighted Phi(R)/sqrt(M_s M_s').
+hipError_t launch_mass_weight(const double* phi, const double* mass, int nR, int nm, cd* out,
+                              hipStream_t s);
+
+// In-place batched Hermitian eigensolver (cyclic Jacobi, FP64).  A [batch, n, n]
+// is destroyed; w [batch, n] ascending; V [batch, n, n] eigenvectors as columns.
+hipError_t launch_eig_herm(cd* A, int n, int64_t batch, double* w, cd* V, hipStream_t s);
+
+// Phonon post-processing: omega = C_OMEGA sqrt(max(lam, 0)); e[q, sa, nu] =
+// z[q, sa, nu] l_{s, q nu} (0 when omega < omega_min); nb Bose occupation
+// (0 when inactive or kT <= 0).
+hipError_t launch_phonon_post(const double* lam, const cd* z, const double* mass, int nat,
+                              int64_t nq, double omega_min, double kT, double* omega, cd* e,
+                              double* nb, hipStream_t s);
+
+// Fermi occupations of a band table.
+hipError_t launch_fermi(const double* eps, int64_t n, double mu, double kT, double* f,
+                        hipStream_t s);
+
+// Window: mask[k, b] = win_lo < eps[k, b] < win_hi; flag[k] = any(mask[k, :]).
+hipError_t launch_window(const double* eps, int64_t nk, int nW, double lo, double hi,
+                         uint8_t* mask, int32_t* flag, hipStream_t s);
+
+// Ordered compaction of flags: out[j] = j-th index with flag != 0; *count on device.
+hipError_t launch_compact(const int32_t* flag, int64_t n, int32_t* out, int32_t* count,
+                          hipStream_t s);
+
+// Per-band min/max over a band table and the maximum phonon energy.
+hipError_t launch_band_extrema(const double* eps, int64_t nk, int nW, const double* omega,
+                               int64_t nq, int nm, double* bmin, double* bmax, double* wmax,
+                               hipStream_t s);
+
+// Stage-1 fold: F[st, r, sa*nW + b] = sum_a conj(U_k[a, n]) G[kb, r, sa, a, b]
+// for each state st = (kb, n); rows r >= n_rp and columns >= NC are zero.
+hipError_t launch_fold_uk(const cd* G, int64_t ldg, const cd* U, const int32_t* st_krow,
+                          int row0, const int32_t* st_kmesh, const int32_t* st_band, int nst, int n_rp,
+                          int nm, int nW, int rp_pad, int nc_pad, cd* F, hipStream_t s);
+
+struct RateArgs {
+    const cd* F;            // [nst, rp_pad, nc_pad]
+    int rp_pad, nc_pad;
+    int n_rp;
+    const int32_t* rp_packed;  // [n_rp] (R0+r) | (R1+r)<<8 | (R2+r)<<16
+    int rmax;
+    Mesh mesh;
+    int64_t nq_mesh;
+    const int32_t* st_kmesh;   // [nst] mesh index of the state's k
+    const int32_t* st_band;    // [nst]
+    const int32_t* st_row;     // [nst] evaluated-k row of the state
+    const int32_t* st_mlo;     // [nst] first final band to sum
+    const int32_t* st_mhi;     // [nst] last final band to sum (inclusive)
+    const int64_t* q_off;      // per row, or nullptr for full mesh
+    const int32_t* q_idx;
+    const double* q_w;
+    const double* eps;         // [Nk, nW]
+    const double* focc;        // [Nk, nW]
+    const cd* U;               // [Nk, nW, nW]
+    const double* omega;       // [Nq, nm]
+    const double* nb;          // [Nq, nm]
+    const cd* E;               // [Nq, nm, nm] z * l
+    int nW, nm;
+    double sigma;
+    double* partial;           // [nst, n_qtiles]
+    int n_qtiles;
+};
+
+// Fused stage 2 (sum over Rp on MFMA) + rotations + rate terms.
+hipError_t launch_stage2_rates(const RateArgs& a, int nst, hipStream_t s);
+
+// gamma[row, band] = scale * sum_t partial[st, t]
+hipError_t launch_reduce_partials(const double* partial, int nst, int ntiles,
+                                  const int32_t* st_row, const int32_t* st_band, int nW,
+                                  double scale, double* gamma, hipStream_t s);
+
+// interp_g rotation: g[k, q, nu, n, m] from X[q, sa, n, b] of one k.
+hipError_t launch_rotate_g(const cd* X, int64_t nq, const cd* Uk, const cd* Ukq, const cd* E,
+                           int nW, int nm, cd* g, hipStream_t s);
+
+// fold for interp_g (all bands n): F[r, sa, n, b] = sum_a conj(U[a, n]) G[r, sa, a, b]
+hipError_t launch_fold_all(const cd* G, const cd* U, int n_rp, int nm, int nW, cd* F,
+                           hipStream_t s);
+
+hipError_t launch_gather_rows(const uint8_t* mask, const int32_t* kept, int64_t rows, int nW,
+                              int32_t* rowflag, uint8_t* mask_out, int32_t* kept_out,
+                              hipStream_t s);
+hipError_t launch_build_states(const int32_t* ids, int nst, int nW, const int32_t* kept,
+                               const double* eps, const double* bmin, const double* bmax,
+                               const double* wmax, double cut, int32_t* st_row, int32_t* st_band,
+                               int32_t* st_kmesh, int32_t* st_mlo, int32_t* st_mhi,
+                               hipStream_t s);
+int stage2_config(int nm, int nW, int* wq_out, int* tnw_out);
+
+// helpers
+hipError_t launch_kq_points(const double* k, int64_t nk, const double* q, int64_t nq,
+                            double* kq, hipStream_t s);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+
+}  // namespace phx

@@ -1,0 +1,541 @@
+// Dense building blocks on gfx950: phase tables, complex FP64 GEMM on MFMA,
+// batched Hermitian Jacobi eigensolver, phonon/electron post-processing and
+// mesh bookkeeping (window, ordered compaction).
+#include "kernels.hpp"
+
+namespace phx {
+
+// ---------------------------------------------------------------------------
+// Phase table P[p, r] = e^{i 2 pi x_p . R_r}
+// Mesh points use exact integer reduction: x.R = sum_d (i_d R_d mod N_d)/N_d.
+// Fractional points reduce x.R by its nearest integer before sincospi.
+// ---------------------------------------------------------------------------
+__global__ void phase_table_kernel(const double* frac, const int32_t* idx, Mesh m, int64_t np,
+                                   const int32_t* R, int nR, cd* P, int64_t ldp) {
+    const int64_t total = np * (int64_t)nR;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = t / nR;
+        const int r = (int)(t - p * nR);
+        const int r0 = R[3 * r], r1 = R[3 * r + 1], r2 = R[3 * r + 2];
+        double x;
+        if (frac) {
+            const double* f = frac + 3 * p;
+            x = f[0] * r0 + f[1] * r1 + f[2] * r2;
+            x -= rint(x);
+        } else {
+            const int64_t li = idx ? (int64_t)idx[p] : p;
+            int i0, i1, i2;
+            mesh_triple(li, m, i0, i1, i2);
+            int a0 = (int)(((int64_t)i0 * r0) % m.n0);
+            int a1 = (int)(((int64_t)i1 * r1) % m.n1);
+            int a2 = (int)(((int64_t)i2 * r2) % m.n2);
+            if (a0 < 0) a0 += m.n0;
+            if (a1 < 0) a1 += m.n1;
+            if (a2 < 0) a2 += m.n2;
+            x = (double)a0 / m.n0 + (double)a1 / m.n1 + (double)a2 / m.n2;
+            x -= rint(x);
+        }
+        P[p * ldp + r] = expi2pi(x);
+    }
+}
+
+static inline int grid_for(int64_t n, int block) {
+    int64_t g = (n + block - 1) / block;
+    if (g > 65535 * 16) g = 65535 * 16;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+hipError_t launch_phase_table(const double* frac, const int32_t* idx, Mesh m, int64_t np,
+                              const int32_t* R, int nR, cd* P, int64_t ldp, hipStream_t s) {
+    if (np <= 0 || nR <= 0) return hipSuccess;
+    hipLaunchKernelGGL(phase_table_kernel, dim3(grid_for(np * nR, 256)), dim3(256), 0, s, frac,
+                       idx, m, np, R, nR, P, ldp);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Complex FP64 GEMM C = A B on v_mfma_f64_16x16x4f64.
+// A work-group is 4 waves side by side along N; each wave owns TM x TN tiles
+// of 16 x 16.  MFMA operand layouts (16x16x4 f64): lane l holds A[l%16][l/16],
+// B[l/16][l%16]; result v (0..3) of lane l is D[l/16 + 4v][l%16].
+// Complex product with 4 real MFMAs: Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br.
+// ---------------------------------------------------------------------------
+template <int TM, int TN>
+__global__ __launch_bounds__(256) void zgemm_kernel(const cd* __restrict__ A, int64_t lda,
+                                                    const cd* __restrict__ B, int64_t ldb,
+                                                    cd* __restrict__ C, int64_t ldc, int64_t M,
+                                                    int64_t N, int K) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int64_t m0 = (int64_t)blockIdx.y * (16 * TM);
+    const int64_t n0 = ((int64_t)blockIdx.x * 4 + wave) * (16 * TN);
+    if (n0 >= N) return;
+    d4 cr[TM][TN], ci[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            cr[i][j] = d4{0, 0, 0, 0};
+            ci[i][j] = d4{0, 0, 0, 0};
+        }
+    cd a_cur[TM], b_cur[TN];
+    auto load = [&](int k0, cd* av, cd* bv) {
+        const int k = k0 + lk;
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            const int64_t row = m0 + 16 * i + li;
+            av[i] = (row < M && k < K) ? A[row * lda + k] : cd{0.0, 0.0};
+        }
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const int64_t col = n0 + 16 * j + li;
+            bv[j] = (col < N && k < K) ? B[(int64_t)k * ldb + col] : cd{0.0, 0.0};
+        }
+    };
+    load(0, a_cur, b_cur);
+    for (int k0 = 0; k0 < K; k0 += 4) {
+        cd a_nxt[TM], b_nxt[TN];
+        if (k0 + 4 < K) load(k0 + 4, a_nxt, b_nxt);
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            const double ar = a_cur[i].x, ai = a_cur[i].y, nai = -a_cur[i].y;
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, b_cur[j].x, cr[i][j], 0, 0, 0);
+                cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai, b_cur[j].y, cr[i][j], 0, 0, 0);
+                ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, b_cur[j].y, ci[i][j], 0, 0, 0);
+                ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, b_cur[j].x, ci[i][j], 0, 0, 0);
+            }
+        }
+        if (k0 + 4 < K) {
+#pragma unroll
+            for (int i = 0; i < TM; ++i) a_cur[i] = a_nxt[i];
+#pragma unroll
+            for (int j = 0; j < TN; ++j) b_cur[j] = b_nxt[j];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t row = m0 + 16 * i + lk + 4 * v;
+                const int64_t col = n0 + 16 * j + li;
+                if (row < M && col < N) C[row * ldc + col] = cd{cr[i][j][v], ci[i][j][v]};
+            }
+}
+
+hipError_t launch_zgemm(const cd* A, int64_t lda, const cd* B, int64_t ldb, cd* C, int64_t ldc,
+                        int64_t M, int64_t N, int K, hipStream_t s) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    if (K <= 0) return hipErrorInvalidValue;
+    // Tall-and-narrow products (Fourier transforms over many points) use 4 row
+    // tiles per wave; short-and-wide ones (stage 1, M = a batch of k) cover all
+    // rows of up to 128 in one work-group so each B column is read once.
+    if (M <= 64) {
+        const int TM = 4, TN = 2;
+        dim3 grid((unsigned)((N + 4 * 16 * TN - 1) / (4 * 16 * TN)), (unsigned)((M + 63) / 64));
+        hipLaunchKernelGGL((zgemm_kernel<TM, TN>), grid, dim3(256), 0, s, A, lda, B, ldb, C, ldc,
+                           M, N, K);
+    } else if (M <= 128) {
+        const int TM = 8, TN = 1;
+        dim3 grid((unsigned)((N + 4 * 16 * TN - 1) / (4 * 16 * TN)), (unsigned)((M + 127) / 128));
+        hipLaunchKernelGGL((zgemm_kernel<TM, TN>), grid, dim3(256), 0, s, A, lda, B, ldb, C, ldc,
+                           M, N, K);
+    } else {
+        const int TM = 4, TN = 1;
+        dim3 grid((unsigned)((N + 4 * 16 * TN - 1) / (4 * 16 * TN)),
+                  (unsigned)((M + 16 * TM - 1) / (16 * TM)));
+        hipLaunchKernelGGL((zgemm_kernel<TM, TN>), grid, dim3(256), 0, s, A, lda, B, ldb, C, ldc,
+                           M, N, K);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Mass weighting of the force constants: D-kernel entries Phi(R)/sqrt(M_s M_s')
+// ---------------------------------------------------------------------------
+__global__ void mass_weight_kernel(const double* phi, const double* mass, int nR, int nm, cd* out) {
+    const int64_t total = (int64_t)nR * nm * nm;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int j = (int)(t % nm);
+        const int i = (int)((t / nm) % nm);
+        out[t] = cd{phi[t] / sqrt(mass[i / 3] * mass[j / 3]), 0.0};
+    }
+}
+
+hipError_t launch_mass_weight(const double* phi, const double* mass, int nR, int nm, cd* out,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(mass_weight_kernel, dim3(grid_for((int64_t)nR * nm * nm, 256)), dim3(256),
+                       0, s, phi, mass, nR, nm, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batched Hermitian eigensolver: cyclic Jacobi with the round-robin parallel
+// ordering, one wavefront per matrix, matrix and eigenvectors in LDS.
+// Rotation of pivot (p, q) with a = A_pp, d = A_qq, b = A_pq = |b| e^{i phi}:
+//   tau = (d - a) / (2|b|), t = sign(tau) / (|tau| + sqrt(1 + tau^2)),
+//   c = 1/sqrt(1 + t^2), s = t c,
+//   J_pp = J_qq = c, J_pq = s e^{i phi}, J_qp = -s e^{-i phi};  A <- J^H A J, V <- V J.
+// ---------------------------------------------------------------------------
+__device__ inline void rr_pair(int k, int round, int np, int& p, int& q) {
+    const int m = np - 1;
+    int a, b;
+    if (k == 0) {
+        a = m;
+        b = round;
+    } else {
+        a = (round + k) % m;
+        b = (round - k + m) % m;
+    }
+    p = a < b ? a : b;
+    q = a < b ? b : a;
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__global__ __launch_bounds__(64) void eig_herm_kernel(cd* __restrict__ Aall, int n, double* __restrict__ w_out,
+                                                      cd* __restrict__ V_out) {
+    extern __shared__ char smem_raw[];
+    cd* A = reinterpret_cast<cd*>(smem_raw);
+    const int ld = n + 1;
+    cd* V = A + n * ld;
+    double* rc = reinterpret_cast<double*>(V + n * ld);  // [n/2+1] c
+    double* rs = rc + (n / 2 + 1);                         // s
+    cd* re = reinterpret_cast<cd*>(rs + (n / 2 + 1));      // e^{i phi}
+    int* rp = reinterpret_cast<int*>(re + (n / 2 + 1));    // p
+    int* rq = rp + (n / 2 + 1);                            // q
+    const int64_t b = blockIdx.x;
+    const int lane = threadIdx.x;
+    cd* Ag = Aall + b * (int64_t)n * n;
+    for (int i = lane; i < n * n; i += 64) {
+        const int r = i / n, c = i % n;
+        A[r * ld + c] = Ag[i];
+        V[r * ld + c] = cd{r == c ? 1.0 : 0.0, 0.0};
+    }
+    __syncthreads();
+    const int np = n + (n & 1);
+    const int half = np / 2;
+    const double eps2 = 4.9e-32;  // (2.2e-16)^2
+    for (int sweep = 0; sweep < 40 && n > 1; ++sweep) {
+        double off = 0.0, dia = 0.0;
+        for (int i = lane; i < n * n; i += 64) {
+            const int r = i / n, c = i % n;
+            const double v = cabs2(A[r * ld + c]);
+            if (r == c)
+                dia += v;
+            else
+                off += v;
+        }
+        off = wave_sum(off);
+        dia = wave_sum(dia);
+        if (!(off > 1e-32 * dia)) break;
+        for (int round = 0; round < np - 1; ++round) {
+            if (lane < half) {
+                int p, q;
+                rr_pair(lane, round, np, p, q);
+                double c = 1.0, s = 0.0;
+                cd e = {1.0, 0.0};
+                if (q < n) {
+                    const double a = A[p * ld + p].x, d = A[q * ld + q].x;
+                    const cd bpq = A[p * ld + q];
+                    const double bb2 = cabs2(bpq);
+                    if (bb2 > eps2 * fabs(a * d) && bb2 > 0.0) {
+                        const double bb = sqrt(bb2);
+                        const double tau = (d - a) / (2.0 * bb);
+                        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                        c = 1.0 / sqrt(1.0 + t * t);
+                        s = t * c;
+                        e = cd{bpq.x / bb, bpq.y / bb};
+                    }
+                }
+                rc[lane] = c;
+                rs[lane] = s;
+                re[lane] = e;
+                rp[lane] = p;
+                rq[lane] = q < n ? q : -1;
+            }
+            __syncthreads();
+            // rows: A'_pj = c A_pj - s e A_qj ; A'_qj = s conj(e) A_pj + c A_qj
+            for (int it = lane; it < half * n; it += 64) {
+                const int k = it / n, j = it % n;
+                const int q = rq[k];
+                if (q < 0 || rs[k] == 0.0) continue;
+                const int p = rp[k];
+                const double c = rc[k], s = rs[k];
+                const cd e = re[k];
+                const cd apj = A[p * ld + j], aqj = A[q * ld + j];
+                const cd eq = cmul(e, aqj);
+                const cd ep = cmulc(e, apj);
+                A[p * ld + j] = cd{c * apj.x - s * eq.x, c * apj.y - s * eq.y};
+                A[q * ld + j] = cd{s * ep.x + c * aqj.x, s * ep.y + c * aqj.y};
+            }
+            __syncthreads();
+            // columns: A'_ip = c A_ip - s conj(e) A_iq ; A'_iq = s e A_ip + c A_iq ; same for V
+            for (int it = lane; it < 2 * half * n; it += 64) {
+                const int which = it / (half * n);
+                const int r = it % (half * n);
+                const int k = r / n, i = r % n;
+                const int q = rq[k];
+                if (q < 0 || rs[k] == 0.0) continue;
+                const int p = rp[k];
+                const double c = rc[k], s = rs[k];
+                const cd e = re[k];
+                cd* M = which ? V : A;
+                const cd aip = M[i * ld + p], aiq = M[i * ld + q];
+                const cd eq = cmulc(e, aiq);
+                const cd ep = cmul(e, aip);
+                M[i * ld + p] = cd{c * aip.x - s * eq.x, c * aip.y - s * eq.y};
+                M[i * ld + q] = cd{s * ep.x + c * aiq.x, s * ep.y + c * aiq.y};
+            }
+            __syncthreads();
+            if (lane < half) {
+                const int q = rq[lane];
+                if (q >= 0 && rs[lane] != 0.0) {
+                    const int p = rp[lane];
+                    A[p * ld + q] = cd{0.0, 0.0};
+                    A[q * ld + p] = cd{0.0, 0.0};
+                    A[p * ld + p].y = 0.0;
+                    A[q * ld + q].y = 0.0;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // ascending order, ties by index
+    for (int i = lane; i < n; i += 64) {
+        const double wi = A[i * ld + i].x;
+        int rank = 0;
+        for (int j = 0; j < n; ++j) {
+            const double wj = A[j * ld + j].x;
+            rank += (wj < wi) || (wj == wi && j < i);
+        }
+        w_out[b * n + rank] = wi;
+        cd* Vg = V_out + b * (int64_t)n * n;
+        for (int r = 0; r < n; ++r) Vg[r * n + rank] = V[r * ld + i];
+    }
+}
+
+hipError_t launch_eig_herm(cd* A, int n, int64_t batch, double* w, cd* V, hipStream_t s) {
+    if (batch <= 0) return hipSuccess;
+    const int h = n / 2 + 1;
+    const size_t shm = (size_t)2 * n * (n + 1) * sizeof(cd) + 2 * h * sizeof(double) +
+                       h * sizeof(cd) + 2 * h * sizeof(int);
+    for (int64_t b0 = 0; b0 < batch; b0 += 2000000000LL) {
+        const int64_t nb = batch - b0 < 2000000000LL ? batch - b0 : 2000000000LL;
+        hipLaunchKernelGGL(eig_herm_kernel, dim3((unsigned)nb), dim3(64), shm, s,
+                           A + b0 * n * n, n, w + b0 * n, V + b0 * n * n);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Phonon post-processing and occupations
+// ---------------------------------------------------------------------------
+__global__ void phonon_post_kernel(const double* lam, const cd* z, const double* mass, int nat,
+                                   int64_t nq, double omega_min, double kT, double c_om,
+                                   double c_ph, double* omega, cd* e, double* nb) {
+    const int nm = 3 * nat;
+    const int64_t total = nq * nm;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t q = t / nm;
+        const int nu = (int)(t % nm);
+        const double l = lam[t];
+        const double w = c_om * sqrt(l > 0.0 ? l : 0.0);
+        const bool act = w >= omega_min && w > 0.0;
+        if (omega) omega[t] = w;
+        if (nb) nb[t] = (act && kT > 0.0) ? 1.0 / expm1(w / kT) : 0.0;
+        if (e) {
+            for (int sa = 0; sa < nm; ++sa) {
+                const int64_t o = (q * nm + sa) * nm + nu;
+                if (act) {
+                    const double ls = sqrt(c_ph / (2.0 * mass[sa / 3] * w));
+                    e[o] = cd{z[o].x * ls, z[o].y * ls};
+                } else {
+                    e[o] = cd{0.0, 0.0};
+                }
+            }
+        }
+    }
+}
+
+hipError_t launch_phonon_post(const double* lam, const cd* z, const double* mass, int nat,
+                              int64_t nq, double omega_min, double kT, double* omega, cd* e,
+                              double* nb, hipStream_t s) {
+    if (nq <= 0) return hipSuccess;
+    hipLaunchKernelGGL(phonon_post_kernel, dim3(grid_for(nq * 3 * nat, 256)), dim3(256), 0, s, lam,
+                       z, mass, nat, nq, omega_min, kT, c_omega(), kCPh, omega, e, nb);
+    return hipGetLastError();
+}
+
+__global__ void fermi_kernel(const double* eps, int64_t n, double mu, double kT, double* f) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const double x = (eps[t] - mu) / kT;
+        if (x > 0.0) {
+            const double ex = exp(-x);
+            f[t] = ex / (1.0 + ex);
+        } else {
+            f[t] = 1.0 / (1.0 + exp(x));
+        }
+    }
+}
+
+hipError_t launch_fermi(const double* eps, int64_t n, double mu, double kT, double* f,
+                        hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fermi_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, eps, n, mu, kT, f);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Window, ordered compaction, band extrema
+// ---------------------------------------------------------------------------
+__global__ void window_kernel(const double* eps, int64_t nk, int nW, double lo, double hi,
+                              uint8_t* mask, int32_t* flag) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nk;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        int any = 0;
+        for (int b = 0; b < nW; ++b) {
+            const double e = eps[k * nW + b];
+            const int in = (e > lo) && (e < hi);
+            if (mask) mask[k * nW + b] = (uint8_t)in;
+            any |= in;
+        }
+        if (flag) flag[k] = any;
+    }
+}
+
+hipError_t launch_window(const double* eps, int64_t nk, int nW, double lo, double hi,
+                         uint8_t* mask, int32_t* flag, hipStream_t s) {
+    if (nk <= 0) return hipSuccess;
+    hipLaunchKernelGGL(window_kernel, dim3(grid_for(nk, 256)), dim3(256), 0, s, eps, nk, nW, lo,
+                       hi, mask, flag);
+    return hipGetLastError();
+}
+
+// One work-group of 1024 threads scans the flags chunk by chunk in order.
+__global__ __launch_bounds__(1024) void compact_kernel(const int32_t* flag, int64_t n, int32_t* out,
+                                                        int32_t* count) {
+    __shared__ int32_t wsum[16];
+    __shared__ int32_t base_sh;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid == 0) base_sh = 0;
+    __syncthreads();
+    for (int64_t c0 = 0; c0 < n; c0 += 1024) {
+        const int64_t i = c0 + tid;
+        const int f = (i < n && flag[i] != 0) ? 1 : 0;
+        // inclusive scan within the wave
+        int v = f;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int u = __shfl_up(v, o, 64);
+            if (lane >= o) v += u;
+        }
+        if (lane == 63) wsum[wave] = v;
+        __syncthreads();
+        int before = 0;
+        for (int w = 0; w < wave; ++w) before += wsum[w];
+        const int base = base_sh;
+        if (f) out[base + before + v - 1] = (int32_t)i;
+        __syncthreads();
+        if (tid == 1023) base_sh = base + before + v;
+        __syncthreads();
+    }
+    if (tid == 0) *count = base_sh;
+}
+
+hipError_t launch_compact(const int32_t* flag, int64_t n, int32_t* out, int32_t* count,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(compact_kernel, dim3(1), dim3(1024), 0, s, flag, n, out, count);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void extrema_kernel(const double* eps, int64_t nk, int nW,
+                                                      const double* omega, int64_t nq, int nm,
+                                                      double* bmin, double* bmax, double* wmax) {
+    __shared__ double s1[256], s2[256];
+    const int b = blockIdx.x;  // b < nW: band b; b == nW: phonon maximum
+    double lo = 1e300, hi = -1e300;
+    if (b < nW) {
+        for (int64_t k = threadIdx.x; k < nk; k += 256) {
+            const double e = eps[k * nW + b];
+            lo = fmin(lo, e);
+            hi = fmax(hi, e);
+        }
+    } else {
+        for (int64_t t = threadIdx.x; t < nq * nm; t += 256) hi = fmax(hi, omega[t]);
+    }
+    s1[threadIdx.x] = lo;
+    s2[threadIdx.x] = hi;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            s1[threadIdx.x] = fmin(s1[threadIdx.x], s1[threadIdx.x + o]);
+            s2[threadIdx.x] = fmax(s2[threadIdx.x], s2[threadIdx.x + o]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (b < nW) {
+            bmin[b] = s1[0];
+            bmax[b] = s2[0];
+        } else {
+            *wmax = s2[0];
+        }
+    }
+}
+
+hipError_t launch_band_extrema(const double* eps, int64_t nk, int nW, const double* omega,
+                               int64_t nq, int nm, double* bmin, double* bmax, double* wmax,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(extrema_kernel, dim3(nW + 1), dim3(256), 0, s, eps, nk, nW, omega, nq, nm,
+                       bmin, bmax, wmax);
+    return hipGetLastError();
+}
+
+__global__ void kq_kernel(const double* k, int64_t nk, const double* q, int64_t nq, double* kq) {
+    const int64_t total = nk * nq;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = t / nq, j = t % nq;
+        for (int d = 0; d < 3; ++d) kq[3 * t + d] = k[3 * i + d] + q[3 * j + d];
+    }
+}
+
+hipError_t launch_kq_points(const double* k, int64_t nk, const double* q, int64_t nq,
+                            double* kq, hipStream_t s) {
+    if (nk * nq <= 0) return hipSuccess;
+    hipLaunchKernelGGL(kq_kernel, dim3(grid_for(nk * nq, 256)), dim3(256), 0, s, k, nk, q, nq, kq);
+    return hipGetLastError();
+}
+
+// Fill with zeros by a kernel (safe under stream capture).
+__global__ void zero_kernel(uint32_t* p, int64_t n, uint8_t* tail, int ntail) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x)
+        p[t] = 0u;
+    if (blockIdx.x == 0 && (int)threadIdx.x < ntail) tail[threadIdx.x] = 0;
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return hipSuccess;
+    // buffers come from the workspace or the caller and are at least 4-byte aligned
+    const int64_t n = (int64_t)(bytes / 4);
+    const int ntail = (int)(bytes % 4);
+    hipLaunchKernelGGL(zero_kernel, dim3(grid_for(n > 0 ? n : 1, 256)), dim3(256), 0, s,
+                       (uint32_t*)p, n, (uint8_t*)p + 4 * n, ntail);
+    return hipGetLastError();
+}
+
+}  // namespace phx

@@ -94,11 +94,13 @@ def perovskite_structure():
     return pos, [0.5, math.sqrt(2.0) / 2.0]
 
 
-def random_structure(seed: int, n_atoms: int, min_sep: float = 0.25, cutoff: float = 0.75):
+def random_structure(seed: int, n_atoms: int, min_sep: float = 0.25, cutoff: float = 1.01):
     """n_atoms random positions in the unit cell, pairwise periodic distance >= min_sep.
 
     Bonds are drawn to every neighbour closer than ``cutoff`` (returned as a
-    single open shell ``('cutoff', cutoff)``).
+    single open shell ``('cutoff', cutoff)``).  The default 1.01 A includes each
+    atom's own periodic images along the axes, which keeps the spring network
+    free of soft modes away from q = 0.
     """
     rng = _rng(seed, _TAG_POS)
     for _ in range(10000):
