@@ -521,8 +521,8 @@ phoebe_status phoebe_gpu_scatter_rates(void* handle, const phoebe_system* sys,
             set_err(h, "this build implements the FP64 contractions only");
             throw Fail{PHOEBE_E_UNSUPPORTED};
         }
-        int wq = 0, tnw = 0;
-        const int nc_pad = stage2_config(nm, nW, &wq, &tnw);
+        int tq = 0, tn = 0;
+        const int nc_pad = stage2_config(nm, nW, &tq, &tn);
         if (nc_pad < 0) {
             set_err(h, "no stage-2 tiling for nModes*nW = %d", nm * nW);
             throw Fail{PHOEBE_E_UNSUPPORTED};
@@ -536,9 +536,9 @@ phoebe_status phoebe_gpu_scatter_rates(void* handle, const phoebe_system* sys,
         // kept k points per stage-1 batch: G and F of a batch stay under 8 GB each
         int BK = 64;
         while (BK > 16 && ((double)BK * NC2 * sizeof(cd) > 8e9 ||
-                           (double)BK * nW * rp_pad * NC2 / n_rp * sizeof(cd) > 8e9))
+                           (double)BK * nW * rp_pad * nc_pad * sizeof(cd) > 8e9))
             BK /= 2;
-        const int BQ = 16 * wq;
+        const int BQ = 16 * tq;
 
         // q-list lengths (host) for the tile count
         int64_t max_list = N;

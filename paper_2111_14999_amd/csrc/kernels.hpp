@@ -107,7 +107,7 @@ hipError_t launch_build_states(const int32_t* ids, int nst, int nW, const int32_
                                const double* wmax, double cut, int32_t* st_row, int32_t* st_band,
                                int32_t* st_kmesh, int32_t* st_mlo, int32_t* st_mhi,
                                hipStream_t s);
-int stage2_config(int nm, int nW, int* wq_out, int* tnw_out);
+int stage2_config(int nm, int nW, int* tq_out, int* tn_out);
 
 // helpers
 hipError_t launch_kq_points(const double* k, int64_t nk, const double* q, int64_t nq,

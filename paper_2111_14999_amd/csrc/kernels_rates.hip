@@ -58,36 +58,45 @@ hipError_t launch_fold_uk(const cd* G, int64_t ldg, const cd* U, const int32_t* 
 // ---------------------------------------------------------------------------
 // Fused stage 2 + rotations + rate terms.
 //
-// Work-group = 4 waves = one state x BQ = 16*WQ q points.  Waves are arranged
-// WQ (q row tiles) x WC (column groups); each wave holds TNW 16-column tiles
-// of X[q, sa*nW + b] = sum_Rp e^{i2pi q.Rp} F[Rp, sa*nW + b] in MFMA
-// accumulators.  The phase of (q, Rp) is the product of three per-axis
+// Work-group = 4 waves = one state x BQ = 16*TQ q points.  Every wave holds the
+// same TQ row tiles of 16 q and its own TN column tiles of 16 columns of
+//   X[q, sa*nW + b] = sum_Rp e^{i2pi q.Rp} F[Rp, sa*nW + b],
+// so nc_pad = 64*TN.  The phase of (q, Rp) is the product of three per-axis
 // factors e^{i2pi (i_d R_d mod N_d)/N_d} kept in LDS for the tile's q points.
+// MFMA f64 16x16x4 layouts: lane l holds A[l%16][l/16] and B[l/16][l%16];
+// result v of lane l is row l/16 + 4v, column l%16.
 //
-// The rotation runs in two chunks of 8 rows per row tile: the chunk's X goes
-// to LDS, then each (q, m) item forms Y[sa] = sum_b X[q, sa, b] U_{k+q}[b, m],
-// Z[nu] = sum_sa E_q[sa, nu] Y[sa] and the rate terms
+// The rotation runs in four chunks (one per result index v, 4*TQ q rows):
+// the chunk's X goes to LDS; threads over (q, m, sa) form
+// Y[q, sa, m] = sum_b X[q, sa, b] U_{k+q}[b, m]; threads over (q, m, nu) form
+// Z = sum_sa E_q[sa, nu] Y[q, sa, m] and the rate terms
 //   |Z|^2 [(n+1-f) G(x - w) + (n+f) G(x + w)],  G(y) = exp(-y^2/sigma^2),
 // x = eps_nk - eps_{m,k+q}.  Final bands outside [mlo, mhi] are skipped: their
 // Gaussians underflow to exactly zero in FP64 for every mode.
 // ---------------------------------------------------------------------------
-template <int WQ, int TNW, int NMX>
-__global__ __launch_bounds__(256, 1) void stage2_rates_kernel(RateArgs a) {
-    constexpr int BQ = 16 * WQ;
-    constexpr int CQ = 8 * WQ;
+constexpr int kMB = 8;  // final bands per rotation pass
+
+template <int TQ, int TN>
+__global__ __launch_bounds__(256, (TN >= 12 ? 1 : 2)) void stage2_rates_kernel(RateArgs a) {
+    constexpr int BQ = 16 * TQ;
+    constexpr int CQ = 4 * TQ;  // q rows per rotation chunk
     extern __shared__ char smem_raw[];
     const int W = 2 * a.rmax + 1;
+    const int nW = a.nW, nm = a.nm;
     cd* sAx = reinterpret_cast<cd*>(smem_raw);               // [BQ][3][W]
     int* sRp = reinterpret_cast<int*>(sAx + BQ * 3 * W);     // [rp_pad]
     size_t off = (size_t)BQ * 3 * W * sizeof(cd) + (size_t)a.rp_pad * sizeof(int);
     off = (off + 15) & ~(size_t)15;
     cd* sX = reinterpret_cast<cd*>(smem_raw + off);           // [CQ][nc_pad]
+    cd* sY = sX + CQ * a.nc_pad;                              // [CQ][kMB][nm]
     __shared__ double sRed[4];
+    __shared__ int sKq[CQ];
+    __shared__ int sQ[CQ];
+    __shared__ double sWq[CQ];
 
     const int st = blockIdx.y;
     const int qt = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wq = wave % WQ, wc = wave / WQ;
     const int li = lane & 15, lg = lane >> 4;
     const int row = a.st_row[st];
     int64_t qbeg = 0, qcount = a.nq_mesh;
@@ -126,47 +135,60 @@ __global__ __launch_bounds__(256, 1) void stage2_rates_kernel(RateArgs a) {
     __syncthreads();
 
     // ---- stage 2 on MFMA ----
-    d4 cr[TNW], ci[TNW];
+    d4 cr[TQ][TN], ci[TQ][TN];
 #pragma unroll
-    for (int t = 0; t < TNW; ++t) {
-        cr[t] = d4{0, 0, 0, 0};
-        ci[t] = d4{0, 0, 0, 0};
-    }
+    for (int i = 0; i < TQ; ++i)
+#pragma unroll
+        for (int t = 0; t < TN; ++t) {
+            cr[i][t] = d4{0, 0, 0, 0};
+            ci[i][t] = d4{0, 0, 0, 0};
+        }
     const cd* Fst = a.F + (int64_t)st * a.rp_pad * a.nc_pad;
-    const int qlocal = wq * 16 + li;
-    const cd* ax0 = sAx + qlocal * 3 * W;
-    const cd* ax1 = ax0 + W;
-    const cd* ax2 = ax1 + W;
-    const int colbase = wc * TNW * 16 + li;
+    const int colbase = wave * TN * 16 + li;
     const int ldf = a.nc_pad;
-    cd bc[TNW];
+    // B fragments of step k+4 are loaded while the MFMAs of step k run
+    cd bc[TN];
     {
         const cd* Fr = Fst + (int64_t)lg * ldf + colbase;
 #pragma unroll
-        for (int t = 0; t < TNW; ++t) bc[t] = Fr[t * 16];
+        for (int t = 0; t < TN; ++t) bc[t] = Fr[t * 16];
     }
     for (int k0 = 0; k0 < a.rp_pad; k0 += 4) {
         const int k = k0 + lg;
         const int pk = sRp[k];
-        const cd ph = cmul(cmul(ax0[pk & 255], ax1[(pk >> 8) & 255]), ax2[(pk >> 16) & 255]);
-        const double ar = ph.x, ai = ph.y, nai = -ph.y;
-        cd bn[TNW];
+        const int p0 = pk & 255, p1 = (pk >> 8) & 255, p2 = (pk >> 16) & 255;
+        cd bn[TN];
         const bool more = k0 + 4 < a.rp_pad;
         if (more) {
             const cd* Fr = Fst + (int64_t)(k + 4) * ldf + colbase;
 #pragma unroll
-            for (int t = 0; t < TNW; ++t) bn[t] = Fr[t * 16];
+            for (int t = 0; t < TN; ++t) bn[t] = Fr[t * 16];
+        }
+        double ar[TQ], ai[TQ];
+#pragma unroll
+        for (int i = 0; i < TQ; ++i) {
+            const cd* ax = sAx + (16 * i + li) * 3 * W;
+            const cd ph = cmul(cmul(ax[p0], ax[W + p1]), ax[2 * W + p2]);
+            ar[i] = ph.x;
+            ai[i] = ph.y;
         }
 #pragma unroll
-        for (int t = 0; t < TNW; ++t) {
-            cr[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bc[t].x, cr[t], 0, 0, 0);
-            cr[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai, bc[t].y, cr[t], 0, 0, 0);
-            ci[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bc[t].y, ci[t], 0, 0, 0);
-            ci[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bc[t].x, ci[t], 0, 0, 0);
-        }
+        for (int i = 0; i < TQ; ++i)
+#pragma unroll
+            for (int t = 0; t < TN; ++t) {
+                cr[i][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bc[t].x, cr[i][t], 0, 0, 0);
+                ci[i][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bc[t].y, ci[i][t], 0, 0, 0);
+            }
+#pragma unroll
+        for (int i = 0; i < TQ; ++i)
+#pragma unroll
+            for (int t = 0; t < TN; ++t) {
+                cr[i][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai[i], bc[t].y, cr[i][t], 0, 0, 0);
+                ci[i][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], bc[t].x, ci[i][t], 0, 0, 0);
+            }
         if (more) {
 #pragma unroll
-            for (int t = 0; t < TNW; ++t) bc[t] = bn[t];
+            for (int t = 0; t < TN; ++t) bc[t] = bn[t];
         }
     }
 
@@ -174,68 +196,77 @@ __global__ __launch_bounds__(256, 1) void stage2_rates_kernel(RateArgs a) {
     const int kmesh = a.st_kmesh[st];
     const int nband = a.st_band[st];
     const int mlo = a.st_mlo[st], mhi = a.st_mhi[st];
-    const int n_m = mhi - mlo + 1;
-    const int nW = a.nW, nm = a.nm;
     int k0i, k1i, k2i;
     mesh_triple(kmesh, mesh, k0i, k1i, k2i);
     const double eps_n = a.eps[(int64_t)kmesh * nW + nband];
     const double inv_s2 = 1.0 / (a.sigma * a.sigma);
     double gacc = 0.0;
 #pragma unroll
-    for (int ch = 0; ch < 2; ++ch) {
+    for (int v = 0; v < 4; ++v) {
         __syncthreads();
-        // result v of lane group lg is tile row lg + 4v: this chunk holds rows
-        // 8ch .. 8ch+7, i.e. v = 2ch and 2ch+1 of every lane
+        // chunk row c = 4*i + lg holds tile row 16*i + lg + 4*v
 #pragma unroll
-        for (int t = 0; t < TNW; ++t)
+        for (int i = 0; i < TQ; ++i)
 #pragma unroll
-            for (int vv = 0; vv < 2; ++vv) {
-                const int v = 2 * ch + vv;
-                const int qr = wq * 8 + lg + 4 * vv;
-                sX[qr * ldf + colbase + t * 16] = cd{cr[t][v], ci[t][v]};
-            }
-        __syncthreads();
-        if (n_m <= 0) continue;
-        for (int it = tid; it < CQ * n_m; it += 256) {
-            const int qc = it / n_m;
-            const int m = mlo + (it - qc * n_m);
-            const int qloc = (qc / 8) * 16 + 8 * ch + (qc % 8);
+            for (int t = 0; t < TN; ++t)
+                sX[(4 * i + lg) * ldf + colbase + t * 16] = cd{cr[i][t][v], ci[i][t][v]};
+        if (tid < CQ) {
+            const int c = tid;
+            const int qloc = 16 * (c >> 2) + (c & 3) + 4 * v;
             const int64_t j = qt0 + qloc;
-            if (j >= qcount) continue;
-            const int64_t q = a.q_idx ? (int64_t)a.q_idx[qbeg + j] : j;
-            const double wq_ = a.q_w ? a.q_w[qbeg + j] : 1.0;
-            int q0, q1, q2;
-            mesh_triple(q, mesh, q0, q1, q2);
-            const int64_t kq = mesh_linear((k0i + q0) % mesh.n0, (k1i + q1) % mesh.n1,
-                                           (k2i + q2) % mesh.n2, mesh);
-            const cd* Xq = sX + qc * ldf;
-            const cd* Uc = a.U + kq * nW * nW + m;
-            cd Y[NMX];
-#pragma unroll
-            for (int s = 0; s < NMX; ++s) Y[s] = cd{0.0, 0.0};
-            for (int b = 0; b < nW; ++b) {
-                const cd u = Uc[(int64_t)b * nW];
-#pragma unroll
-                for (int s = 0; s < NMX; ++s)
-                    if (s < nm) Y[s] = cfma(Xq[s * nW + b], u, Y[s]);
+            int kq = -1, q = 0;
+            double w = 0.0;
+            if (j < qcount) {
+                q = a.q_idx ? a.q_idx[qbeg + j] : (int)j;
+                w = a.q_w ? a.q_w[qbeg + j] : 1.0;
+                int q0, q1, q2;
+                mesh_triple(q, mesh, q0, q1, q2);
+                kq = (int)mesh_linear((k0i + q0) % mesh.n0, (k1i + q1) % mesh.n1,
+                                      (k2i + q2) % mesh.n2, mesh);
             }
-            const double x = eps_n - a.eps[kq * nW + m];
-            const double fm = a.focc[kq * nW + m];
-            const cd* Eq = a.E + q * nm * nm;
-            const double* wv = a.omega + q * nm;
-            const double* nv = a.nb + q * nm;
-            double tsum = 0.0;
-            for (int nu = 0; nu < nm; ++nu) {
+            sKq[c] = kq;
+            sQ[c] = q;
+            sWq[c] = w;
+        }
+        __syncthreads();
+        for (int m0 = mlo; m0 <= mhi; m0 += kMB) {
+            const int nmb = min(kMB, mhi - m0 + 1);
+            // Y[c, mb, sa] = sum_b X[c, sa*nW + b] U_{k+q}[b, m0 + mb]
+            for (int it = tid; it < CQ * nmb * nm; it += 256) {
+                const int c = it / (nmb * nm);
+                const int r = it - c * nmb * nm;
+                const int mb = r / nm, sa = r - mb * nm;
+                const int kq = sKq[c];
+                cd y = {0.0, 0.0};
+                if (kq >= 0) {
+                    const cd* Xr = sX + c * ldf + sa * nW;
+                    const cd* Uc = a.U + (int64_t)kq * nW * nW + m0 + mb;
+                    for (int b = 0; b < nW; ++b) y = cfma(Xr[b], Uc[(int64_t)b * nW], y);
+                }
+                sY[(c * kMB + mb) * nm + sa] = y;
+            }
+            __syncthreads();
+            // Z[c, mb, nu] = sum_sa E_q[sa, nu] Y[c, mb, sa]; rate terms
+            for (int it = tid; it < CQ * nmb * nm; it += 256) {
+                const int c = it / (nmb * nm);
+                const int r = it - c * nmb * nm;
+                const int mb = r / nm, nu = r - mb * nm;
+                const int kq = sKq[c];
+                if (kq < 0) continue;
+                const int64_t q = sQ[c];
+                const cd* Yr = sY + (c * kMB + mb) * nm;
+                const cd* Eq = a.E + q * nm * nm + nu;
                 cd z = {0.0, 0.0};
-#pragma unroll
-                for (int s = 0; s < NMX; ++s)
-                    if (s < nm) z = cfma(Eq[s * nm + nu], Y[s], z);
-                const double w = wv[nu], nbq = nv[nu];
+                for (int sa = 0; sa < nm; ++sa) z = cfma(Eq[sa * nm], Yr[sa], z);
+                const int m = m0 + mb;
+                const double x = eps_n - a.eps[(int64_t)kq * nW + m];
+                const double fm = a.focc[(int64_t)kq * nW + m];
+                const double w = a.omega[q * nm + nu], nbq = a.nb[q * nm + nu];
                 const double y1 = x - w, y2 = x + w;
                 const double g1 = exp(-y1 * y1 * inv_s2), g2 = exp(-y2 * y2 * inv_s2);
-                tsum += cabs2(z) * ((nbq + 1.0 - fm) * g1 + (nbq + fm) * g2);
+                gacc += sWq[c] * cabs2(z) * ((nbq + 1.0 - fm) * g1 + (nbq + fm) * g2);
             }
-            gacc += wq_ * tsum;
+            __syncthreads();
         }
     }
     // fixed-order reduction of the work-group's partial sum
@@ -247,15 +278,19 @@ __global__ __launch_bounds__(256, 1) void stage2_rates_kernel(RateArgs a) {
         a.partial[(int64_t)st * a.n_qtiles + qt] = (sRed[0] + sRed[1]) + (sRed[2] + sRed[3]);
 }
 
-template <int WQ, int TNW, int NMX>
-static hipError_t go_stage2(const RateArgs& a, int nst, hipStream_t s) {
-    constexpr int BQ = 16 * WQ, CQ = 8 * WQ;
-    const int W = 2 * a.rmax + 1;
-    size_t shm = (size_t)BQ * 3 * W * sizeof(cd) + (size_t)a.rp_pad * sizeof(int);
+static size_t stage2_lds(int TQ, int rmax, int rp_pad, int nc_pad, int nm) {
+    const int BQ = 16 * TQ, CQ = 4 * TQ, W = 2 * rmax + 1;
+    size_t shm = (size_t)BQ * 3 * W * sizeof(cd) + (size_t)rp_pad * sizeof(int);
     shm = (shm + 15) & ~(size_t)15;
-    shm += (size_t)CQ * a.nc_pad * sizeof(cd);
-    if (shm > 160 * 1024 - 64) return hipErrorInvalidValue;
-    hipError_t e = hipFuncSetAttribute((const void*)stage2_rates_kernel<WQ, TNW, NMX>,
+    shm += (size_t)CQ * nc_pad * sizeof(cd) + (size_t)CQ * kMB * nm * sizeof(cd);
+    return shm;
+}
+
+template <int TQ, int TN>
+static hipError_t go_stage2(const RateArgs& a, int nst, hipStream_t s) {
+    const size_t shm = stage2_lds(TQ, a.rmax, a.rp_pad, a.nc_pad, a.nm);
+    if (shm > 160 * 1024 - 1024) return hipErrorInvalidValue;
+    hipError_t e = hipFuncSetAttribute((const void*)stage2_rates_kernel<TQ, TN>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) return e;
     for (int s0 = 0; s0 < nst; s0 += 65535) {
@@ -268,66 +303,36 @@ static hipError_t go_stage2(const RateArgs& a, int nst, hipStream_t s) {
         b.st_mlo += s0;
         b.st_mhi += s0;
         b.partial = a.partial + (int64_t)s0 * a.n_qtiles;
-        hipLaunchKernelGGL((stage2_rates_kernel<WQ, TNW, NMX>), dim3(a.n_qtiles, ns), dim3(256),
-                           shm, s, b);
+        hipLaunchKernelGGL((stage2_rates_kernel<TQ, TN>), dim3(a.n_qtiles, ns), dim3(256), shm, s,
+                           b);
     }
     return hipGetLastError();
 }
 
-// Column layout: nc = nm*nW split into 16-wide tiles; nc_pad = 16 * WC * TNW.
-int stage2_config(int nm, int nW, int* wq_out, int* tnw_out) {
+// Column tiling of nc = nm*nW: 4 waves x TN tiles of 16 (nc_pad = 64 TN) and
+// TQ row tiles of 16 q per work-group.  Returns nc_pad and the q tile BQ.
+int stage2_config(int nm, int nW, int* tq_out, int* tn_out) {
     const int nt = (nm * nW + 15) / 16;
-    if (nt <= 16) {
-        static const int opts[] = {1, 2, 3, 4, 6, 8, 12, 15, 16};
-        for (int o : opts)
-            if (o >= nt) {
-                *wq_out = 4;
-                *tnw_out = o;
-                return 16 * o;
-            }
-    }
-    if (nt <= 32) {  // WQ = 2, WC = 2
-        const int t = (nt + 1) / 2;
-        static const int opts[] = {9, 12, 16};
-        for (int o : opts)
-            if (o >= t) {
-                *wq_out = 2;
-                *tnw_out = o;
-                return 16 * 2 * o;
-            }
-    }
-    if (nt <= 64) {  // WQ = 1, WC = 4
-        const int t = (nt + 3) / 4;
-        static const int opts[] = {9, 12, 16};
-        for (int o : opts)
-            if (o >= t) {
-                *wq_out = 1;
-                *tnw_out = o;
-                return 16 * 4 * o;
-            }
+    static const int tns[] = {1, 2, 3, 4, 6, 8, 12, 16};
+    for (int tn : tns) {
+        if (4 * tn >= nt) {
+            *tn_out = tn;
+            *tq_out = tn <= 2 ? 4 : (tn <= 4 ? 2 : 1);
+            return 64 * tn;
+        }
     }
     return -1;
 }
 
-template <int NMX>
-static hipError_t dispatch_stage2(const RateArgs& a, int nst, int wq, int tnw, hipStream_t s) {
-#define PHX_CASE(WQv, TNWv) \
-    if (wq == WQv && tnw == TNWv) return go_stage2<WQv, TNWv, NMX>(a, nst, s);
-    PHX_CASE(4, 1) PHX_CASE(4, 2) PHX_CASE(4, 3) PHX_CASE(4, 4) PHX_CASE(4, 6) PHX_CASE(4, 8)
-    PHX_CASE(4, 12) PHX_CASE(4, 15) PHX_CASE(4, 16)
-    PHX_CASE(2, 9) PHX_CASE(2, 12) PHX_CASE(2, 16)
-    PHX_CASE(1, 9) PHX_CASE(1, 12) PHX_CASE(1, 16)
-#undef PHX_CASE
-    return hipErrorInvalidValue;
-}
-
 hipError_t launch_stage2_rates(const RateArgs& a, int nst, hipStream_t s) {
     if (nst <= 0 || a.n_qtiles <= 0) return hipSuccess;
-    int wq = 0, tnw = 0;
-    if (stage2_config(a.nm, a.nW, &wq, &tnw) != a.nc_pad) return hipErrorInvalidValue;
-    if (a.nm <= 8) return dispatch_stage2<8>(a, nst, wq, tnw, s);
-    if (a.nm <= 16) return dispatch_stage2<16>(a, nst, wq, tnw, s);
-    if (a.nm <= 32) return dispatch_stage2<32>(a, nst, wq, tnw, s);
+    int tq = 0, tn = 0;
+    if (stage2_config(a.nm, a.nW, &tq, &tn) != a.nc_pad) return hipErrorInvalidValue;
+#define PHX_CASE(TQv, TNv) \
+    if (tq == TQv && tn == TNv) return go_stage2<TQv, TNv>(a, nst, s);
+    PHX_CASE(4, 1) PHX_CASE(4, 2) PHX_CASE(2, 3) PHX_CASE(2, 4) PHX_CASE(1, 6) PHX_CASE(1, 8)
+    PHX_CASE(1, 12) PHX_CASE(1, 16)
+#undef PHX_CASE
     return hipErrorInvalidValue;
 }
 
