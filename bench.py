@@ -50,6 +50,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=6, help="kept k points timed on the oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--interp-k", type=int, default=2, help="k points of the interp_g rate run")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3", "bf16x6"])
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -78,7 +79,8 @@ def main():
     kept = torch.zeros((N,), dtype=torch.int32, device="cuda")
 
     def step():
-        return lib.scatter_rates(ds, mesh, par, gamma, band_mask=mask, kept_k_out=kept)
+        return lib.scatter_rates(ds, mesh, par, gamma, band_mask=mask, kept_k_out=kept,
+                                 precision=args.precision)
 
     for i in range(args.warmup):
         n_kept = step()
@@ -107,8 +109,12 @@ def main():
     avg_ms = ms_st2 / max(n_st2, 1)
     launches_per_step = n_st2 / args.steps
     achieved = flops_st2 / launches_per_step / (avg_ms * 1e-3) / 1e12 if n_st2 else 0.0
-    roofline = dict(bound="mfma", achieved=round(achieved, 3), peak=PEAK_FP64_TFLOPS,
-                    unit="TFLOP/s", frac=round(achieved / PEAK_FP64_TFLOPS, 4), traffic=None,
+    # peak of the MFMA the form runs on; split-BF16 executes 3 or 6 BF16 products per
+    # real product, so its complex-GEMM flops are measured against BF16 peak / products
+    peak = {"fp64": PEAK_FP64_TFLOPS, "fp32": 157.3, "bf16x3": 2500.0 / 3,
+            "bf16x6": 2500.0 / 6}[args.precision]
+    roofline = dict(bound="mfma", achieved=round(achieved, 3), peak=round(peak, 2),
+                    unit="TFLOP/s", frac=round(achieved / peak, 4), traffic=None,
                     kernel="stage2_rates", launches_per_step=launches_per_step,
                     avg_launch_ms=round(avg_ms, 4),
                     flops_per_launch=flops_st2 / max(launches_per_step, 1))
@@ -122,10 +128,10 @@ def main():
         qf = torch.from_numpy(mesh_points_frac(mesh, np.arange(N))).cuda()
         nk_i = kf.shape[0]
         gout = torch.empty((nk_i, N, nm, nW, nW), dtype=torch.complex128, device="cuda")
-        lib.interp_g(ds, kf, qf, gout, omega_min=par["omega_min"])
+        lib.interp_g(ds, kf, qf, gout, omega_min=par["omega_min"], precision=args.precision)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        lib.interp_g(ds, kf, qf, gout, omega_min=par["omega_min"])
+        lib.interp_g(ds, kf, qf, gout, omega_min=par["omega_min"], precision=args.precision)
         torch.cuda.synchronize()
         ti = time.perf_counter() - t1
         gel = nk_i * N * nm * nW * nW / ti
@@ -170,7 +176,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3+f32acc",
+                  "bf16x6": "bf16x6+f32acc"}[args.precision],
         "data": "synthetic",
         "config": {
             "workload": (f"{args.workload}: {s.n_atoms} atoms ({nm} modes), nW={nW}, "

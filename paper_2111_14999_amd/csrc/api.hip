@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "lowp.hpp"
 
 using namespace phx;
 
@@ -404,10 +405,8 @@ phoebe_status phoebe_gpu_interp_g(void* handle, const phoebe_system* sys, const 
             set_err(h, "nW > 32 or nModes > 32 is not supported");
             throw Fail{PHOEBE_E_UNSUPPORTED};
         }
-        if (prec != PHOEBE_FP64) {
-            set_err(h, "interp_g implements the FP64 contractions only");
-            throw Fail{PHOEBE_E_UNSUPPORTED};
-        }
+        const bool lowp = prec != PHOEBE_FP64;
+        const size_t el = lowp ? sizeof(cf) : sizeof(cd);
         HIPCHK(h, hipSetDevice(h->device));
         const int n_re = sys->n_re, n_rp = sys->n_rp;
         const int64_t NC3 = (int64_t)nm * nW * nW;
@@ -427,10 +426,10 @@ phoebe_status phoebe_gpu_interp_g(void* handle, const phoebe_system* sys, const 
             double* om = omega_q ? omega_q : ar.take<double>((size_t)nq * nm);
             cd* E = ar.take<cd>((size_t)nq * nm * nm);
             cd* Pe = ar.take<cd>((size_t)kb * n_re);
-            cd* G1 = ar.take<cd>((size_t)kb * n_rp * NC3);
+            char* G1 = ar.take<char>((size_t)kb * n_rp * NC3 * el);
             cd* Pp = ar.take<cd>((size_t)nq * n_rp);
-            cd* F = ar.take<cd>((size_t)n_rp * NC3);
-            cd* X = ar.take<cd>((size_t)qchunk * NC3);
+            char* F = ar.take<char>((size_t)n_rp * NC3 * el);
+            char* X = ar.take<char>((size_t)qchunk * NC3 * el);
             {
                 Arena sub = ar;  // band scratch, reused after the tables are built
                 electron_bands_dev(h, sub, sys, rh, k_frac, nullptr, Mesh{1, 1, 1}, nk, ek, Uk, s);
@@ -450,23 +449,44 @@ phoebe_status phoebe_gpu_interp_g(void* handle, const phoebe_system* sys, const 
                 HIPCHK(h, launch_phase_table(k_frac + 3 * k0, nullptr, Mesh{1, 1, 1}, nb, re, n_re,
                                              Pe, n_re, s));
                 Timer t1(h, s, "stage1_phase");
-                HIPCHK(h, launch_zgemm(Pe, n_re, reinterpret_cast<const cd*>(sys->g_rr),
-                                       (int64_t)n_rp * NC3, G1, (int64_t)n_rp * NC3, nb,
-                                       (int64_t)n_rp * NC3, n_re, s));
+                if (lowp)
+                    HIPCHK(h, launch_cgemm_lp(prec, Pe, n_re, reinterpret_cast<const cd*>(sys->g_rr),
+                                              (int64_t)n_rp * NC3, reinterpret_cast<cf*>(G1),
+                                              (int64_t)n_rp * NC3, nb, (int64_t)n_rp * NC3, n_re, s));
+                else
+                    HIPCHK(h, launch_zgemm(Pe, n_re, reinterpret_cast<const cd*>(sys->g_rr),
+                                           (int64_t)n_rp * NC3, reinterpret_cast<cd*>(G1),
+                                           (int64_t)n_rp * NC3, nb, (int64_t)n_rp * NC3, n_re, s));
                 t1.done();
                 for (int64_t i = 0; i < nb; ++i) {
                     const int64_t k = k0 + i;
-                    HIPCHK(h, launch_fold_all(G1 + i * n_rp * NC3, Uk + k * nW * nW, n_rp, nm, nW,
-                                              F, s));
+                    if (lowp)
+                        HIPCHK(h, launch_fold_all_lp(reinterpret_cast<const cf*>(G1) + i * n_rp * NC3,
+                                                     Uk + k * nW * nW, n_rp, nm, nW,
+                                                     reinterpret_cast<cf*>(F), s));
+                    else
+                        HIPCHK(h, launch_fold_all(reinterpret_cast<const cd*>(G1) + i * n_rp * NC3,
+                                                  Uk + k * nW * nW, n_rp, nm, nW,
+                                                  reinterpret_cast<cd*>(F), s));
                     for (int64_t q0 = 0; q0 < nq; q0 += qchunk) {
                         const int64_t nqc = std::min(qchunk, nq - q0);
-                        HIPCHK(h, launch_zgemm(Pp + q0 * n_rp, n_rp, F, NC3, X, NC3, nqc, NC3, n_rp,
-                                               s));
-                        HIPCHK(h, launch_rotate_g(X, nqc, Uk + k * nW * nW,
-                                                  Ukq + (k * nq + q0) * nW * nW, E + q0 * nm * nm,
-                                                  nW, nm,
-                                                  reinterpret_cast<cd*>(g_out) + (k * nq + q0) * NC3,
-                                                  s));
+                        cd* gk = reinterpret_cast<cd*>(g_out) + (k * nq + q0) * NC3;
+                        if (lowp) {
+                            HIPCHK(h, launch_cgemm_lp_cf(prec, Pp + q0 * n_rp, n_rp,
+                                                         reinterpret_cast<const cf*>(F), NC3,
+                                                         reinterpret_cast<cf*>(X), NC3, nqc, NC3,
+                                                         n_rp, s));
+                            HIPCHK(h, launch_rotate_g_lp(reinterpret_cast<const cf*>(X), nqc,
+                                                         Ukq + (k * nq + q0) * nW * nW,
+                                                         E + q0 * nm * nm, nW, nm, gk, s));
+                        } else {
+                            HIPCHK(h, launch_zgemm(Pp + q0 * n_rp, n_rp, reinterpret_cast<const cd*>(F),
+                                                   NC3, reinterpret_cast<cd*>(X), NC3, nqc, NC3, n_rp,
+                                                   s));
+                            HIPCHK(h, launch_rotate_g(reinterpret_cast<const cd*>(X), nqc,
+                                                      Uk + k * nW * nW, Ukq + (k * nq + q0) * nW * nW,
+                                                      E + q0 * nm * nm, nW, nm, gk, s));
+                        }
                     }
                 }
             }
@@ -517,12 +537,9 @@ phoebe_status phoebe_gpu_scatter_rates(void* handle, const phoebe_system* sys,
             set_err(h, "nW > 32 or nModes > 32 is not supported");
             throw Fail{PHOEBE_E_UNSUPPORTED};
         }
-        if (prec != PHOEBE_FP64) {
-            set_err(h, "this build implements the FP64 contractions only");
-            throw Fail{PHOEBE_E_UNSUPPORTED};
-        }
+        const bool lowp = prec != PHOEBE_FP64;
         int tq = 0, tn = 0;
-        const int nc_pad = stage2_config(nm, nW, &tq, &tn);
+        const int nc_pad = lowp ? stage2_lp_config(nm, nW, &tq, &tn) : stage2_config(nm, nW, &tq, &tn);
         if (nc_pad < 0) {
             set_err(h, "no stage-2 tiling for nModes*nW = %d", nm * nW);
             throw Fail{PHOEBE_E_UNSUPPORTED};
@@ -531,12 +548,23 @@ phoebe_status phoebe_gpu_scatter_rates(void* handle, const phoebe_system* sys,
         REQUIRE(h, rmax_p <= 100, "|Rp| components above 100 are not supported");
         HIPCHK(h, hipSetDevice(h->device));
         const int n_re = sys->n_re, n_rp = sys->n_rp;
-        const int rp_pad = (n_rp + 3) & ~3;
+        // K padding of the stage-2 operand: 4 (K of the f64/f32 MFMA) or 32 (bf16)
+        const bool bf16 = prec == PHOEBE_BF16X3 || prec == PHOEBE_BF16X6;
+        const int rp_pad = bf16 ? (n_rp + 31) & ~31 : (n_rp + 3) & ~3;
         const int64_t NC2 = (int64_t)n_rp * nm * nW * nW;
+        // bytes of one stage-1 element and of one stage-2 operand element
+        const size_t g_elem = lowp ? sizeof(cf) : sizeof(cd);
+        const size_t f_elem = prec == PHOEBE_FP64 ? sizeof(cd)
+                              : prec == PHOEBE_FP32 ? sizeof(cf)
+                              : prec == PHOEBE_BF16X3 ? 4 * sizeof(uint16_t) : 6 * sizeof(uint16_t);
+        if (lowp && stage2_lp_lds(tq, rmax_p, rp_pad, nc_pad, nm) > 159 * 1024) {
+            set_err(h, "stage-2 tile does not fit in LDS");
+            throw Fail{PHOEBE_E_UNSUPPORTED};
+        }
         // kept k points per stage-1 batch: G and F of a batch stay under 8 GB each
         int BK = 64;
-        while (BK > 16 && ((double)BK * NC2 * sizeof(cd) > 8e9 ||
-                           (double)BK * nW * rp_pad * nc_pad * sizeof(cd) > 8e9))
+        while (BK > 16 && ((double)BK * NC2 * g_elem > 8e9 ||
+                           (double)BK * nW * rp_pad * nc_pad * f_elem > 8e9))
             BK /= 2;
         const int BQ = 16 * tq;
 
@@ -619,8 +647,8 @@ phoebe_status phoebe_gpu_scatter_rates(void* handle, const phoebe_system* sys,
         // batch buffers (upper bound on the states of a batch: BK * nW)
         const int max_states = BK * nW;
         const size_t batch_bytes = 4 * 256 + (size_t)BK * n_re * sizeof(cd) +
-                                   (size_t)BK * NC2 * sizeof(cd) +
-                                   (size_t)max_states * rp_pad * nc_pad * sizeof(cd) +
+                                   (size_t)BK * NC2 * g_elem +
+                                   (size_t)max_states * rp_pad * nc_pad * f_elem +
                                    (size_t)max_states * n_qtiles * sizeof(double);
         ensure_ws(h, tables_end + std::max(scratch_bands, batch_bytes) + 256);
         Arena ar(h->ws);
@@ -684,8 +712,8 @@ phoebe_status phoebe_gpu_scatter_rates(void* handle, const phoebe_system* sys,
 
         // ---- phase B: batches of BK rows ----
         cd* P1 = ar.take<cd>((size_t)BK * n_re);
-        cd* G = ar.take<cd>((size_t)BK * NC2);
-        cd* F = ar.take<cd>((size_t)max_states * rp_pad * nc_pad);
+        char* Gbuf = ar.take<char>((size_t)BK * NC2 * g_elem);
+        char* Fbuf = ar.take<char>((size_t)max_states * rp_pad * nc_pad * f_elem);
         double* partial = ar.take<double>((size_t)max_states * n_qtiles);
 
         const double inv_sqrtpi_sigma = 1.0 / (std::sqrt(kPi) * par->sigma);
@@ -699,13 +727,24 @@ phoebe_status phoebe_gpu_scatter_rates(void* handle, const phoebe_system* sys,
             if (ns == 0) continue;
             HIPCHK(h, launch_phase_table(nullptr, kept + r0, mesh, nb, T.re, n_re, P1, n_re, s));
             Timer t1(h, s, "stage1_phase");
-            HIPCHK(h, launch_zgemm(P1, n_re, reinterpret_cast<const cd*>(sys->g_rr), NC2, G, NC2, nb,
-                                   NC2, n_re, s));
+            if (lowp)
+                HIPCHK(h, launch_cgemm_lp(prec, P1, n_re, reinterpret_cast<const cd*>(sys->g_rr), NC2,
+                                          reinterpret_cast<cf*>(Gbuf), NC2, nb, NC2, n_re, s));
+            else
+                HIPCHK(h, launch_zgemm(P1, n_re, reinterpret_cast<const cd*>(sys->g_rr), NC2,
+                                       reinterpret_cast<cd*>(Gbuf), NC2, nb, NC2, n_re, s));
             t1.done();
-            HIPCHK(h, launch_fold_uk(G, NC2, T.U, T.st_row + sbeg, (int)r0, T.st_kmesh + sbeg,
-                                     T.st_band + sbeg, ns, n_rp, nm, nW, rp_pad, nc_pad, F, s));
+            if (lowp)
+                HIPCHK(h, launch_fold_uk_lp(prec, reinterpret_cast<const cf*>(Gbuf), NC2, T.U,
+                                            T.st_row + sbeg, (int)r0, T.st_kmesh + sbeg,
+                                            T.st_band + sbeg, ns, n_rp, nm, nW, rp_pad, nc_pad,
+                                            Fbuf, s));
+            else
+                HIPCHK(h, launch_fold_uk(reinterpret_cast<const cd*>(Gbuf), NC2, T.U, T.st_row + sbeg,
+                                         (int)r0, T.st_kmesh + sbeg, T.st_band + sbeg, ns, n_rp, nm,
+                                         nW, rp_pad, nc_pad, reinterpret_cast<cd*>(Fbuf), s));
             RateArgs ra{};
-            ra.F = F;
+            ra.F = reinterpret_cast<const cd*>(Fbuf);
             ra.rp_pad = rp_pad;
             ra.nc_pad = nc_pad;
             ra.n_rp = n_rp;
@@ -733,7 +772,21 @@ phoebe_status phoebe_gpu_scatter_rates(void* handle, const phoebe_system* sys,
             ra.partial = partial;
             ra.n_qtiles = n_qtiles;
             Timer t2(h, s, "stage2_rates");
-            HIPCHK(h, launch_stage2_rates(ra, ns, s));
+            if (lowp) {
+                RateArgsLP rl{};
+                rl.F = Fbuf;
+                rl.rp_pad = ra.rp_pad; rl.nc_pad = ra.nc_pad; rl.n_rp = ra.n_rp;
+                rl.rp_packed = ra.rp_packed; rl.rmax = ra.rmax; rl.mesh = ra.mesh;
+                rl.nq_mesh = ra.nq_mesh; rl.st_kmesh = ra.st_kmesh; rl.st_band = ra.st_band;
+                rl.st_row = ra.st_row; rl.st_mlo = ra.st_mlo; rl.st_mhi = ra.st_mhi;
+                rl.q_off = ra.q_off; rl.q_idx = ra.q_idx; rl.q_w = ra.q_w; rl.eps = ra.eps;
+                rl.focc = ra.focc; rl.U = ra.U; rl.omega = ra.omega; rl.nb = ra.nb; rl.E = ra.E;
+                rl.nW = nW; rl.nm = nm; rl.sigma = ra.sigma; rl.partial = partial;
+                rl.n_qtiles = n_qtiles;
+                HIPCHK(h, launch_stage2_rates_lp(prec, rl, ns, s));
+            } else {
+                HIPCHK(h, launch_stage2_rates(ra, ns, s));
+            }
             t2.done();
             HIPCHK(h, launch_reduce_partials(partial, ns, n_qtiles, T.st_row + sbeg,
                                              T.st_band + sbeg, nW, scale, gamma_out, s));

@@ -1,0 +1,110 @@
+"""Reduced-precision forms (FP32 MFMA, split-BF16 x3 / x6) vs the FP64 oracle.
+
+Phases are formed in FP64 and the band structure, occupations, Gaussians and
+the rate sum stay FP64; only the phase and rotation contractions change.  The
+bounds below are the measured errors with headroom; the errors themselves are
+printed (and reported by bench.py --precision).
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_common import rel_err, torch_cuda, workload_params
+from helpers import group_sum_g2
+from oracle import constants, coupling, rates
+
+pytestmark = pytest.mark.gpu
+
+# max relative error of Gamma allowed per form (states above 1e-10 of the maximum)
+GAMMA_BOUND = {"fp32": 1e-4, "bf16x3": 1e-2, "bf16x6": 1e-4}
+# max error of |g|^2 relative to the largest |g|^2 of its (k, q) pair
+G2_BOUND = {"fp32": 1e-5, "bf16x3": 1e-3, "bf16x6": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def lib():
+    torch_cuda()
+    from paper_2111_14999_amd import Library
+    L = Library(0)
+    yield L
+    L.close()
+
+
+@pytest.fixture(scope="module")
+def toy():
+    s = synth.config_c1()
+    p = workload_params()["toy"]
+    par = dict(mu=p["mu"], kT=p["kT"], sigma=p["sigma"], win_lo=p["win_lo"], win_hi=p["win_hi"],
+               omega_min=p["omega_min"])
+    mesh = tuple(p["mesh"])
+    ref = rates.scattering_rates(s, mesh, **par)
+    return s, mesh, par, ref
+
+
+def _rates(lib, s, mesh, par, prec):
+    torch = torch_cuda()
+    from paper_2111_14999_amd import DeviceSystem
+    ds = DeviceSystem.from_host(s)
+    N = int(np.prod(mesh))
+    gamma = torch.zeros((N, s.n_wannier), dtype=torch.float64, device="cuda")
+    n = lib.scatter_rates(ds, mesh, par, gamma, precision=prec)
+    torch.cuda.synchronize()
+    return n, gamma.cpu().numpy()[:n]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16x6"])
+def test_toy_rates(lib, toy, prec):
+    s, mesh, par, ref = toy
+    n, g = _rates(lib, s, mesh, par, prec)
+    assert n == len(ref["k_idx"])
+    mx, med, ab = rel_err(g, ref["gamma"])
+    print(f"[{prec}] Gamma rel err max {mx:.3e} median {med:.3e}", flush=True)
+    assert mx < GAMMA_BOUND[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16x6"])
+def test_toy_coupling(lib, toy, prec):
+    torch = torch_cuda()
+    from paper_2111_14999_amd import DeviceSystem
+    s = toy[0]
+    rng = np.random.default_rng(5)
+    k = rng.uniform(-1, 1, size=(3, 3))
+    q = rng.uniform(-1, 1, size=(40, 3))
+    ref = coupling.coupling(k, q, s)
+    ds = DeviceSystem.from_host(s)
+    nk, nq, nW, nm = 3, 40, s.n_wannier, s.n_modes
+    g = torch.empty((nk, nq, nm, nW, nW), dtype=torch.complex128, device="cuda")
+    lib.interp_g(ds, torch.from_numpy(k).cuda(), torch.from_numpy(q).cuda(), g, precision=prec)
+    torch.cuda.synchronize()
+    g = g.cpu().numpy()
+    a = np.empty(g.shape)
+    b = np.empty(g.shape)
+    for i in range(nk):
+        for j in range(nq):
+            a[i, j] = group_sum_g2(g[i, j], ref["eps_k"][i], ref["eps_kq"][i, j], ref["omega_q"][j])
+            b[i, j] = group_sum_g2(ref["g"][i, j], ref["eps_k"][i], ref["eps_kq"][i, j],
+                                   ref["omega_q"][j])
+    blk = np.max(b.reshape(nk, nq, -1), axis=2)[:, :, None, None, None]
+    err = np.abs(a - b) / blk
+    mx, med, _ = rel_err(a, b, floor_frac=1e-6)
+    print(f"[{prec}] |g|^2 err/pair-max {np.max(err):.3e}; entrywise (>1e-6 max) max {mx:.3e} "
+          f"median {med:.3e}", flush=True)
+    assert np.max(err) < G2_BOUND[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x6"])
+@pytest.mark.parametrize("seed,nW,nat,mesh", [(71, 5, 2, (3, 5, 4)), (72, 16, 5, (2, 3, 4))])
+def test_ragged_windows(lib, prec, seed, nW, nat, mesh):
+    s = synth.small_system(seed, n_wannier=nW, n_atoms=nat, r=1)
+    s.h_r *= 0.3
+    t = rates.mesh_tables(s, mesh)
+    mu = float(np.median(t["eps"]))
+    par = dict(mu=mu, kT=constants.kT_of(300.0), sigma=0.05, win_lo=mu - 0.7, win_hi=mu + 0.7,
+               omega_min=1e-4)
+    ref = rates.scattering_rates(s, mesh, tables=t, **par)
+    n, g = _rates(lib, s, mesh, par, prec)
+    assert n == len(ref["k_idx"])
+    mx, med, ab = rel_err(g, ref["gamma"])
+    print(f"[{prec}] ragged Gamma rel err max {mx:.3e} median {med:.3e}", flush=True)
+    assert mx < GAMMA_BOUND[prec]

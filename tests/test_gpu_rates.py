@@ -139,6 +139,13 @@ def test_argument_errors(lib, toy):
     with pytest.raises(PhoebeError) as e:
         lib.scatter_rates(ds, (0, 2, 2), par, gamma)
     assert e.value.status == -1
-    with pytest.raises(PhoebeError) as e:
-        lib.scatter_rates(ds, mesh, par, gamma, precision="bf16x6")
-    assert e.value.status in (-4, 0)
+    # precision enum out of range, through the raw C ABI
+    import ctypes
+    from paper_2111_14999_amd import binding
+    c = ds.c_struct()
+    m = (ctypes.c_int32 * 3)(*mesh)
+    p = binding.CRateParams(par["mu"], par["kT"], par["sigma"], par["win_lo"], par["win_hi"], 1e-4)
+    st = lib.lib.phoebe_gpu_scatter_rates(lib.handle, ctypes.byref(c), m, None, 0, None, None, None,
+                                          ctypes.byref(p), 7, gamma.data_ptr(), None, None, None,
+                                          None)
+    assert st == -1
