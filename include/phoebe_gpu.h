@@ -195,6 +195,43 @@ phoebe_status phoebe_gpu_scatter_rates(void *handle, const phoebe_system *sys,
                                        int32_t *kept_k_out, int64_t *n_kept_out,
                                        void *stream);
 
+/* Batched form: many independent systems (different nW, nModes, lattice-vector
+ * sets and meshes) evaluated together (Transport Methods, electron lifetime,
+ * per system exactly as phoebe_gpu_scatter_rates over the full q mesh with
+ * k_idx = NULL).  A plan builds every system's band and phonon tables, windows
+ * and kept-state lists, picks each system's tile shape with an autotuner (the
+ * candidates are timed on the device; choices are read from and written to
+ * tune_cache, a small JSON file, when it is not NULL), and captures one
+ * hipGraph: stage 1 and the U_k fold of every system, then one persistent
+ * kernel that drains a work queue of (system, state, q tile) tasks, then the
+ * per-system reductions.  Only PHOEBE_FP32 contractions (complex64) are
+ * offered; tables, eigensolves, occupations and rate sums are FP64.
+ *   systems   host [n_sys] (their tensors are device pointers, used until the
+ *             plan is destroyed)
+ *   meshes    host [n_sys, 3];  params host [n_sys]
+ *   n_kept_out host [n_sys] (nullable): kept k per system
+ * The plan call synchronises the stream.  Errors as phoebe_gpu_scatter_rates,
+ * PHOEBE_E_UNSUPPORTED for other precisions. */
+phoebe_status phoebe_gpu_batched_plan(void *handle, const phoebe_system *systems, int32_t n_sys,
+                                      const int32_t *meshes, const phoebe_rate_params *params,
+                                      phoebe_precision prec, const char *tune_cache,
+                                      void **plan, int64_t *n_kept_out, void *stream);
+
+/* Launch the plan's graph on `stream`, then copy each system's rates to
+ * gamma_out[i] (device [n_kept_i, nW_i], rows in ascending mesh order of the
+ * kept k; bands outside the window get 0).  gamma_out is a host array of
+ * n_sys device pointers; it or any entry may be NULL (no copy). */
+phoebe_status phoebe_gpu_batched_run(void *plan, double *const *gamma_out, void *stream);
+
+/* Plan facts: tile shape of system `sys` (q rows = 16 tq, column tiles per
+ * wave tn), its kept states, the total number of queue tasks, and the time
+ * the autotuner spent. Any out-pointer may be NULL. */
+phoebe_status phoebe_gpu_batched_info(void *plan, int32_t sys, int32_t *tq, int32_t *tn,
+                                      int64_t *n_states, int64_t *n_tasks, double *tune_ms);
+
+/* Release a plan (synchronises the device). NULL is accepted. */
+phoebe_status phoebe_gpu_batched_destroy(void *plan);
+
 /* Kernel timing for measurement: when enabled, the named hot kernels are
  * bracketed by HIP events on the stream they run on; phoebe_gpu_kernel_time
  * returns the number of timed launches and their summed duration since the

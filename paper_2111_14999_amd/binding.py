@@ -31,6 +31,8 @@ EXPORTS = (
     "phoebe_gpu_last_error", "phoebe_gpu_electron_bands", "phoebe_gpu_phonon_modes",
     "phoebe_gpu_interp_g", "phoebe_gpu_scatter_rates", "phoebe_gpu_set_timing",
     "phoebe_gpu_kernel_time", "phoebe_gpu_reset_timing",
+    "phoebe_gpu_batched_plan", "phoebe_gpu_batched_run", "phoebe_gpu_batched_info",
+    "phoebe_gpu_batched_destroy",
 )
 
 
@@ -87,6 +89,15 @@ def load(path: str = LIB_PATH):
     lib.phoebe_gpu_reset_timing.argtypes = [vp]
     lib.phoebe_gpu_kernel_time.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(i64),
                                            ctypes.POINTER(ctypes.c_double)]
+    lib.phoebe_gpu_batched_plan.argtypes = [vp, ctypes.POINTER(CSystem), i32, ctypes.POINTER(i32),
+                                            ctypes.POINTER(CRateParams), ctypes.c_int,
+                                            ctypes.c_char_p, ctypes.POINTER(vp),
+                                            ctypes.POINTER(i64), vp]
+    lib.phoebe_gpu_batched_run.argtypes = [vp, ctypes.POINTER(vp), vp]
+    lib.phoebe_gpu_batched_info.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                            ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                            ctypes.POINTER(ctypes.c_double)]
+    lib.phoebe_gpu_batched_destroy.argtypes = [vp]
     for name in EXPORTS:
         if name not in ("phoebe_gpu_abi_version", "phoebe_gpu_last_error"):
             getattr(lib, name).restype = ctypes.c_int
@@ -222,6 +233,23 @@ class Library:
             _ptr(kept_k_out), ctypes.byref(n_kept), _stream(stream)))
         return int(n_kept.value)
 
+    # -- batched form -------------------------------------------------------
+    def batched_plan(self, systems, meshes, params_list, precision="fp32", tune_cache=None,
+                     stream=None) -> "BatchedPlan":
+        n = len(systems)
+        cs = (CSystem * n)(*[sy.c_struct() for sy in systems])
+        m = (ctypes.c_int32 * (3 * n))(*[int(x) for mm in meshes for x in mm])
+        ps = (CRateParams * n)(*[CRateParams(p["mu"], p["kT"], p["sigma"], p["win_lo"],
+                                             p["win_hi"], p.get("omega_min", 1e-4))
+                                 for p in params_list])
+        kept = (ctypes.c_int64 * n)()
+        plan = ctypes.c_void_p()
+        path = tune_cache.encode() if tune_cache else None
+        self._check(self.lib.phoebe_gpu_batched_plan(self.handle, cs, n, m, ps,
+                                                     PRECISIONS[precision], path,
+                                                     ctypes.byref(plan), kept, _stream(stream)))
+        return BatchedPlan(self, plan, [int(x) for x in kept], systems)
+
     # -- timing -------------------------------------------------------------
     def set_timing(self, on: bool):
         self._check(self.lib.phoebe_gpu_set_timing(self.handle, 1 if on else 0))
@@ -235,3 +263,40 @@ class Library:
         self._check(self.lib.phoebe_gpu_kernel_time(self.handle, name.encode(), ctypes.byref(n),
                                                     ctypes.byref(ms)))
         return int(n.value), float(ms.value)
+
+
+class BatchedPlan:
+    """A captured multi-system plan (see phoebe_gpu_batched_plan)."""
+
+    def __init__(self, lib: Library, plan, n_kept, systems):
+        self.lib = lib
+        self.plan = plan
+        self.n_kept = n_kept
+        self._systems = systems  # keeps the device tensors alive
+
+    def run(self, gamma_outs=None, stream=None):
+        n = len(self.n_kept)
+        arr = None
+        if gamma_outs is not None:
+            arr = (ctypes.c_void_p * n)(*[_ptr(g) for g in gamma_outs])
+        self.lib._check(self.lib.lib.phoebe_gpu_batched_run(self.plan, arr, _stream(stream)))
+
+    def info(self, i):
+        tq, tn = ctypes.c_int32(), ctypes.c_int32()
+        ns, nt = ctypes.c_int64(), ctypes.c_int64()
+        tm = ctypes.c_double()
+        self.lib._check(self.lib.lib.phoebe_gpu_batched_info(
+            self.plan, i, ctypes.byref(tq), ctypes.byref(tn), ctypes.byref(ns), ctypes.byref(nt),
+            ctypes.byref(tm)))
+        return dict(tq=tq.value, tn=tn.value, states=ns.value, tasks=nt.value, tune_ms=tm.value)
+
+    def close(self):
+        if self.plan:
+            self.lib.lib.phoebe_gpu_batched_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

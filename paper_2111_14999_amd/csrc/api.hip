@@ -1,240 +1,12 @@
 // C ABI of the library: argument validation, workspace, orchestration of the
 // kernels for the band structure, the coupling interpolation and the rates.
-#include <algorithm>
-#include <cmath>
-#include <cstdarg>
-#include <cstdio>
-#include <cstring>
-#include <functional>
-#include <string>
-#include <vector>
-
-#include "kernels.hpp"
-#include "lowp.hpp"
+#include "host.hpp"
 
 using namespace phx;
 
-namespace {
-
+namespace phx {
 std::string g_create_error;
-
-struct TimedLaunch {
-    std::string name;
-    hipEvent_t start, stop;
-};
-
-struct KernelStat {
-    std::string name;
-    int64_t launches = 0;
-    double total_ms = 0.0;
-};
-
-struct Handle {
-    int device = 0;
-    size_t budget = 0;
-    char* ws = nullptr;
-    size_t ws_cap = 0;
-    std::string err;
-    bool timing = false;
-    std::vector<TimedLaunch> pending;
-    std::vector<KernelStat> stats;
-};
-
-struct Fail {
-    phoebe_status st;
-};
-
-// Bump allocation over the handle's workspace.  A first pass with base ==
-// nullptr only sizes the request.
-struct Arena {
-    char* base;
-    size_t used = 0;
-    explicit Arena(char* b) : base(b) {}
-    template <class T>
-    T* take(size_t count) {
-        used = (used + 255) & ~(size_t)255;
-        T* p = base ? reinterpret_cast<T*>(base + used) : nullptr;
-        used += count * sizeof(T);
-        return p;
-    }
-};
-
-void set_err(Handle* h, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
-void set_err(Handle* h, const char* fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    h->err = buf;
 }
-
-#define REQUIRE(h, cond, ...)                    \
-    do {                                         \
-        if (!(cond)) {                           \
-            set_err((h), __VA_ARGS__);           \
-            throw Fail{PHOEBE_E_INVALID};        \
-        }                                        \
-    } while (0)
-
-#define HIPCHK(h, expr)                                                                   \
-    do {                                                                                  \
-        hipError_t e_ = (expr);                                                           \
-        if (e_ != hipSuccess) {                                                           \
-            set_err((h), "HIP error %s at %s:%d", hipGetErrorString(e_), __FILE__, __LINE__); \
-            throw Fail{PHOEBE_E_DEVICE};                                                  \
-        }                                                                                 \
-    } while (0)
-
-void ensure_ws(Handle* h, size_t bytes) {
-    if (bytes <= h->ws_cap) return;
-    if (bytes > h->budget) {
-        set_err(h, "workspace of %zu bytes exceeds the budget of %zu bytes", bytes, h->budget);
-        throw Fail{PHOEBE_E_NOMEM};
-    }
-    if (h->ws) {
-        HIPCHK(h, hipDeviceSynchronize());
-        HIPCHK(h, hipFree(h->ws));
-        h->ws = nullptr;
-        h->ws_cap = 0;
-    }
-    hipError_t e = hipMalloc(&h->ws, bytes);
-    if (e != hipSuccess) {
-        h->ws = nullptr;
-        set_err(h, "hipMalloc of %zu workspace bytes failed: %s", bytes, hipGetErrorString(e));
-        throw Fail{PHOEBE_E_NOMEM};
-    }
-    h->ws_cap = bytes;
-}
-
-// Timing brackets on the launch stream.
-struct Timer {
-    Handle* h;
-    hipStream_t s;
-    TimedLaunch t;
-    bool on;
-    Timer(Handle* h_, hipStream_t s_, const char* name) : h(h_), s(s_), on(h_->timing) {
-        if (!on) return;
-        t.name = name;
-        HIPCHK(h, hipEventCreate(&t.start));
-        HIPCHK(h, hipEventCreate(&t.stop));
-        HIPCHK(h, hipEventRecord(t.start, s));
-    }
-    void done() {
-        if (!on) return;
-        HIPCHK(h, hipEventRecord(t.stop, s));
-        h->pending.push_back(t);
-        on = false;
-    }
-};
-
-void flush_timing(Handle* h, hipStream_t s) {
-    if (h->pending.empty()) return;
-    HIPCHK(h, hipStreamSynchronize(s));
-    for (auto& t : h->pending) {
-        float ms = 0.f;
-        HIPCHK(h, hipEventElapsedTime(&ms, t.start, t.stop));
-        KernelStat* ks = nullptr;
-        for (auto& k : h->stats)
-            if (k.name == t.name) ks = &k;
-        if (!ks) {
-            h->stats.push_back(KernelStat{t.name, 0, 0.0});
-            ks = &h->stats.back();
-        }
-        ks->launches += 1;
-        ks->total_ms += ms;
-        (void)hipEventDestroy(t.start);
-        (void)hipEventDestroy(t.stop);
-    }
-    h->pending.clear();
-}
-
-void check_system(Handle* h, const phoebe_system* sys, bool need_h, bool need_ph, bool need_g) {
-    REQUIRE(h, sys != nullptr, "system is NULL");
-    REQUIRE(h, sys->n_wannier >= 1, "n_wannier must be >= 1 (got %d)", sys->n_wannier);
-    REQUIRE(h, sys->n_atoms >= 1, "n_atoms must be >= 1 (got %d)", sys->n_atoms);
-    if (need_h) {
-        REQUIRE(h, sys->n_rh >= 1 && sys->rh && sys->h_r, "H(R) arrays missing");
-    }
-    if (need_ph) {
-        REQUIRE(h, sys->n_rd >= 1 && sys->rd && sys->phi_r && sys->mass, "force constants missing");
-    }
-    if (need_g) {
-        REQUIRE(h, sys->n_re >= 1 && sys->re && sys->n_rp >= 1 && sys->rp && sys->g_rr,
-                "g(Re,Rp) arrays missing");
-    }
-}
-
-int32_t* upload_r(Handle* h, Arena& ar, const int32_t* host, int n, hipStream_t s) {
-    int32_t* d = ar.take<int32_t>((size_t)3 * n);
-    if (d) HIPCHK(h, hipMemcpyAsync(d, host, sizeof(int32_t) * 3 * n, hipMemcpyHostToDevice, s));
-    return d;
-}
-
-int rmax_of(const int32_t* r, int n) {
-    int m = 0;
-    for (int i = 0; i < 3 * n; ++i) m = std::max(m, std::abs(r[i]));
-    return m;
-}
-
-// ---------------------------------------------------------------------------
-// band structure on a set of points (fractional coordinates or mesh indices)
-// ---------------------------------------------------------------------------
-struct BandBufs {
-    double* eps;
-    cd* U;
-};
-
-void electron_bands_dev(Handle* h, Arena& ar, const phoebe_system* sys, const int32_t* rh_d,
-                        const double* frac, const int32_t* idx, Mesh m, int64_t np, double* eps,
-                        cd* U, hipStream_t s) {
-    const int nW = sys->n_wannier, nR = sys->n_rh;
-    cd* P = ar.take<cd>((size_t)np * nR);
-    cd* H = ar.take<cd>((size_t)np * nW * nW);
-    if (!ar.base) return;
-    HIPCHK(h, launch_phase_table(frac, idx, m, np, rh_d, nR, P, nR, s));
-    Timer t(h, s, "bands_fft");
-    HIPCHK(h, launch_zgemm(P, nR, reinterpret_cast<const cd*>(sys->h_r), (int64_t)nW * nW, H,
-                           (int64_t)nW * nW, np, (int64_t)nW * nW, nR, s));
-    t.done();
-    Timer te(h, s, "eig_jacobi");
-    HIPCHK(h, launch_eig_herm(H, nW, np, eps, U, s));
-    te.done();
-}
-
-void phonon_dev(Handle* h, Arena& ar, const phoebe_system* sys, const int32_t* rd_d,
-                const double* frac, const int32_t* idx, Mesh m, int64_t np, double omega_min,
-                double kT, double* omega, cd* E, double* nb, cd* z_out, hipStream_t s) {
-    const int nm = 3 * sys->n_atoms, nR = sys->n_rd;
-    cd* P = ar.take<cd>((size_t)np * nR);
-    cd* phic = ar.take<cd>((size_t)nR * nm * nm);
-    cd* D = ar.take<cd>((size_t)np * nm * nm);
-    double* lam = ar.take<double>((size_t)np * nm);
-    cd* z = z_out ? z_out : ar.take<cd>((size_t)np * nm * nm);
-    if (!ar.base) return;
-    HIPCHK(h, launch_phase_table(frac, idx, m, np, rd_d, nR, P, nR, s));
-    HIPCHK(h, launch_mass_weight(sys->phi_r, sys->mass, nR, nm, phic, s));
-    HIPCHK(h, launch_zgemm(P, nR, phic, (int64_t)nm * nm, D, (int64_t)nm * nm, np,
-                           (int64_t)nm * nm, nR, s));
-    HIPCHK(h, launch_eig_herm(D, nm, np, lam, z, s));
-    HIPCHK(h, launch_phonon_post(lam, z, sys->mass, sys->n_atoms, np, omega_min, kT, omega, E, nb,
-                                 s));
-}
-
-phoebe_status run(Handle* h, const std::function<void()>& body) {
-    try {
-        h->err.clear();
-        body();
-        return PHOEBE_OK;
-    } catch (const Fail& f) {
-        return f.st;
-    } catch (const std::bad_alloc&) {
-        set_err(h, "host allocation failed");
-        return PHOEBE_E_NOMEM;
-    }
-}
-
-}  // namespace
 
 extern "C" {
 

@@ -17,5 +17,6 @@ from .systems import (  # noqa: F401
     cscl_structure,
     perovskite_structure,
     random_structure,
-    config_c4_systems,
+    config_c4_specs,
+    config_c4,
 )

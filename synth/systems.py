@@ -290,35 +290,46 @@ def small_system(seed: int, n_wannier: int = 3, n_atoms: int = 2, r: int = 1) ->
     return make_system(seed, n_wannier, pos, shells, r_h=r, r_e=r, r_p=r)
 
 
-def config_c4_systems(base_seed: int = 400, count: int = 32, cap_bytes: float = 160e9):
-    """Parameters of the batched workload: per-system sizes (arrays are built lazily).
+def config_c4_specs(base_seed: int = 400, count: int = 32, per_system_cap: float = 1.5e9,
+                    total_cap: float = 24e9):
+    """Sizes of the batched workload's independent systems (arrays built by ``config_c4``).
 
-    nW ~ U{4..24}, nat ~ U{2..10}, |R| box ~ U{5^3..9^3}, mesh ~ U{16..32}^3.
-    The complex64 size of g(Re,Rp) summed over systems is capped at ``cap_bytes``
-    by redrawing the largest systems.
+    nW ~ U{4..24}, nat ~ U{2..10} (nModes 6..30), H(R) box r_h ~ U{2,3,4}
+    (125..729 vectors), g(Re,Rp) box r_g ~ U{2,3,4}, mesh ~ U{16..32}^3.  A
+    system whose complex128 g(Re,Rp) exceeds ``per_system_cap`` bytes redraws
+    (nW, nat, r_g) from its own stream until it fits; the total is then capped at
+    ``total_cap`` by shrinking the largest systems the same way.  (Uncapped, the
+    largest draws need ~150 GB each: more than one GPU holds.)
     """
     specs = []
-    for i in range(count):
-        rng = _rng(base_seed + i, 99)
-        spec = dict(seed=base_seed + i,
-                    n_wannier=int(rng.integers(4, 25)),
-                    n_atoms=int(rng.integers(2, 11)),
-                    r=int(rng.integers(2, 5)),
-                    mesh=int(rng.integers(16, 33)))
-        specs.append(spec)
 
     def nbytes(sp):
-        nr = (2 * sp["r"] + 1) ** 3
-        return nr * nr * 3 * sp["n_atoms"] * sp["n_wannier"] ** 2 * 8
+        nr = (2 * sp["r_g"] + 1) ** 3
+        return nr * nr * 3 * sp["n_atoms"] * sp["n_wannier"] ** 2 * 16
 
-    total = sum(nbytes(s) for s in specs)
-    redraw = 0
-    while total > cap_bytes:
-        j = max(range(count), key=lambda i: nbytes(specs[i]))
-        redraw += 1
-        rng = _rng(specs[j]["seed"], 100 + redraw)
-        specs[j]["n_wannier"] = int(rng.integers(4, 25))
-        specs[j]["n_atoms"] = int(rng.integers(2, 11))
-        specs[j]["r"] = int(rng.integers(2, 5))
-        total = sum(nbytes(s) for s in specs)
+    for i in range(count):
+        rng = _rng(base_seed + i, 99)
+        sp = dict(seed=base_seed + i, n_wannier=int(rng.integers(4, 25)),
+                  n_atoms=int(rng.integers(2, 11)), r_h=int(rng.integers(2, 5)),
+                  r_g=int(rng.integers(2, 5)), mesh=int(rng.integers(16, 33)))
+        while nbytes(sp) > per_system_cap:
+            sp["n_wannier"] = int(rng.integers(4, 25))
+            sp["n_atoms"] = int(rng.integers(2, 11))
+            sp["r_g"] = int(rng.integers(2, 5))
+        specs.append(sp)
+    while sum(nbytes(sp) for sp in specs) > total_cap:
+        j = max(range(count), key=lambda k: nbytes(specs[k]))
+        rng = _rng(specs[j]["seed"], 98)
+        specs[j]["r_g"] = max(2, specs[j]["r_g"] - 1)
+        if nbytes(specs[j]) > per_system_cap / 4:
+            specs[j]["n_wannier"] = max(4, specs[j]["n_wannier"] // 2)
     return specs
+
+
+def config_c4(spec: dict, threads: int = 8) -> System:
+    """One system of the batched workload from its spec (random positions, bonds < 1.01 A)."""
+    pos, shells = random_structure(spec["seed"], spec["n_atoms"])
+    s = make_system(spec["seed"], spec["n_wannier"], pos, shells, r_h=spec["r_h"],
+                    r_e=spec["r_g"], r_p=spec["r_g"], threads=threads)
+    s.meta["mesh"] = (spec["mesh"],) * 3
+    return s
