@@ -46,7 +46,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="realistic", choices=["realistic", "toy", "batched"])
+    ap.add_argument("--workload", default="realistic",
+                    choices=["realistic", "toy", "batched", "learned"])
     ap.add_argument("--tune-cache", default=None, help="JSON tile cache of the batched form")
     ap.add_argument("--cpu-sample", type=int, default=6, help="kept k points timed on the oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -65,6 +66,8 @@ def main():
 
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "learned":
+        return bench_learned(args)
     p = load_params(args.workload)
     mesh = tuple(p["mesh"])
     N = int(np.prod(mesh))
@@ -292,6 +295,214 @@ def bench_batched(args):
     }
     print(json.dumps(out), flush=True)
     plan.close()
+    lib.close()
+
+
+def bench_learned(args):
+    """Learned q-proposal on the realistic system: train on the method's own terms,
+    importance-sample 4096 q per k, compare with the full-mesh rates."""
+    import torch
+
+    import synth
+    from paper_2111_14999_amd import DeviceSystem, Library
+
+    p = load_params("realistic")
+    mesh = tuple(p["mesh"])
+    N = int(np.prod(mesh))
+    par = dict(mu=p["mu"], kT=p["kT"], sigma=p["sigma"], win_lo=p["win_lo"], win_hi=p["win_hi"],
+               omega_min=p["omega_min"])
+    s = synth.config_c2()
+    ds = DeviceSystem.from_host(s)
+    lib = Library(0)
+    nW, nm = s.n_wannier, s.n_modes
+    gamma = torch.zeros((N, nW), dtype=torch.float64, device="cuda")
+    mask = torch.zeros((N, nW), dtype=torch.uint8, device="cuda")
+    kept = torch.zeros((N,), dtype=torch.int32, device="cuda")
+    n_kept = lib.scatter_rates(ds, mesh, par, gamma, band_mask=mask, kept_k_out=kept)
+    torch.cuda.synchronize()
+    kidx = kept.cpu().numpy()[:n_kept]
+    m = mask.cpu().numpy()[:n_kept]
+    g_full = gamma.cpu().numpy()[:n_kept]
+    rng = np.random.default_rng(2021)
+    perm = rng.permutation(n_kept)
+    n_train, n_test = 34, 64
+    tr, te = np.sort(perm[:n_train]), np.sort(perm[n_train:n_train + n_test])
+    # integrand samples of the plain method on the training k, and their smearing weights
+    t0 = time.perf_counter()
+    gam_tr = torch.zeros((n_train, nW), dtype=torch.float64, device="cuda")
+    terms = torch.zeros((n_train * nW, N, nm), dtype=torch.float64, device="cuda")
+    dws = torch.zeros_like(terms)
+    strow = torch.zeros(n_train * nW, dtype=torch.int32, device="cuda")
+    stband = torch.zeros(n_train * nW, dtype=torch.int32, device="cuda")
+    ns = lib.rate_terms(ds, mesh, par, torch.from_numpy(kidx[tr]).cuda(), gam_tr, terms,
+                        dweights=dws, st_row=strow, st_band=stband)
+    torch.cuda.synchronize()
+    t_terms = time.perf_counter() - t0
+    T, D = terms[:ns], dws[:ns]
+    thr = 1e-6
+    sel = D > thr * D.reshape(ns, -1).amax(dim=1)[:, None, None]
+    si_all, qi_all, vi_all = torch.nonzero(sel, as_tuple=True)
+    ratio = T[si_all, qi_all, vi_all] / D[si_all, qi_all, vi_all]
+    c_floor = float(1e-3 * ratio.mean().item())
+    n_samp = min(2_000_000, int(si_all.numel()))
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
+    pick = torch.randperm(int(si_all.numel()), device="cuda", generator=gen)[:n_samp]
+    si, qi, vi = si_all[pick], qi_all[pick], vi_all[pick]
+    y = torch.log(ratio[pick] + c_floor).float().contiguous()
+    y_var = float(y.var().item())
+    rows = strow[:ns].long()[si]
+    bands = stband[:ns].long()[si]
+    kk = torch.from_numpy(kidx[tr]).cuda()[rows].int().contiguous()
+    kf = torch.from_numpy(mesh_points_frac(mesh, kidx[tr])).cuda()
+    ek = torch.zeros((n_train, nW), dtype=torch.float64, device="cuda")
+    lib.electron_bands(ds, kf, ek, None)
+    ee = ek[rows, bands].contiguous()
+    n_in, width, depth = 7 + nm, 256, 4
+    escale = 0.3
+    X = torch.zeros((n_samp, n_in), dtype=torch.float32, device="cuda")
+    lib.mlp_features(mesh, nm, kk, ee, qi.int().contiguous(), vi.int().contiguous(), X, par["mu"],
+                     escale)
+    del T, D, terms, dws, sel, si_all, qi_all, vi_all, ratio
+    # parameters: U(-1/sqrt(in), 1/sqrt(in)) weights, zero biases, packed per layer
+    prng = np.random.default_rng(17)
+    parts, prev = [], n_in
+    for l in range(depth + 1):
+        out_d = 1 if l == depth else width
+        parts.append(prng.uniform(-1 / np.sqrt(prev), 1 / np.sqrt(prev), size=out_d * prev))
+        parts.append(np.zeros(out_d))
+        prev = out_d
+    theta = torch.from_numpy(np.concatenate(parts).astype(np.float32)).cuda()
+    assert theta.numel() == lib.mlp_param_count(n_in, width, depth)
+    gbuf = torch.zeros_like(theta)
+    mom1 = torch.zeros_like(theta)
+    mom2 = torch.zeros_like(theta)
+    bs, epochs = 4096, 2
+    steps = epochs * n_samp // bs
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = []
+    for step in range(1, steps + 1):
+        idx = torch.randint(0, n_samp, (bs,), device="cuda", generator=gen)
+        loss = lib.mlp_grad(theta, X[idx].contiguous(), y[idx].contiguous(), gbuf, n_in, width,
+                            depth, precision="bf16")
+        lib.mlp_adam(theta, gbuf, mom1, mom2, step, 1e-3 if step < steps // 2 else 3e-4)
+        if step == 1 or step % 100 == 0:
+            losses.append(loss)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(f"terms of {ns} training states in {t_terms:.2f} s; {steps} Adam steps in {t_train:.1f} s, "
+        f"loss {losses[0]:.3f} -> {losses[-1]:.3f} (target variance {y_var:.3f})")
+    del X, y
+
+    # test k: full-mesh plain rates (the reference result) vs importance sampling
+    S, seeds = 4096, 8
+    test_k = kidx[te]
+    kd = torch.from_numpy(test_k.astype(np.int32)).cuda()
+    # plain form on exactly these k, timed
+    gp = torch.zeros((n_test, nW), dtype=torch.float64, device="cuda")
+    lib.scatter_rates(ds, mesh, par, gp, k_idx=kd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lib.scatter_rates(ds, mesh, par, gp, k_idx=kd)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    # smearing weights of the test states (part of the proposal's cost)
+    dt = torch.zeros((n_test * nW, N, nm), dtype=torch.float64, device="cuda")
+    gs = torch.zeros((n_test, nW), dtype=torch.float64, device="cuda")
+    trow = torch.zeros(n_test * nW, dtype=torch.int32, device="cuda")
+    tband = torch.zeros(n_test * nW, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nst = lib.delta_weights(ds, mesh, par, kd, dt, gs, st_row=trow, st_band=tband)
+    torch.cuda.synchronize()
+    t_dw = time.perf_counter() - t0
+    trow_h, tband_h = trow[:nst].cpu().numpy(), tband[:nst].cpu().numpy()
+    first = np.array([np.nonzero(trow_h == j)[0][0] for j in range(n_test)])
+    tb = tband_h[first]
+    Dsel = dt[torch.from_numpy(first).cuda()].contiguous()
+    del dt
+    kf = torch.from_numpy(mesh_points_frac(mesh, test_k)).cuda()
+    ek = torch.zeros((n_test, nW), dtype=torch.float64, device="cuda")
+    lib.electron_bands(ds, kf, ek, None)
+    eps_k = ek.cpu().numpy()[np.arange(n_test), tb]
+    full = g_full[te, tb]
+    ugen = torch.Generator(device="cuda")
+    ugen.manual_seed(77)
+    est = {"learned": [], "smearing": [], "uniform": []}
+    t_prop, t_is = 0.0, 0.0
+    for sd in range(seeds):
+        u = torch.rand(n_test * S, dtype=torch.float64, device="cuda", generator=ugen)
+        for name, prm in (("learned", theta), ("smearing", None)):
+            q_off = torch.zeros(n_test + 1, dtype=torch.int64, device="cuda")
+            q_idx = torch.zeros(n_test * S, dtype=torch.int32, device="cuda")
+            q_w = torch.zeros(n_test * S, dtype=torch.float64, device="cuda")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lib.propose_q(mesh, nm, test_k, eps_k, Dsel, prm, width, depth, par["mu"], escale,
+                          thr, 0.1, S, u, q_off, q_idx, q_w)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            gl = torch.zeros((n_test, nW), dtype=torch.float64, device="cuda")
+            lib.scatter_rates(ds, mesh, par, gl, k_idx=kd, q_lists=(q_off, q_idx, q_w))
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            if name == "learned":
+                t_prop += t1 - t0
+                t_is += t2 - t1
+            est[name].append(gl.cpu().numpy()[np.arange(n_test), tb])
+        qu = torch.randint(0, N, (n_test * S,), device="cuda", generator=ugen).int()
+        wu = torch.full((n_test * S,), 1.0 / S, dtype=torch.float64, device="cuda")
+        gu = torch.zeros((n_test, nW), dtype=torch.float64, device="cuda")
+        lib.scatter_rates(ds, mesh, par, gu, k_idx=kd, q_lists=(q_off, qu, wu))
+        torch.cuda.synchronize()
+        est["uniform"].append(gu.cpu().numpy()[np.arange(n_test), tb])
+    est = {k: np.array(v) for k, v in est.items()}
+    t_prop /= seeds
+    t_is /= seeds
+    t_step = t_dw + t_prop + t_is
+    rel = {k: np.abs(v - full[None]) / full[None] for k, v in est.items()}
+    cv = {k: v.std(axis=0, ddof=1) / full for k, v in est.items()}
+    bias = np.abs(est["learned"].mean(axis=0) - full) / (est["learned"].std(axis=0, ddof=1)
+                                                         / np.sqrt(seeds))
+    log(f"plain {n_test} k in {t_plain * 1e3:.1f} ms; learned: weights {t_dw * 1e3:.1f} ms + "
+        f"proposal {t_prop * 1e3:.1f} ms + IS rates {t_is * 1e3:.1f} ms; median rel err learned "
+        f"{np.median(rel['learned']):.3e}, smearing-only {np.median(rel['smearing']):.3e}, uniform "
+        f"{np.median(rel['uniform']):.3e}")
+    out = {
+        "metric": METRIC,
+        "value": round(n_test / t_step, 3),
+        "unit": "k-pts/s",
+        "n_gpus": 1,
+        "steps": seeds,
+        "warmup": 1,
+        "ms_per_step": round(t_step * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16 MLP + f64 rates",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"learned proposal on the realistic system: MLP {n_in}->{width}x{depth} "
+                         f"silu->1 fitting ln(|g|^2 + c) on {n_samp} samples of {ns} kept states; "
+                         f"p(q) ~ sum_nu D_nu(q) e^net, mixture 0.9 + 0.1 uniform; S={S} q per k "
+                         f"of {N}; {n_test} held-out kept k, {seeds} sampling seeds"),
+            "train_s": round(t_train, 2), "terms_s": round(t_terms, 2),
+        },
+        "plain_same_k_per_s": round(n_test / t_plain, 3),
+        "weights_ms": round(t_dw * 1e3, 3),
+        "proposal_ms": round(t_prop * 1e3, 3),
+        "is_rates_ms": round(t_is * 1e3, 3),
+        "rel_err_median": {k: float(np.median(v)) for k, v in rel.items()},
+        "rel_err_max": {k: float(v.max()) for k, v in rel.items()},
+        "coef_var_median": {k: float(np.median(v)) for k, v in cv.items()},
+        "variance_ratio_vs_uniform_median": {
+            k: float(np.median((cv[k] / cv["uniform"]) ** 2)) for k in ("learned", "smearing")},
+        "bias_in_std_errors_max": float(bias.max()),
+        "training_loss": [round(x, 4) for x in losses],
+        "target_variance": round(y_var, 4),
+    }
+    print(json.dumps(out), flush=True)
     lib.close()
 
 

@@ -67,7 +67,8 @@ typedef enum {
     PHOEBE_FP64 = 0,   /* FP64 MFMA, FP64 accumulation */
     PHOEBE_FP32 = 1,   /* operands rounded to FP32, FP32 MFMA, FP32 accumulation */
     PHOEBE_BF16X3 = 2, /* FP32 operands split hi+lo in BF16, 3 products, FP32 accumulation */
-    PHOEBE_BF16X6 = 3  /* FP32 operands split in 3 BF16 pieces, 6 products, FP32 accumulation */
+    PHOEBE_BF16X6 = 3, /* FP32 operands split in 3 BF16 pieces, 6 products, FP32 accumulation */
+    PHOEBE_BF16 = 4    /* MLP only: FP32 storage, BF16 operands, FP32 accumulation */
 } phoebe_precision;
 
 /* One crystal.  Integer lattice-vector lists are HOST pointers; the tensors
@@ -231,6 +232,91 @@ phoebe_status phoebe_gpu_batched_info(void *plan, int32_t sys, int32_t *tq, int3
 
 /* Release a plan (synchronises the device). NULL is accepted. */
 phoebe_status phoebe_gpu_batched_destroy(void *plan);
+
+/* Per-term output of the rate sum (FP64): for each kept state of the given k
+ * points, terms[state, q, nu] = 2 pi/(sqrt(pi) sigma) x sum_m |g_{nu n m}(k,q)|^2
+ *   [(n+1-f) e^{-(x-w)^2/sigma^2} + (n+f) e^{-(x+w)^2/sigma^2}]
+ * over the full q mesh, so that Gamma_nk = (1/N_q) sum_{q,nu} terms.  These are
+ * the integrand samples the learned proposal is trained on.  dweights
+ * (nullable, same shape) receives the same expression with |g|^2 = 1 (the
+ * smearing weight D), so terms / D is the |g|^2 the proposal network fits.
+ *   k_idx    device [nk] (required);  gamma_out device [nk, nW] as scatter_rates
+ *   terms    device [states, N_q, nModes] with capacity nk*nW states
+ *   st_row, st_band device int32 [states] (nullable): row (index into k_idx)
+ *            and band of each state, states ordered by row then band
+ *   n_states host (nullable)
+ * Synchronises the stream.  Terms of final bands outside the window-wide
+ * non-zero range (see phoebe_gpu_scatter_rates) are exactly zero. */
+phoebe_status phoebe_gpu_rate_terms(void *handle, const phoebe_system *sys, const int32_t mesh[3],
+                                    const int32_t *k_idx, int64_t nk,
+                                    const phoebe_rate_params *par, double *gamma_out,
+                                    double *terms, double *dweights, int32_t *st_row,
+                                    int32_t *st_band, int64_t *n_states, void *stream);
+
+/* Smearing weights D[state, q, nu] alone (see phoebe_gpu_rate_terms): band and
+ * phonon tables, window and states as in the rate path, no coupling work.
+ * gamma_scratch device [nk, nW] is zeroed.  Synchronises the stream. */
+phoebe_status phoebe_gpu_delta_weights(void *handle, const phoebe_system *sys,
+                                       const int32_t mesh[3], const int32_t *k_idx, int64_t nk,
+                                       const phoebe_rate_params *par, double *dweights,
+                                       int32_t *st_row, int32_t *st_band, int64_t *n_states,
+                                       double *gamma_scratch, void *stream);
+
+/* Learned q-proposal network: a multilayer perceptron with n_in inputs, `depth`
+ * hidden layers of `width` silu units and one linear output.  Parameters are
+ * packed layer by layer as W_l [out, in] (row major) then b_l [out].
+ * PHOEBE_BF16: float storage, BF16 operands on MFMA, FP32 accumulation;
+ * PHOEBE_FP64: double storage and arithmetic (for checking gradients).
+ * Returns the number of parameters (-1 for a bad shape). */
+int64_t phoebe_gpu_mlp_param_count(int32_t n_in, int32_t width, int32_t depth);
+
+/* out[b] = network(X[b]);  X device [batch, n_in], out device [batch]. */
+phoebe_status phoebe_gpu_mlp_forward(void *handle, phoebe_precision prec, const void *params,
+                                     int32_t n_in, int32_t width, int32_t depth, const void *X,
+                                     int64_t batch, void *out, void *stream);
+
+/* Mean squared error L = (1/B) sum_b (network(X_b) - target_b)^2 and its
+ * gradient with respect to the packed parameters (backpropagation).
+ *   grad device [param_count] (same storage type as params); loss host (nullable,
+ *   synchronises the stream when set). */
+phoebe_status phoebe_gpu_mlp_grad(void *handle, phoebe_precision prec, const void *params,
+                                  int32_t n_in, int32_t width, int32_t depth, const void *X,
+                                  const void *target, int64_t batch, void *grad, double *loss,
+                                  void *stream);
+
+/* One Adam step (Kingma & Ba, bias-corrected; step >= 1) on FP32 parameters
+ * with FP32 first and second moments m, v (device [n]). */
+phoebe_status phoebe_gpu_mlp_adam(void *handle, float *params, const float *grad, float *m,
+                                  float *v, int64_t n, int32_t step, double lr, double beta1,
+                                  double beta2, double eps, void *stream);
+
+/* Network inputs x = [k (3 crystal coords), (eps - e0)/escale, q (3), one-hot(nu)]
+ * for samples given by mesh indices k_idx, q_idx, band energy eps and mode nu
+ * (device arrays [batch]); X device [batch, 7 + n_modes] (float for BF16,
+ * double for FP64). */
+phoebe_status phoebe_gpu_mlp_features(void *handle, phoebe_precision prec, const int32_t mesh[3],
+                                      int32_t n_modes, const int32_t *k_idx, const double *eps,
+                                      const int32_t *q_idx, const int32_t *nu, int64_t batch,
+                                      double e0, double escale, void *X, void *stream);
+
+/* Importance-sampling lists from the learned proposal.  For each k (host
+ * k_idx[i], host band energy eps_k[i] of its targeted state, smearing weights
+ * dweights + i N_q nModes of that state) the proposal is
+ *   p_raw(q) = sum_nu D[q, nu] e^{net(k, eps, q, nu)}
+ * where the network (BF16) estimates ln(|g|^2 + c) and is evaluated only where
+ * D > d_threshold x max D; with params = NULL the network factor is 1 (the
+ * smearing-only proposal, the method without the network).  The proposal is
+ * p = (1 - mix) p_raw / sum p_raw + mix / N_q; mix in (0, 1] keeps every q
+ * possible, which keeps the estimate unbiased.  S points are drawn by inverse
+ * CDF of the given uniforms (device [nk, S] in [0, 1)) and weighted
+ * w = 1 / (N_q S p(q)): q_off device int64 [nk+1], q_idx device int32 [nk S],
+ * q_w device [nk S], ready for phoebe_gpu_scatter_rates.  Synchronises. */
+phoebe_status phoebe_gpu_propose_q(void *handle, const int32_t mesh[3], int32_t n_modes,
+                                   const int32_t *k_idx, const double *eps_k, int64_t nk,
+                                   const double *dweights, const float *params, int32_t width,
+                                   int32_t depth, double e0, double escale, double d_threshold,
+                                   double mix, int32_t S, const double *uniforms, int64_t *q_off,
+                                   int32_t *q_idx, double *q_w, void *stream);
 
 /* Kernel timing for measurement: when enabled, the named hot kernels are
  * bracketed by HIP events on the stream they run on; phoebe_gpu_kernel_time

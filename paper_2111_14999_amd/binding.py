@@ -19,9 +19,9 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libphoebe_gpu.so")
 
-PHOEBE_FP64, PHOEBE_FP32, PHOEBE_BF16X3, PHOEBE_BF16X6 = 0, 1, 2, 3
+PHOEBE_FP64, PHOEBE_FP32, PHOEBE_BF16X3, PHOEBE_BF16X6, PHOEBE_BF16 = 0, 1, 2, 3, 4
 PRECISIONS = {"fp64": PHOEBE_FP64, "fp32": PHOEBE_FP32, "bf16x3": PHOEBE_BF16X3,
-              "bf16x6": PHOEBE_BF16X6}
+              "bf16x6": PHOEBE_BF16X6, "bf16": PHOEBE_BF16}
 STATUS = {0: "PHOEBE_OK", -1: "PHOEBE_E_INVALID", -2: "PHOEBE_E_NOMEM", -3: "PHOEBE_E_DEVICE",
           -4: "PHOEBE_E_UNSUPPORTED", -5: "PHOEBE_E_NUMERIC"}
 
@@ -32,7 +32,9 @@ EXPORTS = (
     "phoebe_gpu_interp_g", "phoebe_gpu_scatter_rates", "phoebe_gpu_set_timing",
     "phoebe_gpu_kernel_time", "phoebe_gpu_reset_timing",
     "phoebe_gpu_batched_plan", "phoebe_gpu_batched_run", "phoebe_gpu_batched_info",
-    "phoebe_gpu_batched_destroy",
+    "phoebe_gpu_batched_destroy", "phoebe_gpu_rate_terms", "phoebe_gpu_mlp_param_count",
+    "phoebe_gpu_mlp_forward", "phoebe_gpu_mlp_grad", "phoebe_gpu_mlp_adam",
+    "phoebe_gpu_mlp_features", "phoebe_gpu_propose_q", "phoebe_gpu_delta_weights",
 )
 
 
@@ -98,8 +100,28 @@ def load(path: str = LIB_PATH):
                                             ctypes.POINTER(i64), ctypes.POINTER(i64),
                                             ctypes.POINTER(ctypes.c_double)]
     lib.phoebe_gpu_batched_destroy.argtypes = [vp]
+    lib.phoebe_gpu_rate_terms.argtypes = [vp, ctypes.POINTER(CSystem), ctypes.POINTER(i32), vp, i64,
+                                          ctypes.POINTER(CRateParams), vp, vp, vp, vp, vp,
+                                          ctypes.POINTER(i64), vp]
+    lib.phoebe_gpu_delta_weights.argtypes = [vp, ctypes.POINTER(CSystem), ctypes.POINTER(i32), vp,
+                                             i64, ctypes.POINTER(CRateParams), vp, vp, vp,
+                                             ctypes.POINTER(i64), vp, vp]
+    lib.phoebe_gpu_mlp_param_count.argtypes = [i32, i32, i32]
+    lib.phoebe_gpu_mlp_param_count.restype = i64
+    lib.phoebe_gpu_mlp_forward.argtypes = [vp, ctypes.c_int, vp, i32, i32, i32, vp, i64, vp, vp]
+    lib.phoebe_gpu_mlp_grad.argtypes = [vp, ctypes.c_int, vp, i32, i32, i32, vp, vp, i64, vp,
+                                        ctypes.POINTER(ctypes.c_double), vp]
+    lib.phoebe_gpu_mlp_adam.argtypes = [vp, vp, vp, vp, vp, i64, i32, ctypes.c_double,
+                                        ctypes.c_double, ctypes.c_double, ctypes.c_double, vp]
+    lib.phoebe_gpu_mlp_features.argtypes = [vp, ctypes.c_int, ctypes.POINTER(i32), i32, vp, vp, vp,
+                                            vp, i64, ctypes.c_double, ctypes.c_double, vp, vp]
+    lib.phoebe_gpu_propose_q.argtypes = [vp, ctypes.POINTER(i32), i32, ctypes.POINTER(i32),
+                                         ctypes.POINTER(ctypes.c_double), i64, vp, vp, i32, i32,
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_double, i32, vp, vp, vp, vp, vp]
     for name in EXPORTS:
-        if name not in ("phoebe_gpu_abi_version", "phoebe_gpu_last_error"):
+        if name not in ("phoebe_gpu_abi_version", "phoebe_gpu_last_error",
+                        "phoebe_gpu_mlp_param_count"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -232,6 +254,74 @@ class Library:
             ctypes.byref(p), PRECISIONS[precision], _ptr(gamma_out), _ptr(band_mask),
             _ptr(kept_k_out), ctypes.byref(n_kept), _stream(stream)))
         return int(n_kept.value)
+
+    # -- learned proposal ---------------------------------------------------
+    def rate_terms(self, sys: DeviceSystem, mesh, params: dict, k_idx, gamma_out, terms,
+                   dweights=None, st_row=None, st_band=None, stream=None) -> int:
+        c = sys.c_struct()
+        m = (ctypes.c_int32 * 3)(*[int(x) for x in mesh])
+        p = CRateParams(params["mu"], params["kT"], params["sigma"], params["win_lo"],
+                        params["win_hi"], params.get("omega_min", 1e-4))
+        ns = ctypes.c_int64(0)
+        self._check(self.lib.phoebe_gpu_rate_terms(
+            self.handle, ctypes.byref(c), m, _ptr(k_idx), int(k_idx.shape[0]), ctypes.byref(p),
+            _ptr(gamma_out), _ptr(terms), _ptr(dweights), _ptr(st_row), _ptr(st_band),
+            ctypes.byref(ns), _stream(stream)))
+        return int(ns.value)
+
+    def delta_weights(self, sys: DeviceSystem, mesh, params: dict, k_idx, dweights, gamma_scratch,
+                      st_row=None, st_band=None, stream=None) -> int:
+        c = sys.c_struct()
+        m = (ctypes.c_int32 * 3)(*[int(x) for x in mesh])
+        p = CRateParams(params["mu"], params["kT"], params["sigma"], params["win_lo"],
+                        params["win_hi"], params.get("omega_min", 1e-4))
+        ns = ctypes.c_int64(0)
+        self._check(self.lib.phoebe_gpu_delta_weights(
+            self.handle, ctypes.byref(c), m, _ptr(k_idx), int(k_idx.shape[0]), ctypes.byref(p),
+            _ptr(dweights), _ptr(st_row), _ptr(st_band), ctypes.byref(ns), _ptr(gamma_scratch),
+            _stream(stream)))
+        return int(ns.value)
+
+    @staticmethod
+    def mlp_param_count(n_in, width, depth) -> int:
+        return int(load().phoebe_gpu_mlp_param_count(n_in, width, depth))
+
+    def mlp_forward(self, params, X, out, n_in, width, depth, precision="bf16", stream=None):
+        self._check(self.lib.phoebe_gpu_mlp_forward(
+            self.handle, PRECISIONS[precision], _ptr(params), n_in, width, depth, _ptr(X),
+            int(X.shape[0]), _ptr(out), _stream(stream)))
+
+    def mlp_grad(self, params, X, target, grad, n_in, width, depth, precision="bf16",
+                 stream=None) -> float:
+        loss = ctypes.c_double(0.0)
+        self._check(self.lib.phoebe_gpu_mlp_grad(
+            self.handle, PRECISIONS[precision], _ptr(params), n_in, width, depth, _ptr(X),
+            _ptr(target), int(X.shape[0]), _ptr(grad), ctypes.byref(loss), _stream(stream)))
+        return float(loss.value)
+
+    def mlp_adam(self, params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8,
+                 stream=None):
+        self._check(self.lib.phoebe_gpu_mlp_adam(
+            self.handle, _ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(params.numel()),
+            int(step), lr, beta1, beta2, eps, _stream(stream)))
+
+    def mlp_features(self, mesh, n_modes, k_idx, eps, q_idx, nu, X, e0, escale,
+                     precision="bf16", stream=None):
+        m = (ctypes.c_int32 * 3)(*[int(x) for x in mesh])
+        self._check(self.lib.phoebe_gpu_mlp_features(
+            self.handle, PRECISIONS[precision], m, n_modes, _ptr(k_idx), _ptr(eps), _ptr(q_idx),
+            _ptr(nu), int(k_idx.shape[0]), e0, escale, _ptr(X), _stream(stream)))
+
+    def propose_q(self, mesh, n_modes, k_idx, eps_k, dweights, params, width, depth, e0, escale,
+                  d_threshold, mix, S, uniforms, q_off, q_idx, q_w, stream=None):
+        m = (ctypes.c_int32 * 3)(*[int(x) for x in mesh])
+        nk = len(k_idx)
+        kk = (ctypes.c_int32 * nk)(*[int(x) for x in k_idx])
+        ee = (ctypes.c_double * nk)(*[float(x) for x in eps_k])
+        self._check(self.lib.phoebe_gpu_propose_q(
+            self.handle, m, n_modes, kk, ee, nk, _ptr(dweights), _ptr(params), width, depth, e0,
+            escale, d_threshold, mix, S, _ptr(uniforms), _ptr(q_off), _ptr(q_idx), _ptr(q_w),
+            _stream(stream)))
 
     # -- batched form -------------------------------------------------------
     def batched_plan(self, systems, meshes, params_list, precision="fp32", tune_cache=None,

@@ -274,13 +274,19 @@ phoebe_status phoebe_gpu_interp_g(void* handle, const phoebe_system* sys, const 
     });
 }
 
-phoebe_status phoebe_gpu_scatter_rates(void* handle, const phoebe_system* sys,
-                                       const int32_t mesh_in[3], const int32_t* k_idx, int64_t nk,
-                                       const int64_t* q_off, const int32_t* q_idx,
-                                       const double* q_w, const phoebe_rate_params* par,
-                                       phoebe_precision prec, double* gamma_out,
-                                       uint8_t* band_mask, int32_t* kept_k_out,
-                                       int64_t* n_kept_out, void* stream) {
+}  // extern "C"
+
+// Rate path; with `terms` (FP64, full q mesh only) it also writes each kept
+// state's per-(q, mode) terms and the state list.
+static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
+                                        const int32_t mesh_in[3], const int32_t* k_idx, int64_t nk,
+                                        const int64_t* q_off, const int32_t* q_idx,
+                                        const double* q_w, const phoebe_rate_params* par,
+                                        phoebe_precision prec, double* gamma_out,
+                                        uint8_t* band_mask, int32_t* kept_k_out,
+                                        int64_t* n_kept_out, double* terms, int32_t* st_row_out,
+                                        int32_t* st_band_out, int64_t* n_states_out,
+                                        double* dweights, bool rates, void* stream) {
     if (!handle) return PHOEBE_E_INVALID;
     Handle* h = static_cast<Handle*>(handle);
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -301,6 +307,10 @@ phoebe_status phoebe_gpu_scatter_rates(void* handle, const phoebe_system* sys,
         REQUIRE(h, (q_off == nullptr) == (q_idx == nullptr) && (q_off == nullptr) == (q_w == nullptr),
                 "q_off, q_idx and q_w must be all NULL or all set");
         REQUIRE(h, q_off == nullptr || k_idx != nullptr, "explicit q lists need explicit k_idx");
+        REQUIRE(h, terms == nullptr || (prec == PHOEBE_FP64 && q_off == nullptr && k_idx != nullptr),
+                "per-term output needs FP64, explicit k_idx and the full q mesh");
+        REQUIRE(h, dweights == nullptr || (q_off == nullptr && k_idx != nullptr),
+                "smearing weights need explicit k_idx and the full q mesh");
         const Mesh mesh{mesh_in[0], mesh_in[1], mesh_in[2]};
         const int64_t N = (int64_t)mesh.n0 * mesh.n1 * mesh.n2;
         REQUIRE(h, N <= (int64_t)1 << 30, "mesh too large");
@@ -470,6 +480,7 @@ phoebe_status phoebe_gpu_scatter_rates(void* handle, const phoebe_system* sys,
         HIPCHK(h, hipMemcpyAsync(&nst_i, T.cnt + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIPCHK(h, hipStreamSynchronize(s));
         const int nst = nst_i;
+        if (n_states_out) *n_states_out = nst;
         if (nst == 0) {
             flush_timing(h, s);
             return;
@@ -477,6 +488,23 @@ phoebe_status phoebe_gpu_scatter_rates(void* handle, const phoebe_system* sys,
         const double cut = 27.5 * par->sigma;  // exp(-27.5^2) underflows to 0 in FP64
         HIPCHK(h, launch_build_states(T.ids, nst, nW, kept, T.eps, T.bmin, T.bmax, T.wmax, cut,
                                       T.st_row, T.st_band, T.st_kmesh, T.st_mlo, T.st_mhi, s));
+        if (dweights)
+            HIPCHK(h, launch_delta_weights(nst, N, mesh, T.st_kmesh, T.st_band, T.st_mlo, T.st_mhi,
+                                           T.eps, T.focc, T.omega, T.nb, nW, nm, par->sigma,
+                                           par->omega_min,
+                                           2.0 * kPi / (std::sqrt(kPi) * par->sigma), dweights, s));
+        if (terms || dweights) {
+            if (terms) HIPCHK(h, launch_zero(terms, (size_t)nst * N * nm * sizeof(double), s));
+            if (st_row_out)
+                HIPCHK(h, hipMemcpyAsync(st_row_out, T.st_row, 4 * (size_t)nst, hipMemcpyDeviceToDevice, s));
+            if (st_band_out)
+                HIPCHK(h, hipMemcpyAsync(st_band_out, T.st_band, 4 * (size_t)nst, hipMemcpyDeviceToDevice, s));
+        }
+        if (!rates) {
+            HIPCHK(h, hipStreamSynchronize(s));
+            flush_timing(h, s);
+            return;
+        }
         std::vector<int32_t> strow(nst);
         HIPCHK(h, hipMemcpyAsync(strow.data(), T.st_row, sizeof(int32_t) * nst,
                                  hipMemcpyDeviceToHost, s));
@@ -543,6 +571,8 @@ phoebe_status phoebe_gpu_scatter_rates(void* handle, const phoebe_system* sys,
             ra.sigma = par->sigma;
             ra.partial = partial;
             ra.n_qtiles = n_qtiles;
+            ra.terms = terms ? terms + (int64_t)sbeg * N * nm : nullptr;
+            ra.terms_scale = 2.0 * kPi * inv_sqrtpi_sigma;
             Timer t2(h, s, "stage2_rates");
             if (lowp) {
                 RateArgsLP rl{};
@@ -567,6 +597,50 @@ phoebe_status phoebe_gpu_scatter_rates(void* handle, const phoebe_system* sys,
         HIPCHK(h, hipGetLastError());
         flush_timing(h, s);
     });
+}
+
+extern "C" {
+
+phoebe_status phoebe_gpu_scatter_rates(void* handle, const phoebe_system* sys,
+                                       const int32_t mesh[3], const int32_t* k_idx, int64_t nk,
+                                       const int64_t* q_off, const int32_t* q_idx,
+                                       const double* q_w, const phoebe_rate_params* par,
+                                       phoebe_precision prec, double* gamma_out,
+                                       uint8_t* band_mask, int32_t* kept_k_out,
+                                       int64_t* n_kept_out, void* stream) {
+    return scatter_rates_impl(handle, sys, mesh, k_idx, nk, q_off, q_idx, q_w, par, prec,
+                              gamma_out, band_mask, kept_k_out, n_kept_out, nullptr, nullptr,
+                              nullptr, nullptr, nullptr, true, stream);
+}
+
+phoebe_status phoebe_gpu_rate_terms(void* handle, const phoebe_system* sys, const int32_t mesh[3],
+                                    const int32_t* k_idx, int64_t nk,
+                                    const phoebe_rate_params* par, double* gamma_out,
+                                    double* terms, double* dweights, int32_t* st_row,
+                                    int32_t* st_band, int64_t* n_states, void* stream) {
+    if (!handle) return PHOEBE_E_INVALID;
+    if (!terms) {
+        static_cast<Handle*>(handle)->err = "terms is NULL";
+        return PHOEBE_E_INVALID;
+    }
+    return scatter_rates_impl(handle, sys, mesh, k_idx, nk, nullptr, nullptr, nullptr, par,
+                              PHOEBE_FP64, gamma_out, nullptr, nullptr, nullptr, terms, st_row,
+                              st_band, n_states, dweights, true, stream);
+}
+
+phoebe_status phoebe_gpu_delta_weights(void* handle, const phoebe_system* sys,
+                                       const int32_t mesh[3], const int32_t* k_idx, int64_t nk,
+                                       const phoebe_rate_params* par, double* dweights,
+                                       int32_t* st_row, int32_t* st_band, int64_t* n_states,
+                                       double* gamma_scratch, void* stream) {
+    if (!handle) return PHOEBE_E_INVALID;
+    if (!dweights) {
+        static_cast<Handle*>(handle)->err = "dweights is NULL";
+        return PHOEBE_E_INVALID;
+    }
+    return scatter_rates_impl(handle, sys, mesh, k_idx, nk, nullptr, nullptr, nullptr, par,
+                              PHOEBE_FP64, gamma_scratch, nullptr, nullptr, nullptr, nullptr,
+                              st_row, st_band, n_states, dweights, false, stream);
 }
 
 }  // extern "C"

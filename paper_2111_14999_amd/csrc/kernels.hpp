@@ -81,6 +81,8 @@ struct RateArgs {
     double sigma;
     double* partial;           // [nst, n_qtiles]
     int n_qtiles;
+    double* terms;             // nullable [nst, nq_mesh, nm]: per-(q, mode) terms, summed over m
+    double terms_scale;        // factor applied to each stored term
 };
 
 // Fused stage 2 (sum over Rp on MFMA) + rotations + rate terms.
@@ -108,6 +110,12 @@ hipError_t launch_build_states(const int32_t* ids, int nst, int nW, const int32_
                                int32_t* st_kmesh, int32_t* st_mlo, int32_t* st_mhi,
                                hipStream_t s);
 int stage2_config(int nm, int nW, int* tq_out, int* tn_out);
+
+hipError_t launch_delta_weights(int nst, int64_t N, Mesh mesh, const int32_t* st_kmesh,
+                                const int32_t* st_band, const int32_t* st_mlo,
+                                const int32_t* st_mhi, const double* eps, const double* focc,
+                                const double* omega, const double* nb, int nW, int nm, double sigma,
+                                double omega_min, double scale, double* D, hipStream_t s);
 
 // helpers
 hipError_t launch_kq_points(const double* k, int64_t nk, const double* q, int64_t nq,

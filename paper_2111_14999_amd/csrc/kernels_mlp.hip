@@ -1,0 +1,546 @@
+// Learned q-proposal: multilayer perceptron training and inference kernels,
+// the proposal/inverse-CDF sampler and the importance-sampling weights.
+//
+// Network: z_l = W_l a_{l-1} + b_l, a_l = silu(z_l) for hidden layers, linear
+// output; parameters packed per layer as W_l [out, in] then b_l [out].
+// Two arithmetic paths: BF16 operands on v_mfma_f32_16x16x32_bf16 with FP32
+// accumulation (float storage), and an FP64 path on v_mfma_f64_16x16x4f64
+// (double storage) used to check gradients against the FP64 oracle.
+#include "mlp.hpp"
+
+namespace phx {
+
+static inline int gridm(int64_t n, int block) {
+    int64_t g = (n + block - 1) / block;
+    if (g > 65535 * 16) g = 65535 * 16;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+__device__ inline uint16_t f2bf(float x) {
+    const uint32_t u = __float_as_uint(x);
+    return (uint16_t)((u + (((u >> 16) & 1u) + 0x7FFFu)) >> 16);
+}
+
+typedef short s8m __attribute__((ext_vector_type(8)));
+typedef __bf16 bf8m __attribute__((ext_vector_type(8)));
+
+// ---------------------------------------------------------------------------
+// C[M, N] = op(A)[M, K] op(B)[K, N] (+ bias[N]) (+ C if accumulate)
+//   A(i, k) = TA ? A[k lda + i] : A[i lda + k];  B(k, j) = TB ? B[j ldb + k] : B[k ldb + j]
+// Work-group: 4 waves side by side along N, each 2 x 2 tiles of 16 x 16.
+// ---------------------------------------------------------------------------
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void mlp_gemm_bf16(const float* __restrict__ A, int64_t lda,
+                                                     const float* __restrict__ B, int64_t ldb,
+                                                     float* __restrict__ C, int64_t ldc, int64_t M,
+                                                     int64_t N, int64_t K,
+                                                     const float* __restrict__ bias, int accumulate) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int64_t m0 = (int64_t)blockIdx.y * 32;
+    const int64_t n0 = ((int64_t)blockIdx.x * 4 + wave) * 32;
+    if (n0 >= N) return;
+    f4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) acc[i][t] = f4{0, 0, 0, 0};
+    for (int64_t k0 = 0; k0 < K; k0 += 32) {
+        s8m a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int64_t row = m0 + 16 * i + li;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int64_t k = k0 + 8 * lk + j;
+                float v = 0.f;
+                if (row < M && k < K) v = TA ? A[k * lda + row] : A[row * lda + k];
+                a[i][j] = (short)f2bf(v);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int64_t col = n0 + 16 * t + li;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int64_t k = k0 + 8 * lk + j;
+                float v = 0.f;
+                if (col < N && k < K) v = TB ? B[col * ldb + k] : B[k * ldb + col];
+                b[t][j] = (short)f2bf(v);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+                acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    __builtin_bit_cast(bf8m, a[i]), __builtin_bit_cast(bf8m, b[t]), acc[i][t], 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t row = m0 + 16 * i + 4 * lk + v;
+                const int64_t col = n0 + 16 * t + li;
+                if (row < M && col < N) {
+                    float r = acc[i][t][v];
+                    if (bias) r += bias[col];
+                    if (accumulate) r += C[row * ldc + col];
+                    C[row * ldc + col] = r;
+                }
+            }
+}
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void mlp_gemm_f64(const double* __restrict__ A, int64_t lda,
+                                                    const double* __restrict__ B, int64_t ldb,
+                                                    double* __restrict__ C, int64_t ldc, int64_t M,
+                                                    int64_t N, int64_t K,
+                                                    const double* __restrict__ bias, int accumulate) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int64_t m0 = (int64_t)blockIdx.y * 32;
+    const int64_t n0 = ((int64_t)blockIdx.x * 4 + wave) * 32;
+    if (n0 >= N) return;
+    d4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int t = 0; t < 2; ++t) acc[i][t] = d4{0, 0, 0, 0};
+    for (int64_t k0 = 0; k0 < K; k0 += 4) {
+        const int64_t k = k0 + lk;
+        double a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int64_t row = m0 + 16 * i + li;
+            a[i] = (row < M && k < K) ? (TA ? A[k * lda + row] : A[row * lda + k]) : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int64_t col = n0 + 16 * t + li;
+            b[t] = (col < N && k < K) ? (TB ? B[col * ldb + k] : B[k * ldb + col]) : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+                acc[i][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[t], acc[i][t], 0, 0, 0);
+    }
+    // f64 MFMA result v of lane group lk is row lk + 4v
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t row = m0 + 16 * i + lk + 4 * v;
+                const int64_t col = n0 + 16 * t + li;
+                if (row < M && col < N) {
+                    double r = acc[i][t][v];
+                    if (bias) r += bias[col];
+                    if (accumulate) r += C[row * ldc + col];
+                    C[row * ldc + col] = r;
+                }
+            }
+}
+
+template <class T>
+hipError_t launch_mlp_gemm(bool ta, bool tb, const T* A, int64_t lda, const T* B, int64_t ldb, T* C,
+                           int64_t ldc, int64_t M, int64_t N, int64_t K, const T* bias, int acc,
+                           hipStream_t s) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    dim3 grid((unsigned)((N + 127) / 128), (unsigned)((M + 31) / 32));
+    if (grid.y > 65535) return hipErrorInvalidValue;
+#define PHX_GO(TAv, TBv)                                                                        \
+    if (ta == TAv && tb == TBv) {                                                               \
+        if constexpr (sizeof(T) == 4)                                                           \
+            hipLaunchKernelGGL((mlp_gemm_bf16<TAv, TBv>), grid, dim3(256), 0, s,                  \
+                               (const float*)A, lda, (const float*)B, ldb, (float*)C, ldc, M, N, \
+                               K, (const float*)bias, acc);                                      \
+        else                                                                                    \
+            hipLaunchKernelGGL((mlp_gemm_f64<TAv, TBv>), grid, dim3(256), 0, s,                   \
+                               (const double*)A, lda, (const double*)B, ldb, (double*)C, ldc, M, \
+                               N, K, (const double*)bias, acc);                                  \
+        return hipGetLastError();                                                               \
+    }
+    PHX_GO(false, false) PHX_GO(false, true) PHX_GO(true, false) PHX_GO(true, true)
+#undef PHX_GO
+    return hipErrorInvalidValue;
+}
+template hipError_t launch_mlp_gemm<float>(bool, bool, const float*, int64_t, const float*, int64_t,
+                                           float*, int64_t, int64_t, int64_t, int64_t, const float*,
+                                           int, hipStream_t);
+template hipError_t launch_mlp_gemm<double>(bool, bool, const double*, int64_t, const double*,
+                                            int64_t, double*, int64_t, int64_t, int64_t, int64_t,
+                                            const double*, int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// elementwise pieces
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void silu_fwd_kernel(const T* z, T* a, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const T x = z[i];
+        a[i] = x / ((T)1 + exp(-x));
+    }
+}
+template <class T>
+__global__ void silu_bwd_kernel(const T* da, const T* z, T* dz, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const T x = z[i];
+        const T sg = (T)1 / ((T)1 + exp(-x));
+        dz[i] = da[i] * sg * ((T)1 + x * ((T)1 - sg));
+    }
+}
+// dY = 2 (Y - t) / B; squared errors summed per block into sums[block]
+template <class T>
+__global__ void mse_grad_kernel(const T* y, const T* t, T* dy, int64_t B, double* sums) {
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < B;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const T r = y[i] - t[i];
+        dy[i] = (T)2 * r / (T)B;
+        acc += (double)r * (double)r;
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sums[blockIdx.x] = sh[0];
+}
+// db[j] = sum_b dZ[b, j]
+template <class T>
+__global__ __launch_bounds__(256) void colsum_kernel(const T* dz, int64_t B, int64_t N, T* db) {
+    __shared__ double sh[256];
+    const int64_t j = blockIdx.x;
+    double acc = 0.0;
+    for (int64_t b = threadIdx.x; b < B; b += 256) acc += (double)dz[b * N + j];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) db[j] = (T)sh[0];
+}
+
+template <class T>
+hipError_t launch_silu_fwd(const T* z, T* a, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(silu_fwd_kernel<T>, dim3(gridm(n, 256)), dim3(256), 0, s, z, a, n);
+    return hipGetLastError();
+}
+template <class T>
+hipError_t launch_silu_bwd(const T* da, const T* z, T* dz, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(silu_bwd_kernel<T>, dim3(gridm(n, 256)), dim3(256), 0, s, da, z, dz, n);
+    return hipGetLastError();
+}
+template <class T>
+hipError_t launch_mse_grad(const T* y, const T* t, T* dy, int64_t B, double* sums, int nblk,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(mse_grad_kernel<T>, dim3(nblk), dim3(256), 0, s, y, t, dy, B, sums);
+    return hipGetLastError();
+}
+template <class T>
+hipError_t launch_colsum(const T* dz, int64_t B, int64_t N, T* db, hipStream_t s) {
+    hipLaunchKernelGGL(colsum_kernel<T>, dim3((unsigned)N), dim3(256), 0, s, dz, B, N, db);
+    return hipGetLastError();
+}
+#define PHX_INST(T)                                                                              \
+    template hipError_t launch_silu_fwd<T>(const T*, T*, int64_t, hipStream_t);                  \
+    template hipError_t launch_silu_bwd<T>(const T*, const T*, T*, int64_t, hipStream_t);         \
+    template hipError_t launch_mse_grad<T>(const T*, const T*, T*, int64_t, double*, int,          \
+                                           hipStream_t);                                          \
+    template hipError_t launch_colsum<T>(const T*, int64_t, int64_t, T*, hipStream_t);
+PHX_INST(float)
+PHX_INST(double)
+#undef PHX_INST
+
+// Adam on FP32 master parameters (Kingma & Ba, bias-corrected moments)
+__global__ void adam_kernel(float* p, const float* g, float* m, float* v, int64_t n, double lr,
+                            double b1, double b2, double eps, double c1, double c2) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double gi = g[i];
+        const double mi = b1 * m[i] + (1.0 - b1) * gi;
+        const double vi = b2 * v[i] + (1.0 - b2) * gi * gi;
+        m[i] = (float)mi;
+        v[i] = (float)vi;
+        p[i] = (float)(p[i] - lr * (mi / c1) / (sqrt(vi / c2) + eps));
+    }
+}
+
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, int t, double lr,
+                       double b1, double b2, double eps, hipStream_t s) {
+    const double c1 = 1.0 - pow(b1, t), c2 = 1.0 - pow(b2, t);
+    hipLaunchKernelGGL(adam_kernel, dim3(gridm(n, 256)), dim3(256), 0, s, p, g, m, v, n, lr, b1, b2,
+                       eps, c1, c2);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// features x = [k (3), (eps - e0)/escale, q (3), one-hot(nu, nm)] for sample b
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ void features_kernel(const int32_t* k_idx, const double* eps, const int32_t* q_idx,
+                                const int32_t* nu, int64_t B, Mesh mesh, int nm, double e0,
+                                double escale, T* X) {
+    const int nin = 7 + nm;
+    for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < B;
+         b += (int64_t)gridDim.x * blockDim.x) {
+        int k0, k1, k2, q0, q1, q2;
+        mesh_triple(k_idx[b], mesh, k0, k1, k2);
+        mesh_triple(q_idx[b], mesh, q0, q1, q2);
+        T* x = X + b * nin;
+        x[0] = (T)((double)k0 / mesh.n0);
+        x[1] = (T)((double)k1 / mesh.n1);
+        x[2] = (T)((double)k2 / mesh.n2);
+        x[3] = (T)((eps[b] - e0) / escale);
+        x[4] = (T)((double)q0 / mesh.n0);
+        x[5] = (T)((double)q1 / mesh.n1);
+        x[6] = (T)((double)q2 / mesh.n2);
+        for (int v = 0; v < nm; ++v) x[7 + v] = (T)(v == nu[b] ? 1 : 0);
+    }
+}
+
+template <class T>
+hipError_t launch_features(const int32_t* k_idx, const double* eps, const int32_t* q_idx,
+                           const int32_t* nu, int64_t B, Mesh mesh, int nm, double e0,
+                           double escale, T* X, hipStream_t s) {
+    if (B <= 0) return hipSuccess;
+    hipLaunchKernelGGL(features_kernel<T>, dim3(gridm(B, 256)), dim3(256), 0, s, k_idx, eps, q_idx,
+                       nu, B, mesh, nm, e0, escale, X);
+    return hipGetLastError();
+}
+template hipError_t launch_features<float>(const int32_t*, const double*, const int32_t*,
+                                           const int32_t*, int64_t, Mesh, int, double, double,
+                                           float*, hipStream_t);
+template hipError_t launch_features<double>(const int32_t*, const double*, const int32_t*,
+                                            const int32_t*, int64_t, Mesh, int, double, double,
+                                            double*, hipStream_t);
+
+// features of every (q, nu) of q in [q0, q0 + nq) for one k (proposal evaluation)
+__global__ void features_grid_kernel(int32_t kmesh, double eps, int64_t q0, int64_t nq, Mesh mesh,
+                                     int nm, double e0, double escale, float* X) {
+    const int nin = 7 + nm;
+    const int64_t total = nq * nm;
+    int k0, k1, k2;
+    mesh_triple(kmesh, mesh, k0, k1, k2);
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < total;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t q = q0 + r / nm;
+        const int nu = (int)(r % nm);
+        int a0, a1, a2;
+        mesh_triple(q, mesh, a0, a1, a2);
+        float* x = X + r * nin;
+        x[0] = (float)((double)k0 / mesh.n0);
+        x[1] = (float)((double)k1 / mesh.n1);
+        x[2] = (float)((double)k2 / mesh.n2);
+        x[3] = (float)((eps - e0) / escale);
+        x[4] = (float)((double)a0 / mesh.n0);
+        x[5] = (float)((double)a1 / mesh.n1);
+        x[6] = (float)((double)a2 / mesh.n2);
+        for (int v = 0; v < nm; ++v) x[7 + v] = v == nu ? 1.f : 0.f;
+    }
+}
+
+hipError_t launch_features_grid(int32_t kmesh, double eps, int64_t q0, int64_t nq, Mesh mesh,
+                                int nm, double e0, double escale, float* X, hipStream_t s) {
+    hipLaunchKernelGGL(features_grid_kernel, dim3(gridm(nq * nm, 256)), dim3(256), 0, s, kmesh, eps,
+                       q0, nq, mesh, nm, e0, escale, X);
+    return hipGetLastError();
+}
+
+// p_raw[q] = sum_nu max(exp(y[q nm + nu]) - c, 0)
+__global__ void proposal_raw_kernel(const float* y, int64_t nq, int nm, double c, double* p) {
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nq;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        double acc = 0.0;
+        for (int v = 0; v < nm; ++v) {
+            const double e = exp(fmin((double)y[q * nm + v], 80.0)) - c;
+            acc += e > 0.0 ? e : 0.0;
+        }
+        p[q] = acc;
+    }
+}
+
+hipError_t launch_proposal_raw(const float* y, int64_t nq, int nm, double c, double* p,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(proposal_raw_kernel, dim3(gridm(nq, 256)), dim3(256), 0, s, y, nq, nm, c, p);
+    return hipGetLastError();
+}
+
+// max of a row (single work-group)
+__global__ __launch_bounds__(1024) void rowmax_kernel(const double* x, int64_t n, double* out) {
+    __shared__ double sh[1024];
+    double m = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) m = fmax(m, x[i]);
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0];
+}
+
+// list (in any order) of the entries with D > thr * max; count[0] must start at 0
+__global__ void select_kernel(const double* D, int64_t n, const double* dmax, double thr,
+                              int32_t* list, int32_t* count) {
+    const double cut = thr * *dmax;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        if (D[i] > cut) list[atomicAdd(count, 1)] = (int32_t)i;
+}
+
+// features of listed (q, nu) entries r = q nm + nu for one k
+__global__ void features_list_kernel(int32_t kmesh, double eps, const int32_t* list, int64_t n,
+                                     Mesh mesh, int nm, double e0, double escale, float* X) {
+    const int nin = 7 + nm;
+    int k0, k1, k2;
+    mesh_triple(kmesh, mesh, k0, k1, k2);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = list[i];
+        const int64_t q = r / nm;
+        const int nu = (int)(r % nm);
+        int a0, a1, a2;
+        mesh_triple(q, mesh, a0, a1, a2);
+        float* x = X + i * nin;
+        x[0] = (float)((double)k0 / mesh.n0);
+        x[1] = (float)((double)k1 / mesh.n1);
+        x[2] = (float)((double)k2 / mesh.n2);
+        x[3] = (float)((eps - e0) / escale);
+        x[4] = (float)((double)a0 / mesh.n0);
+        x[5] = (float)((double)a1 / mesh.n1);
+        x[6] = (float)((double)a2 / mesh.n2);
+        for (int v = 0; v < nm; ++v) x[7 + v] = v == nu ? 1.f : 0.f;
+    }
+}
+
+// E[list[i]] = D[list[i]] exp(y[i])
+__global__ void weight_list_kernel(const double* D, const int32_t* list, const float* y, int64_t n,
+                                   double* E) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = list[i];
+        E[r] = D[r] * exp(fmin((double)y[i], 80.0));
+    }
+}
+
+// p_raw[q] = sum_nu E[q nm + nu] (fixed order)
+__global__ void sum_modes_kernel(const double* E, int64_t N, int nm, double* p) {
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < N;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        double acc = 0.0;
+        for (int v = 0; v < nm; ++v) acc += E[q * nm + v];
+        p[q] = acc;
+    }
+}
+
+hipError_t launch_rowmax(const double* x, int64_t n, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(rowmax_kernel, dim3(1), dim3(1024), 0, s, x, n, out);
+    return hipGetLastError();
+}
+hipError_t launch_select(const double* D, int64_t n, const double* dmax, double thr, int32_t* list,
+                         int32_t* count, hipStream_t s) {
+    hipLaunchKernelGGL(select_kernel, dim3(gridm(n, 256)), dim3(256), 0, s, D, n, dmax, thr, list,
+                       count);
+    return hipGetLastError();
+}
+hipError_t launch_features_list(int32_t kmesh, double eps, const int32_t* list, int64_t n,
+                                Mesh mesh, int nm, double e0, double escale, float* X,
+                                hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(features_list_kernel, dim3(gridm(n, 256)), dim3(256), 0, s, kmesh, eps, list,
+                       n, mesh, nm, e0, escale, X);
+    return hipGetLastError();
+}
+hipError_t launch_weight_list(const double* D, const int32_t* list, const float* y, int64_t n,
+                              double* E, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(weight_list_kernel, dim3(gridm(n, 256)), dim3(256), 0, s, D, list, y, n, E);
+    return hipGetLastError();
+}
+hipError_t launch_sum_modes(const double* E, int64_t N, int nm, double* p, hipStream_t s) {
+    hipLaunchKernelGGL(sum_modes_kernel, dim3(gridm(N, 256)), dim3(256), 0, s, E, N, nm, p);
+    return hipGetLastError();
+}
+
+// One work-group per k: normalise p_raw (mixed with the uniform distribution),
+// build the CDF by an ordered FP64 scan, draw S points by inverse CDF of the
+// given uniforms and write the importance weights 1 / (N S p(q)).
+__global__ __launch_bounds__(1024) void sample_kernel(double* p, int64_t N, double mix,
+                                                      const double* u, int S, int32_t* q_idx,
+                                                      double* q_w) {
+    __shared__ double wsum[16];
+    __shared__ double base_sh;
+    __shared__ double total_sh;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // total of p_raw
+    double loc = 0.0;
+    for (int64_t i = tid; i < N; i += 1024) loc += p[i];
+    for (int o = 32; o > 0; o >>= 1) loc += __shfl_xor(loc, o, 64);
+    if (lane == 0) wsum[wave] = loc;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+        for (int w = 0; w < 16; ++w) t += wsum[w];
+        total_sh = t;
+        base_sh = 0.0;
+    }
+    __syncthreads();
+    const double tot = total_sh;
+    const double a = tot > 0.0 ? (1.0 - mix) / tot : 0.0;
+    const double b = tot > 0.0 ? mix / (double)N : 1.0 / (double)N;
+    // p <- normalised mixture; then in-place inclusive scan (CDF)
+    for (int64_t c0 = 0; c0 < N; c0 += 1024) {
+        const int64_t i = c0 + tid;
+        double v = i < N ? a * p[i] + b : 0.0;
+        double x = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const double y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        __syncthreads();
+        if (lane == 63) wsum[wave] = x;
+        __syncthreads();
+        double before = base_sh;
+        for (int w = 0; w < wave; ++w) before += wsum[w];
+        if (i < N) p[i] = before + x;
+        __syncthreads();
+        if (tid == 1023) base_sh = before + x;
+        __syncthreads();
+    }
+    const double last = p[N - 1];
+    for (int j = tid; j < S; j += 1024) {
+        const double target = u[j] * last;
+        int64_t lo = 0, hi = N - 1;
+        while (lo < hi) {  // first index with CDF > target
+            const int64_t mid = (lo + hi) / 2;
+            if (p[mid] > target)
+                hi = mid;
+            else
+                lo = mid + 1;
+        }
+        const double pq = (p[lo] - (lo > 0 ? p[lo - 1] : 0.0)) / last;
+        q_idx[j] = (int32_t)lo;
+        q_w[j] = 1.0 / ((double)N * (double)S * pq);
+    }
+}
+
+hipError_t launch_sample(double* p, int64_t N, double mix, const double* u, int S, int32_t* q_idx,
+                         double* q_w, hipStream_t s) {
+    hipLaunchKernelGGL(sample_kernel, dim3(1), dim3(1024), 0, s, p, N, mix, u, S, q_idx, q_w);
+    return hipGetLastError();
+}
+
+}  // namespace phx

@@ -264,7 +264,10 @@ __global__ __launch_bounds__(256, (TN >= 12 ? 1 : 2)) void stage2_rates_kernel(R
                 const double w = a.omega[q * nm + nu], nbq = a.nb[q * nm + nu];
                 const double y1 = x - w, y2 = x + w;
                 const double g1 = exp(-y1 * y1 * inv_s2), g2 = exp(-y2 * y2 * inv_s2);
-                gacc += sWq[c] * cabs2(z) * ((nbq + 1.0 - fm) * g1 + (nbq + fm) * g2);
+                const double term = cabs2(z) * ((nbq + 1.0 - fm) * g1 + (nbq + fm) * g2);
+                gacc += sWq[c] * term;
+                if (a.terms)
+                    atomicAdd(&a.terms[((int64_t)st * a.nq_mesh + q) * nm + nu], a.terms_scale * term);
             }
             __syncthreads();
         }
@@ -303,6 +306,7 @@ static hipError_t go_stage2(const RateArgs& a, int nst, hipStream_t s) {
         b.st_mlo += s0;
         b.st_mhi += s0;
         b.partial = a.partial + (int64_t)s0 * a.n_qtiles;
+        if (a.terms) b.terms = a.terms + (int64_t)s0 * a.nq_mesh * a.nm;
         hipLaunchKernelGGL((stage2_rates_kernel<TQ, TN>), dim3(a.n_qtiles, ns), dim3(256), shm, s,
                            b);
     }
@@ -419,6 +423,61 @@ hipError_t launch_build_states(const int32_t* ids, int nst, int nW, const int32_
     if (nst <= 0) return hipSuccess;
     hipLaunchKernelGGL(build_states_kernel, dim3((nst + 127) / 128), dim3(128), 0, s, ids, nst, nW,
                        kept, eps, bmin, bmax, wmax, cut, st_row, st_band, st_kmesh, st_mlo, st_mhi);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Smearing weights of the rate sum for each state and (q, mode):
+//   D[st, q, nu] = scale sum_{m in [mlo, mhi]} [(n+1-f_m) e^{-(x-w)^2/s^2} + (n+f_m) e^{-(x+w)^2/s^2}],
+// x = eps_nk - eps_{m,k+q}, w = hbar omega_{q nu}; 0 for modes below omega_min.
+// With it the rate term of (q, nu) is |g|^2 x D, so terms / D is a smooth
+// |g|^2 average the learned proposal fits.
+// ---------------------------------------------------------------------------
+__global__ void delta_weights_kernel(int nst, int64_t N, Mesh mesh, const int32_t* st_kmesh,
+                                     const int32_t* st_band, const int32_t* st_mlo,
+                                     const int32_t* st_mhi, const double* eps, const double* focc,
+                                     const double* omega, const double* nb, int nW, int nm,
+                                     double sigma, double omega_min, double scale, double* D) {
+    const int64_t total = (int64_t)nst * N;
+    const double inv_s2 = 1.0 / (sigma * sigma);
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int st = (int)(t / N);
+        const int64_t q = t - (int64_t)st * N;
+        const int km = st_kmesh[st];
+        int k0, k1, k2, q0, q1, q2;
+        mesh_triple(km, mesh, k0, k1, k2);
+        mesh_triple(q, mesh, q0, q1, q2);
+        const int64_t kq =
+            mesh_linear((k0 + q0) % mesh.n0, (k1 + q1) % mesh.n1, (k2 + q2) % mesh.n2, mesh);
+        const double en = eps[(int64_t)km * nW + st_band[st]];
+        double* Dq = D + t * nm;
+        for (int nu = 0; nu < nm; ++nu) {
+            const double w = omega[q * nm + nu];
+            double acc = 0.0;
+            if (w >= omega_min && w > 0.0) {
+                const double n = nb[q * nm + nu];
+                for (int m = st_mlo[st]; m <= st_mhi[st]; ++m) {
+                    const double x = en - eps[kq * nW + m];
+                    const double f = focc[kq * nW + m];
+                    const double y1 = x - w, y2 = x + w;
+                    acc += (n + 1.0 - f) * exp(-y1 * y1 * inv_s2) + (n + f) * exp(-y2 * y2 * inv_s2);
+                }
+            }
+            Dq[nu] = scale * acc;
+        }
+    }
+}
+
+hipError_t launch_delta_weights(int nst, int64_t N, Mesh mesh, const int32_t* st_kmesh,
+                                const int32_t* st_band, const int32_t* st_mlo,
+                                const int32_t* st_mhi, const double* eps, const double* focc,
+                                const double* omega, const double* nb, int nW, int nm, double sigma,
+                                double omega_min, double scale, double* D, hipStream_t s) {
+    if (nst <= 0) return hipSuccess;
+    hipLaunchKernelGGL(delta_weights_kernel, dim3(grid1((int64_t)nst * N, 256)), dim3(256), 0, s,
+                       nst, N, mesh, st_kmesh, st_band, st_mlo, st_mhi, eps, focc, omega, nb, nW,
+                       nm, sigma, omega_min, scale, D);
     return hipGetLastError();
 }
 

@@ -1,0 +1,43 @@
+// Learned-proposal launchers (MLP training/inference, sampler).
+#pragma once
+
+#include "kernels.hpp"
+
+namespace phx {
+
+template <class T>
+hipError_t launch_mlp_gemm(bool ta, bool tb, const T* A, int64_t lda, const T* B, int64_t ldb, T* C,
+                           int64_t ldc, int64_t M, int64_t N, int64_t K, const T* bias, int acc,
+                           hipStream_t s);
+template <class T>
+hipError_t launch_silu_fwd(const T* z, T* a, int64_t n, hipStream_t s);
+template <class T>
+hipError_t launch_silu_bwd(const T* da, const T* z, T* dz, int64_t n, hipStream_t s);
+template <class T>
+hipError_t launch_mse_grad(const T* y, const T* t, T* dy, int64_t B, double* sums, int nblk,
+                           hipStream_t s);
+template <class T>
+hipError_t launch_colsum(const T* dz, int64_t B, int64_t N, T* db, hipStream_t s);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, int t, double lr,
+                       double b1, double b2, double eps, hipStream_t s);
+template <class T>
+hipError_t launch_features(const int32_t* k_idx, const double* eps, const int32_t* q_idx,
+                           const int32_t* nu, int64_t B, Mesh mesh, int nm, double e0,
+                           double escale, T* X, hipStream_t s);
+hipError_t launch_features_grid(int32_t kmesh, double eps, int64_t q0, int64_t nq, Mesh mesh,
+                                int nm, double e0, double escale, float* X, hipStream_t s);
+hipError_t launch_proposal_raw(const float* y, int64_t nq, int nm, double c, double* p,
+                               hipStream_t s);
+hipError_t launch_rowmax(const double* x, int64_t n, double* out, hipStream_t s);
+hipError_t launch_select(const double* D, int64_t n, const double* dmax, double thr, int32_t* list,
+                         int32_t* count, hipStream_t s);
+hipError_t launch_features_list(int32_t kmesh, double eps, const int32_t* list, int64_t n,
+                                Mesh mesh, int nm, double e0, double escale, float* X,
+                                hipStream_t s);
+hipError_t launch_weight_list(const double* D, const int32_t* list, const float* y, int64_t n,
+                              double* E, hipStream_t s);
+hipError_t launch_sum_modes(const double* E, int64_t N, int nm, double* p, hipStream_t s);
+hipError_t launch_sample(double* p, int64_t N, double mix, const double* u, int S, int32_t* q_idx,
+                         double* q_w, hipStream_t s);
+
+}  // namespace phx
