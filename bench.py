@@ -21,6 +21,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "el-ph g(k,q) elements/s + Γ_nk k-pts/s at stated err vs FP64 oracle, 1 GPU"
 PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
 
 
 def log(msg):
@@ -53,6 +54,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--interp-k", type=int, default=2, help="k points of the interp_g rate run")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3", "bf16x6"])
+    ap.add_argument("--mesh-sum", default="auto", choices=["auto", "direct", "factored"],
+                    help="full-mesh sum over Rp: direct contraction or per-axis factorised")
+    ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
+                    help="only copy a GIB-sized buffer 5 times (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -64,6 +69,15 @@ def main():
     import synth
     from paper_2111_14999_amd import DeviceSystem, Library
 
+    if args.copy_calibration > 0:
+        n = int(args.copy_calibration * 2**30) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copied {n * 8} bytes 5 times")
+        return
     if args.workload == "batched":
         return bench_batched(args)
     if args.workload == "learned":
@@ -79,7 +93,8 @@ def main():
     ds = DeviceSystem.from_host(s)
     torch.cuda.synchronize()
     lib = Library(0)
-    nW, nm, n_rp = s.n_wannier, s.n_modes, s.rp.shape[0]
+    lib.set_mesh_sum(args.mesh_sum)
+    nW, nm, n_rp, n_re = s.n_wannier, s.n_modes, s.rp.shape[0], s.re.shape[0]
     gamma = torch.zeros((N, nW), dtype=torch.float64, device="cuda")
     mask = torch.zeros((N, nW), dtype=torch.uint8, device="cuda")
     kept = torch.zeros((N,), dtype=torch.int32, device="cuda")
@@ -102,30 +117,55 @@ def main():
     dt = (time.perf_counter() - t0) / args.steps
     lib.set_timing(False)
     log(f"{args.steps} timed steps, {dt * 1e3:.1f} ms/step")
-    n_st2, ms_st2 = lib.kernel_time("stage2_rates")
-    n_st1, ms_st1 = lib.kernel_time("stage1_phase")
     g = gamma.cpu().numpy()[:n_kept]
     m = mask.cpu().numpy()[:n_kept]
     kidx = kept.cpu().numpy()[:n_kept]
     n_states = int(m.sum())
 
-    # algorithmic FP64 flops of the dominant kernel (the Rp phase sum, 8 flops per
-    # complex multiply-add; rotation and rate terms not counted) per step
-    flops_st2 = 8.0 * n_states * N * n_rp * nm * nW
-    avg_ms = ms_st2 / max(n_st2, 1)
-    launches_per_step = n_st2 / args.steps
-    achieved = flops_st2 / launches_per_step / (avg_ms * 1e-3) / 1e12 if n_st2 else 0.0
+    # Algorithmic work per step of each timed kernel (complex multiply-add = 8 real
+    # flops; rotations and rate terms are not counted):
+    #   stage2_rates    direct sum over the Rp list: 8 N_q n_rp nModes nW per state
+    #   stage1_phase    sum over Re: 8 n_re n_rp nModes nW^2 per kept k
+    #   line_rates      last axis of the factorised sum: 8 N_q W nModes nW per state
+    #   axis_transforms first two axes, HBM traffic: 16 B nModes nW per state x
+    #                   (n_rp read + 2 W^2 N2 for T1 + W N1 N2 for T2)
+    W = 2 * int(np.abs(s.rp).max()) + 1
+    nc = nm * nW
+    work = {
+        "stage2_rates": ("mfma", 8.0 * n_states * N * n_rp * nc),
+        "stage1_phase": ("mfma", 8.0 * n_kept * n_re * n_rp * nm * nW * nW),
+        "line_rates": ("mfma", 8.0 * n_states * N * W * nc),
+        "axis_transforms": ("hbm", 16.0 * nc * n_states *
+                            (n_rp + 2 * W * W * mesh[2] + W * mesh[1] * mesh[2])),
+    }
+    peak_mfma = {"fp64": PEAK_FP64_TFLOPS, "fp32": 157.3, "bf16x3": 2500.0 / 3,
+                 "bf16x6": 2500.0 / 6}[args.precision]
+    kernels = {}
+    for name, (bound, amount) in work.items():
+        n_l, ms = lib.kernel_time(name)
+        if n_l == 0:
+            continue
+        lps = n_l / args.steps
+        avg_ms = ms / n_l
+        per_launch = amount / lps
+        if bound == "mfma":
+            ach, peak, unit = per_launch / (avg_ms * 1e-3) / 1e12, peak_mfma, "TFLOP/s"
+        else:
+            ach, peak, unit = per_launch / (avg_ms * 1e-3) / 1e9, PEAK_HBM_GBS, "GB/s"
+        kernels[name] = dict(bound=bound, achieved=round(ach, 3), peak=round(peak, 2), unit=unit,
+                             frac=round(ach / peak, 4), launches_per_step=lps,
+                             avg_launch_ms=round(avg_ms, 4), ms_per_step=round(ms / args.steps, 3),
+                             work_per_launch=per_launch)
+        log(f"{name}: {n_l} launches, avg {avg_ms:.3f} ms, {ach:.2f} {unit} "
+            f"({ach / peak:.3f} of peak), {ms / args.steps:.1f} ms/step")
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
+    d = kernels[dom]
     # peak of the MFMA the form runs on; split-BF16 executes 3 or 6 BF16 products per
     # real product, so its complex-GEMM flops are measured against BF16 peak / products
-    peak = {"fp64": PEAK_FP64_TFLOPS, "fp32": 157.3, "bf16x3": 2500.0 / 3,
-            "bf16x6": 2500.0 / 6}[args.precision]
-    roofline = dict(bound="mfma", achieved=round(achieved, 3), peak=round(peak, 2),
-                    unit="TFLOP/s", frac=round(achieved / peak, 4), traffic=None,
-                    kernel="stage2_rates", launches_per_step=launches_per_step,
-                    avg_launch_ms=round(avg_ms, 4),
-                    flops_per_launch=flops_st2 / max(launches_per_step, 1))
-    log(f"stage2: {n_st2} launches, avg {avg_ms:.3f} ms, {achieved:.2f} TFLOP/s; "
-        f"stage1: {n_st1} launches, {ms_st1 / max(args.steps, 1):.1f} ms/step")
+    roofline = dict(bound=d["bound"], achieved=d["achieved"], peak=d["peak"], unit=d["unit"],
+                    frac=d["frac"], traffic=None, kernel=dom,
+                    launches_per_step=d["launches_per_step"], avg_launch_ms=d["avg_launch_ms"],
+                    work_per_launch=d["work_per_launch"])
 
     # interp_g element rate (all (nu, n, m) of nk kept k x the full q mesh)
     gel = None
@@ -195,6 +235,8 @@ def main():
         "g_elements_per_s": gel,
         "err_vs_oracle": err,
         "roofline": roofline,
+        "kernels": kernels,
+        "mesh_sum": args.mesh_sum,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

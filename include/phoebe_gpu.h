@@ -318,11 +318,30 @@ phoebe_status phoebe_gpu_propose_q(void *handle, const int32_t mesh[3], int32_t 
                                    double mix, int32_t S, const double *uniforms, int64_t *q_off,
                                    int32_t *q_idx, double *q_w, void *stream);
 
+/* How phoebe_gpu_scatter_rates (and rate_terms) evaluate the sum over Rp on a
+ * full q mesh in FP64.  DIRECT: one MFMA contraction over the Rp list per q
+ * tile, as for q lists.  FACTORED: the phase e^{i2pi q.Rp} is a product of
+ * three per-axis factors on a full mesh, so the sum is taken one axis at a
+ * time over the box [-rmax, rmax]^3 holding the Rp list (zero where the list
+ * has no vector); the result is the same sum up to the order of additions.
+ * Needs FP64, the full q mesh, |Rp components| <= 15 and nModes*nW <= 512.
+ * AUTO (the default) takes FACTORED where it applies and the box width is at
+ * most half the number of Rp vectors.  Lists of q, the reduced precisions and
+ * the batched form always use DIRECT.  Returns PHOEBE_E_INVALID for an
+ * unknown mode; scatter_rates returns PHOEBE_E_UNSUPPORTED when FACTORED is
+ * forced where it does not apply. */
+typedef enum {
+    PHOEBE_MESH_SUM_AUTO = 0,
+    PHOEBE_MESH_SUM_DIRECT = 1,
+    PHOEBE_MESH_SUM_FACTORED = 2
+} phoebe_mesh_sum;
+phoebe_status phoebe_gpu_set_mesh_sum(void *handle, int32_t mode);
+
 /* Kernel timing for measurement: when enabled, the named hot kernels are
  * bracketed by HIP events on the stream they run on; phoebe_gpu_kernel_time
  * returns the number of timed launches and their summed duration since the
- * last reset.  Names: "stage2_rates", "stage1_phase", "bands_fft",
- * "eig_jacobi".  Timing synchronises the stream at the end of each call. */
+ * last reset.  Names: "stage2_rates" (direct sum), "stage1_phase",
+ * "axis_transforms" and "line_rates" (factorised sum), "bands_fft", "eig_jacobi".  Timing synchronises the stream at the end of each call. */
 phoebe_status phoebe_gpu_set_timing(void *handle, int enable);
 phoebe_status phoebe_gpu_kernel_time(void *handle, const char *name,
                                      int64_t *launches, double *total_ms);

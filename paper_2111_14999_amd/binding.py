@@ -35,6 +35,7 @@ EXPORTS = (
     "phoebe_gpu_batched_destroy", "phoebe_gpu_rate_terms", "phoebe_gpu_mlp_param_count",
     "phoebe_gpu_mlp_forward", "phoebe_gpu_mlp_grad", "phoebe_gpu_mlp_adam",
     "phoebe_gpu_mlp_features", "phoebe_gpu_propose_q", "phoebe_gpu_delta_weights",
+    "phoebe_gpu_set_mesh_sum",
 )
 
 
@@ -88,6 +89,7 @@ def load(path: str = LIB_PATH):
                                              ctypes.POINTER(CRateParams), ctypes.c_int,
                                              vp, vp, vp, ctypes.POINTER(i64), vp]
     lib.phoebe_gpu_set_timing.argtypes = [vp, ctypes.c_int]
+    lib.phoebe_gpu_set_mesh_sum.argtypes = [vp, i32]
     lib.phoebe_gpu_reset_timing.argtypes = [vp]
     lib.phoebe_gpu_kernel_time.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(i64),
                                            ctypes.POINTER(ctypes.c_double)]
@@ -341,6 +343,12 @@ class Library:
         return BatchedPlan(self, plan, [int(x) for x in kept], systems)
 
     # -- timing -------------------------------------------------------------
+    MESH_SUM = {"auto": 0, "direct": 1, "factored": 2}
+
+    def set_mesh_sum(self, mode: str):
+        """How full-mesh FP64 rate sums run over Rp: "auto", "direct" or "factored"."""
+        self._check(self.lib.phoebe_gpu_set_mesh_sum(self.handle, self.MESH_SUM[mode]))
+
     def set_timing(self, on: bool):
         self._check(self.lib.phoebe_gpu_set_timing(self.handle, 1 if on else 0))
 

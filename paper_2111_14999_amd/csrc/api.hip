@@ -73,6 +73,17 @@ const char* phoebe_gpu_last_error(void* handle) {
     return static_cast<Handle*>(handle)->err.c_str();
 }
 
+phoebe_status phoebe_gpu_set_mesh_sum(void* handle, int32_t mode) {
+    if (!handle) return PHOEBE_E_INVALID;
+    Handle* h = static_cast<Handle*>(handle);
+    if (mode < PHOEBE_MESH_SUM_AUTO || mode > PHOEBE_MESH_SUM_FACTORED) {
+        h->err = "mesh-sum mode out of range";
+        return PHOEBE_E_INVALID;
+    }
+    h->mesh_sum = mode;
+    return PHOEBE_OK;
+}
+
 phoebe_status phoebe_gpu_set_timing(void* handle, int enable) {
     if (!handle) return PHOEBE_E_INVALID;
     static_cast<Handle*>(handle)->timing = enable != 0;
@@ -349,6 +360,26 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                            (double)BK * nW * rp_pad * nc_pad * f_elem > 8e9))
             BK /= 2;
         const int BQ = 16 * tq;
+        // Full-mesh FP64 sums may take the per-axis factorised form (see
+        // launch_axis_transforms / launch_line_rates).
+        const int Wbox = 2 * rmax_p + 1;
+        const bool can_factor = prec == PHOEBE_FP64 && q_off == nullptr && Wbox <= 32 &&
+                                (nc_pad / 64 <= 4 || nc_pad / 64 == 6 || nc_pad / 64 == 8) &&
+                                line_rates_lds(Wbox, mesh.n0, nc_pad, nm) <= 159 * 1024;
+        if (h->mesh_sum == PHOEBE_MESH_SUM_FACTORED && !can_factor) {
+            set_err(h, "the factorised mesh sum needs FP64, the full q mesh, |Rp| <= 15 and "
+                       "nModes*nW <= 512");
+            throw Fail{PHOEBE_E_UNSUPPORTED};
+        }
+        const bool factored = can_factor && (h->mesh_sum == PHOEBE_MESH_SUM_FACTORED ||
+                                             (h->mesh_sum == PHOEBE_MESH_SUM_AUTO &&
+                                              2 * Wbox <= n_rp));
+        // states per factorised sub-batch: T1 + T2 of a sub-batch stay under 4 GB
+        const int64_t NL = (int64_t)mesh.n1 * mesh.n2;
+        const size_t t12_state = ((size_t)Wbox * Wbox * mesh.n2 + (size_t)Wbox * NL) * nc_pad * sizeof(cd);
+        const int nsb = factored ? (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)BK * nW,
+                                                      (int64_t)(4e9 / (double)t12_state)))
+                                 : 0;
 
         // q-list lengths (host) for the tile count
         int64_t max_list = N;
@@ -375,7 +406,7 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                             (long long)i, qh[i]);
             }
         }
-        const int n_qtiles = (int)std::max<int64_t>(1, (max_list + BQ - 1) / BQ);
+        const int n_qtiles = factored ? (int)NL : (int)std::max<int64_t>(1, (max_list + BQ - 1) / BQ);
 
         // ---- phase A: tables, window, states (sized for the whole mesh) ----
         struct Tables {
@@ -385,6 +416,8 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
             uint8_t* mask;
             int32_t *flag, *kept, *cnt, *rowflag, *ids;
             int32_t *st_row, *st_band, *st_kmesh, *st_mlo, *st_mhi;
+            int32_t* box_rp;
+            cd* Pax;
         } T{};
         const int64_t rows_cap = k_idx ? nk : N;
         auto plan_tables = [&](Arena& ar) {
@@ -413,6 +446,10 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
             T.st_kmesh = ar.take<int32_t>((size_t)rows_cap * nW);
             T.st_mlo = ar.take<int32_t>((size_t)rows_cap * nW);
             T.st_mhi = ar.take<int32_t>((size_t)rows_cap * nW);
+            if (factored) {
+                T.box_rp = ar.take<int32_t>((size_t)Wbox * Wbox * Wbox);
+                T.Pax = ar.take<cd>((size_t)(mesh.n0 + mesh.n1 + mesh.n2) * Wbox);
+            }
         };
         // band scratch is carved after the tables and reused by the batches
         size_t tables_end = 0, scratch_bands = 0;
@@ -431,7 +468,8 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
         const size_t batch_bytes = 4 * 256 + (size_t)BK * n_re * sizeof(cd) +
                                    (size_t)BK * NC2 * g_elem +
                                    (size_t)max_states * rp_pad * nc_pad * f_elem +
-                                   (size_t)max_states * n_qtiles * sizeof(double);
+                                   (size_t)max_states * n_qtiles * sizeof(double) +
+                                   (factored ? (size_t)nsb * t12_state + 512 : 0);
         ensure_ws(h, tables_end + std::max(scratch_bands, batch_bytes) + 256);
         Arena ar(h->ws);
         plan_tables(ar);
@@ -442,6 +480,21 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                             ((sys->rp[3 * i + 2] + rmax_p) << 16);
             HIPCHK(h, hipMemcpyAsync(T.rp_packed, packed.data(), sizeof(int32_t) * n_rp,
                                      hipMemcpyHostToDevice, s));
+            std::vector<int32_t> box;
+            if (factored) {
+                // box position ((R0+r) W + R1+r) W + R2+r -> row of F (-1: no such Rp)
+                box.assign((size_t)Wbox * Wbox * Wbox, -1);
+                for (int i = 0; i < n_rp; ++i) {
+                    const int64_t b = ((int64_t)(sys->rp[3 * i] + rmax_p) * Wbox +
+                                       (sys->rp[3 * i + 1] + rmax_p)) * Wbox +
+                                      (sys->rp[3 * i + 2] + rmax_p);
+                    REQUIRE(h, box[b] < 0, "Rp list holds a vector twice");
+                    box[b] = i;
+                }
+                HIPCHK(h, hipMemcpyAsync(T.box_rp, box.data(), sizeof(int32_t) * box.size(),
+                                         hipMemcpyHostToDevice, s));
+                HIPCHK(h, launch_axis_phases(mesh, rmax_p, T.Pax, s));
+            }
             // the host vector must outlive the copy
             HIPCHK(h, hipStreamSynchronize(s));
         }
@@ -515,6 +568,8 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
         char* Gbuf = ar.take<char>((size_t)BK * NC2 * g_elem);
         char* Fbuf = ar.take<char>((size_t)max_states * rp_pad * nc_pad * f_elem);
         double* partial = ar.take<double>((size_t)max_states * n_qtiles);
+        cd* T1buf = factored ? ar.take<cd>((size_t)nsb * Wbox * Wbox * mesh.n2 * nc_pad) : nullptr;
+        cd* T2buf = factored ? ar.take<cd>((size_t)nsb * Wbox * NL * nc_pad) : nullptr;
 
         const double inv_sqrtpi_sigma = 1.0 / (std::sqrt(kPi) * par->sigma);
         const double scale = 2.0 * kPi * inv_sqrtpi_sigma * (q_off ? 1.0 : 1.0 / (double)N);
@@ -573,8 +628,8 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
             ra.n_qtiles = n_qtiles;
             ra.terms = terms ? terms + (int64_t)sbeg * N * nm : nullptr;
             ra.terms_scale = 2.0 * kPi * inv_sqrtpi_sigma;
-            Timer t2(h, s, "stage2_rates");
             if (lowp) {
+                Timer t2(h, s, "stage2_rates");
                 RateArgsLP rl{};
                 rl.F = Fbuf;
                 rl.rp_pad = ra.rp_pad; rl.nc_pad = ra.nc_pad; rl.n_rp = ra.n_rp;
@@ -586,10 +641,35 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                 rl.nW = nW; rl.nm = nm; rl.sigma = ra.sigma; rl.partial = partial;
                 rl.n_qtiles = n_qtiles;
                 HIPCHK(h, launch_stage2_rates_lp(prec, rl, ns, s));
-            } else {
+                t2.done();
+            } else if (!factored) {
+                Timer t2(h, s, "stage2_rates");
                 HIPCHK(h, launch_stage2_rates(ra, ns, s));
+                t2.done();
+            } else {
+                ra.P0 = T.Pax;
+                ra.W = Wbox;
+                for (int sb = 0; sb < ns; sb += nsb) {
+                    const int nn = std::min(nsb, ns - sb);
+                    Timer ta(h, s, "axis_transforms");
+                    HIPCHK(h, launch_axis_transforms(
+                                  reinterpret_cast<const cd*>(Fbuf) + (int64_t)sb * rp_pad * nc_pad,
+                                  rp_pad, nc_pad, T.box_rp, rmax_p, mesh, T.Pax, nn, T1buf, T2buf, s));
+                    ta.done();
+                    RateArgs rb = ra;
+                    rb.T2 = T2buf;
+                    rb.st_kmesh += sb;
+                    rb.st_band += sb;
+                    rb.st_row += sb;
+                    rb.st_mlo += sb;
+                    rb.st_mhi += sb;
+                    rb.partial = partial + (int64_t)sb * n_qtiles;
+                    if (ra.terms) rb.terms = ra.terms + (int64_t)sb * N * nm;
+                    Timer tl(h, s, "line_rates");
+                    HIPCHK(h, launch_line_rates(rb, nn, s));
+                    tl.done();
+                }
             }
-            t2.done();
             HIPCHK(h, launch_reduce_partials(partial, ns, n_qtiles, T.st_row + sbeg,
                                              T.st_band + sbeg, nW, scale, gamma_out, s));
             sbeg = send;

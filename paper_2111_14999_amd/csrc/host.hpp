@@ -38,6 +38,7 @@ struct Handle {
     size_t ws_cap = 0;
     std::string err;
     bool timing = false;
+    int mesh_sum = 0;  // PHOEBE_MESH_SUM_AUTO / _DIRECT / _FACTORED
     std::vector<TimedLaunch> pending;
     std::vector<KernelStat> stats;
 };

@@ -83,10 +83,24 @@ struct RateArgs {
     int n_qtiles;
     double* terms;             // nullable [nst, nq_mesh, nm]: per-(q, mode) terms, summed over m
     double terms_scale;        // factor applied to each stored term
+    // factorised full-mesh form: X[q] = sum_R0 P0[q0, R0] T2[R0, q1 N2 + q2]
+    const cd* T2;              // [nst, W, N1*N2, nc_pad]
+    const cd* P0;              // [N0, W]
+    int W;                     // 2 rmax + 1
 };
 
 // Fused stage 2 (sum over Rp on MFMA) + rotations + rate terms.
 hipError_t launch_stage2_rates(const RateArgs& a, int nst, hipStream_t s);
+
+// Per-axis phase tables P[d][n, r] = e^{i2pi (n (r - rmax) mod N_d)/N_d}, [N0+N1+N2, W].
+hipError_t launch_axis_phases(Mesh m, int rmax, cd* P, hipStream_t s);
+// T1 (axis 2) and T2 (axis 1) of the factorised full-mesh sum over Rp.
+hipError_t launch_axis_transforms(const cd* F, int rp_pad, int nc_pad, const int32_t* box_rp,
+                                  int rmax, Mesh m, const cd* P, int nst, cd* T1, cd* T2,
+                                  hipStream_t s);
+// Axis 0 on MFMA + rotations + rate terms, one work-group per (state, q1, q2) line.
+hipError_t launch_line_rates(const RateArgs& a, int nst, hipStream_t s);
+size_t line_rates_lds(int W, int N0, int nc_pad, int nm);
 
 // gamma[row, band] = scale * sum_t partial[st, t]
 hipError_t launch_reduce_partials(const double* partial, int nst, int ntiles,

@@ -98,17 +98,22 @@ __global__ __launch_bounds__(256) void zgemm_kernel(const cd* __restrict__ A, in
     for (int k0 = 0; k0 < K; k0 += 4) {
         cd a_nxt[TM], b_nxt[TN];
         if (k0 + 4 < K) load(k0 + 4, a_nxt, b_nxt);
+        // two passes over the tiles, so that dependent MFMAs on one accumulator
+        // are 2 TM TN - 1 instructions apart
 #pragma unroll
-        for (int i = 0; i < TM; ++i) {
-            const double ar = a_cur[i].x, ai = a_cur[i].y, nai = -a_cur[i].y;
+        for (int i = 0; i < TM; ++i)
 #pragma unroll
             for (int j = 0; j < TN; ++j) {
-                cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, b_cur[j].x, cr[i][j], 0, 0, 0);
-                cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai, b_cur[j].y, cr[i][j], 0, 0, 0);
-                ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, b_cur[j].y, ci[i][j], 0, 0, 0);
-                ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, b_cur[j].x, ci[i][j], 0, 0, 0);
+                cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur[i].x, b_cur[j].x, cr[i][j], 0, 0, 0);
+                ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur[i].x, b_cur[j].y, ci[i][j], 0, 0, 0);
             }
-        }
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a_cur[i].y, b_cur[j].y, cr[i][j], 0, 0, 0);
+                ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur[i].y, b_cur[j].x, ci[i][j], 0, 0, 0);
+            }
         if (k0 + 4 < K) {
 #pragma unroll
             for (int i = 0; i < TM; ++i) a_cur[i] = a_nxt[i];

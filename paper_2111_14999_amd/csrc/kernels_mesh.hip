@@ -1,0 +1,318 @@
+// Stage 2 on a full q mesh, factorised over the three axes.
+//
+// On a full mesh the phase of (q, Rp) is the product of three per-axis
+// factors, e^{i2pi q.Rp} = P0[q0, R0] P1[q1, R1] P2[q2, R2] with
+// Pd[n, r] = e^{i2pi (n r mod N_d) / N_d}, so the sum over Rp of the fixed-k
+// precomputation F(k, Rp) splits into three one-axis transforms
+// (Electron Properties, interpolation of g; the Kokkos-section precompute at
+// fixed k).  Rp is embedded in the box [-rmax, rmax]^3 (W = 2 rmax + 1 per
+// axis) with zeros where the list has no vector:
+//   T1[R0, R1, q2, c] = sum_R2 P2[q2, R2] F[R0, R1, R2, c]
+//   T2[R0, q1, q2, c] = sum_R1 P1[q1, R1] T1[R0, R1, q2, c]
+//   X [q0, q1, q2, c] = sum_R0 P0[q0, R0] T2[R0, q1, q2, c]
+// The last transform runs on MFMA inside the rate kernel, one work-group per
+// (state, q1, q2) line of N0 points, followed by the same rotations and
+// smeared rate terms as the direct kernel; X never reaches memory.  The sum
+// is the same as the direct one up to the order of the additions.
+#include "kernels.hpp"
+
+namespace phx {
+
+static inline int gridm(int64_t n, int block) {
+    int64_t g = (n + block - 1) / block;
+    if (g > 65535 * 16) g = 65535 * 16;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+// P[d][n, r] for the three axes, stored one after another ([N0 + N1 + N2, W])
+__global__ void axis_phase_kernel(Mesh m, int rmax, cd* P) {
+    const int W = 2 * rmax + 1;
+    const int total = (m.n0 + m.n1 + m.n2) * W;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += gridDim.x * blockDim.x) {
+        const int row = t / W;
+        const int r = t - row * W - rmax;
+        int n = row, N = m.n0;
+        if (n >= m.n0) {
+            n -= m.n0;
+            N = m.n1;
+            if (n >= m.n1) {
+                n -= m.n1;
+                N = m.n2;
+            }
+        }
+        int a = (int)(((int64_t)n * r) % N);
+        if (a < 0) a += N;
+        P[t] = expi2pi((double)a / N);
+    }
+}
+
+hipError_t launch_axis_phases(Mesh m, int rmax, cd* P, hipStream_t s) {
+    const int W = 2 * rmax + 1;
+    hipLaunchKernelGGL(axis_phase_kernel, dim3(gridm((int64_t)(m.n0 + m.n1 + m.n2) * W, 256)),
+                       dim3(256), 0, s, m, rmax, P);
+    return hipGetLastError();
+}
+
+constexpr int kMaxW = 32;
+
+// T1[st, p, q2, c] = sum_r P2[q2, r] F[st, box_rp[p W + r], c]   (p = (R0, R1))
+// box_rp maps a box position to its row of F, or -1 where the list has no Rp.
+__global__ __launch_bounds__(256) void axis2_kernel(const cd* __restrict__ F, int rp_pad,
+                                                    int nc_pad, const int32_t* __restrict__ box_rp,
+                                                    int W, int N2, const cd* __restrict__ P2,
+                                                    int nst, cd* __restrict__ T1) {
+    const int64_t total = (int64_t)nst * W * W * nc_pad;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(t % nc_pad);
+        const int64_t sp = t / nc_pad;  // st * W^2 + p
+        const int p = (int)(sp % (W * W));
+        const int st = (int)(sp / (W * W));
+        cd v[kMaxW];
+        for (int r = 0; r < W; ++r) {
+            const int row = box_rp[p * W + r];
+            v[r] = row >= 0 ? F[((int64_t)st * rp_pad + row) * nc_pad + c] : cd{0.0, 0.0};
+        }
+        cd* out = T1 + sp * N2 * nc_pad + c;
+        for (int q = 0; q < N2; ++q) {
+            const cd* Pq = P2 + q * W;
+            cd acc = {0.0, 0.0};
+            for (int r = 0; r < W; ++r) acc = cfma(Pq[r], v[r], acc);
+            out[(int64_t)q * nc_pad] = acc;
+        }
+    }
+}
+
+// out[o, n, i] = sum_r P[n, r] in[o, r, i]   (i < inner, contiguous)
+__global__ __launch_bounds__(256) void axis_mid_kernel(const cd* __restrict__ in, int64_t n_outer,
+                                                       int W, int64_t inner, int N,
+                                                       const cd* __restrict__ P,
+                                                       cd* __restrict__ out) {
+    const int64_t total = n_outer * inner;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = t % inner;
+        const int64_t o = t / inner;
+        cd v[kMaxW];
+        const cd* src = in + o * W * inner + i;
+        for (int r = 0; r < W; ++r) v[r] = src[(int64_t)r * inner];
+        cd* dst = out + o * N * inner + i;
+        for (int n = 0; n < N; ++n) {
+            const cd* Pn = P + n * W;
+            cd acc = {0.0, 0.0};
+            for (int r = 0; r < W; ++r) acc = cfma(Pn[r], v[r], acc);
+            dst[(int64_t)n * inner] = acc;
+        }
+    }
+}
+
+hipError_t launch_axis_transforms(const cd* F, int rp_pad, int nc_pad, const int32_t* box_rp,
+                                  int rmax, Mesh m, const cd* P, int nst, cd* T1, cd* T2,
+                                  hipStream_t s) {
+    const int W = 2 * rmax + 1;
+    if (W > kMaxW) return hipErrorInvalidValue;
+    if (nst <= 0) return hipSuccess;
+    const cd* P1 = P + (int64_t)m.n0 * W;
+    const cd* P2 = P1 + (int64_t)m.n1 * W;
+    hipLaunchKernelGGL(axis2_kernel, dim3(gridm((int64_t)nst * W * W * nc_pad, 256)), dim3(256), 0,
+                       s, F, rp_pad, nc_pad, box_rp, W, m.n2, P2, nst, T1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t inner = (int64_t)m.n2 * nc_pad;
+    hipLaunchKernelGGL(axis_mid_kernel, dim3(gridm((int64_t)nst * W * inner, 256)), dim3(256), 0, s,
+                       T1, (int64_t)nst * W, W, inner, m.n1, P1, T2);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Last axis on MFMA + rotations + rate terms.  Work-group = one state x one
+// (q1, q2) line; the N0 points of the line are taken 16 at a time.  Lane l
+// holds A[l%16][l/16] = P0[q0, R0] and B[l/16][l%16] = T2[R0, line, col];
+// result v of lane l is row l/16 + 4v (f64 16x16x4 layout), so after a
+// chunk every row 0..15 of X is in LDS and the rotation runs once over it.
+// ---------------------------------------------------------------------------
+constexpr int kMBL = 2;  // final bands per rotation pass
+
+template <int TN>
+__global__ __launch_bounds__(256, 2) void line_rates_kernel(RateArgs a) {
+    extern __shared__ char smem_raw[];
+    const int W = a.W;
+    const int Wp = (W + 3) & ~3;
+    const int nW = a.nW, nm = a.nm;
+    const Mesh mesh = a.mesh;
+    const int N0 = mesh.n0;
+    const int N0p = (N0 + 15) & ~15;
+    const int ldf = a.nc_pad;
+    cd* sP = reinterpret_cast<cd*>(smem_raw);     // [N0p][Wp]
+    cd* sX = sP + N0p * Wp;                       // [16][nc_pad]
+    cd* sY = sX + 16 * ldf;                       // [16][kMBL][nm]
+    __shared__ double sRed[4];
+    __shared__ int sKq[16];
+    __shared__ int sQ[16];
+
+    const int st = blockIdx.y;
+    const int line = blockIdx.x;
+    const int NL = mesh.n1 * mesh.n2;
+    const int q1 = line / mesh.n2, q2 = line - q1 * mesh.n2;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+
+    for (int i = tid; i < N0p * Wp; i += 256) {
+        const int q0 = i / Wp, r = i - q0 * Wp;
+        sP[i] = (q0 < N0 && r < W) ? a.P0[q0 * W + r] : cd{0.0, 0.0};
+    }
+
+    const int kmesh = a.st_kmesh[st];
+    const int nband = a.st_band[st];
+    const int mlo = a.st_mlo[st], mhi = a.st_mhi[st];
+    int k0i, k1i, k2i;
+    mesh_triple(kmesh, mesh, k0i, k1i, k2i);
+    const double eps_n = a.eps[(int64_t)kmesh * nW + nband];
+    const double inv_s2 = 1.0 / (a.sigma * a.sigma);
+    const int colbase = wave * TN * 16 + li;
+    const cd* Tst = a.T2 + (int64_t)st * W * NL * ldf + (int64_t)line * ldf + colbase;
+    double gacc = 0.0;
+
+    for (int qc = 0; qc < N0; qc += 16) {
+        d4 cr[TN], ci[TN];
+#pragma unroll
+        for (int t = 0; t < TN; ++t) {
+            cr[t] = d4{0, 0, 0, 0};
+            ci[t] = d4{0, 0, 0, 0};
+        }
+        __syncthreads();  // sP ready; the previous chunk is done with sX and sY
+        for (int k0 = 0; k0 < Wp; k0 += 4) {
+            const int k = k0 + lg;
+            cd bc[TN];
+            if (k < W) {
+                const cd* Tr = Tst + (int64_t)k * NL * ldf;
+#pragma unroll
+                for (int t = 0; t < TN; ++t) bc[t] = Tr[t * 16];
+            } else {
+#pragma unroll
+                for (int t = 0; t < TN; ++t) bc[t] = cd{0.0, 0.0};
+            }
+            const cd ph = sP[(qc + li) * Wp + k];
+#pragma unroll
+            for (int t = 0; t < TN; ++t) {
+                cr[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ph.x, bc[t].x, cr[t], 0, 0, 0);
+                ci[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ph.x, bc[t].y, ci[t], 0, 0, 0);
+            }
+#pragma unroll
+            for (int t = 0; t < TN; ++t) {
+                cr[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ph.y, bc[t].y, cr[t], 0, 0, 0);
+                ci[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ph.y, bc[t].x, ci[t], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int t = 0; t < TN; ++t)
+                sX[(lg + 4 * v) * ldf + colbase + t * 16] = cd{cr[t][v], ci[t][v]};
+        if (tid < 16) {
+            const int q0 = qc + tid;
+            int kq = -1, q = 0;
+            if (q0 < N0) {
+                q = (int)mesh_linear(q0, q1, q2, mesh);
+                kq = (int)mesh_linear((k0i + q0) % mesh.n0, (k1i + q1) % mesh.n1,
+                                      (k2i + q2) % mesh.n2, mesh);
+            }
+            sKq[tid] = kq;
+            sQ[tid] = q;
+        }
+        __syncthreads();
+        for (int m0 = mlo; m0 <= mhi; m0 += kMBL) {
+            const int nmb = min(kMBL, mhi - m0 + 1);
+            // Y[c, mb, sa] = sum_b X[c, sa*nW + b] U_{k+q}[b, m0 + mb]
+            for (int it = tid; it < 16 * nmb * nm; it += 256) {
+                const int c = it / (nmb * nm);
+                const int r = it - c * nmb * nm;
+                const int mb = r / nm, sa = r - mb * nm;
+                const int kq = sKq[c];
+                cd y = {0.0, 0.0};
+                if (kq >= 0) {
+                    const cd* Xr = sX + c * ldf + sa * nW;
+                    const cd* Uc = a.U + (int64_t)kq * nW * nW + m0 + mb;
+                    for (int b = 0; b < nW; ++b) y = cfma(Xr[b], Uc[(int64_t)b * nW], y);
+                }
+                sY[(c * kMBL + mb) * nm + sa] = y;
+            }
+            __syncthreads();
+            // Z[c, mb, nu] = sum_sa E_q[sa, nu] Y[c, mb, sa]; rate terms
+            for (int it = tid; it < 16 * nmb * nm; it += 256) {
+                const int c = it / (nmb * nm);
+                const int r = it - c * nmb * nm;
+                const int mb = r / nm, nu = r - mb * nm;
+                const int kq = sKq[c];
+                if (kq < 0) continue;
+                const int64_t q = sQ[c];
+                const cd* Yr = sY + (c * kMBL + mb) * nm;
+                const cd* Eq = a.E + q * nm * nm + nu;
+                cd z = {0.0, 0.0};
+                for (int sa = 0; sa < nm; ++sa) z = cfma(Eq[sa * nm], Yr[sa], z);
+                const int m = m0 + mb;
+                const double x = eps_n - a.eps[(int64_t)kq * nW + m];
+                const double fm = a.focc[(int64_t)kq * nW + m];
+                const double w = a.omega[q * nm + nu], nbq = a.nb[q * nm + nu];
+                const double y1 = x - w, y2 = x + w;
+                const double g1 = exp(-y1 * y1 * inv_s2), g2 = exp(-y2 * y2 * inv_s2);
+                const double term = cabs2(z) * ((nbq + 1.0 - fm) * g1 + (nbq + fm) * g2);
+                gacc += term;
+                if (a.terms)
+                    atomicAdd(&a.terms[((int64_t)st * a.nq_mesh + q) * nm + nu], a.terms_scale * term);
+            }
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) gacc += __shfl_xor(gacc, o, 64);
+    if (lane == 0) sRed[wave] = gacc;
+    __syncthreads();
+    if (tid == 0) a.partial[(int64_t)st * a.n_qtiles + line] = (sRed[0] + sRed[1]) + (sRed[2] + sRed[3]);
+}
+
+size_t line_rates_lds(int W, int N0, int nc_pad, int nm) {
+    const int Wp = (W + 3) & ~3, N0p = (N0 + 15) & ~15;
+    return ((size_t)N0p * Wp + 16 * (size_t)nc_pad + 16 * (size_t)kMBL * nm) * sizeof(cd);
+}
+
+template <int TN>
+static hipError_t go_line(const RateArgs& a, int nst, hipStream_t s) {
+    const size_t shm = line_rates_lds(a.W, a.mesh.n0, a.nc_pad, a.nm);
+    if (shm > 160 * 1024 - 1024) return hipErrorInvalidValue;
+    hipError_t e = hipFuncSetAttribute((const void*)line_rates_kernel<TN>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+    const int64_t NL = (int64_t)a.mesh.n1 * a.mesh.n2;
+    for (int s0 = 0; s0 < nst; s0 += 65535) {
+        const int ns = nst - s0 < 65535 ? nst - s0 : 65535;
+        RateArgs b = a;
+        b.T2 = a.T2 + (int64_t)s0 * a.W * NL * a.nc_pad;
+        b.st_kmesh += s0;
+        b.st_band += s0;
+        b.st_row += s0;
+        b.st_mlo += s0;
+        b.st_mhi += s0;
+        b.partial = a.partial + (int64_t)s0 * a.n_qtiles;
+        if (a.terms) b.terms = a.terms + (int64_t)s0 * a.nq_mesh * a.nm;
+        hipLaunchKernelGGL((line_rates_kernel<TN>), dim3((unsigned)NL, ns), dim3(256), shm, s, b);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_line_rates(const RateArgs& a, int nst, hipStream_t s) {
+    if (nst <= 0) return hipSuccess;
+    if (a.n_qtiles != a.mesh.n1 * a.mesh.n2 || a.W > kMaxW) return hipErrorInvalidValue;
+    switch (a.nc_pad / 64) {
+        case 1: return go_line<1>(a, nst, s);
+        case 2: return go_line<2>(a, nst, s);
+        case 3: return go_line<3>(a, nst, s);
+        case 4: return go_line<4>(a, nst, s);
+        case 6: return go_line<6>(a, nst, s);
+        case 8: return go_line<8>(a, nst, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace phx

@@ -149,3 +149,64 @@ def test_argument_errors(lib, toy):
                                           ctypes.byref(p), 7, gamma.data_ptr(), None, None, None,
                                           None)
     assert st == -1
+
+
+# ---------------------------------------------------------------------------
+# full-mesh sum over Rp: direct contraction vs the per-axis factorised form
+# ---------------------------------------------------------------------------
+
+def _sparse_rp(s, seed, keep_frac):
+    """The same system with a random subset of its Rp vectors (not a full box)."""
+    rng = np.random.default_rng(seed)
+    keep = np.sort(rng.choice(len(s.rp), size=max(1, int(keep_frac * len(s.rp))), replace=False))
+    s.rp = np.ascontiguousarray(s.rp[keep])
+    s.g_rr = np.ascontiguousarray(s.g_rr[:, keep])
+    return s
+
+
+@pytest.mark.parametrize("case", ["toy", "ragged-5x6x7", "sparse-rp", "c2-tiling", "single-line"])
+def test_mesh_sum_forms_match_oracle(lib, toy, case):
+    if case == "toy":
+        s, mesh, par, ref = toy
+    else:
+        if case == "ragged-5x6x7":
+            s, mesh = synth.small_system(71, n_wannier=5, n_atoms=2, r=2), (5, 6, 7)
+        elif case == "sparse-rp":
+            s, mesh = _sparse_rp(synth.small_system(72, n_wannier=4, n_atoms=2, r=2), 5, 0.4), (6, 4, 5)
+        elif case == "c2-tiling":
+            s, mesh = synth.small_system(73, n_wannier=16, n_atoms=5, r=1), (17, 3, 2)
+        else:
+            s, mesh = synth.small_system(74, n_wannier=3, n_atoms=1, r=2), (33, 1, 1)
+        s.h_r *= 0.3
+        t = rates.mesh_tables(s, mesh)
+        mu = float(np.median(t["eps"]))
+        par = dict(mu=mu, kT=constants.kT_of(300.0), sigma=0.05, win_lo=mu - 0.8,
+                   win_hi=mu + 0.8, omega_min=1e-4)
+        ref = rates.scattering_rates(s, mesh, tables=t, **par)
+    out = {}
+    try:
+        for mode in ("direct", "factored"):
+            lib.set_mesh_sum(mode)
+            out[mode] = _gpu_rates(lib, s, mesh, par)
+            _check(*out[mode], ref)
+    finally:
+        lib.set_mesh_sum("auto")
+    gd, gf = out["direct"][1], out["factored"][1]
+    scale = max(np.max(np.abs(gd)), 1e-300)
+    assert np.max(np.abs(gd - gf)) < 1e-12 * scale
+
+
+def test_mesh_sum_mode_errors(lib, toy):
+    from paper_2111_14999_amd import PhoebeError
+    s, mesh, par, _ = toy
+    assert lib.lib.phoebe_gpu_set_mesh_sum(lib.handle, 3) == -1
+    assert lib.lib.phoebe_gpu_set_mesh_sum(lib.handle, -1) == -1
+    # the factorised form needs the full q mesh
+    lib.set_mesh_sum("factored")
+    try:
+        with pytest.raises(PhoebeError) as e:
+            _gpu_rates(lib, s, mesh, par, k_idx=[1, 2],
+                       q_lists=(np.array([0, 3, 5]), np.array([0, 1, 2, 3, 4]), np.ones(5)))
+        assert e.value.status == -4
+    finally:
+        lib.set_mesh_sum("auto")
