@@ -54,6 +54,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--interp-k", type=int, default=2, help="k points of the interp_g rate run")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3", "bf16x6"])
+    ap.add_argument("--n-harm", type=int, default=0,
+                    help="learned form: 0 = raw crystal coordinates as network inputs, H > 0 = "
+                         "cos/sin harmonics 1..H of k and q")
     ap.add_argument("--mesh-sum", default="auto", choices=["auto", "direct", "factored"],
                     help="full-mesh sum over Rp: direct contraction or per-axis factorised")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
@@ -400,11 +403,11 @@ def bench_learned(args):
     ek = torch.zeros((n_train, nW), dtype=torch.float64, device="cuda")
     lib.electron_bands(ds, kf, ek, None)
     ee = ek[rows, bands].contiguous()
-    n_in, width, depth = 7 + nm, 256, 4
+    n_in, width, depth = lib.mlp_feature_count(nm, args.n_harm), 256, 4
     escale = 0.3
     X = torch.zeros((n_samp, n_in), dtype=torch.float32, device="cuda")
     lib.mlp_features(mesh, nm, kk, ee, qi.int().contiguous(), vi.int().contiguous(), X, par["mu"],
-                     escale)
+                     escale, n_harm=args.n_harm)
     del T, D, terms, dws, sel, si_all, qi_all, vi_all, ratio
     # parameters: U(-1/sqrt(in), 1/sqrt(in)) weights, zero biases, packed per layer
     prng = np.random.default_rng(17)
@@ -482,7 +485,7 @@ def bench_learned(args):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             lib.propose_q(mesh, nm, test_k, eps_k, Dsel, prm, width, depth, par["mu"], escale,
-                          thr, 0.1, S, u, q_off, q_idx, q_w)
+                          thr, 0.1, S, u, q_off, q_idx, q_w, n_harm=args.n_harm)
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             gl = torch.zeros((n_test, nW), dtype=torch.float64, device="cuda")
@@ -526,6 +529,7 @@ def bench_learned(args):
         "data": "synthetic",
         "config": {
             "workload": (f"learned proposal on the realistic system: MLP {n_in}->{width}x{depth} "
+                         f"({'raw coordinates' if args.n_harm == 0 else f'{args.n_harm} harmonics'}) "
                          f"silu->1 fitting ln(|g|^2 + c) on {n_samp} samples of {ns} kept states; "
                          f"p(q) ~ sum_nu D_nu(q) e^net, mixture 0.9 + 0.1 uniform; S={S} q per k "
                          f"of {N}; {n_test} held-out kept k, {seeds} sampling seeds"),

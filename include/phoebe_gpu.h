@@ -290,20 +290,26 @@ phoebe_status phoebe_gpu_mlp_adam(void *handle, float *params, const float *grad
                                   float *v, int64_t n, int32_t step, double lr, double beta1,
                                   double beta2, double eps, void *stream);
 
-/* Network inputs x = [k (3 crystal coords), (eps - e0)/escale, q (3), one-hot(nu)]
- * for samples given by mesh indices k_idx, q_idx, band energy eps and mode nu
- * (device arrays [batch]); X device [batch, 7 + n_modes] (float for BF16,
- * double for FP64). */
+/* Network inputs of samples given by mesh indices k_idx, q_idx, band energy
+ * eps and mode nu (device arrays [batch]), e = (eps - e0)/escale:
+ *   n_harm = 0: x = [k (3 crystal coords), e, q (3), one-hot(nu)]  (7 + n_modes)
+ *   n_harm > 0: x = [e, one-hot(nu), and for h = 1..n_harm: cos and sin of
+ *               2 pi h k_d (d = 0..2), then of 2 pi h q_d]       (1 + n_modes + 12 n_harm)
+ * X device [batch, phoebe_gpu_mlp_feature_count(n_modes, n_harm)] (float for
+ * BF16, double for FP64).  n_harm in [0, 16]. */
+int32_t phoebe_gpu_mlp_feature_count(int32_t n_modes, int32_t n_harm);
 phoebe_status phoebe_gpu_mlp_features(void *handle, phoebe_precision prec, const int32_t mesh[3],
-                                      int32_t n_modes, const int32_t *k_idx, const double *eps,
-                                      const int32_t *q_idx, const int32_t *nu, int64_t batch,
-                                      double e0, double escale, void *X, void *stream);
+                                      int32_t n_modes, int32_t n_harm, const int32_t *k_idx,
+                                      const double *eps, const int32_t *q_idx, const int32_t *nu,
+                                      int64_t batch, double e0, double escale, void *X,
+                                      void *stream);
 
 /* Importance-sampling lists from the learned proposal.  For each k (host
  * k_idx[i], host band energy eps_k[i] of its targeted state, smearing weights
  * dweights + i N_q nModes of that state) the proposal is
  *   p_raw(q) = sum_nu D[q, nu] e^{net(k, eps, q, nu)}
- * where the network (BF16) estimates ln(|g|^2 + c) and is evaluated only where
+ * where the network (BF16, inputs as phoebe_gpu_mlp_features with n_harm)
+ * estimates ln(|g|^2 + c) and is evaluated only where
  * D > d_threshold x max D; with params = NULL the network factor is 1 (the
  * smearing-only proposal, the method without the network).  The proposal is
  * p = (1 - mix) p_raw / sum p_raw + mix / N_q; mix in (0, 1] keeps every q
@@ -312,7 +318,7 @@ phoebe_status phoebe_gpu_mlp_features(void *handle, phoebe_precision prec, const
  * w = 1 / (N_q S p(q)): q_off device int64 [nk+1], q_idx device int32 [nk S],
  * q_w device [nk S], ready for phoebe_gpu_scatter_rates.  Synchronises. */
 phoebe_status phoebe_gpu_propose_q(void *handle, const int32_t mesh[3], int32_t n_modes,
-                                   const int32_t *k_idx, const double *eps_k, int64_t nk,
+                                   int32_t n_harm, const int32_t *k_idx, const double *eps_k, int64_t nk,
                                    const double *dweights, const float *params, int32_t width,
                                    int32_t depth, double e0, double escale, double d_threshold,
                                    double mix, int32_t S, const double *uniforms, int64_t *q_off,
@@ -324,7 +330,8 @@ phoebe_status phoebe_gpu_propose_q(void *handle, const int32_t mesh[3], int32_t 
  * three per-axis factors on a full mesh, so the sum is taken one axis at a
  * time over the box [-rmax, rmax]^3 holding the Rp list (zero where the list
  * has no vector); the result is the same sum up to the order of additions.
- * Needs FP64, the full q mesh, |Rp components| <= 15 and nModes*nW <= 512.
+ * Needs FP64, the full q mesh, |Rp components| <= 15, nW <= 16, nModes <= 32
+ * and N1*N2 <= 65535.
  * AUTO (the default) takes FACTORED where it applies and the box width is at
  * most half the number of Rp vectors.  Lists of q, the reduced precisions and
  * the batched form always use DIRECT.  Returns PHOEBE_E_INVALID for an

@@ -35,7 +35,7 @@ EXPORTS = (
     "phoebe_gpu_batched_destroy", "phoebe_gpu_rate_terms", "phoebe_gpu_mlp_param_count",
     "phoebe_gpu_mlp_forward", "phoebe_gpu_mlp_grad", "phoebe_gpu_mlp_adam",
     "phoebe_gpu_mlp_features", "phoebe_gpu_propose_q", "phoebe_gpu_delta_weights",
-    "phoebe_gpu_set_mesh_sum",
+    "phoebe_gpu_set_mesh_sum", "phoebe_gpu_mlp_feature_count",
 )
 
 
@@ -115,9 +115,12 @@ def load(path: str = LIB_PATH):
                                         ctypes.POINTER(ctypes.c_double), vp]
     lib.phoebe_gpu_mlp_adam.argtypes = [vp, vp, vp, vp, vp, i64, i32, ctypes.c_double,
                                         ctypes.c_double, ctypes.c_double, ctypes.c_double, vp]
-    lib.phoebe_gpu_mlp_features.argtypes = [vp, ctypes.c_int, ctypes.POINTER(i32), i32, vp, vp, vp,
-                                            vp, i64, ctypes.c_double, ctypes.c_double, vp, vp]
-    lib.phoebe_gpu_propose_q.argtypes = [vp, ctypes.POINTER(i32), i32, ctypes.POINTER(i32),
+    lib.phoebe_gpu_mlp_features.argtypes = [vp, ctypes.c_int, ctypes.POINTER(i32), i32, i32, vp,
+                                            vp, vp, vp, i64, ctypes.c_double, ctypes.c_double, vp,
+                                            vp]
+    lib.phoebe_gpu_mlp_feature_count.restype = i32
+    lib.phoebe_gpu_mlp_feature_count.argtypes = [i32, i32]
+    lib.phoebe_gpu_propose_q.argtypes = [vp, ctypes.POINTER(i32), i32, i32, ctypes.POINTER(i32),
                                          ctypes.POINTER(ctypes.c_double), i64, vp, vp, i32, i32,
                                          ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                          ctypes.c_double, i32, vp, vp, vp, vp, vp]
@@ -307,21 +310,25 @@ class Library:
             self.handle, _ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(params.numel()),
             int(step), lr, beta1, beta2, eps, _stream(stream)))
 
+    @staticmethod
+    def mlp_feature_count(n_modes, n_harm=0) -> int:
+        return int(load().phoebe_gpu_mlp_feature_count(n_modes, n_harm))
+
     def mlp_features(self, mesh, n_modes, k_idx, eps, q_idx, nu, X, e0, escale,
-                     precision="bf16", stream=None):
+                     precision="bf16", n_harm=0, stream=None):
         m = (ctypes.c_int32 * 3)(*[int(x) for x in mesh])
         self._check(self.lib.phoebe_gpu_mlp_features(
-            self.handle, PRECISIONS[precision], m, n_modes, _ptr(k_idx), _ptr(eps), _ptr(q_idx),
+            self.handle, PRECISIONS[precision], m, n_modes, n_harm, _ptr(k_idx), _ptr(eps), _ptr(q_idx),
             _ptr(nu), int(k_idx.shape[0]), e0, escale, _ptr(X), _stream(stream)))
 
     def propose_q(self, mesh, n_modes, k_idx, eps_k, dweights, params, width, depth, e0, escale,
-                  d_threshold, mix, S, uniforms, q_off, q_idx, q_w, stream=None):
+                  d_threshold, mix, S, uniforms, q_off, q_idx, q_w, n_harm=0, stream=None):
         m = (ctypes.c_int32 * 3)(*[int(x) for x in mesh])
         nk = len(k_idx)
         kk = (ctypes.c_int32 * nk)(*[int(x) for x in k_idx])
         ee = (ctypes.c_double * nk)(*[float(x) for x in eps_k])
         self._check(self.lib.phoebe_gpu_propose_q(
-            self.handle, m, n_modes, kk, ee, nk, _ptr(dweights), _ptr(params), width, depth, e0,
+            self.handle, m, n_modes, n_harm, kk, ee, nk, _ptr(dweights), _ptr(params), width, depth, e0,
             escale, d_threshold, mix, S, _ptr(uniforms), _ptr(q_off), _ptr(q_idx), _ptr(q_w),
             _stream(stream)))
 

@@ -332,13 +332,32 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
         }
         const bool lowp = prec != PHOEBE_FP64;
         int tq = 0, tn = 0;
-        const int nc_pad = lowp ? stage2_lp_config(nm, nW, &tq, &tn) : stage2_config(nm, nW, &tq, &tn);
-        if (nc_pad < 0) {
+        const int nc_direct = lowp ? stage2_lp_config(nm, nW, &tq, &tn) : stage2_config(nm, nW, &tq, &tn);
+        if (nc_direct < 0) {
             set_err(h, "no stage-2 tiling for nModes*nW = %d", nm * nW);
             throw Fail{PHOEBE_E_UNSUPPORTED};
         }
         const int rmax_p = rmax_of(sys->rp, sys->n_rp);
         REQUIRE(h, rmax_p <= 100, "|Rp| components above 100 are not supported");
+        // Full-mesh FP64 sums may take the per-axis factorised form (see
+        // launch_axis_transforms / launch_line_rates).
+        const int Wbox = 2 * rmax_p + 1;
+        const int nc_line = line_rates_ncpad(nm, nW);
+        const int64_t NL = (int64_t)mesh.n1 * mesh.n2;
+        const bool can_factor = prec == PHOEBE_FP64 && q_off == nullptr && Wbox <= 31 &&
+                                nc_line > 0 && NL <= 65535 &&
+                                line_rates_lds(Wbox, mesh.n0, nm) <= 64 * 1024;
+        if (h->mesh_sum == PHOEBE_MESH_SUM_FACTORED && !can_factor) {
+            set_err(h, "the factorised mesh sum needs FP64, the full q mesh, |Rp| <= 15, "
+                       "nW <= 16, nModes <= 32 and N1*N2 <= 65535");
+            throw Fail{PHOEBE_E_UNSUPPORTED};
+        }
+        const bool factored = can_factor && (h->mesh_sum == PHOEBE_MESH_SUM_FACTORED ||
+                                             (h->mesh_sum == PHOEBE_MESH_SUM_AUTO &&
+                                              2 * Wbox <= sys->n_rp));
+        // stage-2 operand columns: sa*nW + b (direct), sa*16 + b (factorised)
+        const int nc_pad = factored ? nc_line : nc_direct;
+        const int cw = factored ? 16 : nW;
         HIPCHK(h, hipSetDevice(h->device));
         const int n_re = sys->n_re, n_rp = sys->n_rp;
         // K padding of the stage-2 operand: 4 (K of the f64/f32 MFMA) or 32 (bf16)
@@ -360,22 +379,7 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                            (double)BK * nW * rp_pad * nc_pad * f_elem > 8e9))
             BK /= 2;
         const int BQ = 16 * tq;
-        // Full-mesh FP64 sums may take the per-axis factorised form (see
-        // launch_axis_transforms / launch_line_rates).
-        const int Wbox = 2 * rmax_p + 1;
-        const bool can_factor = prec == PHOEBE_FP64 && q_off == nullptr && Wbox <= 32 &&
-                                (nc_pad / 64 <= 4 || nc_pad / 64 == 6 || nc_pad / 64 == 8) &&
-                                line_rates_lds(Wbox, mesh.n0, nc_pad, nm) <= 159 * 1024;
-        if (h->mesh_sum == PHOEBE_MESH_SUM_FACTORED && !can_factor) {
-            set_err(h, "the factorised mesh sum needs FP64, the full q mesh, |Rp| <= 15 and "
-                       "nModes*nW <= 512");
-            throw Fail{PHOEBE_E_UNSUPPORTED};
-        }
-        const bool factored = can_factor && (h->mesh_sum == PHOEBE_MESH_SUM_FACTORED ||
-                                             (h->mesh_sum == PHOEBE_MESH_SUM_AUTO &&
-                                              2 * Wbox <= n_rp));
         // states per factorised sub-batch: T1 + T2 of a sub-batch stay under 4 GB
-        const int64_t NL = (int64_t)mesh.n1 * mesh.n2;
         const size_t t12_state = ((size_t)Wbox * Wbox * mesh.n2 + (size_t)Wbox * NL) * nc_pad * sizeof(cd);
         const int nsb = factored ? (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)BK * nW,
                                                       (int64_t)(4e9 / (double)t12_state)))
@@ -597,7 +601,7 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
             else
                 HIPCHK(h, launch_fold_uk(reinterpret_cast<const cd*>(Gbuf), NC2, T.U, T.st_row + sbeg,
                                          (int)r0, T.st_kmesh + sbeg, T.st_band + sbeg, ns, n_rp, nm,
-                                         nW, rp_pad, nc_pad, reinterpret_cast<cd*>(Fbuf), s));
+                                         nW, cw, rp_pad, nc_pad, reinterpret_cast<cd*>(Fbuf), s));
             RateArgs ra{};
             ra.F = reinterpret_cast<const cd*>(Fbuf);
             ra.rp_pad = rp_pad;

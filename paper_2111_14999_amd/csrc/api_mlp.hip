@@ -189,32 +189,39 @@ phoebe_status phoebe_gpu_mlp_adam(void* handle, float* params, const float* grad
     });
 }
 
+int32_t phoebe_gpu_mlp_feature_count(int32_t n_modes, int32_t n_harm) {
+    if (n_modes < 1 || n_harm < 0 || n_harm > 16) return -1;
+    return feature_count(n_modes, n_harm);
+}
+
 phoebe_status phoebe_gpu_mlp_features(void* handle, phoebe_precision prec, const int32_t mesh[3],
-                                      int32_t n_modes, const int32_t* k_idx, const double* eps,
-                                      const int32_t* q_idx, const int32_t* nu, int64_t batch,
-                                      double e0, double escale, void* X, void* stream) {
+                                      int32_t n_modes, int32_t n_harm, const int32_t* k_idx,
+                                      const double* eps, const int32_t* q_idx, const int32_t* nu,
+                                      int64_t batch, double e0, double escale, void* X,
+                                      void* stream) {
     if (!handle) return PHOEBE_E_INVALID;
     Handle* h = static_cast<Handle*>(handle);
     hipStream_t s = static_cast<hipStream_t>(stream);
     return run(h, [&] {
         REQUIRE(h, mesh && mesh[0] >= 1 && mesh[1] >= 1 && mesh[2] >= 1, "bad mesh");
         REQUIRE(h, n_modes >= 1 && escale > 0.0, "n_modes >= 1 and escale > 0 required");
+        REQUIRE(h, n_harm >= 0 && n_harm <= 16, "n_harm must be in [0, 16]");
         REQUIRE(h, prec == PHOEBE_FP64 || prec == PHOEBE_BF16, "precision must be FP64 or BF16");
         if (batch == 0) return;
         REQUIRE(h, batch > 0 && k_idx && eps && q_idx && nu && X, "NULL arrays");
         HIPCHK(h, hipSetDevice(h->device));
         const Mesh m{mesh[0], mesh[1], mesh[2]};
         if (prec == PHOEBE_FP64)
-            HIPCHK(h, launch_features<double>(k_idx, eps, q_idx, nu, batch, m, n_modes, e0, escale,
-                                              (double*)X, s));
+            HIPCHK(h, launch_features<double>(k_idx, eps, q_idx, nu, batch, m, n_modes, n_harm, e0,
+                                              escale, (double*)X, s));
         else
-            HIPCHK(h, launch_features<float>(k_idx, eps, q_idx, nu, batch, m, n_modes, e0, escale,
-                                             (float*)X, s));
+            HIPCHK(h, launch_features<float>(k_idx, eps, q_idx, nu, batch, m, n_modes, n_harm, e0,
+                                             escale, (float*)X, s));
     });
 }
 
 phoebe_status phoebe_gpu_propose_q(void* handle, const int32_t mesh[3], int32_t n_modes,
-                                   const int32_t* k_idx, const double* eps_k, int64_t nk,
+                                   int32_t n_harm, const int32_t* k_idx, const double* eps_k, int64_t nk,
                                    const double* dweights, const float* params, int32_t width,
                                    int32_t depth, double e0, double escale, double d_threshold,
                                    double mix, int32_t S, const double* uniforms, int64_t* q_off,
@@ -228,10 +235,11 @@ phoebe_status phoebe_gpu_propose_q(void* handle, const int32_t mesh[3], int32_t 
         REQUIRE(h, mix > 0.0 && mix <= 1.0, "mix must be in (0, 1]: the uniform share keeps the "
                                             "proposal's support full");
         REQUIRE(h, d_threshold >= 0.0 && d_threshold < 1.0, "d_threshold must be in [0, 1)");
+        REQUIRE(h, n_harm >= 0 && n_harm <= 16, "n_harm must be in [0, 16]");
         if (nk == 0) return;
         REQUIRE(h, nk > 0 && k_idx && eps_k && dweights && uniforms && q_off && q_idx && q_w,
                 "NULL arrays");
-        const int n_in = 7 + n_modes;
+        const int n_in = feature_count(n_modes, n_harm);
         if (params) check_net(h, n_in, width, depth);
         HIPCHK(h, hipSetDevice(h->device));
         const Mesh m{mesh[0], mesh[1], mesh[2]};
@@ -285,8 +293,8 @@ phoebe_status phoebe_gpu_propose_q(void* handle, const int32_t mesh[3], int32_t 
                 HIPCHK(h, hipStreamSynchronize(s));
                 for (int64_t c0 = 0; c0 < cnt; c0 += chunk) {
                     const int64_t nc = std::min<int64_t>(chunk, cnt - c0);
-                    HIPCHK(h, launch_features_list(k_idx[i], eps_k[i], list + c0, nc, m, n_modes, e0,
-                                                   escale, X, s));
+                    HIPCHK(h, launch_features_list(k_idx[i], eps_k[i], list + c0, nc, m, n_modes,
+                                                   n_harm, e0, escale, X, s));
                     forward_impl<float>(h, net, params, X, nc, y, Z, A, s);
                     HIPCHK(h, launch_weight_list(D, list + c0, y, nc, E, s));
                 }

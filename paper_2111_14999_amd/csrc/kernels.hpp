@@ -53,7 +53,7 @@ hipError_t launch_band_extrema(const double* eps, int64_t nk, int nW, const doub
 // for each state st = (kb, n); rows r >= n_rp and columns >= NC are zero.
 hipError_t launch_fold_uk(const cd* G, int64_t ldg, const cd* U, const int32_t* st_krow,
                           int row0, const int32_t* st_kmesh, const int32_t* st_band, int nst, int n_rp,
-                          int nm, int nW, int rp_pad, int nc_pad, cd* F, hipStream_t s);
+                          int nm, int nW, int cw, int rp_pad, int nc_pad, cd* F, hipStream_t s);
 
 struct RateArgs {
     const cd* F;            // [nst, rp_pad, nc_pad]
@@ -99,8 +99,10 @@ hipError_t launch_axis_transforms(const cd* F, int rp_pad, int nc_pad, const int
                                   int rmax, Mesh m, const cd* P, int nst, cd* T1, cd* T2,
                                   hipStream_t s);
 // Axis 0 on MFMA + rotations + rate terms, one work-group per (state, q1, q2) line.
+// Columns sa*16 + b (nW <= 16), nc_pad = 64 TN with 4 TN >= nModes.
 hipError_t launch_line_rates(const RateArgs& a, int nst, hipStream_t s);
-size_t line_rates_lds(int W, int N0, int nc_pad, int nm);
+size_t line_rates_lds(int W, int N0, int nm);
+int line_rates_ncpad(int nm, int nW);  // -1 where the form does not apply
 
 // gamma[row, band] = scale * sum_t partial[st, t]
 hipError_t launch_reduce_partials(const double* partial, int nst, int ntiles,

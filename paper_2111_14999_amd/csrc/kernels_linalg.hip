@@ -94,10 +94,14 @@ __global__ __launch_bounds__(256) void zgemm_kernel(const cd* __restrict__ A, in
             bv[j] = (col < N && k < K) ? B[(int64_t)k * ldb + col] : cd{0.0, 0.0};
         }
     };
+    // operands are prefetched two k-steps ahead: one step of MFMA work is
+    // shorter than the HBM latency of the streamed B operand
+    cd a_n1[TM], b_n1[TN];
     load(0, a_cur, b_cur);
+    load(4, a_n1, b_n1);  // zeros where k >= K
     for (int k0 = 0; k0 < K; k0 += 4) {
-        cd a_nxt[TM], b_nxt[TN];
-        if (k0 + 4 < K) load(k0 + 4, a_nxt, b_nxt);
+        cd a_n2[TM], b_n2[TN];
+        load(k0 + 8, a_n2, b_n2);  // zeros past K
         // two passes over the tiles, so that dependent MFMAs on one accumulator
         // are 2 TM TN - 1 instructions apart
 #pragma unroll
@@ -114,11 +118,15 @@ __global__ __launch_bounds__(256) void zgemm_kernel(const cd* __restrict__ A, in
                 cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a_cur[i].y, b_cur[j].y, cr[i][j], 0, 0, 0);
                 ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur[i].y, b_cur[j].x, ci[i][j], 0, 0, 0);
             }
-        if (k0 + 4 < K) {
 #pragma unroll
-            for (int i = 0; i < TM; ++i) a_cur[i] = a_nxt[i];
+        for (int i = 0; i < TM; ++i) {
+            a_cur[i] = a_n1[i];
+            a_n1[i] = a_n2[i];
+        }
 #pragma unroll
-            for (int j = 0; j < TN; ++j) b_cur[j] = b_nxt[j];
+        for (int j = 0; j < TN; ++j) {
+            b_cur[j] = b_n1[j];
+            b_n1[j] = b_n2[j];
         }
     }
 #pragma unroll

@@ -58,10 +58,15 @@ constexpr int kMaxW = 32;
 
 // T1[st, p, q2, c] = sum_r P2[q2, r] F[st, box_rp[p W + r], c]   (p = (R0, R1))
 // box_rp maps a box position to its row of F, or -1 where the list has no Rp.
+// WT > 0 fixes the box width at compile time (the W inputs stay in registers);
+// WT = 0 takes it from the argument.
+template <int WT>
 __global__ __launch_bounds__(256) void axis2_kernel(const cd* __restrict__ F, int rp_pad,
                                                     int nc_pad, const int32_t* __restrict__ box_rp,
-                                                    int W, int N2, const cd* __restrict__ P2,
+                                                    int Wr, int N2, const cd* __restrict__ P2,
                                                     int nst, cd* __restrict__ T1) {
+    constexpr int NV = WT > 0 ? WT : kMaxW;
+    const int W = WT > 0 ? WT : Wr;
     const int64_t total = (int64_t)nst * W * W * nc_pad;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
@@ -69,42 +74,68 @@ __global__ __launch_bounds__(256) void axis2_kernel(const cd* __restrict__ F, in
         const int64_t sp = t / nc_pad;  // st * W^2 + p
         const int p = (int)(sp % (W * W));
         const int st = (int)(sp / (W * W));
-        cd v[kMaxW];
-        for (int r = 0; r < W; ++r) {
-            const int row = box_rp[p * W + r];
-            v[r] = row >= 0 ? F[((int64_t)st * rp_pad + row) * nc_pad + c] : cd{0.0, 0.0};
+        cd v[NV];
+#pragma unroll
+        for (int r = 0; r < NV; ++r) {
+            if (r < W) {
+                const int row = box_rp[p * W + r];
+                v[r] = row >= 0 ? F[((int64_t)st * rp_pad + row) * nc_pad + c] : cd{0.0, 0.0};
+            }
         }
         cd* out = T1 + sp * N2 * nc_pad + c;
         for (int q = 0; q < N2; ++q) {
             const cd* Pq = P2 + q * W;
             cd acc = {0.0, 0.0};
-            for (int r = 0; r < W; ++r) acc = cfma(Pq[r], v[r], acc);
+#pragma unroll
+            for (int r = 0; r < NV; ++r)
+                if (r < W) acc = cfma(Pq[r], v[r], acc);
             out[(int64_t)q * nc_pad] = acc;
         }
     }
 }
 
 // out[o, n, i] = sum_r P[n, r] in[o, r, i]   (i < inner, contiguous)
+template <int WT>
 __global__ __launch_bounds__(256) void axis_mid_kernel(const cd* __restrict__ in, int64_t n_outer,
-                                                       int W, int64_t inner, int N,
+                                                       int Wr, int64_t inner, int N,
                                                        const cd* __restrict__ P,
                                                        cd* __restrict__ out) {
+    constexpr int NV = WT > 0 ? WT : kMaxW;
+    const int W = WT > 0 ? WT : Wr;
     const int64_t total = n_outer * inner;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = t % inner;
         const int64_t o = t / inner;
-        cd v[kMaxW];
+        cd v[NV];
         const cd* src = in + o * W * inner + i;
-        for (int r = 0; r < W; ++r) v[r] = src[(int64_t)r * inner];
+#pragma unroll
+        for (int r = 0; r < NV; ++r)
+            if (r < W) v[r] = src[(int64_t)r * inner];
         cd* dst = out + o * N * inner + i;
         for (int n = 0; n < N; ++n) {
             const cd* Pn = P + n * W;
             cd acc = {0.0, 0.0};
-            for (int r = 0; r < W; ++r) acc = cfma(Pn[r], v[r], acc);
+#pragma unroll
+            for (int r = 0; r < NV; ++r)
+                if (r < W) acc = cfma(Pn[r], v[r], acc);
             dst[(int64_t)n * inner] = acc;
         }
     }
+}
+
+template <int WT>
+static hipError_t go_axes(const cd* F, int rp_pad, int nc_pad, const int32_t* box_rp, int W,
+                          Mesh m, const cd* P1, const cd* P2, int nst, cd* T1, cd* T2,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(axis2_kernel<WT>, dim3(gridm((int64_t)nst * W * W * nc_pad, 256)),
+                       dim3(256), 0, s, F, rp_pad, nc_pad, box_rp, W, m.n2, P2, nst, T1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t inner = (int64_t)m.n2 * nc_pad;
+    hipLaunchKernelGGL(axis_mid_kernel<WT>, dim3(gridm((int64_t)nst * W * inner, 256)), dim3(256),
+                       0, s, T1, (int64_t)nst * W, W, inner, m.n1, P1, T2);
+    return hipGetLastError();
 }
 
 hipError_t launch_axis_transforms(const cd* F, int rp_pad, int nc_pad, const int32_t* box_rp,
@@ -115,24 +146,31 @@ hipError_t launch_axis_transforms(const cd* F, int rp_pad, int nc_pad, const int
     if (nst <= 0) return hipSuccess;
     const cd* P1 = P + (int64_t)m.n0 * W;
     const cd* P2 = P1 + (int64_t)m.n1 * W;
-    hipLaunchKernelGGL(axis2_kernel, dim3(gridm((int64_t)nst * W * W * nc_pad, 256)), dim3(256), 0,
-                       s, F, rp_pad, nc_pad, box_rp, W, m.n2, P2, nst, T1);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const int64_t inner = (int64_t)m.n2 * nc_pad;
-    hipLaunchKernelGGL(axis_mid_kernel, dim3(gridm((int64_t)nst * W * inner, 256)), dim3(256), 0, s,
-                       T1, (int64_t)nst * W, W, inner, m.n1, P1, T2);
-    return hipGetLastError();
+    switch (W) {
+        case 1: return go_axes<1>(F, rp_pad, nc_pad, box_rp, W, m, P1, P2, nst, T1, T2, s);
+        case 3: return go_axes<3>(F, rp_pad, nc_pad, box_rp, W, m, P1, P2, nst, T1, T2, s);
+        case 5: return go_axes<5>(F, rp_pad, nc_pad, box_rp, W, m, P1, P2, nst, T1, T2, s);
+        case 7: return go_axes<7>(F, rp_pad, nc_pad, box_rp, W, m, P1, P2, nst, T1, T2, s);
+        case 9: return go_axes<9>(F, rp_pad, nc_pad, box_rp, W, m, P1, P2, nst, T1, T2, s);
+        default: return go_axes<0>(F, rp_pad, nc_pad, box_rp, W, m, P1, P2, nst, T1, T2, s);
+    }
 }
 
 // ---------------------------------------------------------------------------
 // Last axis on MFMA + rotations + rate terms.  Work-group = one state x one
 // (q1, q2) line; the N0 points of the line are taken 16 at a time.  Lane l
 // holds A[l%16][l/16] = P0[q0, R0] and B[l/16][l%16] = T2[R0, line, col];
-// result v of lane l is row l/16 + 4v (f64 16x16x4 layout), so after a
-// chunk every row 0..15 of X is in LDS and the rotation runs once over it.
+// result v of lane l is row l/16 + 4v (f64 16x16x4 layout).
+//
+// Columns are laid out c = sa*16 + b (b < nW <= 16), so every 16-column MFMA
+// tile holds one mode index sa with b on the lane: the k+q rotation
+//   Y[q, sa, m] = sum_b X[q, sa, b] U_{k+q}[b, m]
+// is a product per lane and a sum over the 16 lanes of a row group, done in
+// registers.  Only Y (16 q x modes x final bands) goes through LDS to the
+// threads that apply E_q = z l and form the rate terms.  The grid runs over
+// states fastest, so the work-groups of one line (same E_q) run together.
 // ---------------------------------------------------------------------------
-constexpr int kMBL = 2;  // final bands per rotation pass
+constexpr int kMBL = 4;  // final bands per rotation pass
 
 template <int TN>
 __global__ __launch_bounds__(256, 2) void line_rates_kernel(RateArgs a) {
@@ -145,14 +183,11 @@ __global__ __launch_bounds__(256, 2) void line_rates_kernel(RateArgs a) {
     const int N0p = (N0 + 15) & ~15;
     const int ldf = a.nc_pad;
     cd* sP = reinterpret_cast<cd*>(smem_raw);     // [N0p][Wp]
-    cd* sX = sP + N0p * Wp;                       // [16][nc_pad]
-    cd* sY = sX + 16 * ldf;                       // [16][kMBL][nm]
+    cd* sY = sP + N0p * Wp;                       // [16][kMBL][nm]
     __shared__ double sRed[4];
-    __shared__ int sKq[16];
-    __shared__ int sQ[16];
 
-    const int st = blockIdx.y;
-    const int line = blockIdx.x;
+    const int st = blockIdx.x;
+    const int line = blockIdx.y;
     const int NL = mesh.n1 * mesh.n2;
     const int q1 = line / mesh.n2, q2 = line - q1 * mesh.n2;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -168,11 +203,14 @@ __global__ __launch_bounds__(256, 2) void line_rates_kernel(RateArgs a) {
     const int mlo = a.st_mlo[st], mhi = a.st_mhi[st];
     int k0i, k1i, k2i;
     mesh_triple(kmesh, mesh, k0i, k1i, k2i);
+    const int kq12 = ((k1i + q1) % mesh.n1) * mesh.n2 + (k2i + q2) % mesh.n2;
+    const int q12 = q1 * mesh.n2 + q2;
     const double eps_n = a.eps[(int64_t)kmesh * nW + nband];
     const double inv_s2 = 1.0 / (a.sigma * a.sigma);
     const int colbase = wave * TN * 16 + li;
     const cd* Tst = a.T2 + (int64_t)st * W * NL * ldf + (int64_t)line * ldf + colbase;
     double gacc = 0.0;
+    __syncthreads();
 
     for (int qc = 0; qc < N0; qc += 16) {
         d4 cr[TN], ci[TN];
@@ -181,7 +219,6 @@ __global__ __launch_bounds__(256, 2) void line_rates_kernel(RateArgs a) {
             cr[t] = d4{0, 0, 0, 0};
             ci[t] = d4{0, 0, 0, 0};
         }
-        __syncthreads();  // sP ready; the previous chunk is done with sX and sY
         for (int k0 = 0; k0 < Wp; k0 += 4) {
             const int k = k0 + lg;
             cd bc[TN];
@@ -205,38 +242,36 @@ __global__ __launch_bounds__(256, 2) void line_rates_kernel(RateArgs a) {
                 ci[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ph.y, bc[t].x, ci[t], 0, 0, 0);
             }
         }
+        // final-band index of k+q for the four rows of this lane group
+        int kqv[4];
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-#pragma unroll
-            for (int t = 0; t < TN; ++t)
-                sX[(lg + 4 * v) * ldf + colbase + t * 16] = cd{cr[t][v], ci[t][v]};
-        if (tid < 16) {
-            const int q0 = qc + tid;
-            int kq = -1, q = 0;
-            if (q0 < N0) {
-                q = (int)mesh_linear(q0, q1, q2, mesh);
-                kq = (int)mesh_linear((k0i + q0) % mesh.n0, (k1i + q1) % mesh.n1,
-                                      (k2i + q2) % mesh.n2, mesh);
-            }
-            sKq[tid] = kq;
-            sQ[tid] = q;
+        for (int v = 0; v < 4; ++v) {
+            const int q0 = qc + lg + 4 * v;
+            kqv[v] = q0 < N0 ? ((k0i + q0) % mesh.n0) * NL + kq12 : -1;
         }
-        __syncthreads();
         for (int m0 = mlo; m0 <= mhi; m0 += kMBL) {
             const int nmb = min(kMBL, mhi - m0 + 1);
-            // Y[c, mb, sa] = sum_b X[c, sa*nW + b] U_{k+q}[b, m0 + mb]
-            for (int it = tid; it < 16 * nmb * nm; it += 256) {
-                const int c = it / (nmb * nm);
-                const int r = it - c * nmb * nm;
-                const int mb = r / nm, sa = r - mb * nm;
-                const int kq = sKq[c];
-                cd y = {0.0, 0.0};
-                if (kq >= 0) {
-                    const cd* Xr = sX + c * ldf + sa * nW;
-                    const cd* Uc = a.U + (int64_t)kq * nW * nW + m0 + mb;
-                    for (int b = 0; b < nW; ++b) y = cfma(Xr[b], Uc[(int64_t)b * nW], y);
+            // Y in registers: lane (li = b) product, then a sum over the 16 lanes
+            for (int mb = 0; mb < nmb; ++mb) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    cd u = {0.0, 0.0};
+                    if (kqv[v] >= 0 && li < nW)
+                        u = a.U[((int64_t)kqv[v] * nW + li) * nW + m0 + mb];
+#pragma unroll
+                    for (int t = 0; t < TN; ++t) {
+                        double yr = cr[t][v] * u.x - ci[t][v] * u.y;
+                        double yi = cr[t][v] * u.y + ci[t][v] * u.x;
+#pragma unroll
+                        for (int o = 8; o > 0; o >>= 1) {
+                            yr += __shfl_xor(yr, o, 64);
+                            yi += __shfl_xor(yi, o, 64);
+                        }
+                        const int sa = wave * TN + t;
+                        if (li == 0 && sa < nm)
+                            sY[((lg + 4 * v) * kMBL + mb) * nm + sa] = cd{yr, yi};
+                    }
                 }
-                sY[(c * kMBL + mb) * nm + sa] = y;
             }
             __syncthreads();
             // Z[c, mb, nu] = sum_sa E_q[sa, nu] Y[c, mb, sa]; rate terms
@@ -244,23 +279,25 @@ __global__ __launch_bounds__(256, 2) void line_rates_kernel(RateArgs a) {
                 const int c = it / (nmb * nm);
                 const int r = it - c * nmb * nm;
                 const int mb = r / nm, nu = r - mb * nm;
-                const int kq = sKq[c];
-                if (kq < 0) continue;
-                const int64_t q = sQ[c];
+                const int q0 = qc + c;
+                if (q0 >= N0) continue;
+                const int64_t q = (int64_t)q0 * NL + q12;
+                const int64_t kq = (int64_t)((k0i + q0) % mesh.n0) * NL + kq12;
                 const cd* Yr = sY + (c * kMBL + mb) * nm;
                 const cd* Eq = a.E + q * nm * nm + nu;
                 cd z = {0.0, 0.0};
                 for (int sa = 0; sa < nm; ++sa) z = cfma(Eq[sa * nm], Yr[sa], z);
                 const int m = m0 + mb;
-                const double x = eps_n - a.eps[(int64_t)kq * nW + m];
-                const double fm = a.focc[(int64_t)kq * nW + m];
+                const double x = eps_n - a.eps[kq * nW + m];
+                const double fm = a.focc[kq * nW + m];
                 const double w = a.omega[q * nm + nu], nbq = a.nb[q * nm + nu];
                 const double y1 = x - w, y2 = x + w;
                 const double g1 = exp(-y1 * y1 * inv_s2), g2 = exp(-y2 * y2 * inv_s2);
                 const double term = cabs2(z) * ((nbq + 1.0 - fm) * g1 + (nbq + fm) * g2);
                 gacc += term;
                 if (a.terms)
-                    atomicAdd(&a.terms[((int64_t)st * a.nq_mesh + q) * nm + nu], a.terms_scale * term);
+                    atomicAdd(&a.terms[((int64_t)st * a.nq_mesh + q) * nm + nu],
+                              a.terms_scale * term);
             }
             __syncthreads();
         }
@@ -272,15 +309,22 @@ __global__ __launch_bounds__(256, 2) void line_rates_kernel(RateArgs a) {
     if (tid == 0) a.partial[(int64_t)st * a.n_qtiles + line] = (sRed[0] + sRed[1]) + (sRed[2] + sRed[3]);
 }
 
-size_t line_rates_lds(int W, int N0, int nc_pad, int nm) {
+size_t line_rates_lds(int W, int N0, int nm) {
     const int Wp = (W + 3) & ~3, N0p = (N0 + 15) & ~15;
-    return ((size_t)N0p * Wp + 16 * (size_t)nc_pad + 16 * (size_t)kMBL * nm) * sizeof(cd);
+    return ((size_t)N0p * Wp + 16 * (size_t)kMBL * nm) * sizeof(cd);
+}
+
+// Columns of the factorised form: one 16-wide tile per mode index, 4 waves x TN tiles.
+int line_rates_ncpad(int nm, int nW) {
+    if (nW > 16 || nm > 32) return -1;
+    const int tn = (nm + 3) / 4;
+    return 64 * (tn == 5 ? 6 : (tn == 7 ? 8 : tn));
 }
 
 template <int TN>
 static hipError_t go_line(const RateArgs& a, int nst, hipStream_t s) {
-    const size_t shm = line_rates_lds(a.W, a.mesh.n0, a.nc_pad, a.nm);
-    if (shm > 160 * 1024 - 1024) return hipErrorInvalidValue;
+    const size_t shm = line_rates_lds(a.W, a.mesh.n0, a.nm);
+    if (shm > 64 * 1024) return hipErrorInvalidValue;
     hipError_t e = hipFuncSetAttribute((const void*)line_rates_kernel<TN>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) return e;
@@ -296,14 +340,16 @@ static hipError_t go_line(const RateArgs& a, int nst, hipStream_t s) {
         b.st_mhi += s0;
         b.partial = a.partial + (int64_t)s0 * a.n_qtiles;
         if (a.terms) b.terms = a.terms + (int64_t)s0 * a.nq_mesh * a.nm;
-        hipLaunchKernelGGL((line_rates_kernel<TN>), dim3((unsigned)NL, ns), dim3(256), shm, s, b);
+        hipLaunchKernelGGL((line_rates_kernel<TN>), dim3(ns, (unsigned)NL), dim3(256), shm, s, b);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_line_rates(const RateArgs& a, int nst, hipStream_t s) {
     if (nst <= 0) return hipSuccess;
-    if (a.n_qtiles != a.mesh.n1 * a.mesh.n2 || a.W > kMaxW) return hipErrorInvalidValue;
+    if (a.n_qtiles != a.mesh.n1 * a.mesh.n2 || a.n_qtiles > 65535 || a.W > kMaxW ||
+        line_rates_ncpad(a.nm, a.nW) != a.nc_pad)
+        return hipErrorInvalidValue;
     switch (a.nc_pad / 64) {
         case 1: return go_line<1>(a, nst, s);
         case 2: return go_line<2>(a, nst, s);

@@ -286,77 +286,79 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, 
 }
 
 // ---------------------------------------------------------------------------
-// features x = [k (3), (eps - e0)/escale, q (3), one-hot(nu, nm)] for sample b
+// Network inputs of one sample (k, band energy, q, mode nu):
+//   n_harm = 0: [k (3 crystal coords), (eps - e0)/escale, q (3), one-hot(nu)]
+//   n_harm > 0: [(eps - e0)/escale, one-hot(nu), then for h = 1..n_harm
+//                cos, sin of 2 pi h k_d (3 + 3) and of 2 pi h q_d (3 + 3)]
+// The periodic form gives the network the Fourier harmonics in which the
+// Wannier-gauge coupling is band-limited; h i_d mod N_d is reduced exactly.
 // ---------------------------------------------------------------------------
+__host__ __device__ inline int n_features(int nm, int n_harm) {
+    return n_harm == 0 ? 7 + nm : 1 + nm + 12 * n_harm;
+}
+
+template <class T>
+__device__ inline void write_features(T* x, int k0, int k1, int k2, int q0, int q1, int q2, int nu,
+                                      double e, Mesh mesh, int nm, int n_harm) {
+    if (n_harm == 0) {
+        x[0] = (T)((double)k0 / mesh.n0);
+        x[1] = (T)((double)k1 / mesh.n1);
+        x[2] = (T)((double)k2 / mesh.n2);
+        x[3] = (T)e;
+        x[4] = (T)((double)q0 / mesh.n0);
+        x[5] = (T)((double)q1 / mesh.n1);
+        x[6] = (T)((double)q2 / mesh.n2);
+        for (int v = 0; v < nm; ++v) x[7 + v] = (T)(v == nu ? 1 : 0);
+        return;
+    }
+    x[0] = (T)e;
+    for (int v = 0; v < nm; ++v) x[1 + v] = (T)(v == nu ? 1 : 0);
+    const int idx[6] = {k0, k1, k2, q0, q1, q2};
+    const int Ns[6] = {mesh.n0, mesh.n1, mesh.n2, mesh.n0, mesh.n1, mesh.n2};
+    T* y = x + 1 + nm;
+    for (int h = 1; h <= n_harm; ++h)
+        for (int d = 0; d < 6; ++d) {
+            const int a = (int)(((int64_t)h * idx[d]) % Ns[d]);
+            double sn, cs;
+            sincospi(2.0 * (double)a / Ns[d], &sn, &cs);
+            y[0] = (T)cs;
+            y[1] = (T)sn;
+            y += 2;
+        }
+}
+
 template <class T>
 __global__ void features_kernel(const int32_t* k_idx, const double* eps, const int32_t* q_idx,
-                                const int32_t* nu, int64_t B, Mesh mesh, int nm, double e0,
-                                double escale, T* X) {
-    const int nin = 7 + nm;
+                                const int32_t* nu, int64_t B, Mesh mesh, int nm, int n_harm,
+                                double e0, double escale, T* X) {
+    const int nin = n_features(nm, n_harm);
     for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < B;
          b += (int64_t)gridDim.x * blockDim.x) {
         int k0, k1, k2, q0, q1, q2;
         mesh_triple(k_idx[b], mesh, k0, k1, k2);
         mesh_triple(q_idx[b], mesh, q0, q1, q2);
-        T* x = X + b * nin;
-        x[0] = (T)((double)k0 / mesh.n0);
-        x[1] = (T)((double)k1 / mesh.n1);
-        x[2] = (T)((double)k2 / mesh.n2);
-        x[3] = (T)((eps[b] - e0) / escale);
-        x[4] = (T)((double)q0 / mesh.n0);
-        x[5] = (T)((double)q1 / mesh.n1);
-        x[6] = (T)((double)q2 / mesh.n2);
-        for (int v = 0; v < nm; ++v) x[7 + v] = (T)(v == nu[b] ? 1 : 0);
+        write_features<T>(X + b * nin, k0, k1, k2, q0, q1, q2, nu[b], (eps[b] - e0) / escale, mesh,
+                          nm, n_harm);
     }
 }
 
 template <class T>
 hipError_t launch_features(const int32_t* k_idx, const double* eps, const int32_t* q_idx,
-                           const int32_t* nu, int64_t B, Mesh mesh, int nm, double e0,
+                           const int32_t* nu, int64_t B, Mesh mesh, int nm, int n_harm, double e0,
                            double escale, T* X, hipStream_t s) {
     if (B <= 0) return hipSuccess;
     hipLaunchKernelGGL(features_kernel<T>, dim3(gridm(B, 256)), dim3(256), 0, s, k_idx, eps, q_idx,
-                       nu, B, mesh, nm, e0, escale, X);
+                       nu, B, mesh, nm, n_harm, e0, escale, X);
     return hipGetLastError();
 }
 template hipError_t launch_features<float>(const int32_t*, const double*, const int32_t*,
-                                           const int32_t*, int64_t, Mesh, int, double, double,
+                                           const int32_t*, int64_t, Mesh, int, int, double, double,
                                            float*, hipStream_t);
 template hipError_t launch_features<double>(const int32_t*, const double*, const int32_t*,
-                                            const int32_t*, int64_t, Mesh, int, double, double,
+                                            const int32_t*, int64_t, Mesh, int, int, double, double,
                                             double*, hipStream_t);
 
-// features of every (q, nu) of q in [q0, q0 + nq) for one k (proposal evaluation)
-__global__ void features_grid_kernel(int32_t kmesh, double eps, int64_t q0, int64_t nq, Mesh mesh,
-                                     int nm, double e0, double escale, float* X) {
-    const int nin = 7 + nm;
-    const int64_t total = nq * nm;
-    int k0, k1, k2;
-    mesh_triple(kmesh, mesh, k0, k1, k2);
-    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < total;
-         r += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t q = q0 + r / nm;
-        const int nu = (int)(r % nm);
-        int a0, a1, a2;
-        mesh_triple(q, mesh, a0, a1, a2);
-        float* x = X + r * nin;
-        x[0] = (float)((double)k0 / mesh.n0);
-        x[1] = (float)((double)k1 / mesh.n1);
-        x[2] = (float)((double)k2 / mesh.n2);
-        x[3] = (float)((eps - e0) / escale);
-        x[4] = (float)((double)a0 / mesh.n0);
-        x[5] = (float)((double)a1 / mesh.n1);
-        x[6] = (float)((double)a2 / mesh.n2);
-        for (int v = 0; v < nm; ++v) x[7 + v] = v == nu ? 1.f : 0.f;
-    }
-}
-
-hipError_t launch_features_grid(int32_t kmesh, double eps, int64_t q0, int64_t nq, Mesh mesh,
-                                int nm, double e0, double escale, float* X, hipStream_t s) {
-    hipLaunchKernelGGL(features_grid_kernel, dim3(gridm(nq * nm, 256)), dim3(256), 0, s, kmesh, eps,
-                       q0, nq, mesh, nm, e0, escale, X);
-    return hipGetLastError();
-}
+int feature_count(int nm, int n_harm) { return n_features(nm, n_harm); }
 
 // p_raw[q] = sum_nu max(exp(y[q nm + nu]) - c, 0)
 __global__ void proposal_raw_kernel(const float* y, int64_t nq, int nm, double c, double* p) {
@@ -402,8 +404,9 @@ __global__ void select_kernel(const double* D, int64_t n, const double* dmax, do
 
 // features of listed (q, nu) entries r = q nm + nu for one k
 __global__ void features_list_kernel(int32_t kmesh, double eps, const int32_t* list, int64_t n,
-                                     Mesh mesh, int nm, double e0, double escale, float* X) {
-    const int nin = 7 + nm;
+                                     Mesh mesh, int nm, int n_harm, double e0, double escale,
+                                     float* X) {
+    const int nin = n_features(nm, n_harm);
     int k0, k1, k2;
     mesh_triple(kmesh, mesh, k0, k1, k2);
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
@@ -413,15 +416,8 @@ __global__ void features_list_kernel(int32_t kmesh, double eps, const int32_t* l
         const int nu = (int)(r % nm);
         int a0, a1, a2;
         mesh_triple(q, mesh, a0, a1, a2);
-        float* x = X + i * nin;
-        x[0] = (float)((double)k0 / mesh.n0);
-        x[1] = (float)((double)k1 / mesh.n1);
-        x[2] = (float)((double)k2 / mesh.n2);
-        x[3] = (float)((eps - e0) / escale);
-        x[4] = (float)((double)a0 / mesh.n0);
-        x[5] = (float)((double)a1 / mesh.n1);
-        x[6] = (float)((double)a2 / mesh.n2);
-        for (int v = 0; v < nm; ++v) x[7 + v] = v == nu ? 1.f : 0.f;
+        write_features<float>(X + i * nin, k0, k1, k2, a0, a1, a2, nu, (eps - e0) / escale, mesh,
+                              nm, n_harm);
     }
 }
 
@@ -456,11 +452,11 @@ hipError_t launch_select(const double* D, int64_t n, const double* dmax, double 
     return hipGetLastError();
 }
 hipError_t launch_features_list(int32_t kmesh, double eps, const int32_t* list, int64_t n,
-                                Mesh mesh, int nm, double e0, double escale, float* X,
+                                Mesh mesh, int nm, int n_harm, double e0, double escale, float* X,
                                 hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(features_list_kernel, dim3(gridm(n, 256)), dim3(256), 0, s, kmesh, eps, list,
-                       n, mesh, nm, e0, escale, X);
+                       n, mesh, nm, n_harm, e0, escale, X);
     return hipGetLastError();
 }
 hipError_t launch_weight_list(const double* D, const int32_t* list, const float* y, int64_t n,

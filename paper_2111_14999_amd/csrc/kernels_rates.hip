@@ -18,24 +18,25 @@ static inline int grid1(int64_t n, int block) {
 }
 
 // ---------------------------------------------------------------------------
-// F[st, r, sa*nW + b] = sum_a conj(U_k[a, n]) G[kb, r, sa, a, b]
+// F[st, r, sa*cw + b] = sum_a conj(U_k[a, n]) G[kb, r, sa, a, b]
+// (cw = column width per mode index: nW for the direct sum, 16 for the
+// factorised one, whose rate kernel keeps one mode index per MFMA tile)
 // ---------------------------------------------------------------------------
 __global__ void fold_uk_kernel(const cd* __restrict__ G, int64_t ldg, const cd* __restrict__ U,
                                const int32_t* st_krow, int row0, const int32_t* st_kmesh,
-                               const int32_t* st_band, int nst, int n_rp, int nm, int nW,
+                               const int32_t* st_band, int nst, int n_rp, int nm, int nW, int cw,
                                int rp_pad, int nc_pad, cd* __restrict__ F) {
     const int64_t per = (int64_t)rp_pad * nc_pad;
     const int64_t total = (int64_t)nst * per;
-    const int nc = nm * nW;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
         const int st = (int)(t / per);
         const int64_t o = t - st * per;
         const int r = (int)(o / nc_pad);
         const int c = (int)(o - (int64_t)r * nc_pad);
+        const int sa = c / cw, b = c - sa * cw;
         cd acc = {0.0, 0.0};
-        if (r < n_rp && c < nc) {
-            const int sa = c / nW, b = c - sa * nW;
+        if (r < n_rp && sa < nm && b < nW) {
             const int n = st_band[st];
             const cd* Uk = U + (int64_t)st_kmesh[st] * nW * nW;
             const cd* Gk = G + (int64_t)(st_krow[st] - row0) * ldg + ((int64_t)r * nm + sa) * nW * nW + b;
@@ -47,11 +48,12 @@ __global__ void fold_uk_kernel(const cd* __restrict__ G, int64_t ldg, const cd* 
 
 hipError_t launch_fold_uk(const cd* G, int64_t ldg, const cd* U, const int32_t* st_krow,
                           int row0, const int32_t* st_kmesh, const int32_t* st_band, int nst, int n_rp,
-                          int nm, int nW, int rp_pad, int nc_pad, cd* F, hipStream_t s) {
+                          int nm, int nW, int cw, int rp_pad, int nc_pad, cd* F, hipStream_t s) {
     if (nst <= 0) return hipSuccess;
+    if (cw < nW || (int64_t)cw * nm > nc_pad) return hipErrorInvalidValue;
     hipLaunchKernelGGL(fold_uk_kernel, dim3(grid1((int64_t)nst * rp_pad * nc_pad, 256)), dim3(256),
-                       0, s, G, ldg, U, st_krow, row0, st_kmesh, st_band, nst, n_rp, nm, nW, rp_pad,
-                       nc_pad, F);
+                       0, s, G, ldg, U, st_krow, row0, st_kmesh, st_band, nst, n_rp, nm, nW, cw,
+                       rp_pad, nc_pad, F);
     return hipGetLastError();
 }
 

@@ -22,17 +22,16 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, 
                        double b1, double b2, double eps, hipStream_t s);
 template <class T>
 hipError_t launch_features(const int32_t* k_idx, const double* eps, const int32_t* q_idx,
-                           const int32_t* nu, int64_t B, Mesh mesh, int nm, double e0,
+                           const int32_t* nu, int64_t B, Mesh mesh, int nm, int n_harm, double e0,
                            double escale, T* X, hipStream_t s);
-hipError_t launch_features_grid(int32_t kmesh, double eps, int64_t q0, int64_t nq, Mesh mesh,
-                                int nm, double e0, double escale, float* X, hipStream_t s);
+int feature_count(int nm, int n_harm);
 hipError_t launch_proposal_raw(const float* y, int64_t nq, int nm, double c, double* p,
                                hipStream_t s);
 hipError_t launch_rowmax(const double* x, int64_t n, double* out, hipStream_t s);
 hipError_t launch_select(const double* D, int64_t n, const double* dmax, double thr, int32_t* list,
                          int32_t* count, hipStream_t s);
 hipError_t launch_features_list(int32_t kmesh, double eps, const int32_t* list, int64_t n,
-                                Mesh mesh, int nm, double e0, double escale, float* X,
+                                Mesh mesh, int nm, int n_harm, double e0, double escale, float* X,
                                 hipStream_t s);
 hipError_t launch_weight_list(const double* D, const int32_t* list, const float* y, int64_t n,
                               double* E, hipStream_t s);

@@ -14,6 +14,7 @@ from .systems import (  # noqa: F401
     config_c1,
     config_c2,
     small_system,
+    local_coupling_system,
     cscl_structure,
     perovskite_structure,
     random_structure,

