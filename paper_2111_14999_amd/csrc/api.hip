@@ -505,6 +505,8 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
         {
             Arena b1 = ar, b2 = ar;
             electron_bands_dev(h, b1, sys, T.rh, nullptr, nullptr, mesh, N, T.eps, T.U, s);
+            // the rate kernels read each eigenvector contiguously
+            HIPCHK(h, launch_transpose_batch(T.U, N, nW, s));
             phonon_dev(h, b2, sys, T.rd, nullptr, nullptr, mesh, N, par->omega_min, par->kT,
                        T.omega, T.E, T.nb, nullptr, s);
         }

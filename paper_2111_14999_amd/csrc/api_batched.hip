@@ -294,6 +294,8 @@ phoebe_status phoebe_gpu_batched_plan(void* handle, const phoebe_system* systems
             {
                 Arena b1(h->ws), b2(h->ws);
                 electron_bands_dev(h, b1, sys, p.rh, nullptr, nullptr, p.mesh, p.N, p.eps, p.U, s);
+                // the rate kernels read each eigenvector contiguously
+                HIPCHK(h, launch_transpose_batch(p.U, p.N, p.nW, s));
                 phonon_dev(h, b2, sys, p.rd, nullptr, nullptr, p.mesh, p.N, par->omega_min, par->kT,
                            p.omega, p.E, p.nb, nullptr, s);
             }

@@ -23,7 +23,7 @@ struct SysDesc {
     const double* focc;
     const double* omega;
     const double* nb;
-    const cd* U;
+    const cd* U;  // transposed: U[k, band, orbital]
     const cd* E;
     double sigma;
     double* partial;           // [states][n_qtiles]

@@ -49,6 +49,9 @@ hipError_t launch_band_extrema(const double* eps, int64_t nk, int nW, const doub
                                int64_t nq, int nm, double* bmin, double* bmax, double* wmax,
                                hipStream_t s);
 
+// In-place transpose of count n x n complex matrices.
+hipError_t launch_transpose_batch(cd* U, int64_t count, int n, hipStream_t s);
+
 // Stage-1 fold: F[st, r, sa*nW + b] = sum_a conj(U_k[a, n]) G[kb, r, sa, a, b]
 // for each state st = (kb, n); rows r >= n_rp and columns >= NC are zero.
 hipError_t launch_fold_uk(const cd* G, int64_t ldg, const cd* U, const int32_t* st_krow,
@@ -73,7 +76,7 @@ struct RateArgs {
     const double* q_w;
     const double* eps;         // [Nk, nW]
     const double* focc;        // [Nk, nW]
-    const cd* U;               // [Nk, nW, nW]
+    const cd* U;               // [Nk, nW, nW] transposed: U[k, band, orbital]
     const double* omega;       // [Nq, nm]
     const double* nb;          // [Nq, nm]
     const cd* E;               // [Nq, nm, nm] z * l

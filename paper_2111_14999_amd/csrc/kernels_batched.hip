@@ -132,10 +132,10 @@ __device__ void batched_tile(const SysDesc& d, int st, int qt, char* smem) {
             float yr = 0.f, yi = 0.f;
             if (kq >= 0) {
                 const cf* Xr = sX + c * ldf + sa * nW;
-                const cd* Uc = d.U + (int64_t)kq * nW * nW + m0 + mb;
+                const cd* Um = d.U + ((int64_t)kq * nW + m0 + mb) * nW;  // eigenvector m
                 for (int b = 0; b < nW; ++b) {
                     const cf x = Xr[b];
-                    const cd u = Uc[(int64_t)b * nW];
+                    const cd u = Um[b];
                     const float ur = (float)u.x, ui = (float)u.y;
                     yr = fmaf(x.x, ur, fmaf(-x.y, ui, yr));
                     yi = fmaf(x.x, ui, fmaf(x.y, ur, yi));

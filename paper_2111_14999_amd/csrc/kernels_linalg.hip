@@ -63,7 +63,7 @@ hipError_t launch_phase_table(const double* frac, const int32_t* idx, Mesh m, in
 // Complex product with 4 real MFMAs: Cr += Ar Br - Ai Bi, Ci += Ar Bi + Ai Br.
 // ---------------------------------------------------------------------------
 template <int TM, int TN>
-__global__ __launch_bounds__(256) void zgemm_kernel(const cd* __restrict__ A, int64_t lda,
+__global__ __launch_bounds__(256, 2) void zgemm_kernel(const cd* __restrict__ A, int64_t lda,
                                                     const cd* __restrict__ B, int64_t ldb,
                                                     cd* __restrict__ C, int64_t ldc, int64_t M,
                                                     int64_t N, int K) {
@@ -165,6 +165,32 @@ hipError_t launch_zgemm(const cd* A, int64_t lda, const cd* B, int64_t ldb, cd* 
         hipLaunchKernelGGL((zgemm_kernel<TM, TN>), grid, dim3(256), 0, s, A, lda, B, ldb, C, ldc,
                            M, N, K);
     }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// In-place transpose of a batch of n x n matrices: the rate path keeps each
+// eigenvector contiguous (Ut[k, band, orbital] = U_k[orbital, band]), so a
+// band's column is one coalesced read.
+// ---------------------------------------------------------------------------
+__global__ void transpose_batch_kernel(cd* U, int64_t count, int n) {
+    const int64_t total = count * n * n;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int j = (int)(t % n);
+        const int i = (int)((t / n) % n);
+        if (i >= j) continue;
+        const int64_t base = (t / ((int64_t)n * n)) * n * n;
+        const cd a = U[base + (int64_t)i * n + j];
+        U[base + (int64_t)i * n + j] = U[base + (int64_t)j * n + i];
+        U[base + (int64_t)j * n + i] = a;
+    }
+}
+
+hipError_t launch_transpose_batch(cd* U, int64_t count, int n, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(transpose_batch_kernel, dim3(grid_for(count * n * n, 256)), dim3(256), 0, s,
+                       U, count, n);
     return hipGetLastError();
 }
 

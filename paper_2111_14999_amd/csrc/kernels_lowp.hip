@@ -143,7 +143,7 @@ __global__ __launch_bounds__(256) void cgemm_f32_kernel(const cd* __restrict__ A
 // Split-BF16 complex GEMM, K blocks of 32.  Each lane gathers 8 consecutive k of
 // its A row and B column, rounds to FP32 and splits into NP pieces.
 template <int PREC, int TM, int TN, class TB>
-__global__ __launch_bounds__(256) void cgemm_bf16_kernel(const cd* __restrict__ A, int64_t lda,
+__global__ __launch_bounds__(256, 2) void cgemm_bf16_kernel(const cd* __restrict__ A, int64_t lda,
                                                          const TB* __restrict__ B, int64_t ldb,
                                                          cf* __restrict__ C, int64_t ldc,
                                                          int64_t M, int64_t N, int K) {
@@ -242,19 +242,15 @@ static hipError_t cgemm_lp(int prec, const cd* A, int64_t lda, const TB* B, int6
         else
             hipLaunchKernelGGL((cgemm_f32_kernel<4, 1, TB>), grid, dim3(256), 0, s, A, lda, B, ldb,
                                C, ldc, M, N, K);
-    } else if (prec == PHOEBE_BF16X3) {
-        if (TN == 2)
-            hipLaunchKernelGGL((cgemm_bf16_kernel<PHOEBE_BF16X3, 4, 2, TB>), grid, dim3(256), 0, s,
+    } else if (prec == PHOEBE_BF16X3 || prec == PHOEBE_BF16X6) {
+        // one column tile per wave keeps the split fragments within the
+        // register budget of two waves per SIMD
+        dim3 g1((unsigned)((N + 63) / 64), grid.y);
+        if (prec == PHOEBE_BF16X3)
+            hipLaunchKernelGGL((cgemm_bf16_kernel<PHOEBE_BF16X3, 4, 1, TB>), g1, dim3(256), 0, s,
                                A, lda, B, ldb, C, ldc, M, N, K);
         else
-            hipLaunchKernelGGL((cgemm_bf16_kernel<PHOEBE_BF16X3, 4, 1, TB>), grid, dim3(256), 0, s,
-                               A, lda, B, ldb, C, ldc, M, N, K);
-    } else if (prec == PHOEBE_BF16X6) {
-        if (TN == 2)
-            hipLaunchKernelGGL((cgemm_bf16_kernel<PHOEBE_BF16X6, 4, 2, TB>), grid, dim3(256), 0, s,
-                               A, lda, B, ldb, C, ldc, M, N, K);
-        else
-            hipLaunchKernelGGL((cgemm_bf16_kernel<PHOEBE_BF16X6, 4, 1, TB>), grid, dim3(256), 0, s,
+            hipLaunchKernelGGL((cgemm_bf16_kernel<PHOEBE_BF16X6, 4, 1, TB>), g1, dim3(256), 0, s,
                                A, lda, B, ldb, C, ldc, M, N, K);
     } else {
         return hipErrorInvalidValue;
@@ -301,10 +297,10 @@ __global__ void fold_uk_lp_kernel(const cf* __restrict__ G, int64_t ldg, const c
         if (r < n_rp && c < nc) {
             const int sa = c / nW, b = c - sa * nW;
             const int n = st_band[st];
-            const cd* Uk = U + (int64_t)st_kmesh[st] * nW * nW;
+            const cd* Un = U + ((int64_t)st_kmesh[st] * nW + n) * nW;  // eigenvector n
             const cf* Gk = G + (int64_t)(st_row[st] - row0) * ldg + ((int64_t)r * nm + sa) * nW * nW + b;
             for (int a = 0; a < nW; ++a) {
-                const cd u = Uk[a * nW + n];
+                const cd u = Un[a];
                 const cf g = Gk[a * nW];
                 const float ur = (float)u.x, ui = (float)u.y;
                 ar = fmaf(ur, g.x, fmaf(ui, g.y, ar));
@@ -554,10 +550,10 @@ __global__ __launch_bounds__(256, 2) void stage2_rates_lp_kernel(RateArgsLP a) {
                 float yr = 0.f, yi = 0.f;
                 if (kq >= 0) {
                     const cf* Xr = sX + cc * ldf + sa * nW;
-                    const cd* Uc = a.U + (int64_t)kq * nW * nW + m0 + mb;
+                    const cd* Um = a.U + ((int64_t)kq * nW + m0 + mb) * nW;  // eigenvector m
                     for (int b = 0; b < nW; ++b) {
                         const cf x = Xr[b];
-                        const cd u = Uc[(int64_t)b * nW];
+                        const cd u = Um[b];
                         const float ur = (float)u.x, ui = (float)u.y;
                         yr = fmaf(x.x, ur, fmaf(-x.y, ui, yr));
                         yi = fmaf(x.x, ui, fmaf(x.y, ur, yi));

@@ -257,7 +257,7 @@ __global__ __launch_bounds__(256, 2) void line_rates_kernel(RateArgs a) {
                 for (int v = 0; v < 4; ++v) {
                     cd u = {0.0, 0.0};
                     if (kqv[v] >= 0 && li < nW)
-                        u = a.U[((int64_t)kqv[v] * nW + li) * nW + m0 + mb];
+                        u = a.U[((int64_t)kqv[v] * nW + m0 + mb) * nW + li];  // eigenvector m
 #pragma unroll
                     for (int t = 0; t < TN; ++t) {
                         double yr = cr[t][v] * u.x - ci[t][v] * u.y;

@@ -18,7 +18,7 @@ static inline int grid1(int64_t n, int block) {
 }
 
 // ---------------------------------------------------------------------------
-// F[st, r, sa*cw + b] = sum_a conj(U_k[a, n]) G[kb, r, sa, a, b]
+// F[st, r, sa*cw + b] = sum_a conj(U_k[a, n]) G[kb, r, sa, a, b]   (U passed transposed)
 // (cw = column width per mode index: nW for the direct sum, 16 for the
 // factorised one, whose rate kernel keeps one mode index per MFMA tile)
 // ---------------------------------------------------------------------------
@@ -38,9 +38,9 @@ __global__ void fold_uk_kernel(const cd* __restrict__ G, int64_t ldg, const cd* 
         cd acc = {0.0, 0.0};
         if (r < n_rp && sa < nm && b < nW) {
             const int n = st_band[st];
-            const cd* Uk = U + (int64_t)st_kmesh[st] * nW * nW;
+            const cd* Un = U + ((int64_t)st_kmesh[st] * nW + n) * nW;  // eigenvector n
             const cd* Gk = G + (int64_t)(st_krow[st] - row0) * ldg + ((int64_t)r * nm + sa) * nW * nW + b;
-            for (int a = 0; a < nW; ++a) acc = cfmac(Uk[a * nW + n], Gk[a * nW], acc);
+            for (int a = 0; a < nW; ++a) acc = cfmac(Un[a], Gk[a * nW], acc);
         }
         F[t] = acc;
     }
@@ -242,8 +242,8 @@ __global__ __launch_bounds__(256, (TN >= 12 ? 1 : 2)) void stage2_rates_kernel(R
                 cd y = {0.0, 0.0};
                 if (kq >= 0) {
                     const cd* Xr = sX + c * ldf + sa * nW;
-                    const cd* Uc = a.U + (int64_t)kq * nW * nW + m0 + mb;
-                    for (int b = 0; b < nW; ++b) y = cfma(Xr[b], Uc[(int64_t)b * nW], y);
+                    const cd* Um = a.U + ((int64_t)kq * nW + m0 + mb) * nW;  // eigenvector m
+                    for (int b = 0; b < nW; ++b) y = cfma(Xr[b], Um[b], y);
                 }
                 sY[(c * kMB + mb) * nm + sa] = y;
             }
