@@ -90,6 +90,7 @@ struct RateArgs {
     const cd* T2;              // [nst, W, N1*N2, nc_pad]
     const cd* P0;              // [N0, W]
     int W;                     // 2 rmax + 1
+    int n_states;              // states of one launch (set by the launcher)
 };
 
 // Fused stage 2 (sum over Rp on MFMA) + rotations + rate terms.

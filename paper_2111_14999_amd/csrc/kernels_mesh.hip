@@ -14,6 +14,8 @@
 // (state, q1, q2) line of N0 points, followed by the same rotations and
 // smeared rate terms as the direct kernel; X never reaches memory.  The sum
 // is the same as the direct one up to the order of the additions.
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace phx {
@@ -167,10 +169,29 @@ hipError_t launch_axis_transforms(const cd* F, int rp_pad, int nc_pad, const int
 //   Y[q, sa, m] = sum_b X[q, sa, b] U_{k+q}[b, m]
 // is a product per lane and a sum over the 16 lanes of a row group, done in
 // registers.  Only Y (16 q x modes x final bands) goes through LDS to the
-// threads that apply E_q = z l and form the rate terms.  The grid runs over
-// states fastest, so the work-groups of one line (same E_q) run together.
+// threads that apply E_q = z l and form the rate terms.
 // ---------------------------------------------------------------------------
 constexpr int kMBL = 4;  // final bands per rotation pass
+
+// One DPP move of a double (two 32-bit halves) within each row of 16 lanes.
+template <int CTRL>
+__device__ inline double dpp_f64(double x) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Sum over the 16 lanes of a DPP row, left in every lane of the row: swap
+// neighbours and pairs within quads (quad_perm 1,0,3,2 and 2,3,0,1), then
+// add the mirrored half row and the mirrored row.
+__device__ inline double row16_sum(double x) {
+    x += dpp_f64<0xB1>(x);
+    x += dpp_f64<0x4E>(x);
+    x += dpp_f64<0x141>(x);
+    x += dpp_f64<0x140>(x);
+    return x;
+}
 
 template <int TN>
 __global__ __launch_bounds__(256, 2) void line_rates_kernel(RateArgs a) {
@@ -186,9 +207,17 @@ __global__ __launch_bounds__(256, 2) void line_rates_kernel(RateArgs a) {
     cd* sY = sP + N0p * Wp;                       // [16][kMBL][nm]
     __shared__ double sRed[4];
 
-    const int st = blockIdx.x;
-    const int line = blockIdx.y;
+    // XCD-aware order: work-groups are dealt to the 8 XCDs round-robin, so
+    // with id = 8 j + x every state of a line lands on XCD x, one after
+    // another, and the line's phonon tables E_q are fetched into one L2 once.
     const int NL = mesh.n1 * mesh.n2;
+    const int nst = a.n_states;
+    const int64_t id = blockIdx.x;
+    const int xcd = (int)(id & 7);
+    const int64_t j = id >> 3;
+    const int line = (int)((j / nst) * 8 + xcd);
+    const int st = (int)(j % nst);
+    if (line >= NL) return;
     const int q1 = line / mesh.n2, q2 = line - q1 * mesh.n2;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lg = lane >> 4;
@@ -213,6 +242,13 @@ __global__ __launch_bounds__(256, 2) void line_rates_kernel(RateArgs a) {
     __syncthreads();
 
     for (int qc = 0; qc < N0; qc += 16) {
+        // k+q of the four rows of this lane group
+        int kqv[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int q0 = qc + lg + 4 * v;
+            kqv[v] = q0 < N0 ? ((k0i + q0) % mesh.n0) * NL + kq12 : -1;
+        }
         d4 cr[TN], ci[TN];
 #pragma unroll
         for (int t = 0; t < TN; ++t) {
@@ -242,13 +278,6 @@ __global__ __launch_bounds__(256, 2) void line_rates_kernel(RateArgs a) {
                 ci[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ph.y, bc[t].x, ci[t], 0, 0, 0);
             }
         }
-        // final-band index of k+q for the four rows of this lane group
-        int kqv[4];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int q0 = qc + lg + 4 * v;
-            kqv[v] = q0 < N0 ? ((k0i + q0) % mesh.n0) * NL + kq12 : -1;
-        }
         for (int m0 = mlo; m0 <= mhi; m0 += kMBL) {
             const int nmb = min(kMBL, mhi - m0 + 1);
             // Y in registers: lane (li = b) product, then a sum over the 16 lanes
@@ -260,13 +289,8 @@ __global__ __launch_bounds__(256, 2) void line_rates_kernel(RateArgs a) {
                         u = a.U[((int64_t)kqv[v] * nW + m0 + mb) * nW + li];  // eigenvector m
 #pragma unroll
                     for (int t = 0; t < TN; ++t) {
-                        double yr = cr[t][v] * u.x - ci[t][v] * u.y;
-                        double yi = cr[t][v] * u.y + ci[t][v] * u.x;
-#pragma unroll
-                        for (int o = 8; o > 0; o >>= 1) {
-                            yr += __shfl_xor(yr, o, 64);
-                            yi += __shfl_xor(yi, o, 64);
-                        }
+                        const double yr = row16_sum(cr[t][v] * u.x - ci[t][v] * u.y);
+                        const double yi = row16_sum(cr[t][v] * u.y + ci[t][v] * u.x);
                         const int sa = wave * TN + t;
                         if (li == 0 && sa < nm)
                             sY[((lg + 4 * v) * kMBL + mb) * nm + sa] = cd{yr, yi};
@@ -329,8 +353,10 @@ static hipError_t go_line(const RateArgs& a, int nst, hipStream_t s) {
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) return e;
     const int64_t NL = (int64_t)a.mesh.n1 * a.mesh.n2;
-    for (int s0 = 0; s0 < nst; s0 += 65535) {
-        const int ns = nst - s0 < 65535 ? nst - s0 : 65535;
+    const int64_t groups = (NL + 7) / 8;
+    const int chunk = (int)std::min<int64_t>(65535, 2147483647LL / (groups * 8));
+    for (int s0 = 0; s0 < nst; s0 += chunk) {
+        const int ns = nst - s0 < chunk ? nst - s0 : chunk;
         RateArgs b = a;
         b.T2 = a.T2 + (int64_t)s0 * a.W * NL * a.nc_pad;
         b.st_kmesh += s0;
@@ -340,7 +366,9 @@ static hipError_t go_line(const RateArgs& a, int nst, hipStream_t s) {
         b.st_mhi += s0;
         b.partial = a.partial + (int64_t)s0 * a.n_qtiles;
         if (a.terms) b.terms = a.terms + (int64_t)s0 * a.nq_mesh * a.nm;
-        hipLaunchKernelGGL((line_rates_kernel<TN>), dim3(ns, (unsigned)NL), dim3(256), shm, s, b);
+        b.n_states = ns;
+        hipLaunchKernelGGL((line_rates_kernel<TN>), dim3((unsigned)(groups * 8 * ns)), dim3(256), shm,
+                           s, b);
     }
     return hipGetLastError();
 }
