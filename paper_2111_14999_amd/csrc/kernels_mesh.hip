@@ -236,6 +236,9 @@ __global__ __launch_bounds__(256, 2) void line_rates_kernel(RateArgs a) {
     const int q12 = q1 * mesh.n2 + q2;
     const double eps_n = a.eps[(int64_t)kmesh * nW + nband];
     const double inv_s2 = 1.0 / (a.sigma * a.sigma);
+    // |y| > 27.5 sigma: y^2/sigma^2 > 756 and exp(-756) is below the smallest
+    // FP64 subnormal, so such a Gaussian is exactly 0
+    const double cut = 27.5 * a.sigma;
     const int colbase = wave * TN * 16 + li;
     const cd* Tst = a.T2 + (int64_t)st * W * NL * ldf + (int64_t)line * ldf + colbase;
     double gacc = 0.0;
@@ -307,15 +310,18 @@ __global__ __launch_bounds__(256, 2) void line_rates_kernel(RateArgs a) {
                 if (q0 >= N0) continue;
                 const int64_t q = (int64_t)q0 * NL + q12;
                 const int64_t kq = (int64_t)((k0i + q0) % mesh.n0) * NL + kq12;
+                const int m = m0 + mb;
+                const double x = eps_n - a.eps[kq * nW + m];
+                const double w = a.omega[q * nm + nu];
+                const double y1 = x - w, y2 = x + w;
+                // both Gaussians underflow to exactly 0: the term is 0
+                if (fabs(y1) > cut && fabs(y2) > cut) continue;
+                const double fm = a.focc[kq * nW + m];
+                const double nbq = a.nb[q * nm + nu];
                 const cd* Yr = sY + (c * kMBL + mb) * nm;
                 const cd* Eq = a.E + q * nm * nm + nu;
                 cd z = {0.0, 0.0};
                 for (int sa = 0; sa < nm; ++sa) z = cfma(Eq[sa * nm], Yr[sa], z);
-                const int m = m0 + mb;
-                const double x = eps_n - a.eps[kq * nW + m];
-                const double fm = a.focc[kq * nW + m];
-                const double w = a.omega[q * nm + nu], nbq = a.nb[q * nm + nu];
-                const double y1 = x - w, y2 = x + w;
                 const double g1 = exp(-y1 * y1 * inv_s2), g2 = exp(-y2 * y2 * inv_s2);
                 const double term = cabs2(z) * ((nbq + 1.0 - fm) * g1 + (nbq + fm) * g2);
                 gacc += term;
