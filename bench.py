@@ -153,6 +153,8 @@ def main():
     # flops; rotations and rate terms are not counted):
     #   stage2_rates    direct sum over the Rp list: 8 N_q n_rp nModes nW per state
     #   stage1_phase    sum over Re: 8 n_re n_rp nModes nW^2 per kept k
+    #   stage1_axes     the same sum factorised over the Re box, HBM: g(Re,Rp) read
+    #                   once per batch and G written once per kept k
     #   line_rates      last axis of the factorised sum: 8 N_q W nModes nW per state
     #   axis_transforms first two axes, HBM traffic: 16 B nModes nW per state x
     #                   (n_rp read + 2 W^2 N2 for T1 + W N1 N2 for T2)
@@ -161,6 +163,8 @@ def main():
     work = {
         "stage2_rates": ("mfma", 8.0 * n_states * N * n_rp * nc),
         "stage1_phase": ("mfma", 8.0 * n_kept * n_re * n_rp * nm * nW * nW),
+        # factorised stage 1, HBM: g(Re,Rp) read once per batch, G written once per kept k
+        "stage1_axes": ("hbm", None),
         "line_rates": ("mfma", 8.0 * n_states * N * W * nc),
         "axis_transforms": ("hbm", 16.0 * nc * n_states *
                             (n_rp + 2 * W * W * mesh[2] + W * mesh[1] * mesh[2])),
@@ -168,11 +172,14 @@ def main():
     peak_mfma = {"fp64": PEAK_FP64_TFLOPS, "fp32": 157.3, "bf16x3": 2500.0 / 3,
                  "bf16x6": 2500.0 / 6}[args.precision]
     kernels = {}
+    g_bytes = 16.0 * n_re * n_rp * nm * nW * nW
     for name, (bound, amount) in work.items():
         n_l, ms = lib.kernel_time(name)
         if n_l == 0:
             continue
         lps = n_l / args.steps
+        if name == "stage1_axes":
+            amount = lps * g_bytes + n_kept * g_bytes / n_re
         avg_ms = ms / n_l
         per_launch = amount / lps
         if bound == "mfma":

@@ -1,5 +1,7 @@
 // C ABI of the library: argument validation, workspace, orchestration of the
 // kernels for the band structure, the coupling interpolation and the rates.
+#include <array>
+
 #include "host.hpp"
 
 using namespace phx;
@@ -374,7 +376,15 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
             throw Fail{PHOEBE_E_UNSUPPORTED};
         }
         // kept k points per stage-1 batch: G and F of a batch stay under 8 GB each
-        int BK = 64;
+        // Stage 1 takes the same per-axis factorisation over the Re box when the
+        // mesh sum is factorised (launch_re_axes); its batches are larger, limited
+        // by the distinct k0 and (k0, k1) values they hold (see below).
+        const int rmax_e = rmax_of(sys->re, n_re);
+        const int We = 2 * rmax_e + 1;
+        const bool re_fact = factored && rmax_e <= 15 &&
+                             (h->mesh_sum == PHOEBE_MESH_SUM_FACTORED || 2 * We <= n_re);
+        constexpr int kD0Max = 8, kD01Max = 64;
+        int BK = re_fact ? 256 : 64;
         while (BK > 16 && ((double)BK * NC2 * g_elem > 8e9 ||
                            (double)BK * nW * rp_pad * nc_pad * f_elem > 8e9))
             BK /= 2;
@@ -420,8 +430,8 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
             uint8_t* mask;
             int32_t *flag, *kept, *cnt, *rowflag, *ids;
             int32_t *st_row, *st_band, *st_kmesh, *st_mlo, *st_mhi;
-            int32_t* box_rp;
-            cd* Pax;
+            int32_t *box_rp, *box_re;
+            cd *Pax, *Pre;
         } T{};
         const int64_t rows_cap = k_idx ? nk : N;
         auto plan_tables = [&](Arena& ar) {
@@ -454,6 +464,10 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                 T.box_rp = ar.take<int32_t>((size_t)Wbox * Wbox * Wbox);
                 T.Pax = ar.take<cd>((size_t)(mesh.n0 + mesh.n1 + mesh.n2) * Wbox);
             }
+            if (re_fact) {
+                T.box_re = ar.take<int32_t>((size_t)We * We * We);
+                T.Pre = ar.take<cd>((size_t)(mesh.n0 + mesh.n1 + mesh.n2) * We);
+            }
         };
         // band scratch is carved after the tables and reused by the batches
         size_t tables_end = 0, scratch_bands = 0;
@@ -473,7 +487,11 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                                    (size_t)BK * NC2 * g_elem +
                                    (size_t)max_states * rp_pad * nc_pad * f_elem +
                                    (size_t)max_states * n_qtiles * sizeof(double) +
-                                   (factored ? (size_t)nsb * t12_state + 512 : 0);
+                                   (factored ? (size_t)nsb * t12_state + 512 : 0) +
+                                   (re_fact ? ((size_t)kD0Max * We * We + (size_t)kD01Max * We) *
+                                                      NC2 * sizeof(cd) +
+                                                  (size_t)rows_cap * 160 * sizeof(int32_t) + 1024
+                                            : 0);
         ensure_ws(h, tables_end + std::max(scratch_bands, batch_bytes) + 256);
         Arena ar(h->ws);
         plan_tables(ar);
@@ -498,6 +516,21 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                 HIPCHK(h, hipMemcpyAsync(T.box_rp, box.data(), sizeof(int32_t) * box.size(),
                                          hipMemcpyHostToDevice, s));
                 HIPCHK(h, launch_axis_phases(mesh, rmax_p, T.Pax, s));
+            }
+            std::vector<int32_t> box_e;
+            if (re_fact) {
+                // box position of Re -> row of g(Re, Rp) (-1: no such Re)
+                box_e.assign((size_t)We * We * We, -1);
+                for (int i = 0; i < n_re; ++i) {
+                    const int64_t b = ((int64_t)(sys->re[3 * i] + rmax_e) * We +
+                                       (sys->re[3 * i + 1] + rmax_e)) * We +
+                                      (sys->re[3 * i + 2] + rmax_e);
+                    REQUIRE(h, box_e[b] < 0, "Re list holds a vector twice");
+                    box_e[b] = i;
+                }
+                HIPCHK(h, hipMemcpyAsync(T.box_re, box_e.data(), sizeof(int32_t) * box_e.size(),
+                                         hipMemcpyHostToDevice, s));
+                HIPCHK(h, launch_axis_phases(mesh, rmax_e, T.Pre, s));
             }
             // the host vector must outlive the copy
             HIPCHK(h, hipStreamSynchronize(s));
@@ -569,7 +602,89 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                                  hipMemcpyDeviceToHost, s));
         HIPCHK(h, hipStreamSynchronize(s));
 
-        // ---- phase B: batches of BK rows ----
+        // ---- phase B: batches of kept-k rows ----
+        // Direct stage 1: BK rows each.  Factorised stage 1: consecutive rows
+        // while the batch holds at most BK rows, kD0Max distinct k0 and kD01Max
+        // distinct (k0, k1), with the grouping lists the three axis kernels use.
+        std::vector<std::pair<int64_t, int64_t>> batches;
+        std::vector<int32_t> rbh;          // grouping lists of every batch, one array
+        std::vector<std::array<int64_t, 8>> rbo;  // per batch: d0, d01, offsets of the 6 lists
+        if (!re_fact) {
+            for (int64_t r0 = 0; r0 < rows; r0 += BK) batches.push_back({r0, std::min<int64_t>(BK, rows - r0)});
+        } else {
+            std::vector<int32_t> kh(rows);
+            HIPCHK(h, hipMemcpyAsync(kh.data(), kept, sizeof(int32_t) * rows, hipMemcpyDeviceToHost, s));
+            HIPCHK(h, hipStreamSynchronize(s));
+            const int64_t n12 = (int64_t)mesh.n1 * mesh.n2;
+            int64_t r = 0;
+            while (r < rows) {
+                std::vector<int32_t> k0s, prs;  // distinct k0 and pair ids k0 n1 + k1
+                int64_t e = r;
+                while (e < rows && e - r < BK) {
+                    const int32_t k0 = (int32_t)(kh[e] / n12);
+                    const int32_t pr = (int32_t)(kh[e] / mesh.n2);
+                    const bool n0 = std::find(k0s.begin(), k0s.end(), k0) == k0s.end();
+                    const bool n01 = std::find(prs.begin(), prs.end(), pr) == prs.end();
+                    if ((int)k0s.size() + n0 > kD0Max || (int)prs.size() + n01 > kD01Max) break;
+                    if (n0) k0s.push_back(k0);
+                    if (n01) prs.push_back(pr);
+                    ++e;
+                }
+                std::sort(k0s.begin(), k0s.end());
+                std::sort(prs.begin(), prs.end());
+                const int d0 = (int)k0s.size(), d01 = (int)prs.size();
+                const int64_t nb = e - r;
+                std::array<int64_t, 8> o{};
+                o[0] = d0;
+                o[1] = d01;
+                // d_k0
+                o[2] = (int64_t)rbh.size();
+                rbh.insert(rbh.end(), k0s.begin(), k0s.end());
+                // pair_k1 and pair_off (pairs are sorted by k0, then k1)
+                o[3] = (int64_t)rbh.size();
+                for (int32_t pr : prs) rbh.push_back(pr % mesh.n1);
+                o[4] = (int64_t)rbh.size();
+                {
+                    int pp = 0;
+                    for (int d = 0; d <= d0; ++d) {
+                        while (d < d0 && pp < d01 && prs[pp] / mesh.n1 < k0s[d]) ++pp;
+                        rbh.push_back(pp);
+                    }
+                    rbh[o[4] + d0] = d01;
+                }
+                // rows grouped by pair: kp_off, k_row (batch-local), k_k2
+                std::vector<std::vector<int32_t>> byp(d01);
+                for (int64_t i = r; i < e; ++i) {
+                    const int32_t pr = (int32_t)(kh[i] / mesh.n2);
+                    const int pidx = (int)(std::lower_bound(prs.begin(), prs.end(), pr) - prs.begin());
+                    byp[pidx].push_back((int32_t)(i - r));
+                }
+                o[5] = (int64_t)rbh.size();
+                {
+                    int32_t acc = 0;
+                    for (int pp = 0; pp < d01; ++pp) {
+                        rbh.push_back(acc);
+                        acc += (int32_t)byp[pp].size();
+                    }
+                    rbh.push_back(acc);
+                }
+                o[6] = (int64_t)rbh.size();
+                for (int pp = 0; pp < d01; ++pp) rbh.insert(rbh.end(), byp[pp].begin(), byp[pp].end());
+                o[7] = (int64_t)rbh.size();
+                for (int pp = 0; pp < d01; ++pp)
+                    for (int32_t lr : byp[pp]) rbh.push_back((int32_t)(kh[r + lr] % mesh.n2));
+                rbo.push_back(o);
+                batches.push_back({r, nb});
+                r = e;
+            }
+            REQUIRE(h, rbh.size() <= (size_t)rows_cap * 160, "stage-1 grouping lists too long");
+        }
+        int32_t* rbd = re_fact ? ar.take<int32_t>(std::max<size_t>(rbh.size(), 1)) : nullptr;
+        if (re_fact)
+            HIPCHK(h, hipMemcpyAsync(rbd, rbh.data(), sizeof(int32_t) * rbh.size(),
+                                     hipMemcpyHostToDevice, s));
+        cd* T0re = re_fact ? ar.take<cd>((size_t)kD0Max * We * We * NC2) : nullptr;
+        cd* T1re = re_fact ? ar.take<cd>((size_t)kD01Max * We * NC2) : nullptr;
         cd* P1 = ar.take<cd>((size_t)BK * n_re);
         char* Gbuf = ar.take<char>((size_t)BK * NC2 * g_elem);
         char* Fbuf = ar.take<char>((size_t)max_states * rp_pad * nc_pad * f_elem);
@@ -580,12 +695,22 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
         const double inv_sqrtpi_sigma = 1.0 / (std::sqrt(kPi) * par->sigma);
         const double scale = 2.0 * kPi * inv_sqrtpi_sigma * (q_off ? 1.0 : 1.0 / (double)N);
         int sbeg = 0;
-        for (int64_t r0 = 0; r0 < rows; r0 += BK) {
-            const int64_t nb = std::min<int64_t>(BK, rows - r0);
+        for (size_t bi = 0; bi < batches.size(); ++bi) {
+            const int64_t r0 = batches[bi].first, nb = batches[bi].second;
             int send = sbeg;
             while (send < nst && strow[send] < r0 + nb) ++send;
             const int ns = send - sbeg;
             if (ns == 0) continue;
+            if (re_fact) {
+                const auto& o = rbo[bi];
+                ReBatch rb{(int)o[0], (int)o[1], rbd + o[2], rbd + o[3], rbd + o[4],
+                           rbd + o[5], rbd + o[6], rbd + o[7]};
+                Timer t1(h, s, "stage1_axes");
+                HIPCHK(h, launch_re_axes(reinterpret_cast<const cd*>(sys->g_rr), NC2, T.box_re,
+                                         rmax_e, mesh, T.Pre, rb, T0re, T1re,
+                                         reinterpret_cast<cd*>(Gbuf), NC2, s));
+                t1.done();
+            } else {
             HIPCHK(h, launch_phase_table(nullptr, kept + r0, mesh, nb, T.re, n_re, P1, n_re, s));
             Timer t1(h, s, "stage1_phase");
             if (lowp)
@@ -595,6 +720,7 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                 HIPCHK(h, launch_zgemm(P1, n_re, reinterpret_cast<const cd*>(sys->g_rr), NC2,
                                        reinterpret_cast<cd*>(Gbuf), NC2, nb, NC2, n_re, s));
             t1.done();
+            }
             if (lowp)
                 HIPCHK(h, launch_fold_uk_lp(prec, reinterpret_cast<const cf*>(Gbuf), NC2, T.U,
                                             T.st_row + sbeg, (int)r0, T.st_kmesh + sbeg,

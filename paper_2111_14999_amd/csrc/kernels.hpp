@@ -102,6 +102,18 @@ hipError_t launch_axis_phases(Mesh m, int rmax, cd* P, hipStream_t s);
 hipError_t launch_axis_transforms(const cd* F, int rp_pad, int nc_pad, const int32_t* box_rp,
                                   int rmax, Mesh m, const cd* P, int nst, cd* T1, cd* T2,
                                   hipStream_t s);
+// Stage 1 factorised over the axes of the Re box for one batch of kept k.
+// Device lists: d_k0 [d0] distinct k0; pair_k1 [d01] and pair_off [d0+1] the
+// distinct (k0, k1) pairs grouped by k0; kp_off [d01+1], k_row, k_k2 [nb] the
+// batch rows (and their k2) grouped by pair.
+struct ReBatch {
+    int d0, d01;
+    const int32_t *d_k0, *pair_k1, *pair_off, *kp_off, *k_row, *k_k2;
+};
+hipError_t launch_re_axes(const cd* g, int64_t NC, const int32_t* box_re, int rmax, Mesh m,
+                          const cd* P, const ReBatch& b, cd* T0, cd* T1, cd* G, int64_t ldg,
+                          hipStream_t s);
+
 // Axis 0 on MFMA + rotations + rate terms, one work-group per (state, q1, q2) line.
 // Columns sa*16 + b (nW <= 16), nc_pad = 64 TN with 4 TN >= nModes.
 hipError_t launch_line_rates(const RateArgs& a, int nst, hipStream_t s);

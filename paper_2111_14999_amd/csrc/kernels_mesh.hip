@@ -159,6 +159,145 @@ hipError_t launch_axis_transforms(const cd* F, int rp_pad, int nc_pad, const int
 }
 
 // ---------------------------------------------------------------------------
+// Stage 1 (sum over Re at the kept k of a batch), factorised the same way.
+// The kept k are mesh points, so e^{i2pi k.Re} = P0[k0, R0] P1[k1, R1]
+// P2[k2, R2]; with Re embedded in its box (box_re: box position -> row of
+// g(Re, Rp), -1 where the list has no vector) the sum is taken one axis at a
+// time over the distinct k0 of the batch, then the distinct (k0, k1) pairs,
+// then each k:
+//   T0[d, R1 R2, c] = sum_R0 P0[k0_d, R0] g[R0 R1 R2, c]          (streams g once)
+//   T1[p, R2, c]    = sum_R1 P1[k1_p, R1] T0[d(p), R1 R2, c]
+//   G[row, c]       = sum_R2 P2[k2, R2] T1[p(row), R2, c]
+// with c over the n_rp nModes nW^2 columns of g.
+// ---------------------------------------------------------------------------
+template <int WT>
+__global__ __launch_bounds__(256) void re_axis0_kernel(const cd* __restrict__ g, int64_t NC,
+                                                       const int32_t* __restrict__ box_re, int Wr,
+                                                       const cd* __restrict__ P0,
+                                                       const int32_t* __restrict__ d_k0, int d0,
+                                                       cd* __restrict__ T0) {
+    constexpr int NV = WT > 0 ? WT : kMaxW;
+    const int W = WT > 0 ? WT : Wr;
+    const int64_t W2 = (int64_t)W * W;
+    const int64_t total = W2 * NC;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = t % NC;
+        const int64_t p = t / NC;
+        cd v[NV];
+#pragma unroll
+        for (int r = 0; r < NV; ++r)
+            if (r < W) {
+                const int row = box_re[r * W2 + p];
+                v[r] = row >= 0 ? g[(int64_t)row * NC + c] : cd{0.0, 0.0};
+            }
+        for (int d = 0; d < d0; ++d) {
+            const cd* Pk = P0 + (int64_t)d_k0[d] * W;
+            cd acc = {0.0, 0.0};
+#pragma unroll
+            for (int r = 0; r < NV; ++r)
+                if (r < W) acc = cfma(Pk[r], v[r], acc);
+            T0[((int64_t)d * W2 + p) * NC + c] = acc;
+        }
+    }
+}
+
+template <int WT>
+__global__ __launch_bounds__(256) void re_axis1_kernel(const cd* __restrict__ T0, int64_t NC, int Wr,
+                                                       const cd* __restrict__ P1,
+                                                       const int32_t* __restrict__ pair_k1,
+                                                       const int32_t* __restrict__ pair_off, int d0,
+                                                       cd* __restrict__ T1) {
+    constexpr int NV = WT > 0 ? WT : kMaxW;
+    const int W = WT > 0 ? WT : Wr;
+    const int64_t total = (int64_t)d0 * W * NC;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = t % NC;
+        const int64_t dr = t / NC;  // d * W + R2
+        const int r2 = (int)(dr % W);
+        const int d = (int)(dr / W);
+        cd v[NV];
+        const cd* src = T0 + ((int64_t)d * W * W + r2) * NC + c;
+#pragma unroll
+        for (int r = 0; r < NV; ++r)
+            if (r < W) v[r] = src[(int64_t)r * W * NC];
+        for (int pp = pair_off[d]; pp < pair_off[d + 1]; ++pp) {
+            const cd* Pk = P1 + (int64_t)pair_k1[pp] * W;
+            cd acc = {0.0, 0.0};
+#pragma unroll
+            for (int r = 0; r < NV; ++r)
+                if (r < W) acc = cfma(Pk[r], v[r], acc);
+            T1[((int64_t)pp * W + r2) * NC + c] = acc;
+        }
+    }
+}
+
+template <int WT>
+__global__ __launch_bounds__(256) void re_axis2_kernel(const cd* __restrict__ T1, int64_t NC, int Wr,
+                                                       const cd* __restrict__ P2,
+                                                       const int32_t* __restrict__ kp_off,
+                                                       const int32_t* __restrict__ k_row,
+                                                       const int32_t* __restrict__ k_k2, int d01,
+                                                       cd* __restrict__ G, int64_t ldg) {
+    constexpr int NV = WT > 0 ? WT : kMaxW;
+    const int W = WT > 0 ? WT : Wr;
+    const int64_t total = (int64_t)d01 * NC;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = t % NC;
+        const int pp = (int)(t / NC);
+        cd v[NV];
+        const cd* src = T1 + (int64_t)pp * W * NC + c;
+#pragma unroll
+        for (int r = 0; r < NV; ++r)
+            if (r < W) v[r] = src[(int64_t)r * NC];
+        for (int i = kp_off[pp]; i < kp_off[pp + 1]; ++i) {
+            const cd* Pk = P2 + (int64_t)k_k2[i] * W;
+            cd acc = {0.0, 0.0};
+#pragma unroll
+            for (int r = 0; r < NV; ++r)
+                if (r < W) acc = cfma(Pk[r], v[r], acc);
+            G[(int64_t)k_row[i] * ldg + c] = acc;
+        }
+    }
+}
+
+template <int WT>
+static hipError_t go_re_axes(const cd* g, int64_t NC, const int32_t* box_re, int W, Mesh m,
+                             const cd* P, const ReBatch& b, cd* T0, cd* T1, cd* G, int64_t ldg,
+                             hipStream_t s) {
+    const cd* P1 = P + (int64_t)m.n0 * W;
+    const cd* P2 = P1 + (int64_t)m.n1 * W;
+    hipLaunchKernelGGL(re_axis0_kernel<WT>, dim3(gridm((int64_t)W * W * NC, 256)), dim3(256), 0, s,
+                       g, NC, box_re, W, P, b.d_k0, b.d0, T0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(re_axis1_kernel<WT>, dim3(gridm((int64_t)b.d0 * W * NC, 256)), dim3(256), 0,
+                       s, T0, NC, W, P1, b.pair_k1, b.pair_off, b.d0, T1);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(re_axis2_kernel<WT>, dim3(gridm((int64_t)b.d01 * NC, 256)), dim3(256), 0, s,
+                       T1, NC, W, P2, b.kp_off, b.k_row, b.k_k2, b.d01, G, ldg);
+    return hipGetLastError();
+}
+
+hipError_t launch_re_axes(const cd* g, int64_t NC, const int32_t* box_re, int rmax, Mesh m,
+                          const cd* P, const ReBatch& b, cd* T0, cd* T1, cd* G, int64_t ldg,
+                          hipStream_t s) {
+    const int W = 2 * rmax + 1;
+    if (W > kMaxW || b.d0 <= 0 || b.d01 <= 0) return hipErrorInvalidValue;
+    switch (W) {
+        case 1: return go_re_axes<1>(g, NC, box_re, W, m, P, b, T0, T1, G, ldg, s);
+        case 3: return go_re_axes<3>(g, NC, box_re, W, m, P, b, T0, T1, G, ldg, s);
+        case 5: return go_re_axes<5>(g, NC, box_re, W, m, P, b, T0, T1, G, ldg, s);
+        case 7: return go_re_axes<7>(g, NC, box_re, W, m, P, b, T0, T1, G, ldg, s);
+        case 9: return go_re_axes<9>(g, NC, box_re, W, m, P, b, T0, T1, G, ldg, s);
+        default: return go_re_axes<0>(g, NC, box_re, W, m, P, b, T0, T1, G, ldg, s);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Last axis on MFMA + rotations + rate terms.  Work-group = one state x one
 // (q1, q2) line; the N0 points of the line are taken 16 at a time.  Lane l
 // holds A[l%16][l/16] = P0[q0, R0] and B[l/16][l%16] = T2[R0, line, col];

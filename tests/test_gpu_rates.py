@@ -164,7 +164,17 @@ def _sparse_rp(s, seed, keep_frac):
     return s
 
 
-@pytest.mark.parametrize("case", ["toy", "ragged-5x6x7", "sparse-rp", "c2-tiling", "single-line"])
+def _sparse_re(s, seed, keep_frac):
+    """The same system with a random subset of its Re vectors."""
+    rng = np.random.default_rng(seed)
+    keep = np.sort(rng.choice(len(s.re), size=max(1, int(keep_frac * len(s.re))), replace=False))
+    s.re = np.ascontiguousarray(s.re[keep])
+    s.g_rr = np.ascontiguousarray(s.g_rr[keep])
+    return s
+
+
+@pytest.mark.parametrize("case", ["toy", "ragged-5x6x7", "sparse-rp", "sparse-re", "c2-tiling",
+                                  "single-line"])
 def test_mesh_sum_forms_match_oracle(lib, toy, case):
     if case == "toy":
         s, mesh, par, ref = toy
@@ -173,6 +183,8 @@ def test_mesh_sum_forms_match_oracle(lib, toy, case):
             s, mesh = synth.small_system(71, n_wannier=5, n_atoms=2, r=2), (5, 6, 7)
         elif case == "sparse-rp":
             s, mesh = _sparse_rp(synth.small_system(72, n_wannier=4, n_atoms=2, r=2), 5, 0.4), (6, 4, 5)
+        elif case == "sparse-re":
+            s, mesh = _sparse_re(synth.small_system(75, n_wannier=4, n_atoms=2, r=2), 6, 0.3), (5, 4, 6)
         elif case == "c2-tiling":
             s, mesh = synth.small_system(73, n_wannier=16, n_atoms=5, r=1), (17, 3, 2)
         else:
@@ -194,6 +206,21 @@ def test_mesh_sum_forms_match_oracle(lib, toy, case):
     gd, gf = out["direct"][1], out["factored"][1]
     scale = max(np.max(np.abs(gd)), 1e-300)
     assert np.max(np.abs(gd - gf)) < 1e-12 * scale
+
+
+def test_mesh_sum_forms_unsorted_k_list(lib, toy):
+    """Explicit k rows in no particular order over the full q mesh, both forms."""
+    s, mesh, par, _ = toy
+    k_idx = np.array([77, 5, 215, 0, 100, 3, 36, 37, 180, 1], dtype=np.int64)
+    ref = rates.scattering_rates(s, mesh, k_idx=k_idx, **par)
+    out = {}
+    try:
+        for mode in ("direct", "factored"):
+            lib.set_mesh_sum(mode)
+            out[mode] = _gpu_rates(lib, s, mesh, par, k_idx=k_idx)
+            _check(*out[mode], ref)
+    finally:
+        lib.set_mesh_sum("auto")
 
 
 def test_mesh_sum_mode_errors(lib, toy):
