@@ -781,6 +781,7 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
             } else {
                 ra.P0 = T.Pax;
                 ra.W = Wbox;
+                ra.wmax = T.wmax;
                 for (int sb = 0; sb < ns; sb += nsb) {
                     const int nn = std::min(nsb, ns - sb);
                     Timer ta(h, s, "axis_transforms");

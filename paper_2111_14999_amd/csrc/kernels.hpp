@@ -91,6 +91,7 @@ struct RateArgs {
     const cd* P0;              // [N0, W]
     int W;                     // 2 rmax + 1
     int n_states;              // states of one launch (set by the launcher)
+    const double* wmax;        // device scalar: largest phonon energy on the mesh
 };
 
 // Fused stage 2 (sum over Rp on MFMA) + rotations + rate terms.

@@ -383,7 +383,17 @@ __global__ __launch_bounds__(256, 2) void line_rates_kernel(RateArgs a) {
     double gacc = 0.0;
     __syncthreads();
 
+    const double wmax = *a.wmax;
     for (int qc = 0; qc < N0; qc += 16) {
+        // A chunk whose 16 points all have |eps_n - eps_{m,k+q}| > cut + max omega
+        // for every final band m has only exactly-zero terms: skip it whole.
+        int live = 0;
+        if (tid < 16 && qc + tid < N0) {
+            const int64_t kq = (int64_t)((k0i + qc + tid) % mesh.n0) * NL + kq12;
+            for (int m = mlo; m <= mhi; ++m)
+                live |= fabs(eps_n - a.eps[kq * nW + m]) <= cut + wmax;
+        }
+        if (!__syncthreads_or(live)) continue;
         // k+q of the four rows of this lane group
         int kqv[4];
 #pragma unroll
