@@ -154,7 +154,7 @@ def main():
     #   stage2_rates    direct sum over the Rp list: 8 N_q n_rp nModes nW per state
     #   stage1_phase    sum over Re: 8 n_re n_rp nModes nW^2 per kept k
     #   stage1_axes     the same sum factorised over the Re box, HBM: g(Re,Rp) read
-    #                   once per batch and G written once per kept k
+    #                   once per batch, intermediates once each way, G once
     #   line_rates      last axis of the factorised sum: 8 N_q W nModes nW per state
     #   axis_transforms first two axes, HBM traffic: 16 B nModes nW per state x
     #                   (n_rp read + 2 W^2 N2 for T1 + W N1 N2 for T2)
@@ -163,7 +163,8 @@ def main():
     work = {
         "stage2_rates": ("mfma", 8.0 * n_states * N * n_rp * nc),
         "stage1_phase": ("mfma", 8.0 * n_kept * n_re * n_rp * nm * nW * nW),
-        # factorised stage 1, HBM: g(Re,Rp) read once per batch, G written once per kept k
+        # factorised stage 1, HBM: g(Re,Rp) read once per batch, its two intermediates
+        # written and read once, G written once (bytes recorded by the library)
         "stage1_axes": ("hbm", None),
         "line_rates": ("mfma", 8.0 * n_states * N * W * nc),
         "axis_transforms": ("hbm", 16.0 * nc * n_states *
@@ -179,7 +180,8 @@ def main():
             continue
         lps = n_l / args.steps
         if name == "stage1_axes":
-            amount = lps * g_bytes + n_kept * g_bytes / n_re
+            # the library records each batch's bytes (g, both intermediates, G)
+            amount = lib.kernel_bytes(name) / args.steps
         avg_ms = ms / n_l
         per_launch = amount / lps
         if bound == "mfma":

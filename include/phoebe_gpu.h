@@ -347,12 +347,17 @@ phoebe_status phoebe_gpu_set_mesh_sum(void *handle, int32_t mode);
 /* Kernel timing for measurement: when enabled, the named hot kernels are
  * bracketed by HIP events on the stream they run on; phoebe_gpu_kernel_time
  * returns the number of timed launches and their summed duration since the
- * last reset.  Names: "stage2_rates" (direct sum), "stage1_phase",
- * "axis_transforms" and "line_rates" (factorised sum), "bands_fft", "eig_jacobi".  Timing synchronises the stream at the end of each call. */
+ * last reset.  Names: "stage2_rates" (direct sum), "stage1_phase" (direct sum over
+ * Re), "stage1_axes" (factorised sum over Re), "axis_transforms" and "line_rates"
+ * (factorised sum over Rp), "bands_fft", "eig_jacobi".  Timing synchronises the stream at the end of each call. */
 phoebe_status phoebe_gpu_set_timing(void *handle, int enable);
 phoebe_status phoebe_gpu_kernel_time(void *handle, const char *name,
                                      int64_t *launches, double *total_ms);
 phoebe_status phoebe_gpu_reset_timing(void *handle);
+/* Algorithmic HBM bytes the library recorded for the timed launches of a
+ * kernel since the last reset (0 where it records none; "stage1_axes" records
+ * the g(Re,Rp) read, its two intermediates written and read once, and G). */
+phoebe_status phoebe_gpu_kernel_bytes(void *handle, const char *name, double *bytes);
 
 #ifdef __cplusplus
 }

@@ -35,7 +35,7 @@ EXPORTS = (
     "phoebe_gpu_batched_destroy", "phoebe_gpu_rate_terms", "phoebe_gpu_mlp_param_count",
     "phoebe_gpu_mlp_forward", "phoebe_gpu_mlp_grad", "phoebe_gpu_mlp_adam",
     "phoebe_gpu_mlp_features", "phoebe_gpu_propose_q", "phoebe_gpu_delta_weights",
-    "phoebe_gpu_set_mesh_sum", "phoebe_gpu_mlp_feature_count",
+    "phoebe_gpu_set_mesh_sum", "phoebe_gpu_mlp_feature_count", "phoebe_gpu_kernel_bytes",
 )
 
 
@@ -90,6 +90,7 @@ def load(path: str = LIB_PATH):
                                              vp, vp, vp, ctypes.POINTER(i64), vp]
     lib.phoebe_gpu_set_timing.argtypes = [vp, ctypes.c_int]
     lib.phoebe_gpu_set_mesh_sum.argtypes = [vp, i32]
+    lib.phoebe_gpu_kernel_bytes.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double)]
     lib.phoebe_gpu_reset_timing.argtypes = [vp]
     lib.phoebe_gpu_kernel_time.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(i64),
                                            ctypes.POINTER(ctypes.c_double)]
@@ -368,6 +369,12 @@ class Library:
         self._check(self.lib.phoebe_gpu_kernel_time(self.handle, name.encode(), ctypes.byref(n),
                                                     ctypes.byref(ms)))
         return int(n.value), float(ms.value)
+
+    def kernel_bytes(self, name: str) -> float:
+        """Algorithmic HBM bytes recorded for the named kernel's timed launches."""
+        b = ctypes.c_double(0.0)
+        self._check(self.lib.phoebe_gpu_kernel_bytes(self.handle, name.encode(), ctypes.byref(b)))
+        return float(b.value)
 
 
 class BatchedPlan:

@@ -112,6 +112,15 @@ phoebe_status phoebe_gpu_kernel_time(void* handle, const char* name, int64_t* la
     return PHOEBE_OK;
 }
 
+phoebe_status phoebe_gpu_kernel_bytes(void* handle, const char* name, double* bytes) {
+    if (!handle || !name || !bytes) return PHOEBE_E_INVALID;
+    Handle* h = static_cast<Handle*>(handle);
+    *bytes = 0.0;
+    for (auto& k : h->stats)
+        if (k.name == name) *bytes = k.bytes;
+    return PHOEBE_OK;
+}
+
 phoebe_status phoebe_gpu_electron_bands(void* handle, const phoebe_system* sys,
                                         const double* k_frac, int64_t nk, double* eps_out,
                                         phoebe_c128* u_out, void* stream) {
@@ -709,7 +718,9 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                 HIPCHK(h, launch_re_axes(reinterpret_cast<const cd*>(sys->g_rr), NC2, T.box_re,
                                          rmax_e, mesh, T.Pre, rb, T0re, T1re,
                                          reinterpret_cast<cd*>(Gbuf), NC2, s));
-                t1.done();
+                // g read once; T0 and T1 written and read once; G written once
+                t1.done(16.0 * (double)NC2 *
+                        ((double)n_re + 2.0 * rb.d0 * We * We + 2.0 * rb.d01 * We + (double)nb));
             } else {
             HIPCHK(h, launch_phase_table(nullptr, kept + r0, mesh, nb, T.re, n_re, P1, n_re, s));
             Timer t1(h, s, "stage1_phase");

@@ -23,12 +23,14 @@ extern std::string g_create_error;
 struct TimedLaunch {
     std::string name;
     hipEvent_t start, stop;
+    double bytes = 0.0;  // algorithmic HBM bytes of the launch, where the host knows them
 };
 
 struct KernelStat {
     std::string name;
     int64_t launches = 0;
     double total_ms = 0.0;
+    double bytes = 0.0;
 };
 
 struct Handle {
@@ -123,8 +125,9 @@ struct Timer {
         HIPCHK(h, hipEventCreate(&t.stop));
         HIPCHK(h, hipEventRecord(t.start, s));
     }
-    void done() {
+    void done(double bytes = 0.0) {
         if (!on) return;
+        t.bytes = bytes;
         HIPCHK(h, hipEventRecord(t.stop, s));
         h->pending.push_back(t);
         on = false;
@@ -141,11 +144,12 @@ inline void flush_timing(Handle* h, hipStream_t s) {
         for (auto& k : h->stats)
             if (k.name == t.name) ks = &k;
         if (!ks) {
-            h->stats.push_back(KernelStat{t.name, 0, 0.0});
+            h->stats.push_back(KernelStat{t.name, 0, 0.0, 0.0});
             ks = &h->stats.back();
         }
         ks->launches += 1;
         ks->total_ms += ms;
+        ks->bytes += t.bytes;
         (void)hipEventDestroy(t.start);
         (void)hipEventDestroy(t.stop);
     }
