@@ -406,15 +406,16 @@ def bench_learned(args):
     g_full = gamma.cpu().numpy()[:n_kept]
     rng = np.random.default_rng(2021)
     perm = rng.permutation(n_kept)
-    n_train, n_test = 34, 64
+    n_train, n_test = 200, 64
     tr, te = np.sort(perm[:n_train]), np.sort(perm[n_train:n_train + n_test])
     # integrand samples of the plain method on the training k, and their smearing weights
     t0 = time.perf_counter()
     gam_tr = torch.zeros((n_train, nW), dtype=torch.float64, device="cuda")
-    terms = torch.zeros((n_train * nW, N, nm), dtype=torch.float64, device="cuda")
+    ns_tr = int(m[tr].sum())  # states in the window at the training k (capacity of the outputs)
+    terms = torch.zeros((ns_tr, N, nm), dtype=torch.float64, device="cuda")
     dws = torch.zeros_like(terms)
-    strow = torch.zeros(n_train * nW, dtype=torch.int32, device="cuda")
-    stband = torch.zeros(n_train * nW, dtype=torch.int32, device="cuda")
+    strow = torch.zeros(ns_tr, dtype=torch.int32, device="cuda")
+    stband = torch.zeros(ns_tr, dtype=torch.int32, device="cuda")
     ns = lib.rate_terms(ds, mesh, par, torch.from_numpy(kidx[tr]).cuda(), gam_tr, terms,
                         dweights=dws, st_row=strow, st_band=stband)
     torch.cuda.synchronize()
@@ -489,10 +490,11 @@ def bench_learned(args):
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
     # smearing weights of the test states (part of the proposal's cost)
-    dt = torch.zeros((n_test * nW, N, nm), dtype=torch.float64, device="cuda")
+    ns_te = int(m[te].sum())
+    dt = torch.zeros((ns_te, N, nm), dtype=torch.float64, device="cuda")
     gs = torch.zeros((n_test, nW), dtype=torch.float64, device="cuda")
-    trow = torch.zeros(n_test * nW, dtype=torch.int32, device="cuda")
-    tband = torch.zeros(n_test * nW, dtype=torch.int32, device="cuda")
+    trow = torch.zeros(ns_te, dtype=torch.int32, device="cuda")
+    tband = torch.zeros(ns_te, dtype=torch.int32, device="cuda")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     nst = lib.delta_weights(ds, mesh, par, kd, dt, gs, st_row=trow, st_band=tband)

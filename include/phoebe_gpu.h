@@ -241,26 +241,31 @@ phoebe_status phoebe_gpu_batched_destroy(void *plan);
  * (nullable, same shape) receives the same expression with |g|^2 = 1 (the
  * smearing weight D), so terms / D is the |g|^2 the proposal network fits.
  *   k_idx    device [nk] (required);  gamma_out device [nk, nW] as scatter_rates
- *   terms    device [states, N_q, nModes] with capacity nk*nW states
- *   st_row, st_band device int32 [states] (nullable): row (index into k_idx)
- *            and band of each state, states ordered by row then band
- *   n_states host (nullable)
+ *   terms    device [max_states, N_q, nModes]; dweights the same
+ *   st_row, st_band device int32 [max_states] (nullable): row (index into
+ *            k_idx) and band of each state, states ordered by row then band
+ *   max_states capacity of the per-state outputs (nk*nW always suffices); if the
+ *            window holds more states the call fails with PHOEBE_E_INVALID
+ *            before writing any of them
+ *   n_states host (nullable): number of states written
  * Synchronises the stream.  Terms of final bands outside the window-wide
  * non-zero range (see phoebe_gpu_scatter_rates) are exactly zero. */
 phoebe_status phoebe_gpu_rate_terms(void *handle, const phoebe_system *sys, const int32_t mesh[3],
                                     const int32_t *k_idx, int64_t nk,
                                     const phoebe_rate_params *par, double *gamma_out,
                                     double *terms, double *dweights, int32_t *st_row,
-                                    int32_t *st_band, int64_t *n_states, void *stream);
+                                    int32_t *st_band, int64_t max_states, int64_t *n_states,
+                                    void *stream);
 
 /* Smearing weights D[state, q, nu] alone (see phoebe_gpu_rate_terms): band and
- * phonon tables, window and states as in the rate path, no coupling work.
- * gamma_scratch device [nk, nW] is zeroed.  Synchronises the stream. */
+ * phonon tables, window and states as in the rate path, no coupling work;
+ * dweights, st_row, st_band and max_states as there.  gamma_scratch device
+ * [nk, nW] is zeroed.  Synchronises the stream. */
 phoebe_status phoebe_gpu_delta_weights(void *handle, const phoebe_system *sys,
                                        const int32_t mesh[3], const int32_t *k_idx, int64_t nk,
                                        const phoebe_rate_params *par, double *dweights,
-                                       int32_t *st_row, int32_t *st_band, int64_t *n_states,
-                                       double *gamma_scratch, void *stream);
+                                       int32_t *st_row, int32_t *st_band, int64_t max_states,
+                                       int64_t *n_states, double *gamma_scratch, void *stream);
 
 /* Learned q-proposal network: a multilayer perceptron with n_in inputs, `depth`
  * hidden layers of `width` silu units and one linear output.  Parameters are

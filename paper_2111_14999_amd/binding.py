@@ -104,10 +104,10 @@ def load(path: str = LIB_PATH):
                                             ctypes.POINTER(ctypes.c_double)]
     lib.phoebe_gpu_batched_destroy.argtypes = [vp]
     lib.phoebe_gpu_rate_terms.argtypes = [vp, ctypes.POINTER(CSystem), ctypes.POINTER(i32), vp, i64,
-                                          ctypes.POINTER(CRateParams), vp, vp, vp, vp, vp,
+                                          ctypes.POINTER(CRateParams), vp, vp, vp, vp, vp, i64,
                                           ctypes.POINTER(i64), vp]
     lib.phoebe_gpu_delta_weights.argtypes = [vp, ctypes.POINTER(CSystem), ctypes.POINTER(i32), vp,
-                                             i64, ctypes.POINTER(CRateParams), vp, vp, vp,
+                                             i64, ctypes.POINTER(CRateParams), vp, vp, vp, i64,
                                              ctypes.POINTER(i64), vp, vp]
     lib.phoebe_gpu_mlp_param_count.argtypes = [i32, i32, i32]
     lib.phoebe_gpu_mlp_param_count.restype = i64
@@ -137,6 +137,21 @@ def _ptr(t) -> Optional[int]:
     if t is None:
         return None
     return int(t.data_ptr())
+
+
+def _state_capacity(mesh, sys, per_q, per_q2, st_row, st_band) -> int:
+    """Rows every per-state output can hold; per-(q, mode) outputs must be [rows, N_q, nModes]."""
+    nq = int(mesh[0]) * int(mesh[1]) * int(mesh[2])
+    caps = []
+    for t in (per_q, per_q2):
+        if t is not None:
+            if tuple(t.shape[1:]) != (nq, 3 * sys.n_atoms):
+                raise ValueError(f"per-(q, mode) output must be [states, {nq}, {3 * sys.n_atoms}]")
+            caps.append(int(t.shape[0]))
+    for t in (st_row, st_band):
+        if t is not None:
+            caps.append(int(t.shape[0]))
+    return min(caps)
 
 
 def _stream(stream) -> Optional[int]:
@@ -272,7 +287,8 @@ class Library:
         self._check(self.lib.phoebe_gpu_rate_terms(
             self.handle, ctypes.byref(c), m, _ptr(k_idx), int(k_idx.shape[0]), ctypes.byref(p),
             _ptr(gamma_out), _ptr(terms), _ptr(dweights), _ptr(st_row), _ptr(st_band),
-            ctypes.byref(ns), _stream(stream)))
+            _state_capacity(mesh, sys, terms, dweights, st_row, st_band), ctypes.byref(ns),
+            _stream(stream)))
         return int(ns.value)
 
     def delta_weights(self, sys: DeviceSystem, mesh, params: dict, k_idx, dweights, gamma_scratch,
@@ -284,8 +300,9 @@ class Library:
         ns = ctypes.c_int64(0)
         self._check(self.lib.phoebe_gpu_delta_weights(
             self.handle, ctypes.byref(c), m, _ptr(k_idx), int(k_idx.shape[0]), ctypes.byref(p),
-            _ptr(dweights), _ptr(st_row), _ptr(st_band), ctypes.byref(ns), _ptr(gamma_scratch),
-            _stream(stream)))
+            _ptr(dweights), _ptr(st_row), _ptr(st_band),
+            _state_capacity(mesh, sys, dweights, None, st_row, st_band), ctypes.byref(ns),
+            _ptr(gamma_scratch), _stream(stream)))
         return int(ns.value)
 
     @staticmethod

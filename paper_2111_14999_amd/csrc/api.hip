@@ -308,7 +308,8 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                                         uint8_t* band_mask, int32_t* kept_k_out,
                                         int64_t* n_kept_out, double* terms, int32_t* st_row_out,
                                         int32_t* st_band_out, int64_t* n_states_out,
-                                        double* dweights, bool rates, void* stream) {
+                                        double* dweights, bool rates, int64_t state_cap,
+                                        void* stream) {
     if (!handle) return PHOEBE_E_INVALID;
     Handle* h = static_cast<Handle*>(handle);
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -582,6 +583,9 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
         HIPCHK(h, hipStreamSynchronize(s));
         const int nst = nst_i;
         if (n_states_out) *n_states_out = nst;
+        REQUIRE(h, state_cap < 0 || nst <= state_cap,
+                "%d states in the window exceed the per-state output capacity of %lld", nst,
+                (long long)state_cap);
         if (nst == 0) {
             flush_timing(h, s);
             return;
@@ -834,14 +838,15 @@ phoebe_status phoebe_gpu_scatter_rates(void* handle, const phoebe_system* sys,
                                        int64_t* n_kept_out, void* stream) {
     return scatter_rates_impl(handle, sys, mesh, k_idx, nk, q_off, q_idx, q_w, par, prec,
                               gamma_out, band_mask, kept_k_out, n_kept_out, nullptr, nullptr,
-                              nullptr, nullptr, nullptr, true, stream);
+                              nullptr, nullptr, nullptr, true, -1, stream);
 }
 
 phoebe_status phoebe_gpu_rate_terms(void* handle, const phoebe_system* sys, const int32_t mesh[3],
                                     const int32_t* k_idx, int64_t nk,
                                     const phoebe_rate_params* par, double* gamma_out,
                                     double* terms, double* dweights, int32_t* st_row,
-                                    int32_t* st_band, int64_t* n_states, void* stream) {
+                                    int32_t* st_band, int64_t max_states, int64_t* n_states,
+                                    void* stream) {
     if (!handle) return PHOEBE_E_INVALID;
     if (!terms) {
         static_cast<Handle*>(handle)->err = "terms is NULL";
@@ -849,14 +854,14 @@ phoebe_status phoebe_gpu_rate_terms(void* handle, const phoebe_system* sys, cons
     }
     return scatter_rates_impl(handle, sys, mesh, k_idx, nk, nullptr, nullptr, nullptr, par,
                               PHOEBE_FP64, gamma_out, nullptr, nullptr, nullptr, terms, st_row,
-                              st_band, n_states, dweights, true, stream);
+                              st_band, n_states, dweights, true, max_states, stream);
 }
 
 phoebe_status phoebe_gpu_delta_weights(void* handle, const phoebe_system* sys,
                                        const int32_t mesh[3], const int32_t* k_idx, int64_t nk,
                                        const phoebe_rate_params* par, double* dweights,
-                                       int32_t* st_row, int32_t* st_band, int64_t* n_states,
-                                       double* gamma_scratch, void* stream) {
+                                       int32_t* st_row, int32_t* st_band, int64_t max_states,
+                                       int64_t* n_states, double* gamma_scratch, void* stream) {
     if (!handle) return PHOEBE_E_INVALID;
     if (!dweights) {
         static_cast<Handle*>(handle)->err = "dweights is NULL";
@@ -864,7 +869,7 @@ phoebe_status phoebe_gpu_delta_weights(void* handle, const phoebe_system* sys,
     }
     return scatter_rates_impl(handle, sys, mesh, k_idx, nk, nullptr, nullptr, nullptr, par,
                               PHOEBE_FP64, gamma_scratch, nullptr, nullptr, nullptr, nullptr,
-                              st_row, st_band, n_states, dweights, false, stream);
+                              st_row, st_band, n_states, dweights, false, max_states, stream);
 }
 
 }  // extern "C"

@@ -6,6 +6,8 @@
 // Two arithmetic paths: BF16 operands on v_mfma_f32_16x16x32_bf16 with FP32
 // accumulation (float storage), and an FP64 path on v_mfma_f64_16x16x4f64
 // (double storage) used to check gradients against the FP64 oracle.
+#include <algorithm>
+
 #include "mlp.hpp"
 
 namespace phx {
@@ -379,18 +381,23 @@ hipError_t launch_proposal_raw(const float* y, int64_t nq, int nm, double c, dou
     return hipGetLastError();
 }
 
-// max of a row (single work-group)
-__global__ __launch_bounds__(1024) void rowmax_kernel(const double* x, int64_t n, double* out) {
-    __shared__ double sh[1024];
+// max of a non-negative array: block maxima combined by an atomic max on the
+// IEEE bit patterns (ordered like the values for non-negative doubles); *out
+// must hold +0.0 before the launch
+__global__ __launch_bounds__(256) void rowmax_kernel(const double* x, int64_t n,
+                                                     unsigned long long* out) {
+    __shared__ double sh[256];
     double m = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += 1024) m = fmax(m, x[i]);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        m = fmax(m, x[i]);
     sh[threadIdx.x] = m;
     __syncthreads();
-    for (int o = 512; o > 0; o >>= 1) {
+    for (int o = 128; o > 0; o >>= 1) {
         if ((int)threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out = sh[0];
+    if (threadIdx.x == 0) atomicMax(out, (unsigned long long)__double_as_longlong(sh[0]));
 }
 
 // list (in any order) of the entries with D > thr * max; count[0] must start at 0
@@ -442,7 +449,10 @@ __global__ void sum_modes_kernel(const double* E, int64_t N, int nm, double* p) 
 }
 
 hipError_t launch_rowmax(const double* x, int64_t n, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(rowmax_kernel, dim3(1), dim3(1024), 0, s, x, n, out);
+    hipError_t e = hipMemsetAsync(out, 0, sizeof(double), s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(rowmax_kernel, dim3(std::min<int64_t>(gridm(n, 256), 1024)), dim3(256), 0, s,
+                       x, n, reinterpret_cast<unsigned long long*>(out));
     return hipGetLastError();
 }
 hipError_t launch_select(const double* D, int64_t n, const double* dmax, double thr, int32_t* list,

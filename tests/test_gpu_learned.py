@@ -150,6 +150,28 @@ def test_rate_terms_sum_to_rates(lib):
     assert torch.equal(dw2[:ns], dw[:ns])
 
 
+def test_rate_terms_state_capacity(lib):
+    """Outputs too small for the window's states: an error before anything is written."""
+    torch = torch_cuda()
+    from paper_2111_14999_amd import DeviceSystem, PhoebeError
+    s = synth.config_c1()
+    mesh, par = _toy_par()
+    ds = DeviceSystem.from_host(s)
+    k_idx = torch.from_numpy(np.array([3, 50, 199], dtype=np.int32)).cuda()
+    gam = torch.zeros((3, s.n_wannier), dtype=torch.float64, device="cuda")
+    small = torch.full((11, 216, s.n_modes), 7.0, dtype=torch.float64, device="cuda")
+    with pytest.raises(PhoebeError) as e:
+        lib.rate_terms(ds, mesh, par, k_idx, gam, small)
+    assert e.value.status == -1
+    with pytest.raises(PhoebeError):
+        lib.delta_weights(ds, mesh, par, k_idx, small, gam)
+    torch.cuda.synchronize()
+    assert torch.all(small == 7.0)
+    with pytest.raises(ValueError):
+        lib.rate_terms(ds, mesh, par, k_idx, gam, torch.zeros((12, 215, s.n_modes),
+                                                              dtype=torch.float64, device="cuda"))
+
+
 def test_features_match_definition(lib):
     torch = torch_cuda()
     mesh, nm = (5, 6, 7), 6
