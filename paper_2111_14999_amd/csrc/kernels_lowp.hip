@@ -452,28 +452,47 @@ __global__ __launch_bounds__(256, 2) void stage2_rates_lp_kernel(RateArgsLP a) {
         using P = Pairs<PREC>;
         const int64_t per = (int64_t)a.rp_pad * a.nc_pad;
         const uint16_t* Fst = reinterpret_cast<const uint16_t*>(a.F) + (int64_t)st * 2 * NP * per;
-        for (int k0 = 0; k0 < a.rp_pad; k0 += 32) {
+        // The A fragments (phase pieces) are the same for the four waves: the
+        // work-group forms each once per K step into LDS (double-buffered,
+        // [buf][piece][re, im][i][lane] slots of 8 BF16), TPS threads per slot.
+        s8v* sAf = reinterpret_cast<s8v*>(sY + CQ * kMBLP * nm);
+        constexpr int SLOTS = TQ * 64;
+        constexpr int TPS = 256 / SLOTS;  // threads per slot
+        constexpr int JPT = 8 / TPS;      // phases per thread
+        const int fslot = tid / TPS, fpart = tid % TPS;
+        const int fi = fslot / 64, fl = fslot % 64;
+        const cd* fax = sAx + (16 * fi + (fl & 15)) * 3 * W;
+        int buf = 0;
+        for (int k0 = 0; k0 < a.rp_pad; k0 += 32, buf ^= 1) {
             const int kb = k0 + 8 * lg;
-            // A pieces of the 8 phases of this lane (FP64 product, rounded, split)
-            s8v ar[TQ][NP], ai[TQ][NP];
+            {
+                // FP64 product of the three axis factors, rounded to FP32, split
+                short* dr = reinterpret_cast<short*>(sAf + ((buf * NP) * 2 * TQ + fi) * 64 + fl);
 #pragma unroll
-            for (int i = 0; i < TQ; ++i) {
-                const cd* ax = sAx + (16 * i + li) * 3 * W;
-#pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const int pk = sRp[kb + j];
-                    const cd ph = cmul(cmul(ax[pk & 255], ax[W + ((pk >> 8) & 255)]),
-                                       ax[2 * W + ((pk >> 16) & 255)]);
+                for (int jj = 0; jj < JPT; ++jj) {
+                    const int j = fpart * JPT + jj;
+                    const int pk = sRp[k0 + 8 * (fl >> 4) + j];
+                    const cd ph = cmul(cmul(fax[pk & 255], fax[W + ((pk >> 8) & 255)]),
+                                       fax[2 * W + ((pk >> 16) & 255)]);
                     uint16_t pr[NP], pi[NP];
                     split_bf16<NP>((float)ph.x, pr);
                     split_bf16<NP>((float)ph.y, pi);
 #pragma unroll
                     for (int p = 0; p < NP; ++p) {
-                        ar[i][p][j] = (short)pr[p];
-                        ai[i][p][j] = (short)pi[p];
+                        dr[((p * 2 + 0) * TQ * 64) * 8 + j] = (short)pr[p];
+                        dr[((p * 2 + 1) * TQ * 64) * 8 + j] = (short)pi[p];
                     }
                 }
             }
+            __syncthreads();
+            s8v ar[TQ][NP], ai[TQ][NP];
+#pragma unroll
+            for (int i = 0; i < TQ; ++i)
+#pragma unroll
+                for (int p = 0; p < NP; ++p) {
+                    ar[i][p] = sAf[(((buf * NP + p) * 2 + 0) * TQ + i) * 64 + lane];
+                    ai[i][p] = sAf[(((buf * NP + p) * 2 + 1) * TQ + i) * 64 + lane];
+                }
 #pragma unroll
             for (int t = 0; t < TN; ++t) {
                 s8v br[NP], bi[NP];
@@ -599,17 +618,21 @@ __global__ __launch_bounds__(256, 2) void stage2_rates_lp_kernel(RateArgsLP a) {
         a.partial[(int64_t)st * a.n_qtiles + qt] = (sRed[0] + sRed[1]) + (sRed[2] + sRed[3]);
 }
 
-size_t stage2_lp_lds(int tq, int rmax, int rp_pad, int nc_pad, int nm) {
+size_t stage2_lp_lds(int prec, int tq, int rmax, int rp_pad, int nc_pad, int nm) {
     const int BQ = 16 * tq, CQ = 4 * tq, W = 2 * rmax + 1;
     size_t shm = (size_t)BQ * 3 * W * sizeof(cd) + (size_t)rp_pad * sizeof(int);
     shm = (shm + 15) & ~(size_t)15;
     shm += (size_t)CQ * nc_pad * sizeof(cf) + (size_t)CQ * kMBLP * nm * sizeof(cf);
+    shm = (shm + 15) & ~(size_t)15;
+    // split-BF16: two buffers of NP pieces x (re, im) x TQ x 64 lanes x 8 BF16
+    const int np = prec == PHOEBE_BF16X3 ? 2 : (prec == PHOEBE_BF16X6 ? 3 : 0);
+    shm += (size_t)2 * np * 2 * tq * 64 * 16;
     return shm;
 }
 
 template <int PREC, int TQ, int TN>
 static hipError_t go_stage2_lp(const RateArgsLP& a, int nst, hipStream_t s) {
-    const size_t shm = stage2_lp_lds(TQ, a.rmax, a.rp_pad, a.nc_pad, a.nm);
+    const size_t shm = stage2_lp_lds(PREC, TQ, a.rmax, a.rp_pad, a.nc_pad, a.nm);
     if (shm > 160 * 1024 - 1024) return hipErrorInvalidValue;
     hipError_t e = hipFuncSetAttribute((const void*)stage2_rates_lp_kernel<PREC, TQ, TN>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);

@@ -49,7 +49,7 @@ hipError_t launch_fold_uk_lp(int prec, const cf* G, int64_t ldg, const cd* U,
                              const int32_t* st_band, int nst, int n_rp, int nm, int nW, int rp_pad,
                              int nc_pad, void* F, hipStream_t s);
 hipError_t launch_stage2_rates_lp(int prec, const RateArgsLP& a, int nst, hipStream_t s);
-size_t stage2_lp_lds(int tq, int rmax, int rp_pad, int nc_pad, int nm);
+size_t stage2_lp_lds(int prec, int tq, int rmax, int rp_pad, int nc_pad, int nm);
 int stage2_lp_config(int nm, int nW, int* tq_out, int* tn_out);
 hipError_t launch_fold_all_lp(const cf* G, const cd* U, int n_rp, int nm, int nW, cf* F,
                               hipStream_t s);
