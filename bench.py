@@ -156,7 +156,7 @@ def main():
     #   stage1_axes     the same sum factorised over the Re box, HBM: g(Re,Rp) read
     #                   once per batch, intermediates once each way, G once
     #   line_rates      last axis of the factorised sum: 8 N_q W nModes nW per state
-    #   axis_transforms first two axes, HBM traffic: 16 B nModes nW per state x
+    #   axis_transforms first two axes, HBM traffic: 16 B (8 B in FP32) nModes nW per state x
     #                   (n_rp read + 2 W^2 N2 for T1 + W N1 N2 for T2)
     W = 2 * int(np.abs(s.rp).max()) + 1
     nc = nm * nW
@@ -167,7 +167,7 @@ def main():
         # written and read once, G written once (bytes recorded by the library)
         "stage1_axes": ("hbm", None),
         "line_rates": ("mfma", 8.0 * n_states * N * W * nc),
-        "axis_transforms": ("hbm", 16.0 * nc * n_states *
+        "axis_transforms": ("hbm", (8.0 if args.precision == "fp32" else 16.0) * nc * n_states *
                             (n_rp + 2 * W * W * mesh[2] + W * mesh[1] * mesh[2])),
     }
     peak_mfma = {"fp64": PEAK_FP64_TFLOPS, "fp32": 157.3, "bf16x3": 2500.0 / 3,

@@ -356,11 +356,11 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
         const int Wbox = 2 * rmax_p + 1;
         const int nc_line = line_rates_ncpad(nm, nW);
         const int64_t NL = (int64_t)mesh.n1 * mesh.n2;
-        const bool can_factor = prec == PHOEBE_FP64 && q_off == nullptr && Wbox <= 31 &&
-                                nc_line > 0 && NL <= 65535 &&
-                                line_rates_lds(Wbox, mesh.n0, nm) <= 64 * 1024;
+        const bool can_factor = (prec == PHOEBE_FP64 || prec == PHOEBE_FP32) && q_off == nullptr &&
+                                Wbox <= 31 && nc_line > 0 && NL <= 65535 &&
+                                line_rates_lds(Wbox, mesh.n0, nm, lowp) <= 64 * 1024;
         if (h->mesh_sum == PHOEBE_MESH_SUM_FACTORED && !can_factor) {
-            set_err(h, "the factorised mesh sum needs FP64, the full q mesh, |Rp| <= 15, "
+            set_err(h, "the factorised mesh sum needs FP64 or FP32, the full q mesh, |Rp| <= 15, "
                        "nW <= 16, nModes <= 32 and N1*N2 <= 65535");
             throw Fail{PHOEBE_E_UNSUPPORTED};
         }
@@ -400,7 +400,7 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
             BK /= 2;
         const int BQ = 16 * tq;
         // states per factorised sub-batch: T1 + T2 of a sub-batch stay under 4 GB
-        const size_t t12_state = ((size_t)Wbox * Wbox * mesh.n2 + (size_t)Wbox * NL) * nc_pad * sizeof(cd);
+        const size_t t12_state = ((size_t)Wbox * Wbox * mesh.n2 + (size_t)Wbox * NL) * nc_pad * g_elem;
         const int nsb = factored ? (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)BK * nW,
                                                       (int64_t)(4e9 / (double)t12_state)))
                                  : 0;
@@ -499,7 +499,7 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                                    (size_t)max_states * n_qtiles * sizeof(double) +
                                    (factored ? (size_t)nsb * t12_state + 512 : 0) +
                                    (re_fact ? ((size_t)kD0Max * We * We + (size_t)kD01Max * We) *
-                                                      NC2 * sizeof(cd) +
+                                                      NC2 * g_elem +
                                                   (size_t)rows_cap * 160 * sizeof(int32_t) + 1024
                                             : 0);
         ensure_ws(h, tables_end + std::max(scratch_bands, batch_bytes) + 256);
@@ -696,14 +696,15 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
         if (re_fact)
             HIPCHK(h, hipMemcpyAsync(rbd, rbh.data(), sizeof(int32_t) * rbh.size(),
                                      hipMemcpyHostToDevice, s));
-        cd* T0re = re_fact ? ar.take<cd>((size_t)kD0Max * We * We * NC2) : nullptr;
-        cd* T1re = re_fact ? ar.take<cd>((size_t)kD01Max * We * NC2) : nullptr;
+        char* T0re = re_fact ? ar.take<char>((size_t)kD0Max * We * We * NC2 * g_elem) : nullptr;
+        char* T1re = re_fact ? ar.take<char>((size_t)kD01Max * We * NC2 * g_elem) : nullptr;
         cd* P1 = ar.take<cd>((size_t)BK * n_re);
         char* Gbuf = ar.take<char>((size_t)BK * NC2 * g_elem);
         char* Fbuf = ar.take<char>((size_t)max_states * rp_pad * nc_pad * f_elem);
         double* partial = ar.take<double>((size_t)max_states * n_qtiles);
-        cd* T1buf = factored ? ar.take<cd>((size_t)nsb * Wbox * Wbox * mesh.n2 * nc_pad) : nullptr;
-        cd* T2buf = factored ? ar.take<cd>((size_t)nsb * Wbox * NL * nc_pad) : nullptr;
+        char* T1buf = factored ? ar.take<char>((size_t)nsb * Wbox * Wbox * mesh.n2 * nc_pad * g_elem)
+                               : nullptr;
+        char* T2buf = factored ? ar.take<char>((size_t)nsb * Wbox * NL * nc_pad * g_elem) : nullptr;
 
         const double inv_sqrtpi_sigma = 1.0 / (std::sqrt(kPi) * par->sigma);
         const double scale = 2.0 * kPi * inv_sqrtpi_sigma * (q_off ? 1.0 : 1.0 / (double)N);
@@ -719,12 +720,20 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                 ReBatch rb{(int)o[0], (int)o[1], rbd + o[2], rbd + o[3], rbd + o[4],
                            rbd + o[5], rbd + o[6], rbd + o[7]};
                 Timer t1(h, s, "stage1_axes");
-                HIPCHK(h, launch_re_axes(reinterpret_cast<const cd*>(sys->g_rr), NC2, T.box_re,
-                                         rmax_e, mesh, T.Pre, rb, T0re, T1re,
-                                         reinterpret_cast<cd*>(Gbuf), NC2, s));
-                // g read once; T0 and T1 written and read once; G written once
-                t1.done(16.0 * (double)NC2 *
-                        ((double)n_re + 2.0 * rb.d0 * We * We + 2.0 * rb.d01 * We + (double)nb));
+                if (lowp)
+                    HIPCHK(h, launch_re_axes_f32(reinterpret_cast<const cd*>(sys->g_rr), NC2,
+                                                 T.box_re, rmax_e, mesh, T.Pre, rb,
+                                                 reinterpret_cast<cf*>(T0re),
+                                                 reinterpret_cast<cf*>(T1re),
+                                                 reinterpret_cast<cf*>(Gbuf), NC2, s));
+                else
+                    HIPCHK(h, launch_re_axes(reinterpret_cast<const cd*>(sys->g_rr), NC2, T.box_re,
+                                             rmax_e, mesh, T.Pre, rb, reinterpret_cast<cd*>(T0re),
+                                             reinterpret_cast<cd*>(T1re),
+                                             reinterpret_cast<cd*>(Gbuf), NC2, s));
+                // g (FP64) read once; T0 and T1 written and read once; G written once
+                t1.done((double)NC2 * (16.0 * n_re + (double)g_elem * (2.0 * rb.d0 * We * We +
+                                                                        2.0 * rb.d01 * We + nb)));
             } else {
             HIPCHK(h, launch_phase_table(nullptr, kept + r0, mesh, nb, T.re, n_re, P1, n_re, s));
             Timer t1(h, s, "stage1_phase");
@@ -739,7 +748,7 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
             if (lowp)
                 HIPCHK(h, launch_fold_uk_lp(prec, reinterpret_cast<const cf*>(Gbuf), NC2, T.U,
                                             T.st_row + sbeg, (int)r0, T.st_kmesh + sbeg,
-                                            T.st_band + sbeg, ns, n_rp, nm, nW, rp_pad, nc_pad,
+                                            T.st_band + sbeg, ns, n_rp, nm, nW, cw, rp_pad, nc_pad,
                                             Fbuf, s));
             else
                 HIPCHK(h, launch_fold_uk(reinterpret_cast<const cd*>(Gbuf), NC2, T.U, T.st_row + sbeg,
@@ -775,7 +784,7 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
             ra.n_qtiles = n_qtiles;
             ra.terms = terms ? terms + (int64_t)sbeg * N * nm : nullptr;
             ra.terms_scale = 2.0 * kPi * inv_sqrtpi_sigma;
-            if (lowp) {
+            if (lowp && !factored) {
                 Timer t2(h, s, "stage2_rates");
                 RateArgsLP rl{};
                 rl.F = Fbuf;
@@ -800,9 +809,16 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                 for (int sb = 0; sb < ns; sb += nsb) {
                     const int nn = std::min(nsb, ns - sb);
                     Timer ta(h, s, "axis_transforms");
-                    HIPCHK(h, launch_axis_transforms(
-                                  reinterpret_cast<const cd*>(Fbuf) + (int64_t)sb * rp_pad * nc_pad,
-                                  rp_pad, nc_pad, T.box_rp, rmax_p, mesh, T.Pax, nn, T1buf, T2buf, s));
+                    if (lowp)
+                        HIPCHK(h, launch_axis_transforms_f32(
+                                      reinterpret_cast<const cf*>(Fbuf) + (int64_t)sb * rp_pad * nc_pad,
+                                      rp_pad, nc_pad, T.box_rp, rmax_p, mesh, T.Pax, nn,
+                                      reinterpret_cast<cf*>(T1buf), reinterpret_cast<cf*>(T2buf), s));
+                    else
+                        HIPCHK(h, launch_axis_transforms(
+                                      reinterpret_cast<const cd*>(Fbuf) + (int64_t)sb * rp_pad * nc_pad,
+                                      rp_pad, nc_pad, T.box_rp, rmax_p, mesh, T.Pax, nn,
+                                      reinterpret_cast<cd*>(T1buf), reinterpret_cast<cd*>(T2buf), s));
                     ta.done();
                     RateArgs rb = ra;
                     rb.T2 = T2buf;
@@ -814,7 +830,10 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                     rb.partial = partial + (int64_t)sb * n_qtiles;
                     if (ra.terms) rb.terms = ra.terms + (int64_t)sb * N * nm;
                     Timer tl(h, s, "line_rates");
-                    HIPCHK(h, launch_line_rates(rb, nn, s));
+                    if (lowp)
+                        HIPCHK(h, launch_line_rates_f32(rb, nn, s));
+                    else
+                        HIPCHK(h, launch_line_rates(rb, nn, s));
                     tl.done();
                 }
             }

@@ -148,7 +148,8 @@ void enqueue_stage1(Handle* h, const SysPlan& p, cf* G, int s0, int s1, cf* F, i
                                   p.n_re, s));
         HIPCHK(h, launch_fold_uk_lp(PHOEBE_FP32, G, NC2, p.U, p.st_row + a, (int)r0,
                                     p.st_kmesh + a, p.st_band + a, b - a, p.n_rp, p.nm, p.nW,
-                                    p.rp_pad, nc_pad, F + (int64_t)(a - s0) * p.rp_pad * nc_pad, s));
+                                    p.nW, p.rp_pad, nc_pad, F + (int64_t)(a - s0) * p.rp_pad * nc_pad,
+                                    s));
         a = b;
     }
 }

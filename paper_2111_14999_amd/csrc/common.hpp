@@ -42,6 +42,20 @@ __host__ __device__ inline cd cfmac(cd a, cd b, cd c) {  // conj(a)*b + c
 }
 __host__ __device__ inline double cabs2(cd a) { return a.x * a.x + a.y * a.y; }
 
+struct cf {
+    float x, y;
+};
+__host__ __device__ inline cf cfma(cf a, cf b, cf c) {  // a*b + c, FP32
+    return {fmaf(a.x, b.x, fmaf(-a.y, b.y, c.x)), fmaf(a.x, b.y, fmaf(a.y, b.x, c.y))};
+}
+__host__ __device__ inline double cabs2(cf a) { return (double)a.x * a.x + (double)a.y * a.y; }
+
+// complex value in the working type C (cd or cf) from an FP64 one
+template <class C>
+__host__ __device__ inline C to_c(cd v) {
+    return C{(decltype(C::x))v.x, (decltype(C::x))v.y};
+}
+
 // e^{i 2 pi t} for t already reduced to [-1, 1)
 __device__ inline cd expi2pi(double t) {
     double s, c;

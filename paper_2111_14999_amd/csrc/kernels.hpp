@@ -87,7 +87,7 @@ struct RateArgs {
     double* terms;             // nullable [nst, nq_mesh, nm]: per-(q, mode) terms, summed over m
     double terms_scale;        // factor applied to each stored term
     // factorised full-mesh form: X[q] = sum_R0 P0[q0, R0] T2[R0, q1 N2 + q2]
-    const cd* T2;              // [nst, W, N1*N2, nc_pad]
+    const void* T2;            // [nst, W, N1*N2, nc_pad] of cd (FP64) or cf (FP32 form)
     const cd* P0;              // [N0, W]
     int W;                     // 2 rmax + 1
     int n_states;              // states of one launch (set by the launcher)
@@ -103,6 +103,9 @@ hipError_t launch_axis_phases(Mesh m, int rmax, cd* P, hipStream_t s);
 hipError_t launch_axis_transforms(const cd* F, int rp_pad, int nc_pad, const int32_t* box_rp,
                                   int rmax, Mesh m, const cd* P, int nst, cd* T1, cd* T2,
                                   hipStream_t s);
+hipError_t launch_axis_transforms_f32(const cf* F, int rp_pad, int nc_pad, const int32_t* box_rp,
+                                      int rmax, Mesh m, const cd* P, int nst, cf* T1, cf* T2,
+                                      hipStream_t s);
 // Stage 1 factorised over the axes of the Re box for one batch of kept k.
 // Device lists: d_k0 [d0] distinct k0; pair_k1 [d01] and pair_off [d0+1] the
 // distinct (k0, k1) pairs grouped by k0; kp_off [d01+1], k_row, k_k2 [nb] the
@@ -114,11 +117,15 @@ struct ReBatch {
 hipError_t launch_re_axes(const cd* g, int64_t NC, const int32_t* box_re, int rmax, Mesh m,
                           const cd* P, const ReBatch& b, cd* T0, cd* T1, cd* G, int64_t ldg,
                           hipStream_t s);
+hipError_t launch_re_axes_f32(const cd* g, int64_t NC, const int32_t* box_re, int rmax, Mesh m,
+                              const cd* P, const ReBatch& b, cf* T0, cf* T1, cf* G, int64_t ldg,
+                              hipStream_t s);
 
 // Axis 0 on MFMA + rotations + rate terms, one work-group per (state, q1, q2) line.
 // Columns sa*16 + b (nW <= 16), nc_pad = 64 TN with 4 TN >= nModes.
 hipError_t launch_line_rates(const RateArgs& a, int nst, hipStream_t s);
-size_t line_rates_lds(int W, int N0, int nm);
+hipError_t launch_line_rates_f32(const RateArgs& a, int nst, hipStream_t s);
+size_t line_rates_lds(int W, int N0, int nm, bool f32);
 int line_rates_ncpad(int nm, int nW);  // -1 where the form does not apply
 
 // gamma[row, band] = scale * sum_t partial[st, t]

@@ -277,10 +277,9 @@ template <int NP>
 __global__ void fold_uk_lp_kernel(const cf* __restrict__ G, int64_t ldg, const cd* __restrict__ U,
                                   const int32_t* st_row, int row0, const int32_t* st_kmesh,
                                   const int32_t* st_band, int nst, int n_rp, int nm, int nW,
-                                  int rp_pad, int nc_pad, void* __restrict__ Fout) {
+                                  int cw, int rp_pad, int nc_pad, void* __restrict__ Fout) {
     const int64_t per = (int64_t)rp_pad * nc_pad;
     const int64_t total = (int64_t)nst * per;
-    const int nc = nm * nW;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
         const int st = (int)(t / per);
@@ -294,8 +293,8 @@ __global__ void fold_uk_lp_kernel(const cf* __restrict__ G, int64_t ldg, const c
             r = (int)(o - (int64_t)c * rp_pad);
         }
         float ar = 0.f, ai = 0.f;
-        if (r < n_rp && c < nc) {
-            const int sa = c / nW, b = c - sa * nW;
+        const int sa = c / cw, b = c - sa * cw;
+        if (r < n_rp && sa < nm && b < nW) {
             const int n = st_band[st];
             const cd* Un = U + ((int64_t)st_kmesh[st] * nW + n) * nW;  // eigenvector n
             const cf* Gk = G + (int64_t)(st_row[st] - row0) * ldg + ((int64_t)r * nm + sa) * nW * nW + b;
@@ -325,19 +324,20 @@ __global__ void fold_uk_lp_kernel(const cf* __restrict__ G, int64_t ldg, const c
 
 hipError_t launch_fold_uk_lp(int prec, const cf* G, int64_t ldg, const cd* U,
                              const int32_t* st_row, int row0, const int32_t* st_kmesh,
-                             const int32_t* st_band, int nst, int n_rp, int nm, int nW, int rp_pad,
-                             int nc_pad, void* F, hipStream_t s) {
+                             const int32_t* st_band, int nst, int n_rp, int nm, int nW, int cw,
+                             int rp_pad, int nc_pad, void* F, hipStream_t s) {
     if (nst <= 0) return hipSuccess;
+    if (cw < nW || (int64_t)cw * nm > nc_pad) return hipErrorInvalidValue;
     const int g = gridn((int64_t)nst * rp_pad * nc_pad, 256);
     if (prec == PHOEBE_FP32)
         hipLaunchKernelGGL(fold_uk_lp_kernel<0>, dim3(g), dim3(256), 0, s, G, ldg, U, st_row, row0,
-                           st_kmesh, st_band, nst, n_rp, nm, nW, rp_pad, nc_pad, F);
+                           st_kmesh, st_band, nst, n_rp, nm, nW, cw, rp_pad, nc_pad, F);
     else if (prec == PHOEBE_BF16X3)
         hipLaunchKernelGGL(fold_uk_lp_kernel<2>, dim3(g), dim3(256), 0, s, G, ldg, U, st_row, row0,
-                           st_kmesh, st_band, nst, n_rp, nm, nW, rp_pad, nc_pad, F);
+                           st_kmesh, st_band, nst, n_rp, nm, nW, cw, rp_pad, nc_pad, F);
     else
         hipLaunchKernelGGL(fold_uk_lp_kernel<3>, dim3(g), dim3(256), 0, s, G, ldg, U, st_row, row0,
-                           st_kmesh, st_band, nst, n_rp, nm, nW, rp_pad, nc_pad, F);
+                           st_kmesh, st_band, nst, n_rp, nm, nW, cw, rp_pad, nc_pad, F);
     return hipGetLastError();
 }
 

@@ -15,6 +15,7 @@
 // smeared rate terms as the direct kernel; X never reaches memory.  The sum
 // is the same as the direct one up to the order of the additions.
 #include <algorithm>
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -61,12 +62,13 @@ constexpr int kMaxW = 32;
 // T1[st, p, q2, c] = sum_r P2[q2, r] F[st, box_rp[p W + r], c]   (p = (R0, R1))
 // box_rp maps a box position to its row of F, or -1 where the list has no Rp.
 // WT > 0 fixes the box width at compile time (the W inputs stay in registers);
-// WT = 0 takes it from the argument.
-template <int WT>
-__global__ __launch_bounds__(256) void axis2_kernel(const cd* __restrict__ F, int rp_pad,
+// WT = 0 takes it from the argument.  C is the working type: cd (FP64) or cf
+// (FP32 form: phases formed in FP64 and rounded once, FP32 accumulation).
+template <int WT, class C>
+__global__ __launch_bounds__(256) void axis2_kernel(const C* __restrict__ F, int rp_pad,
                                                     int nc_pad, const int32_t* __restrict__ box_rp,
                                                     int Wr, int N2, const cd* __restrict__ P2,
-                                                    int nst, cd* __restrict__ T1) {
+                                                    int nst, C* __restrict__ T1) {
     constexpr int NV = WT > 0 ? WT : kMaxW;
     const int W = WT > 0 ? WT : Wr;
     const int64_t total = (int64_t)nst * W * W * nc_pad;
@@ -76,32 +78,32 @@ __global__ __launch_bounds__(256) void axis2_kernel(const cd* __restrict__ F, in
         const int64_t sp = t / nc_pad;  // st * W^2 + p
         const int p = (int)(sp % (W * W));
         const int st = (int)(sp / (W * W));
-        cd v[NV];
+        C v[NV];
 #pragma unroll
         for (int r = 0; r < NV; ++r) {
             if (r < W) {
                 const int row = box_rp[p * W + r];
-                v[r] = row >= 0 ? F[((int64_t)st * rp_pad + row) * nc_pad + c] : cd{0.0, 0.0};
+                v[r] = row >= 0 ? F[((int64_t)st * rp_pad + row) * nc_pad + c] : C{0, 0};
             }
         }
-        cd* out = T1 + sp * N2 * nc_pad + c;
+        C* out = T1 + sp * N2 * nc_pad + c;
         for (int q = 0; q < N2; ++q) {
             const cd* Pq = P2 + q * W;
-            cd acc = {0.0, 0.0};
+            C acc = {0, 0};
 #pragma unroll
             for (int r = 0; r < NV; ++r)
-                if (r < W) acc = cfma(Pq[r], v[r], acc);
+                if (r < W) acc = cfma(to_c<C>(Pq[r]), v[r], acc);
             out[(int64_t)q * nc_pad] = acc;
         }
     }
 }
 
 // out[o, n, i] = sum_r P[n, r] in[o, r, i]   (i < inner, contiguous)
-template <int WT>
-__global__ __launch_bounds__(256) void axis_mid_kernel(const cd* __restrict__ in, int64_t n_outer,
+template <int WT, class C>
+__global__ __launch_bounds__(256) void axis_mid_kernel(const C* __restrict__ in, int64_t n_outer,
                                                        int Wr, int64_t inner, int N,
                                                        const cd* __restrict__ P,
-                                                       cd* __restrict__ out) {
+                                                       C* __restrict__ out) {
     constexpr int NV = WT > 0 ? WT : kMaxW;
     const int W = WT > 0 ? WT : Wr;
     const int64_t total = n_outer * inner;
@@ -109,39 +111,40 @@ __global__ __launch_bounds__(256) void axis_mid_kernel(const cd* __restrict__ in
          t += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = t % inner;
         const int64_t o = t / inner;
-        cd v[NV];
-        const cd* src = in + o * W * inner + i;
+        C v[NV];
+        const C* src = in + o * W * inner + i;
 #pragma unroll
         for (int r = 0; r < NV; ++r)
             if (r < W) v[r] = src[(int64_t)r * inner];
-        cd* dst = out + o * N * inner + i;
+        C* dst = out + o * N * inner + i;
         for (int n = 0; n < N; ++n) {
             const cd* Pn = P + n * W;
-            cd acc = {0.0, 0.0};
+            C acc = {0, 0};
 #pragma unroll
             for (int r = 0; r < NV; ++r)
-                if (r < W) acc = cfma(Pn[r], v[r], acc);
+                if (r < W) acc = cfma(to_c<C>(Pn[r]), v[r], acc);
             dst[(int64_t)n * inner] = acc;
         }
     }
 }
 
-template <int WT>
-static hipError_t go_axes(const cd* F, int rp_pad, int nc_pad, const int32_t* box_rp, int W,
-                          Mesh m, const cd* P1, const cd* P2, int nst, cd* T1, cd* T2,
+template <int WT, class C>
+static hipError_t go_axes(const C* F, int rp_pad, int nc_pad, const int32_t* box_rp, int W,
+                          Mesh m, const cd* P1, const cd* P2, int nst, C* T1, C* T2,
                           hipStream_t s) {
-    hipLaunchKernelGGL(axis2_kernel<WT>, dim3(gridm((int64_t)nst * W * W * nc_pad, 256)),
+    hipLaunchKernelGGL((axis2_kernel<WT, C>), dim3(gridm((int64_t)nst * W * W * nc_pad, 256)),
                        dim3(256), 0, s, F, rp_pad, nc_pad, box_rp, W, m.n2, P2, nst, T1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t inner = (int64_t)m.n2 * nc_pad;
-    hipLaunchKernelGGL(axis_mid_kernel<WT>, dim3(gridm((int64_t)nst * W * inner, 256)), dim3(256),
-                       0, s, T1, (int64_t)nst * W, W, inner, m.n1, P1, T2);
+    hipLaunchKernelGGL((axis_mid_kernel<WT, C>), dim3(gridm((int64_t)nst * W * inner, 256)),
+                       dim3(256), 0, s, T1, (int64_t)nst * W, W, inner, m.n1, P1, T2);
     return hipGetLastError();
 }
 
-hipError_t launch_axis_transforms(const cd* F, int rp_pad, int nc_pad, const int32_t* box_rp,
-                                  int rmax, Mesh m, const cd* P, int nst, cd* T1, cd* T2,
+template <class C>
+static hipError_t axis_transforms(const C* F, int rp_pad, int nc_pad, const int32_t* box_rp,
+                                  int rmax, Mesh m, const cd* P, int nst, C* T1, C* T2,
                                   hipStream_t s) {
     const int W = 2 * rmax + 1;
     if (W > kMaxW) return hipErrorInvalidValue;
@@ -149,13 +152,24 @@ hipError_t launch_axis_transforms(const cd* F, int rp_pad, int nc_pad, const int
     const cd* P1 = P + (int64_t)m.n0 * W;
     const cd* P2 = P1 + (int64_t)m.n1 * W;
     switch (W) {
-        case 1: return go_axes<1>(F, rp_pad, nc_pad, box_rp, W, m, P1, P2, nst, T1, T2, s);
-        case 3: return go_axes<3>(F, rp_pad, nc_pad, box_rp, W, m, P1, P2, nst, T1, T2, s);
-        case 5: return go_axes<5>(F, rp_pad, nc_pad, box_rp, W, m, P1, P2, nst, T1, T2, s);
-        case 7: return go_axes<7>(F, rp_pad, nc_pad, box_rp, W, m, P1, P2, nst, T1, T2, s);
-        case 9: return go_axes<9>(F, rp_pad, nc_pad, box_rp, W, m, P1, P2, nst, T1, T2, s);
-        default: return go_axes<0>(F, rp_pad, nc_pad, box_rp, W, m, P1, P2, nst, T1, T2, s);
+        case 1: return go_axes<1, C>(F, rp_pad, nc_pad, box_rp, W, m, P1, P2, nst, T1, T2, s);
+        case 3: return go_axes<3, C>(F, rp_pad, nc_pad, box_rp, W, m, P1, P2, nst, T1, T2, s);
+        case 5: return go_axes<5, C>(F, rp_pad, nc_pad, box_rp, W, m, P1, P2, nst, T1, T2, s);
+        case 7: return go_axes<7, C>(F, rp_pad, nc_pad, box_rp, W, m, P1, P2, nst, T1, T2, s);
+        case 9: return go_axes<9, C>(F, rp_pad, nc_pad, box_rp, W, m, P1, P2, nst, T1, T2, s);
+        default: return go_axes<0, C>(F, rp_pad, nc_pad, box_rp, W, m, P1, P2, nst, T1, T2, s);
     }
+}
+
+hipError_t launch_axis_transforms(const cd* F, int rp_pad, int nc_pad, const int32_t* box_rp,
+                                  int rmax, Mesh m, const cd* P, int nst, cd* T1, cd* T2,
+                                  hipStream_t s) {
+    return axis_transforms<cd>(F, rp_pad, nc_pad, box_rp, rmax, m, P, nst, T1, T2, s);
+}
+hipError_t launch_axis_transforms_f32(const cf* F, int rp_pad, int nc_pad, const int32_t* box_rp,
+                                      int rmax, Mesh m, const cd* P, int nst, cf* T1, cf* T2,
+                                      hipStream_t s) {
+    return axis_transforms<cf>(F, rp_pad, nc_pad, box_rp, rmax, m, P, nst, T1, T2, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -168,14 +182,15 @@ hipError_t launch_axis_transforms(const cd* F, int rp_pad, int nc_pad, const int
 //   T0[d, R1 R2, c] = sum_R0 P0[k0_d, R0] g[R0 R1 R2, c]          (streams g once)
 //   T1[p, R2, c]    = sum_R1 P1[k1_p, R1] T0[d(p), R1 R2, c]
 //   G[row, c]       = sum_R2 P2[k2, R2] T1[p(row), R2, c]
-// with c over the n_rp nModes nW^2 columns of g.
+// with c over the n_rp nModes nW^2 columns of g; C = cd, or cf for the FP32
+// form (g rounded to FP32 as it is read).
 // ---------------------------------------------------------------------------
-template <int WT>
+template <int WT, class C>
 __global__ __launch_bounds__(256) void re_axis0_kernel(const cd* __restrict__ g, int64_t NC,
                                                        const int32_t* __restrict__ box_re, int Wr,
                                                        const cd* __restrict__ P0,
                                                        const int32_t* __restrict__ d_k0, int d0,
-                                                       cd* __restrict__ T0) {
+                                                       C* __restrict__ T0) {
     constexpr int NV = WT > 0 ? WT : kMaxW;
     const int W = WT > 0 ? WT : Wr;
     const int64_t W2 = (int64_t)W * W;
@@ -184,30 +199,30 @@ __global__ __launch_bounds__(256) void re_axis0_kernel(const cd* __restrict__ g,
          t += (int64_t)gridDim.x * blockDim.x) {
         const int64_t c = t % NC;
         const int64_t p = t / NC;
-        cd v[NV];
+        C v[NV];
 #pragma unroll
         for (int r = 0; r < NV; ++r)
             if (r < W) {
                 const int row = box_re[r * W2 + p];
-                v[r] = row >= 0 ? g[(int64_t)row * NC + c] : cd{0.0, 0.0};
+                v[r] = row >= 0 ? to_c<C>(g[(int64_t)row * NC + c]) : C{0, 0};
             }
         for (int d = 0; d < d0; ++d) {
             const cd* Pk = P0 + (int64_t)d_k0[d] * W;
-            cd acc = {0.0, 0.0};
+            C acc = {0, 0};
 #pragma unroll
             for (int r = 0; r < NV; ++r)
-                if (r < W) acc = cfma(Pk[r], v[r], acc);
+                if (r < W) acc = cfma(to_c<C>(Pk[r]), v[r], acc);
             T0[((int64_t)d * W2 + p) * NC + c] = acc;
         }
     }
 }
 
-template <int WT>
-__global__ __launch_bounds__(256) void re_axis1_kernel(const cd* __restrict__ T0, int64_t NC, int Wr,
+template <int WT, class C>
+__global__ __launch_bounds__(256) void re_axis1_kernel(const C* __restrict__ T0, int64_t NC, int Wr,
                                                        const cd* __restrict__ P1,
                                                        const int32_t* __restrict__ pair_k1,
                                                        const int32_t* __restrict__ pair_off, int d0,
-                                                       cd* __restrict__ T1) {
+                                                       C* __restrict__ T1) {
     constexpr int NV = WT > 0 ? WT : kMaxW;
     const int W = WT > 0 ? WT : Wr;
     const int64_t total = (int64_t)d0 * W * NC;
@@ -217,29 +232,29 @@ __global__ __launch_bounds__(256) void re_axis1_kernel(const cd* __restrict__ T0
         const int64_t dr = t / NC;  // d * W + R2
         const int r2 = (int)(dr % W);
         const int d = (int)(dr / W);
-        cd v[NV];
-        const cd* src = T0 + ((int64_t)d * W * W + r2) * NC + c;
+        C v[NV];
+        const C* src = T0 + ((int64_t)d * W * W + r2) * NC + c;
 #pragma unroll
         for (int r = 0; r < NV; ++r)
             if (r < W) v[r] = src[(int64_t)r * W * NC];
         for (int pp = pair_off[d]; pp < pair_off[d + 1]; ++pp) {
             const cd* Pk = P1 + (int64_t)pair_k1[pp] * W;
-            cd acc = {0.0, 0.0};
+            C acc = {0, 0};
 #pragma unroll
             for (int r = 0; r < NV; ++r)
-                if (r < W) acc = cfma(Pk[r], v[r], acc);
+                if (r < W) acc = cfma(to_c<C>(Pk[r]), v[r], acc);
             T1[((int64_t)pp * W + r2) * NC + c] = acc;
         }
     }
 }
 
-template <int WT>
-__global__ __launch_bounds__(256) void re_axis2_kernel(const cd* __restrict__ T1, int64_t NC, int Wr,
+template <int WT, class C>
+__global__ __launch_bounds__(256) void re_axis2_kernel(const C* __restrict__ T1, int64_t NC, int Wr,
                                                        const cd* __restrict__ P2,
                                                        const int32_t* __restrict__ kp_off,
                                                        const int32_t* __restrict__ k_row,
                                                        const int32_t* __restrict__ k_k2, int d01,
-                                                       cd* __restrict__ G, int64_t ldg) {
+                                                       C* __restrict__ G, int64_t ldg) {
     constexpr int NV = WT > 0 ? WT : kMaxW;
     const int W = WT > 0 ? WT : Wr;
     const int64_t total = (int64_t)d01 * NC;
@@ -247,54 +262,66 @@ __global__ __launch_bounds__(256) void re_axis2_kernel(const cd* __restrict__ T1
          t += (int64_t)gridDim.x * blockDim.x) {
         const int64_t c = t % NC;
         const int pp = (int)(t / NC);
-        cd v[NV];
-        const cd* src = T1 + (int64_t)pp * W * NC + c;
+        C v[NV];
+        const C* src = T1 + (int64_t)pp * W * NC + c;
 #pragma unroll
         for (int r = 0; r < NV; ++r)
             if (r < W) v[r] = src[(int64_t)r * NC];
         for (int i = kp_off[pp]; i < kp_off[pp + 1]; ++i) {
             const cd* Pk = P2 + (int64_t)k_k2[i] * W;
-            cd acc = {0.0, 0.0};
+            C acc = {0, 0};
 #pragma unroll
             for (int r = 0; r < NV; ++r)
-                if (r < W) acc = cfma(Pk[r], v[r], acc);
+                if (r < W) acc = cfma(to_c<C>(Pk[r]), v[r], acc);
             G[(int64_t)k_row[i] * ldg + c] = acc;
         }
     }
 }
 
-template <int WT>
+template <int WT, class C>
 static hipError_t go_re_axes(const cd* g, int64_t NC, const int32_t* box_re, int W, Mesh m,
-                             const cd* P, const ReBatch& b, cd* T0, cd* T1, cd* G, int64_t ldg,
+                             const cd* P, const ReBatch& b, C* T0, C* T1, C* G, int64_t ldg,
                              hipStream_t s) {
     const cd* P1 = P + (int64_t)m.n0 * W;
     const cd* P2 = P1 + (int64_t)m.n1 * W;
-    hipLaunchKernelGGL(re_axis0_kernel<WT>, dim3(gridm((int64_t)W * W * NC, 256)), dim3(256), 0, s,
-                       g, NC, box_re, W, P, b.d_k0, b.d0, T0);
+    hipLaunchKernelGGL((re_axis0_kernel<WT, C>), dim3(gridm((int64_t)W * W * NC, 256)), dim3(256),
+                       0, s, g, NC, box_re, W, P, b.d_k0, b.d0, T0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(re_axis1_kernel<WT>, dim3(gridm((int64_t)b.d0 * W * NC, 256)), dim3(256), 0,
-                       s, T0, NC, W, P1, b.pair_k1, b.pair_off, b.d0, T1);
+    hipLaunchKernelGGL((re_axis1_kernel<WT, C>), dim3(gridm((int64_t)b.d0 * W * NC, 256)),
+                       dim3(256), 0, s, T0, NC, W, P1, b.pair_k1, b.pair_off, b.d0, T1);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(re_axis2_kernel<WT>, dim3(gridm((int64_t)b.d01 * NC, 256)), dim3(256), 0, s,
-                       T1, NC, W, P2, b.kp_off, b.k_row, b.k_k2, b.d01, G, ldg);
+    hipLaunchKernelGGL((re_axis2_kernel<WT, C>), dim3(gridm((int64_t)b.d01 * NC, 256)), dim3(256),
+                       0, s, T1, NC, W, P2, b.kp_off, b.k_row, b.k_k2, b.d01, G, ldg);
     return hipGetLastError();
+}
+
+template <class C>
+static hipError_t re_axes(const cd* g, int64_t NC, const int32_t* box_re, int rmax, Mesh m,
+                          const cd* P, const ReBatch& b, C* T0, C* T1, C* G, int64_t ldg,
+                          hipStream_t s) {
+    const int W = 2 * rmax + 1;
+    if (W > kMaxW || b.d0 <= 0 || b.d01 <= 0) return hipErrorInvalidValue;
+    switch (W) {
+        case 1: return go_re_axes<1, C>(g, NC, box_re, W, m, P, b, T0, T1, G, ldg, s);
+        case 3: return go_re_axes<3, C>(g, NC, box_re, W, m, P, b, T0, T1, G, ldg, s);
+        case 5: return go_re_axes<5, C>(g, NC, box_re, W, m, P, b, T0, T1, G, ldg, s);
+        case 7: return go_re_axes<7, C>(g, NC, box_re, W, m, P, b, T0, T1, G, ldg, s);
+        case 9: return go_re_axes<9, C>(g, NC, box_re, W, m, P, b, T0, T1, G, ldg, s);
+        default: return go_re_axes<0, C>(g, NC, box_re, W, m, P, b, T0, T1, G, ldg, s);
+    }
 }
 
 hipError_t launch_re_axes(const cd* g, int64_t NC, const int32_t* box_re, int rmax, Mesh m,
                           const cd* P, const ReBatch& b, cd* T0, cd* T1, cd* G, int64_t ldg,
                           hipStream_t s) {
-    const int W = 2 * rmax + 1;
-    if (W > kMaxW || b.d0 <= 0 || b.d01 <= 0) return hipErrorInvalidValue;
-    switch (W) {
-        case 1: return go_re_axes<1>(g, NC, box_re, W, m, P, b, T0, T1, G, ldg, s);
-        case 3: return go_re_axes<3>(g, NC, box_re, W, m, P, b, T0, T1, G, ldg, s);
-        case 5: return go_re_axes<5>(g, NC, box_re, W, m, P, b, T0, T1, G, ldg, s);
-        case 7: return go_re_axes<7>(g, NC, box_re, W, m, P, b, T0, T1, G, ldg, s);
-        case 9: return go_re_axes<9>(g, NC, box_re, W, m, P, b, T0, T1, G, ldg, s);
-        default: return go_re_axes<0>(g, NC, box_re, W, m, P, b, T0, T1, G, ldg, s);
-    }
+    return re_axes<cd>(g, NC, box_re, rmax, m, P, b, T0, T1, G, ldg, s);
+}
+hipError_t launch_re_axes_f32(const cd* g, int64_t NC, const int32_t* box_re, int rmax, Mesh m,
+                              const cd* P, const ReBatch& b, cf* T0, cf* T1, cf* G, int64_t ldg,
+                              hipStream_t s) {
+    return re_axes<cf>(g, NC, box_re, rmax, m, P, b, T0, T1, G, ldg, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -331,9 +358,27 @@ __device__ inline double row16_sum(double x) {
     x += dpp_f64<0x140>(x);
     return x;
 }
+template <int CTRL>
+__device__ inline float dpp_f32(float x) {
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
+}
+__device__ inline float row16_sum(float x) {
+    x += dpp_f32<0xB1>(x);
+    x += dpp_f32<0x4E>(x);
+    x += dpp_f32<0x141>(x);
+    x += dpp_f32<0x140>(x);
+    return x;
+}
 
-template <int TN>
-__global__ __launch_bounds__(256, 2) void line_rates_kernel(RateArgs a) {
+// C = cd: FP64 on v_mfma_f64_16x16x4f64 (result v of lane l is row l/16 + 4v);
+// C = cf: the FP32 form on v_mfma_f32_16x16x4f32 (row 4(l/16) + v), with the
+// rotations in FP32 and the Gaussian terms and sums in FP64.
+template <int TN, class C>
+__global__ __launch_bounds__(256, (TN >= 6 ? 2 : 4)) void line_rates_kernel(RateArgs a) {
+    using R = decltype(C::x);
+    constexpr bool F64 = sizeof(R) == 8;
+    using V4 = std::conditional_t<F64, d4, f4>;
     extern __shared__ char smem_raw[];
     const int W = a.W;
     const int Wp = (W + 3) & ~3;
@@ -342,8 +387,8 @@ __global__ __launch_bounds__(256, 2) void line_rates_kernel(RateArgs a) {
     const int N0 = mesh.n0;
     const int N0p = (N0 + 15) & ~15;
     const int ldf = a.nc_pad;
-    cd* sP = reinterpret_cast<cd*>(smem_raw);     // [N0p][Wp]
-    cd* sY = sP + N0p * Wp;                       // [16][kMBL][nm]
+    C* sP = reinterpret_cast<C*>(smem_raw);       // [N0p][Wp]
+    C* sY = sP + N0p * Wp;                        // [16][kMBL][nm]
     __shared__ double sRed[4];
 
     // XCD-aware order: work-groups are dealt to the 8 XCDs round-robin, so
@@ -363,7 +408,7 @@ __global__ __launch_bounds__(256, 2) void line_rates_kernel(RateArgs a) {
 
     for (int i = tid; i < N0p * Wp; i += 256) {
         const int q0 = i / Wp, r = i - q0 * Wp;
-        sP[i] = (q0 < N0 && r < W) ? a.P0[q0 * W + r] : cd{0.0, 0.0};
+        sP[i] = (q0 < N0 && r < W) ? to_c<C>(a.P0[q0 * W + r]) : C{0, 0};
     }
 
     const int kmesh = a.st_kmesh[st];
@@ -379,7 +424,8 @@ __global__ __launch_bounds__(256, 2) void line_rates_kernel(RateArgs a) {
     // FP64 subnormal, so such a Gaussian is exactly 0
     const double cut = 27.5 * a.sigma;
     const int colbase = wave * TN * 16 + li;
-    const cd* Tst = a.T2 + (int64_t)st * W * NL * ldf + (int64_t)line * ldf + colbase;
+    const C* Tst = reinterpret_cast<const C*>(a.T2) + (int64_t)st * W * NL * ldf +
+                   (int64_t)line * ldf + colbase;
     double gacc = 0.0;
     __syncthreads();
 
@@ -398,36 +444,42 @@ __global__ __launch_bounds__(256, 2) void line_rates_kernel(RateArgs a) {
         int kqv[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int q0 = qc + lg + 4 * v;
+            const int q0 = qc + (F64 ? lg + 4 * v : 4 * lg + v);
             kqv[v] = q0 < N0 ? ((k0i + q0) % mesh.n0) * NL + kq12 : -1;
         }
-        d4 cr[TN], ci[TN];
+        V4 cr[TN], ci[TN];
 #pragma unroll
         for (int t = 0; t < TN; ++t) {
-            cr[t] = d4{0, 0, 0, 0};
-            ci[t] = d4{0, 0, 0, 0};
+            cr[t] = V4{0, 0, 0, 0};
+            ci[t] = V4{0, 0, 0, 0};
         }
         for (int k0 = 0; k0 < Wp; k0 += 4) {
             const int k = k0 + lg;
-            cd bc[TN];
+            C bc[TN];
             if (k < W) {
-                const cd* Tr = Tst + (int64_t)k * NL * ldf;
+                const C* Tr = Tst + (int64_t)k * NL * ldf;
 #pragma unroll
                 for (int t = 0; t < TN; ++t) bc[t] = Tr[t * 16];
             } else {
 #pragma unroll
-                for (int t = 0; t < TN; ++t) bc[t] = cd{0.0, 0.0};
+                for (int t = 0; t < TN; ++t) bc[t] = C{0, 0};
             }
-            const cd ph = sP[(qc + li) * Wp + k];
+            const C ph = sP[(qc + li) * Wp + k];
+            auto mfma = [](R x, R y, V4 c) {
+                if constexpr (F64)
+                    return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0);
+                else
+                    return __builtin_amdgcn_mfma_f32_16x16x4f32(x, y, c, 0, 0, 0);
+            };
 #pragma unroll
             for (int t = 0; t < TN; ++t) {
-                cr[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ph.x, bc[t].x, cr[t], 0, 0, 0);
-                ci[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ph.x, bc[t].y, ci[t], 0, 0, 0);
+                cr[t] = mfma(ph.x, bc[t].x, cr[t]);
+                ci[t] = mfma(ph.x, bc[t].y, ci[t]);
             }
 #pragma unroll
             for (int t = 0; t < TN; ++t) {
-                cr[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ph.y, bc[t].y, cr[t], 0, 0, 0);
-                ci[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ph.y, bc[t].x, ci[t], 0, 0, 0);
+                cr[t] = mfma(-ph.y, bc[t].y, cr[t]);
+                ci[t] = mfma(ph.y, bc[t].x, ci[t]);
             }
         }
         for (int m0 = mlo; m0 <= mhi; m0 += kMBL) {
@@ -436,16 +488,16 @@ __global__ __launch_bounds__(256, 2) void line_rates_kernel(RateArgs a) {
             for (int mb = 0; mb < nmb; ++mb) {
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    cd u = {0.0, 0.0};
-                    if (kqv[v] >= 0 && li < nW)
-                        u = a.U[((int64_t)kqv[v] * nW + m0 + mb) * nW + li];  // eigenvector m
+                    C u = {0, 0};
+                    if (kqv[v] >= 0 && li < nW)  // eigenvector m
+                        u = to_c<C>(a.U[((int64_t)kqv[v] * nW + m0 + mb) * nW + li]);
+                    const int row = F64 ? lg + 4 * v : 4 * lg + v;
 #pragma unroll
                     for (int t = 0; t < TN; ++t) {
-                        const double yr = row16_sum(cr[t][v] * u.x - ci[t][v] * u.y);
-                        const double yi = row16_sum(cr[t][v] * u.y + ci[t][v] * u.x);
+                        const R yr = row16_sum(cr[t][v] * u.x - ci[t][v] * u.y);
+                        const R yi = row16_sum(cr[t][v] * u.y + ci[t][v] * u.x);
                         const int sa = wave * TN + t;
-                        if (li == 0 && sa < nm)
-                            sY[((lg + 4 * v) * kMBL + mb) * nm + sa] = cd{yr, yi};
+                        if (li == 0 && sa < nm) sY[(row * kMBL + mb) * nm + sa] = C{yr, yi};
                     }
                 }
             }
@@ -467,10 +519,10 @@ __global__ __launch_bounds__(256, 2) void line_rates_kernel(RateArgs a) {
                 if (fabs(y1) > cut && fabs(y2) > cut) continue;
                 const double fm = a.focc[kq * nW + m];
                 const double nbq = a.nb[q * nm + nu];
-                const cd* Yr = sY + (c * kMBL + mb) * nm;
+                const C* Yr = sY + (c * kMBL + mb) * nm;
                 const cd* Eq = a.E + q * nm * nm + nu;
-                cd z = {0.0, 0.0};
-                for (int sa = 0; sa < nm; ++sa) z = cfma(Eq[sa * nm], Yr[sa], z);
+                C z = {0, 0};
+                for (int sa = 0; sa < nm; ++sa) z = cfma(to_c<C>(Eq[sa * nm]), Yr[sa], z);
                 const double g1 = exp(-y1 * y1 * inv_s2), g2 = exp(-y2 * y2 * inv_s2);
                 const double term = cabs2(z) * ((nbq + 1.0 - fm) * g1 + (nbq + fm) * g2);
                 gacc += term;
@@ -488,9 +540,9 @@ __global__ __launch_bounds__(256, 2) void line_rates_kernel(RateArgs a) {
     if (tid == 0) a.partial[(int64_t)st * a.n_qtiles + line] = (sRed[0] + sRed[1]) + (sRed[2] + sRed[3]);
 }
 
-size_t line_rates_lds(int W, int N0, int nm) {
+size_t line_rates_lds(int W, int N0, int nm, bool f32) {
     const int Wp = (W + 3) & ~3, N0p = (N0 + 15) & ~15;
-    return ((size_t)N0p * Wp + 16 * (size_t)kMBL * nm) * sizeof(cd);
+    return ((size_t)N0p * Wp + 16 * (size_t)kMBL * nm) * (f32 ? sizeof(cf) : sizeof(cd));
 }
 
 // Columns of the factorised form: one 16-wide tile per mode index, 4 waves x TN tiles.
@@ -500,11 +552,11 @@ int line_rates_ncpad(int nm, int nW) {
     return 64 * (tn == 5 ? 6 : (tn == 7 ? 8 : tn));
 }
 
-template <int TN>
+template <int TN, class C>
 static hipError_t go_line(const RateArgs& a, int nst, hipStream_t s) {
-    const size_t shm = line_rates_lds(a.W, a.mesh.n0, a.nm);
+    const size_t shm = line_rates_lds(a.W, a.mesh.n0, a.nm, sizeof(C) == sizeof(cf));
     if (shm > 64 * 1024) return hipErrorInvalidValue;
-    hipError_t e = hipFuncSetAttribute((const void*)line_rates_kernel<TN>,
+    hipError_t e = hipFuncSetAttribute((const void*)line_rates_kernel<TN, C>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) return e;
     const int64_t NL = (int64_t)a.mesh.n1 * a.mesh.n2;
@@ -513,7 +565,7 @@ static hipError_t go_line(const RateArgs& a, int nst, hipStream_t s) {
     for (int s0 = 0; s0 < nst; s0 += chunk) {
         const int ns = nst - s0 < chunk ? nst - s0 : chunk;
         RateArgs b = a;
-        b.T2 = a.T2 + (int64_t)s0 * a.W * NL * a.nc_pad;
+        b.T2 = reinterpret_cast<const C*>(a.T2) + (int64_t)s0 * a.W * NL * a.nc_pad;
         b.st_kmesh += s0;
         b.st_band += s0;
         b.st_row += s0;
@@ -522,26 +574,34 @@ static hipError_t go_line(const RateArgs& a, int nst, hipStream_t s) {
         b.partial = a.partial + (int64_t)s0 * a.n_qtiles;
         if (a.terms) b.terms = a.terms + (int64_t)s0 * a.nq_mesh * a.nm;
         b.n_states = ns;
-        hipLaunchKernelGGL((line_rates_kernel<TN>), dim3((unsigned)(groups * 8 * ns)), dim3(256), shm,
-                           s, b);
+        hipLaunchKernelGGL((line_rates_kernel<TN, C>), dim3((unsigned)(groups * 8 * ns)), dim3(256),
+                           shm, s, b);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_line_rates(const RateArgs& a, int nst, hipStream_t s) {
+template <class C>
+static hipError_t line_rates(const RateArgs& a, int nst, hipStream_t s) {
     if (nst <= 0) return hipSuccess;
     if (a.n_qtiles != a.mesh.n1 * a.mesh.n2 || a.n_qtiles > 65535 || a.W > kMaxW ||
         line_rates_ncpad(a.nm, a.nW) != a.nc_pad)
         return hipErrorInvalidValue;
     switch (a.nc_pad / 64) {
-        case 1: return go_line<1>(a, nst, s);
-        case 2: return go_line<2>(a, nst, s);
-        case 3: return go_line<3>(a, nst, s);
-        case 4: return go_line<4>(a, nst, s);
-        case 6: return go_line<6>(a, nst, s);
-        case 8: return go_line<8>(a, nst, s);
+        case 1: return go_line<1, C>(a, nst, s);
+        case 2: return go_line<2, C>(a, nst, s);
+        case 3: return go_line<3, C>(a, nst, s);
+        case 4: return go_line<4, C>(a, nst, s);
+        case 6: return go_line<6, C>(a, nst, s);
+        case 8: return go_line<8, C>(a, nst, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_line_rates(const RateArgs& a, int nst, hipStream_t s) {
+    return line_rates<cd>(a, nst, s);
+}
+hipError_t launch_line_rates_f32(const RateArgs& a, int nst, hipStream_t s) {
+    return line_rates<cf>(a, nst, s);
 }
 
 }  // namespace phx

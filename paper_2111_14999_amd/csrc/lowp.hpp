@@ -5,10 +5,6 @@
 
 namespace phx {
 
-struct cf {
-    float x, y;
-};
-
 constexpr int kMBLP = 8;  // final bands per rotation pass
 
 struct RateArgsLP {
@@ -46,8 +42,8 @@ hipError_t launch_cgemm_lp_cf(int prec, const cd* A, int64_t lda, const cf* B, i
                               int64_t ldc, int64_t M, int64_t N, int K, hipStream_t s);
 hipError_t launch_fold_uk_lp(int prec, const cf* G, int64_t ldg, const cd* U,
                              const int32_t* st_row, int row0, const int32_t* st_kmesh,
-                             const int32_t* st_band, int nst, int n_rp, int nm, int nW, int rp_pad,
-                             int nc_pad, void* F, hipStream_t s);
+                             const int32_t* st_band, int nst, int n_rp, int nm, int nW, int cw,
+                             int rp_pad, int nc_pad, void* F, hipStream_t s);
 hipError_t launch_stage2_rates_lp(int prec, const RateArgsLP& a, int nst, hipStream_t s);
 size_t stage2_lp_lds(int prec, int tq, int rmax, int rp_pad, int nc_pad, int nm);
 int stage2_lp_config(int nm, int nW, int* tq_out, int* tn_out);

@@ -108,3 +108,37 @@ def test_ragged_windows(lib, prec, seed, nW, nat, mesh):
     mx, med, ab = rel_err(g, ref["gamma"])
     print(f"[{prec}] ragged Gamma rel err max {mx:.3e} median {med:.3e}", flush=True)
     assert mx < GAMMA_BOUND[prec]
+
+
+@pytest.mark.parametrize("case", ["toy", "sparse-r", "ragged-5x6x7"])
+def test_fp32_mesh_sum_forms(lib, toy, case):
+    """FP32 form: the direct and the factorised full-mesh sums both meet the FP32 bound."""
+    if case == "toy":
+        s, mesh, par, ref = toy
+    else:
+        rng = np.random.default_rng(8)
+        s = synth.small_system(77, n_wannier=5, n_atoms=2, r=2)
+        if case == "sparse-r":
+            keep_e = np.sort(rng.choice(len(s.re), size=40, replace=False))
+            keep_p = np.sort(rng.choice(len(s.rp), size=50, replace=False))
+            s.re, s.rp = s.re[keep_e].copy(), s.rp[keep_p].copy()
+            s.g_rr = np.ascontiguousarray(s.g_rr[keep_e][:, keep_p])
+            mesh = (6, 4, 5)
+        else:
+            mesh = (5, 6, 7)
+        s.h_r *= 0.3
+        t = rates.mesh_tables(s, mesh)
+        mu = float(np.median(t["eps"]))
+        par = dict(mu=mu, kT=constants.kT_of(300.0), sigma=0.05, win_lo=mu - 0.8,
+                   win_hi=mu + 0.8, omega_min=1e-4)
+        ref = rates.scattering_rates(s, mesh, tables=t, **par)
+    try:
+        for mode in ("direct", "factored"):
+            lib.set_mesh_sum(mode)
+            n, g = _rates(lib, s, mesh, par, "fp32")
+            assert n == len(ref["k_idx"])
+            mx, med, ab = rel_err(g, ref["gamma"])
+            print(f"[fp32 {mode}] {case} Gamma rel err max {mx:.3e} median {med:.3e}", flush=True)
+            assert mx < GAMMA_BOUND["fp32"]
+    finally:
+        lib.set_mesh_sum("auto")
