@@ -242,8 +242,13 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
-__global__ __launch_bounds__(64) void eig_herm_kernel(cd* __restrict__ Aall, int n, double* __restrict__ w_out,
+// NT > 0 fixes the matrix order at compile time (index arithmetic without
+// integer division); NT = 0 takes it from the argument.
+template <int NT>
+__global__ __launch_bounds__(64) void eig_herm_kernel(cd* __restrict__ Aall, int n_arg,
+                                                      double* __restrict__ w_out,
                                                       cd* __restrict__ V_out) {
+    const int n = NT > 0 ? NT : n_arg;
     extern __shared__ char smem_raw[];
     cd* A = reinterpret_cast<cd*>(smem_raw);
     const int ld = n + 1;
@@ -371,8 +376,23 @@ hipError_t launch_eig_herm(cd* A, int n, int64_t batch, double* w, cd* V, hipStr
                        h * sizeof(cd) + 2 * h * sizeof(int);
     for (int64_t b0 = 0; b0 < batch; b0 += 2000000000LL) {
         const int64_t nb = batch - b0 < 2000000000LL ? batch - b0 : 2000000000LL;
-        hipLaunchKernelGGL(eig_herm_kernel, dim3((unsigned)nb), dim3(64), shm, s,
-                           A + b0 * n * n, n, w + b0 * n, V + b0 * n * n);
+        cd* Ab = A + b0 * n * n;
+        double* wb = w + b0 * n;
+        cd* Vb = V + b0 * n * n;
+        switch (n) {
+#define PHX_EIG(NV)                                                                             \
+    case NV:                                                                                    \
+        hipLaunchKernelGGL(eig_herm_kernel<NV>, dim3((unsigned)nb), dim3(64), shm, s, Ab, n, wb, \
+                           Vb);                                                                 \
+        break;
+            PHX_EIG(3) PHX_EIG(4) PHX_EIG(5) PHX_EIG(6) PHX_EIG(7) PHX_EIG(8) PHX_EIG(9)
+            PHX_EIG(10) PHX_EIG(12) PHX_EIG(14) PHX_EIG(15) PHX_EIG(16) PHX_EIG(18) PHX_EIG(20)
+            PHX_EIG(21) PHX_EIG(24) PHX_EIG(27) PHX_EIG(30)
+#undef PHX_EIG
+            default:
+                hipLaunchKernelGGL(eig_herm_kernel<0>, dim3((unsigned)nb), dim3(64), shm, s, Ab, n,
+                                   wb, Vb);
+        }
     }
     return hipGetLastError();
 }
