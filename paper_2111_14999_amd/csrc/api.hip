@@ -392,8 +392,9 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
         const int rmax_e = rmax_of(sys->re, n_re);
         const int We = 2 * rmax_e + 1;
         const bool re_fact = factored && rmax_e <= 15 &&
+                             re_axes_lds(rmax_e, lowp) <= 160 * 1024 &&
                              (h->mesh_sum == PHOEBE_MESH_SUM_FACTORED || 2 * We <= n_re);
-        constexpr int kD0Max = 8, kD01Max = 64;
+        constexpr int kD0Max = 8, kD01Max = 256;
         int BK = re_fact ? 256 : 64;
         while (BK > 16 && ((double)BK * NC2 * g_elem > 8e9 ||
                            (double)BK * nW * rp_pad * nc_pad * f_elem > 8e9))
@@ -498,8 +499,7 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                                    (size_t)max_states * rp_pad * nc_pad * f_elem +
                                    (size_t)max_states * n_qtiles * sizeof(double) +
                                    (factored ? (size_t)nsb * t12_state + 512 : 0) +
-                                   (re_fact ? ((size_t)kD0Max * We * We + (size_t)kD01Max * We) *
-                                                      NC2 * g_elem +
+                                   (re_fact ? (size_t)kD0Max * We * We * NC2 * g_elem +
                                                   (size_t)rows_cap * 160 * sizeof(int32_t) + 1024
                                             : 0);
         ensure_ws(h, tables_end + std::max(scratch_bands, batch_bytes) + 256);
@@ -618,7 +618,7 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
         // ---- phase B: batches of kept-k rows ----
         // Direct stage 1: BK rows each.  Factorised stage 1: consecutive rows
         // while the batch holds at most BK rows, kD0Max distinct k0 and kD01Max
-        // distinct (k0, k1), with the grouping lists the three axis kernels use.
+        // distinct (k0, k1), with the grouping lists the axis kernels use.
         std::vector<std::pair<int64_t, int64_t>> batches;
         std::vector<int32_t> rbh;          // grouping lists of every batch, one array
         std::vector<std::array<int64_t, 8>> rbo;  // per batch: d0, d01, offsets of the 6 lists
@@ -697,7 +697,6 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
             HIPCHK(h, hipMemcpyAsync(rbd, rbh.data(), sizeof(int32_t) * rbh.size(),
                                      hipMemcpyHostToDevice, s));
         char* T0re = re_fact ? ar.take<char>((size_t)kD0Max * We * We * NC2 * g_elem) : nullptr;
-        char* T1re = re_fact ? ar.take<char>((size_t)kD01Max * We * NC2 * g_elem) : nullptr;
         cd* P1 = ar.take<cd>((size_t)BK * n_re);
         char* Gbuf = ar.take<char>((size_t)BK * NC2 * g_elem);
         char* Fbuf = ar.take<char>((size_t)max_states * rp_pad * nc_pad * f_elem);
@@ -724,16 +723,13 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                     HIPCHK(h, launch_re_axes_f32(reinterpret_cast<const cd*>(sys->g_rr), NC2,
                                                  T.box_re, rmax_e, mesh, T.Pre, rb,
                                                  reinterpret_cast<cf*>(T0re),
-                                                 reinterpret_cast<cf*>(T1re),
                                                  reinterpret_cast<cf*>(Gbuf), NC2, s));
                 else
                     HIPCHK(h, launch_re_axes(reinterpret_cast<const cd*>(sys->g_rr), NC2, T.box_re,
                                              rmax_e, mesh, T.Pre, rb, reinterpret_cast<cd*>(T0re),
-                                             reinterpret_cast<cd*>(T1re),
                                              reinterpret_cast<cd*>(Gbuf), NC2, s));
-                // g (FP64) read once; T0 and T1 written and read once; G written once
-                t1.done((double)NC2 * (16.0 * n_re + (double)g_elem * (2.0 * rb.d0 * We * We +
-                                                                        2.0 * rb.d01 * We + nb)));
+                // g (FP64) read once; T0 written and read once; G written once
+                t1.done((double)NC2 * (16.0 * n_re + (double)g_elem * (2.0 * rb.d0 * We * We + nb)));
             } else {
             HIPCHK(h, launch_phase_table(nullptr, kept + r0, mesh, nb, T.re, n_re, P1, n_re, s));
             Timer t1(h, s, "stage1_phase");

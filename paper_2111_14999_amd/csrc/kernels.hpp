@@ -115,11 +115,12 @@ struct ReBatch {
     const int32_t *d_k0, *pair_k1, *pair_off, *kp_off, *k_row, *k_k2;
 };
 hipError_t launch_re_axes(const cd* g, int64_t NC, const int32_t* box_re, int rmax, Mesh m,
-                          const cd* P, const ReBatch& b, cd* T0, cd* T1, cd* G, int64_t ldg,
+                          const cd* P, const ReBatch& b, cd* T0, cd* G, int64_t ldg,
                           hipStream_t s);
 hipError_t launch_re_axes_f32(const cd* g, int64_t NC, const int32_t* box_re, int rmax, Mesh m,
-                              const cd* P, const ReBatch& b, cf* T0, cf* T1, cf* G, int64_t ldg,
+                              const cd* P, const ReBatch& b, cf* T0, cf* G, int64_t ldg,
                               hipStream_t s);
+size_t re_axes_lds(int rmax, bool f32);
 
 // Axis 0 on MFMA + rotations + rate terms, one work-group per (state, q1, q2) line.
 // Columns sa*16 + b (nW <= 16), nc_pad = 64 TN with 4 TN >= nModes.

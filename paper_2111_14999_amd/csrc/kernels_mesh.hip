@@ -180,7 +180,7 @@ hipError_t launch_axis_transforms_f32(const cf* F, int rp_pad, int nc_pad, const
 // time over the distinct k0 of the batch, then the distinct (k0, k1) pairs,
 // then each k:
 //   T0[d, R1 R2, c] = sum_R0 P0[k0_d, R0] g[R0 R1 R2, c]          (streams g once)
-//   T1[p, R2, c]    = sum_R1 P1[k1_p, R1] T0[d(p), R1 R2, c]
+//   T1[p, R2, c]    = sum_R1 P1[k1_p, R1] T0[d(p), R1 R2, c]      (registers only)
 //   G[row, c]       = sum_R2 P2[k2, R2] T1[p(row), R2, c]
 // with c over the n_rp nModes nW^2 columns of g; C = cd, or cf for the FP32
 // form (g rounded to FP32 as it is read).
@@ -217,70 +217,65 @@ __global__ __launch_bounds__(256) void re_axis0_kernel(const cd* __restrict__ g,
     }
 }
 
+// The (k0, k1) and k steps, fused: a work-group takes one distinct k0 (d) and
+// 64 columns; T0[d, :, cols] (W^2 x 64) is staged in LDS once, and the four
+// thread groups take the pairs of d in turn, each forming
+//   T1[R2] = sum_R1 P1[k1, R1] T0[R1 R2]   in registers, then
+//   G[row] = sum_R2 P2[k2, R2] T1[R2]      for the pair's rows,
+// so the pair intermediate never reaches memory.
 template <int WT, class C>
-__global__ __launch_bounds__(256) void re_axis1_kernel(const C* __restrict__ T0, int64_t NC, int Wr,
-                                                       const cd* __restrict__ P1,
-                                                       const int32_t* __restrict__ pair_k1,
-                                                       const int32_t* __restrict__ pair_off, int d0,
-                                                       C* __restrict__ T1) {
+__global__ __launch_bounds__(256) void re_axis12_kernel(const C* __restrict__ T0, int64_t NC, int Wr,
+                                                        const cd* __restrict__ P1,
+                                                        const cd* __restrict__ P2,
+                                                        const int32_t* __restrict__ pair_k1,
+                                                        const int32_t* __restrict__ pair_off,
+                                                        const int32_t* __restrict__ kp_off,
+                                                        const int32_t* __restrict__ k_row,
+                                                        const int32_t* __restrict__ k_k2, int64_t ncb,
+                                                        C* __restrict__ G, int64_t ldg) {
     constexpr int NV = WT > 0 ? WT : kMaxW;
     const int W = WT > 0 ? WT : Wr;
-    const int64_t total = (int64_t)d0 * W * NC;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t c = t % NC;
-        const int64_t dr = t / NC;  // d * W + R2
-        const int r2 = (int)(dr % W);
-        const int d = (int)(dr / W);
-        C v[NV];
-        const C* src = T0 + ((int64_t)d * W * W + r2) * NC + c;
-#pragma unroll
-        for (int r = 0; r < NV; ++r)
-            if (r < W) v[r] = src[(int64_t)r * W * NC];
-        for (int pp = pair_off[d]; pp < pair_off[d + 1]; ++pp) {
-            const cd* Pk = P1 + (int64_t)pair_k1[pp] * W;
-            C acc = {0, 0};
-#pragma unroll
-            for (int r = 0; r < NV; ++r)
-                if (r < W) acc = cfma(to_c<C>(Pk[r]), v[r], acc);
-            T1[((int64_t)pp * W + r2) * NC + c] = acc;
-        }
+    extern __shared__ char smem_raw[];
+    C* sT = reinterpret_cast<C*>(smem_raw);  // [W^2][64]
+    const int d = (int)(blockIdx.x / ncb);
+    const int64_t c0 = (blockIdx.x % ncb) * 64;
+    const int tid = threadIdx.x;
+    const C* src = T0 + (int64_t)d * W * W * NC + c0;
+    for (int i = tid; i < W * W * 64; i += 256) {
+        const int rr = i >> 6, cc = i & 63;
+        sT[i] = c0 + cc < NC ? src[(int64_t)rr * NC + cc] : C{0, 0};
     }
-}
-
-template <int WT, class C>
-__global__ __launch_bounds__(256) void re_axis2_kernel(const C* __restrict__ T1, int64_t NC, int Wr,
-                                                       const cd* __restrict__ P2,
-                                                       const int32_t* __restrict__ kp_off,
-                                                       const int32_t* __restrict__ k_row,
-                                                       const int32_t* __restrict__ k_k2, int d01,
-                                                       C* __restrict__ G, int64_t ldg) {
-    constexpr int NV = WT > 0 ? WT : kMaxW;
-    const int W = WT > 0 ? WT : Wr;
-    const int64_t total = (int64_t)d01 * NC;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t c = t % NC;
-        const int pp = (int)(t / NC);
-        C v[NV];
-        const C* src = T1 + (int64_t)pp * W * NC + c;
+    __syncthreads();
+    const int cc = tid & 63, tg = tid >> 6;
+    const int64_t c = c0 + cc;
+    for (int pp = pair_off[d] + tg; pp < pair_off[d + 1]; pp += 4) {
+        const cd* Pk1 = P1 + (int64_t)pair_k1[pp] * W;
+        C t1[NV];
 #pragma unroll
-        for (int r = 0; r < NV; ++r)
-            if (r < W) v[r] = src[(int64_t)r * NC];
+        for (int r2 = 0; r2 < NV; ++r2) t1[r2] = C{0, 0};
+        // one R1 row at a time keeps the register footprint to the W sums
+#pragma unroll 1
+        for (int r1 = 0; r1 < W; ++r1) {
+            const C p1 = to_c<C>(Pk1[r1]);
+            const C* row = sT + r1 * W * 64 + cc;
+#pragma unroll
+            for (int r2 = 0; r2 < NV; ++r2)
+                if (r2 < W) t1[r2] = cfma(p1, row[r2 * 64], t1[r2]);
+        }
         for (int i = kp_off[pp]; i < kp_off[pp + 1]; ++i) {
-            const cd* Pk = P2 + (int64_t)k_k2[i] * W;
+            const cd* Pk2 = P2 + (int64_t)k_k2[i] * W;
             C acc = {0, 0};
 #pragma unroll
-            for (int r = 0; r < NV; ++r)
-                if (r < W) acc = cfma(to_c<C>(Pk[r]), v[r], acc);
-            G[(int64_t)k_row[i] * ldg + c] = acc;
+            for (int r2 = 0; r2 < NV; ++r2)
+                if (r2 < W) acc = cfma(to_c<C>(Pk2[r2]), t1[r2], acc);
+            if (c < NC) G[(int64_t)k_row[i] * ldg + c] = acc;
         }
     }
 }
 
 template <int WT, class C>
 static hipError_t go_re_axes(const cd* g, int64_t NC, const int32_t* box_re, int W, Mesh m,
-                             const cd* P, const ReBatch& b, C* T0, C* T1, C* G, int64_t ldg,
+                             const cd* P, const ReBatch& b, C* T0, C* G, int64_t ldg,
                              hipStream_t s) {
     const cd* P1 = P + (int64_t)m.n0 * W;
     const cd* P2 = P1 + (int64_t)m.n1 * W;
@@ -288,40 +283,49 @@ static hipError_t go_re_axes(const cd* g, int64_t NC, const int32_t* box_re, int
                        0, s, g, NC, box_re, W, P, b.d_k0, b.d0, T0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((re_axis1_kernel<WT, C>), dim3(gridm((int64_t)b.d0 * W * NC, 256)),
-                       dim3(256), 0, s, T0, NC, W, P1, b.pair_k1, b.pair_off, b.d0, T1);
-    e = hipGetLastError();
+    const size_t shm = (size_t)W * W * 64 * sizeof(C);
+    e = hipFuncSetAttribute((const void*)re_axis12_kernel<WT, C>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((re_axis2_kernel<WT, C>), dim3(gridm((int64_t)b.d01 * NC, 256)), dim3(256),
-                       0, s, T1, NC, W, P2, b.kp_off, b.k_row, b.k_k2, b.d01, G, ldg);
+    const int64_t ncb = (NC + 63) / 64;
+    if ((int64_t)b.d0 * ncb > 2147483647LL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((re_axis12_kernel<WT, C>), dim3((unsigned)(b.d0 * ncb)), dim3(256), shm, s,
+                       T0, NC, W, P1, P2, b.pair_k1, b.pair_off, b.kp_off, b.k_row, b.k_k2, ncb, G,
+                       ldg);
     return hipGetLastError();
+}
+
+// LDS of the fused kernel: W^2 x 64 staged values
+size_t re_axes_lds(int rmax, bool f32) {
+    const int W = 2 * rmax + 1;
+    return (size_t)W * W * 64 * (f32 ? sizeof(cf) : sizeof(cd));
 }
 
 template <class C>
 static hipError_t re_axes(const cd* g, int64_t NC, const int32_t* box_re, int rmax, Mesh m,
-                          const cd* P, const ReBatch& b, C* T0, C* T1, C* G, int64_t ldg,
-                          hipStream_t s) {
+                          const cd* P, const ReBatch& b, C* T0, C* G, int64_t ldg, hipStream_t s) {
     const int W = 2 * rmax + 1;
-    if (W > kMaxW || b.d0 <= 0 || b.d01 <= 0) return hipErrorInvalidValue;
+    if (W > kMaxW || b.d0 <= 0 || b.d01 <= 0 || re_axes_lds(rmax, sizeof(C) == sizeof(cf)) > 160 * 1024)
+        return hipErrorInvalidValue;
     switch (W) {
-        case 1: return go_re_axes<1, C>(g, NC, box_re, W, m, P, b, T0, T1, G, ldg, s);
-        case 3: return go_re_axes<3, C>(g, NC, box_re, W, m, P, b, T0, T1, G, ldg, s);
-        case 5: return go_re_axes<5, C>(g, NC, box_re, W, m, P, b, T0, T1, G, ldg, s);
-        case 7: return go_re_axes<7, C>(g, NC, box_re, W, m, P, b, T0, T1, G, ldg, s);
-        case 9: return go_re_axes<9, C>(g, NC, box_re, W, m, P, b, T0, T1, G, ldg, s);
-        default: return go_re_axes<0, C>(g, NC, box_re, W, m, P, b, T0, T1, G, ldg, s);
+        case 1: return go_re_axes<1, C>(g, NC, box_re, W, m, P, b, T0, G, ldg, s);
+        case 3: return go_re_axes<3, C>(g, NC, box_re, W, m, P, b, T0, G, ldg, s);
+        case 5: return go_re_axes<5, C>(g, NC, box_re, W, m, P, b, T0, G, ldg, s);
+        case 7: return go_re_axes<7, C>(g, NC, box_re, W, m, P, b, T0, G, ldg, s);
+        case 9: return go_re_axes<9, C>(g, NC, box_re, W, m, P, b, T0, G, ldg, s);
+        default: return go_re_axes<0, C>(g, NC, box_re, W, m, P, b, T0, G, ldg, s);
     }
 }
 
 hipError_t launch_re_axes(const cd* g, int64_t NC, const int32_t* box_re, int rmax, Mesh m,
-                          const cd* P, const ReBatch& b, cd* T0, cd* T1, cd* G, int64_t ldg,
+                          const cd* P, const ReBatch& b, cd* T0, cd* G, int64_t ldg,
                           hipStream_t s) {
-    return re_axes<cd>(g, NC, box_re, rmax, m, P, b, T0, T1, G, ldg, s);
+    return re_axes<cd>(g, NC, box_re, rmax, m, P, b, T0, G, ldg, s);
 }
 hipError_t launch_re_axes_f32(const cd* g, int64_t NC, const int32_t* box_re, int rmax, Mesh m,
-                              const cd* P, const ReBatch& b, cf* T0, cf* T1, cf* G, int64_t ldg,
+                              const cd* P, const ReBatch& b, cf* T0, cf* G, int64_t ldg,
                               hipStream_t s) {
-    return re_axes<cf>(g, NC, box_re, rmax, m, P, b, T0, T1, G, ldg, s);
+    return re_axes<cf>(g, NC, box_re, rmax, m, P, b, T0, G, ldg, s);
 }
 
 // ---------------------------------------------------------------------------
