@@ -335,11 +335,12 @@ phoebe_status phoebe_gpu_propose_q(void *handle, const int32_t mesh[3], int32_t 
  * three per-axis factors on a full mesh, so the sum is taken one axis at a
  * time over the box [-rmax, rmax]^3 holding the Rp list (zero where the list
  * has no vector); the result is the same sum up to the order of additions.
- * Needs FP64, the full q mesh, |Rp components| <= 15, nW <= 16, nModes <= 32
- * and N1*N2 <= 65535.
+ * Needs FP64 or FP32, the full q mesh, |Rp components| <= 15, nW <= 16,
+ * nModes <= 32, N0 <= 1024 and N1*N2 <= 65535.
  * AUTO (the default) takes FACTORED where it applies and the box width is at
- * most half the number of Rp vectors.  Lists of q, the reduced precisions and
- * the batched form always use DIRECT.  Returns PHOEBE_E_INVALID for an
+ * most half the number of Rp vectors (the sum over Re is then factorised the
+ * same way over its box).  Lists of q, the split-BF16 precisions and the
+ * batched form always use DIRECT.  Returns PHOEBE_E_INVALID for an
  * unknown mode; scatter_rates returns PHOEBE_E_UNSUPPORTED when FACTORED is
  * forced where it does not apply. */
 typedef enum {

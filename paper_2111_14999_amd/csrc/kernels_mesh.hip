@@ -341,7 +341,8 @@ hipError_t launch_re_axes_f32(const cd* g, int64_t NC, const int32_t* box_re, in
 // registers.  Only Y (16 q x modes x final bands) goes through LDS to the
 // threads that apply E_q = z l and form the rate terms.
 // ---------------------------------------------------------------------------
-constexpr int kMBL = 4;  // final bands per rotation pass
+constexpr int kMBL = 4;         // final bands per rotation pass
+constexpr int kMaxChunks = 64;  // 16-point chunks of a line: N0 <= 1024
 
 // One DPP move of a double (two 32-bit halves) within each row of 16 lanes.
 template <int CTRL>
@@ -410,11 +411,6 @@ __global__ __launch_bounds__(256, (TN >= 6 ? 2 : 4)) void line_rates_kernel(Rate
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lg = lane >> 4;
 
-    for (int i = tid; i < N0p * Wp; i += 256) {
-        const int q0 = i / Wp, r = i - q0 * Wp;
-        sP[i] = (q0 < N0 && r < W) ? to_c<C>(a.P0[q0 * W + r]) : C{0, 0};
-    }
-
     const int kmesh = a.st_kmesh[st];
     const int nband = a.st_band[st];
     const int mlo = a.st_mlo[st], mhi = a.st_mhi[st];
@@ -431,19 +427,35 @@ __global__ __launch_bounds__(256, (TN >= 6 ? 2 : 4)) void line_rates_kernel(Rate
     const C* Tst = reinterpret_cast<const C*>(a.T2) + (int64_t)st * W * NL * ldf +
                    (int64_t)line * ldf + colbase;
     double gacc = 0.0;
+
+    // A 16-point chunk whose points all have |eps_n - eps_{m,k+q}| > cut + max
+    // omega for every final band m holds only exactly-zero terms: mark the live
+    // chunks first, and leave at once when the line has none.
+    const double wmax = *a.wmax;
+    __shared__ int sLive[kMaxChunks];
+    if (tid < kMaxChunks) sLive[tid] = 0;
+    __syncthreads();
+    for (int q0 = tid; q0 < N0; q0 += 256) {
+        const int64_t kq = (int64_t)((k0i + q0) % mesh.n0) * NL + kq12;
+        int live = 0;
+        for (int m = mlo; m <= mhi; ++m) live |= fabs(eps_n - a.eps[kq * nW + m]) <= cut + wmax;
+        if (live) atomicOr(&sLive[q0 >> 4], 1);
+    }
+    __syncthreads();
+    int any = 0;
+    for (int c = 0; c < (N0 + 15) / 16; ++c) any |= sLive[c];
+    if (!any) {
+        if (tid == 0) a.partial[(int64_t)st * a.n_qtiles + line] = 0.0;
+        return;
+    }
+    for (int i = tid; i < N0p * Wp; i += 256) {
+        const int q0 = i / Wp, r = i - q0 * Wp;
+        sP[i] = (q0 < N0 && r < W) ? to_c<C>(a.P0[q0 * W + r]) : C{0, 0};
+    }
     __syncthreads();
 
-    const double wmax = *a.wmax;
     for (int qc = 0; qc < N0; qc += 16) {
-        // A chunk whose 16 points all have |eps_n - eps_{m,k+q}| > cut + max omega
-        // for every final band m has only exactly-zero terms: skip it whole.
-        int live = 0;
-        if (tid < 16 && qc + tid < N0) {
-            const int64_t kq = (int64_t)((k0i + qc + tid) % mesh.n0) * NL + kq12;
-            for (int m = mlo; m <= mhi; ++m)
-                live |= fabs(eps_n - a.eps[kq * nW + m]) <= cut + wmax;
-        }
-        if (!__syncthreads_or(live)) continue;
+        if (!sLive[qc >> 4]) continue;
         // k+q of the four rows of this lane group
         int kqv[4];
 #pragma unroll
@@ -588,7 +600,7 @@ template <class C>
 static hipError_t line_rates(const RateArgs& a, int nst, hipStream_t s) {
     if (nst <= 0) return hipSuccess;
     if (a.n_qtiles != a.mesh.n1 * a.mesh.n2 || a.n_qtiles > 65535 || a.W > kMaxW ||
-        line_rates_ncpad(a.nm, a.nW) != a.nc_pad)
+        a.mesh.n0 > 16 * kMaxChunks || line_rates_ncpad(a.nm, a.nW) != a.nc_pad)
         return hipErrorInvalidValue;
     switch (a.nc_pad / 64) {
         case 1: return go_line<1, C>(a, nst, s);
