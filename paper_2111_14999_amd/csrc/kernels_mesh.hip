@@ -246,7 +246,9 @@ __global__ __launch_bounds__(256) void re_axis12_kernel(const C* __restrict__ T0
         sT[i] = c0 + cc < NC ? src[(int64_t)rr * NC + cc] : C{0, 0};
     }
     __syncthreads();
-    const int cc = tid & 63, tg = tid >> 6;
+    // the wave index is uniform across the wave: with it the pair and row
+    // indices, and the phase-table reads they address, become scalar loads
+    const int cc = tid & 63, tg = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t c = c0 + cc;
     for (int pp = pair_off[d] + tg; pp < pair_off[d + 1]; pp += 4) {
         const cd* Pk1 = P1 + (int64_t)pair_k1[pp] * W;
