@@ -251,7 +251,9 @@ __global__ __launch_bounds__(64) void eig_herm_kernel(cd* __restrict__ Aall, int
     const int n = NT > 0 ? NT : n_arg;
     extern __shared__ char smem_raw[];
     cd* A = reinterpret_cast<cd*>(smem_raw);
-    const int ld = n + 1;
+    // odd row stride: 16 lanes walking down a column of 16-byte elements hit 16
+    // distinct 4-bank groups (an even stride such as 16 would serialise them)
+    const int ld = n | 1;
     cd* V = A + n * ld;
     double* rc = reinterpret_cast<double*>(V + n * ld);  // [n/2+1] c
     double* rs = rc + (n / 2 + 1);                         // s
@@ -271,6 +273,7 @@ __global__ __launch_bounds__(64) void eig_herm_kernel(cd* __restrict__ Aall, int
     const int half = np / 2;
     const double eps2 = 4.9e-32;  // (2.2e-16)^2
     for (int sweep = 0; sweep < 40 && n > 1; ++sweep) {
+        int rotated = 0;
         double off = 0.0, dia = 0.0;
         for (int i = lane; i < n * n; i += 64) {
             const int r = i / n, c = i % n;
@@ -283,6 +286,11 @@ __global__ __launch_bounds__(64) void eig_herm_kernel(cd* __restrict__ Aall, int
         off = wave_sum(off);
         dia = wave_sum(dia);
         if (!(off > 1e-32 * dia)) break;
+        // A pair is left alone once |A_pq|^2 is at the rounding level of its own diagonal
+        // entries or of the mean squared diagonal entry, whichever is larger: with the
+        // first test alone, pairs next to a zero eigenvalue keep rotating on rounding noise
+        // and the off-diagonal norm never falls below the stopping level above.
+        const double skip_abs = eps2 * dia / n;
         for (int round = 0; round < np - 1; ++round) {
             if (lane < half) {
                 int p, q;
@@ -293,7 +301,8 @@ __global__ __launch_bounds__(64) void eig_herm_kernel(cd* __restrict__ Aall, int
                     const double a = A[p * ld + p].x, d = A[q * ld + q].x;
                     const cd bpq = A[p * ld + q];
                     const double bb2 = cabs2(bpq);
-                    if (bb2 > eps2 * fabs(a * d) && bb2 > 0.0) {
+                    if (bb2 > fmax(eps2 * fabs(a * d), skip_abs) && bb2 > 0.0) {
+                        rotated = 1;
                         const double bb = sqrt(bb2);
                         const double tau = (d - a) / (2.0 * bb);
                         const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
@@ -354,6 +363,7 @@ __global__ __launch_bounds__(64) void eig_herm_kernel(cd* __restrict__ Aall, int
             }
             __syncthreads();
         }
+        if (!__any(rotated)) break;  // a sweep with no rotation leaves A unchanged
     }
     // ascending order, ties by index
     for (int i = lane; i < n; i += 64) {

@@ -332,55 +332,72 @@ hipError_t launch_re_axes_f32(const cd* g, int64_t NC, const int32_t* box_re, in
 
 // ---------------------------------------------------------------------------
 // Last axis on MFMA + rotations + rate terms.  Work-group = one state x one
-// (q1, q2) line; the N0 points of the line are taken 16 at a time.  Lane l
-// holds A[l%16][l/16] = P0[q0, R0] and B[l/16][l%16] = T2[R0, line, col];
-// result v of lane l is row l/16 + 4v (f64 16x16x4 layout).
+// (q1, q2) line; the N0 points of the line are taken 16 at a time.  The MFMA
+// computes the transposed tile X^T[b, q0] = sum_R0 T2[R0, col b] P0[q0, R0]:
+// lane l feeds A[l%16][l/16] = T2[R0, line, col] and B[l/16][l%16] = P0[q0, R0].
 //
-// Columns are laid out c = sa*16 + b (b < nW <= 16), so every 16-column MFMA
-// tile holds one mode index sa with b on the lane: the k+q rotation
+// Columns are laid out c = sa*16 + b (b < nW <= 16), so every 16-column tile
+// holds one mode index sa.  The tile's rows are ordered so that lane (g, i)
+// (g = l/16, i = l%16) ends up with X[q0 = i, sa, b = 4g + v] in its result
+// register v (FP64 16x16x4: result row g + 4v, so row r loads column
+// b = 4(r%4) + r/4; FP32 16x16x4: result row 4g + v, natural order).  The k+q
+// rotation
 //   Y[q, sa, m] = sum_b X[q, sa, b] U_{k+q}[b, m]
-// is a product per lane and a sum over the 16 lanes of a row group, done in
-// registers.  Only Y (16 q x modes x final bands) goes through LDS to the
-// threads that apply E_q = z l and form the rate terms.
+// is then four products per lane and a sum over the four 16-lane rows, done
+// for four vectors at once with the gfx950 lane swaps.  Only Y (16 q x final
+// bands x modes) goes through LDS to the threads that apply E_q = z l and form
+// the rate terms.
 // ---------------------------------------------------------------------------
 constexpr int kMBL = 4;         // final bands per rotation pass
 constexpr int kMaxChunks = 64;  // 16-point chunks of a line: N0 <= 1024
 
-// One DPP move of a double (two 32-bit halves) within each row of 16 lanes.
-template <int CTRL>
-__device__ inline double dpp_f64(double x) {
-    const uint64_t b = __builtin_bit_cast(uint64_t, x);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
-    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+// permlane32_swap exchanges lanes 32-63 of a with lanes 0-31 of b;
+// permlane16_swap exchanges the odd 16-lane rows of a with the even rows of b.
+template <int ROWS>
+__device__ inline void lane_swap(uint32_t& a, uint32_t& b) {
+    if constexpr (ROWS == 2) {
+        const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+        a = r[0];
+        b = r[1];
+    } else {
+        const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+        a = r[0];
+        b = r[1];
+    }
+}
+template <int ROWS>
+__device__ inline void lane_swap(double& a, double& b) {
+    const uint64_t x = __builtin_bit_cast(uint64_t, a), y = __builtin_bit_cast(uint64_t, b);
+    uint32_t xl = (uint32_t)x, xh = (uint32_t)(x >> 32), yl = (uint32_t)y, yh = (uint32_t)(y >> 32);
+    lane_swap<ROWS>(xl, yl);
+    lane_swap<ROWS>(xh, yh);
+    a = __builtin_bit_cast(double, ((uint64_t)xh << 32) | xl);
+    b = __builtin_bit_cast(double, ((uint64_t)yh << 32) | yl);
+}
+template <int ROWS>
+__device__ inline void lane_swap(float& a, float& b) {
+    uint32_t x = __builtin_bit_cast(uint32_t, a), y = __builtin_bit_cast(uint32_t, b);
+    lane_swap<ROWS>(x, y);
+    a = __builtin_bit_cast(float, x);
+    b = __builtin_bit_cast(float, y);
 }
 
-// Sum over the 16 lanes of a DPP row, left in every lane of the row: swap
-// neighbours and pairs within quads (quad_perm 1,0,3,2 and 2,3,0,1), then
-// add the mirrored half row and the mirrored row.
-__device__ inline double row16_sum(double x) {
-    x += dpp_f64<0xB1>(x);
-    x += dpp_f64<0x4E>(x);
-    x += dpp_f64<0x141>(x);
-    x += dpp_f64<0x140>(x);
-    return x;
-}
-template <int CTRL>
-__device__ inline float dpp_f32(float x) {
-    return __builtin_bit_cast(
-        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
-}
-__device__ inline float row16_sum(float x) {
-    x += dpp_f32<0xB1>(x);
-    x += dpp_f32<0x4E>(x);
-    x += dpp_f32<0x141>(x);
-    x += dpp_f32<0x140>(x);
-    return x;
+// Four sums over the four 16-lane rows at once: on return lane (g, i) holds
+// sum_{g'} u_g[g', i], i.e. row 0 the sum of u0, row 1 of u1, row 2 of u2 and
+// row 3 of u3.  After the 32-lane swap and add, lanes 0-31 hold half sums of
+// u0 (u1) and lanes 32-63 of u2 (u3); the 16-lane swap and add completes them.
+template <class R>
+__device__ inline R rows4_reduce_scatter(R u0, R u1, R u2, R u3) {
+    lane_swap<2>(u0, u2);
+    lane_swap<2>(u1, u3);
+    R s = u0 + u2, t = u1 + u3;
+    lane_swap<4>(s, t);
+    return s + t;
 }
 
-// C = cd: FP64 on v_mfma_f64_16x16x4f64 (result v of lane l is row l/16 + 4v);
-// C = cf: the FP32 form on v_mfma_f32_16x16x4f32 (row 4(l/16) + v), with the
-// rotations in FP32 and the Gaussian terms and sums in FP64.
+// C = cd: FP64 on v_mfma_f64_16x16x4f64; C = cf: the FP32 form on
+// v_mfma_f32_16x16x4f32, with the rotations in FP32 and the Gaussian terms and
+// sums in FP64.
 template <int TN, class C>
 __global__ __launch_bounds__(256, (TN >= 6 ? 2 : 4)) void line_rates_kernel(RateArgs a) {
     using R = decltype(C::x);
@@ -425,26 +442,29 @@ __global__ __launch_bounds__(256, (TN >= 6 ? 2 : 4)) void line_rates_kernel(Rate
     // |y| > 27.5 sigma: y^2/sigma^2 > 756 and exp(-756) is below the smallest
     // FP64 subnormal, so such a Gaussian is exactly 0
     const double cut = 27.5 * a.sigma;
-    const int colbase = wave * TN * 16 + li;
+    // tile row li loads column b = perm(li), see above
+    const int bcol = F64 ? (((li & 3) << 2) | (li >> 2)) : li;
     const C* Tst = reinterpret_cast<const C*>(a.T2) + (int64_t)st * W * NL * ldf +
-                   (int64_t)line * ldf + colbase;
+                   (int64_t)line * ldf + wave * TN * 16 + bcol;
     double gacc = 0.0;
 
-    // A 16-point chunk whose points all have |eps_n - eps_{m,k+q}| > cut + max
-    // omega for every final band m holds only exactly-zero terms: mark the live
-    // chunks first, and leave at once when the line has none.
+    // Final band m is live in a 16-point chunk if some point of the chunk has
+    // |eps_n - eps_{m,k+q}| <= cut + max omega; every term of a dead (chunk,
+    // band) is exactly zero.  Mark the live bands of each chunk first, and
+    // leave at once when the line has none.
     const double wmax = *a.wmax;
-    __shared__ int sLive[kMaxChunks];
+    __shared__ uint32_t sLive[kMaxChunks];
     if (tid < kMaxChunks) sLive[tid] = 0;
     __syncthreads();
     for (int q0 = tid; q0 < N0; q0 += 256) {
         const int64_t kq = (int64_t)((k0i + q0) % mesh.n0) * NL + kq12;
-        int live = 0;
-        for (int m = mlo; m <= mhi; ++m) live |= fabs(eps_n - a.eps[kq * nW + m]) <= cut + wmax;
-        if (live) atomicOr(&sLive[q0 >> 4], 1);
+        uint32_t live = 0;
+        for (int m = mlo; m <= mhi; ++m)
+            live |= (uint32_t)(fabs(eps_n - a.eps[kq * nW + m]) <= cut + wmax) << m;
+        if (live) atomicOr(&sLive[q0 >> 4], live);
     }
     __syncthreads();
-    int any = 0;
+    uint32_t any = 0;
     for (int c = 0; c < (N0 + 15) / 16; ++c) any |= sLive[c];
     if (!any) {
         if (tid == 0) a.partial[(int64_t)st * a.n_qtiles + line] = 0.0;
@@ -457,14 +477,10 @@ __global__ __launch_bounds__(256, (TN >= 6 ? 2 : 4)) void line_rates_kernel(Rate
     __syncthreads();
 
     for (int qc = 0; qc < N0; qc += 16) {
-        if (!sLive[qc >> 4]) continue;
-        // k+q of the four rows of this lane group
-        int kqv[4];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int q0 = qc + (F64 ? lg + 4 * v : 4 * lg + v);
-            kqv[v] = q0 < N0 ? ((k0i + q0) % mesh.n0) * NL + kq12 : -1;
-        }
+        uint32_t bands = sLive[qc >> 4];
+        if (!bands) continue;
+        // k+q of this lane's point q0 = qc + li
+        const int64_t kql = qc + li < N0 ? (int64_t)((k0i + qc + li) % mesh.n0) * NL + kq12 : -1;
         V4 cr[TN], ci[TN];
 #pragma unroll
         for (int t = 0; t < TN; ++t) {
@@ -491,32 +507,55 @@ __global__ __launch_bounds__(256, (TN >= 6 ? 2 : 4)) void line_rates_kernel(Rate
             };
 #pragma unroll
             for (int t = 0; t < TN; ++t) {
-                cr[t] = mfma(ph.x, bc[t].x, cr[t]);
-                ci[t] = mfma(ph.x, bc[t].y, ci[t]);
+                cr[t] = mfma(bc[t].x, ph.x, cr[t]);
+                ci[t] = mfma(bc[t].y, ph.x, ci[t]);
             }
 #pragma unroll
             for (int t = 0; t < TN; ++t) {
-                cr[t] = mfma(-ph.y, bc[t].y, cr[t]);
-                ci[t] = mfma(ph.y, bc[t].x, ci[t]);
+                cr[t] = mfma(bc[t].y, -ph.y, cr[t]);
+                ci[t] = mfma(bc[t].x, ph.y, ci[t]);
             }
         }
-        for (int m0 = mlo; m0 <= mhi; m0 += kMBL) {
-            const int nmb = min(kMBL, mhi - m0 + 1);
-            // Y in registers: lane (li = b) product, then a sum over the 16 lanes
-            for (int mb = 0; mb < nmb; ++mb) {
+        while (bands) {
+            // up to kMBL live bands of this chunk, ascending
+            int ml[kMBL];
+            int nmb = 0;
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    C u = {0, 0};
-                    if (kqv[v] >= 0 && li < nW)  // eigenvector m
-                        u = to_c<C>(a.U[((int64_t)kqv[v] * nW + m0 + mb) * nW + li]);
-                    const int row = F64 ? lg + 4 * v : 4 * lg + v;
+            for (int mb = 0; mb < kMBL; ++mb) {
+                ml[mb] = bands ? __builtin_ctz(bands) : 0;
+                nmb += bands ? 1 : 0;
+                bands &= bands - 1;
+            }
 #pragma unroll
-                    for (int t = 0; t < TN; ++t) {
-                        const R yr = row16_sum(cr[t][v] * u.x - ci[t][v] * u.y);
-                        const R yi = row16_sum(cr[t][v] * u.y + ci[t][v] * u.x);
-                        const int sa = wave * TN + t;
-                        if (li == 0 && sa < nm) sY[(row * kMBL + mb) * nm + sa] = C{yr, yi};
+            for (int mb = 0; mb < kMBL; ++mb) {
+                if (mb >= nmb) break;
+                // U_{k+q}[b, m] for b = 4 lg + v (eigenvectors stored as [k][band][orbital])
+                C u[4];
+                const cd* Ur = a.U + ((kql < 0 ? 0 : kql) * nW + ml[mb]) * nW + 4 * lg;
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    u[v] = (kql >= 0 && 4 * lg + v < nW) ? to_c<C>(Ur[v]) : C{0, 0};
+                R pr[TN], pi[TN];
+#pragma unroll
+                for (int t = 0; t < TN; ++t) {
+                    R xr = 0, xi = 0;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        xr += cr[t][v] * u[v].x - ci[t][v] * u[v].y;
+                        xi += cr[t][v] * u[v].y + ci[t][v] * u[v].x;
                     }
+                    pr[t] = xr;
+                    pi[t] = xi;
+                }
+                // rows 0/1 get Re Y of tiles t/t+1, rows 2/3 Im Y of tiles t/t+1
+#pragma unroll
+                for (int t = 0; t < TN; t += 2) {
+                    const R y = rows4_reduce_scatter(pr[t], t + 1 < TN ? pr[t + 1] : R(0), pi[t],
+                                                     t + 1 < TN ? pi[t + 1] : R(0));
+                    const int tt = t + (lg & 1);
+                    const int sa = wave * TN + tt;
+                    if (tt < TN && sa < nm)
+                        reinterpret_cast<R*>(sY + (li * kMBL + mb) * nm + sa)[lg >> 1] = y;
                 }
             }
             __syncthreads();
@@ -529,7 +568,7 @@ __global__ __launch_bounds__(256, (TN >= 6 ? 2 : 4)) void line_rates_kernel(Rate
                 if (q0 >= N0) continue;
                 const int64_t q = (int64_t)q0 * NL + q12;
                 const int64_t kq = (int64_t)((k0i + q0) % mesh.n0) * NL + kq12;
-                const int m = m0 + mb;
+                const int m = mb == 0 ? ml[0] : mb == 1 ? ml[1] : mb == 2 ? ml[2] : ml[3];
                 const double x = eps_n - a.eps[kq * nW + m];
                 const double w = a.omega[q * nm + nu];
                 const double y1 = x - w, y2 = x + w;

@@ -25,7 +25,9 @@ def lib():
 
 @pytest.mark.parametrize("make", [lambda: synth.config_c1(),
                                   lambda: synth.small_system(41, n_wannier=7, n_atoms=5, r=1),
-                                  lambda: synth.small_system(42, n_wannier=1, n_atoms=1, r=2)])
+                                  lambda: synth.small_system(42, n_wannier=1, n_atoms=1, r=2),
+                                  lambda: synth.config_c2(with_coupling=False)],
+                         ids=["toy", "nW7-5atoms", "nW1-1atom", "nW16-15modes"])
 def test_electron_and_phonon_bands(lib, make):
     torch = torch_cuda()
     from paper_2111_14999_amd import DeviceSystem
