@@ -402,6 +402,7 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
         const int BQ = 16 * tq;
         // states per factorised sub-batch: T1 + T2 of a sub-batch stay under 4 GB
         const size_t t12_state = ((size_t)Wbox * Wbox * mesh.n2 + (size_t)Wbox * NL) * nc_pad * g_elem;
+        const int nch_line = (mesh.n0 + 15) / 16;
         const int nsb = factored ? (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)BK * nW,
                                                       (int64_t)(4e9 / (double)t12_state)))
                                  : 0;
@@ -499,6 +500,8 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                                    (size_t)max_states * rp_pad * nc_pad * f_elem +
                                    (size_t)max_states * n_qtiles * sizeof(double) +
                                    (factored ? (size_t)nsb * t12_state + 512 : 0) +
+                                   (factored ? (size_t)nsb * NL * nch_line * sizeof(uint32_t) + 256
+                                             : 0) +
                                    (re_fact ? (size_t)kD0Max * We * We * NC2 * g_elem +
                                                   (size_t)rows_cap * 160 * sizeof(int32_t) + 1024
                                             : 0);
@@ -704,6 +707,7 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
         char* T1buf = factored ? ar.take<char>((size_t)nsb * Wbox * Wbox * mesh.n2 * nc_pad * g_elem)
                                : nullptr;
         char* T2buf = factored ? ar.take<char>((size_t)nsb * Wbox * NL * nc_pad * g_elem) : nullptr;
+        uint32_t* livebuf = factored ? ar.take<uint32_t>((size_t)nsb * NL * nch_line) : nullptr;
 
         const double inv_sqrtpi_sigma = 1.0 / (std::sqrt(kPi) * par->sigma);
         const double scale = 2.0 * kPi * inv_sqrtpi_sigma * (q_off ? 1.0 : 1.0 / (double)N);
@@ -825,6 +829,8 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                     rb.st_mhi += sb;
                     rb.partial = partial + (int64_t)sb * n_qtiles;
                     if (ra.terms) rb.terms = ra.terms + (int64_t)sb * N * nm;
+                    rb.live = livebuf;
+                    HIPCHK(h, launch_line_live(rb, nn, livebuf, s));
                     Timer tl(h, s, "line_rates");
                     if (lowp)
                         HIPCHK(h, launch_line_rates_f32(rb, nn, s));

@@ -79,7 +79,7 @@ struct RateArgs {
     const cd* U;               // [Nk, nW, nW] transposed: U[k, band, orbital]
     const double* omega;       // [Nq, nm]
     const double* nb;          // [Nq, nm]
-    const cd* E;               // [Nq, nm, nm] z * l
+    const cd* E;               // [Nq, nm, nm]: E[q, nu, sa] = z[q][sa][nu] l_{sa,nu}
     int nW, nm;
     double sigma;
     double* partial;           // [nst, n_qtiles]
@@ -92,6 +92,7 @@ struct RateArgs {
     int W;                     // 2 rmax + 1
     int n_states;              // states of one launch (set by the launcher)
     const double* wmax;        // device scalar: largest phonon energy on the mesh
+    const uint32_t* live;      // [nst, N1*N2, ceil(N0/16)] live final bands per chunk (line_live)
 };
 
 // Fused stage 2 (sum over Rp on MFMA) + rotations + rate terms.
@@ -124,6 +125,8 @@ size_t re_axes_lds(int rmax, bool f32);
 
 // Axis 0 on MFMA + rotations + rate terms, one work-group per (state, q1, q2) line.
 // Columns sa*16 + b (nW <= 16), nc_pad = 64 TN with 4 TN >= nModes.
+// Live-band masks of every (state, line, 16-point chunk) for the line kernel.
+hipError_t launch_line_live(const RateArgs& a, int nst, uint32_t* live, hipStream_t s);
 hipError_t launch_line_rates(const RateArgs& a, int nst, hipStream_t s);
 hipError_t launch_line_rates_f32(const RateArgs& a, int nst, hipStream_t s);
 size_t line_rates_lds(int W, int N0, int nm, bool f32);

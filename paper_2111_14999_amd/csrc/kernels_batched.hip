@@ -152,10 +152,10 @@ __device__ void batched_tile(const SysDesc& d, int st, int qt, char* smem) {
             if (kq < 0) continue;
             const int64_t q = qt0 + c;
             const cf* Yr = sY + (c * kMBB + mb) * nm;
-            const cd* Eq = d.E + q * nm * nm + nu;
+            const cd* Eq = d.E + (q * nm + nu) * nm;
             float zr = 0.f, zi = 0.f;
             for (int sa = 0; sa < nm; ++sa) {
-                const cd e = Eq[sa * nm];
+                const cd e = Eq[sa];
                 const float er = (float)e.x, ei = (float)e.y;
                 const cf y = Yr[sa];
                 zr = fmaf(er, y.x, fmaf(-ei, y.y, zr));

@@ -425,13 +425,15 @@ __global__ void phonon_post_kernel(const double* lam, const cd* z, const double*
         if (omega) omega[t] = w;
         if (nb) nb[t] = (act && kT > 0.0) ? 1.0 / expm1(w / kT) : 0.0;
         if (e) {
+            // E[q, nu, sa] = z[q][sa][nu] l_{sa,nu}: one mode's column contiguous
             for (int sa = 0; sa < nm; ++sa) {
                 const int64_t o = (q * nm + sa) * nm + nu;
+                const int64_t oe = (q * nm + nu) * nm + sa;
                 if (act) {
                     const double ls = sqrt(c_ph / (2.0 * mass[sa / 3] * w));
-                    e[o] = cd{z[o].x * ls, z[o].y * ls};
+                    e[oe] = cd{z[o].x * ls, z[o].y * ls};
                 } else {
-                    e[o] = cd{0.0, 0.0};
+                    e[oe] = cd{0.0, 0.0};
                 }
             }
         }

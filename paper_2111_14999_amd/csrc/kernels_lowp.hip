@@ -589,10 +589,10 @@ __global__ __launch_bounds__(256, 2) void stage2_rates_lp_kernel(RateArgsLP a) {
                 if (kq < 0) continue;
                 const int64_t q = sQ[cc];
                 const cf* Yr = sY + (cc * kMBLP + mb) * nm;
-                const cd* Eq = a.E + q * nm * nm + nu;
+                const cd* Eq = a.E + (q * nm + nu) * nm;
                 float zr = 0.f, zi = 0.f;
                 for (int sa = 0; sa < nm; ++sa) {
-                    const cd e = Eq[sa * nm];
+                    const cd e = Eq[sa];
                     const float er = (float)e.x, ei = (float)e.y;
                     const cf y = Yr[sa];
                     zr = fmaf(er, y.x, fmaf(-ei, y.y, zr));
@@ -741,7 +741,7 @@ __global__ void rotate_g_lp_kernel(const cf* __restrict__ X, int64_t nq, const c
         for (int nu = 0; nu < nm; ++nu) {
             float zr = 0.f, zi = 0.f;
             for (int sa = 0; sa < nm; ++sa) {
-                const cd e = Eq[sa * nm + nu];
+                const cd e = Eq[nu * nm + sa];
                 const float er = (float)e.x, ei = (float)e.y;
                 zr = fmaf(er, yr[sa], fmaf(-ei, yi[sa], zr));
                 zi = fmaf(er, yi[sa], fmaf(ei, yr[sa], zi));

@@ -344,11 +344,10 @@ hipError_t launch_re_axes_f32(const cd* g, int64_t NC, const int32_t* box_re, in
 // rotation
 //   Y[q, sa, m] = sum_b X[q, sa, b] U_{k+q}[b, m]
 // is then four products per lane and a sum over the four 16-lane rows, done
-// for four vectors at once with the gfx950 lane swaps.  Only Y (16 q x final
-// bands x modes) goes through LDS to the threads that apply E_q = z l and form
-// the rate terms.
+// for four vectors at once with the gfx950 lane swaps.  Only Y (16 q x modes,
+// one final band at a time) goes through LDS to the threads that apply
+// E_q = z l and form the rate terms.
 // ---------------------------------------------------------------------------
-constexpr int kMBL = 4;         // final bands per rotation pass
 constexpr int kMaxChunks = 64;  // 16-point chunks of a line: N0 <= 1024
 
 // permlane32_swap exchanges lanes 32-63 of a with lanes 0-31 of b;
@@ -395,11 +394,69 @@ __device__ inline R rows4_reduce_scatter(R u0, R u1, R u2, R u3) {
     return s + t;
 }
 
+// Live final bands of every 16-point chunk of every line.  Bit m of
+// live[(st * NL + line) * nch + c] is set when some point q0 of chunk c has
+// |eps_n - eps_{m,k+q}| <= 27.5 sigma + max omega; otherwise both Gaussians of
+// every term of band m in that chunk are beyond 27.5 sigma, i.e. exactly 0.
+// One thread per (state, line, chunk), every entry written.
+__global__ void line_live_kernel(RateArgs a, uint32_t* __restrict__ live) {
+    const Mesh mesh = a.mesh;
+    const int N0 = mesh.n0, NL = mesh.n1 * mesh.n2, nch = (N0 + 15) / 16, nW = a.nW;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= (int64_t)a.n_states * NL * nch) return;
+    const int c = (int)(i % nch);
+    const int64_t sl = i / nch;
+    const int line = (int)(sl % NL), st = (int)(sl / NL);
+    const int q1 = line / mesh.n2, q2 = line - q1 * mesh.n2;
+    const int kmesh = a.st_kmesh[st];
+    const int mlo = a.st_mlo[st], mhi = a.st_mhi[st];
+    int k0i, k1i, k2i;
+    mesh_triple(kmesh, mesh, k0i, k1i, k2i);
+    const int kq12 = ((k1i + q1) % mesh.n1) * mesh.n2 + (k2i + q2) % mesh.n2;
+    const double eps_n = a.eps[(int64_t)kmesh * nW + a.st_band[st]];
+    const double lim = 27.5 * a.sigma + *a.wmax;
+    uint32_t bits = 0;
+    for (int p = 0; p < 16; ++p) {
+        const int q0 = c * 16 + p;
+        if (q0 >= N0) break;
+        const int64_t kq = (int64_t)((k0i + q0) % N0) * NL + kq12;
+        for (int m = mlo; m <= mhi; ++m)
+            bits |= (uint32_t)(fabs(eps_n - a.eps[kq * nW + m]) <= lim) << m;
+    }
+    live[i] = bits;
+}
+
+hipError_t launch_line_live(const RateArgs& a, int nst, uint32_t* live, hipStream_t s) {
+    if (nst <= 0) return hipSuccess;
+    if (a.nW > 32) return hipErrorInvalidValue;
+    RateArgs b = a;
+    b.n_states = nst;
+    const int64_t n = (int64_t)nst * a.mesh.n1 * a.mesh.n2 * ((a.mesh.n0 + 15) / 16);
+    hipLaunchKernelGGL(line_live_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, b, live);
+    return hipGetLastError();
+}
+
 // C = cd: FP64 on v_mfma_f64_16x16x4f64; C = cf: the FP32 form on
 // v_mfma_f32_16x16x4f32, with the rotations in FP32 and the Gaussian terms and
 // sums in FP64.
+//
+// A work-group walks the live (chunk, band) units of its line in order.  The
+// eigenvector, band and phonon values a unit needs are loaded before its MFMA
+// work (for the first unit together with the phase table), so that only the
+// E_q loads of the terms that survive the Gaussian test wait on memory after
+// the rotation.  (On the workloads measured, a live chunk has one live final
+// band.)
+constexpr int kTP = 2;  // column tiles per MFMA pass
+
+__device__ inline d4 mfma16(double x, double y, d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0);
+}
+__device__ inline f4 mfma16(float x, float y, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(x, y, c, 0, 0, 0);
+}
+
 template <int TN, class C>
-__global__ __launch_bounds__(256, (TN >= 6 ? 2 : 4)) void line_rates_kernel(RateArgs a) {
+__global__ __launch_bounds__(256, 4) void line_rates_kernel(RateArgs a) {
     using R = decltype(C::x);
     constexpr bool F64 = sizeof(R) == 8;
     using V4 = std::conditional_t<F64, d4, f4>;
@@ -410,10 +467,12 @@ __global__ __launch_bounds__(256, (TN >= 6 ? 2 : 4)) void line_rates_kernel(Rate
     const Mesh mesh = a.mesh;
     const int N0 = mesh.n0;
     const int N0p = (N0 + 15) & ~15;
+    const int nch = N0p / 16;
     const int ldf = a.nc_pad;
     C* sP = reinterpret_cast<C*>(smem_raw);       // [N0p][Wp]
-    C* sY = sP + N0p * Wp;                        // [16][kMBL][nm]
+    C* sY = sP + N0p * Wp;                        // [16][nm]: Y of one (chunk, band) unit
     __shared__ double sRed[4];
+    __shared__ uint32_t sLive[kMaxChunks];
 
     // XCD-aware order: work-groups are dealt to the 8 XCDs round-robin, so
     // with id = 8 j + x every state of a line lands on XCD x, one after
@@ -430,9 +489,16 @@ __global__ __launch_bounds__(256, (TN >= 6 ? 2 : 4)) void line_rates_kernel(Rate
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int li = lane & 15, lg = lane >> 4;
 
+    if (tid < nch) sLive[tid] = a.live[((int64_t)st * NL + line) * nch + tid];
     const int kmesh = a.st_kmesh[st];
     const int nband = a.st_band[st];
-    const int mlo = a.st_mlo[st], mhi = a.st_mhi[st];
+    __syncthreads();
+    uint32_t any = 0;
+    for (int c = 0; c < nch; ++c) any |= sLive[c];
+    if (!any) {
+        if (tid == 0) a.partial[(int64_t)st * a.n_qtiles + line] = 0.0;
+        return;
+    }
     int k0i, k1i, k2i;
     mesh_triple(kmesh, mesh, k0i, k1i, k2i);
     const int kq12 = ((k1i + q1) % mesh.n1) * mesh.n2 + (k2i + q2) % mesh.n2;
@@ -446,149 +512,144 @@ __global__ __launch_bounds__(256, (TN >= 6 ? 2 : 4)) void line_rates_kernel(Rate
     const int bcol = F64 ? (((li & 3) << 2) | (li >> 2)) : li;
     const C* Tst = reinterpret_cast<const C*>(a.T2) + (int64_t)st * W * NL * ldf +
                    (int64_t)line * ldf + wave * TN * 16 + bcol;
-    double gacc = 0.0;
+    const int64_t Tk = (int64_t)NL * ldf;  // stride of R0 in T2
 
-    // Final band m is live in a 16-point chunk if some point of the chunk has
-    // |eps_n - eps_{m,k+q}| <= cut + max omega; every term of a dead (chunk,
-    // band) is exactly zero.  Mark the live bands of each chunk first, and
-    // leave at once when the line has none.
-    const double wmax = *a.wmax;
-    __shared__ uint32_t sLive[kMaxChunks];
-    if (tid < kMaxChunks) sLive[tid] = 0;
-    __syncthreads();
-    for (int q0 = tid; q0 < N0; q0 += 256) {
-        const int64_t kq = (int64_t)((k0i + q0) % mesh.n0) * NL + kq12;
-        uint32_t live = 0;
-        for (int m = mlo; m <= mhi; ++m)
-            live |= (uint32_t)(fabs(eps_n - a.eps[kq * nW + m]) <= cut + wmax) << m;
-        if (live) atomicOr(&sLive[q0 >> 4], live);
-    }
-    __syncthreads();
-    uint32_t any = 0;
-    for (int c = 0; c < (N0 + 15) / 16; ++c) any |= sLive[c];
-    if (!any) {
-        if (tid == 0) a.partial[(int64_t)st * a.n_qtiles + line] = 0.0;
-        return;
-    }
     for (int i = tid; i < N0p * Wp; i += 256) {
         const int q0 = i / Wp, r = i - q0 * Wp;
         sP[i] = (q0 < N0 && r < W) ? to_c<C>(a.P0[q0 * W + r]) : C{0, 0};
     }
-    __syncthreads();
+    // Values one (chunk qc, band m) unit needs: per lane, U_{k+q}[b = 4 lg + v, m]
+    // at the lane's point q0 = qc + li; per thread, for its term item
+    // (point c = tid / nm, mode nu = tid % nm), eps and f of band m at k+q and
+    // omega and n of (q, nu).  Items beyond the first of a thread (nm > 16)
+    // read theirs in place.
+    struct Unit {
+        C u[4];
+        double em, fm, om, nbq;
+    };
+    const bool has_item = tid < 16 * nm;
+    const int ic = tid / nm, inu = tid - ic * nm;
+    auto load_unit = [&](int qc, int m, Unit& d) {
+        const int64_t kql = qc + li < N0 ? (int64_t)((k0i + qc + li) % N0) * NL + kq12 : -1;
+        const cd* Ur = a.U + ((kql < 0 ? 0 : kql) * nW + m) * nW + 4 * lg;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) d.u[v] = (kql >= 0 && 4 * lg + v < nW) ? to_c<C>(Ur[v]) : C{0, 0};
+        d.em = d.fm = d.om = d.nbq = 0.0;
+        if (has_item && qc + ic < N0) {
+            const int64_t q = (int64_t)(qc + ic) * NL + q12;
+            const int64_t kq = (int64_t)((k0i + qc + ic) % N0) * NL + kq12;
+            d.em = a.eps[kq * nW + m];
+            d.fm = a.focc[kq * nW + m];
+            d.om = a.omega[q * nm + inu];
+            d.nbq = a.nb[q * nm + inu];
+        }
+    };
+    // rate term of one item; E_q is read only for terms that survive the test
+    double gacc = 0.0;
+    auto item_term = [&](int qc, int c, int nu, double em, double fm, double w, double nbq) {
+        const double x = eps_n - em;
+        const double y1 = x - w, y2 = x + w;
+        // both Gaussians underflow to exactly 0: the term is 0
+        if (fabs(y1) > cut && fabs(y2) > cut) return;
+        const int64_t q = (int64_t)(qc + c) * NL + q12;
+        const C* Yr = sY + c * nm;
+        const cd* Eq = a.E + (q * nm + nu) * nm;
+        C z = {0, 0};
+        for (int sa = 0; sa < nm; ++sa) z = cfma(to_c<C>(Eq[sa]), Yr[sa], z);
+        const double g1 = exp(-y1 * y1 * inv_s2), g2 = exp(-y2 * y2 * inv_s2);
+        const double term = cabs2(z) * ((nbq + 1.0 - fm) * g1 + (nbq + fm) * g2);
+        gacc += term;
+        if (a.terms)
+            atomicAdd(&a.terms[((int64_t)st * a.nq_mesh + q) * nm + nu], a.terms_scale * term);
+    };
 
-    for (int qc = 0; qc < N0; qc += 16) {
-        uint32_t bands = sLive[qc >> 4];
-        if (!bands) continue;
-        // k+q of this lane's point q0 = qc + li
-        const int64_t kql = qc + li < N0 ? (int64_t)((k0i + qc + li) % mesh.n0) * NL + kq12 : -1;
-        V4 cr[TN], ci[TN];
+    // first live unit
+    int qc = 0;
+    while (!sLive[qc >> 4]) qc += 16;
+    uint32_t bands = sLive[qc >> 4];
+    int m = __builtin_ctz(bands);
+    Unit d;
+    load_unit(qc, m, d);
+    __syncthreads();  // sP
+
+    while (true) {
+        // X^T tiles of chunk qc and Y, two column tiles at a time (the
+        // accumulators of a pass are the kernel's largest register block; a
+        // second live band of the same chunk recomputes them)
 #pragma unroll
-        for (int t = 0; t < TN; ++t) {
-            cr[t] = V4{0, 0, 0, 0};
-            ci[t] = V4{0, 0, 0, 0};
-        }
-        for (int k0 = 0; k0 < Wp; k0 += 4) {
-            const int k = k0 + lg;
-            C bc[TN];
-            if (k < W) {
-                const C* Tr = Tst + (int64_t)k * NL * ldf;
+        for (int t0 = 0; t0 < TN; t0 += kTP) {
+            constexpr int P = TN < kTP ? TN : kTP;
+            V4 cr[P], ci[P];
 #pragma unroll
-                for (int t = 0; t < TN; ++t) bc[t] = Tr[t * 16];
-            } else {
-#pragma unroll
-                for (int t = 0; t < TN; ++t) bc[t] = C{0, 0};
+            for (int t = 0; t < P; ++t) {
+                cr[t] = V4{0, 0, 0, 0};
+                ci[t] = V4{0, 0, 0, 0};
             }
-            const C ph = sP[(qc + li) * Wp + k];
-            auto mfma = [](R x, R y, V4 c) {
-                if constexpr (F64)
-                    return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0);
-                else
-                    return __builtin_amdgcn_mfma_f32_16x16x4f32(x, y, c, 0, 0, 0);
-            };
+            for (int k0 = 0; k0 < Wp; k0 += 4) {
+                const int k = k0 + lg;
+                C bc[P];
 #pragma unroll
-            for (int t = 0; t < TN; ++t) {
-                cr[t] = mfma(bc[t].x, ph.x, cr[t]);
-                ci[t] = mfma(bc[t].y, ph.x, ci[t]);
-            }
+                for (int t = 0; t < P; ++t)
+                    bc[t] = (k < W && t0 + t < TN) ? Tst[k * Tk + (t0 + t) * 16] : C{0, 0};
+                const C ph = sP[(qc + li) * Wp + k];
 #pragma unroll
-            for (int t = 0; t < TN; ++t) {
-                cr[t] = mfma(bc[t].y, -ph.y, cr[t]);
-                ci[t] = mfma(bc[t].x, ph.y, ci[t]);
-            }
-        }
-        while (bands) {
-            // up to kMBL live bands of this chunk, ascending
-            int ml[kMBL];
-            int nmb = 0;
-#pragma unroll
-            for (int mb = 0; mb < kMBL; ++mb) {
-                ml[mb] = bands ? __builtin_ctz(bands) : 0;
-                nmb += bands ? 1 : 0;
-                bands &= bands - 1;
-            }
-#pragma unroll
-            for (int mb = 0; mb < kMBL; ++mb) {
-                if (mb >= nmb) break;
-                // U_{k+q}[b, m] for b = 4 lg + v (eigenvectors stored as [k][band][orbital])
-                C u[4];
-                const cd* Ur = a.U + ((kql < 0 ? 0 : kql) * nW + ml[mb]) * nW + 4 * lg;
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    u[v] = (kql >= 0 && 4 * lg + v < nW) ? to_c<C>(Ur[v]) : C{0, 0};
-                R pr[TN], pi[TN];
-#pragma unroll
-                for (int t = 0; t < TN; ++t) {
-                    R xr = 0, xi = 0;
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        xr += cr[t][v] * u[v].x - ci[t][v] * u[v].y;
-                        xi += cr[t][v] * u[v].y + ci[t][v] * u[v].x;
-                    }
-                    pr[t] = xr;
-                    pi[t] = xi;
+                for (int t = 0; t < P; ++t) {
+                    cr[t] = mfma16(bc[t].x, ph.x, cr[t]);
+                    ci[t] = mfma16(bc[t].y, ph.x, ci[t]);
                 }
-                // rows 0/1 get Re Y of tiles t/t+1, rows 2/3 Im Y of tiles t/t+1
 #pragma unroll
-                for (int t = 0; t < TN; t += 2) {
-                    const R y = rows4_reduce_scatter(pr[t], t + 1 < TN ? pr[t + 1] : R(0), pi[t],
-                                                     t + 1 < TN ? pi[t + 1] : R(0));
-                    const int tt = t + (lg & 1);
-                    const int sa = wave * TN + tt;
-                    if (tt < TN && sa < nm)
-                        reinterpret_cast<R*>(sY + (li * kMBL + mb) * nm + sa)[lg >> 1] = y;
+                for (int t = 0; t < P; ++t) {
+                    cr[t] = mfma16(bc[t].y, -ph.y, cr[t]);
+                    ci[t] = mfma16(bc[t].x, ph.y, ci[t]);
                 }
             }
-            __syncthreads();
-            // Z[c, mb, nu] = sum_sa E_q[sa, nu] Y[c, mb, sa]; rate terms
-            for (int it = tid; it < 16 * nmb * nm; it += 256) {
-                const int c = it / (nmb * nm);
-                const int r = it - c * nmb * nm;
-                const int mb = r / nm, nu = r - mb * nm;
-                const int q0 = qc + c;
-                if (q0 >= N0) continue;
-                const int64_t q = (int64_t)q0 * NL + q12;
-                const int64_t kq = (int64_t)((k0i + q0) % mesh.n0) * NL + kq12;
-                const int m = mb == 0 ? ml[0] : mb == 1 ? ml[1] : mb == 2 ? ml[2] : ml[3];
-                const double x = eps_n - a.eps[kq * nW + m];
-                const double w = a.omega[q * nm + nu];
-                const double y1 = x - w, y2 = x + w;
-                // both Gaussians underflow to exactly 0: the term is 0
-                if (fabs(y1) > cut && fabs(y2) > cut) continue;
-                const double fm = a.focc[kq * nW + m];
-                const double nbq = a.nb[q * nm + nu];
-                const C* Yr = sY + (c * kMBL + mb) * nm;
-                const cd* Eq = a.E + q * nm * nm + nu;
-                C z = {0, 0};
-                for (int sa = 0; sa < nm; ++sa) z = cfma(to_c<C>(Eq[sa * nm]), Yr[sa], z);
-                const double g1 = exp(-y1 * y1 * inv_s2), g2 = exp(-y2 * y2 * inv_s2);
-                const double term = cabs2(z) * ((nbq + 1.0 - fm) * g1 + (nbq + fm) * g2);
-                gacc += term;
-                if (a.terms)
-                    atomicAdd(&a.terms[((int64_t)st * a.nq_mesh + q) * nm + nu],
-                              a.terms_scale * term);
+            // Y[q0 = qc + li, sa] = sum_b X[q0, sa, b] U_{k+q}[b, m]: products over
+            // the lane's four b, then the sum over the four rows; rows 0/1 receive
+            // Re Y of tiles t/t+1, rows 2/3 Im Y of tiles t/t+1.
+            R pr[P], pi[P];
+#pragma unroll
+            for (int t = 0; t < P; ++t) {
+                R xr = 0, xi = 0;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    xr += cr[t][v] * d.u[v].x - ci[t][v] * d.u[v].y;
+                    xi += cr[t][v] * d.u[v].y + ci[t][v] * d.u[v].x;
+                }
+                pr[t] = xr;
+                pi[t] = xi;
             }
-            __syncthreads();
+#pragma unroll
+            for (int t = 0; t < P; t += 2) {
+                const R y = rows4_reduce_scatter(pr[t], t + 1 < P ? pr[t + 1] : R(0), pi[t],
+                                                 t + 1 < P ? pi[t + 1] : R(0));
+                const int tt = t0 + t + (lg & 1);
+                const int sa = wave * TN + tt;
+                if (t + (lg & 1) < P && tt < TN && sa < nm)
+                    reinterpret_cast<R*>(sY + li * nm + sa)[lg >> 1] = y;
+            }
         }
+        __syncthreads();
+        // Z[c, nu] = sum_sa E_q[sa, nu] Y[c, sa] and the rate terms
+        if (has_item && qc + ic < N0) item_term(qc, ic, inu, d.em, d.fm, d.om, d.nbq);
+        for (int it = tid + 256; it < 16 * nm; it += 256) {
+            const int c = it / nm, nu = it - c * nm;
+            if (qc + c >= N0) continue;
+            const int64_t q = (int64_t)(qc + c) * NL + q12;
+            const int64_t kq = (int64_t)((k0i + qc + c) % N0) * NL + kq12;
+            item_term(qc, c, nu, a.eps[kq * nW + m], a.focc[kq * nW + m], a.omega[q * nm + nu],
+                      a.nb[q * nm + nu]);
+        }
+        // next unit: the next live band of this chunk, else the next live chunk
+        bands &= bands - 1;
+        while (!bands) {
+            qc += 16;
+            if (qc >= N0) break;
+            bands = sLive[qc >> 4];
+        }
+        if (qc >= N0) break;
+        m = __builtin_ctz(bands);
+        load_unit(qc, m, d);
+        __syncthreads();  // sY is rewritten by the next unit
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) gacc += __shfl_xor(gacc, o, 64);
@@ -599,7 +660,7 @@ __global__ __launch_bounds__(256, (TN >= 6 ? 2 : 4)) void line_rates_kernel(Rate
 
 size_t line_rates_lds(int W, int N0, int nm, bool f32) {
     const int Wp = (W + 3) & ~3, N0p = (N0 + 15) & ~15;
-    return ((size_t)N0p * Wp + 16 * (size_t)kMBL * nm) * (f32 ? sizeof(cf) : sizeof(cd));
+    return ((size_t)N0p * Wp + 16 * (size_t)nm) * (f32 ? sizeof(cf) : sizeof(cd));
 }
 
 // Columns of the factorised form: one 16-wide tile per mode index, 4 waves x TN tiles.
@@ -630,6 +691,7 @@ static hipError_t go_line(const RateArgs& a, int nst, hipStream_t s) {
         b.st_mhi += s0;
         b.partial = a.partial + (int64_t)s0 * a.n_qtiles;
         if (a.terms) b.terms = a.terms + (int64_t)s0 * a.nq_mesh * a.nm;
+        b.live = a.live + (int64_t)s0 * NL * ((a.mesh.n0 + 15) / 16);
         b.n_states = ns;
         hipLaunchKernelGGL((line_rates_kernel<TN, C>), dim3((unsigned)(groups * 8 * ns)), dim3(256),
                            shm, s, b);
@@ -641,7 +703,7 @@ template <class C>
 static hipError_t line_rates(const RateArgs& a, int nst, hipStream_t s) {
     if (nst <= 0) return hipSuccess;
     if (a.n_qtiles != a.mesh.n1 * a.mesh.n2 || a.n_qtiles > 65535 || a.W > kMaxW ||
-        a.mesh.n0 > 16 * kMaxChunks || line_rates_ncpad(a.nm, a.nW) != a.nc_pad)
+        a.mesh.n0 > 16 * kMaxChunks || line_rates_ncpad(a.nm, a.nW) != a.nc_pad || !a.live)
         return hipErrorInvalidValue;
     switch (a.nc_pad / 64) {
         case 1: return go_line<1, C>(a, nst, s);

@@ -257,9 +257,9 @@ __global__ __launch_bounds__(256, (TN >= 12 ? 1 : 2)) void stage2_rates_kernel(R
                 if (kq < 0) continue;
                 const int64_t q = sQ[c];
                 const cd* Yr = sY + (c * kMB + mb) * nm;
-                const cd* Eq = a.E + q * nm * nm + nu;
+                const cd* Eq = a.E + (q * nm + nu) * nm;
                 cd z = {0.0, 0.0};
-                for (int sa = 0; sa < nm; ++sa) z = cfma(Eq[sa * nm], Yr[sa], z);
+                for (int sa = 0; sa < nm; ++sa) z = cfma(Eq[sa], Yr[sa], z);
                 const int m = m0 + mb;
                 const double x = eps_n - a.eps[(int64_t)kq * nW + m];
                 const double fm = a.focc[(int64_t)kq * nW + m];
@@ -509,7 +509,7 @@ hipError_t launch_fold_all(const cd* G, const cd* U, int n_rp, int nm, int nW, c
     return hipGetLastError();
 }
 
-// g[q, nu, n, m] = sum_sa E[q, sa, nu] sum_b X[q, sa, n, b] Ukq[q, b, m]
+// g[q, nu, n, m] = sum_sa E[q, nu, sa] sum_b X[q, sa, n, b] Ukq[q, b, m]
 __global__ void rotate_g_kernel(const cd* __restrict__ X, int64_t nq, const cd* __restrict__ Ukq,
                                 const cd* __restrict__ E, int nW, int nm, cd* __restrict__ g) {
     const int64_t total = nq * nW * nW;
@@ -531,7 +531,7 @@ __global__ void rotate_g_kernel(const cd* __restrict__ X, int64_t nq, const cd* 
         cd* go = g + q * nm * nW * nW;
         for (int nu = 0; nu < nm; ++nu) {
             cd z = {0.0, 0.0};
-            for (int sa = 0; sa < nm; ++sa) z = cfma(Eq[sa * nm + nu], Y[sa], z);
+            for (int sa = 0; sa < nm; ++sa) z = cfma(Eq[nu * nm + sa], Y[sa], z);
             go[((int64_t)nu * nW + n) * nW + m] = z;
         }
     }
