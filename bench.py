@@ -100,10 +100,15 @@ def main():
         n = int(args.copy_calibration * 2**30) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
-        for _ in range(5):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+        for i in range(5):
+            ev[i].record()
             dst.copy_(src)
+        ev[5].record()
         torch.cuda.synchronize()
-        log(f"copied {n * 8} bytes 5 times")
+        best = min(ev[i].elapsed_time(ev[i + 1]) for i in range(5))
+        log(f"copied {n * 8} bytes 5 times; best {best:.3f} ms = "
+            f"{2 * n * 8 / best / 1e6:.1f} GB/s read + write")
         return
     if args.workload == "batched":
         return bench_batched(args)
@@ -153,8 +158,10 @@ def main():
     # flops; rotations and rate terms are not counted):
     #   stage2_rates    direct sum over the Rp list: 8 N_q n_rp nModes nW per state
     #   stage1_phase    sum over Re: 8 n_re n_rp nModes nW^2 per kept k
-    #   stage1_axes     the same sum factorised over the Re box, HBM: g(Re,Rp) read
-    #                   once per batch, intermediates once each way, G once
+    #   stage1_axes     the same sum factorised over the Re box, HBM: per batch, the
+    #                   batch's T0 planes read (with g read and T0 written first when
+    #                   the planes are per batch) and G written once
+    #   stage1_planes   T0 of every k0 plane in one pass: g read once, T0 written once
     #   line_rates      last axis of the factorised sum: 8 N_q W nModes nW per state
     #   axis_transforms first two axes, HBM traffic: 16 B (8 B in FP32) nModes nW per state x
     #                   (n_rp read + 2 W^2 N2 for T1 + W N1 N2 for T2)
@@ -163,9 +170,10 @@ def main():
     work = {
         "stage2_rates": ("mfma", 8.0 * n_states * N * n_rp * nc),
         "stage1_phase": ("mfma", 8.0 * n_kept * n_re * n_rp * nm * nW * nW),
-        # factorised stage 1, HBM: g(Re,Rp) read once per batch, its two intermediates
-        # written and read once, G written once (bytes recorded by the library)
+        # factorised stage 1, HBM (bytes recorded by the library per launch)
         "stage1_axes": ("hbm", None),
+        # T0 of every k0 plane in one pass over g (when the workspace holds them all)
+        "stage1_planes": ("hbm", None),
         "line_rates": ("mfma", 8.0 * n_states * N * W * nc),
         "axis_transforms": ("hbm", (8.0 if args.precision == "fp32" else 16.0) * nc * n_states *
                             (n_rp + 2 * W * W * mesh[2] + W * mesh[1] * mesh[2])),
@@ -179,8 +187,8 @@ def main():
         if n_l == 0:
             continue
         lps = n_l / args.steps
-        if name == "stage1_axes":
-            # the library records each batch's bytes (g, both intermediates, G)
+        if name in ("stage1_axes", "stage1_planes"):
+            # the library records each launch's bytes (g, the intermediates, G)
             amount = lib.kernel_bytes(name) / args.steps
         avg_ms = ms / n_l
         per_launch = amount / lps

@@ -495,6 +495,12 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
         }
         // batch buffers (upper bound on the states of a batch: BK * nW)
         const int max_states = BK * nW;
+        // Factorised stage 1 keeps the first intermediate T0 either for the k0
+        // planes of one batch (g(Re,Rp) is read once per batch) or, when the
+        // workspace budget allows it, for every k0 plane of the call (g is read
+        // once per call and the batches are no longer limited by their k0 count).
+        const size_t plane_bytes = (size_t)We * We * NC2 * g_elem;
+        const int64_t planes_cap = std::min<int64_t>(mesh.n0, rows_cap);
         const size_t batch_bytes = 4 * 256 + (size_t)BK * n_re * sizeof(cd) +
                                    (size_t)BK * NC2 * g_elem +
                                    (size_t)max_states * rp_pad * nc_pad * f_elem +
@@ -502,10 +508,13 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                                    (factored ? (size_t)nsb * t12_state + 512 : 0) +
                                    (factored ? (size_t)nsb * NL * nch_line * sizeof(uint32_t) + 256
                                              : 0) +
-                                   (re_fact ? (size_t)kD0Max * We * We * NC2 * g_elem +
-                                                  (size_t)rows_cap * 160 * sizeof(int32_t) + 1024
+                                   (re_fact ? (size_t)rows_cap * 168 * sizeof(int32_t) + 1024
                                             : 0);
-        ensure_ws(h, tables_end + std::max(scratch_bands, batch_bytes) + 256);
+        const bool all_planes =
+            re_fact && tables_end + std::max(scratch_bands, batch_bytes + planes_cap * plane_bytes) +
+                               256 <= h->budget;
+        const size_t t0_bytes = re_fact ? (all_planes ? planes_cap : kD0Max) * plane_bytes : 0;
+        ensure_ws(h, tables_end + std::max(scratch_bands, batch_bytes + t0_bytes) + 256);
         Arena ar(h->ws);
         plan_tables(ar);
         {
@@ -624,7 +633,8 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
         // distinct (k0, k1), with the grouping lists the axis kernels use.
         std::vector<std::pair<int64_t, int64_t>> batches;
         std::vector<int32_t> rbh;          // grouping lists of every batch, one array
-        std::vector<std::array<int64_t, 8>> rbo;  // per batch: d0, d01, offsets of the 6 lists
+        std::vector<std::array<int64_t, 9>> rbo;  // per batch: d0, d01, offsets of the 7 lists
+        std::vector<int32_t> planes;               // every distinct k0 of the call, ascending
         if (!re_fact) {
             for (int64_t r0 = 0; r0 < rows; r0 += BK) batches.push_back({r0, std::min<int64_t>(BK, rows - r0)});
         } else {
@@ -632,6 +642,11 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
             HIPCHK(h, hipMemcpyAsync(kh.data(), kept, sizeof(int32_t) * rows, hipMemcpyDeviceToHost, s));
             HIPCHK(h, hipStreamSynchronize(s));
             const int64_t n12 = (int64_t)mesh.n1 * mesh.n2;
+            if (all_planes) {
+                for (int64_t i = 0; i < rows; ++i) planes.push_back((int32_t)(kh[i] / n12));
+                std::sort(planes.begin(), planes.end());
+                planes.erase(std::unique(planes.begin(), planes.end()), planes.end());
+            }
             int64_t r = 0;
             while (r < rows) {
                 std::vector<int32_t> k0s, prs;  // distinct k0 and pair ids k0 n1 + k1
@@ -641,7 +656,9 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                     const int32_t pr = (int32_t)(kh[e] / mesh.n2);
                     const bool n0 = std::find(k0s.begin(), k0s.end(), k0) == k0s.end();
                     const bool n01 = std::find(prs.begin(), prs.end(), pr) == prs.end();
-                    if ((int)k0s.size() + n0 > kD0Max || (int)prs.size() + n01 > kD01Max) break;
+                    if ((!all_planes && (int)k0s.size() + n0 > kD0Max) ||
+                        (int)prs.size() + n01 > kD01Max)
+                        break;
                     if (n0) k0s.push_back(k0);
                     if (n01) prs.push_back(pr);
                     ++e;
@@ -650,7 +667,7 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                 std::sort(prs.begin(), prs.end());
                 const int d0 = (int)k0s.size(), d01 = (int)prs.size();
                 const int64_t nb = e - r;
-                std::array<int64_t, 8> o{};
+                std::array<int64_t, 9> o{};
                 o[0] = d0;
                 o[1] = d01;
                 // d_k0
@@ -689,17 +706,27 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                 o[7] = (int64_t)rbh.size();
                 for (int pp = 0; pp < d01; ++pp)
                     for (int32_t lr : byp[pp]) rbh.push_back((int32_t)(kh[r + lr] % mesh.n2));
+                // d_plane: position of each distinct k0 in the call's plane list
+                o[8] = (int64_t)rbh.size();
+                for (int32_t k0 : k0s)
+                    rbh.push_back(all_planes ? (int32_t)(std::lower_bound(planes.begin(), planes.end(),
+                                                                           k0) - planes.begin())
+                                             : 0);
                 rbo.push_back(o);
                 batches.push_back({r, nb});
                 r = e;
             }
-            REQUIRE(h, rbh.size() <= (size_t)rows_cap * 160, "stage-1 grouping lists too long");
+            if (all_planes) {  // the plane list itself, after the batch lists
+                rbo.push_back({(int64_t)planes.size(), 0, (int64_t)rbh.size(), 0, 0, 0, 0, 0, 0});
+                rbh.insert(rbh.end(), planes.begin(), planes.end());
+            }
+            REQUIRE(h, rbh.size() <= (size_t)rows_cap * 168, "stage-1 grouping lists too long");
         }
         int32_t* rbd = re_fact ? ar.take<int32_t>(std::max<size_t>(rbh.size(), 1)) : nullptr;
         if (re_fact)
             HIPCHK(h, hipMemcpyAsync(rbd, rbh.data(), sizeof(int32_t) * rbh.size(),
                                      hipMemcpyHostToDevice, s));
-        char* T0re = re_fact ? ar.take<char>((size_t)kD0Max * We * We * NC2 * g_elem) : nullptr;
+        char* T0re = re_fact ? ar.take<char>(t0_bytes) : nullptr;
         cd* P1 = ar.take<cd>((size_t)BK * n_re);
         char* Gbuf = ar.take<char>((size_t)BK * NC2 * g_elem);
         char* Fbuf = ar.take<char>((size_t)max_states * rp_pad * nc_pad * f_elem);
@@ -711,6 +738,20 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
 
         const double inv_sqrtpi_sigma = 1.0 / (std::sqrt(kPi) * par->sigma);
         const double scale = 2.0 * kPi * inv_sqrtpi_sigma * (q_off ? 1.0 : 1.0 / (double)N);
+        if (all_planes) {
+            // T0 of every k0 plane of the call: g(Re,Rp) read once, the planes written once
+            const auto& o = rbo.back();
+            Timer tp(h, s, "stage1_planes");
+            if (lowp)
+                HIPCHK(h, launch_re_planes_f32(reinterpret_cast<const cd*>(sys->g_rr), NC2, T.box_re,
+                                               rmax_e, T.Pre, rbd + o[2], (int)o[0],
+                                               reinterpret_cast<cf*>(T0re), s));
+            else
+                HIPCHK(h, launch_re_planes(reinterpret_cast<const cd*>(sys->g_rr), NC2, T.box_re,
+                                           rmax_e, T.Pre, rbd + o[2], (int)o[0],
+                                           reinterpret_cast<cd*>(T0re), s));
+            tp.done((double)NC2 * (16.0 * n_re + (double)g_elem * (double)o[0] * We * We));
+        }
         int sbeg = 0;
         for (size_t bi = 0; bi < batches.size(); ++bi) {
             const int64_t r0 = batches[bi].first, nb = batches[bi].second;
@@ -721,19 +762,33 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
             if (re_fact) {
                 const auto& o = rbo[bi];
                 ReBatch rb{(int)o[0], (int)o[1], rbd + o[2], rbd + o[3], rbd + o[4],
-                           rbd + o[5], rbd + o[6], rbd + o[7]};
+                           rbd + o[5], rbd + o[6], rbd + o[7], all_planes ? rbd + o[8] : nullptr};
                 Timer t1(h, s, "stage1_axes");
-                if (lowp)
-                    HIPCHK(h, launch_re_axes_f32(reinterpret_cast<const cd*>(sys->g_rr), NC2,
+                if (all_planes) {
+                    if (lowp)
+                        HIPCHK(h, launch_re_pairs_f32(reinterpret_cast<const cf*>(T0re), NC2, rmax_e,
+                                                      mesh, T.Pre, rb, reinterpret_cast<cf*>(Gbuf),
+                                                      NC2, s));
+                    else
+                        HIPCHK(h, launch_re_pairs(reinterpret_cast<const cd*>(T0re), NC2, rmax_e, mesh,
+                                                  T.Pre, rb, reinterpret_cast<cd*>(Gbuf), NC2, s));
+                    // the batch's T0 planes read once; G written once
+                    t1.done((double)NC2 * (double)g_elem * ((double)rb.d0 * We * We + nb));
+                } else {
+                    if (lowp)
+                        HIPCHK(h, launch_re_axes_f32(reinterpret_cast<const cd*>(sys->g_rr), NC2,
+                                                     T.box_re, rmax_e, mesh, T.Pre, rb,
+                                                     reinterpret_cast<cf*>(T0re),
+                                                     reinterpret_cast<cf*>(Gbuf), NC2, s));
+                    else
+                        HIPCHK(h, launch_re_axes(reinterpret_cast<const cd*>(sys->g_rr), NC2,
                                                  T.box_re, rmax_e, mesh, T.Pre, rb,
-                                                 reinterpret_cast<cf*>(T0re),
-                                                 reinterpret_cast<cf*>(Gbuf), NC2, s));
-                else
-                    HIPCHK(h, launch_re_axes(reinterpret_cast<const cd*>(sys->g_rr), NC2, T.box_re,
-                                             rmax_e, mesh, T.Pre, rb, reinterpret_cast<cd*>(T0re),
-                                             reinterpret_cast<cd*>(Gbuf), NC2, s));
-                // g (FP64) read once; T0 written and read once; G written once
-                t1.done((double)NC2 * (16.0 * n_re + (double)g_elem * (2.0 * rb.d0 * We * We + nb)));
+                                                 reinterpret_cast<cd*>(T0re),
+                                                 reinterpret_cast<cd*>(Gbuf), NC2, s));
+                    // g (FP64) read once; T0 written and read once; G written once
+                    t1.done((double)NC2 *
+                            (16.0 * n_re + (double)g_elem * (2.0 * rb.d0 * We * We + nb)));
+                }
             } else {
             HIPCHK(h, launch_phase_table(nullptr, kept + r0, mesh, nb, T.re, n_re, P1, n_re, s));
             Timer t1(h, s, "stage1_phase");

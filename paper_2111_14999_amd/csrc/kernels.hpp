@@ -114,6 +114,7 @@ hipError_t launch_axis_transforms_f32(const cf* F, int rp_pad, int nc_pad, const
 struct ReBatch {
     int d0, d01;
     const int32_t *d_k0, *pair_k1, *pair_off, *kp_off, *k_row, *k_k2;
+    const int32_t* d_plane;  // T0 plane of each distinct k0 (all planes resident), else null
 };
 hipError_t launch_re_axes(const cd* g, int64_t NC, const int32_t* box_re, int rmax, Mesh m,
                           const cd* P, const ReBatch& b, cd* T0, cd* G, int64_t ldg,
@@ -121,6 +122,17 @@ hipError_t launch_re_axes(const cd* g, int64_t NC, const int32_t* box_re, int rm
 hipError_t launch_re_axes_f32(const cd* g, int64_t NC, const int32_t* box_re, int rmax, Mesh m,
                               const cd* P, const ReBatch& b, cf* T0, cf* G, int64_t ldg,
                               hipStream_t s);
+// The same two steps apart, with T0 held for every k0 plane of the call: the
+// planes in one pass over g, then the pair and k steps of each batch.
+hipError_t launch_re_planes(const cd* g, int64_t NC, const int32_t* box_re, int rmax,
+                            const cd* P, const int32_t* k0_list, int n, cd* T0, hipStream_t s);
+hipError_t launch_re_planes_f32(const cd* g, int64_t NC, const int32_t* box_re, int rmax,
+                                const cd* P, const int32_t* k0_list, int n, cf* T0,
+                                hipStream_t s);
+hipError_t launch_re_pairs(const cd* T0, int64_t NC, int rmax, Mesh m, const cd* P,
+                           const ReBatch& b, cd* G, int64_t ldg, hipStream_t s);
+hipError_t launch_re_pairs_f32(const cf* T0, int64_t NC, int rmax, Mesh m, const cd* P,
+                               const ReBatch& b, cf* G, int64_t ldg, hipStream_t s);
 size_t re_axes_lds(int rmax, bool f32);
 
 // Axis 0 on MFMA + rotations + rate terms, one work-group per (state, q1, q2) line.

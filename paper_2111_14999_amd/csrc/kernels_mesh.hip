@@ -231,8 +231,9 @@ __global__ __launch_bounds__(256) void re_axis12_kernel(const C* __restrict__ T0
                                                         const int32_t* __restrict__ pair_off,
                                                         const int32_t* __restrict__ kp_off,
                                                         const int32_t* __restrict__ k_row,
-                                                        const int32_t* __restrict__ k_k2, int64_t ncb,
-                                                        C* __restrict__ G, int64_t ldg) {
+                                                        const int32_t* __restrict__ k_k2,
+                                                        const int32_t* __restrict__ d_plane,
+                                                        int64_t ncb, C* __restrict__ G, int64_t ldg) {
     constexpr int NV = WT > 0 ? WT : kMaxW;
     const int W = WT > 0 ? WT : Wr;
     extern __shared__ char smem_raw[];
@@ -240,7 +241,9 @@ __global__ __launch_bounds__(256) void re_axis12_kernel(const C* __restrict__ T0
     const int d = (int)(blockIdx.x / ncb);
     const int64_t c0 = (blockIdx.x % ncb) * 64;
     const int tid = threadIdx.x;
-    const C* src = T0 + (int64_t)d * W * W * NC + c0;
+    // T0 plane of the batch's d-th distinct k0 (all planes resident, or the batch's own)
+    const int plane = d_plane ? d_plane[d] : d;
+    const C* src = T0 + (int64_t)plane * W * W * NC + c0;
     for (int i = tid; i < W * W * 64; i += 256) {
         const int rr = i >> 6, cc = i & 63;
         sT[i] = c0 + cc < NC ? src[(int64_t)rr * NC + cc] : C{0, 0};
@@ -250,51 +253,81 @@ __global__ __launch_bounds__(256) void re_axis12_kernel(const C* __restrict__ T0
     // indices, and the phase-table reads they address, become scalar loads
     const int cc = tid & 63, tg = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t c = c0 + cc;
-    for (int pp = pair_off[d] + tg; pp < pair_off[d + 1]; pp += 4) {
-        const cd* Pk1 = P1 + (int64_t)pair_k1[pp] * W;
-        C t1[NV];
+    // two pairs per pass (pp and pp + 4): every T0 value read from LDS feeds
+    // two complex multiply-adds
+    const int pend = pair_off[d + 1];
+    for (int pp = pair_off[d] + tg; pp < pend; pp += 8) {
+        const bool two = pp + 4 < pend;
+        const cd* Pka = P1 + (int64_t)pair_k1[pp] * W;
+        const cd* Pkb = P1 + (int64_t)pair_k1[two ? pp + 4 : pp] * W;
+        C ta[NV], tb[NV];
 #pragma unroll
-        for (int r2 = 0; r2 < NV; ++r2) t1[r2] = C{0, 0};
-        // one R1 row at a time keeps the register footprint to the W sums
+        for (int r2 = 0; r2 < NV; ++r2) ta[r2] = tb[r2] = C{0, 0};
+        // one R1 row at a time keeps the register footprint to the 2 W sums
 #pragma unroll 1
         for (int r1 = 0; r1 < W; ++r1) {
-            const C p1 = to_c<C>(Pk1[r1]);
+            const C pa = to_c<C>(Pka[r1]), pb = to_c<C>(Pkb[r1]);
             const C* row = sT + r1 * W * 64 + cc;
 #pragma unroll
             for (int r2 = 0; r2 < NV; ++r2)
-                if (r2 < W) t1[r2] = cfma(p1, row[r2 * 64], t1[r2]);
+                if (r2 < W) {
+                    const C v = row[r2 * 64];
+                    ta[r2] = cfma(pa, v, ta[r2]);
+                    tb[r2] = cfma(pb, v, tb[r2]);
+                }
         }
-        for (int i = kp_off[pp]; i < kp_off[pp + 1]; ++i) {
-            const cd* Pk2 = P2 + (int64_t)k_k2[i] * W;
-            C acc = {0, 0};
 #pragma unroll
-            for (int r2 = 0; r2 < NV; ++r2)
-                if (r2 < W) acc = cfma(to_c<C>(Pk2[r2]), t1[r2], acc);
-            if (c < NC) G[(int64_t)k_row[i] * ldg + c] = acc;
+        for (int h = 0; h < 2; ++h) {
+            if (h == 1 && !two) break;
+            const int p = pp + 4 * h;
+            for (int i = kp_off[p]; i < kp_off[p + 1]; ++i) {
+                const cd* Pk2 = P2 + (int64_t)k_k2[i] * W;
+                C acc = {0, 0};
+#pragma unroll
+                for (int r2 = 0; r2 < NV; ++r2)
+                    if (r2 < W) acc = cfma(to_c<C>(Pk2[r2]), h ? tb[r2] : ta[r2], acc);
+                if (c < NC) G[(int64_t)k_row[i] * ldg + c] = acc;
+            }
         }
     }
 }
 
 template <int WT, class C>
-static hipError_t go_re_axes(const cd* g, int64_t NC, const int32_t* box_re, int W, Mesh m,
-                             const cd* P, const ReBatch& b, C* T0, C* G, int64_t ldg,
-                             hipStream_t s) {
+static hipError_t go_re_axis0(const cd* g, int64_t NC, const int32_t* box_re, int W, const cd* P,
+                              const int32_t* k0_list, int n, C* T0, hipStream_t s) {
+    hipLaunchKernelGGL((re_axis0_kernel<WT, C>), dim3(gridm((int64_t)W * W * NC, 256)), dim3(256),
+                       0, s, g, NC, box_re, W, P, k0_list, n, T0);
+    return hipGetLastError();
+}
+
+template <int WT, class C>
+static hipError_t go_re_axis12(const C* T0, int64_t NC, int W, Mesh m, const cd* P,
+                               const ReBatch& b, C* G, int64_t ldg, hipStream_t s) {
     const cd* P1 = P + (int64_t)m.n0 * W;
     const cd* P2 = P1 + (int64_t)m.n1 * W;
-    hipLaunchKernelGGL((re_axis0_kernel<WT, C>), dim3(gridm((int64_t)W * W * NC, 256)), dim3(256),
-                       0, s, g, NC, box_re, W, P, b.d_k0, b.d0, T0);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
     const size_t shm = (size_t)W * W * 64 * sizeof(C);
-    e = hipFuncSetAttribute((const void*)re_axis12_kernel<WT, C>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    hipError_t e = hipFuncSetAttribute((const void*)re_axis12_kernel<WT, C>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) return e;
     const int64_t ncb = (NC + 63) / 64;
     if ((int64_t)b.d0 * ncb > 2147483647LL) return hipErrorInvalidValue;
     hipLaunchKernelGGL((re_axis12_kernel<WT, C>), dim3((unsigned)(b.d0 * ncb)), dim3(256), shm, s,
-                       T0, NC, W, P1, P2, b.pair_k1, b.pair_off, b.kp_off, b.k_row, b.k_k2, ncb, G,
-                       ldg);
+                       T0, NC, W, P1, P2, b.pair_k1, b.pair_off, b.kp_off, b.k_row, b.k_k2,
+                       b.d_plane, ncb, G, ldg);
     return hipGetLastError();
+}
+
+// the box width as a compile-time constant where it is a common one
+template <class F>
+static hipError_t with_box_width(int W, F&& f) {
+    switch (W) {
+        case 1: return f(std::integral_constant<int, 1>{});
+        case 3: return f(std::integral_constant<int, 3>{});
+        case 5: return f(std::integral_constant<int, 5>{});
+        case 7: return f(std::integral_constant<int, 7>{});
+        case 9: return f(std::integral_constant<int, 9>{});
+        default: return f(std::integral_constant<int, 0>{});
+    }
 }
 
 // LDS of the fused kernel: W^2 x 64 staged values
@@ -307,16 +340,37 @@ template <class C>
 static hipError_t re_axes(const cd* g, int64_t NC, const int32_t* box_re, int rmax, Mesh m,
                           const cd* P, const ReBatch& b, C* T0, C* G, int64_t ldg, hipStream_t s) {
     const int W = 2 * rmax + 1;
-    if (W > kMaxW || b.d0 <= 0 || b.d01 <= 0 || re_axes_lds(rmax, sizeof(C) == sizeof(cf)) > 160 * 1024)
+    if (W > kMaxW || b.d0 <= 0 || b.d01 <= 0 || b.d_plane ||
+        re_axes_lds(rmax, sizeof(C) == sizeof(cf)) > 160 * 1024)
         return hipErrorInvalidValue;
-    switch (W) {
-        case 1: return go_re_axes<1, C>(g, NC, box_re, W, m, P, b, T0, G, ldg, s);
-        case 3: return go_re_axes<3, C>(g, NC, box_re, W, m, P, b, T0, G, ldg, s);
-        case 5: return go_re_axes<5, C>(g, NC, box_re, W, m, P, b, T0, G, ldg, s);
-        case 7: return go_re_axes<7, C>(g, NC, box_re, W, m, P, b, T0, G, ldg, s);
-        case 9: return go_re_axes<9, C>(g, NC, box_re, W, m, P, b, T0, G, ldg, s);
-        default: return go_re_axes<0, C>(g, NC, box_re, W, m, P, b, T0, G, ldg, s);
-    }
+    return with_box_width(W, [&](auto wt) {
+        constexpr int WT = decltype(wt)::value;
+        hipError_t e = go_re_axis0<WT, C>(g, NC, box_re, W, P, b.d_k0, b.d0, T0, s);
+        if (e != hipSuccess) return e;
+        return go_re_axis12<WT, C>(T0, NC, W, m, P, b, G, ldg, s);
+    });
+}
+
+template <class C>
+static hipError_t re_planes(const cd* g, int64_t NC, const int32_t* box_re, int rmax,
+                            const cd* P, const int32_t* k0_list, int n, C* T0, hipStream_t s) {
+    const int W = 2 * rmax + 1;
+    if (W > kMaxW || n <= 0) return hipErrorInvalidValue;
+    return with_box_width(W, [&](auto wt) {
+        return go_re_axis0<decltype(wt)::value, C>(g, NC, box_re, W, P, k0_list, n, T0, s);
+    });
+}
+
+template <class C>
+static hipError_t re_pairs(const C* T0, int64_t NC, int rmax, Mesh m, const cd* P,
+                           const ReBatch& b, C* G, int64_t ldg, hipStream_t s) {
+    const int W = 2 * rmax + 1;
+    if (W > kMaxW || b.d0 <= 0 || b.d01 <= 0 || !b.d_plane ||
+        re_axes_lds(rmax, sizeof(C) == sizeof(cf)) > 160 * 1024)
+        return hipErrorInvalidValue;
+    return with_box_width(W, [&](auto wt) {
+        return go_re_axis12<decltype(wt)::value, C>(T0, NC, W, m, P, b, G, ldg, s);
+    });
 }
 
 hipError_t launch_re_axes(const cd* g, int64_t NC, const int32_t* box_re, int rmax, Mesh m,
@@ -328,6 +382,23 @@ hipError_t launch_re_axes_f32(const cd* g, int64_t NC, const int32_t* box_re, in
                               const cd* P, const ReBatch& b, cf* T0, cf* G, int64_t ldg,
                               hipStream_t s) {
     return re_axes<cf>(g, NC, box_re, rmax, m, P, b, T0, G, ldg, s);
+}
+hipError_t launch_re_planes(const cd* g, int64_t NC, const int32_t* box_re, int rmax,
+                            const cd* P, const int32_t* k0_list, int n, cd* T0, hipStream_t s) {
+    return re_planes<cd>(g, NC, box_re, rmax, P, k0_list, n, T0, s);
+}
+hipError_t launch_re_planes_f32(const cd* g, int64_t NC, const int32_t* box_re, int rmax,
+                                const cd* P, const int32_t* k0_list, int n, cf* T0,
+                                hipStream_t s) {
+    return re_planes<cf>(g, NC, box_re, rmax, P, k0_list, n, T0, s);
+}
+hipError_t launch_re_pairs(const cd* T0, int64_t NC, int rmax, Mesh m, const cd* P,
+                           const ReBatch& b, cd* G, int64_t ldg, hipStream_t s) {
+    return re_pairs<cd>(T0, NC, rmax, m, P, b, G, ldg, s);
+}
+hipError_t launch_re_pairs_f32(const cf* T0, int64_t NC, int rmax, Mesh m, const cd* P,
+                               const ReBatch& b, cf* G, int64_t ldg, hipStream_t s) {
+    return re_pairs<cf>(T0, NC, rmax, m, P, b, G, ldg, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -6,7 +6,10 @@ the oracle checks the kept-k list and window masks bit for bit (its band
 tables cover the whole mesh) and Gamma on a seeded sample of kept k, each over
 the full 64,000-q mesh.  The two forms of the full-mesh sum over Rp (per-axis
 factorised, the default here, and the direct contraction) agree at every kept
-state.
+state, and so do the two forms of the factorised stage 1 (the first Re-axis
+intermediate held for every k0 plane of the call, the default with a large
+workspace budget, or for the k0 planes of one batch under a smaller budget),
+bit for bit, since every state's arithmetic is the same in both.
 """
 
 import numpy as np
@@ -30,6 +33,7 @@ def test_realistic_workload_sampled_parity():
     s = synth.config_c2()
     print("inputs ready", flush=True)
     lib = Library(0)
+    lib.set_timing(True)
     ds = DeviceSystem.from_host(s)
     gamma = torch.zeros((N, 16), dtype=torch.float64, device="cuda")
     mask = torch.zeros((N, 16), dtype=torch.uint8, device="cuda")
@@ -37,6 +41,7 @@ def test_realistic_workload_sampled_parity():
     n = lib.scatter_rates(ds, mesh, par, gamma, band_mask=mask, kept_k_out=kept)
     torch.cuda.synchronize()
     print(f"GPU done: {n} kept k", flush=True)
+    assert lib.kernel_time("stage1_planes")[0] == 1  # every k0 plane in one pass
     g = gamma.cpu().numpy()[:n]
     m = mask.cpu().numpy()[:n]
     kidx = kept.cpu().numpy()[:n]
@@ -53,8 +58,20 @@ def test_realistic_workload_sampled_parity():
           flush=True)
     assert dmax < 1e-11
     assert np.all(gd[~sel] == 0.0)
-    del ds
     lib.close()
+    # a 40 GB workspace budget holds the k0 planes of one batch only
+    small = Library(0, workspace_budget=40 * 10**9)
+    small.set_timing(True)
+    gamma.zero_()
+    n3 = small.scatter_rates(ds, mesh, par, gamma)
+    torch.cuda.synchronize()
+    assert small.kernel_time("stage1_planes")[0] == 0
+    assert small.kernel_time("stage1_axes")[0] > 0
+    assert n3 == n
+    assert np.array_equal(gamma.cpu().numpy()[:n], g)
+    print("per-batch and all-plane stage 1 agree bit for bit", flush=True)
+    small.close()
+    del ds
 
     tables = rates.mesh_tables(s, mesh)
     mask_all = rates.window_mask(tables["eps"], par["win_lo"], par["win_hi"])
