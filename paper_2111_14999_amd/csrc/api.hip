@@ -395,6 +395,9 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                              re_axes_lds(rmax_e, lowp) <= 160 * 1024 &&
                              (h->mesh_sum == PHOEBE_MESH_SUM_FACTORED || 2 * We <= n_re);
         constexpr int kD0Max = 8, kD01Max = 256;
+        // nW = 16: the pair and k steps of stage 1 apply the U_k fold themselves and
+        // write F; G (nW times larger) never reaches HBM
+        const bool fold_fused = re_fact && nW == 16 && cw == 16;
         int BK = re_fact ? 256 : 64;
         while (BK > 16 && ((double)BK * NC2 * g_elem > 8e9 ||
                            (double)BK * nW * rp_pad * nc_pad * f_elem > 8e9))
@@ -502,7 +505,7 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
         const size_t plane_bytes = (size_t)We * We * NC2 * g_elem;
         const int64_t planes_cap = std::min<int64_t>(mesh.n0, rows_cap);
         const size_t batch_bytes = 4 * 256 + (size_t)BK * n_re * sizeof(cd) +
-                                   (size_t)BK * NC2 * g_elem +
+                                   (fold_fused ? 0 : (size_t)BK * NC2 * g_elem) +
                                    (size_t)max_states * rp_pad * nc_pad * f_elem +
                                    (size_t)max_states * n_qtiles * sizeof(double) +
                                    (factored ? (size_t)nsb * t12_state + 512 : 0) +
@@ -633,7 +636,7 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
         // distinct (k0, k1), with the grouping lists the axis kernels use.
         std::vector<std::pair<int64_t, int64_t>> batches;
         std::vector<int32_t> rbh;          // grouping lists of every batch, one array
-        std::vector<std::array<int64_t, 9>> rbo;  // per batch: d0, d01, offsets of the 7 lists
+        std::vector<std::array<int64_t, 10>> rbo;  // per batch: d0, d01, offsets of the 8 lists
         std::vector<int32_t> planes;               // every distinct k0 of the call, ascending
         if (!re_fact) {
             for (int64_t r0 = 0; r0 < rows; r0 += BK) batches.push_back({r0, std::min<int64_t>(BK, rows - r0)});
@@ -667,7 +670,7 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                 std::sort(prs.begin(), prs.end());
                 const int d0 = (int)k0s.size(), d01 = (int)prs.size();
                 const int64_t nb = e - r;
-                std::array<int64_t, 9> o{};
+                std::array<int64_t, 10> o{};
                 o[0] = d0;
                 o[1] = d01;
                 // d_k0
@@ -712,12 +715,21 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                     rbh.push_back(all_planes ? (int32_t)(std::lower_bound(planes.begin(), planes.end(),
                                                                            k0) - planes.begin())
                                              : 0);
+                // row_st: first state (batch-local) of every batch row, and the end
+                o[9] = (int64_t)rbh.size();
+                {
+                    const int64_t s0 = std::lower_bound(strow.begin(), strow.end(), (int32_t)r) -
+                                       strow.begin();
+                    for (int64_t i = r; i <= e; ++i)
+                        rbh.push_back((int32_t)(std::lower_bound(strow.begin(), strow.end(),
+                                                                 (int32_t)i) - strow.begin() - s0));
+                }
                 rbo.push_back(o);
                 batches.push_back({r, nb});
                 r = e;
             }
             if (all_planes) {  // the plane list itself, after the batch lists
-                rbo.push_back({(int64_t)planes.size(), 0, (int64_t)rbh.size(), 0, 0, 0, 0, 0, 0});
+                rbo.push_back({(int64_t)planes.size(), 0, (int64_t)rbh.size(), 0, 0, 0, 0, 0, 0, 0});
                 rbh.insert(rbh.end(), planes.begin(), planes.end());
             }
             REQUIRE(h, rbh.size() <= (size_t)rows_cap * 168, "stage-1 grouping lists too long");
@@ -728,7 +740,7 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                                      hipMemcpyHostToDevice, s));
         char* T0re = re_fact ? ar.take<char>(t0_bytes) : nullptr;
         cd* P1 = ar.take<cd>((size_t)BK * n_re);
-        char* Gbuf = ar.take<char>((size_t)BK * NC2 * g_elem);
+        char* Gbuf = fold_fused ? nullptr : ar.take<char>((size_t)BK * NC2 * g_elem);
         char* Fbuf = ar.take<char>((size_t)max_states * rp_pad * nc_pad * f_elem);
         double* partial = ar.take<double>((size_t)max_states * n_qtiles);
         char* T1buf = factored ? ar.take<char>((size_t)nsb * Wbox * Wbox * mesh.n2 * nc_pad * g_elem)
@@ -738,17 +750,19 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
 
         const double inv_sqrtpi_sigma = 1.0 / (std::sqrt(kPi) * par->sigma);
         const double scale = 2.0 * kPi * inv_sqrtpi_sigma * (q_off ? 1.0 : 1.0 / (double)N);
+        if (fold_fused)  // F's padding (rows >= n_rp, columns of no mode) is never written
+            HIPCHK(h, hipMemsetAsync(Fbuf, 0, (size_t)max_states * rp_pad * nc_pad * f_elem, s));
         if (all_planes) {
             // T0 of every k0 plane of the call: g(Re,Rp) read once, the planes written once
             const auto& o = rbo.back();
             Timer tp(h, s, "stage1_planes");
             if (lowp)
                 HIPCHK(h, launch_re_planes_f32(reinterpret_cast<const cd*>(sys->g_rr), NC2, T.box_re,
-                                               rmax_e, T.Pre, rbd + o[2], (int)o[0],
+                                               rmax_e, T.Pre, rbd + o[2], (int)o[0], fold_fused,
                                                reinterpret_cast<cf*>(T0re), s));
             else
                 HIPCHK(h, launch_re_planes(reinterpret_cast<const cd*>(sys->g_rr), NC2, T.box_re,
-                                           rmax_e, T.Pre, rbd + o[2], (int)o[0],
+                                           rmax_e, T.Pre, rbd + o[2], (int)o[0], fold_fused,
                                            reinterpret_cast<cd*>(T0re), s));
             tp.done((double)NC2 * (16.0 * n_re + (double)g_elem * (double)o[0] * We * We));
         }
@@ -763,31 +777,37 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                 const auto& o = rbo[bi];
                 ReBatch rb{(int)o[0], (int)o[1], rbd + o[2], rbd + o[3], rbd + o[4],
                            rbd + o[5], rbd + o[6], rbd + o[7], all_planes ? rbd + o[8] : nullptr};
+                FoldOut fo{rbd + o[9], T.st_kmesh + sbeg, T.st_band + sbeg, T.U,
+                           nW, nm, n_rp, rp_pad, nc_pad, Fbuf};
+                const FoldOut* fop = fold_fused ? &fo : nullptr;
+                // written once: G, or F when the fold is applied here
+                const double out_bytes = fold_fused ? (double)ns * n_rp * nm * nW * f_elem
+                                                    : (double)nb * NC2 * g_elem;
                 Timer t1(h, s, "stage1_axes");
                 if (all_planes) {
                     if (lowp)
                         HIPCHK(h, launch_re_pairs_f32(reinterpret_cast<const cf*>(T0re), NC2, rmax_e,
-                                                      mesh, T.Pre, rb, reinterpret_cast<cf*>(Gbuf),
-                                                      NC2, s));
+                                                      mesh, T.Pre, rb, fop,
+                                                      reinterpret_cast<cf*>(Gbuf), NC2, s));
                     else
                         HIPCHK(h, launch_re_pairs(reinterpret_cast<const cd*>(T0re), NC2, rmax_e, mesh,
-                                                  T.Pre, rb, reinterpret_cast<cd*>(Gbuf), NC2, s));
-                    // the batch's T0 planes read once; G written once
-                    t1.done((double)NC2 * (double)g_elem * ((double)rb.d0 * We * We + nb));
+                                                  T.Pre, rb, fop, reinterpret_cast<cd*>(Gbuf), NC2, s));
+                    // the batch's T0 planes read once
+                    t1.done((double)NC2 * (double)g_elem * rb.d0 * We * We + out_bytes);
                 } else {
                     if (lowp)
                         HIPCHK(h, launch_re_axes_f32(reinterpret_cast<const cd*>(sys->g_rr), NC2,
-                                                     T.box_re, rmax_e, mesh, T.Pre, rb,
+                                                     T.box_re, rmax_e, mesh, T.Pre, rb, fop,
                                                      reinterpret_cast<cf*>(T0re),
                                                      reinterpret_cast<cf*>(Gbuf), NC2, s));
                     else
                         HIPCHK(h, launch_re_axes(reinterpret_cast<const cd*>(sys->g_rr), NC2,
-                                                 T.box_re, rmax_e, mesh, T.Pre, rb,
+                                                 T.box_re, rmax_e, mesh, T.Pre, rb, fop,
                                                  reinterpret_cast<cd*>(T0re),
                                                  reinterpret_cast<cd*>(Gbuf), NC2, s));
-                    // g (FP64) read once; T0 written and read once; G written once
-                    t1.done((double)NC2 *
-                            (16.0 * n_re + (double)g_elem * (2.0 * rb.d0 * We * We + nb)));
+                    // g (FP64) read once; T0 written and read once
+                    t1.done((double)NC2 * (16.0 * n_re + (double)g_elem * 2.0 * rb.d0 * We * We) +
+                            out_bytes);
                 }
             } else {
             HIPCHK(h, launch_phase_table(nullptr, kept + r0, mesh, nb, T.re, n_re, P1, n_re, s));
@@ -800,7 +820,9 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                                        reinterpret_cast<cd*>(Gbuf), NC2, nb, NC2, n_re, s));
             t1.done();
             }
-            if (lowp)
+            if (fold_fused) {
+                // F written by the stage-1 pair and k kernel
+            } else if (lowp)
                 HIPCHK(h, launch_fold_uk_lp(prec, reinterpret_cast<const cf*>(Gbuf), NC2, T.U,
                                             T.st_row + sbeg, (int)r0, T.st_kmesh + sbeg,
                                             T.st_band + sbeg, ns, n_rp, nm, nW, cw, rp_pad, nc_pad,

@@ -116,23 +116,37 @@ struct ReBatch {
     const int32_t *d_k0, *pair_k1, *pair_off, *kp_off, *k_row, *k_k2;
     const int32_t* d_plane;  // T0 plane of each distinct k0 (all planes resident), else null
 };
+// With fo set (nW = 16), the pair and k steps apply the U_k fold of the rates at
+// once and write F [states of the batch, rp_pad, nc_pad] (columns sa*16 + b)
+// instead of G; T0 is then stored with each 16 x 16 (a, b) block transposed.
+struct FoldOut {
+    const int32_t* row_st;    // [rows of the batch + 1] first state of each batch row
+    const int32_t* st_kmesh;  // [states of the batch] mesh index of the state's k
+    const int32_t* st_band;   // [states of the batch]
+    const cd* U;              // [Nk, nW, nW] eigenvectors, transposed: U[k, band, orbital]
+    int nW, nm, n_rp, rp_pad, nc_pad;
+    void* F;                  // cd (FP64) or cf (FP32 form)
+};
 hipError_t launch_re_axes(const cd* g, int64_t NC, const int32_t* box_re, int rmax, Mesh m,
-                          const cd* P, const ReBatch& b, cd* T0, cd* G, int64_t ldg,
-                          hipStream_t s);
+                          const cd* P, const ReBatch& b, const FoldOut* fo, cd* T0, cd* G,
+                          int64_t ldg, hipStream_t s);
 hipError_t launch_re_axes_f32(const cd* g, int64_t NC, const int32_t* box_re, int rmax, Mesh m,
-                              const cd* P, const ReBatch& b, cf* T0, cf* G, int64_t ldg,
-                              hipStream_t s);
+                              const cd* P, const ReBatch& b, const FoldOut* fo, cf* T0, cf* G,
+                              int64_t ldg, hipStream_t s);
 // The same two steps apart, with T0 held for every k0 plane of the call: the
-// planes in one pass over g, then the pair and k steps of each batch.
+// planes in one pass over g (tr: transposed (a, b) blocks, for the folded
+// form), then the pair and k steps of each batch.
 hipError_t launch_re_planes(const cd* g, int64_t NC, const int32_t* box_re, int rmax,
-                            const cd* P, const int32_t* k0_list, int n, cd* T0, hipStream_t s);
+                            const cd* P, const int32_t* k0_list, int n, bool tr, cd* T0,
+                            hipStream_t s);
 hipError_t launch_re_planes_f32(const cd* g, int64_t NC, const int32_t* box_re, int rmax,
-                                const cd* P, const int32_t* k0_list, int n, cf* T0,
+                                const cd* P, const int32_t* k0_list, int n, bool tr, cf* T0,
                                 hipStream_t s);
 hipError_t launch_re_pairs(const cd* T0, int64_t NC, int rmax, Mesh m, const cd* P,
-                           const ReBatch& b, cd* G, int64_t ldg, hipStream_t s);
+                           const ReBatch& b, const FoldOut* fo, cd* G, int64_t ldg, hipStream_t s);
 hipError_t launch_re_pairs_f32(const cf* T0, int64_t NC, int rmax, Mesh m, const cd* P,
-                               const ReBatch& b, cf* G, int64_t ldg, hipStream_t s);
+                               const ReBatch& b, const FoldOut* fo, cf* G, int64_t ldg,
+                               hipStream_t s);
 size_t re_axes_lds(int rmax, bool f32);
 
 // Axis 0 on MFMA + rotations + rate terms, one work-group per (state, q1, q2) line.

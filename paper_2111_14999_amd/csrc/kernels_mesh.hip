@@ -190,7 +190,7 @@ __global__ __launch_bounds__(256) void re_axis0_kernel(const cd* __restrict__ g,
                                                        const int32_t* __restrict__ box_re, int Wr,
                                                        const cd* __restrict__ P0,
                                                        const int32_t* __restrict__ d_k0, int d0,
-                                                       C* __restrict__ T0) {
+                                                       int tr, C* __restrict__ T0) {
     constexpr int NV = WT > 0 ? WT : kMaxW;
     const int W = WT > 0 ? WT : Wr;
     const int64_t W2 = (int64_t)W * W;
@@ -199,12 +199,15 @@ __global__ __launch_bounds__(256) void re_axis0_kernel(const cd* __restrict__ g,
          t += (int64_t)gridDim.x * blockDim.x) {
         const int64_t c = t % NC;
         const int64_t p = t / NC;
+        // tr: every 16 x 16 (a, b) block of a column group is stored transposed,
+        // T0 column (b, a) taking g column (a, b)
+        const int64_t cg = tr ? ((c & ~(int64_t)255) | ((c & 15) << 4) | ((c >> 4) & 15)) : c;
         C v[NV];
 #pragma unroll
         for (int r = 0; r < NV; ++r)
             if (r < W) {
                 const int row = box_re[r * W2 + p];
-                v[r] = row >= 0 ? to_c<C>(g[(int64_t)row * NC + c]) : C{0, 0};
+                v[r] = row >= 0 ? to_c<C>(g[(int64_t)row * NC + cg]) : C{0, 0};
             }
         for (int d = 0; d < d0; ++d) {
             const cd* Pk = P0 + (int64_t)d_k0[d] * W;
@@ -292,29 +295,152 @@ __global__ __launch_bounds__(256) void re_axis12_kernel(const C* __restrict__ T0
     }
 }
 
+// 16-lane row sum by DPP (quad_perm 1,0,3,2 and 2,3,0,1, row_half_mirror,
+// row_mirror), left in every lane of the row.
+template <int CTRL>
+__device__ inline double dpp_f64(double x) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+template <int CTRL>
+__device__ inline float dpp_f32(float x) {
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
+}
+template <class R>
+__device__ inline R row16_sum(R x) {
+    if constexpr (sizeof(R) == 8) {
+        x += dpp_f64<0xB1>(x);
+        x += dpp_f64<0x4E>(x);
+        x += dpp_f64<0x141>(x);
+        x += dpp_f64<0x140>(x);
+    } else {
+        x += dpp_f32<0xB1>(x);
+        x += dpp_f32<0x4E>(x);
+        x += dpp_f32<0x141>(x);
+        x += dpp_f32<0x140>(x);
+    }
+    return x;
+}
+
+// The pair and k steps with the U_k fold of the rates applied at once (nW = 16):
+// T0 holds every 16 x 16 (a, b) block transposed, so a 64-column block is
+// (b = 4 qb + g, a = i) for lane (g, i) of each wave and
+//   F[st, Rp, sa*16 + b] = sum_a conj(U_k[a, n_st]) G[k, Rp, sa, a, b]
+// is a sum over the 16 lanes of a row.  G never leaves the registers; F is
+// written once per state.
+template <int WT, class C>
+__global__ __launch_bounds__(256) void re_axis12_fold_kernel(
+    const C* __restrict__ T0, int64_t NC, int Wr, const cd* __restrict__ P1,
+    const cd* __restrict__ P2, const int32_t* __restrict__ pair_k1,
+    const int32_t* __restrict__ pair_off, const int32_t* __restrict__ kp_off,
+    const int32_t* __restrict__ k_row, const int32_t* __restrict__ k_k2,
+    const int32_t* __restrict__ d_plane, int64_t ncb, FoldOut fo) {
+    using R = decltype(C::x);
+    constexpr int NV = WT > 0 ? WT : kMaxW;
+    const int W = WT > 0 ? WT : Wr;
+    extern __shared__ char smem_raw[];
+    C* sT = reinterpret_cast<C*>(smem_raw);  // [W^2][64]
+    const int d = (int)(blockIdx.x / ncb);
+    const int64_t cb = blockIdx.x % ncb;
+    const int64_t c0 = cb * 64;
+    const int tid = threadIdx.x;
+    const int plane = d_plane ? d_plane[d] : d;
+    const C* src = T0 + (int64_t)plane * W * W * NC + c0;
+    for (int i = tid; i < W * W * 64; i += 256) sT[i] = src[(int64_t)(i >> 6) * NC + (i & 63)];
+    __syncthreads();
+    const int cc = tid & 63, tg = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int li = cc & 15, lg = cc >> 4;
+    // column block -> (Rp row r, mode sa, b quarter)
+    const int64_t grp = cb >> 2;
+    const int r = (int)(grp / fo.nm), sa = (int)(grp - (int64_t)r * fo.nm);
+    const int b = 4 * (int)(cb & 3) + lg;
+    C* Fo = reinterpret_cast<C*>(fo.F) + (int64_t)r * fo.nc_pad + sa * 16 + b;
+    const int64_t fst = (int64_t)fo.rp_pad * fo.nc_pad;
+    const int pend = pair_off[d + 1];
+    for (int pp = pair_off[d] + tg; pp < pend; pp += 8) {
+        const bool two = pp + 4 < pend;
+        const cd* Pka = P1 + (int64_t)pair_k1[pp] * W;
+        const cd* Pkb = P1 + (int64_t)pair_k1[two ? pp + 4 : pp] * W;
+        C ta[NV], tb[NV];
+#pragma unroll
+        for (int r2 = 0; r2 < NV; ++r2) ta[r2] = tb[r2] = C{0, 0};
+#pragma unroll 1
+        for (int r1 = 0; r1 < W; ++r1) {
+            const C pa = to_c<C>(Pka[r1]), pbv = to_c<C>(Pkb[r1]);
+            const C* row = sT + r1 * W * 64 + cc;
+#pragma unroll
+            for (int r2 = 0; r2 < NV; ++r2)
+                if (r2 < W) {
+                    const C v = row[r2 * 64];
+                    ta[r2] = cfma(pa, v, ta[r2]);
+                    tb[r2] = cfma(pbv, v, tb[r2]);
+                }
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (h == 1 && !two) break;
+            const int p = pp + 4 * h;
+            for (int i = kp_off[p]; i < kp_off[p + 1]; ++i) {
+                const cd* Pk2 = P2 + (int64_t)k_k2[i] * W;
+                C acc = {0, 0};
+#pragma unroll
+                for (int r2 = 0; r2 < NV; ++r2)
+                    if (r2 < W) acc = cfma(to_c<C>(Pk2[r2]), h ? tb[r2] : ta[r2], acc);
+                // this lane's G[k, Rp r, sa, a = li, b]; fold it into every state of row k
+                const int krow = k_row[i];
+                for (int st = fo.row_st[krow]; st < fo.row_st[krow + 1]; ++st) {
+                    const C u = to_c<C>(
+                        fo.U[((int64_t)fo.st_kmesh[st] * 16 + fo.st_band[st]) * 16 + li]);
+                    const R fr = row16_sum(u.x * acc.x + u.y * acc.y);
+                    const R fi = row16_sum(u.x * acc.y - u.y * acc.x);
+                    if (li == 0) Fo[st * fst] = C{fr, fi};
+                }
+            }
+        }
+    }
+}
+
 template <int WT, class C>
 static hipError_t go_re_axis0(const cd* g, int64_t NC, const int32_t* box_re, int W, const cd* P,
-                              const int32_t* k0_list, int n, C* T0, hipStream_t s) {
+                              const int32_t* k0_list, int n, bool tr, C* T0, hipStream_t s) {
     hipLaunchKernelGGL((re_axis0_kernel<WT, C>), dim3(gridm((int64_t)W * W * NC, 256)), dim3(256),
-                       0, s, g, NC, box_re, W, P, k0_list, n, T0);
+                       0, s, g, NC, box_re, W, P, k0_list, n, tr ? 1 : 0, T0);
     return hipGetLastError();
 }
 
 template <int WT, class C>
 static hipError_t go_re_axis12(const C* T0, int64_t NC, int W, Mesh m, const cd* P,
-                               const ReBatch& b, C* G, int64_t ldg, hipStream_t s) {
+                               const ReBatch& b, const FoldOut* fo, C* G, int64_t ldg,
+                               hipStream_t s) {
     const cd* P1 = P + (int64_t)m.n0 * W;
     const cd* P2 = P1 + (int64_t)m.n1 * W;
     const size_t shm = (size_t)W * W * 64 * sizeof(C);
-    hipError_t e = hipFuncSetAttribute((const void*)re_axis12_kernel<WT, C>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    const void* kern = fo ? (const void*)re_axis12_fold_kernel<WT, C>
+                          : (const void*)re_axis12_kernel<WT, C>;
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) return e;
     const int64_t ncb = (NC + 63) / 64;
     if ((int64_t)b.d0 * ncb > 2147483647LL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((re_axis12_kernel<WT, C>), dim3((unsigned)(b.d0 * ncb)), dim3(256), shm, s,
-                       T0, NC, W, P1, P2, b.pair_k1, b.pair_off, b.kp_off, b.k_row, b.k_k2,
-                       b.d_plane, ncb, G, ldg);
+    if (fo)
+        hipLaunchKernelGGL((re_axis12_fold_kernel<WT, C>), dim3((unsigned)(b.d0 * ncb)), dim3(256),
+                           shm, s, T0, NC, W, P1, P2, b.pair_k1, b.pair_off, b.kp_off, b.k_row,
+                           b.k_k2, b.d_plane, ncb, *fo);
+    else
+        hipLaunchKernelGGL((re_axis12_kernel<WT, C>), dim3((unsigned)(b.d0 * ncb)), dim3(256), shm,
+                           s, T0, NC, W, P1, P2, b.pair_k1, b.pair_off, b.kp_off, b.k_row, b.k_k2,
+                           b.d_plane, ncb, G, ldg);
     return hipGetLastError();
+}
+
+// the folded form needs nW = 16 (a 64-column block is 4 b x 16 a of one Rp row
+// and mode) and F columns sa*16 + b
+static bool fold_ok(const FoldOut* fo, int64_t NC) {
+    return !fo || (fo->nW == 16 && NC == (int64_t)fo->n_rp * fo->nm * 256 && fo->nc_pad >= 16 * fo->nm &&
+                   fo->rp_pad >= fo->n_rp && fo->row_st && fo->st_kmesh && fo->st_band && fo->U &&
+                   fo->F);
 }
 
 // the box width as a compile-time constant where it is a common one
@@ -338,67 +464,71 @@ size_t re_axes_lds(int rmax, bool f32) {
 
 template <class C>
 static hipError_t re_axes(const cd* g, int64_t NC, const int32_t* box_re, int rmax, Mesh m,
-                          const cd* P, const ReBatch& b, C* T0, C* G, int64_t ldg, hipStream_t s) {
+                          const cd* P, const ReBatch& b, const FoldOut* fo, C* T0, C* G,
+                          int64_t ldg, hipStream_t s) {
     const int W = 2 * rmax + 1;
-    if (W > kMaxW || b.d0 <= 0 || b.d01 <= 0 || b.d_plane ||
+    if (W > kMaxW || b.d0 <= 0 || b.d01 <= 0 || b.d_plane || !fold_ok(fo, NC) ||
         re_axes_lds(rmax, sizeof(C) == sizeof(cf)) > 160 * 1024)
         return hipErrorInvalidValue;
     return with_box_width(W, [&](auto wt) {
         constexpr int WT = decltype(wt)::value;
-        hipError_t e = go_re_axis0<WT, C>(g, NC, box_re, W, P, b.d_k0, b.d0, T0, s);
+        hipError_t e = go_re_axis0<WT, C>(g, NC, box_re, W, P, b.d_k0, b.d0, fo != nullptr, T0, s);
         if (e != hipSuccess) return e;
-        return go_re_axis12<WT, C>(T0, NC, W, m, P, b, G, ldg, s);
+        return go_re_axis12<WT, C>(T0, NC, W, m, P, b, fo, G, ldg, s);
     });
 }
 
 template <class C>
 static hipError_t re_planes(const cd* g, int64_t NC, const int32_t* box_re, int rmax,
-                            const cd* P, const int32_t* k0_list, int n, C* T0, hipStream_t s) {
+                            const cd* P, const int32_t* k0_list, int n, bool tr, C* T0,
+                            hipStream_t s) {
     const int W = 2 * rmax + 1;
-    if (W > kMaxW || n <= 0) return hipErrorInvalidValue;
+    if (W > kMaxW || n <= 0 || (tr && NC % 256 != 0)) return hipErrorInvalidValue;
     return with_box_width(W, [&](auto wt) {
-        return go_re_axis0<decltype(wt)::value, C>(g, NC, box_re, W, P, k0_list, n, T0, s);
+        return go_re_axis0<decltype(wt)::value, C>(g, NC, box_re, W, P, k0_list, n, tr, T0, s);
     });
 }
 
 template <class C>
 static hipError_t re_pairs(const C* T0, int64_t NC, int rmax, Mesh m, const cd* P,
-                           const ReBatch& b, C* G, int64_t ldg, hipStream_t s) {
+                           const ReBatch& b, const FoldOut* fo, C* G, int64_t ldg, hipStream_t s) {
     const int W = 2 * rmax + 1;
-    if (W > kMaxW || b.d0 <= 0 || b.d01 <= 0 || !b.d_plane ||
+    if (W > kMaxW || b.d0 <= 0 || b.d01 <= 0 || !b.d_plane || !fold_ok(fo, NC) ||
         re_axes_lds(rmax, sizeof(C) == sizeof(cf)) > 160 * 1024)
         return hipErrorInvalidValue;
     return with_box_width(W, [&](auto wt) {
-        return go_re_axis12<decltype(wt)::value, C>(T0, NC, W, m, P, b, G, ldg, s);
+        return go_re_axis12<decltype(wt)::value, C>(T0, NC, W, m, P, b, fo, G, ldg, s);
     });
 }
 
 hipError_t launch_re_axes(const cd* g, int64_t NC, const int32_t* box_re, int rmax, Mesh m,
-                          const cd* P, const ReBatch& b, cd* T0, cd* G, int64_t ldg,
-                          hipStream_t s) {
-    return re_axes<cd>(g, NC, box_re, rmax, m, P, b, T0, G, ldg, s);
+                          const cd* P, const ReBatch& b, const FoldOut* fo, cd* T0, cd* G,
+                          int64_t ldg, hipStream_t s) {
+    return re_axes<cd>(g, NC, box_re, rmax, m, P, b, fo, T0, G, ldg, s);
 }
 hipError_t launch_re_axes_f32(const cd* g, int64_t NC, const int32_t* box_re, int rmax, Mesh m,
-                              const cd* P, const ReBatch& b, cf* T0, cf* G, int64_t ldg,
-                              hipStream_t s) {
-    return re_axes<cf>(g, NC, box_re, rmax, m, P, b, T0, G, ldg, s);
+                              const cd* P, const ReBatch& b, const FoldOut* fo, cf* T0, cf* G,
+                              int64_t ldg, hipStream_t s) {
+    return re_axes<cf>(g, NC, box_re, rmax, m, P, b, fo, T0, G, ldg, s);
 }
 hipError_t launch_re_planes(const cd* g, int64_t NC, const int32_t* box_re, int rmax,
-                            const cd* P, const int32_t* k0_list, int n, cd* T0, hipStream_t s) {
-    return re_planes<cd>(g, NC, box_re, rmax, P, k0_list, n, T0, s);
+                            const cd* P, const int32_t* k0_list, int n, bool tr, cd* T0,
+                            hipStream_t s) {
+    return re_planes<cd>(g, NC, box_re, rmax, P, k0_list, n, tr, T0, s);
 }
 hipError_t launch_re_planes_f32(const cd* g, int64_t NC, const int32_t* box_re, int rmax,
-                                const cd* P, const int32_t* k0_list, int n, cf* T0,
+                                const cd* P, const int32_t* k0_list, int n, bool tr, cf* T0,
                                 hipStream_t s) {
-    return re_planes<cf>(g, NC, box_re, rmax, P, k0_list, n, T0, s);
+    return re_planes<cf>(g, NC, box_re, rmax, P, k0_list, n, tr, T0, s);
 }
 hipError_t launch_re_pairs(const cd* T0, int64_t NC, int rmax, Mesh m, const cd* P,
-                           const ReBatch& b, cd* G, int64_t ldg, hipStream_t s) {
-    return re_pairs<cd>(T0, NC, rmax, m, P, b, G, ldg, s);
+                           const ReBatch& b, const FoldOut* fo, cd* G, int64_t ldg, hipStream_t s) {
+    return re_pairs<cd>(T0, NC, rmax, m, P, b, fo, G, ldg, s);
 }
 hipError_t launch_re_pairs_f32(const cf* T0, int64_t NC, int rmax, Mesh m, const cd* P,
-                               const ReBatch& b, cf* G, int64_t ldg, hipStream_t s) {
-    return re_pairs<cf>(T0, NC, rmax, m, P, b, G, ldg, s);
+                               const ReBatch& b, const FoldOut* fo, cf* G, int64_t ldg,
+                               hipStream_t s) {
+    return re_pairs<cf>(T0, NC, rmax, m, P, b, fo, G, ldg, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -174,7 +174,7 @@ def _sparse_re(s, seed, keep_frac):
 
 
 @pytest.mark.parametrize("case", ["toy", "ragged-5x6x7", "sparse-rp", "sparse-re", "c2-tiling",
-                                  "single-line"])
+                                  "single-line", "nW16-sparse-re"])
 def test_mesh_sum_forms_match_oracle(lib, toy, case):
     if case == "toy":
         s, mesh, par, ref = toy
@@ -187,6 +187,8 @@ def test_mesh_sum_forms_match_oracle(lib, toy, case):
             s, mesh = _sparse_re(synth.small_system(75, n_wannier=4, n_atoms=2, r=2), 6, 0.3), (5, 4, 6)
         elif case == "c2-tiling":
             s, mesh = synth.small_system(73, n_wannier=16, n_atoms=5, r=1), (17, 3, 2)
+        elif case == "nW16-sparse-re":  # the folded stage 1 over a sparse 5^3 Re box
+            s, mesh = _sparse_re(synth.small_system(76, n_wannier=16, n_atoms=1, r=2), 7, 0.4), (6, 3, 4)
         else:
             s, mesh = synth.small_system(74, n_wannier=3, n_atoms=1, r=2), (33, 1, 1)
         s.h_r *= 0.3
@@ -208,10 +210,19 @@ def test_mesh_sum_forms_match_oracle(lib, toy, case):
     assert np.max(np.abs(gd - gf)) < 1e-12 * scale
 
 
-def test_mesh_sum_forms_unsorted_k_list(lib, toy):
+@pytest.mark.parametrize("system", ["toy", "nW16"])
+def test_mesh_sum_forms_unsorted_k_list(lib, toy, system):
     """Explicit k rows in no particular order over the full q mesh, both forms."""
-    s, mesh, par, _ = toy
-    k_idx = np.array([77, 5, 215, 0, 100, 3, 36, 37, 180, 1], dtype=np.int64)
+    if system == "toy":
+        s, mesh, par, _ = toy
+        k_idx = np.array([77, 5, 215, 0, 100, 3, 36, 37, 180, 1], dtype=np.int64)
+    else:
+        s, mesh = synth.small_system(77, n_wannier=16, n_atoms=1, r=1), (5, 4, 3)
+        s.h_r *= 0.3
+        mu = float(np.median(rates.mesh_tables(s, mesh)["eps"]))
+        par = dict(mu=mu, kT=constants.kT_of(300.0), sigma=0.05, win_lo=mu - 0.8,
+                   win_hi=mu + 0.8, omega_min=1e-4)
+        k_idx = np.array([41, 7, 59, 0, 23, 12, 36, 35, 50, 2, 19], dtype=np.int64)
     ref = rates.scattering_rates(s, mesh, k_idx=k_idx, **par)
     out = {}
     try:
