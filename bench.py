@@ -164,7 +164,7 @@ def main():
     #   stage1_planes   T0 of every k0 plane in one pass: g read once, T0 written once
     #   line_rates      last axis of the factorised sum: 8 N_q W nModes nW per state
     #   axis_transforms first two axes, HBM traffic: 16 B (8 B in FP32) nModes nW per state x
-    #                   (n_rp read + 2 W^2 N2 for T1 + W N1 N2 for T2)
+    #                   (n_rp read + 2 W^2 N2 for T1) + W per live (state, line) for T2
     W = 2 * int(np.abs(s.rp).max()) + 1
     nc = nm * nW
     work = {
@@ -175,8 +175,8 @@ def main():
         # T0 of every k0 plane in one pass over g (when the workspace holds them all)
         "stage1_planes": ("hbm", None),
         "line_rates": ("mfma", 8.0 * n_states * N * W * nc),
-        "axis_transforms": ("hbm", (8.0 if args.precision == "fp32" else 16.0) * nc * n_states *
-                            (n_rp + 2 * W * W * mesh[2] + W * mesh[1] * mesh[2])),
+        # first two Rp axes, HBM (bytes recorded by the library: T2 of live lines only)
+        "axis_transforms": ("hbm", None),
     }
     peak_mfma = {"fp64": PEAK_FP64_TFLOPS, "fp32": 157.3, "bf16x3": 2500.0 / 3,
                  "bf16x6": 2500.0 / 6}[args.precision]
@@ -187,7 +187,7 @@ def main():
         if n_l == 0:
             continue
         lps = n_l / args.steps
-        if name in ("stage1_axes", "stage1_planes"):
+        if name in ("stage1_axes", "stage1_planes", "axis_transforms"):
             # the library records each launch's bytes (g, the intermediates, G)
             amount = lib.kernel_bytes(name) / args.steps
         avg_ms = ms / n_l

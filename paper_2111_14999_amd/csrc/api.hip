@@ -509,7 +509,8 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                                    (size_t)max_states * rp_pad * nc_pad * f_elem +
                                    (size_t)max_states * n_qtiles * sizeof(double) +
                                    (factored ? (size_t)nsb * t12_state + 512 : 0) +
-                                   (factored ? (size_t)nsb * NL * nch_line * sizeof(uint32_t) + 256
+                                   (factored ? (size_t)nsb * NL * (nch_line * sizeof(uint32_t) + 1) +
+                                                   (size_t)rows_cap * nW * sizeof(uint32_t) + 512
                                              : 0) +
                                    (re_fact ? (size_t)rows_cap * 168 * sizeof(int32_t) + 1024
                                             : 0);
@@ -747,6 +748,20 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                                : nullptr;
         char* T2buf = factored ? ar.take<char>((size_t)nsb * Wbox * NL * nc_pad * g_elem) : nullptr;
         uint32_t* livebuf = factored ? ar.take<uint32_t>((size_t)nsb * NL * nch_line) : nullptr;
+        uint8_t* lineany = factored ? ar.take<uint8_t>((size_t)nsb * NL) : nullptr;
+        // live (state, line) count of every factorised sub-batch (traffic accounting)
+        int64_t n_sub = 0;
+        if (factored)
+            for (const auto& bt : batches) {
+                const int64_t a0 = std::lower_bound(strow.begin(), strow.end(), (int32_t)bt.first) -
+                                   strow.begin();
+                const int64_t a1 = std::lower_bound(strow.begin(), strow.end(),
+                                                    (int32_t)(bt.first + bt.second)) - strow.begin();
+                n_sub += (a1 - a0 + nsb - 1) / nsb;
+            }
+        uint32_t* nlive = factored ? ar.take<uint32_t>((size_t)std::max<int64_t>(n_sub, 1)) : nullptr;
+        if (factored) HIPCHK(h, hipMemsetAsync(nlive, 0, sizeof(uint32_t) * std::max<int64_t>(n_sub, 1), s));
+        int64_t isub = 0;
 
         const double inv_sqrtpi_sigma = 1.0 / (std::sqrt(kPi) * par->sigma);
         const double scale = 2.0 * kPi * inv_sqrtpi_sigma * (q_off ? 1.0 : 1.0 / (double)N);
@@ -885,18 +900,8 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                 ra.wmax = T.wmax;
                 for (int sb = 0; sb < ns; sb += nsb) {
                     const int nn = std::min(nsb, ns - sb);
-                    Timer ta(h, s, "axis_transforms");
-                    if (lowp)
-                        HIPCHK(h, launch_axis_transforms_f32(
-                                      reinterpret_cast<const cf*>(Fbuf) + (int64_t)sb * rp_pad * nc_pad,
-                                      rp_pad, nc_pad, T.box_rp, rmax_p, mesh, T.Pax, nn,
-                                      reinterpret_cast<cf*>(T1buf), reinterpret_cast<cf*>(T2buf), s));
-                    else
-                        HIPCHK(h, launch_axis_transforms(
-                                      reinterpret_cast<const cd*>(Fbuf) + (int64_t)sb * rp_pad * nc_pad,
-                                      rp_pad, nc_pad, T.box_rp, rmax_p, mesh, T.Pax, nn,
-                                      reinterpret_cast<cd*>(T1buf), reinterpret_cast<cd*>(T2buf), s));
-                    ta.done();
+                    REQUIRE(h, isub < n_sub, "sub-batch count");
+                    uint32_t* nl = nlive + isub++;
                     RateArgs rb = ra;
                     rb.T2 = T2buf;
                     rb.st_kmesh += sb;
@@ -907,7 +912,22 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                     rb.partial = partial + (int64_t)sb * n_qtiles;
                     if (ra.terms) rb.terms = ra.terms + (int64_t)sb * N * nm;
                     rb.live = livebuf;
-                    HIPCHK(h, launch_line_live(rb, nn, livebuf, s));
+                    // live bands of every (state, line, chunk) first: T2 is formed for live lines only
+                    HIPCHK(h, launch_line_live(rb, nn, livebuf, lineany, nl, s));
+                    Timer ta(h, s, "axis_transforms");
+                    if (lowp)
+                        HIPCHK(h, launch_axis_transforms_f32(
+                                      reinterpret_cast<const cf*>(Fbuf) + (int64_t)sb * rp_pad * nc_pad,
+                                      rp_pad, nc_pad, T.box_rp, rmax_p, mesh, T.Pax, nn, lineany,
+                                      reinterpret_cast<cf*>(T1buf), reinterpret_cast<cf*>(T2buf), s));
+                    else
+                        HIPCHK(h, launch_axis_transforms(
+                                      reinterpret_cast<const cd*>(Fbuf) + (int64_t)sb * rp_pad * nc_pad,
+                                      rp_pad, nc_pad, T.box_rp, rmax_p, mesh, T.Pax, nn, lineany,
+                                      reinterpret_cast<cd*>(T1buf), reinterpret_cast<cd*>(T2buf), s));
+                    // F read once, T1 written and read once; T2 written for the live lines
+                    const double ab = (double)g_elem * nm * nW;
+                    ta.done(ab * nn * ((double)n_rp + 2.0 * Wbox * Wbox * mesh.n2), nl, ab * Wbox);
                     Timer tl(h, s, "line_rates");
                     if (lowp)
                         HIPCHK(h, launch_line_rates_f32(rb, nn, s));

@@ -24,6 +24,9 @@ struct TimedLaunch {
     std::string name;
     hipEvent_t start, stop;
     double bytes = 0.0;  // algorithmic HBM bytes of the launch, where the host knows them
+    // plus bytes_per_count times a count the device leaves in *dcount
+    const uint32_t* dcount = nullptr;
+    double bytes_per_count = 0.0;
 };
 
 struct KernelStat {
@@ -125,9 +128,11 @@ struct Timer {
         HIPCHK(h, hipEventCreate(&t.stop));
         HIPCHK(h, hipEventRecord(t.start, s));
     }
-    void done(double bytes = 0.0) {
+    void done(double bytes = 0.0, const uint32_t* dcount = nullptr, double bytes_per_count = 0.0) {
         if (!on) return;
         t.bytes = bytes;
+        t.dcount = dcount;
+        t.bytes_per_count = bytes_per_count;
         HIPCHK(h, hipEventRecord(t.stop, s));
         h->pending.push_back(t);
         on = false;
@@ -150,6 +155,11 @@ inline void flush_timing(Handle* h, hipStream_t s) {
         ks->launches += 1;
         ks->total_ms += ms;
         ks->bytes += t.bytes;
+        if (t.dcount) {
+            uint32_t n = 0;
+            HIPCHK(h, hipMemcpy(&n, t.dcount, sizeof(n), hipMemcpyDeviceToHost));
+            ks->bytes += t.bytes_per_count * n;
+        }
         (void)hipEventDestroy(t.start);
         (void)hipEventDestroy(t.stop);
     }

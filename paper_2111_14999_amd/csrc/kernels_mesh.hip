@@ -98,12 +98,16 @@ __global__ __launch_bounds__(256) void axis2_kernel(const C* __restrict__ F, int
     }
 }
 
-// out[o, n, i] = sum_r P[n, r] in[o, r, i]   (i < inner, contiguous)
+// out[o, n, i] = sum_r P[n, r] in[o, r, i]   (i < inner, contiguous); here
+// o = (st, R0), n = q1 and i = (q2, column).  With line_any set, the output of a
+// (st, line = q1 N2 + q2) whose flag is 0 is not formed: the line kernel never
+// reads it.
 template <int WT, class C>
 __global__ __launch_bounds__(256) void axis_mid_kernel(const C* __restrict__ in, int64_t n_outer,
                                                        int Wr, int64_t inner, int N,
                                                        const cd* __restrict__ P,
-                                                       C* __restrict__ out) {
+                                                       const uint8_t* __restrict__ line_any,
+                                                       int nc, C* __restrict__ out) {
     constexpr int NV = WT > 0 ? WT : kMaxW;
     const int W = WT > 0 ? WT : Wr;
     const int64_t total = n_outer * inner;
@@ -117,7 +121,10 @@ __global__ __launch_bounds__(256) void axis_mid_kernel(const C* __restrict__ in,
         for (int r = 0; r < NV; ++r)
             if (r < W) v[r] = src[(int64_t)r * inner];
         C* dst = out + o * N * inner + i;
+        const int64_t n2 = inner / nc, q2 = i / nc;
+        const uint8_t* fl = line_any ? line_any + (o / W) * N * n2 + q2 : nullptr;
         for (int n = 0; n < N; ++n) {
+            if (fl && !fl[n * n2]) continue;
             const cd* Pn = P + n * W;
             C acc = {0, 0};
 #pragma unroll
@@ -130,46 +137,47 @@ __global__ __launch_bounds__(256) void axis_mid_kernel(const C* __restrict__ in,
 
 template <int WT, class C>
 static hipError_t go_axes(const C* F, int rp_pad, int nc_pad, const int32_t* box_rp, int W,
-                          Mesh m, const cd* P1, const cd* P2, int nst, C* T1, C* T2,
-                          hipStream_t s) {
+                          Mesh m, const cd* P1, const cd* P2, int nst, const uint8_t* line_any,
+                          C* T1, C* T2, hipStream_t s) {
     hipLaunchKernelGGL((axis2_kernel<WT, C>), dim3(gridm((int64_t)nst * W * W * nc_pad, 256)),
                        dim3(256), 0, s, F, rp_pad, nc_pad, box_rp, W, m.n2, P2, nst, T1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t inner = (int64_t)m.n2 * nc_pad;
     hipLaunchKernelGGL((axis_mid_kernel<WT, C>), dim3(gridm((int64_t)nst * W * inner, 256)),
-                       dim3(256), 0, s, T1, (int64_t)nst * W, W, inner, m.n1, P1, T2);
+                       dim3(256), 0, s, T1, (int64_t)nst * W, W, inner, m.n1, P1, line_any, nc_pad,
+                       T2);
     return hipGetLastError();
 }
 
 template <class C>
 static hipError_t axis_transforms(const C* F, int rp_pad, int nc_pad, const int32_t* box_rp,
-                                  int rmax, Mesh m, const cd* P, int nst, C* T1, C* T2,
-                                  hipStream_t s) {
+                                  int rmax, Mesh m, const cd* P, int nst, const uint8_t* line_any,
+                                  C* T1, C* T2, hipStream_t s) {
     const int W = 2 * rmax + 1;
     if (W > kMaxW) return hipErrorInvalidValue;
     if (nst <= 0) return hipSuccess;
     const cd* P1 = P + (int64_t)m.n0 * W;
     const cd* P2 = P1 + (int64_t)m.n1 * W;
     switch (W) {
-        case 1: return go_axes<1, C>(F, rp_pad, nc_pad, box_rp, W, m, P1, P2, nst, T1, T2, s);
-        case 3: return go_axes<3, C>(F, rp_pad, nc_pad, box_rp, W, m, P1, P2, nst, T1, T2, s);
-        case 5: return go_axes<5, C>(F, rp_pad, nc_pad, box_rp, W, m, P1, P2, nst, T1, T2, s);
-        case 7: return go_axes<7, C>(F, rp_pad, nc_pad, box_rp, W, m, P1, P2, nst, T1, T2, s);
-        case 9: return go_axes<9, C>(F, rp_pad, nc_pad, box_rp, W, m, P1, P2, nst, T1, T2, s);
-        default: return go_axes<0, C>(F, rp_pad, nc_pad, box_rp, W, m, P1, P2, nst, T1, T2, s);
+        case 1: return go_axes<1, C>(F, rp_pad, nc_pad, box_rp, W, m, P1, P2, nst, line_any, T1, T2, s);
+        case 3: return go_axes<3, C>(F, rp_pad, nc_pad, box_rp, W, m, P1, P2, nst, line_any, T1, T2, s);
+        case 5: return go_axes<5, C>(F, rp_pad, nc_pad, box_rp, W, m, P1, P2, nst, line_any, T1, T2, s);
+        case 7: return go_axes<7, C>(F, rp_pad, nc_pad, box_rp, W, m, P1, P2, nst, line_any, T1, T2, s);
+        case 9: return go_axes<9, C>(F, rp_pad, nc_pad, box_rp, W, m, P1, P2, nst, line_any, T1, T2, s);
+        default: return go_axes<0, C>(F, rp_pad, nc_pad, box_rp, W, m, P1, P2, nst, line_any, T1, T2, s);
     }
 }
 
 hipError_t launch_axis_transforms(const cd* F, int rp_pad, int nc_pad, const int32_t* box_rp,
-                                  int rmax, Mesh m, const cd* P, int nst, cd* T1, cd* T2,
-                                  hipStream_t s) {
-    return axis_transforms<cd>(F, rp_pad, nc_pad, box_rp, rmax, m, P, nst, T1, T2, s);
+                                  int rmax, Mesh m, const cd* P, int nst, const uint8_t* line_any,
+                                  cd* T1, cd* T2, hipStream_t s) {
+    return axis_transforms<cd>(F, rp_pad, nc_pad, box_rp, rmax, m, P, nst, line_any, T1, T2, s);
 }
 hipError_t launch_axis_transforms_f32(const cf* F, int rp_pad, int nc_pad, const int32_t* box_rp,
-                                      int rmax, Mesh m, const cd* P, int nst, cf* T1, cf* T2,
-                                      hipStream_t s) {
-    return axis_transforms<cf>(F, rp_pad, nc_pad, box_rp, rmax, m, P, nst, T1, T2, s);
+                                      int rmax, Mesh m, const cd* P, int nst,
+                                      const uint8_t* line_any, cf* T1, cf* T2, hipStream_t s) {
+    return axis_transforms<cf>(F, rp_pad, nc_pad, box_rp, rmax, m, P, nst, line_any, T1, T2, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -627,13 +635,33 @@ __global__ void line_live_kernel(RateArgs a, uint32_t* __restrict__ live) {
     live[i] = bits;
 }
 
-hipError_t launch_line_live(const RateArgs& a, int nst, uint32_t* live, hipStream_t s) {
+// flag of every (state, line): some chunk live; the live pairs are counted
+// (one atomic per wave)
+__global__ void line_any_kernel(const uint32_t* __restrict__ live, int64_t n_lines, int nch,
+                                uint8_t* __restrict__ line_any, uint32_t* __restrict__ n_live) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    uint32_t any = 0;
+    if (i < n_lines)
+        for (int c = 0; c < nch; ++c) any |= live[i * nch + c];
+    if (i < n_lines) line_any[i] = any ? 1 : 0;
+    const uint64_t bal = __ballot(any != 0);
+    if ((threadIdx.x & 63) == 0 && bal) atomicAdd(n_live, (uint32_t)__popcll(bal));
+}
+
+hipError_t launch_line_live(const RateArgs& a, int nst, uint32_t* live, uint8_t* line_any,
+                            uint32_t* n_live, hipStream_t s) {
     if (nst <= 0) return hipSuccess;
-    if (a.nW > 32) return hipErrorInvalidValue;
+    if (a.nW > 32 || !live || !line_any || !n_live) return hipErrorInvalidValue;
     RateArgs b = a;
     b.n_states = nst;
-    const int64_t n = (int64_t)nst * a.mesh.n1 * a.mesh.n2 * ((a.mesh.n0 + 15) / 16);
+    const int nch = (a.mesh.n0 + 15) / 16;
+    const int64_t n_lines = (int64_t)nst * a.mesh.n1 * a.mesh.n2;
+    const int64_t n = n_lines * nch;
     hipLaunchKernelGGL(line_live_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, b, live);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(line_any_kernel, dim3((unsigned)((n_lines + 255) / 256)), dim3(256), 0, s,
+                       live, n_lines, nch, line_any, n_live);
     return hipGetLastError();
 }
 
