@@ -766,7 +766,8 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
         const double inv_sqrtpi_sigma = 1.0 / (std::sqrt(kPi) * par->sigma);
         const double scale = 2.0 * kPi * inv_sqrtpi_sigma * (q_off ? 1.0 : 1.0 / (double)N);
         if (fold_fused)  // F's padding (rows >= n_rp, columns of no mode) is never written
-            HIPCHK(h, hipMemsetAsync(Fbuf, 0, (size_t)max_states * rp_pad * nc_pad * f_elem, s));
+            HIPCHK(h, launch_zero_fpad(Fbuf, max_states, rp_pad, nc_pad, n_rp, 16 * nm, (int)f_elem,
+                                       s));
         if (all_planes) {
             // T0 of every k0 plane of the call: g(Re,Rp) read once, the planes written once
             const auto& o = rbo.back();

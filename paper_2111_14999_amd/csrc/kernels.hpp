@@ -54,6 +54,10 @@ hipError_t launch_transpose_batch(cd* U, int64_t count, int n, hipStream_t s);
 
 // Stage-1 fold: F[st, r, sa*nW + b] = sum_a conj(U_k[a, n]) G[kb, r, sa, a, b]
 // for each state st = (kb, n); rows r >= n_rp and columns >= NC are zero.
+// Zeroes the padding of F (rows n_rp.., columns ncol..), which the folded stage 1
+// does not write.
+hipError_t launch_zero_fpad(void* F, int64_t nst, int rp_pad, int nc_pad, int n_rp, int ncol,
+                            int esize, hipStream_t s);
 hipError_t launch_fold_uk(const cd* G, int64_t ldg, const cd* U, const int32_t* st_krow,
                           int row0, const int32_t* st_kmesh, const int32_t* st_band, int nst, int n_rp,
                           int nm, int nW, int cw, int rp_pad, int nc_pad, cd* F, hipStream_t s);

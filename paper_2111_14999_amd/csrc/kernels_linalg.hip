@@ -532,25 +532,29 @@ hipError_t launch_compact(const int32_t* flag, int64_t n, int32_t* out, int32_t*
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void extrema_kernel(const double* eps, int64_t nk, int nW,
-                                                      const double* omega, int64_t nq, int nm,
-                                                      double* bmin, double* bmax, double* wmax) {
-    __shared__ double s1[256], s2[256];
+// min and max are exact in any order; the loads of a thread are unrolled so that
+// eight are in flight at once
+__global__ __launch_bounds__(1024) void extrema_kernel(const double* eps, int64_t nk, int nW,
+                                                       const double* omega, int64_t nq, int nm,
+                                                       double* bmin, double* bmax, double* wmax) {
+    __shared__ double s1[1024], s2[1024];
     const int b = blockIdx.x;  // b < nW: band b; b == nW: phonon maximum
     double lo = 1e300, hi = -1e300;
     if (b < nW) {
-        for (int64_t k = threadIdx.x; k < nk; k += 256) {
+#pragma unroll 8
+        for (int64_t k = threadIdx.x; k < nk; k += 1024) {
             const double e = eps[k * nW + b];
             lo = fmin(lo, e);
             hi = fmax(hi, e);
         }
     } else {
-        for (int64_t t = threadIdx.x; t < nq * nm; t += 256) hi = fmax(hi, omega[t]);
+#pragma unroll 8
+        for (int64_t t = threadIdx.x; t < nq * nm; t += 1024) hi = fmax(hi, omega[t]);
     }
     s1[threadIdx.x] = lo;
     s2[threadIdx.x] = hi;
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
+    for (int o = 512; o > 0; o >>= 1) {
         if (threadIdx.x < o) {
             s1[threadIdx.x] = fmin(s1[threadIdx.x], s1[threadIdx.x + o]);
             s2[threadIdx.x] = fmax(s2[threadIdx.x], s2[threadIdx.x + o]);
@@ -570,7 +574,7 @@ __global__ __launch_bounds__(256) void extrema_kernel(const double* eps, int64_t
 hipError_t launch_band_extrema(const double* eps, int64_t nk, int nW, const double* omega,
                                int64_t nq, int nm, double* bmin, double* bmax, double* wmax,
                                hipStream_t s) {
-    hipLaunchKernelGGL(extrema_kernel, dim3(nW + 1), dim3(256), 0, s, eps, nk, nW, omega, nq, nm,
+    hipLaunchKernelGGL(extrema_kernel, dim3(nW + 1), dim3(1024), 0, s, eps, nk, nW, omega, nq, nm,
                        bmin, bmax, wmax);
     return hipGetLastError();
 }

@@ -46,6 +46,41 @@ __global__ void fold_uk_kernel(const cd* __restrict__ G, int64_t ldg, const cd* 
     }
 }
 
+// Zero of the padding of F [nst, rp_pad, nc_pad] (elements of esize bytes): rows
+// n_rp.. and columns ncol.. of every row; the rest is written by the fold.
+__global__ void zero_fpad_kernel(char* F, int64_t nst, int rp_pad, int nc_pad, int n_rp, int ncol,
+                                 int esize) {
+    const int64_t pad_row = (int64_t)nc_pad - ncol;  // padded columns of a data row
+    const int64_t per = (int64_t)n_rp * pad_row + (int64_t)(rp_pad - n_rp) * nc_pad;
+    const int64_t total = nst * per;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t st = t / per, o = t - st * per;
+        int64_t r, c;
+        if (o < (int64_t)n_rp * pad_row) {
+            r = o / pad_row;
+            c = ncol + (o - r * pad_row);
+        } else {
+            const int64_t o2 = o - (int64_t)n_rp * pad_row;
+            r = n_rp + o2 / nc_pad;
+            c = o2 % nc_pad;
+        }
+        char* e = F + ((st * rp_pad + r) * nc_pad + c) * esize;
+        for (int i = 0; i < esize; i += 4) *reinterpret_cast<uint32_t*>(e + i) = 0u;
+    }
+}
+
+hipError_t launch_zero_fpad(void* F, int64_t nst, int rp_pad, int nc_pad, int n_rp, int ncol,
+                            int esize, hipStream_t s) {
+    if (nst <= 0) return hipSuccess;
+    if (n_rp > rp_pad || ncol > nc_pad || esize % 4 != 0) return hipErrorInvalidValue;
+    const int64_t per = (int64_t)n_rp * (nc_pad - ncol) + (int64_t)(rp_pad - n_rp) * nc_pad;
+    if (per == 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_fpad_kernel, dim3(grid1(nst * per, 256)), dim3(256), 0, s,
+                       reinterpret_cast<char*>(F), nst, rp_pad, nc_pad, n_rp, ncol, esize);
+    return hipGetLastError();
+}
+
 hipError_t launch_fold_uk(const cd* G, int64_t ldg, const cd* U, const int32_t* st_krow,
                           int row0, const int32_t* st_kmesh, const int32_t* st_band, int nst, int n_rp,
                           int nm, int nW, int cw, int rp_pad, int nc_pad, cd* F, hipStream_t s) {
@@ -342,22 +377,28 @@ hipError_t launch_stage2_rates(const RateArgs& a, int nst, hipStream_t s) {
     return hipErrorInvalidValue;
 }
 
+// one wave per state: lane j sums tiles j, j + 64, ... in order, then a fixed
+// butterfly over the wave (the same order on every call)
 __global__ void reduce_partials_kernel(const double* partial, int nst, int ntiles,
                                        const int32_t* st_row, const int32_t* st_band, int nW,
                                        double scale, double* gamma) {
-    const int st = blockIdx.x * blockDim.x + threadIdx.x;
+    const int st = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63;
     if (st >= nst) return;
     const double* p = partial + (int64_t)st * ntiles;
     double acc = 0.0;
-    for (int t = 0; t < ntiles; ++t) acc += p[t];
-    gamma[(int64_t)st_row[st] * nW + st_band[st]] = scale * acc;
+#pragma unroll 4
+    for (int t = lane; t < ntiles; t += 64) acc += p[t];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) gamma[(int64_t)st_row[st] * nW + st_band[st]] = scale * acc;
 }
 
 hipError_t launch_reduce_partials(const double* partial, int nst, int ntiles,
                                   const int32_t* st_row, const int32_t* st_band, int nW,
                                   double scale, double* gamma, hipStream_t s) {
     if (nst <= 0) return hipSuccess;
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3((nst + 127) / 128), dim3(128), 0, s, partial,
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((nst + 3) / 4), dim3(256), 0, s, partial,
                        nst, ntiles, st_row, st_band, nW, scale, gamma);
     return hipGetLastError();
 }
