@@ -405,7 +405,7 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
         const int BQ = 16 * tq;
         // states per factorised sub-batch: T1 + T2 of a sub-batch stay under 4 GB
         const size_t t12_state = ((size_t)Wbox * Wbox * mesh.n2 + (size_t)Wbox * NL) * nc_pad * g_elem;
-        const int nch_line = (mesh.n0 + 15) / 16;
+        const int n0_line = mesh.n0;
         const int nsb = factored ? (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)BK * nW,
                                                       (int64_t)(4e9 / (double)t12_state)))
                                  : 0;
@@ -509,7 +509,7 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                                    (size_t)max_states * rp_pad * nc_pad * f_elem +
                                    (size_t)max_states * n_qtiles * sizeof(double) +
                                    (factored ? (size_t)nsb * t12_state + 512 : 0) +
-                                   (factored ? (size_t)nsb * NL * (nch_line * sizeof(uint32_t) + 1) +
+                                   (factored ? (size_t)nsb * NL * (n0_line + 1) * sizeof(uint32_t) +
                                                    (size_t)rows_cap * nW * sizeof(uint32_t) + 512
                                              : 0) +
                                    (re_fact ? (size_t)rows_cap * 168 * sizeof(int32_t) + 1024
@@ -747,8 +747,8 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
         char* T1buf = factored ? ar.take<char>((size_t)nsb * Wbox * Wbox * mesh.n2 * nc_pad * g_elem)
                                : nullptr;
         char* T2buf = factored ? ar.take<char>((size_t)nsb * Wbox * NL * nc_pad * g_elem) : nullptr;
-        uint32_t* livebuf = factored ? ar.take<uint32_t>((size_t)nsb * NL * nch_line) : nullptr;
-        uint8_t* lineany = factored ? ar.take<uint8_t>((size_t)nsb * NL) : nullptr;
+        uint32_t* livebuf = factored ? ar.take<uint32_t>((size_t)nsb * NL * n0_line) : nullptr;
+        uint32_t* lineany = factored ? ar.take<uint32_t>((size_t)nsb * NL) : nullptr;
         // live (state, line) count of every factorised sub-batch (traffic accounting)
         int64_t n_sub = 0;
         if (factored)
@@ -913,6 +913,7 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                     rb.partial = partial + (int64_t)sb * n_qtiles;
                     if (ra.terms) rb.terms = ra.terms + (int64_t)sb * N * nm;
                     rb.live = livebuf;
+                    rb.line_bands = lineany;
                     // live bands of every (state, line, chunk) first: T2 is formed for live lines only
                     HIPCHK(h, launch_line_live(rb, nn, livebuf, lineany, nl, s));
                     Timer ta(h, s, "axis_transforms");

@@ -96,7 +96,8 @@ struct RateArgs {
     int W;                     // 2 rmax + 1
     int n_states;              // states of one launch (set by the launcher)
     const double* wmax;        // device scalar: largest phonon energy on the mesh
-    const uint32_t* live;      // [nst, N1*N2, ceil(N0/16)] live final bands per chunk (line_live)
+    const uint32_t* live;        // [nst, N0, N1*N2] live final bands of every point (line_live)
+    const uint32_t* line_bands;  // [nst, N1*N2] union of a line's live bands, 0: none
 };
 
 // Fused stage 2 (sum over Rp on MFMA) + rotations + rate terms.
@@ -105,13 +106,13 @@ hipError_t launch_stage2_rates(const RateArgs& a, int nst, hipStream_t s);
 // Per-axis phase tables P[d][n, r] = e^{i2pi (n (r - rmax) mod N_d)/N_d}, [N0+N1+N2, W].
 hipError_t launch_axis_phases(Mesh m, int rmax, cd* P, hipStream_t s);
 // T1 (axis 2) and T2 (axis 1) of the factorised full-mesh sum over Rp.
-// line_any (nullable): [nst, N1*N2] flags; T2 of a line whose flag is 0 is not formed.
+// line_any (nullable): [nst, N1*N2]; T2 of a line whose entry is 0 is not formed.
 hipError_t launch_axis_transforms(const cd* F, int rp_pad, int nc_pad, const int32_t* box_rp,
-                                  int rmax, Mesh m, const cd* P, int nst, const uint8_t* line_any,
+                                  int rmax, Mesh m, const cd* P, int nst, const uint32_t* line_any,
                                   cd* T1, cd* T2, hipStream_t s);
 hipError_t launch_axis_transforms_f32(const cf* F, int rp_pad, int nc_pad, const int32_t* box_rp,
                                       int rmax, Mesh m, const cd* P, int nst,
-                                      const uint8_t* line_any, cf* T1, cf* T2, hipStream_t s);
+                                      const uint32_t* line_any, cf* T1, cf* T2, hipStream_t s);
 // Stage 1 factorised over the axes of the Re box for one batch of kept k.
 // Device lists: d_k0 [d0] distinct k0; pair_k1 [d01] and pair_off [d0+1] the
 // distinct (k0, k1) pairs grouped by k0; kp_off [d01+1], k_row, k_k2 [nb] the
@@ -156,10 +157,10 @@ size_t re_axes_lds(int rmax, bool f32);
 
 // Axis 0 on MFMA + rotations + rate terms, one work-group per (state, q1, q2) line.
 // Columns sa*16 + b (nW <= 16), nc_pad = 64 TN with 4 TN >= nModes.
-// Live-band masks of every (state, line, 16-point chunk) for the line kernel,
-// a flag per (state, line) (some chunk live) and, added to *n_live, the number
-// of live (state, line) pairs.
-hipError_t launch_line_live(const RateArgs& a, int nst, uint32_t* live, uint8_t* line_any,
+// Live final bands of every (state, point) for the line kernel, their union
+// per (state, line) and, added to *n_live, the number of (state, line) pairs
+// with a live band.
+hipError_t launch_line_live(const RateArgs& a, int nst, uint32_t* live, uint32_t* line_bands,
                             uint32_t* n_live, hipStream_t s);
 hipError_t launch_line_rates(const RateArgs& a, int nst, hipStream_t s);
 hipError_t launch_line_rates_f32(const RateArgs& a, int nst, hipStream_t s);

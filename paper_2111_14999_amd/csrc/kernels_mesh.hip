@@ -106,7 +106,7 @@ template <int WT, class C>
 __global__ __launch_bounds__(256) void axis_mid_kernel(const C* __restrict__ in, int64_t n_outer,
                                                        int Wr, int64_t inner, int N,
                                                        const cd* __restrict__ P,
-                                                       const uint8_t* __restrict__ line_any,
+                                                       const uint32_t* __restrict__ line_any,
                                                        int nc, C* __restrict__ out) {
     constexpr int NV = WT > 0 ? WT : kMaxW;
     const int W = WT > 0 ? WT : Wr;
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(256) void axis_mid_kernel(const C* __restrict__ in,
             if (r < W) v[r] = src[(int64_t)r * inner];
         C* dst = out + o * N * inner + i;
         const int64_t n2 = inner / nc, q2 = i / nc;
-        const uint8_t* fl = line_any ? line_any + (o / W) * N * n2 + q2 : nullptr;
+        const uint32_t* fl = line_any ? line_any + (o / W) * N * n2 + q2 : nullptr;
         for (int n = 0; n < N; ++n) {
             if (fl && !fl[n * n2]) continue;
             const cd* Pn = P + n * W;
@@ -137,7 +137,7 @@ __global__ __launch_bounds__(256) void axis_mid_kernel(const C* __restrict__ in,
 
 template <int WT, class C>
 static hipError_t go_axes(const C* F, int rp_pad, int nc_pad, const int32_t* box_rp, int W,
-                          Mesh m, const cd* P1, const cd* P2, int nst, const uint8_t* line_any,
+                          Mesh m, const cd* P1, const cd* P2, int nst, const uint32_t* line_any,
                           C* T1, C* T2, hipStream_t s) {
     hipLaunchKernelGGL((axis2_kernel<WT, C>), dim3(gridm((int64_t)nst * W * W * nc_pad, 256)),
                        dim3(256), 0, s, F, rp_pad, nc_pad, box_rp, W, m.n2, P2, nst, T1);
@@ -152,7 +152,7 @@ static hipError_t go_axes(const C* F, int rp_pad, int nc_pad, const int32_t* box
 
 template <class C>
 static hipError_t axis_transforms(const C* F, int rp_pad, int nc_pad, const int32_t* box_rp,
-                                  int rmax, Mesh m, const cd* P, int nst, const uint8_t* line_any,
+                                  int rmax, Mesh m, const cd* P, int nst, const uint32_t* line_any,
                                   C* T1, C* T2, hipStream_t s) {
     const int W = 2 * rmax + 1;
     if (W > kMaxW) return hipErrorInvalidValue;
@@ -170,13 +170,13 @@ static hipError_t axis_transforms(const C* F, int rp_pad, int nc_pad, const int3
 }
 
 hipError_t launch_axis_transforms(const cd* F, int rp_pad, int nc_pad, const int32_t* box_rp,
-                                  int rmax, Mesh m, const cd* P, int nst, const uint8_t* line_any,
+                                  int rmax, Mesh m, const cd* P, int nst, const uint32_t* line_any,
                                   cd* T1, cd* T2, hipStream_t s) {
     return axis_transforms<cd>(F, rp_pad, nc_pad, box_rp, rmax, m, P, nst, line_any, T1, T2, s);
 }
 hipError_t launch_axis_transforms_f32(const cf* F, int rp_pad, int nc_pad, const int32_t* box_rp,
                                       int rmax, Mesh m, const cd* P, int nst,
-                                      const uint8_t* line_any, cf* T1, cf* T2, hipStream_t s) {
+                                      const uint32_t* line_any, cf* T1, cf* T2, hipStream_t s) {
     return axis_transforms<cf>(F, rp_pad, nc_pad, box_rp, rmax, m, P, nst, line_any, T1, T2, s);
 }
 
@@ -541,9 +541,9 @@ hipError_t launch_re_pairs_f32(const cf* T0, int64_t NC, int rmax, Mesh m, const
 
 // ---------------------------------------------------------------------------
 // Last axis on MFMA + rotations + rate terms.  Work-group = one state x one
-// (q1, q2) line; the N0 points of the line are taken 16 at a time.  The MFMA
-// computes the transposed tile X^T[b, q0] = sum_R0 T2[R0, col b] P0[q0, R0]:
-// lane l feeds A[l%16][l/16] = T2[R0, line, col] and B[l/16][l%16] = P0[q0, R0].
+// (q1, q2) line; its live points are taken 16 at a time.  The MFMA computes
+// the transposed tile X^T[b, q0] = sum_R0 T2[R0, col b] P0[q0, R0]: lane l
+// feeds A[l%16][l/16] = T2[R0, line, col] and B[l/16][l%16] = P0[q0, R0].
 //
 // Columns are laid out c = sa*16 + b (b < nW <= 16), so every 16-column tile
 // holds one mode index sa.  The tile's rows are ordered so that lane (g, i)
@@ -557,8 +557,6 @@ hipError_t launch_re_pairs_f32(const cf* T0, int64_t NC, int rmax, Mesh m, const
 // one final band at a time) goes through LDS to the threads that apply
 // E_q = z l and form the rate terms.
 // ---------------------------------------------------------------------------
-constexpr int kMaxChunks = 64;  // 16-point chunks of a line: N0 <= 1024
-
 // permlane32_swap exchanges lanes 32-63 of a with lanes 0-31 of b;
 // permlane16_swap exchanges the odd 16-lane rows of a with the even rows of b.
 template <int ROWS>
@@ -603,79 +601,65 @@ __device__ inline R rows4_reduce_scatter(R u0, R u1, R u2, R u3) {
     return s + t;
 }
 
-// Live final bands of every 16-point chunk of every line.  Bit m of
-// live[(st * NL + line) * nch + c] is set when some point q0 of chunk c has
-// |eps_n - eps_{m,k+q}| <= 27.5 sigma + max omega; otherwise both Gaussians of
-// every term of band m in that chunk are beyond 27.5 sigma, i.e. exactly 0.
-// One thread per (state, line, chunk), every entry written.
+// Live final bands of every point.  Bit m of live[(st * N0 + q0) * NL + line]
+// is set when |eps_n - eps_{m,k+q}| <= 27.5 sigma + max omega at that point;
+// otherwise both Gaussians of every term of band m there are beyond 27.5 sigma,
+// i.e. exactly 0.  One thread per (state, point), the line index fastest.
 __global__ void line_live_kernel(RateArgs a, uint32_t* __restrict__ live) {
     const Mesh mesh = a.mesh;
-    const int N0 = mesh.n0, NL = mesh.n1 * mesh.n2, nch = (N0 + 15) / 16, nW = a.nW;
+    const int N0 = mesh.n0, NL = mesh.n1 * mesh.n2, nW = a.nW;
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= (int64_t)a.n_states * NL * nch) return;
-    const int c = (int)(i % nch);
-    const int64_t sl = i / nch;
-    const int line = (int)(sl % NL), st = (int)(sl / NL);
+    if (i >= (int64_t)a.n_states * N0 * NL) return;
+    const int line = (int)(i % NL);
+    const int64_t sq = i / NL;
+    const int q0 = (int)(sq % N0), st = (int)(sq / N0);
     const int q1 = line / mesh.n2, q2 = line - q1 * mesh.n2;
     const int kmesh = a.st_kmesh[st];
     const int mlo = a.st_mlo[st], mhi = a.st_mhi[st];
     int k0i, k1i, k2i;
     mesh_triple(kmesh, mesh, k0i, k1i, k2i);
-    const int kq12 = ((k1i + q1) % mesh.n1) * mesh.n2 + (k2i + q2) % mesh.n2;
+    const int64_t kq = (int64_t)((k0i + q0) % N0) * NL + ((k1i + q1) % mesh.n1) * mesh.n2 +
+                       (k2i + q2) % mesh.n2;
     const double eps_n = a.eps[(int64_t)kmesh * nW + a.st_band[st]];
     const double lim = 27.5 * a.sigma + *a.wmax;
     uint32_t bits = 0;
-    for (int p = 0; p < 16; ++p) {
-        const int q0 = c * 16 + p;
-        if (q0 >= N0) break;
-        const int64_t kq = (int64_t)((k0i + q0) % N0) * NL + kq12;
-        for (int m = mlo; m <= mhi; ++m)
-            bits |= (uint32_t)(fabs(eps_n - a.eps[kq * nW + m]) <= lim) << m;
-    }
+    for (int m = mlo; m <= mhi; ++m)
+        bits |= (uint32_t)(fabs(eps_n - a.eps[kq * nW + m]) <= lim) << m;
     live[i] = bits;
 }
 
-// flag of every (state, line): some chunk live; the live pairs are counted
-// (one atomic per wave)
-__global__ void line_any_kernel(const uint32_t* __restrict__ live, int64_t n_lines, int nch,
-                                uint8_t* __restrict__ line_any, uint32_t* __restrict__ n_live) {
+// union of the live bands over the points of every (state, line); the lines
+// with a live band are counted (one atomic per wave)
+__global__ void line_any_kernel(const uint32_t* __restrict__ live, int nst, int N0, int NL,
+                                uint32_t* __restrict__ line_bands, uint32_t* __restrict__ n_live) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    uint32_t any = 0;
-    if (i < n_lines)
-        for (int c = 0; c < nch; ++c) any |= live[i * nch + c];
-    if (i < n_lines) line_any[i] = any ? 1 : 0;
-    const uint64_t bal = __ballot(any != 0);
+    const int64_t n_lines = (int64_t)nst * NL;
+    uint32_t u = 0;
+    if (i < n_lines) {
+        const int64_t st = i / NL, line = i - st * NL;
+        for (int q0 = 0; q0 < N0; ++q0) u |= live[(st * N0 + q0) * NL + line];
+        line_bands[i] = u;
+    }
+    const uint64_t bal = __ballot(u != 0);
     if ((threadIdx.x & 63) == 0 && bal) atomicAdd(n_live, (uint32_t)__popcll(bal));
 }
 
-hipError_t launch_line_live(const RateArgs& a, int nst, uint32_t* live, uint8_t* line_any,
+hipError_t launch_line_live(const RateArgs& a, int nst, uint32_t* live, uint32_t* line_bands,
                             uint32_t* n_live, hipStream_t s) {
     if (nst <= 0) return hipSuccess;
-    if (a.nW > 32 || !live || !line_any || !n_live) return hipErrorInvalidValue;
+    if (a.nW > 32 || !live || !line_bands || !n_live) return hipErrorInvalidValue;
     RateArgs b = a;
     b.n_states = nst;
-    const int nch = (a.mesh.n0 + 15) / 16;
-    const int64_t n_lines = (int64_t)nst * a.mesh.n1 * a.mesh.n2;
-    const int64_t n = n_lines * nch;
+    const int NL = a.mesh.n1 * a.mesh.n2;
+    const int64_t n = (int64_t)nst * a.mesh.n0 * NL;
     hipLaunchKernelGGL(line_live_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, b, live);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    const int64_t n_lines = (int64_t)nst * NL;
     hipLaunchKernelGGL(line_any_kernel, dim3((unsigned)((n_lines + 255) / 256)), dim3(256), 0, s,
-                       live, n_lines, nch, line_any, n_live);
+                       live, nst, a.mesh.n0, NL, line_bands, n_live);
     return hipGetLastError();
 }
-
-// C = cd: FP64 on v_mfma_f64_16x16x4f64; C = cf: the FP32 form on
-// v_mfma_f32_16x16x4f32, with the rotations in FP32 and the Gaussian terms and
-// sums in FP64.
-//
-// A work-group walks the live (chunk, band) units of its line in order.  The
-// eigenvector, band and phonon values a unit needs are loaded before its MFMA
-// work (for the first unit together with the phase table), so that only the
-// E_q loads of the terms that survive the Gaussian test wait on memory after
-// the rotation.  (On the workloads measured, a live chunk has one live final
-// band.)
-constexpr int kTP = 2;  // column tiles per MFMA pass
 
 __device__ inline d4 mfma16(double x, double y, d4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, c, 0, 0, 0);
@@ -683,6 +667,20 @@ __device__ inline d4 mfma16(double x, double y, d4 c) {
 __device__ inline f4 mfma16(float x, float y, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(x, y, c, 0, 0, 0);
 }
+
+// C = cd: FP64 on v_mfma_f64_16x16x4f64; C = cf: the FP32 form on
+// v_mfma_f32_16x16x4f32, with the rotations in FP32 and the Gaussian terms and
+// sums in FP64.
+//
+// A work-group takes the live final bands of its line in order; for each band
+// it lists the band's live points (a wave ballot over the point masks) and
+// works through the list 16 points at a time, so that every MFMA row and
+// every term item belongs to a live point where possible.  The phase rows, the
+// eigenvectors at k+q and the band and phonon values of a unit are gathered
+// through the list; the last group of a band is padded with an all-zero
+// phase row.  Only the E_q loads of the terms that survive the Gaussian test
+// wait on memory after the rotation.
+constexpr int kTP = 2;  // column tiles per MFMA pass
 
 template <int TN, class C>
 __global__ __launch_bounds__(256, 4) void line_rates_kernel(RateArgs a) {
@@ -695,13 +693,13 @@ __global__ __launch_bounds__(256, 4) void line_rates_kernel(RateArgs a) {
     const int nW = a.nW, nm = a.nm;
     const Mesh mesh = a.mesh;
     const int N0 = mesh.n0;
-    const int N0p = (N0 + 15) & ~15;
-    const int nch = N0p / 16;
     const int ldf = a.nc_pad;
-    C* sP = reinterpret_cast<C*>(smem_raw);       // [N0p][Wp]
-    C* sY = sP + N0p * Wp;                        // [16][nm]: Y of one (chunk, band) unit
+    C* sP = reinterpret_cast<C*>(smem_raw);                    // [N0 + 1][Wp], row N0 zero
+    C* sY = sP + (N0 + 1) * Wp;                                // [16][nm]
+    uint32_t* sPm = reinterpret_cast<uint32_t*>(sY + 16 * nm);  // [N0] live bands per point
+    int* sList = reinterpret_cast<int*>(sPm + N0);             // [N0] live points of a band
     __shared__ double sRed[4];
-    __shared__ uint32_t sLive[kMaxChunks];
+    __shared__ int sCount;
 
     // XCD-aware order: work-groups are dealt to the 8 XCDs round-robin, so
     // with id = 8 j + x every state of a line lands on XCD x, one after
@@ -714,20 +712,16 @@ __global__ __launch_bounds__(256, 4) void line_rates_kernel(RateArgs a) {
     const int line = (int)((j / nst) * 8 + xcd);
     const int st = (int)(j % nst);
     if (line >= NL) return;
-    const int q1 = line / mesh.n2, q2 = line - q1 * mesh.n2;
+    uint32_t bands = a.line_bands[(int64_t)st * NL + line];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int li = lane & 15, lg = lane >> 4;
-
-    if (tid < nch) sLive[tid] = a.live[((int64_t)st * NL + line) * nch + tid];
-    const int kmesh = a.st_kmesh[st];
-    const int nband = a.st_band[st];
-    __syncthreads();
-    uint32_t any = 0;
-    for (int c = 0; c < nch; ++c) any |= sLive[c];
-    if (!any) {
+    if (!bands) {
         if (tid == 0) a.partial[(int64_t)st * a.n_qtiles + line] = 0.0;
         return;
     }
+    const int q1 = line / mesh.n2, q2 = line - q1 * mesh.n2;
+    const int li = lane & 15, lg = lane >> 4;
+    const int kmesh = a.st_kmesh[st];
+    const int nband = a.st_band[st];
     int k0i, k1i, k2i;
     mesh_triple(kmesh, mesh, k0i, k1i, k2i);
     const int kq12 = ((k1i + q1) % mesh.n1) * mesh.n2 + (k2i + q2) % mesh.n2;
@@ -743,30 +737,34 @@ __global__ __launch_bounds__(256, 4) void line_rates_kernel(RateArgs a) {
                    (int64_t)line * ldf + wave * TN * 16 + bcol;
     const int64_t Tk = (int64_t)NL * ldf;  // stride of R0 in T2
 
-    for (int i = tid; i < N0p * Wp; i += 256) {
+    for (int q0 = tid; q0 < N0; q0 += 256) sPm[q0] = a.live[((int64_t)st * N0 + q0) * NL + line];
+    for (int i = tid; i < (N0 + 1) * Wp; i += 256) {
         const int q0 = i / Wp, r = i - q0 * Wp;
         sP[i] = (q0 < N0 && r < W) ? to_c<C>(a.P0[q0 * W + r]) : C{0, 0};
     }
-    // Values one (chunk qc, band m) unit needs: per lane, U_{k+q}[b = 4 lg + v, m]
-    // at the lane's point q0 = qc + li; per thread, for its term item
-    // (point c = tid / nm, mode nu = tid % nm), eps and f of band m at k+q and
-    // omega and n of (q, nu).  Items beyond the first of a thread (nm > 16)
-    // read theirs in place.
+
+    // Values one unit (band m, points list[g .. g+15]) needs: per lane,
+    // U_{k+q}[b = 4 lg + v, m] at the lane's point; per thread, for its term
+    // item (point slot c = tid / nm, mode nu = tid % nm), eps and f of band m
+    // at k+q and omega and n of (q, nu).  Items beyond the first of a thread
+    // (nm > 16) read theirs in place.
     struct Unit {
         C u[4];
         double em, fm, om, nbq;
     };
     const bool has_item = tid < 16 * nm;
     const int ic = tid / nm, inu = tid - ic * nm;
-    auto load_unit = [&](int qc, int m, Unit& d) {
-        const int64_t kql = qc + li < N0 ? (int64_t)((k0i + qc + li) % N0) * NL + kq12 : -1;
-        const cd* Ur = a.U + ((kql < 0 ? 0 : kql) * nW + m) * nW + 4 * lg;
+    auto kq_of = [&](int q0) { return (int64_t)((k0i + q0) % N0) * NL + kq12; };
+    auto load_unit = [&](int pl, int pc, int m, Unit& d) {
+        // pl: this lane's point (-1: padding); pc: this thread's item point
+        const int64_t kql = pl >= 0 ? kq_of(pl) : 0;
+        const cd* Ur = a.U + (kql * nW + m) * nW + 4 * lg;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) d.u[v] = (kql >= 0 && 4 * lg + v < nW) ? to_c<C>(Ur[v]) : C{0, 0};
+        for (int v = 0; v < 4; ++v) d.u[v] = (pl >= 0 && 4 * lg + v < nW) ? to_c<C>(Ur[v]) : C{0, 0};
         d.em = d.fm = d.om = d.nbq = 0.0;
-        if (has_item && qc + ic < N0) {
-            const int64_t q = (int64_t)(qc + ic) * NL + q12;
-            const int64_t kq = (int64_t)((k0i + qc + ic) % N0) * NL + kq12;
+        if (has_item && pc >= 0) {
+            const int64_t q = (int64_t)pc * NL + q12;
+            const int64_t kq = kq_of(pc);
             d.em = a.eps[kq * nW + m];
             d.fm = a.focc[kq * nW + m];
             d.om = a.omega[q * nm + inu];
@@ -775,12 +773,12 @@ __global__ __launch_bounds__(256, 4) void line_rates_kernel(RateArgs a) {
     };
     // rate term of one item; E_q is read only for terms that survive the test
     double gacc = 0.0;
-    auto item_term = [&](int qc, int c, int nu, double em, double fm, double w, double nbq) {
+    auto item_term = [&](int q0, int c, int nu, double em, double fm, double w, double nbq) {
         const double x = eps_n - em;
         const double y1 = x - w, y2 = x + w;
         // both Gaussians underflow to exactly 0: the term is 0
         if (fabs(y1) > cut && fabs(y2) > cut) return;
-        const int64_t q = (int64_t)(qc + c) * NL + q12;
+        const int64_t q = (int64_t)q0 * NL + q12;
         const C* Yr = sY + c * nm;
         const cd* Eq = a.E + (q * nm + nu) * nm;
         C z = {0, 0};
@@ -792,93 +790,98 @@ __global__ __launch_bounds__(256, 4) void line_rates_kernel(RateArgs a) {
             atomicAdd(&a.terms[((int64_t)st * a.nq_mesh + q) * nm + nu], a.terms_scale * term);
     };
 
-    // first live unit
-    int qc = 0;
-    while (!sLive[qc >> 4]) qc += 16;
-    uint32_t bands = sLive[qc >> 4];
-    int m = __builtin_ctz(bands);
-    Unit d;
-    load_unit(qc, m, d);
-    __syncthreads();  // sP
-
-    while (true) {
-        // X^T tiles of chunk qc and Y, two column tiles at a time (the
-        // accumulators of a pass are the kernel's largest register block; a
-        // second live band of the same chunk recomputes them)
-#pragma unroll
-        for (int t0 = 0; t0 < TN; t0 += kTP) {
-            constexpr int P = TN < kTP ? TN : kTP;
-            V4 cr[P], ci[P];
-#pragma unroll
-            for (int t = 0; t < P; ++t) {
-                cr[t] = V4{0, 0, 0, 0};
-                ci[t] = V4{0, 0, 0, 0};
+    __syncthreads();  // sPm, sP
+    while (bands) {
+        const int m = __builtin_ctz(bands);
+        bands &= bands - 1;
+        // live points of band m, ascending
+        if (wave == 0) {
+            int base = 0;
+            for (int w0 = 0; w0 < N0; w0 += 64) {
+                const int p = w0 + lane;
+                const bool bit = p < N0 && ((sPm[p] >> m) & 1u);
+                const uint64_t bal = __ballot(bit);
+                if (bit) sList[base + __popcll(bal & ((1ull << lane) - 1ull))] = p;
+                base += __popcll(bal);
             }
-            for (int k0 = 0; k0 < Wp; k0 += 4) {
-                const int k = k0 + lg;
-                C bc[P];
-#pragma unroll
-                for (int t = 0; t < P; ++t)
-                    bc[t] = (k < W && t0 + t < TN) ? Tst[k * Tk + (t0 + t) * 16] : C{0, 0};
-                const C ph = sP[(qc + li) * Wp + k];
-#pragma unroll
-                for (int t = 0; t < P; ++t) {
-                    cr[t] = mfma16(bc[t].x, ph.x, cr[t]);
-                    ci[t] = mfma16(bc[t].y, ph.x, ci[t]);
-                }
-#pragma unroll
-                for (int t = 0; t < P; ++t) {
-                    cr[t] = mfma16(bc[t].y, -ph.y, cr[t]);
-                    ci[t] = mfma16(bc[t].x, ph.y, ci[t]);
-                }
-            }
-            // Y[q0 = qc + li, sa] = sum_b X[q0, sa, b] U_{k+q}[b, m]: products over
-            // the lane's four b, then the sum over the four rows; rows 0/1 receive
-            // Re Y of tiles t/t+1, rows 2/3 Im Y of tiles t/t+1.
-            R pr[P], pi[P];
-#pragma unroll
-            for (int t = 0; t < P; ++t) {
-                R xr = 0, xi = 0;
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    xr += cr[t][v] * d.u[v].x - ci[t][v] * d.u[v].y;
-                    xi += cr[t][v] * d.u[v].y + ci[t][v] * d.u[v].x;
-                }
-                pr[t] = xr;
-                pi[t] = xi;
-            }
-#pragma unroll
-            for (int t = 0; t < P; t += 2) {
-                const R y = rows4_reduce_scatter(pr[t], t + 1 < P ? pr[t + 1] : R(0), pi[t],
-                                                 t + 1 < P ? pi[t + 1] : R(0));
-                const int tt = t0 + t + (lg & 1);
-                const int sa = wave * TN + tt;
-                if (t + (lg & 1) < P && tt < TN && sa < nm)
-                    reinterpret_cast<R*>(sY + li * nm + sa)[lg >> 1] = y;
-            }
+            if (lane == 0) sCount = base;
         }
         __syncthreads();
-        // Z[c, nu] = sum_sa E_q[sa, nu] Y[c, sa] and the rate terms
-        if (has_item && qc + ic < N0) item_term(qc, ic, inu, d.em, d.fm, d.om, d.nbq);
-        for (int it = tid + 256; it < 16 * nm; it += 256) {
-            const int c = it / nm, nu = it - c * nm;
-            if (qc + c >= N0) continue;
-            const int64_t q = (int64_t)(qc + c) * NL + q12;
-            const int64_t kq = (int64_t)((k0i + qc + c) % N0) * NL + kq12;
-            item_term(qc, c, nu, a.eps[kq * nW + m], a.focc[kq * nW + m], a.omega[q * nm + nu],
-                      a.nb[q * nm + nu]);
+        const int cnt = sCount;
+        if (cnt == 0) __syncthreads();  // (a band of the union has a point; kept for safety)
+        for (int g = 0; g < cnt; g += 16) {
+            const int pl = g + li < cnt ? sList[g + li] : -1;
+            const int pc = has_item && g + ic < cnt ? sList[g + ic] : -1;
+            Unit d;
+            load_unit(pl, pc, m, d);
+            const int prow = (pl >= 0 ? pl : N0) * Wp;
+            // X^T tiles of the unit's points and Y, two column tiles at a time
+#pragma unroll
+            for (int t0 = 0; t0 < TN; t0 += kTP) {
+                constexpr int P = TN < kTP ? TN : kTP;
+                V4 cr[P], ci[P];
+#pragma unroll
+                for (int t = 0; t < P; ++t) {
+                    cr[t] = V4{0, 0, 0, 0};
+                    ci[t] = V4{0, 0, 0, 0};
+                }
+                for (int k0 = 0; k0 < Wp; k0 += 4) {
+                    const int k = k0 + lg;
+                    C bc[P];
+#pragma unroll
+                    for (int t = 0; t < P; ++t)
+                        bc[t] = (k < W && t0 + t < TN) ? Tst[k * Tk + (t0 + t) * 16] : C{0, 0};
+                    const C ph = sP[prow + k];
+#pragma unroll
+                    for (int t = 0; t < P; ++t) {
+                        cr[t] = mfma16(bc[t].x, ph.x, cr[t]);
+                        ci[t] = mfma16(bc[t].y, ph.x, ci[t]);
+                    }
+#pragma unroll
+                    for (int t = 0; t < P; ++t) {
+                        cr[t] = mfma16(bc[t].y, -ph.y, cr[t]);
+                        ci[t] = mfma16(bc[t].x, ph.y, ci[t]);
+                    }
+                }
+                // Y[slot li, sa] = sum_b X[slot li, sa, b] U_{k+q}[b, m]: products over
+                // the lane's four b, then the sum over the four rows; rows 0/1 receive
+                // Re Y of tiles t/t+1, rows 2/3 Im Y of tiles t/t+1.
+                R pr[P], pi[P];
+#pragma unroll
+                for (int t = 0; t < P; ++t) {
+                    R xr = 0, xi = 0;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        xr += cr[t][v] * d.u[v].x - ci[t][v] * d.u[v].y;
+                        xi += cr[t][v] * d.u[v].y + ci[t][v] * d.u[v].x;
+                    }
+                    pr[t] = xr;
+                    pi[t] = xi;
+                }
+#pragma unroll
+                for (int t = 0; t < P; t += 2) {
+                    const R y = rows4_reduce_scatter(pr[t], t + 1 < P ? pr[t + 1] : R(0), pi[t],
+                                                     t + 1 < P ? pi[t + 1] : R(0));
+                    const int tt = t0 + t + (lg & 1);
+                    const int sa = wave * TN + tt;
+                    if (t + (lg & 1) < P && tt < TN && sa < nm)
+                        reinterpret_cast<R*>(sY + li * nm + sa)[lg >> 1] = y;
+                }
+            }
+            __syncthreads();
+            // Z[c, nu] = sum_sa E_q[sa, nu] Y[c, sa] and the rate terms
+            if (pc >= 0) item_term(pc, ic, inu, d.em, d.fm, d.om, d.nbq);
+            for (int it = tid + 256; it < 16 * nm; it += 256) {
+                const int c = it / nm, nu = it - c * nm;
+                if (g + c >= cnt) continue;
+                const int q0 = sList[g + c];
+                const int64_t q = (int64_t)q0 * NL + q12;
+                const int64_t kq = kq_of(q0);
+                item_term(q0, c, nu, a.eps[kq * nW + m], a.focc[kq * nW + m], a.omega[q * nm + nu],
+                          a.nb[q * nm + nu]);
+            }
+            __syncthreads();  // sY (and the list, after a band's last unit) are rewritten
         }
-        // next unit: the next live band of this chunk, else the next live chunk
-        bands &= bands - 1;
-        while (!bands) {
-            qc += 16;
-            if (qc >= N0) break;
-            bands = sLive[qc >> 4];
-        }
-        if (qc >= N0) break;
-        m = __builtin_ctz(bands);
-        load_unit(qc, m, d);
-        __syncthreads();  // sY is rewritten by the next unit
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) gacc += __shfl_xor(gacc, o, 64);
@@ -888,8 +891,9 @@ __global__ __launch_bounds__(256, 4) void line_rates_kernel(RateArgs a) {
 }
 
 size_t line_rates_lds(int W, int N0, int nm, bool f32) {
-    const int Wp = (W + 3) & ~3, N0p = (N0 + 15) & ~15;
-    return ((size_t)N0p * Wp + 16 * (size_t)nm) * (f32 ? sizeof(cf) : sizeof(cd));
+    const int Wp = (W + 3) & ~3;
+    return ((size_t)(N0 + 1) * Wp + 16 * (size_t)nm) * (f32 ? sizeof(cf) : sizeof(cd)) +
+           2 * (size_t)N0 * sizeof(uint32_t);
 }
 
 // Columns of the factorised form: one 16-wide tile per mode index, 4 waves x TN tiles.
@@ -920,7 +924,8 @@ static hipError_t go_line(const RateArgs& a, int nst, hipStream_t s) {
         b.st_mhi += s0;
         b.partial = a.partial + (int64_t)s0 * a.n_qtiles;
         if (a.terms) b.terms = a.terms + (int64_t)s0 * a.nq_mesh * a.nm;
-        b.live = a.live + (int64_t)s0 * NL * ((a.mesh.n0 + 15) / 16);
+        b.live = a.live + (int64_t)s0 * a.mesh.n0 * NL;
+        b.line_bands = a.line_bands + (int64_t)s0 * NL;
         b.n_states = ns;
         hipLaunchKernelGGL((line_rates_kernel<TN, C>), dim3((unsigned)(groups * 8 * ns)), dim3(256),
                            shm, s, b);
@@ -932,7 +937,7 @@ template <class C>
 static hipError_t line_rates(const RateArgs& a, int nst, hipStream_t s) {
     if (nst <= 0) return hipSuccess;
     if (a.n_qtiles != a.mesh.n1 * a.mesh.n2 || a.n_qtiles > 65535 || a.W > kMaxW ||
-        a.mesh.n0 > 16 * kMaxChunks || line_rates_ncpad(a.nm, a.nW) != a.nc_pad || !a.live)
+        line_rates_ncpad(a.nm, a.nW) != a.nc_pad || !a.live || !a.line_bands)
         return hipErrorInvalidValue;
     switch (a.nc_pad / 64) {
         case 1: return go_line<1, C>(a, nst, s);
