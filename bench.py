@@ -162,10 +162,10 @@ def main():
     #                   batch's T0 planes read (with g read and T0 written first when
     #                   the planes are per batch) and G written once
     #   stage1_planes   T0 of every k0 plane in one pass: g read once, T0 written once
-    #   line_rates      last axis of the factorised sum: 8 N_q W nModes nW per state
+    #   line_rates      last axis of the factorised sum, rotations and terms at the live points,
+    #                   HBM: T2 of every live (state, line), U_{k+q} of every 16-point unit
     #   axis_transforms first two axes, HBM traffic: 16 B (8 B in FP32) nModes nW per state x
     #                   (n_rp read + 2 W^2 N2 for T1) + W per live (state, line) for T2
-    W = 2 * int(np.abs(s.rp).max()) + 1
     nc = nm * nW
     work = {
         "stage2_rates": ("mfma", 8.0 * n_states * N * n_rp * nc),
@@ -174,7 +174,10 @@ def main():
         "stage1_axes": ("hbm", None),
         # T0 of every k0 plane in one pass over g (when the workspace holds them all)
         "stage1_planes": ("hbm", None),
-        "line_rates": ("mfma", 8.0 * n_states * N * W * nc),
+        # last Rp axis + rotations + terms on the live points only: by its executed
+        # intensity (about 6 flop/B, below the FP64 ridge) an HBM kernel; bytes recorded
+        # by the library (T2 of the live (state, line) pairs, U_{k+q} of every 16-point unit)
+        "line_rates": ("hbm", None),
         # first two Rp axes, HBM (bytes recorded by the library: T2 of live lines only)
         "axis_transforms": ("hbm", None),
     }
@@ -187,7 +190,7 @@ def main():
         if n_l == 0:
             continue
         lps = n_l / args.steps
-        if name in ("stage1_axes", "stage1_planes", "axis_transforms"):
+        if name in ("stage1_axes", "stage1_planes", "axis_transforms", "line_rates"):
             # the library records each launch's bytes (g, the intermediates, G)
             amount = lib.kernel_bytes(name) / args.steps
         avg_ms = ms / n_l

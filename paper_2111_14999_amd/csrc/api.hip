@@ -759,8 +759,9 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                                                     (int32_t)(bt.first + bt.second)) - strow.begin();
                 n_sub += (a1 - a0 + nsb - 1) / nsb;
             }
-        uint32_t* nlive = factored ? ar.take<uint32_t>((size_t)std::max<int64_t>(n_sub, 1)) : nullptr;
-        if (factored) HIPCHK(h, hipMemsetAsync(nlive, 0, sizeof(uint32_t) * std::max<int64_t>(n_sub, 1), s));
+        uint32_t* nlive = factored ? ar.take<uint32_t>((size_t)2 * std::max<int64_t>(n_sub, 1)) : nullptr;
+        if (factored)
+            HIPCHK(h, hipMemsetAsync(nlive, 0, 2 * sizeof(uint32_t) * std::max<int64_t>(n_sub, 1), s));
         int64_t isub = 0;
 
         const double inv_sqrtpi_sigma = 1.0 / (std::sqrt(kPi) * par->sigma);
@@ -902,7 +903,7 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                 for (int sb = 0; sb < ns; sb += nsb) {
                     const int nn = std::min(nsb, ns - sb);
                     REQUIRE(h, isub < n_sub, "sub-batch count");
-                    uint32_t* nl = nlive + isub++;
+                    uint32_t* nl = nlive + 2 * isub++;
                     RateArgs rb = ra;
                     rb.T2 = T2buf;
                     rb.st_kmesh += sb;
@@ -935,7 +936,9 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                         HIPCHK(h, launch_line_rates_f32(rb, nn, s));
                     else
                         HIPCHK(h, launch_line_rates(rb, nn, s));
-                    tl.done();
+                    // T2 of every live (state, line) read once; U_{k+q} of band m at the 16
+                    // points of every unit
+                    tl.done(0.0, nl, (double)g_elem * Wbox * nm * nW, nl + 1, 16.0 * nW * sizeof(cd));
                 }
             }
             HIPCHK(h, launch_reduce_partials(partial, ns, n_qtiles, T.st_row + sbeg,

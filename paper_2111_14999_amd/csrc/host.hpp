@@ -24,9 +24,9 @@ struct TimedLaunch {
     std::string name;
     hipEvent_t start, stop;
     double bytes = 0.0;  // algorithmic HBM bytes of the launch, where the host knows them
-    // plus bytes_per_count times a count the device leaves in *dcount
-    const uint32_t* dcount = nullptr;
-    double bytes_per_count = 0.0;
+    // plus bytes_per_count[i] times counts the device leaves in dcount[i]
+    const uint32_t* dcount[2] = {nullptr, nullptr};
+    double bytes_per_count[2] = {0.0, 0.0};
 };
 
 struct KernelStat {
@@ -128,11 +128,14 @@ struct Timer {
         HIPCHK(h, hipEventCreate(&t.stop));
         HIPCHK(h, hipEventRecord(t.start, s));
     }
-    void done(double bytes = 0.0, const uint32_t* dcount = nullptr, double bytes_per_count = 0.0) {
+    void done(double bytes = 0.0, const uint32_t* dcount = nullptr, double bytes_per_count = 0.0,
+              const uint32_t* dcount2 = nullptr, double bytes_per_count2 = 0.0) {
         if (!on) return;
         t.bytes = bytes;
-        t.dcount = dcount;
-        t.bytes_per_count = bytes_per_count;
+        t.dcount[0] = dcount;
+        t.bytes_per_count[0] = bytes_per_count;
+        t.dcount[1] = dcount2;
+        t.bytes_per_count[1] = bytes_per_count2;
         HIPCHK(h, hipEventRecord(t.stop, s));
         h->pending.push_back(t);
         on = false;
@@ -155,11 +158,12 @@ inline void flush_timing(Handle* h, hipStream_t s) {
         ks->launches += 1;
         ks->total_ms += ms;
         ks->bytes += t.bytes;
-        if (t.dcount) {
-            uint32_t n = 0;
-            HIPCHK(h, hipMemcpy(&n, t.dcount, sizeof(n), hipMemcpyDeviceToHost));
-            ks->bytes += t.bytes_per_count * n;
-        }
+        for (int i = 0; i < 2; ++i)
+            if (t.dcount[i]) {
+                uint32_t n = 0;
+                HIPCHK(h, hipMemcpy(&n, t.dcount[i], sizeof(n), hipMemcpyDeviceToHost));
+                ks->bytes += t.bytes_per_count[i] * n;
+            }
         (void)hipEventDestroy(t.start);
         (void)hipEventDestroy(t.stop);
     }

@@ -157,9 +157,9 @@ size_t re_axes_lds(int rmax, bool f32);
 
 // Axis 0 on MFMA + rotations + rate terms, one work-group per (state, q1, q2) line.
 // Columns sa*16 + b (nW <= 16), nc_pad = 64 TN with 4 TN >= nModes.
-// Live final bands of every (state, point) for the line kernel, their union
-// per (state, line) and, added to *n_live, the number of (state, line) pairs
-// with a live band.
+// Live final bands of every (state, point) for the line kernel (nW <= 16),
+// their union per (state, line) and, added to n_live[0] and n_live[1], the
+// number of (state, line) pairs with a live band and of 16-point units.
 hipError_t launch_line_live(const RateArgs& a, int nst, uint32_t* live, uint32_t* line_bands,
                             uint32_t* n_live, hipStream_t s);
 hipError_t launch_line_rates(const RateArgs& a, int nst, hipStream_t s);

@@ -628,26 +628,41 @@ __global__ void line_live_kernel(RateArgs a, uint32_t* __restrict__ live) {
     live[i] = bits;
 }
 
-// union of the live bands over the points of every (state, line); the lines
-// with a live band are counted (one atomic per wave)
+// union of the live bands over the points of every (state, line); counted
+// (one atomic per wave): n_live[0] the lines with a live band, n_live[1] the
+// units of 16 points the line kernel will take (per band, its live points / 16
+// rounded up)
 __global__ void line_any_kernel(const uint32_t* __restrict__ live, int nst, int N0, int NL,
                                 uint32_t* __restrict__ line_bands, uint32_t* __restrict__ n_live) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int64_t n_lines = (int64_t)nst * NL;
-    uint32_t u = 0;
+    uint32_t u = 0, units = 0;
     if (i < n_lines) {
         const int64_t st = i / NL, line = i - st * NL;
-        for (int q0 = 0; q0 < N0; ++q0) u |= live[(st * N0 + q0) * NL + line];
+        int cnt[16] = {};
+        for (int q0 = 0; q0 < N0; ++q0) {
+            const uint32_t msk = live[(st * N0 + q0) * NL + line];
+            u |= msk;
+#pragma unroll
+            for (int m = 0; m < 16; ++m) cnt[m] += (msk >> m) & 1u;
+        }
         line_bands[i] = u;
+#pragma unroll
+        for (int m = 0; m < 16; ++m) units += (cnt[m] + 15) / 16;
     }
     const uint64_t bal = __ballot(u != 0);
-    if ((threadIdx.x & 63) == 0 && bal) atomicAdd(n_live, (uint32_t)__popcll(bal));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) units += __shfl_xor(units, o, 64);
+    if ((threadIdx.x & 63) == 0) {
+        if (bal) atomicAdd(n_live, (uint32_t)__popcll(bal));
+        if (units) atomicAdd(n_live + 1, units);
+    }
 }
 
 hipError_t launch_line_live(const RateArgs& a, int nst, uint32_t* live, uint32_t* line_bands,
                             uint32_t* n_live, hipStream_t s) {
     if (nst <= 0) return hipSuccess;
-    if (a.nW > 32 || !live || !line_bands || !n_live) return hipErrorInvalidValue;
+    if (a.nW > 16 || !live || !line_bands || !n_live) return hipErrorInvalidValue;
     RateArgs b = a;
     b.n_states = nst;
     const int NL = a.mesh.n1 * a.mesh.n2;
