@@ -339,8 +339,10 @@ __device__ inline R row16_sum(R x) {
 //   F[st, Rp, sa*16 + b] = sum_a conj(U_k[a, n_st]) G[k, Rp, sa, a, b]
 // is a sum over the 16 lanes of a row.  G never leaves the registers; F is
 // written once per state.
+constexpr int kFoldWaves = 8;  // waves of the folded pair kernel sharing one T0 slab
+
 template <int WT, class C>
-__global__ __launch_bounds__(256) void re_axis12_fold_kernel(
+__global__ __launch_bounds__(64 * kFoldWaves) void re_axis12_fold_kernel(
     const C* __restrict__ T0, int64_t NC, int Wr, const cd* __restrict__ P1,
     const cd* __restrict__ P2, const int32_t* __restrict__ pair_k1,
     const int32_t* __restrict__ pair_off, const int32_t* __restrict__ kp_off,
@@ -357,7 +359,8 @@ __global__ __launch_bounds__(256) void re_axis12_fold_kernel(
     const int tid = threadIdx.x;
     const int plane = d_plane ? d_plane[d] : d;
     const C* src = T0 + (int64_t)plane * W * W * NC + c0;
-    for (int i = tid; i < W * W * 64; i += 256) sT[i] = src[(int64_t)(i >> 6) * NC + (i & 63)];
+    for (int i = tid; i < W * W * 64; i += 64 * kFoldWaves)
+        sT[i] = src[(int64_t)(i >> 6) * NC + (i & 63)];
     __syncthreads();
     const int cc = tid & 63, tg = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int li = cc & 15, lg = cc >> 4;
@@ -368,10 +371,10 @@ __global__ __launch_bounds__(256) void re_axis12_fold_kernel(
     C* Fo = reinterpret_cast<C*>(fo.F) + (int64_t)r * fo.nc_pad + sa * 16 + b;
     const int64_t fst = (int64_t)fo.rp_pad * fo.nc_pad;
     const int pend = pair_off[d + 1];
-    for (int pp = pair_off[d] + tg; pp < pend; pp += 8) {
-        const bool two = pp + 4 < pend;
+    for (int pp = pair_off[d] + tg; pp < pend; pp += 2 * kFoldWaves) {
+        const bool two = pp + kFoldWaves < pend;
         const cd* Pka = P1 + (int64_t)pair_k1[pp] * W;
-        const cd* Pkb = P1 + (int64_t)pair_k1[two ? pp + 4 : pp] * W;
+        const cd* Pkb = P1 + (int64_t)pair_k1[two ? pp + kFoldWaves : pp] * W;
         C ta[NV], tb[NV];
 #pragma unroll
         for (int r2 = 0; r2 < NV; ++r2) ta[r2] = tb[r2] = C{0, 0};
@@ -390,7 +393,7 @@ __global__ __launch_bounds__(256) void re_axis12_fold_kernel(
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             if (h == 1 && !two) break;
-            const int p = pp + 4 * h;
+            const int p = pp + kFoldWaves * h;
             for (int i = kp_off[p]; i < kp_off[p + 1]; ++i) {
                 const cd* Pk2 = P2 + (int64_t)k_k2[i] * W;
                 C acc = {0, 0};
@@ -433,7 +436,8 @@ static hipError_t go_re_axis12(const C* T0, int64_t NC, int W, Mesh m, const cd*
     const int64_t ncb = (NC + 63) / 64;
     if ((int64_t)b.d0 * ncb > 2147483647LL) return hipErrorInvalidValue;
     if (fo)
-        hipLaunchKernelGGL((re_axis12_fold_kernel<WT, C>), dim3((unsigned)(b.d0 * ncb)), dim3(256),
+        hipLaunchKernelGGL((re_axis12_fold_kernel<WT, C>), dim3((unsigned)(b.d0 * ncb)),
+                           dim3(64 * kFoldWaves),
                            shm, s, T0, NC, W, P1, P2, b.pair_k1, b.pair_off, b.kp_off, b.k_row,
                            b.k_k2, b.d_plane, ncb, *fo);
     else
