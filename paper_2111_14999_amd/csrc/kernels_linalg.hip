@@ -379,6 +379,148 @@ __global__ __launch_bounds__(64) void eig_herm_kernel(cd* __restrict__ Aall, int
     }
 }
 
+// The same Jacobi method for n <= 16 with the work of a round split by 2 x 2
+// blocks: in a round the pairs partition the indices, so lane (I, J) (I, J <
+// n/2 rounded up) owns the block of rows {p_I, q_I} and columns {p_J, q_J}.
+// The two-sided rotation of that block reads only the block (rows by pair I,
+// then columns by pair J), and so does the column rotation of V on rows
+// {2I, 2I + 1}: every lane reads, rotates and writes its own elements, and a
+// round needs one barrier after the parameters and one after the update.
+// The pair order, the skip test and the stopping rule are those above.
+template <int NT>
+__global__ __launch_bounds__(64) void eig_herm_blk_kernel(cd* __restrict__ Aall, int n_arg,
+                                                          double* __restrict__ w_out,
+                                                          cd* __restrict__ V_out) {
+    const int n = NT > 0 ? NT : n_arg;
+    constexpr int LD = 17;  // odd row stride (see above)
+    __shared__ cd A[16 * LD], V[16 * LD];
+    __shared__ double prm[8][4];  // c, s, e of every pair of the round
+    const int64_t b = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int I = lane >> 3, J = lane & 7;
+    const int np = n + (n & 1), half = np / 2;
+    const bool act = I < half && J < half;
+    const cd* Ag = Aall + b * (int64_t)n * n;
+    for (int i = lane; i < n * n; i += 64) {
+        const int r = i / n, c = i - r * n;
+        A[r * LD + c] = Ag[i];
+        V[r * LD + c] = cd{r == c ? 1.0 : 0.0, 0.0};
+    }
+    __syncthreads();
+    const double eps2 = 4.9e-32;  // (2.2e-16)^2
+    for (int sweep = 0; sweep < 40 && n > 1; ++sweep) {
+        double off = 0.0, dia = 0.0;
+        for (int i = lane; i < n * n; i += 64) {
+            const int r = i / n, c = i - r * n;
+            const double v = cabs2(A[r * LD + c]);
+            if (r == c)
+                dia += v;
+            else
+                off += v;
+        }
+        off = wave_sum(off);
+        dia = wave_sum(dia);
+        if (!(off > 1e-32 * dia)) break;
+        const double skip_abs = eps2 * dia / n;
+        int rotated = 0;
+        for (int round = 0; round < np - 1; ++round) {
+            if (lane < half) {
+                int p, q;
+                rr_pair(lane, round, np, p, q);
+                double c = 1.0, s = 0.0;
+                cd e = {1.0, 0.0};
+                if (q < n) {
+                    const double a = A[p * LD + p].x, d = A[q * LD + q].x;
+                    const cd bpq = A[p * LD + q];
+                    const double bb2 = cabs2(bpq);
+                    if (bb2 > fmax(eps2 * fabs(a * d), skip_abs) && bb2 > 0.0) {
+                        rotated = 1;
+                        const double bb = sqrt(bb2);
+                        const double tau = (d - a) / (2.0 * bb);
+                        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                        c = 1.0 / sqrt(1.0 + t * t);
+                        s = t * c;
+                        e = cd{bpq.x / bb, bpq.y / bb};
+                    }
+                }
+                prm[lane][0] = c;
+                prm[lane][1] = s;
+                prm[lane][2] = e.x;
+                prm[lane][3] = e.y;
+            }
+            __syncthreads();
+            if (act) {
+                int pI, qI, pJ, qJ;
+                rr_pair(I, round, np, pI, qI);
+                rr_pair(J, round, np, pJ, qJ);
+                const double cI = prm[I][0], sI = prm[I][1], cJ = prm[J][0], sJ = prm[J][1];
+                const cd eI = {prm[I][2], prm[I][3]}, eJ = {prm[J][2], prm[J][3]};
+                const bool qIok = qI < n, qJok = qJ < n;
+                if (sI != 0.0 || sJ != 0.0) {
+                    const cd z = {0.0, 0.0};
+                    cd x00 = A[pI * LD + pJ];
+                    cd x01 = qJok ? A[pI * LD + qJ] : z;
+                    cd x10 = qIok ? A[qI * LD + pJ] : z;
+                    cd x11 = qIok && qJok ? A[qI * LD + qJ] : z;
+                    if (sI != 0.0) {  // rows: A'_p = c A_p - s e A_q ; A'_q = s conj(e) A_p + c A_q
+                        const cd e0 = cmul(eI, x10), e1 = cmul(eI, x11);
+                        const cd f0 = cmulc(eI, x00), f1 = cmulc(eI, x01);
+                        x00 = cd{cI * x00.x - sI * e0.x, cI * x00.y - sI * e0.y};
+                        x01 = cd{cI * x01.x - sI * e1.x, cI * x01.y - sI * e1.y};
+                        x10 = cd{sI * f0.x + cI * x10.x, sI * f0.y + cI * x10.y};
+                        x11 = cd{sI * f1.x + cI * x11.x, sI * f1.y + cI * x11.y};
+                    }
+                    if (sJ != 0.0) {  // columns: A'_ip = c A_ip - s conj(e) A_iq ; A'_iq = s e A_ip + c A_iq
+                        const cd e0 = cmulc(eJ, x01), e1 = cmulc(eJ, x11);
+                        const cd f0 = cmul(eJ, x00), f1 = cmul(eJ, x10);
+                        x00 = cd{cJ * x00.x - sJ * e0.x, cJ * x00.y - sJ * e0.y};
+                        x10 = cd{cJ * x10.x - sJ * e1.x, cJ * x10.y - sJ * e1.y};
+                        x01 = cd{sJ * f0.x + cJ * x01.x, sJ * f0.y + cJ * x01.y};
+                        x11 = cd{sJ * f1.x + cJ * x11.x, sJ * f1.y + cJ * x11.y};
+                    }
+                    if (I == J && sI != 0.0) {  // the rotated pair: exact zero off the diagonal
+                        x01 = z;
+                        x10 = z;
+                        x00.y = 0.0;
+                        x11.y = 0.0;
+                    }
+                    A[pI * LD + pJ] = x00;
+                    if (qJok) A[pI * LD + qJ] = x01;
+                    if (qIok) A[qI * LD + pJ] = x10;
+                    if (qIok && qJok) A[qI * LD + qJ] = x11;
+                }
+                if (sJ != 0.0) {  // V columns p_J, q_J on rows 2I, 2I + 1
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int r = 2 * I + h;
+                        if (r < n) {
+                            const cd vp = V[r * LD + pJ];
+                            const cd vq = qJok ? V[r * LD + qJ] : cd{0.0, 0.0};
+                            const cd eq = cmulc(eJ, vq), ep = cmul(eJ, vp);
+                            V[r * LD + pJ] = cd{cJ * vp.x - sJ * eq.x, cJ * vp.y - sJ * eq.y};
+                            if (qJok) V[r * LD + qJ] = cd{sJ * ep.x + cJ * vq.x, sJ * ep.y + cJ * vq.y};
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        if (!__any(rotated)) break;  // a sweep with no rotation leaves A unchanged
+    }
+    // ascending order, ties by index
+    for (int i = lane; i < n; i += 64) {
+        const double wi = A[i * LD + i].x;
+        int rank = 0;
+        for (int j = 0; j < n; ++j) {
+            const double wj = A[j * LD + j].x;
+            rank += (wj < wi) || (wj == wi && j < i);
+        }
+        w_out[b * n + rank] = wi;
+        cd* Vg = V_out + b * (int64_t)n * n;
+        for (int r = 0; r < n; ++r) Vg[r * n + rank] = V[r * LD + i];
+    }
+}
+
 hipError_t launch_eig_herm(cd* A, int n, int64_t batch, double* w, cd* V, hipStream_t s) {
     if (batch <= 0) return hipSuccess;
     const int h = n / 2 + 1;
@@ -395,10 +537,20 @@ hipError_t launch_eig_herm(cd* A, int n, int64_t batch, double* w, cd* V, hipStr
         hipLaunchKernelGGL(eig_herm_kernel<NV>, dim3((unsigned)nb), dim3(64), shm, s, Ab, n, wb, \
                            Vb);                                                                 \
         break;
-            PHX_EIG(3) PHX_EIG(4) PHX_EIG(5) PHX_EIG(6) PHX_EIG(7) PHX_EIG(8) PHX_EIG(9)
-            PHX_EIG(10) PHX_EIG(12) PHX_EIG(14) PHX_EIG(15) PHX_EIG(16) PHX_EIG(18) PHX_EIG(20)
-            PHX_EIG(21) PHX_EIG(24) PHX_EIG(27) PHX_EIG(30)
+#define PHX_EIGB(NV)                                                                            \
+    case NV:                                                                                    \
+        hipLaunchKernelGGL(eig_herm_blk_kernel<NV>, dim3((unsigned)nb), dim3(64), 0, s, Ab, n,  \
+                           wb, Vb);                                                             \
+        break;
+            PHX_EIGB(3) PHX_EIGB(4) PHX_EIGB(5) PHX_EIGB(6) PHX_EIGB(7) PHX_EIGB(8) PHX_EIGB(9)
+            PHX_EIGB(10) PHX_EIGB(12) PHX_EIGB(14) PHX_EIGB(15) PHX_EIGB(16)
+            PHX_EIG(18) PHX_EIG(20) PHX_EIG(21) PHX_EIG(24) PHX_EIG(27) PHX_EIG(30)
+            case 1: case 2: case 11: case 13:
+                hipLaunchKernelGGL(eig_herm_blk_kernel<0>, dim3((unsigned)nb), dim3(64), 0, s, Ab,
+                                   n, wb, Vb);
+                break;
 #undef PHX_EIG
+#undef PHX_EIGB
             default:
                 hipLaunchKernelGGL(eig_herm_kernel<0>, dim3((unsigned)nb), dim3(64), shm, s, Ab, n,
                                    wb, Vb);
