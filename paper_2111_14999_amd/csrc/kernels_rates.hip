@@ -6,6 +6,9 @@
 // precompute with the k-side rotation folded in) on MFMA, rotates the result
 // by U_{k+q} and by the scaled phonon eigenvectors, and accumulates the
 // smeared rate terms; g(k, q) is never written to memory.
+#include <algorithm>
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace phx {
@@ -578,10 +581,75 @@ __global__ void rotate_g_kernel(const cd* __restrict__ X, int64_t nq, const cd* 
     }
 }
 
+// The same rotation with one work-group per q (nW <= 16): X[q] and E_q are staged
+// in LDS once; thread (n, m) holds U_{k+q}[:, m] and Y[sa] = sum_b X[q, sa, n, b]
+// U[b, m] for every sa in registers and writes g[q, nu, n, m] (m fastest).  The
+// sums run in the same order as above.
+template <int NMX>
+__global__ __launch_bounds__(256) void rotate_g_lds_kernel(const cd* __restrict__ X,
+                                                           const cd* __restrict__ Ukq,
+                                                           const cd* __restrict__ E, int nW,
+                                                           int nm, cd* __restrict__ g) {
+    extern __shared__ char smem_raw[];
+    const int nc = nm * nW * nW;
+    cd* sX = reinterpret_cast<cd*>(smem_raw);  // [nm][nW][nW]
+    cd* sE = sX + nc;                          // [nu][sa]
+    const int64_t q = blockIdx.x;
+    const int tid = threadIdx.x;
+    const cd* Xq = X + q * nc;
+    for (int i = tid; i < nc; i += blockDim.x) sX[i] = Xq[i];
+    const cd* Eq = E + q * nm * nm;
+    for (int i = tid; i < nm * nm; i += blockDim.x) sE[i] = Eq[i];
+    __syncthreads();
+    if (tid >= nW * nW) return;
+    const int n = tid / nW, m = tid - n * nW;
+    const cd* Uq = Ukq + q * nW * nW;
+    cd u[16];
+#pragma unroll
+    for (int b = 0; b < 16; ++b) u[b] = b < nW ? Uq[b * nW + m] : cd{0.0, 0.0};
+    cd Y[NMX];
+#pragma unroll
+    for (int sa = 0; sa < NMX; ++sa) {
+        cd acc = {0.0, 0.0};
+        if (sa < nm) {
+            const cd* xr = sX + (sa * nW + n) * nW;
+#pragma unroll
+            for (int b = 0; b < 16; ++b)
+                if (b < nW) acc = cfma(xr[b], u[b], acc);
+        }
+        Y[sa] = acc;
+    }
+    cd* go = g + q * nc + n * nW + m;
+    for (int nu = 0; nu < nm; ++nu) {
+        const cd* er = sE + nu * nm;
+        cd z = {0.0, 0.0};
+#pragma unroll
+        for (int sa = 0; sa < NMX; ++sa)
+            if (sa < nm) z = cfma(er[sa], Y[sa], z);
+        go[(int64_t)nu * nW * nW] = z;
+    }
+}
+
 hipError_t launch_rotate_g(const cd* X, int64_t nq, const cd* Uk, const cd* Ukq, const cd* E,
                            int nW, int nm, cd* g, hipStream_t s) {
     (void)Uk;
     if (nq <= 0) return hipSuccess;
+    const size_t shm = ((size_t)nm * nW * nW + (size_t)nm * nm) * sizeof(cd);
+    if (nW <= 16 && nm <= 32 && shm <= 160 * 1024 && nq <= 2147483647LL) {
+        const int block = std::max(64, (nW * nW + 63) / 64 * 64);
+        auto go = [&](auto nmx) {
+            constexpr int NMX = decltype(nmx)::value;
+            hipError_t e = hipFuncSetAttribute((const void*)rotate_g_lds_kernel<NMX>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(rotate_g_lds_kernel<NMX>, dim3((unsigned)nq), dim3(block), shm, s, X,
+                               Ukq, E, nW, nm, g);
+            return hipGetLastError();
+        };
+        if (nm <= 8) return go(std::integral_constant<int, 8>{});
+        if (nm <= 16) return go(std::integral_constant<int, 16>{});
+        return go(std::integral_constant<int, 32>{});
+    }
     hipLaunchKernelGGL(rotate_g_kernel, dim3(grid1(nq * nW * nW, 128)), dim3(128), 0, s, X, nq,
                        Ukq, E, nW, nm, g);
     return hipGetLastError();
