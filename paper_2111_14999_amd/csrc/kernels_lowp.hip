@@ -10,6 +10,8 @@
 // stay FP64.  MFMA layouts (f32 16x16x4): lane l holds A[l%16][l/16],
 // B[l/16][l%16]; (bf16 16x16x32): lane l holds A[l%16][8(l/16)+j],
 // B[8(l/16)+j][l%16], j = 0..7; both return row 4(l/16)+v, column l%16.
+#include <type_traits>
+
 #include "kernels.hpp"
 #include "lowp.hpp"
 
@@ -751,9 +753,85 @@ __global__ void rotate_g_lp_kernel(const cf* __restrict__ X, int64_t nq, const c
     }
 }
 
+// The same rotation with one work-group per q (nW <= 16): X[q] and E_q (rounded
+// to FP32) staged in LDS once; thread (n, m) holds U_{k+q}[:, m] and Y[sa] in
+// registers.  The sums run in the same order as above.
+template <int NMX>
+__global__ __launch_bounds__(256) void rotate_g_lp_lds_kernel(const cf* __restrict__ X,
+                                                              const cd* __restrict__ Ukq,
+                                                              const cd* __restrict__ E, int nW,
+                                                              int nm, cd* __restrict__ g) {
+    extern __shared__ char smem_raw[];
+    const int nc = nm * nW * nW;
+    cf* sX = reinterpret_cast<cf*>(smem_raw);  // [nm][nW][nW]
+    cf* sE = sX + nc;                          // [nu][sa]
+    const int64_t q = blockIdx.x;
+    const int tid = threadIdx.x;
+    const cf* Xq = X + q * nc;
+    for (int i = tid; i < nc; i += blockDim.x) sX[i] = Xq[i];
+    const cd* Eq = E + q * nm * nm;
+    for (int i = tid; i < nm * nm; i += blockDim.x) sE[i] = cf{(float)Eq[i].x, (float)Eq[i].y};
+    __syncthreads();
+    if (tid >= nW * nW) return;
+    const int n = tid / nW, m = tid - n * nW;
+    const cd* Uq = Ukq + q * nW * nW;
+    float ur[16], ui[16];
+#pragma unroll
+    for (int b = 0; b < 16; ++b) {
+        const cd u = b < nW ? Uq[b * nW + m] : cd{0.0, 0.0};
+        ur[b] = (float)u.x;
+        ui[b] = (float)u.y;
+    }
+    float yr[NMX], yi[NMX];
+#pragma unroll
+    for (int sa = 0; sa < NMX; ++sa) {
+        float ar = 0.f, ai = 0.f;
+        if (sa < nm) {
+            const cf* xr = sX + (sa * nW + n) * nW;
+#pragma unroll
+            for (int b = 0; b < 16; ++b)
+                if (b < nW) {
+                    const cf x = xr[b];
+                    ar = fmaf(x.x, ur[b], fmaf(-x.y, ui[b], ar));
+                    ai = fmaf(x.x, ui[b], fmaf(x.y, ur[b], ai));
+                }
+        }
+        yr[sa] = ar;
+        yi[sa] = ai;
+    }
+    cd* go = g + q * nc + n * nW + m;
+    for (int nu = 0; nu < nm; ++nu) {
+        const cf* er = sE + nu * nm;
+        float zr = 0.f, zi = 0.f;
+#pragma unroll
+        for (int sa = 0; sa < NMX; ++sa)
+            if (sa < nm) {
+                zr = fmaf(er[sa].x, yr[sa], fmaf(-er[sa].y, yi[sa], zr));
+                zi = fmaf(er[sa].x, yi[sa], fmaf(er[sa].y, yr[sa], zi));
+            }
+        go[(int64_t)nu * nW * nW] = cd{(double)zr, (double)zi};
+    }
+}
+
 hipError_t launch_rotate_g_lp(const cf* X, int64_t nq, const cd* Ukq, const cd* E, int nW, int nm,
                               cd* g, hipStream_t s) {
     if (nq <= 0) return hipSuccess;
+    const size_t shm = ((size_t)nm * nW * nW + (size_t)nm * nm) * sizeof(cf);
+    if (nW <= 16 && nm <= 32 && shm <= 160 * 1024 && nq <= 2147483647LL) {
+        const int block = (nW * nW + 63) / 64 * 64 < 64 ? 64 : (nW * nW + 63) / 64 * 64;
+        auto go = [&](auto nmx) {
+            constexpr int NMX = decltype(nmx)::value;
+            hipError_t e = hipFuncSetAttribute((const void*)rotate_g_lp_lds_kernel<NMX>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(rotate_g_lp_lds_kernel<NMX>, dim3((unsigned)nq), dim3(block), shm, s,
+                               X, Ukq, E, nW, nm, g);
+            return hipGetLastError();
+        };
+        if (nm <= 8) return go(std::integral_constant<int, 8>{});
+        if (nm <= 16) return go(std::integral_constant<int, 16>{});
+        return go(std::integral_constant<int, 32>{});
+    }
     hipLaunchKernelGGL(rotate_g_lp_kernel, dim3(gridn(nq * nW * nW, 128)), dim3(128), 0, s, X, nq,
                        Ukq, E, nW, nm, g);
     return hipGetLastError();
