@@ -608,47 +608,38 @@ __device__ inline R rows4_reduce_scatter(R u0, R u1, R u2, R u3) {
 // Live final bands of every point.  Bit m of live[(st * N0 + q0) * NL + line]
 // is set when |eps_n - eps_{m,k+q}| <= 27.5 sigma + max omega at that point;
 // otherwise both Gaussians of every term of band m there are beyond 27.5 sigma,
-// i.e. exactly 0.  One thread per (state, point), the line index fastest.
-__global__ void line_live_kernel(RateArgs a, uint32_t* __restrict__ live) {
+// i.e. exactly 0.  One thread per (state, line), the line index fastest (the
+// writes of one point are contiguous over the lines).  The thread also leaves
+// the union of its line's bands in line_bands and counts (one atomic per wave)
+// n_live[0] the lines with a live band and n_live[1] the units of 16 points the
+// line kernel will take (per band, its live points / 16 rounded up).
+__global__ void line_live_kernel(RateArgs a, uint32_t* __restrict__ live,
+                                 uint32_t* __restrict__ line_bands, uint32_t* __restrict__ n_live) {
     const Mesh mesh = a.mesh;
     const int N0 = mesh.n0, NL = mesh.n1 * mesh.n2, nW = a.nW;
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= (int64_t)a.n_states * N0 * NL) return;
-    const int line = (int)(i % NL);
-    const int64_t sq = i / NL;
-    const int q0 = (int)(sq % N0), st = (int)(sq / N0);
-    const int q1 = line / mesh.n2, q2 = line - q1 * mesh.n2;
-    const int kmesh = a.st_kmesh[st];
-    const int mlo = a.st_mlo[st], mhi = a.st_mhi[st];
-    int k0i, k1i, k2i;
-    mesh_triple(kmesh, mesh, k0i, k1i, k2i);
-    const int64_t kq = (int64_t)((k0i + q0) % N0) * NL + ((k1i + q1) % mesh.n1) * mesh.n2 +
-                       (k2i + q2) % mesh.n2;
-    const double eps_n = a.eps[(int64_t)kmesh * nW + a.st_band[st]];
-    const double lim = 27.5 * a.sigma + *a.wmax;
-    uint32_t bits = 0;
-    for (int m = mlo; m <= mhi; ++m)
-        bits |= (uint32_t)(fabs(eps_n - a.eps[kq * nW + m]) <= lim) << m;
-    live[i] = bits;
-}
-
-// union of the live bands over the points of every (state, line); counted
-// (one atomic per wave): n_live[0] the lines with a live band, n_live[1] the
-// units of 16 points the line kernel will take (per band, its live points / 16
-// rounded up)
-__global__ void line_any_kernel(const uint32_t* __restrict__ live, int nst, int N0, int NL,
-                                uint32_t* __restrict__ line_bands, uint32_t* __restrict__ n_live) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int64_t n_lines = (int64_t)nst * NL;
     uint32_t u = 0, units = 0;
-    if (i < n_lines) {
-        const int64_t st = i / NL, line = i - st * NL;
+    if (i < (int64_t)a.n_states * NL) {
+        const int line = (int)(i % NL), st = (int)(i / NL);
+        const int q1 = line / mesh.n2, q2 = line - q1 * mesh.n2;
+        const int kmesh = a.st_kmesh[st];
+        const int mlo = a.st_mlo[st], mhi = a.st_mhi[st];
+        int k0i, k1i, k2i;
+        mesh_triple(kmesh, mesh, k0i, k1i, k2i);
+        const int64_t kq12 = ((k1i + q1) % mesh.n1) * mesh.n2 + (k2i + q2) % mesh.n2;
+        const double eps_n = a.eps[(int64_t)kmesh * nW + a.st_band[st]];
+        const double lim = 27.5 * a.sigma + *a.wmax;
         int cnt[16] = {};
+        uint32_t* out = live + (int64_t)st * N0 * NL + line;
+#pragma unroll 4
         for (int q0 = 0; q0 < N0; ++q0) {
-            const uint32_t msk = live[(st * N0 + q0) * NL + line];
-            u |= msk;
+            const double* ek = a.eps + ((int64_t)((k0i + q0) % N0) * NL + kq12) * nW;
+            uint32_t bits = 0;
+            for (int m = mlo; m <= mhi; ++m) bits |= (uint32_t)(fabs(eps_n - ek[m]) <= lim) << m;
+            out[(int64_t)q0 * NL] = bits;
+            u |= bits;
 #pragma unroll
-            for (int m = 0; m < 16; ++m) cnt[m] += (msk >> m) & 1u;
+            for (int m = 0; m < 16; ++m) cnt[m] += (bits >> m) & 1u;
         }
         line_bands[i] = u;
 #pragma unroll
@@ -669,14 +660,9 @@ hipError_t launch_line_live(const RateArgs& a, int nst, uint32_t* live, uint32_t
     if (a.nW > 16 || !live || !line_bands || !n_live) return hipErrorInvalidValue;
     RateArgs b = a;
     b.n_states = nst;
-    const int NL = a.mesh.n1 * a.mesh.n2;
-    const int64_t n = (int64_t)nst * a.mesh.n0 * NL;
-    hipLaunchKernelGGL(line_live_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, b, live);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const int64_t n_lines = (int64_t)nst * NL;
-    hipLaunchKernelGGL(line_any_kernel, dim3((unsigned)((n_lines + 255) / 256)), dim3(256), 0, s,
-                       live, nst, a.mesh.n0, NL, line_bands, n_live);
+    const int64_t n = (int64_t)nst * a.mesh.n1 * a.mesh.n2;
+    hipLaunchKernelGGL(line_live_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, b, live,
+                       line_bands, n_live);
     return hipGetLastError();
 }
 
