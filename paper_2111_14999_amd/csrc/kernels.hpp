@@ -96,7 +96,7 @@ struct RateArgs {
     int W;                     // 2 rmax + 1
     int n_states;              // states of one launch (set by the launcher)
     const double* wmax;        // device scalar: largest phonon energy on the mesh
-    const uint32_t* live;        // [nst, N0, N1*N2] live final bands of every point (line_live)
+    const uint32_t* live;        // [nst, N1*N2, N0] live final bands of every point (line_live)
     const uint32_t* line_bands;  // [nst, N1*N2] union of a line's live bands, 0: none
 };
 

@@ -605,11 +605,12 @@ __device__ inline R rows4_reduce_scatter(R u0, R u1, R u2, R u3) {
     return s + t;
 }
 
-// Live final bands of every point.  Bit m of live[(st * N0 + q0) * NL + line]
+// Live final bands of every point.  Bit m of live[(st * NL + line) * N0 + q0]
 // is set when |eps_n - eps_{m,k+q}| <= 27.5 sigma + max omega at that point;
 // otherwise both Gaussians of every term of band m there are beyond 27.5 sigma,
-// i.e. exactly 0.  One thread per (state, line), the line index fastest (the
-// writes of one point are contiguous over the lines).  The thread also leaves
+// i.e. exactly 0.  One thread per (state, line), the line index fastest; the
+// masks of one line are contiguous, so the line kernel reads them as one
+// block.  The thread also leaves
 // the union of its line's bands in line_bands and counts (one atomic per wave)
 // n_live[0] the lines with a live band and n_live[1] the units of 16 points the
 // line kernel will take (per band, its live points / 16 rounded up).
@@ -630,13 +631,13 @@ __global__ void line_live_kernel(RateArgs a, uint32_t* __restrict__ live,
         const double eps_n = a.eps[(int64_t)kmesh * nW + a.st_band[st]];
         const double lim = 27.5 * a.sigma + *a.wmax;
         int cnt[16] = {};
-        uint32_t* out = live + (int64_t)st * N0 * NL + line;
+        uint32_t* out = live + i * N0;
 #pragma unroll 4
         for (int q0 = 0; q0 < N0; ++q0) {
             const double* ek = a.eps + ((int64_t)((k0i + q0) % N0) * NL + kq12) * nW;
             uint32_t bits = 0;
             for (int m = mlo; m <= mhi; ++m) bits |= (uint32_t)(fabs(eps_n - ek[m]) <= lim) << m;
-            out[(int64_t)q0 * NL] = bits;
+            out[q0] = bits;
             u |= bits;
 #pragma unroll
             for (int m = 0; m < 16; ++m) cnt[m] += (bits >> m) & 1u;
@@ -685,9 +686,14 @@ __device__ inline f4 mfma16(float x, float y, f4 c) {
 // through the list; the last group of a band is padded with an all-zero
 // phase row.  Only the E_q loads of the terms that survive the Gaussian test
 // wait on memory after the rotation.
+//
+// KS > 0 (lines of at most 4 KS rows of T2): the work-group's T2 fragments are
+// loaded into registers right after the live test, behind the point masks and
+// the phase table, so that the three are in flight together and the list
+// building and the unit's gathers overlap them; KS = 0 loads them per K step.
 constexpr int kTP = 2;  // column tiles per MFMA pass
 
-template <int TN, class C>
+template <int TN, int KS, class C>
 __global__ __launch_bounds__(256, 4) void line_rates_kernel(RateArgs a) {
     using R = decltype(C::x);
     constexpr bool F64 = sizeof(R) == 8;
@@ -742,11 +748,42 @@ __global__ __launch_bounds__(256, 4) void line_rates_kernel(RateArgs a) {
                    (int64_t)line * ldf + wave * TN * 16 + bcol;
     const int64_t Tk = (int64_t)NL * ldf;  // stride of R0 in T2
 
-    for (int q0 = tid; q0 < N0; q0 += 256) sPm[q0] = a.live[((int64_t)st * N0 + q0) * NL + line];
-    for (int i = tid; i < (N0 + 1) * Wp; i += 256) {
+    const uint32_t* lv = a.live + ((int64_t)st * NL + line) * N0;
+    const int nP = (N0 + 1) * Wp;
+    auto p0_at = [&](int i) {
         const int q0 = i / Wp, r = i - q0 * Wp;
-        sP[i] = (q0 < N0 && r < W) ? to_c<C>(a.P0[q0 * W + r]) : C{0, 0};
+        return (q0 < N0 && r < W) ? to_c<C>(a.P0[q0 * W + r]) : C{0, 0};
+    };
+    // The first mask and table elements and the T2 fragments are loaded
+    // without branches (clamped addresses), so that the LDS stores wait on
+    // the first two only and T2 stays in flight.  A T2 row k >= W is read
+    // from row W - 1 and meets a zero phase (the table is zero beyond W).
+    const int i0 = min(tid, nP - 1), i1 = min(tid + 256, nP - 1);
+    auto p0_src = [&](int i) {
+        const int q0 = i / Wp, r = i - q0 * Wp;
+        return a.P0[min(q0, N0 - 1) * W + min(r, W - 1)];
+    };
+    const uint32_t pm0 = lv[min(tid, N0 - 1)];
+    const cd pv0 = p0_src(i0), pv1 = p0_src(i1);
+    __builtin_amdgcn_sched_barrier(0);  // keep the T2 loads behind these
+    C tb[KS > 0 ? KS * TN : 1];
+    if constexpr (KS > 0) {
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const int64_t k = min(4 * ks + lg, W - 1);
+#pragma unroll
+            for (int t = 0; t < TN; ++t) tb[ks * TN + t] = Tst[k * Tk + t * 16];
+        }
     }
+    auto p0_keep = [&](int i) {
+        const int q0 = i / Wp, r = i - q0 * Wp;
+        return q0 < N0 && r < W;
+    };
+    if (tid < N0) sPm[tid] = pm0;
+    if (tid < nP) sP[tid] = p0_keep(tid) ? to_c<C>(pv0) : C{0, 0};
+    if (tid + 256 < nP) sP[tid + 256] = p0_keep(tid + 256) ? to_c<C>(pv1) : C{0, 0};
+    for (int q0 = tid + 256; q0 < N0; q0 += 256) sPm[q0] = lv[q0];
+    for (int i = tid + 512; i < nP; i += 256) sP[i] = p0_at(i);
 
     // Values one unit (band m, points list[g .. g+15]) needs: per lane,
     // U_{k+q}[b = 4 lg + v, m] at the lane's point; per thread, for its term
@@ -830,13 +867,7 @@ __global__ __launch_bounds__(256, 4) void line_rates_kernel(RateArgs a) {
                     cr[t] = V4{0, 0, 0, 0};
                     ci[t] = V4{0, 0, 0, 0};
                 }
-                for (int k0 = 0; k0 < Wp; k0 += 4) {
-                    const int k = k0 + lg;
-                    C bc[P];
-#pragma unroll
-                    for (int t = 0; t < P; ++t)
-                        bc[t] = (k < W && t0 + t < TN) ? Tst[k * Tk + (t0 + t) * 16] : C{0, 0};
-                    const C ph = sP[prow + k];
+                auto kstep = [&](const C (&bc)[P], const C ph) {
 #pragma unroll
                     for (int t = 0; t < P; ++t) {
                         cr[t] = mfma16(bc[t].x, ph.x, cr[t]);
@@ -846,6 +877,25 @@ __global__ __launch_bounds__(256, 4) void line_rates_kernel(RateArgs a) {
                     for (int t = 0; t < P; ++t) {
                         cr[t] = mfma16(bc[t].y, -ph.y, cr[t]);
                         ci[t] = mfma16(bc[t].x, ph.y, ci[t]);
+                    }
+                };
+                if constexpr (KS > 0) {
+#pragma unroll
+                    for (int ks = 0; ks < KS; ++ks) {
+                        if (4 * ks >= Wp) break;
+                        C bc[P];
+#pragma unroll
+                        for (int t = 0; t < P; ++t) bc[t] = t0 + t < TN ? tb[ks * TN + t0 + t] : C{0, 0};
+                        kstep(bc, sP[prow + 4 * ks + lg]);
+                    }
+                } else {
+                    for (int k0 = 0; k0 < Wp; k0 += 4) {
+                        const int k = k0 + lg;
+                        C bc[P];
+#pragma unroll
+                        for (int t = 0; t < P; ++t)
+                            bc[t] = (k < W && t0 + t < TN) ? Tst[k * Tk + (t0 + t) * 16] : C{0, 0};
+                        kstep(bc, sP[prow + k]);
                     }
                 }
                 // Y[slot li, sa] = sum_b X[slot li, sa, b] U_{k+q}[b, m]: products over
@@ -908,11 +958,11 @@ int line_rates_ncpad(int nm, int nW) {
     return 64 * (tn == 5 ? 6 : (tn == 7 ? 8 : tn));
 }
 
-template <int TN, class C>
+template <int TN, int KS, class C>
 static hipError_t go_line(const RateArgs& a, int nst, hipStream_t s) {
     const size_t shm = line_rates_lds(a.W, a.mesh.n0, a.nm, sizeof(C) == sizeof(cf));
     if (shm > 64 * 1024) return hipErrorInvalidValue;
-    hipError_t e = hipFuncSetAttribute((const void*)line_rates_kernel<TN, C>,
+    hipError_t e = hipFuncSetAttribute((const void*)line_rates_kernel<TN, KS, C>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) return e;
     const int64_t NL = (int64_t)a.mesh.n1 * a.mesh.n2;
@@ -932,7 +982,7 @@ static hipError_t go_line(const RateArgs& a, int nst, hipStream_t s) {
         b.live = a.live + (int64_t)s0 * a.mesh.n0 * NL;
         b.line_bands = a.line_bands + (int64_t)s0 * NL;
         b.n_states = ns;
-        hipLaunchKernelGGL((line_rates_kernel<TN, C>), dim3((unsigned)(groups * 8 * ns)), dim3(256),
+        hipLaunchKernelGGL((line_rates_kernel<TN, KS, C>), dim3((unsigned)(groups * 8 * ns)), dim3(256),
                            shm, s, b);
     }
     return hipGetLastError();
@@ -944,13 +994,14 @@ static hipError_t line_rates(const RateArgs& a, int nst, hipStream_t s) {
     if (a.n_qtiles != a.mesh.n1 * a.mesh.n2 || a.n_qtiles > 65535 || a.W > kMaxW ||
         line_rates_ncpad(a.nm, a.nW) != a.nc_pad || !a.live || !a.line_bands)
         return hipErrorInvalidValue;
+    const bool pre = a.W <= 8;  // T2 rows fit two K steps: registers
     switch (a.nc_pad / 64) {
-        case 1: return go_line<1, C>(a, nst, s);
-        case 2: return go_line<2, C>(a, nst, s);
-        case 3: return go_line<3, C>(a, nst, s);
-        case 4: return go_line<4, C>(a, nst, s);
-        case 6: return go_line<6, C>(a, nst, s);
-        case 8: return go_line<8, C>(a, nst, s);
+        case 1: return pre ? go_line<1, 2, C>(a, nst, s) : go_line<1, 0, C>(a, nst, s);
+        case 2: return pre ? go_line<2, 2, C>(a, nst, s) : go_line<2, 0, C>(a, nst, s);
+        case 3: return pre ? go_line<3, 2, C>(a, nst, s) : go_line<3, 0, C>(a, nst, s);
+        case 4: return pre ? go_line<4, 2, C>(a, nst, s) : go_line<4, 0, C>(a, nst, s);
+        case 6: return go_line<6, 0, C>(a, nst, s);
+        case 8: return go_line<8, 0, C>(a, nst, s);
         default: return hipErrorInvalidValue;
     }
 }
