@@ -174,8 +174,13 @@ def _sparse_re(s, seed, keep_frac):
 
 
 @pytest.mark.parametrize("case", ["toy", "ragged-5x6x7", "sparse-rp", "sparse-re", "c2-tiling",
-                                  "single-line", "nW16-sparse-re"])
+                                  "single-line", "nW16-sparse-re", "axis0-70", "rp-box-9",
+                                  "18-modes"])
 def test_mesh_sum_forms_match_oracle(lib, toy, case):
+    """Both full-mesh forms against the oracle.  The last three cases take the line
+    kernel's general path: more than 64 points on axis 0 (point lists in LDS, two
+    ballot chunks), an Rp box 9 wide (T2 read per K step, three K steps) and 18 modes
+    (six column tiles per wave, term items beyond one per thread)."""
     if case == "toy":
         s, mesh, par, ref = toy
     else:
@@ -189,6 +194,15 @@ def test_mesh_sum_forms_match_oracle(lib, toy, case):
             s, mesh = synth.small_system(73, n_wannier=16, n_atoms=5, r=1), (17, 3, 2)
         elif case == "nW16-sparse-re":  # the folded stage 1 over a sparse 5^3 Re box
             s, mesh = _sparse_re(synth.small_system(76, n_wannier=16, n_atoms=1, r=2), 7, 0.4), (6, 3, 4)
+        elif case == "axis0-70":
+            s, mesh = synth.small_system(78, n_wannier=3, n_atoms=1, r=2), (70, 2, 1)
+        elif case == "rp-box-9":
+            s = synth.make_system(79, 4, np.zeros((1, 3)), [1.0], r_h=1, r_e=1, r_p=4)
+            s, mesh = _sparse_rp(s, 8, 0.2), (4, 3, 2)
+            assert int(np.abs(s.rp).max()) == 4  # box width 9
+        elif case == "18-modes":
+            s, mesh = synth.small_system(80, n_wannier=4, n_atoms=6, r=1), (4, 3, 2)
+            assert 3 * s.mass.shape[0] == 18
         else:
             s, mesh = synth.small_system(74, n_wannier=3, n_atoms=1, r=2), (33, 1, 1)
         s.h_r *= 0.3
