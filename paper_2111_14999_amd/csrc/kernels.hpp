@@ -159,7 +159,9 @@ size_t re_axes_lds(int rmax, bool f32);
 // Columns sa*16 + b (nW <= 16), nc_pad = 64 TN with 4 TN >= nModes.
 // Live final bands of every (state, point) for the line kernel (nW <= 16),
 // their union per (state, line) and, added to n_live[0] and n_live[1], the
-// number of (state, line) pairs with a live band and of 16-point units.
+// number of (state, line) pairs with a live band and of 16-point units; the
+// partial sum a.partial[st, line] of a pair without a live band is set to 0
+// here (the line kernel skips such pairs).
 hipError_t launch_line_live(const RateArgs& a, int nst, uint32_t* live, uint32_t* line_bands,
                             uint32_t* n_live, hipStream_t s);
 hipError_t launch_line_rates(const RateArgs& a, int nst, hipStream_t s);

@@ -613,7 +613,8 @@ __device__ inline R rows4_reduce_scatter(R u0, R u1, R u2, R u3) {
 // block.  The thread also leaves
 // the union of its line's bands in line_bands and counts (one atomic per wave)
 // n_live[0] the lines with a live band and n_live[1] the units of 16 points the
-// line kernel will take (per band, its live points / 16 rounded up).
+// line kernel will take (per band, its live points / 16 rounded up), and writes
+// the zero partial sum of every pair without a live band.
 __global__ void line_live_kernel(RateArgs a, uint32_t* __restrict__ live,
                                  uint32_t* __restrict__ line_bands, uint32_t* __restrict__ n_live) {
     const Mesh mesh = a.mesh;
@@ -643,6 +644,7 @@ __global__ void line_live_kernel(RateArgs a, uint32_t* __restrict__ live,
             for (int m = 0; m < 16; ++m) cnt[m] += (bits >> m) & 1u;
         }
         line_bands[i] = u;
+        if (!u) a.partial[(int64_t)st * a.n_qtiles + line] = 0.0;  // the line kernel skips the pair
 #pragma unroll
         for (int m = 0; m < 16; ++m) units += (cnt[m] + 15) / 16;
     }
@@ -658,7 +660,9 @@ __global__ void line_live_kernel(RateArgs a, uint32_t* __restrict__ live,
 hipError_t launch_line_live(const RateArgs& a, int nst, uint32_t* live, uint32_t* line_bands,
                             uint32_t* n_live, hipStream_t s) {
     if (nst <= 0) return hipSuccess;
-    if (a.nW > 16 || !live || !line_bands || !n_live) return hipErrorInvalidValue;
+    if (a.nW > 16 || !live || !line_bands || !n_live || !a.partial ||
+        a.n_qtiles != a.mesh.n1 * a.mesh.n2)
+        return hipErrorInvalidValue;
     RateArgs b = a;
     b.n_states = nst;
     const int64_t n = (int64_t)nst * a.mesh.n1 * a.mesh.n2;
@@ -725,10 +729,7 @@ __global__ __launch_bounds__(256, 4) void line_rates_kernel(RateArgs a) {
     if (line >= NL) return;
     uint32_t bands = a.line_bands[(int64_t)st * NL + line];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (!bands) {
-        if (tid == 0) a.partial[(int64_t)st * a.n_qtiles + line] = 0.0;
-        return;
-    }
+    if (!bands) return;  // its partial sum is 0 (written with the masks)
     const int q1 = line / mesh.n2, q2 = line - q1 * mesh.n2;
     const int li = lane & 15, lg = lane >> 4;
     const int kmesh = a.st_kmesh[st];
