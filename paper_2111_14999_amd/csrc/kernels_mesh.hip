@@ -340,9 +340,16 @@ __device__ inline R row16_sum(R x) {
 // is a sum over the 16 lanes of a row.  G never leaves the registers; F is
 // written once per state.
 constexpr int kFoldWaves = 8;  // waves of the folded pair kernel sharing one T0 slab
+// Waves per SIMD the folded pair kernel is compiled for: with a box of at most 7
+// its FP64 slab (49 x 64 x 16 B) lets three work-groups share a CU, which needs
+// six waves per SIMD (80 VGPRs); wider boxes fit one work-group per CU anyway.
+template <int WT>
+constexpr int fold_waves_per_simd() {
+    return WT > 0 && WT <= 7 ? 6 : 2;
+}
 
 template <int WT, class C>
-__global__ __launch_bounds__(64 * kFoldWaves) void re_axis12_fold_kernel(
+__global__ __launch_bounds__(64 * kFoldWaves, fold_waves_per_simd<WT>()) void re_axis12_fold_kernel(
     const C* __restrict__ T0, int64_t NC, int Wr, const cd* __restrict__ P1,
     const cd* __restrict__ P2, const int32_t* __restrict__ pair_k1,
     const int32_t* __restrict__ pair_off, const int32_t* __restrict__ kp_off,
