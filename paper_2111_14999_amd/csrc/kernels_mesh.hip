@@ -622,7 +622,7 @@ __device__ inline R rows4_reduce_scatter(R u0, R u1, R u2, R u3) {
 // n_live[0] the lines with a live band and n_live[1] the units of 16 points the
 // line kernel will take (per band, its live points / 16 rounded up), and writes
 // the zero partial sum of every pair without a live band.
-__global__ void line_live_kernel(RateArgs a, uint32_t* __restrict__ live,
+__global__ __launch_bounds__(256, 8) void line_live_kernel(RateArgs a, uint32_t* __restrict__ live,
                                  uint32_t* __restrict__ line_bands, uint32_t* __restrict__ n_live) {
     const Mesh mesh = a.mesh;
     const int N0 = mesh.n0, NL = mesh.n1 * mesh.n2, nW = a.nW;
