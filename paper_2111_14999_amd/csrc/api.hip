@@ -928,9 +928,13 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                                       reinterpret_cast<const cd*>(Fbuf) + (int64_t)sb * rp_pad * nc_pad,
                                       rp_pad, nc_pad, T.box_rp, rmax_p, mesh, T.Pax, nn, lineany,
                                       reinterpret_cast<cd*>(T1buf), reinterpret_cast<cd*>(T2buf), s));
-                    // F read once, T1 written and read once; T2 written for the live lines
+                    // F read once, T2 written for the live lines; T1 written and read once
+                    // unless both axes ran in one pass
                     const double ab = (double)g_elem * nm * nW;
-                    ta.done(ab * nn * ((double)n_rp + 2.0 * Wbox * Wbox * mesh.n2), nl, ab * Wbox);
+                    const double t1_rw = axis_transforms_fused(rmax_p, nc_pad, lowp)
+                                             ? 0.0
+                                             : 2.0 * Wbox * Wbox * mesh.n2;
+                    ta.done(ab * nn * ((double)n_rp + t1_rw), nl, ab * Wbox);
                     Timer tl(h, s, "line_rates");
                     if (lowp)
                         HIPCHK(h, launch_line_rates_f32(rb, nn, s));

@@ -110,6 +110,10 @@ hipError_t launch_axis_phases(Mesh m, int rmax, cd* P, hipStream_t s);
 hipError_t launch_axis_transforms(const cd* F, int rp_pad, int nc_pad, const int32_t* box_rp,
                                   int rmax, Mesh m, const cd* P, int nst, const uint32_t* line_any,
                                   cd* T1, cd* T2, hipStream_t s);
+// With line_any set, a box of width 1, 3, 5, 7 or 9 whose F slab (W^2 x 64 columns)
+// fits 64 KB of LDS and nc_pad % 64 == 0, both axes run in one pass and T1 is not
+// used (T1 may then be null); this tells which route a call takes.
+bool axis_transforms_fused(int rmax, int nc_pad, bool f32);
 hipError_t launch_axis_transforms_f32(const cf* F, int rp_pad, int nc_pad, const int32_t* box_rp,
                                       int rmax, Mesh m, const cd* P, int nst,
                                       const uint32_t* line_any, cf* T1, cf* T2, hipStream_t s);

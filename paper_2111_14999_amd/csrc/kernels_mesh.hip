@@ -135,10 +135,88 @@ __global__ __launch_bounds__(256) void axis_mid_kernel(const C* __restrict__ in,
     }
 }
 
+// Both Rp axes in one pass: a work-group takes one (state, R0, 64-column block),
+// stages its F rows (R1, R2) in LDS and, for each q2 of its share, forms
+//   T1[R1] = sum_R2 P2[q2, R2] F[st, box_rp[(R0 W + R1) W + R2], c]
+// in registers, then T2[st, R0, q1 N2 + q2, c] = sum_R1 P1[q1, R1] T1[R1] for the
+// live lines.  The sums run in the same order as axis2 then axis_mid, so the two
+// routes agree bit for bit; T1 never goes through HBM.  Wave g of the work-group
+// (64 lanes, one column each) takes q2 = g, g + kAxisWaves, ...  Eight waves
+// share one slab and the kernel is compiled for six waves per SIMD (80 VGPRs), so
+// that three work-groups (three FP64 slabs of a box 7 wide) fill a CU.
+constexpr int kAxisWaves = 8;
+
+template <int WT, class C>
+__global__ __launch_bounds__(64 * kAxisWaves, 6) void axis_fused_kernel(const C* __restrict__ F, int rp_pad,
+                                                         int nc_pad, const int32_t* __restrict__ box_rp,
+                                                         Mesh m, const cd* __restrict__ P1,
+                                                         const cd* __restrict__ P2,
+                                                         const uint32_t* __restrict__ line_any,
+                                                         C* __restrict__ T2) {
+    constexpr int W = WT;
+    extern __shared__ char smem_raw[];
+    C* sF = reinterpret_cast<C*>(smem_raw);  // [W * W][64]
+    const int ncb = nc_pad / 64;
+    int64_t b = blockIdx.x;
+    const int cb = (int)(b % ncb);
+    b /= ncb;
+    const int r0 = (int)(b % W);
+    const int st = (int)(b / W);
+    const int tid = threadIdx.x, cc = tid & 63, g = tid >> 6;
+    const int c = cb * 64 + cc;
+    const C* Fs = F + (int64_t)st * rp_pad * nc_pad + c;
+    for (int i = g; i < W * W; i += kAxisWaves) {
+        const int row = box_rp[r0 * W * W + i];
+        sF[i * 64 + cc] = row >= 0 ? Fs[(int64_t)row * nc_pad] : C{0, 0};
+    }
+    __syncthreads();
+    const int N1 = m.n1, N2 = m.n2, NL = N1 * N2;
+    const uint32_t* fl = line_any + (int64_t)st * NL;
+    C* out = T2 + ((int64_t)st * W + r0) * NL * nc_pad + c;
+    for (int q2 = g; q2 < N2; q2 += kAxisWaves) {
+        // the slab is read from LDS per q2, not held in registers across the loop
+        asm volatile("" ::: "memory");
+        C t1[W];
+        const cd* Pq = P2 + q2 * W;
+#pragma unroll
+        for (int r1 = 0; r1 < W; ++r1) {
+            C acc = {0, 0};
+#pragma unroll
+            for (int r2 = 0; r2 < W; ++r2) acc = cfma(to_c<C>(Pq[r2]), sF[(r1 * W + r2) * 64 + cc], acc);
+            t1[r1] = acc;
+        }
+        for (int q1 = 0; q1 < N1; ++q1) {
+            const int line = q1 * N2 + q2;
+            if (!fl[line]) continue;
+            const cd* Pn = P1 + q1 * W;
+            C acc = {0, 0};
+#pragma unroll
+            for (int r1 = 0; r1 < W; ++r1) acc = cfma(to_c<C>(Pn[r1]), t1[r1], acc);
+            out[(int64_t)line * nc_pad] = acc;
+        }
+    }
+}
+
 template <int WT, class C>
 static hipError_t go_axes(const C* F, int rp_pad, int nc_pad, const int32_t* box_rp, int W,
                           Mesh m, const cd* P1, const cd* P2, int nst, const uint32_t* line_any,
                           C* T1, C* T2, hipStream_t s) {
+    // one pass where the box is a compile-time width, the F slab fits 64 KB of LDS
+    // and the columns come in 64-wide blocks
+    if constexpr (WT > 0) {
+        const size_t shm = (size_t)WT * WT * 64 * sizeof(C);
+        if (line_any && shm <= 64 * 1024 && nc_pad % 64 == 0) {
+            hipError_t e = hipFuncSetAttribute((const void*)axis_fused_kernel<WT, C>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+            if (e != hipSuccess) return e;
+            const int64_t groups = (int64_t)nst * WT * (nc_pad / 64);
+            if (groups > 2147483647LL) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((axis_fused_kernel<WT, C>), dim3((unsigned)groups), dim3(64 * kAxisWaves),
+                               shm, s,
+                               F, rp_pad, nc_pad, box_rp, m, P1, P2, line_any, T2);
+            return hipGetLastError();
+        }
+    }
     hipLaunchKernelGGL((axis2_kernel<WT, C>), dim3(gridm((int64_t)nst * W * W * nc_pad, 256)),
                        dim3(256), 0, s, F, rp_pad, nc_pad, box_rp, W, m.n2, P2, nst, T1);
     hipError_t e = hipGetLastError();
@@ -167,6 +245,13 @@ static hipError_t axis_transforms(const C* F, int rp_pad, int nc_pad, const int3
         case 9: return go_axes<9, C>(F, rp_pad, nc_pad, box_rp, W, m, P1, P2, nst, line_any, T1, T2, s);
         default: return go_axes<0, C>(F, rp_pad, nc_pad, box_rp, W, m, P1, P2, nst, line_any, T1, T2, s);
     }
+}
+
+bool axis_transforms_fused(int rmax, int nc_pad, bool f32) {
+    const int W = 2 * rmax + 1;
+    const bool listed = W == 1 || W == 3 || W == 5 || W == 7 || W == 9;  // compile-time widths
+    return listed && (size_t)W * W * 64 * (f32 ? sizeof(cf) : sizeof(cd)) <= 64 * 1024 &&
+           nc_pad % 64 == 0;
 }
 
 hipError_t launch_axis_transforms(const cd* F, int rp_pad, int nc_pad, const int32_t* box_rp,
