@@ -723,22 +723,45 @@ __global__ __launch_bounds__(256, 8) void line_live_kernel(RateArgs a, uint32_t*
         const int64_t kq12 = ((k1i + q1) % mesh.n1) * mesh.n2 + (k2i + q2) % mesh.n2;
         const double eps_n = a.eps[(int64_t)kmesh * nW + a.st_band[st]];
         const double lim = 27.5 * a.sigma + *a.wmax;
-        int cnt[16] = {};
+        uint32_t cnt2[8] = {};  // live points per band, two 16-bit counts a word (N0 <= 1024)
         uint32_t* out = live + i * N0;
-#pragma unroll 4
-        for (int q0 = 0; q0 < N0; ++q0) {
+        // band values two at a time (16-byte loads from an even band; rows are
+        // nW doubles, nW even here); masks four at a time where N0 % 4 == 0
+        const bool pairs = (nW & 1) == 0;
+        auto bits_of = [&](int q0) {
             const double* ek = a.eps + ((int64_t)((k0i + q0) % N0) * NL + kq12) * nW;
             uint32_t bits = 0;
-            for (int m = mlo; m <= mhi; ++m) bits |= (uint32_t)(fabs(eps_n - ek[m]) <= lim) << m;
-            out[q0] = bits;
+            if (pairs) {
+                for (int m = mlo & ~1; m <= mhi; m += 2) {
+                    const double2 e2 = *reinterpret_cast<const double2*>(ek + m);
+                    bits |= (uint32_t)(m >= mlo && fabs(eps_n - e2.x) <= lim) << m;
+                    bits |= (uint32_t)(m + 1 <= mhi && fabs(eps_n - e2.y) <= lim) << (m + 1);
+                }
+            } else {
+                for (int m = mlo; m <= mhi; ++m) bits |= (uint32_t)(fabs(eps_n - ek[m]) <= lim) << m;
+            }
             u |= bits;
 #pragma unroll
-            for (int m = 0; m < 16; ++m) cnt[m] += (bits >> m) & 1u;
+            for (int m = 0; m < 16; ++m) cnt2[m >> 1] += ((bits >> m) & 1u) << (16 * (m & 1));
+            return bits;
+        };
+        if ((N0 & 3) == 0) {
+            for (int q0 = 0; q0 < N0; q0 += 4) {
+                uint4 v;
+                v.x = bits_of(q0);
+                v.y = bits_of(q0 + 1);
+                v.z = bits_of(q0 + 2);
+                v.w = bits_of(q0 + 3);
+                *reinterpret_cast<uint4*>(out + q0) = v;
+            }
+        } else {
+#pragma unroll 4
+            for (int q0 = 0; q0 < N0; ++q0) out[q0] = bits_of(q0);
         }
         line_bands[i] = u;
         if (!u) a.partial[(int64_t)st * a.n_qtiles + line] = 0.0;  // the line kernel skips the pair
 #pragma unroll
-        for (int m = 0; m < 16; ++m) units += (cnt[m] + 15) / 16;
+        for (int m = 0; m < 16; ++m) units += (((cnt2[m >> 1] >> (16 * (m & 1))) & 0xFFFFu) + 15) / 16;
     }
     const uint64_t bal = __ballot(u != 0);
 #pragma unroll
