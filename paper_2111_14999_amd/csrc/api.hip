@@ -403,8 +403,11 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                            (double)BK * nW * rp_pad * nc_pad * f_elem > 8e9))
             BK /= 2;
         const int BQ = 16 * tq;
-        // states per factorised sub-batch: T1 + T2 of a sub-batch stay under 4 GB
-        const size_t t12_state = ((size_t)Wbox * Wbox * mesh.n2 + (size_t)Wbox * NL) * nc_pad * g_elem;
+        // states per factorised sub-batch: T1 + T2 of a sub-batch stay under 4 GB (T2
+        // alone where both Rp axes run in one pass and T1 is not used)
+        const bool axes_fused = factored && axis_transforms_fused(rmax_p, nc_pad, lowp);
+        const size_t t12_state =
+            ((axes_fused ? 0 : (size_t)Wbox * Wbox * mesh.n2) + (size_t)Wbox * NL) * nc_pad * g_elem;
         const int n0_line = mesh.n0;
         const int nsb = factored ? (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)BK * nW,
                                                       (int64_t)(4e9 / (double)t12_state)))
@@ -744,8 +747,9 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
         char* Gbuf = fold_fused ? nullptr : ar.take<char>((size_t)BK * NC2 * g_elem);
         char* Fbuf = ar.take<char>((size_t)max_states * rp_pad * nc_pad * f_elem);
         double* partial = ar.take<double>((size_t)max_states * n_qtiles);
-        char* T1buf = factored ? ar.take<char>((size_t)nsb * Wbox * Wbox * mesh.n2 * nc_pad * g_elem)
-                               : nullptr;
+        char* T1buf = factored && !axes_fused
+                          ? ar.take<char>((size_t)nsb * Wbox * Wbox * mesh.n2 * nc_pad * g_elem)
+                          : nullptr;
         char* T2buf = factored ? ar.take<char>((size_t)nsb * Wbox * NL * nc_pad * g_elem) : nullptr;
         uint32_t* livebuf = factored ? ar.take<uint32_t>((size_t)nsb * NL * n0_line) : nullptr;
         uint32_t* lineany = factored ? ar.take<uint32_t>((size_t)nsb * NL) : nullptr;
