@@ -403,15 +403,17 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                            (double)BK * nW * rp_pad * nc_pad * f_elem > 8e9))
             BK /= 2;
         const int BQ = 16 * tq;
-        // states per factorised sub-batch: T1 + T2 of a sub-batch stay under 8 GB (T2
-        // alone where both Rp axes run in one pass and T1 is not used); larger
-        // sub-batches mean fewer, longer launches of the axis and line kernels
+        // states per factorised sub-batch: T1 + T2 of a sub-batch stay under 16 GB or a
+        // quarter of the workspace budget, whichever is less (T2 alone where both Rp
+        // axes run in one pass and T1 is not used); larger sub-batches mean fewer,
+        // longer launches of the axis and line kernels
         const bool axes_fused = factored && axis_transforms_fused(rmax_p, nc_pad, lowp);
         const size_t t12_state =
             ((axes_fused ? 0 : (size_t)Wbox * Wbox * mesh.n2) + (size_t)Wbox * NL) * nc_pad * g_elem;
         const int n0_line = mesh.n0;
+        const double sub_cap = std::min(16e9, 0.25 * (double)h->budget);
         const int nsb = factored ? (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)BK * nW,
-                                                      (int64_t)(8e9 / (double)t12_state)))
+                                                      (int64_t)(sub_cap / (double)t12_state)))
                                  : 0;
 
         // q-list lengths (host) for the tile count
