@@ -189,7 +189,9 @@ phoebe_status phoebe_gpu_interp_g(void *handle, const phoebe_system *sys,
  * (n0 planes of (2 r_e + 1)^2 n_rp nModes nW^2 elements; 39 GB for a 40^3 mesh,
  * nW = 16, 15 modes, 343 Re and Rp in FP64), so g(Re,Rp) is read once per call;
  * under a smaller budget it is kept per batch and g is read once per batch.  The
- * results are the same bit for bit.
+ * states are then taken in sub-batches whose Rp-axis intermediates stay under
+ * 16 GB or a quarter of the budget, whichever is less.  The results are the
+ * same bit for bit.
  * Errors: PHOEBE_E_INVALID (mesh < 1, sigma <= 0, kT <= 0, enum, pointers),
  * PHOEBE_E_NOMEM, PHOEBE_E_UNSUPPORTED (nW > 32, nModes > 32), PHOEBE_E_DEVICE. */
 phoebe_status phoebe_gpu_scatter_rates(void *handle, const phoebe_system *sys,
