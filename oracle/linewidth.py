@@ -1,0 +1,82 @@
+"""Phonon scattering rate from the electron-phonon interaction, P^{el-ph}_{q nu} (FP64).
+
+Follows Transport Methods, phonon BTE: the el-ph term on the diagonal of the
+rescaled phonon scattering matrix A,
+
+  P_{q nu} = -(2 pi / (N_k hbar)) n_{q nu} (n_{q nu} + 1)
+             sum_{k b b'} |g_{b b' nu}(k, q)|^2 (f_{k b} - f_{k+q, b'})
+             delta(eps_{k b} - eps_{k+q, b'} - hbar omega_{q nu}),
+
+with the paper's replacement f_{k b} - f_{k+q, b'} ~ (df/d eps)_{k b} hbar omega_{q nu}.
+Since -df/d eps = f (1 - f) / kT this is
+
+  P_{q nu} = (2 pi / N_k) n (n + 1) hbar omega_{q nu}
+             sum_{k, b, b'} |g_{b b' nu}(k, q)|^2 f_{k b} (1 - f_{k b}) / kT
+             delta(eps_{k b} - eps_{k+q, b'} - hbar omega_{q nu}).
+
+Readings taken (besides those of ``oracle.rates`` and ``oracle.coupling``):
+* hbar = 1: P is an energy in eV, like Gamma;
+* the sum over k runs over every point of the k mesh, N_k its size; b runs over
+  the states inside the energy window (the electronic states the calculation
+  keeps), b' over all bands, as m does in the electron lifetime;
+* g_{b b' nu}(k, q) has b at k and b' at k + q, the index order of the
+  electron lifetime's coupling;
+* modes with hbar omega < omega_min are left out (P = 0 there);
+* delta is the Gaussian of the Dirac delta and Smearing section with the given
+  sigma.
+"""
+
+import numpy as np
+
+from .bands import bose_einstein, fermi_dirac
+from .coupling import coupling_k_rp, phonon_length
+from .mesh import sum_index_table
+from .rates import gaussian_delta, kept_points, mesh_tables, window_mask
+
+
+def phonon_linewidth(system, mesh, mu, kT, sigma, win_lo, win_hi, omega_min=1e-4, tables=None,
+                     q_chunk=4096, k_batch=8):
+    """P^{el-ph}_{q nu} at every q of the mesh (the k and the q mesh are the same mesh).
+
+    Returns dict(P [N_q, nModes] eV, k_idx (the kept k summed over), tables).
+    """
+    if tables is None:
+        tables = mesh_tables(system, mesh)
+    eps, U, omega, z = tables["eps"], tables["U"], tables["omega"], tables["z"]
+    pts = tables["points"]
+    N = pts.shape[0]
+    nm = system.n_modes
+    mask_all = window_mask(eps, win_lo, win_hi)
+    k_idx = kept_points(mask_all)
+    f_all = fermi_dirac(eps, mu, kT)
+    mdf = f_all * (1.0 - f_all) / kT                                  # -df/d eps
+    active = omega >= omega_min
+    l_all = phonon_length(omega, system.mass, omega_min)
+    zl_all = z * np.repeat(l_all, 3, axis=1)                          # [N, sa, nu]
+    rp = np.asarray(system.rp, dtype=np.float64)
+
+    # S[q, nu] = sum over kept (k, b) and all b' of |g|^2 (-f'_{k b}) delta(...)
+    S = np.zeros((N, nm))
+    for b0 in range(0, k_idx.size, k_batch):
+        kb = k_idx[b0:b0 + k_batch]
+        f1 = coupling_k_rp(pts[kb], system.re, system.g_rr)          # [b, Rp, sa, a, b]
+        for t, ik in enumerate(kb):
+            nlist = np.nonzero(mask_all[ik])[0]
+            Uh = np.conj(U[ik][:, nlist]).T                             # [n, a]
+            ft = np.einsum("na,rsab->rsnb", Uh, f1[t])
+            ftf = ft.reshape(ft.shape[0], -1)
+            kq_all = sum_index_table([ik], mesh)[0]
+            for c0 in range(0, N, q_chunk):
+                qs = np.arange(c0, min(N, c0 + q_chunk))
+                ph = np.exp(2j * np.pi * (pts[qs] @ rp.T))             # [q, Rp]
+                X = (ph @ ftf).reshape((qs.size,) + ft.shape[1:])      # [q, sa, n, b]
+                kq = kq_all[qs]
+                Y = X @ U[kq][:, None, :, :]                            # [q, sa, n, m]
+                g = np.einsum("qsnm,qsv->qnvm", Y, zl_all[qs])          # [q, n, nu, m]
+                g2 = (g * np.conj(g)).real
+                for j, n in enumerate(nlist):
+                    x = eps[ik, n] - eps[kq][:, None, :] - omega[qs][:, :, None]   # [q, nu, m]
+                    S[qs] += mdf[ik, n] * np.sum(g2[:, j] * gaussian_delta(x, sigma), axis=-1)
+    nb = np.where(active, bose_einstein(np.where(active, omega, 1.0), kT), 0.0)
+    P = np.where(active, (2.0 * np.pi / N) * nb * (nb + 1.0) * omega * S, 0.0)
+    return dict(P=P, k_idx=k_idx, tables=tables)
