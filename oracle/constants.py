@@ -29,3 +29,7 @@ KB_EV = KB_SI / EV_SI
 
 def kT_of(temperature_k: float) -> float:
     return KB_EV * temperature_k
+
+EPS0_SI = 8.8541878128e-12      # F/m
+#: e^2 / (4 pi eps0) expressed in eV A (the Coulomb constant of the polar coupling)
+E2_4PIEPS0 = EV_SI / (4.0 * math.pi * EPS0_SI * ANGSTROM_SI)

@@ -92,9 +92,19 @@ def rotate_to_bloch(G, U_k, U_kq, z, l):
     return np.einsum("...snm,...sv->...vnm", Y, w)
 
 
+def polar_params(system):
+    """(born, eps_inf, alpha, g_max) of a polar system, or None (no long-range term)."""
+    born = getattr(system, "born", None)
+    if born is None:
+        return None
+    return born, system.eps_inf, system.ewald_alpha, system.g_max
+
+
 def coupling(k, q, system, omega_min=1e-4):
     """Interpolated el-ph coupling g(k, q) for every pair of the k and q lists.
 
+    For a polar system (one carrying Born charges) g is the sum of the
+    interpolated short-range part and the long-range part of ``oracle.polar``.
     Returns dict with g [nk, nq, nModes, nW, nW] (index order nu, n at k, m at
     k+q), eps_k [nk, nW], eps_kq [nk, nq, nW], omega_q [nq, nModes].
     """
@@ -110,4 +120,9 @@ def coupling(k, q, system, omega_min=1e-4):
     l = phonon_length(omega, system.mass, omega_min)
     G = coupling_wannier_gauge(k, q, system.re, system.rp, system.g_rr)
     g = rotate_to_bloch(G, U_k[:, None], U_kq, z[None], l[None])
+    pp = polar_params(system)
+    if pp is not None:
+        from .polar import polar_coupling, polar_factor
+        L = polar_factor(q, z, l, *pp)                                # [nq, nu]
+        g = g + polar_coupling(U_k[:, None], U_kq, L[None])
     return dict(g=g, eps_k=eps_k, eps_kq=eps_kq, omega_q=omega)

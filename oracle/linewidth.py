@@ -29,8 +29,9 @@ Readings taken (besides those of ``oracle.rates`` and ``oracle.coupling``):
 import numpy as np
 
 from .bands import bose_einstein, fermi_dirac
-from .coupling import coupling_k_rp, phonon_length
+from .coupling import coupling_k_rp, phonon_length, polar_params
 from .mesh import sum_index_table
+from .polar import polar_factor
 from .rates import gaussian_delta, kept_points, mesh_tables, window_mask
 
 
@@ -54,6 +55,9 @@ def phonon_linewidth(system, mesh, mu, kT, sigma, win_lo, win_hi, omega_min=1e-4
     l_all = phonon_length(omega, system.mass, omega_min)
     zl_all = z * np.repeat(l_all, 3, axis=1)                          # [N, sa, nu]
     rp = np.asarray(system.rp, dtype=np.float64)
+    # polar systems: g = g^S + i L(q, nu) [U_k^dagger U_{k+q}]_{n m} (oracle.polar)
+    pp = polar_params(system)
+    L_all = polar_factor(pts, z, l_all, *pp) if pp is not None else None   # [N, nu]
 
     # S[q, nu] = sum over kept (k, b) and all b' of |g|^2 (-f'_{k b}) delta(...)
     S = np.zeros((N, nm))
@@ -73,6 +77,9 @@ def phonon_linewidth(system, mesh, mu, kT, sigma, win_lo, win_hi, omega_min=1e-4
                 kq = kq_all[qs]
                 Y = X @ U[kq][:, None, :, :]                            # [q, sa, n, m]
                 g = np.einsum("qsnm,qsv->qnvm", Y, zl_all[qs])          # [q, n, nu, m]
+                if L_all is not None:
+                    O = Uh[None] @ U[kq]                                # [q, n, m]
+                    g = g + 1j * L_all[qs][:, None, :, None] * O[:, :, None, :]
                 g2 = (g * np.conj(g)).real
                 for j, n in enumerate(nlist):
                     x = eps[ik, n] - eps[kq][:, None, :] - omega[qs][:, :, None]   # [q, nu, m]

@@ -36,8 +36,9 @@ import numpy as np
 
 from .bands import (bose_einstein, electron_bands, fermi_dirac,
                     phonon_modes)
-from .coupling import coupling_k_rp, phonon_length
+from .coupling import coupling_k_rp, phonon_length, polar_params
 from .mesh import mesh_points, sum_index_table
+from .polar import polar_factor
 
 
 def gaussian_delta(x, sigma):
@@ -110,6 +111,9 @@ def scattering_rates(system, mesh, mu, kT, sigma, win_lo, win_hi, omega_min=1e-4
     l_all = phonon_length(omega, system.mass, omega_min)              # [N, nat, nu]
     zl_all = z * np.repeat(l_all, 3, axis=1)                          # [N, sa, nu]
     rp = np.asarray(system.rp, dtype=np.float64)
+    # polar systems: g = g^S + i L(q, nu) [U_k^dagger U_{k+q}]_{n m} (oracle.polar)
+    pp = polar_params(system)
+    L_all = polar_factor(pts, z, l_all, *pp) if pp is not None else None   # [N, nu]
 
     gamma = np.zeros((nk, nW))
     band_mask = mask_all[k_idx]
@@ -140,6 +144,9 @@ def scattering_rates(system, mesh, mu, kT, sigma, win_lo, win_hi, omega_min=1e-4
                 kq = kq_all[qs]
                 Y = X @ U[kq][:, None, :, :]                            # [q, sa, n, m]
                 g = np.einsum("qsnm,qsv->qnvm", Y, zl_all[qs])          # [q, n, nu, m]
+                if L_all is not None:
+                    O = Uh[None] @ U[kq]                                # [q, n, m]
+                    g = g + 1j * L_all[qs][:, None, :, None] * O[:, :, None, :]
                 g2 = (g * np.conj(g)).real
                 for j, n in enumerate(nlist):
                     terms = rate_terms(g2[:, j], eps[ik, n], eps[kq], f_all[kq],

@@ -20,4 +20,5 @@ from .systems import (  # noqa: F401
     random_structure,
     config_c4_specs,
     config_c4,
+    add_polar,
 )

@@ -36,7 +36,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 # tags that separate the random streams of one system
-_TAG_MASS, _TAG_SPRING, _TAG_H, _TAG_G, _TAG_POS = 11, 12, 13, 14, 15
+_TAG_MASS, _TAG_SPRING, _TAG_H, _TAG_G, _TAG_POS, _TAG_POLAR = 11, 12, 13, 14, 15, 16
 
 
 def _rng(seed: int, tag: int, block: int = 0) -> np.random.Generator:
@@ -66,6 +66,13 @@ class System:
     rp: np.ndarray                   # [n_rp, 3] int32
     g_rr: np.ndarray                 # [n_re, n_rp, 3nat, nW, nW] complex128, eV/A
     meta: dict = field(default_factory=dict)
+    # polar crystals only (None otherwise): Born effective charges [nat, 3, 3] (e),
+    # high-frequency dielectric tensor [3, 3], the Gaussian damping parameter of
+    # the sum over G (A^-2) and the half-width of the integer G box
+    born: np.ndarray = None
+    eps_inf: np.ndarray = None
+    ewald_alpha: float = 0.0
+    g_max: int = 0
 
     @property
     def n_modes(self) -> int:
@@ -354,3 +361,27 @@ def config_c4(spec: dict, threads: int = 8) -> System:
                     r_e=spec["r_g"], r_p=spec["r_g"], threads=threads)
     s.meta["mesh"] = (spec["mesh"],) * 3
     return s
+
+
+def add_polar(system: System, seed: int, alpha: float = 5.0, g_max: int = 3,
+              eps_scale: float = 4.0) -> System:
+    """Give a system Born effective charges and a dielectric tensor (in place).
+
+    Z*_s = diag(d_s) + 0.3 N(0,1)^{3x3} with d_s ~ U[1, 3] and alternating
+    signs, then the mean over atoms removed (charge neutrality, sum_s Z*_s = 0);
+    eps_inf = eps_scale I + A A^T / 6 with A ~ N(0,1)^{3x3} (symmetric positive
+    definite).  alpha and g_max set the damping and the box of the G sum.
+    """
+    rng = _rng(seed, _TAG_POLAR)
+    nat = system.n_atoms
+    d = rng.uniform(1.0, 3.0, size=nat) * np.where(np.arange(nat) % 2 == 0, 1.0, -1.0)
+    Z = np.stack([np.diag(np.full(3, d[s_])) for s_ in range(nat)]) + \
+        0.3 * rng.standard_normal((nat, 3, 3))
+    Z -= Z.mean(axis=0, keepdims=True)
+    A = rng.standard_normal((3, 3))
+    system.born = np.ascontiguousarray(Z)
+    system.eps_inf = eps_scale * np.eye(3) + A @ A.T / 6.0
+    system.ewald_alpha = float(alpha)
+    system.g_max = int(g_max)
+    system.meta.update(polar=True)
+    return system

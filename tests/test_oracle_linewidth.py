@@ -133,3 +133,41 @@ def test_nonnegative_and_acoustic_modes_at_gamma():
     assert np.max(P) > 0
     # q = 0: three acoustic modes below omega_min, left out
     assert np.all(P[0, :3] == 0.0) and np.all(P[0, 3:] > 0)
+
+
+def test_polar_system_against_explicit_coupling_sum():
+    """P of a polar system as an explicit sum over mesh pairs of oracle.coupling's g."""
+    from oracle import coupling, mesh as omesh
+    s = synth.add_polar(synth.small_system(seed=35, n_wannier=2, n_atoms=2, r=1), seed=35,
+                        alpha=3.0, g_max=1, eps_scale=2.0)
+    s.h_r = s.h_r * 0.05
+    mesh = (3, 2, 2)
+    kT, sigma, wmin = KB * 300.0, 0.05, 1e-4
+    t = rates.mesh_tables(s, mesh)
+    mu = float(np.median(t["eps"]))
+    lo, hi = mu - 0.2, mu + 0.2
+    out = linewidth.phonon_linewidth(s, mesh, mu, kT, sigma, lo, hi, wmin, tables=t)
+    pts = omesh.mesh_points(mesh)
+    N = pts.shape[0]
+    ref = np.zeros((N, s.n_modes))
+    for ik in range(N):
+        c = coupling.coupling(pts[ik:ik + 1], pts, s, omega_min=wmin)
+        ek = c["eps_k"][0]
+        for iq in range(N):
+            for v in range(s.n_modes):
+                w = c["omega_q"][iq, v]
+                if w < wmin:
+                    continue
+                for n in range(s.n_wannier):
+                    if not (lo < ek[n] < hi):
+                        continue
+                    fn = 1.0 / (math.exp((ek[n] - mu) / kT) + 1.0)
+                    for m in range(s.n_wannier):
+                        d = math.exp(-((ek[n] - c["eps_kq"][0, iq, m] - w) / sigma) ** 2) / (
+                            math.sqrt(math.pi) * sigma)
+                        ref[iq, v] += abs(c["g"][0, iq, v, n, m]) ** 2 * fn * (1 - fn) / kT * d
+    om = t["omega"]
+    nb = np.where(om >= wmin, 1.0 / np.expm1(np.maximum(om, wmin) / kT), 0.0)
+    ref *= 2 * math.pi / N * nb * (nb + 1) * om
+    assert np.max(ref) > 0
+    assert np.max(np.abs(out["P"] - ref)) < 1e-9 * np.max(ref)
