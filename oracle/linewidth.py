@@ -32,12 +32,15 @@ from .bands import bose_einstein, fermi_dirac
 from .coupling import coupling_k_rp, phonon_length, polar_params
 from .mesh import sum_index_table
 from .polar import polar_factor
-from .rates import gaussian_delta, kept_points, mesh_tables, window_mask
+from .rates import gaussian_delta, kept_points, mesh_tables, transition_sigma, window_mask
+from .velocity import group_velocities
 
 
 def phonon_linewidth(system, mesh, mu, kT, sigma, win_lo, win_hi, omega_min=1e-4, tables=None,
-                     q_chunk=4096, k_batch=8):
+                     q_chunk=4096, k_batch=8, adaptive=None):
     """P^{el-ph}_{q nu} at every q of the mesh (the k and the q mesh are the same mesh).
+
+    adaptive: as in ``oracle.rates.scattering_rates`` (a smearing width per transition).
 
     Returns dict(P [N_q, nModes] eV, k_idx (the kept k summed over), tables).
     """
@@ -58,6 +61,7 @@ def phonon_linewidth(system, mesh, mu, kT, sigma, win_lo, win_hi, omega_min=1e-4
     # polar systems: g = g^S + i L(q, nu) [U_k^dagger U_{k+q}]_{n m} (oracle.polar)
     pp = polar_params(system)
     L_all = polar_factor(pts, z, l_all, *pp) if pp is not None else None   # [N, nu]
+    v_all = group_velocities(pts, system.rh, system.h_r)[1] if adaptive is not None else None
 
     # S[q, nu] = sum over kept (k, b) and all b' of |g|^2 (-f'_{k b}) delta(...)
     S = np.zeros((N, nm))
@@ -83,7 +87,8 @@ def phonon_linewidth(system, mesh, mu, kT, sigma, win_lo, win_hi, omega_min=1e-4
                 g2 = (g * np.conj(g)).real
                 for j, n in enumerate(nlist):
                     x = eps[ik, n] - eps[kq][:, None, :] - omega[qs][:, :, None]   # [q, nu, m]
-                    S[qs] += mdf[ik, n] * np.sum(g2[:, j] * gaussian_delta(x, sigma), axis=-1)
+                    sig = transition_sigma(sigma, adaptive, v_all, ik, n, kq, mesh)
+                    S[qs] += mdf[ik, n] * np.sum(g2[:, j] * gaussian_delta(x, sig), axis=-1)
     nb = np.where(active, bose_einstein(np.where(active, omega, 1.0), kT), 0.0)
     P = np.where(active, (2.0 * np.pi / N) * nb * (nb + 1.0) * omega * S, 0.0)
     return dict(P=P, k_idx=k_idx, tables=tables)

@@ -39,6 +39,7 @@ from .bands import (bose_einstein, electron_bands, fermi_dirac,
 from .coupling import coupling_k_rp, phonon_length, polar_params
 from .mesh import mesh_points, sum_index_table
 from .polar import polar_factor
+from .velocity import adaptive_sigma, group_velocities
 
 
 def gaussian_delta(x, sigma):
@@ -82,9 +83,25 @@ def rate_terms(g2, eps_n, eps_m, f_m, omega, n_b, sigma, active):
     return term.sum(axis=(-1, -2))
 
 
+def transition_sigma(sigma, adaptive, v_all, ik, n, kq, mesh):
+    """Smearing width of the transitions (k, n) -> (k+q, m): the fixed sigma, or
+    with ``adaptive`` = dict(sigma_min=..., prefactor=...) the adaptive width of
+    ``oracle.velocity`` from the group velocities ([q, 1, m], broadcast over nu)."""
+    if adaptive is None:
+        return sigma
+    s = adaptive_sigma(v_all[ik, n][None, None, :], v_all[kq], mesh, adaptive["sigma_min"],
+                       adaptive.get("prefactor", 1.0))
+    return s[:, None, :]
+
+
 def scattering_rates(system, mesh, mu, kT, sigma, win_lo, win_hi, omega_min=1e-4,
-                     k_idx=None, q_lists=None, tables=None, q_chunk=4096, k_batch=8):
+                     k_idx=None, q_lists=None, tables=None, q_chunk=4096, k_batch=8,
+                     adaptive=None):
     """Gamma_nk for kept states of the k mesh (full q mesh or weighted q lists).
+
+    adaptive: None (Gaussian smearing of width sigma) or dict(sigma_min=...,
+      prefactor=1.0): adaptive Gaussian smearing (Dirac delta and Smearing), a
+      width per transition from the group velocities at k and k+q.
 
     mesh: (N0, N1, N2), the same mesh for k and q.
     k_idx: mesh linear indices of the k points to evaluate; None = every k with
@@ -114,6 +131,7 @@ def scattering_rates(system, mesh, mu, kT, sigma, win_lo, win_hi, omega_min=1e-4
     # polar systems: g = g^S + i L(q, nu) [U_k^dagger U_{k+q}]_{n m} (oracle.polar)
     pp = polar_params(system)
     L_all = polar_factor(pts, z, l_all, *pp) if pp is not None else None   # [N, nu]
+    v_all = group_velocities(pts, system.rh, system.h_r)[1] if adaptive is not None else None
 
     gamma = np.zeros((nk, nW))
     band_mask = mask_all[k_idx]
@@ -149,8 +167,9 @@ def scattering_rates(system, mesh, mu, kT, sigma, win_lo, win_hi, omega_min=1e-4
                     g = g + 1j * L_all[qs][:, None, :, None] * O[:, :, None, :]
                 g2 = (g * np.conj(g)).real
                 for j, n in enumerate(nlist):
+                    sig = transition_sigma(sigma, adaptive, v_all, ik, n, kq, mesh)
                     terms = rate_terms(g2[:, j], eps[ik, n], eps[kq], f_all[kq],
-                                       omega[qs], nb_all[qs], sigma, active_all[qs])
+                                       omega[qs], nb_all[qs], sig, active_all[qs])
                     acc[j] += np.sum(wq[c0:c0 + q_chunk] * terms)
             gamma[a_row, nlist] = 2.0 * np.pi * acc
     return dict(gamma=gamma, band_mask=band_mask, k_idx=k_idx, tables=tables)
