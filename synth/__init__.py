@@ -21,4 +21,5 @@ from .systems import (  # noqa: F401
     config_c4_specs,
     config_c4,
     add_polar,
+    third_order_constants,
 )

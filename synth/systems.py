@@ -385,3 +385,47 @@ def add_polar(system: System, seed: int, alpha: float = 5.0, g_max: int = 3,
     system.g_max = int(g_max)
     system.meta.update(polar=True)
     return system
+
+
+_TAG_PHI3 = 17
+
+
+def third_order_constants(seed: int, n_atoms: int, r_src: int = 1, decay: float = 0.8):
+    """Phi3(s a R, s' b R', s'' c 0) symmetric under every permutation of its three displacements.
+
+    A random A0(x1, R1 - R3, x2, R2 - R3, x3) ~ N(0,1) exp(-(|R1-R3| + |R2-R3|)/decay)
+    is drawn for relative vectors in [-r_src, r_src]^3 and averaged over the six
+    orderings of the three (index, cell) pairs, each translated so that its third
+    cell is the reference cell; the result is stored for R, R' in
+    [-2 r_src, 2 r_src]^3, which holds every non-zero entry.
+    Returns (r [n, 3] int32, phi3 [n, n, 3nat, 3nat, 3nat] float64 eV/A^3).
+    """
+    nm = 3 * n_atoms
+    src = box_vectors(r_src)
+    ns = src.shape[0]
+    rng = _rng(seed, _TAG_PHI3)
+    dec = np.exp(-np.linalg.norm(src.astype(np.float64), axis=1) / decay)
+    A0 = rng.standard_normal((ns, ns, nm, nm, nm)) * (dec[:, None] * dec[None, :])[:, :, None, None, None]
+    sidx = {tuple(int(x) for x in v): i for i, v in enumerate(src)}
+    r = box_vectors(2 * r_src)
+    n = r.shape[0]
+    phi = np.zeros((n, n, nm, nm, nm))
+
+    def a0(d1, d2):
+        i, j = sidx.get(tuple(int(x) for x in d1)), sidx.get(tuple(int(x) for x in d2))
+        return None if i is None or j is None else A0[i, j]
+
+    z = np.zeros(3, dtype=np.int64)
+    for i, R in enumerate(r):
+        for j, Rp in enumerate(r):
+            acc = np.zeros((nm, nm, nm))
+            # orderings of (x1, R) (x2, R') (x3, 0); each term is A0 of the ordering
+            # with its third cell moved to the reference cell, axes back in (x1, x2, x3) order
+            for (c1, c2, c3), perm in (((R, Rp, z), (0, 1, 2)), ((Rp, R, z), (1, 0, 2)),
+                                       ((R, z, Rp), (0, 2, 1)), ((z, R, Rp), (2, 0, 1)),
+                                       ((Rp, z, R), (1, 2, 0)), ((z, Rp, R), (2, 1, 0))):
+                blk = a0(c1 - c3, c2 - c3)
+                if blk is not None:
+                    acc += np.transpose(blk, np.argsort(perm))
+            phi[i, j] = acc / 6.0
+    return r, phi
