@@ -16,4 +16,4 @@ closed forms, invariants, brute force on tiny inputs and library special
 cases (NumPy FFT).  Functions without such a pin say "parity unpinned".
 """
 
-from . import constants, mesh, bands, coupling, rates, mlp, linewidth, polar, velocity, phonon3  # noqa: F401
+from . import constants, mesh, bands, coupling, rates, mlp, linewidth, polar, velocity, phonon3, rng  # noqa: F401

@@ -128,3 +128,46 @@ def inverse_cdf(p_unnorm, u):
     """Index j with CDF[j-1] <= u*total < CDF[j] for each uniform u in [0, 1)."""
     c = np.cumsum(np.asarray(p_unnorm, dtype=np.float64))
     return np.searchsorted(c, np.asarray(u) * c[-1], side="right")
+
+
+def init_params_philox(seed, n_in, width, depth, n_out=1):
+    """The library's deterministic initialisation: parameter j of the packed vector is a
+    weight (2 u_j - 1) / sqrt(in_l), u_j element j of the Philox uniform stream (seed, 0)
+    (``oracle.rng``), or a zero bias."""
+    from .rng import uniform
+    n = n_params(n_in, width, depth, n_out)
+    u = uniform(seed, 0, n)
+    theta = np.zeros(n)
+    off = 0
+    for o, i in layer_shapes(n_in, width, depth, n_out):
+        theta[off:off + o * i] = (2.0 * u[off:off + o * i] - 1.0) / np.sqrt(i)
+        off += o * i + o
+    return theta
+
+
+def training_set(terms, dweights, d_threshold, c_frac, max_samples, seed):
+    """Training samples of the proposal network from the method's own terms.
+
+    The network models the coupling part of the integrand: entries (state, q, nu)
+    with D > d_threshold * max_{q, nu} D of their state are selected; an entry is
+    kept when its Philox uniform (seed, flat index (state N_q + q) nModes + nu) is
+    below min(1, max_samples / n_selected); its target is ln(T / D + c) with
+    c = c_frac * mean over the selected entries of T / D.
+    Returns (state, q, nu, y, c), entries in flat-index order.
+    """
+    from .rng import uniform
+    T = np.asarray(terms, dtype=np.float64)
+    D = np.asarray(dweights, dtype=np.float64)
+    ns = T.shape[0]
+    dmax = D.reshape(ns, -1).max(axis=1)
+    sel = D > d_threshold * dmax[:, None, None]
+    flat = np.flatnonzero(sel.ravel())
+    ratio = T.ravel()[flat] / D.ravel()[flat]
+    c = c_frac * ratio.mean() if flat.size else 0.0
+    p_keep = min(1.0, max_samples / flat.size) if flat.size else 0.0
+    u = uniform(seed, 0, T.size)[flat] if flat.size else np.zeros(0)
+    keep = u < p_keep
+    flat, ratio = flat[keep], ratio[keep]
+    st, rem = np.divmod(flat, T.shape[1] * T.shape[2])
+    q, nu = np.divmod(rem, T.shape[2])
+    return st, q, nu, np.log(ratio + c), c
