@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define PHOEBE_GPU_ABI_VERSION 1
+#define PHOEBE_GPU_ABI_VERSION 2
 
 typedef struct {
     double re, im;
@@ -71,6 +71,21 @@ typedef enum {
     PHOEBE_BF16 = 4    /* MLP only: FP32 storage, BF16 operands, FP32 accumulation */
 } phoebe_precision;
 
+/* Long-range (polar) part of the coupling of a polar crystal (Electron
+ * Properties: the split g = g^S + g^L and the long-range expression):
+ *   g^L_{nu n m}(k, q) = i L(q, nu) [U_k^dagger U_{k+q}]_{n m},
+ *   L(q, nu) = 4 pi (e^2/(4 pi eps0)) sum_s l_{s,q nu}
+ *              sum_{G: q+G != 0} [(q+G) . Z*_s . z^s_{q nu}] e^{-(q+G).eps.(q+G)/(4 alpha)}
+ *                                / [(q+G) . eps_inf . (q+G)],
+ * with (q+G) the Cartesian vector 2 pi (q + G) (1/A), G over the integer box
+ * [-g_max, g_max]^3, e^2/(4 pi eps0) = 14.399645 eV A and V = 1 A^3. */
+typedef struct {
+    const double *born;         /* host [nat, 3, 3] Born effective charges Z*_{s, a b}, units of e */
+    double eps_inf[9];          /* high-frequency dielectric tensor, row major (positive definite) */
+    double alpha;               /* Gaussian damping of the G sum, A^-2 (> 0) */
+    int32_t g_max;              /* half-width of the G box (0 <= g_max <= 8) */
+} phoebe_polar;
+
 /* One crystal.  Integer lattice-vector lists are HOST pointers; the tensors
  * are DEVICE pointers. */
 typedef struct {
@@ -89,17 +104,31 @@ typedef struct {
     const int32_t *rp;          /* host   [n_rp, 3] */
     const phoebe_c128 *g_rr;    /* device [n_re, n_rp, nModes, nW, nW] g(Re,Rp), eV/A;
                                    first Wannier index pairs with k, second with k+q */
+    const phoebe_polar *polar;  /* host, nullable: a polar crystal's long-range coupling, added
+                                   to g by interp_g, the rate and the linewidth sums */
 } phoebe_system;
+
+/* Smearing of the energy-conserving delta (Dirac delta and Smearing). */
+typedef enum {
+    PHOEBE_SMEAR_GAUSSIAN = 0, /* fixed width sigma */
+    PHOEBE_SMEAR_ADAPTIVE = 1  /* adaptive Gaussian: a width per transition (k n) -> (k+q m),
+                                  sigma_t = max(sigma, (A / sqrt 12) |(v_nk - v_m,k+q) . 2 pi / N|),
+                                  the velocity difference (eV A) taken per axis times the
+                                  mesh step 2 pi / N_beta (1/A) of that axis, A = adaptive_scale */
+} phoebe_smearing;
 
 /* Parameters of the rate sum.  States with win_lo < eps < win_hi are kept;
  * modes with hbar omega < omega_min are left out (and get l = 0). */
 typedef struct {
     double mu;        /* chemical potential, eV */
     double kT;        /* k_B T, eV (> 0) */
-    double sigma;     /* Gaussian smearing: delta(x) = exp(-x^2/sigma^2)/(sqrt(pi) sigma), > 0 */
+    double sigma;     /* Gaussian smearing: delta(x) = exp(-x^2/sigma^2)/(sqrt(pi) sigma), > 0;
+                         with PHOEBE_SMEAR_ADAPTIVE the floor of the per-transition width */
     double win_lo;    /* energy window, eV */
     double win_hi;
     double omega_min; /* eV, >= 0 */
+    int32_t smearing;       /* phoebe_smearing */
+    double adaptive_scale;  /* A of the adaptive width (> 0; 1 is the plain reading) */
 } phoebe_rate_params;
 
 /* ABI version of the loaded library (PHOEBE_GPU_ABI_VERSION it was built with). */
@@ -168,8 +197,14 @@ phoebe_status phoebe_gpu_interp_g(void *handle, const phoebe_system *sys,
  *       [(n_{q nu}+1-f_{m,k+q}) delta(eps_nk-eps_{m,k+q}-hbar omega_{q nu})
  *      + (n_{q nu}+f_{m,k+q})   delta(eps_nk-eps_{m,k+q}+hbar omega_{q nu})],
  * f Fermi-Dirac(mu, kT), n Bose-Einstein(kT), k+q folded onto the mesh.
- *   mesh      host [3], the k and the q mesh; point (i0,i1,i2) has linear
- *             index (i0 N1 + i1) N2 + i2 (third coordinate fastest)
+ * With sys->polar set, g includes the long-range part g^L (see phoebe_polar);
+ * with par->smearing = PHOEBE_SMEAR_ADAPTIVE each delta takes its own width
+ * (see phoebe_smearing; 1/sigma_t inside the sum).
+ *   k_mesh    host [3], the k mesh; point (i0,i1,i2) has linear index
+ *             (i0 N1 + i1) N2 + i2 (third coordinate fastest)
+ *   q_mesh    host [3], the q mesh.  k + q must be a point of the k mesh, so
+ *             the two must be equal: a q mesh different from the k mesh
+ *             returns PHOEBE_E_UNSUPPORTED
  *   k_idx     device [nk] mesh linear indices of the k points to evaluate, or
  *             NULL: every mesh k with a state in the window, ascending
  *   q_off, q_idx, q_w: NULL for the full q mesh with w_q = 1/N_q; otherwise
@@ -193,9 +228,12 @@ phoebe_status phoebe_gpu_interp_g(void *handle, const phoebe_system *sys,
  * 16 GB or a quarter of the budget, whichever is less.  The results are the
  * same bit for bit.
  * Errors: PHOEBE_E_INVALID (mesh < 1, sigma <= 0, kT <= 0, enum, pointers),
- * PHOEBE_E_NOMEM, PHOEBE_E_UNSUPPORTED (nW > 32, nModes > 32), PHOEBE_E_DEVICE. */
+ * PHOEBE_E_NOMEM, PHOEBE_E_UNSUPPORTED (nW > 32, nModes > 32, q_mesh != k_mesh,
+ * polar or adaptive smearing with another precision than FP64),
+ * PHOEBE_E_NUMERIC (finiteness checks on, see phoebe_gpu_set_check_finite),
+ * PHOEBE_E_DEVICE. */
 phoebe_status phoebe_gpu_scatter_rates(void *handle, const phoebe_system *sys,
-                                       const int32_t mesh[3],
+                                       const int32_t k_mesh[3], const int32_t q_mesh[3],
                                        const int32_t *k_idx, int64_t nk,
                                        const int64_t *q_off, const int32_t *q_idx,
                                        const double *q_w,
@@ -336,6 +374,136 @@ phoebe_status phoebe_gpu_propose_q(void *handle, const int32_t mesh[3], int32_t 
                                    int32_t depth, double e0, double escale, double d_threshold,
                                    double mix, int32_t S, const double *uniforms, int64_t *q_off,
                                    int32_t *q_idx, double *q_w, void *stream);
+
+/* Phonon scattering rate from the electron-phonon interaction, the el-ph
+ * term on the diagonal of the phonon scattering matrix (Transport Methods,
+ * phonon BTE), with the paper's replacement f_kb - f_{k+q,b'} ~ (df/de) hbar omega:
+ *   P_{q nu} = (2 pi / N_k) n (n + 1) hbar omega_{q nu}
+ *              sum_{k, b, b'} |g_{nu b b'}(k, q)|^2 f_kb (1 - f_kb) / kT
+ *              delta(eps_kb - eps_{b',k+q} - hbar omega_{q nu}),
+ * n = n(omega_{q nu}); b runs over the states of the window at every k of the
+ * k mesh, b' over all bands; modes with hbar omega < omega_min get P = 0.  g,
+ * the smearing (fixed or adaptive) and the window are those of
+ * phoebe_gpu_scatter_rates, and so is the evaluation: the coupling of each
+ * kept state is formed once and its terms go to the linewidth of every q.
+ *   k_mesh, q_mesh host [3] (equal; otherwise PHOEBE_E_UNSUPPORTED)
+ *   p_out     device [N_q, nModes] eV
+ *   gamma_out device [N_k, nW] (nullable): the electron rates of the same pass,
+ *             rows as scatter_rates with k_idx = NULL
+ *   n_kept_out host (nullable): kept k points summed over
+ * The sum over states is taken in a fixed order: two calls give equal bits.
+ * Synchronises the stream once (to learn the kept count).  FP64 only.
+ * Errors as phoebe_gpu_scatter_rates; PHOEBE_E_UNSUPPORTED for other
+ * precisions. */
+phoebe_status phoebe_gpu_phonon_linewidth(void *handle, const phoebe_system *sys,
+                                          const int32_t k_mesh[3], const int32_t q_mesh[3],
+                                          const phoebe_rate_params *par, phoebe_precision prec,
+                                          double *p_out, double *gamma_out, int64_t *n_kept_out,
+                                          void *stream);
+
+/* Electron group velocities (Electron Properties, Velocity): the velocity
+ * operator v_a = U_k^dagger (dH^W/dk_a) U_k with the analytic derivative
+ * dH^W/dk_a = sum_R i R_a e^{i 2 pi k.R} H(R) (eV A, Cartesian R, a = 1 A);
+ * a non-degenerate band's velocity is its diagonal element, a degenerate group
+ * (|delta eps| < 1e-6 eV) has its block of each v_a diagonalised and its bands
+ * take the eigenvalues in ascending order.
+ *   k_frac device [nk, 3];  eps_out device [nk, nW] (nullable)
+ *   v_out  device [nk, nW, 3] eV A
+ * Only n_wannier, n_rh, rh, h_r are read.  nk = 0 is a no-op. */
+phoebe_status phoebe_gpu_velocities(void *handle, const phoebe_system *sys, const double *k_frac,
+                                    int64_t nk, double *eps_out, double *v_out, void *stream);
+
+/* The q-dependent factor L(q, nu) of the long-range coupling (see
+ * phoebe_polar), with l = 0 for hbar omega < omega_min.
+ *   q_frac device [nq, 3];  l_out device [nq, nModes] complex, eV
+ * Needs sys->polar and the force constants.  nq = 0 is a no-op. */
+phoebe_status phoebe_gpu_polar_factor(void *handle, const phoebe_system *sys, const double *q_frac,
+                                      int64_t nq, double omega_min, phoebe_c128 *l_out,
+                                      void *stream);
+
+/* Anharmonic force constants of a crystal for the 3-phonon coupling: the
+ * harmonic part as in phoebe_system and the third derivatives
+ * Phi3(s a R, s' b R', s'' c 0) with the third displacement in the reference
+ * cell.  Lattice lists are HOST pointers, tensors DEVICE pointers. */
+typedef struct {
+    int32_t n_atoms;
+    int32_t n_rd;  const int32_t *rd;  const double *phi_r;  const double *mass;
+    int32_t n_r1;  const int32_t *r1;  /* host [n_r1, 3]: R of the first displacement */
+    int32_t n_r2;  const int32_t *r2;  /* host [n_r2, 3]: R' of the second displacement */
+    const double *phi3;                /* device [n_r1, n_r2, nModes, nModes, nModes] eV/A^3 */
+} phoebe_system3;
+
+/* Interpolated 3-phonon coupling for every pair of a q list and a q' list
+ * (Phonon Properties, the Fourier transform of the third derivative; the
+ * generic contraction of the Kokkos section, the sum over R taken at fixed q,
+ * then the sum over R' at each q'):
+ *   V3(q nu, q' nu', q'' nu'') = sum_{R, R'} sum_{sa, s'b, s''c} Phi3(s a R, s' b R', s'' c 0)
+ *       e^{-i 2 pi (q.R + q'.R')} z*_{sa,nu}(q) l z*_{s'b,nu'}(q') l' z*_{s''c,nu''}(q'') l'',
+ * q'' = -q - q', l the phonon length of each mode (0 below omega_min).
+ *   q_frac device [nq, 3];  qp_frac device [nqp, 3]
+ *   v3_out device [nq, nqp, nModes, nModes, nModes] complex, eV (nu, nu', nu'')
+ *   omega_q [nq, nModes], omega_qp [nqp, nModes], omega_qpp [nq, nqp, nModes]
+ *           device (nullable)
+ * Eigenvector phases are the library's, so V3 is defined up to a phase per
+ * mode; |V3|^2 summed over degenerate modes is phase-free.
+ * Errors: PHOEBE_E_INVALID, PHOEBE_E_NOMEM, PHOEBE_E_UNSUPPORTED (nModes > 30),
+ * PHOEBE_E_DEVICE. */
+phoebe_status phoebe_gpu_interp_v3(void *handle, const phoebe_system3 *sys, const double *q_frac,
+                                   int64_t nq, const double *qp_frac, int64_t nqp,
+                                   double omega_min, phoebe_c128 *v3_out, double *omega_q,
+                                   double *omega_qp, double *omega_qpp, void *stream);
+
+/* Counter-based random numbers: Philox-4x64 with 10 rounds (Salmon, Moraes,
+ * Dror and Shaw, "Parallel random numbers: as easy as 1, 2, 3", SC'11).
+ * Element i of the stream (seed, offset) is the first 64-bit word w0 of the
+ * block Philox(counter = (offset + i, 0, 0, 0), key = (seed, 0)), so a stream is
+ * the same on any device and launch shape, and disjoint offsets never overlap.
+ *   uniform: out[i] = (w0 >> 11) 2^-53, a double in [0, 1)
+ *   randint: out[i] = floor(uniform * hi), in [0, hi), 1 <= hi <= 2^31 - 1
+ * out device [n].  n = 0 is a no-op. */
+phoebe_status phoebe_gpu_philox_uniform(void *handle, uint64_t seed, uint64_t offset, int64_t n,
+                                        double *out, void *stream);
+phoebe_status phoebe_gpu_philox_randint(void *handle, uint64_t seed, uint64_t offset, int64_t n,
+                                        int64_t hi, int32_t *out, void *stream);
+
+/* Parameters of a new network (layout as phoebe_gpu_mlp_param_count): each
+ * weight of layer l uniform in (-1/sqrt(in_l), 1/sqrt(in_l)) from the Philox
+ * stream (seed, 0) in packing order, biases 0.  params device (float for
+ * PHOEBE_BF16, double for PHOEBE_FP64). */
+phoebe_status phoebe_gpu_mlp_init(void *handle, phoebe_precision prec, void *params, int32_t n_in,
+                                  int32_t width, int32_t depth, uint64_t seed, void *stream);
+
+/* Training set of the learned proposal from the method's own terms (see
+ * phoebe_gpu_rate_terms): the entries (state, q, nu) with
+ * D > d_threshold x max_{q,nu} D of their state are selected; each is kept
+ * with probability min(1, max_samples / n_selected), decided by the Philox
+ * uniform (seed, flat index); a kept entry gets the target
+ *   y = ln(T / D + c),  c = c_frac x mean over the selected entries of T / D.
+ *   terms, dweights device [n_states, N_q, nModes]
+ *   st_row, st_band device [n_states]: row and band of each state
+ *   out_state, out_q, out_nu device int32 [cap]; out_y device float [cap]
+ *   n_out host: entries written (at most cap; entries beyond cap are dropped,
+ *         in flat-index order); c_out host (nullable): the c used
+ * Synchronises the stream. */
+phoebe_status phoebe_gpu_training_set(void *handle, const double *terms, const double *dweights,
+                                      int64_t n_states, int64_t n_q, int32_t n_modes,
+                                      double d_threshold, double c_frac, int64_t max_samples,
+                                      uint64_t seed, int32_t *out_state, int32_t *out_q,
+                                      int32_t *out_nu, float *out_y, int64_t cap, int64_t *n_out,
+                                      double *c_out, void *stream);
+
+/* Row gather: dst[i] = src[idx[i]] for rows of row_bytes bytes (a multiple
+ * of 4); idx device int32 [n], each in [0, n_src).  For minibatches. */
+phoebe_status phoebe_gpu_gather_rows(void *handle, const void *src, int64_t n_src,
+                                     int64_t row_bytes, const int32_t *idx, int64_t n, void *dst,
+                                     void *stream);
+
+/* Optional input validation: when enabled, the calls that read a system
+ * (electron_bands, phonon_modes, velocities, interp_g, scatter_rates,
+ * phonon_linewidth, rate_terms) first scan h_r, phi_r, mass and g_rr for
+ * NaN or infinity and return PHOEBE_E_NUMERIC, before any other launch, if
+ * one holds one.  The scan reads every input once and synchronises. */
+phoebe_status phoebe_gpu_set_check_finite(void *handle, int enable);
 
 /* How phoebe_gpu_scatter_rates (and rate_terms) evaluate the sum over Rp on a
  * full q mesh in FP64.  DIRECT: one MFMA contraction over the Rp list per q

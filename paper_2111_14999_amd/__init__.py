@@ -8,6 +8,7 @@ host lattice lists into it.
 from .binding import (  # noqa: F401
     EXPORTS,
     DeviceSystem,
+    DeviceSystem3,
     Library,
     PhoebeError,
     load,

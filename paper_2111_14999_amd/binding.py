@@ -36,13 +36,24 @@ EXPORTS = (
     "phoebe_gpu_mlp_forward", "phoebe_gpu_mlp_grad", "phoebe_gpu_mlp_adam",
     "phoebe_gpu_mlp_features", "phoebe_gpu_propose_q", "phoebe_gpu_delta_weights",
     "phoebe_gpu_set_mesh_sum", "phoebe_gpu_mlp_feature_count", "phoebe_gpu_kernel_bytes",
+    "phoebe_gpu_phonon_linewidth", "phoebe_gpu_velocities", "phoebe_gpu_polar_factor",
+    "phoebe_gpu_interp_v3", "phoebe_gpu_philox_uniform", "phoebe_gpu_philox_randint",
+    "phoebe_gpu_mlp_init", "phoebe_gpu_training_set", "phoebe_gpu_gather_rows",
+    "phoebe_gpu_set_check_finite",
 )
+
+SMEARING = {"gaussian": 0, "adaptive": 1}
 
 
 class PhoebeError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"{STATUS.get(status, status)}: {message}")
         self.status = status
+
+
+class CPolar(ctypes.Structure):
+    _fields_ = [("born", ctypes.c_void_p), ("eps_inf", ctypes.c_double * 9),
+                ("alpha", ctypes.c_double), ("g_max", ctypes.c_int32)]
 
 
 class CSystem(ctypes.Structure):
@@ -54,13 +65,34 @@ class CSystem(ctypes.Structure):
         ("n_re", ctypes.c_int32), ("re", ctypes.c_void_p),
         ("n_rp", ctypes.c_int32), ("rp", ctypes.c_void_p),
         ("g_rr", ctypes.c_void_p),
+        ("polar", ctypes.POINTER(CPolar)),
+    ]
+
+
+class CSystem3(ctypes.Structure):
+    _fields_ = [
+        ("n_atoms", ctypes.c_int32),
+        ("n_rd", ctypes.c_int32), ("rd", ctypes.c_void_p), ("phi_r", ctypes.c_void_p),
+        ("mass", ctypes.c_void_p),
+        ("n_r1", ctypes.c_int32), ("r1", ctypes.c_void_p),
+        ("n_r2", ctypes.c_int32), ("r2", ctypes.c_void_p),
+        ("phi3", ctypes.c_void_p),
     ]
 
 
 class CRateParams(ctypes.Structure):
     _fields_ = [("mu", ctypes.c_double), ("kT", ctypes.c_double), ("sigma", ctypes.c_double),
                 ("win_lo", ctypes.c_double), ("win_hi", ctypes.c_double),
-                ("omega_min", ctypes.c_double)]
+                ("omega_min", ctypes.c_double), ("smearing", ctypes.c_int32),
+                ("adaptive_scale", ctypes.c_double)]
+
+
+def rate_params(p: dict) -> CRateParams:
+    """C rate parameters from a dict (mu, kT, sigma, win_lo, win_hi, optional omega_min,
+    smearing "gaussian"/"adaptive" and adaptive_scale)."""
+    return CRateParams(p["mu"], p["kT"], p["sigma"], p["win_lo"], p["win_hi"],
+                       p.get("omega_min", 1e-4), SMEARING[p.get("smearing", "gaussian")],
+                       float(p.get("adaptive_scale", 1.0)))
 
 
 _lib = None
@@ -85,9 +117,27 @@ def load(path: str = LIB_PATH):
     lib.phoebe_gpu_interp_g.argtypes = [vp, ctypes.POINTER(CSystem), vp, i64, vp, i64,
                                         ctypes.c_double, ctypes.c_int, vp, vp, vp, vp, vp]
     lib.phoebe_gpu_scatter_rates.argtypes = [vp, ctypes.POINTER(CSystem),
-                                             ctypes.POINTER(i32), vp, i64, vp, vp, vp,
-                                             ctypes.POINTER(CRateParams), ctypes.c_int,
+                                             ctypes.POINTER(i32), ctypes.POINTER(i32), vp, i64,
+                                             vp, vp, vp, ctypes.POINTER(CRateParams), ctypes.c_int,
                                              vp, vp, vp, ctypes.POINTER(i64), vp]
+    lib.phoebe_gpu_phonon_linewidth.argtypes = [vp, ctypes.POINTER(CSystem), ctypes.POINTER(i32),
+                                                ctypes.POINTER(i32), ctypes.POINTER(CRateParams),
+                                                ctypes.c_int, vp, vp, ctypes.POINTER(i64), vp]
+    lib.phoebe_gpu_velocities.argtypes = [vp, ctypes.POINTER(CSystem), vp, i64, vp, vp, vp]
+    lib.phoebe_gpu_polar_factor.argtypes = [vp, ctypes.POINTER(CSystem), vp, i64, ctypes.c_double,
+                                            vp, vp]
+    lib.phoebe_gpu_interp_v3.argtypes = [vp, ctypes.POINTER(CSystem3), vp, i64, vp, i64,
+                                         ctypes.c_double, vp, vp, vp, vp, vp]
+    u64 = ctypes.c_uint64
+    lib.phoebe_gpu_philox_uniform.argtypes = [vp, u64, u64, i64, vp, vp]
+    lib.phoebe_gpu_philox_randint.argtypes = [vp, u64, u64, i64, i64, vp, vp]
+    lib.phoebe_gpu_mlp_init.argtypes = [vp, ctypes.c_int, vp, i32, i32, i32, u64, vp]
+    lib.phoebe_gpu_training_set.argtypes = [vp, vp, vp, i64, i64, i32, ctypes.c_double,
+                                            ctypes.c_double, i64, u64, vp, vp, vp, vp, i64,
+                                            ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
+                                            vp]
+    lib.phoebe_gpu_gather_rows.argtypes = [vp, vp, i64, i64, vp, i64, vp, vp]
+    lib.phoebe_gpu_set_check_finite.argtypes = [vp, ctypes.c_int]
     lib.phoebe_gpu_set_timing.argtypes = [vp, ctypes.c_int]
     lib.phoebe_gpu_set_mesh_sum.argtypes = [vp, i32]
     lib.phoebe_gpu_kernel_bytes.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double)]
@@ -175,6 +225,7 @@ class DeviceSystem:
     re: np.ndarray
     rp: np.ndarray
     g_rr: object
+    polar: Optional[dict] = None  # born [nat,3,3], eps_inf [3,3], alpha, g_max (host)
 
     @staticmethod
     def from_host(system, device="cuda:0", with_coupling=True) -> "DeviceSystem":
@@ -188,12 +239,24 @@ class DeviceSystem:
             return np.ascontiguousarray(a, dtype=np.int32)
 
         g = dev(system.g_rr) if (with_coupling and system.g_rr is not None) else None
+        polar = None
+        if getattr(system, "born", None) is not None:
+            polar = dict(born=np.ascontiguousarray(system.born, dtype=np.float64),
+                         eps_inf=np.ascontiguousarray(system.eps_inf, dtype=np.float64),
+                         alpha=float(system.ewald_alpha), g_max=int(system.g_max))
         return DeviceSystem(system.n_wannier, system.n_atoms, ivec(system.rh), dev(system.h_r),
                             ivec(system.rd), dev(system.phi_r), dev(system.mass),
-                            ivec(system.re), ivec(system.rp), g)
+                            ivec(system.re), ivec(system.rp), g, polar)
 
     def c_struct(self) -> CSystem:
         c = CSystem()
+        if self.polar is not None:
+            p = CPolar()
+            p.born = self.polar["born"].ctypes.data
+            p.eps_inf = (ctypes.c_double * 9)(*[float(x) for x in self.polar["eps_inf"].ravel()])
+            p.alpha, p.g_max = self.polar["alpha"], self.polar["g_max"]
+            self._cpolar = p  # kept alive with the struct that points to it
+            c.polar = ctypes.pointer(p)
         c.n_wannier, c.n_atoms = self.n_wannier, self.n_atoms
         c.n_rh, c.rh, c.h_r = self.rh.shape[0], self.rh.ctypes.data, _ptr(self.h_r)
         c.n_rd, c.rd, c.phi_r = self.rd.shape[0], self.rd.ctypes.data, _ptr(self.phi_r)
@@ -201,6 +264,42 @@ class DeviceSystem:
         c.n_re, c.re = self.re.shape[0], self.re.ctypes.data
         c.n_rp, c.rp = self.rp.shape[0], self.rp.ctypes.data
         c.g_rr = _ptr(self.g_rr)
+        return c
+
+
+@dataclass
+class DeviceSystem3:
+    """Harmonic and third-order force constants on the GPU, lattice lists on the host."""
+
+    n_atoms: int
+    rd: np.ndarray
+    phi_r: object
+    mass: object
+    r1: np.ndarray
+    r2: np.ndarray
+    phi3: object
+
+    @staticmethod
+    def from_host(system, r, phi3, device="cuda:0") -> "DeviceSystem3":
+        """From a host system (harmonic part) and third-order constants on lattice list r
+        (used for both displacements)."""
+        import torch
+
+        def dev(a):
+            return torch.from_numpy(np.ascontiguousarray(a)).to(device)
+
+        rr = np.ascontiguousarray(r, dtype=np.int32)
+        return DeviceSystem3(system.n_atoms, np.ascontiguousarray(system.rd, dtype=np.int32),
+                             dev(system.phi_r), dev(system.mass), rr, rr.copy(), dev(phi3))
+
+    def c_struct(self) -> CSystem3:
+        c = CSystem3()
+        c.n_atoms = self.n_atoms
+        c.n_rd, c.rd, c.phi_r, c.mass = self.rd.shape[0], self.rd.ctypes.data, _ptr(self.phi_r), \
+            _ptr(self.mass)
+        c.n_r1, c.r1 = self.r1.shape[0], self.r1.ctypes.data
+        c.n_r2, c.r2 = self.r2.shape[0], self.r2.ctypes.data
+        c.phi3 = _ptr(self.phi3)
         return c
 
 
@@ -260,29 +359,97 @@ class Library:
     # -- rates --------------------------------------------------------------
     def scatter_rates(self, sys: DeviceSystem, mesh, params: dict, gamma_out, k_idx=None,
                       q_lists=None, precision="fp64", band_mask=None, kept_k_out=None,
-                      stream=None) -> int:
+                      stream=None, q_mesh=None) -> int:
         c = sys.c_struct()
         m = (ctypes.c_int32 * 3)(*[int(x) for x in mesh])
-        p = CRateParams(params["mu"], params["kT"], params["sigma"], params["win_lo"],
-                        params["win_hi"], params.get("omega_min", 1e-4))
+        mq = (ctypes.c_int32 * 3)(*[int(x) for x in (mesh if q_mesh is None else q_mesh)])
+        p = rate_params(params)
         nk = 0 if k_idx is None else int(k_idx.shape[0])
         q_off = q_idx = q_w = None
         if q_lists is not None:
             q_off, q_idx, q_w = q_lists
         n_kept = ctypes.c_int64(0)
         self._check(self.lib.phoebe_gpu_scatter_rates(
-            self.handle, ctypes.byref(c), m, _ptr(k_idx), nk, _ptr(q_off), _ptr(q_idx), _ptr(q_w),
-            ctypes.byref(p), PRECISIONS[precision], _ptr(gamma_out), _ptr(band_mask),
+            self.handle, ctypes.byref(c), m, mq, _ptr(k_idx), nk, _ptr(q_off), _ptr(q_idx),
+            _ptr(q_w), ctypes.byref(p), PRECISIONS[precision], _ptr(gamma_out), _ptr(band_mask),
             _ptr(kept_k_out), ctypes.byref(n_kept), _stream(stream)))
         return int(n_kept.value)
+
+    def phonon_linewidth(self, sys: DeviceSystem, mesh, params: dict, p_out, gamma_out=None,
+                         precision="fp64", stream=None, q_mesh=None) -> int:
+        """P^{el-ph}[q, nu] on the full mesh (p_out [N, nModes]); returns the kept k count."""
+        c = sys.c_struct()
+        m = (ctypes.c_int32 * 3)(*[int(x) for x in mesh])
+        mq = (ctypes.c_int32 * 3)(*[int(x) for x in (mesh if q_mesh is None else q_mesh)])
+        p = rate_params(params)
+        n_kept = ctypes.c_int64(0)
+        self._check(self.lib.phoebe_gpu_phonon_linewidth(
+            self.handle, ctypes.byref(c), m, mq, ctypes.byref(p), PRECISIONS[precision],
+            _ptr(p_out), _ptr(gamma_out), ctypes.byref(n_kept), _stream(stream)))
+        return int(n_kept.value)
+
+    def velocities(self, sys: DeviceSystem, k_frac, v_out, eps_out=None, stream=None):
+        c = sys.c_struct()
+        self._check(self.lib.phoebe_gpu_velocities(
+            self.handle, ctypes.byref(c), _ptr(k_frac), int(k_frac.shape[0]), _ptr(eps_out),
+            _ptr(v_out), _stream(stream)))
+
+    def polar_factor(self, sys: DeviceSystem, q_frac, l_out, omega_min=1e-4, stream=None):
+        c = sys.c_struct()
+        self._check(self.lib.phoebe_gpu_polar_factor(
+            self.handle, ctypes.byref(c), _ptr(q_frac), int(q_frac.shape[0]), float(omega_min),
+            _ptr(l_out), _stream(stream)))
+
+    def interp_v3(self, sys3: "DeviceSystem3", q_frac, qp_frac, v3_out, omega_min=1e-4,
+                  omega_q=None, omega_qp=None, omega_qpp=None, stream=None):
+        c = sys3.c_struct()
+        self._check(self.lib.phoebe_gpu_interp_v3(
+            self.handle, ctypes.byref(c), _ptr(q_frac), int(q_frac.shape[0]), _ptr(qp_frac),
+            int(qp_frac.shape[0]), float(omega_min), _ptr(v3_out), _ptr(omega_q), _ptr(omega_qp),
+            _ptr(omega_qpp), _stream(stream)))
+
+    def philox_uniform(self, seed, offset, out, stream=None):
+        self._check(self.lib.phoebe_gpu_philox_uniform(
+            self.handle, int(seed), int(offset), int(out.numel()), _ptr(out), _stream(stream)))
+
+    def philox_randint(self, seed, offset, hi, out, stream=None):
+        self._check(self.lib.phoebe_gpu_philox_randint(
+            self.handle, int(seed), int(offset), int(out.numel()), int(hi), _ptr(out),
+            _stream(stream)))
+
+    def mlp_init(self, params, n_in, width, depth, seed, precision="bf16", stream=None):
+        self._check(self.lib.phoebe_gpu_mlp_init(
+            self.handle, PRECISIONS[precision], _ptr(params), n_in, width, depth, int(seed),
+            _stream(stream)))
+
+    def training_set(self, terms, dweights, n_states, d_threshold, c_frac, max_samples, seed,
+                     out_state, out_q, out_nu, out_y, stream=None):
+        """Returns (entries written, c)."""
+        n = ctypes.c_int64(0)
+        c = ctypes.c_double(0.0)
+        self._check(self.lib.phoebe_gpu_training_set(
+            self.handle, _ptr(terms), _ptr(dweights), int(n_states), int(terms.shape[1]),
+            int(terms.shape[2]), float(d_threshold), float(c_frac), int(max_samples), int(seed),
+            _ptr(out_state), _ptr(out_q), _ptr(out_nu), _ptr(out_y), int(out_y.shape[0]),
+            ctypes.byref(n), ctypes.byref(c), _stream(stream)))
+        return int(n.value), float(c.value)
+
+    def gather_rows(self, src, idx, dst, stream=None):
+        """dst[i] = src[idx[i]] (rows of src's trailing dimensions)."""
+        row_bytes = int(src[0].numel() * src.element_size()) if src.shape[0] else 0
+        self._check(self.lib.phoebe_gpu_gather_rows(
+            self.handle, _ptr(src), int(src.shape[0]), row_bytes, _ptr(idx), int(idx.shape[0]),
+            _ptr(dst), _stream(stream)))
+
+    def set_check_finite(self, on: bool):
+        self._check(self.lib.phoebe_gpu_set_check_finite(self.handle, 1 if on else 0))
 
     # -- learned proposal ---------------------------------------------------
     def rate_terms(self, sys: DeviceSystem, mesh, params: dict, k_idx, gamma_out, terms,
                    dweights=None, st_row=None, st_band=None, stream=None) -> int:
         c = sys.c_struct()
         m = (ctypes.c_int32 * 3)(*[int(x) for x in mesh])
-        p = CRateParams(params["mu"], params["kT"], params["sigma"], params["win_lo"],
-                        params["win_hi"], params.get("omega_min", 1e-4))
+        p = rate_params(params)
         ns = ctypes.c_int64(0)
         self._check(self.lib.phoebe_gpu_rate_terms(
             self.handle, ctypes.byref(c), m, _ptr(k_idx), int(k_idx.shape[0]), ctypes.byref(p),
@@ -295,8 +462,7 @@ class Library:
                       st_row=None, st_band=None, stream=None) -> int:
         c = sys.c_struct()
         m = (ctypes.c_int32 * 3)(*[int(x) for x in mesh])
-        p = CRateParams(params["mu"], params["kT"], params["sigma"], params["win_lo"],
-                        params["win_hi"], params.get("omega_min", 1e-4))
+        p = rate_params(params)
         ns = ctypes.c_int64(0)
         self._check(self.lib.phoebe_gpu_delta_weights(
             self.handle, ctypes.byref(c), m, _ptr(k_idx), int(k_idx.shape[0]), ctypes.byref(p),
@@ -356,9 +522,7 @@ class Library:
         n = len(systems)
         cs = (CSystem * n)(*[sy.c_struct() for sy in systems])
         m = (ctypes.c_int32 * (3 * n))(*[int(x) for mm in meshes for x in mm])
-        ps = (CRateParams * n)(*[CRateParams(p["mu"], p["kT"], p["sigma"], p["win_lo"],
-                                             p["win_hi"], p.get("omega_min", 1e-4))
-                                 for p in params_list])
+        ps = (CRateParams * n)(*[rate_params(p) for p in params_list])
         kept = (ctypes.c_int64 * n)()
         plan = ctypes.c_void_p()
         path = tune_cache.encode() if tune_cache else None

@@ -2,6 +2,7 @@
 // kernels for the band structure, the coupling interpolation and the rates.
 #include <array>
 
+#include "ext.hpp"
 #include "host.hpp"
 
 using namespace phx;
@@ -66,6 +67,7 @@ phoebe_status phoebe_gpu_destroy(void* handle) {
         (void)hipEventDestroy(t.stop);
     }
     if (h->ws) (void)hipFree(h->ws);
+    if (h->dflag) (void)hipFree(h->dflag);
     delete h;
     return PHOEBE_OK;
 }
@@ -134,6 +136,7 @@ phoebe_status phoebe_gpu_electron_bands(void* handle, const phoebe_system* sys,
         REQUIRE(h, k_frac && eps_out, "k_frac/eps_out is NULL");
         REQUIRE(h, sys->n_wannier <= 32, "n_wannier > 32 is not supported");
         HIPCHK(h, hipSetDevice(h->device));
+        scan_finite(h, sys, true, false, false, s);
         const int nW = sys->n_wannier;
         auto plan = [&](Arena& ar) {
             int32_t* rh = upload_r(h, ar, sys->rh, sys->n_rh, s);
@@ -143,7 +146,7 @@ phoebe_status phoebe_gpu_electron_bands(void* handle, const phoebe_system* sys,
         Arena dry(nullptr);
         plan(dry);
         ensure_ws(h, dry.used);
-        Arena ar(h->ws);
+        Arena ar(h->ws, h->ws_cap);
         plan(ar);
         HIPCHK(h, hipGetLastError());
         HIPCHK(h, hipStreamSynchronize(s));  // host lattice lists are read before return
@@ -164,6 +167,7 @@ phoebe_status phoebe_gpu_phonon_modes(void* handle, const phoebe_system* sys,
         REQUIRE(h, q_frac && omega_out, "q_frac/omega_out is NULL");
         REQUIRE(h, sys->n_atoms <= 10, "more than 10 atoms (30 modes) is not supported");
         HIPCHK(h, hipSetDevice(h->device));
+        scan_finite(h, sys, false, true, false, s);
         auto plan = [&](Arena& ar) {
             int32_t* rd = upload_r(h, ar, sys->rd, sys->n_rd, s);
             phonon_dev(h, ar, sys, rd, q_frac, nullptr, Mesh{1, 1, 1}, nq, 0.0, 0.0, omega_out,
@@ -172,7 +176,7 @@ phoebe_status phoebe_gpu_phonon_modes(void* handle, const phoebe_system* sys,
         Arena dry(nullptr);
         plan(dry);
         ensure_ws(h, dry.used);
-        Arena ar(h->ws);
+        Arena ar(h->ws, h->ws_cap);
         plan(ar);
         HIPCHK(h, hipGetLastError());
         HIPCHK(h, hipStreamSynchronize(s));  // host lattice lists are read before return
@@ -201,7 +205,10 @@ phoebe_status phoebe_gpu_interp_g(void* handle, const phoebe_system* sys, const 
         }
         const bool lowp = prec != PHOEBE_FP64;
         const size_t el = lowp ? sizeof(cf) : sizeof(cd);
+        const bool polar = sys->polar != nullptr;
+        if (polar) check_polar(h, sys);
         HIPCHK(h, hipSetDevice(h->device));
+        scan_finite(h, sys, true, true, true, s);
         const int n_re = sys->n_re, n_rp = sys->n_rp;
         const int64_t NC3 = (int64_t)nm * nW * nW;
         const int64_t npair = nk * nq;
@@ -224,6 +231,8 @@ phoebe_status phoebe_gpu_interp_g(void* handle, const phoebe_system* sys, const 
             cd* Pp = ar.take<cd>((size_t)nq * n_rp);
             char* F = ar.take<char>((size_t)n_rp * NC3 * el);
             char* X = ar.take<char>((size_t)qchunk * NC3 * el);
+            cd* Lq = polar ? ar.take<cd>((size_t)nq * nm) : nullptr;
+            double* born = polar ? ar.take<double>((size_t)9 * sys->n_atoms) : nullptr;
             {
                 Arena sub = ar;  // band scratch, reused after the tables are built
                 electron_bands_dev(h, sub, sys, rh, k_frac, nullptr, Mesh{1, 1, 1}, nk, ek, Uk, s);
@@ -237,6 +246,12 @@ phoebe_status phoebe_gpu_interp_g(void* handle, const phoebe_system* sys, const 
                 ar.used = std::max(std::max(sub.used, sub2.used), sub3.used);
             }
             if (!ar.base) return;
+            if (polar) {
+                HIPCHK(h, hipMemcpyAsync(born, sys->polar->born, sizeof(double) * 9 * sys->n_atoms,
+                                         hipMemcpyHostToDevice, s));
+                HIPCHK(h, launch_polar_factor(q_frac, Mesh{1, 1, 1}, nq, E, nm, polar_dev(sys, born),
+                                              Lq, s));
+            }
             HIPCHK(h, launch_phase_table(q_frac, nullptr, Mesh{1, 1, 1}, nq, rp, n_rp, Pp, n_rp, s));
             for (int64_t k0 = 0; k0 < nk; k0 += kb) {
                 const int64_t nb = std::min(kb, nk - k0);
@@ -281,6 +296,10 @@ phoebe_status phoebe_gpu_interp_g(void* handle, const phoebe_system* sys, const 
                                                       Uk + k * nW * nW, Ukq + (k * nq + q0) * nW * nW,
                                                       E + q0 * nm * nm, nW, nm, gk, s));
                         }
+                        if (polar)  // + i L(q, nu) [U_k^dagger U_{k+q}]_{n m}
+                            HIPCHK(h, launch_polar_add_g(gk, nqc, Uk + k * nW * nW,
+                                                         Ukq + (k * nq + q0) * nW * nW,
+                                                         Lq + q0 * nm, nW, nm, s));
                     }
                 }
             }
@@ -288,7 +307,7 @@ phoebe_status phoebe_gpu_interp_g(void* handle, const phoebe_system* sys, const 
         Arena dry(nullptr);
         plan(dry);
         ensure_ws(h, dry.used);
-        Arena ar(h->ws);
+        Arena ar(h->ws, h->ws_cap);
         plan(ar);
         HIPCHK(h, hipGetLastError());
         HIPCHK(h, hipStreamSynchronize(s));  // host lattice lists are read before return
@@ -301,7 +320,8 @@ phoebe_status phoebe_gpu_interp_g(void* handle, const phoebe_system* sys, const 
 // Rate path; with `terms` (FP64, full q mesh only) it also writes each kept
 // state's per-(q, mode) terms and the state list.
 static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
-                                        const int32_t mesh_in[3], const int32_t* k_idx, int64_t nk,
+                                        const int32_t mesh_in[3], const int32_t* q_mesh_in,
+                                        double* lw_out, const int32_t* k_idx, int64_t nk,
                                         const int64_t* q_off, const int32_t* q_idx,
                                         const double* q_w, const phoebe_rate_params* par,
                                         phoebe_precision prec, double* gamma_out,
@@ -334,6 +354,34 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                 "per-term output needs FP64, explicit k_idx and the full q mesh");
         REQUIRE(h, dweights == nullptr || (q_off == nullptr && k_idx != nullptr),
                 "smearing weights need explicit k_idx and the full q mesh");
+        REQUIRE(h, par->smearing == PHOEBE_SMEAR_GAUSSIAN || par->smearing == PHOEBE_SMEAR_ADAPTIVE,
+                "smearing enum out of range");
+        const bool adaptive = par->smearing == PHOEBE_SMEAR_ADAPTIVE;
+        REQUIRE(h, !adaptive || (std::isfinite(par->adaptive_scale) && par->adaptive_scale > 0.0),
+                "adaptive_scale must be > 0");
+        const bool polar = sys->polar != nullptr;
+        if (polar) check_polar(h, sys);
+        REQUIRE(h, lw_out == nullptr || (k_idx == nullptr && q_off == nullptr),
+                "the linewidth sums over every kept k of the full meshes");
+        if (q_mesh_in) {
+            REQUIRE(h, q_mesh_in[0] >= 1 && q_mesh_in[1] >= 1 && q_mesh_in[2] >= 1,
+                    "q mesh must be >= 1");
+            if (q_mesh_in[0] != mesh_in[0] || q_mesh_in[1] != mesh_in[1] ||
+                q_mesh_in[2] != mesh_in[2]) {
+                set_err(h, "a q mesh different from the k mesh is not supported (k + q must be a "
+                           "point of the k mesh)");
+                throw Fail{PHOEBE_E_UNSUPPORTED};
+            }
+        }
+        const bool ext = adaptive || polar || lw_out != nullptr;
+        if (ext && prec != PHOEBE_FP64) {
+            set_err(h, "polar coupling, adaptive smearing and the linewidth need FP64");
+            throw Fail{PHOEBE_E_UNSUPPORTED};
+        }
+        if (adaptive && (terms || dweights)) {
+            set_err(h, "per-term outputs and smearing weights take the fixed Gaussian width");
+            throw Fail{PHOEBE_E_UNSUPPORTED};
+        }
         const Mesh mesh{mesh_in[0], mesh_in[1], mesh_in[2]};
         const int64_t N = (int64_t)mesh.n0 * mesh.n1 * mesh.n2;
         REQUIRE(h, N <= (int64_t)1 << 30, "mesh too large");
@@ -358,12 +406,15 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
         const int64_t NL = (int64_t)mesh.n1 * mesh.n2;
         const bool can_factor = (prec == PHOEBE_FP64 || prec == PHOEBE_FP32) && q_off == nullptr &&
                                 Wbox <= 31 && nc_line > 0 && NL <= 65535 && mesh.n0 <= 1024 &&
-                                line_rates_lds(Wbox, mesh.n0, nm, lowp) <= 64 * 1024;
+                                line_rates_lds(Wbox, mesh.n0, nm, lowp, lw_out != nullptr) <=
+                                    64 * 1024;
         if (h->mesh_sum == PHOEBE_MESH_SUM_FACTORED && !can_factor) {
             set_err(h, "the factorised mesh sum needs FP64 or FP32, the full q mesh, |Rp| <= 15, "
                        "nW <= 16, nModes <= 32, N0 <= 1024 and N1*N2 <= 65535");
             throw Fail{PHOEBE_E_UNSUPPORTED};
         }
+        HIPCHK(h, hipSetDevice(h->device));
+        scan_finite(h, sys, true, true, true, s);
         const bool factored = can_factor && (h->mesh_sum == PHOEBE_MESH_SUM_FACTORED ||
                                              (h->mesh_sum == PHOEBE_MESH_SUM_AUTO &&
                                               2 * Wbox <= sys->n_rp));
@@ -453,6 +504,11 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
             int32_t *st_row, *st_band, *st_kmesh, *st_mlo, *st_mhi;
             int32_t *box_rp, *box_re;
             cd *Pax, *Pre;
+            cd* Lpol;            // polar factor [N, nm]
+            double* born;        // Born charges [nat, 3, 3]
+            double *vel, *vmax;  // group velocities [N, nW, 3], per-axis max |v| [3]
+            int32_t* vbad;
+            double* lwacc;       // linewidth sums [N, nm]
         } T{};
         const int64_t rows_cap = k_idx ? nk : N;
         auto plan_tables = [&](Arena& ar) {
@@ -489,6 +545,16 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                 T.box_re = ar.take<int32_t>((size_t)We * We * We);
                 T.Pre = ar.take<cd>((size_t)(mesh.n0 + mesh.n1 + mesh.n2) * We);
             }
+            if (polar) {
+                T.Lpol = ar.take<cd>((size_t)N * nm);
+                T.born = ar.take<double>((size_t)9 * sys->n_atoms);
+            }
+            if (adaptive) {
+                T.vel = ar.take<double>((size_t)N * nW * 3);
+                T.vmax = ar.take<double>(4);
+                T.vbad = ar.take<int32_t>(1);
+            }
+            if (lw_out) T.lwacc = ar.take<double>((size_t)N * nm);
         };
         // band scratch is carved after the tables and reused by the batches
         size_t tables_end = 0, scratch_bands = 0;
@@ -500,7 +566,10 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
             electron_bands_dev(h, d1, sys, nullptr, nullptr, nullptr, mesh, N, nullptr, nullptr, s);
             phonon_dev(h, d2, sys, nullptr, nullptr, nullptr, mesh, N, 0, 0, nullptr, nullptr,
                        nullptr, nullptr, s);
-            scratch_bands = std::max(d1.used, d2.used) - tables_end;
+            Arena d3 = dry;
+            if (adaptive) velocity_dev(h, d3, sys, nullptr, nullptr, mesh, N, nullptr, nullptr, true,
+                                       nullptr, nullptr, s);
+            scratch_bands = std::max(std::max(d1.used, d2.used), d3.used) - tables_end;
         }
         // batch buffers (upper bound on the states of a batch: BK * nW)
         const int max_states = BK * nW;
@@ -516,16 +585,22 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                                    (size_t)max_states * n_qtiles * sizeof(double) +
                                    (factored ? (size_t)nsb * t12_state + 512 : 0) +
                                    (factored ? (size_t)nsb * NL * (n0_line + 1) * sizeof(uint32_t) +
-                                                   (size_t)rows_cap * nW * sizeof(uint32_t) + 512
+                                                   // nlive: 2 per sub-batch; sub-batches <= states + batches
+                                                   2 * (size_t)(rows_cap * nW + rows_cap + 1) *
+                                                       sizeof(uint32_t) + 512
                                              : 0) +
                                    (re_fact ? (size_t)rows_cap * 168 * sizeof(int32_t) + 1024
-                                            : 0);
+                                            : 0) +
+                                   (lw_out ? (factored ? (size_t)nsb * NL * n0_line
+                                                       : (size_t)max_states * N) *
+                                                     nm * sizeof(double) + 256
+                                           : 0);
         const bool all_planes =
             re_fact && tables_end + std::max(scratch_bands, batch_bytes + planes_cap * plane_bytes) +
                                256 <= h->budget;
         const size_t t0_bytes = re_fact ? (all_planes ? planes_cap : kD0Max) * plane_bytes : 0;
         ensure_ws(h, tables_end + std::max(scratch_bands, batch_bytes + t0_bytes) + 256);
-        Arena ar(h->ws);
+        Arena ar(h->ws, h->ws_cap);
         plan_tables(ar);
         {
             std::vector<int32_t> packed(n_rp);
@@ -578,6 +653,38 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
         HIPCHK(h, launch_fermi(T.eps, N * nW, par->mu, par->kT, T.focc, s));
         HIPCHK(h, launch_band_extrema(T.eps, N, nW, T.omega, N, nm, T.bmin, T.bmax, T.wmax, s));
         HIPCHK(h, launch_window(T.eps, N, nW, par->win_lo, par->win_hi, T.mask, T.flag, s));
+        if (polar) {
+            HIPCHK(h, hipMemcpyAsync(T.born, sys->polar->born, sizeof(double) * 9 * sys->n_atoms,
+                                     hipMemcpyHostToDevice, s));
+            HIPCHK(h, launch_polar_factor(nullptr, mesh, N, T.E, nm, polar_dev(sys, T.born), T.Lpol, s));
+        }
+        // adaptive smearing: velocities on the mesh; the widest width any transition
+        // can take bounds the final-band pruning
+        double sigma_bound = par->sigma;
+        const double ad_pref = adaptive ? par->adaptive_scale / std::sqrt(12.0) : 0.0;
+        const double ad_c[3] = {ad_pref * 2.0 * kPi / mesh.n0, ad_pref * 2.0 * kPi / mesh.n1,
+                                ad_pref * 2.0 * kPi / mesh.n2};
+        if (adaptive) {
+            Arena b3 = ar;
+            velocity_dev(h, b3, sys, T.rh, nullptr, mesh, N, T.eps, T.U, true, T.vel, T.vbad, s);
+            HIPCHK(h, launch_velocity_max(T.vel, N, nW, T.vmax, s));
+            double vm[3];
+            int32_t bad = 0;
+            HIPCHK(h, hipMemcpyAsync(vm, T.vmax, sizeof vm, hipMemcpyDeviceToHost, s));
+            HIPCHK(h, hipMemcpyAsync(&bad, T.vbad, sizeof bad, hipMemcpyDeviceToHost, s));
+            HIPCHK(h, hipStreamSynchronize(s));
+            if (bad) {
+                set_err(h, "a degenerate group of more than 8 bands in the velocity operator");
+                throw Fail{PHOEBE_E_UNSUPPORTED};
+            }
+            double s2 = 0.0;
+            for (int d = 0; d < 3; ++d) s2 += (ad_c[d] * 2.0 * vm[d]) * (ad_c[d] * 2.0 * vm[d]);
+            sigma_bound = std::max(par->sigma, std::sqrt(s2));
+        }
+        if (lw_out) {
+            HIPCHK(h, launch_zero(T.lwacc, sizeof(double) * N * nm, s));
+            HIPCHK(h, launch_zero(lw_out, sizeof(double) * N * nm, s));
+        }
         int64_t rows = nk;
         const int32_t* kept = k_idx;
         if (!k_idx) {
@@ -612,7 +719,7 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
             flush_timing(h, s);
             return;
         }
-        const double cut = 27.5 * par->sigma;  // exp(-27.5^2) underflows to 0 in FP64
+        const double cut = 27.5 * sigma_bound;  // exp(-27.5^2) underflows to 0 in FP64
         HIPCHK(h, launch_build_states(T.ids, nst, nW, kept, T.eps, T.bmin, T.bmax, T.wmax, cut,
                                       T.st_row, T.st_band, T.st_kmesh, T.st_mlo, T.st_mhi, s));
         if (dweights)
@@ -756,6 +863,9 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
         char* T2buf = factored ? ar.take<char>((size_t)nsb * Wbox * NL * nc_pad * g_elem) : nullptr;
         uint32_t* livebuf = factored ? ar.take<uint32_t>((size_t)nsb * NL * n0_line) : nullptr;
         uint32_t* lineany = factored ? ar.take<uint32_t>((size_t)nsb * NL) : nullptr;
+        double* lwbuf = lw_out ? ar.take<double>((factored ? (size_t)nsb * NL * n0_line
+                                                           : (size_t)max_states * N) * nm)
+                               : nullptr;
         // live (state, line) count of every factorised sub-batch (traffic accounting)
         int64_t n_sub = 0;
         if (factored)
@@ -771,7 +881,8 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
             HIPCHK(h, hipMemsetAsync(nlive, 0, 2 * sizeof(uint32_t) * std::max<int64_t>(n_sub, 1), s));
         int64_t isub = 0;
 
-        const double inv_sqrtpi_sigma = 1.0 / (std::sqrt(kPi) * par->sigma);
+        // adaptive: every term carries its own 1/sigma_t, so the common factor has sigma = 1
+        const double inv_sqrtpi_sigma = 1.0 / (std::sqrt(kPi) * (adaptive ? 1.0 : par->sigma));
         const double scale = 2.0 * kPi * inv_sqrtpi_sigma * (q_off ? 1.0 : 1.0 / (double)N);
         if (fold_fused)  // F's padding (rows >= n_rp, columns of no mode) is never written
             HIPCHK(h, launch_zero_fpad(Fbuf, max_states, rp_pad, nc_pad, n_rp, 16 * nm, (int)f_elem,
@@ -885,6 +996,11 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
             ra.n_qtiles = n_qtiles;
             ra.terms = terms ? terms + (int64_t)sbeg * N * nm : nullptr;
             ra.terms_scale = 2.0 * kPi * inv_sqrtpi_sigma;
+            ra.Lpol = polar ? T.Lpol : nullptr;
+            ra.vel = adaptive ? T.vel : nullptr;
+            for (int d = 0; d < 3; ++d) ra.ad_c[d] = ad_c[d];
+            ra.lw = lwbuf;
+            ra.inv_kT = 1.0 / par->kT;
             if (lowp && !factored) {
                 Timer t2(h, s, "stage2_rates");
                 RateArgsLP rl{};
@@ -900,9 +1016,11 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                 HIPCHK(h, launch_stage2_rates_lp(prec, rl, ns, s));
                 t2.done();
             } else if (!factored) {
+                if (lwbuf) HIPCHK(h, launch_zero(lwbuf, sizeof(double) * ns * N * nm, s));
                 Timer t2(h, s, "stage2_rates");
                 HIPCHK(h, launch_stage2_rates(ra, ns, s));
                 t2.done();
+                if (lwbuf) HIPCHK(h, launch_lw_reduce_dense(lwbuf, ns, N, nm, T.lwacc, s));
             } else {
                 ra.P0 = T.Pax;
                 ra.W = Wbox;
@@ -950,12 +1068,18 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                     // T2 of every live (state, line) read once; U_{k+q} of band m at the 16
                     // points of every unit
                     tl.done(0.0, nl, (double)g_elem * Wbox * nm * nW, nl + 1, 16.0 * nW * sizeof(cd));
+                    if (lwbuf)
+                        HIPCHK(h, launch_lw_reduce_lines(lwbuf, lineany, nn, (int)NL, mesh.n0, nm,
+                                                         T.lwacc, s));
                 }
             }
             HIPCHK(h, launch_reduce_partials(partial, ns, n_qtiles, T.st_row + sbeg,
                                              T.st_band + sbeg, nW, scale, gamma_out, s));
             sbeg = send;
         }
+        if (lw_out)  // (2 pi / N_k) n (n + 1) hbar omega x the sums, with the delta's 1/(sqrt(pi) sigma)
+            HIPCHK(h, launch_lw_finish(T.lwacc, T.omega, T.nb, N * nm, par->omega_min,
+                                       2.0 * kPi * inv_sqrtpi_sigma / (double)N, lw_out, s));
         HIPCHK(h, hipGetLastError());
         flush_timing(h, s);
     });
@@ -964,15 +1088,153 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
 extern "C" {
 
 phoebe_status phoebe_gpu_scatter_rates(void* handle, const phoebe_system* sys,
-                                       const int32_t mesh[3], const int32_t* k_idx, int64_t nk,
+                                       const int32_t k_mesh[3], const int32_t q_mesh[3],
+                                       const int32_t* k_idx, int64_t nk,
                                        const int64_t* q_off, const int32_t* q_idx,
                                        const double* q_w, const phoebe_rate_params* par,
                                        phoebe_precision prec, double* gamma_out,
                                        uint8_t* band_mask, int32_t* kept_k_out,
                                        int64_t* n_kept_out, void* stream) {
-    return scatter_rates_impl(handle, sys, mesh, k_idx, nk, q_off, q_idx, q_w, par, prec,
-                              gamma_out, band_mask, kept_k_out, n_kept_out, nullptr, nullptr,
-                              nullptr, nullptr, nullptr, true, -1, stream);
+    if (handle && !q_mesh) {
+        static_cast<Handle*>(handle)->err = "q_mesh is NULL";
+        return PHOEBE_E_INVALID;
+    }
+    return scatter_rates_impl(handle, sys, k_mesh, q_mesh, nullptr, k_idx, nk, q_off, q_idx, q_w,
+                              par, prec, gamma_out, band_mask, kept_k_out, n_kept_out, nullptr,
+                              nullptr, nullptr, nullptr, nullptr, true, -1, stream);
+}
+
+phoebe_status phoebe_gpu_phonon_linewidth(void* handle, const phoebe_system* sys,
+                                          const int32_t k_mesh[3], const int32_t q_mesh[3],
+                                          const phoebe_rate_params* par, phoebe_precision prec,
+                                          double* p_out, double* gamma_out, int64_t* n_kept_out,
+                                          void* stream) {
+    if (!handle) return PHOEBE_E_INVALID;
+    Handle* h = static_cast<Handle*>(handle);
+    if (!p_out || !q_mesh || !k_mesh) {
+        h->err = "p_out, k_mesh or q_mesh is NULL";
+        return PHOEBE_E_INVALID;
+    }
+    if (prec != PHOEBE_FP64) {
+        h->err = "the phonon linewidth is computed in FP64 only";
+        return prec >= PHOEBE_FP64 && prec <= PHOEBE_BF16 ? PHOEBE_E_UNSUPPORTED : PHOEBE_E_INVALID;
+    }
+    // the electron rates of the same pass go to gamma_out, or to workspace rows
+    double* g = gamma_out;
+    bool own = false;
+    if (!g) {
+        if (k_mesh[0] < 1 || k_mesh[1] < 1 || k_mesh[2] < 1) {
+            h->err = "mesh must be >= 1";
+            return PHOEBE_E_INVALID;
+        }
+        const size_t rows = (size_t)k_mesh[0] * k_mesh[1] * k_mesh[2];
+        if (sys && sys->n_wannier >= 1 && sys->n_wannier <= 64 && rows <= ((size_t)1 << 30)) {
+            if (hipMalloc(reinterpret_cast<void**>(&g), rows * sys->n_wannier * sizeof(double)) !=
+                hipSuccess) {
+                h->err = "hipMalloc of the rate rows failed";
+                return PHOEBE_E_NOMEM;
+            }
+            own = true;
+        }
+    }
+    const phoebe_status st = scatter_rates_impl(handle, sys, k_mesh, q_mesh, p_out, nullptr, 0,
+                                                nullptr, nullptr, nullptr, par, prec, g, nullptr,
+                                                nullptr, n_kept_out, nullptr, nullptr, nullptr,
+                                                nullptr, nullptr, true, -1, stream);
+    if (own) {
+        (void)hipStreamSynchronize(static_cast<hipStream_t>(stream));
+        (void)hipFree(g);
+    }
+    return st;
+}
+
+phoebe_status phoebe_gpu_set_check_finite(void* handle, int enable) {
+    if (!handle) return PHOEBE_E_INVALID;
+    static_cast<Handle*>(handle)->check_finite = enable != 0;
+    return PHOEBE_OK;
+}
+
+phoebe_status phoebe_gpu_velocities(void* handle, const phoebe_system* sys, const double* k_frac,
+                                    int64_t nk, double* eps_out, double* v_out, void* stream) {
+    if (!handle) return PHOEBE_E_INVALID;
+    Handle* h = static_cast<Handle*>(handle);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return run(h, [&] {
+        check_system(h, sys, true, false, false);
+        REQUIRE(h, nk >= 0, "nk < 0");
+        if (nk == 0) return;
+        REQUIRE(h, k_frac && v_out, "k_frac/v_out is NULL");
+        REQUIRE(h, sys->n_wannier <= 32, "n_wannier > 32 is not supported");
+        HIPCHK(h, hipSetDevice(h->device));
+        scan_finite(h, sys, true, false, false, s);
+        const int nW = sys->n_wannier;
+        auto plan = [&](Arena& ar) {
+            int32_t* rh = upload_r(h, ar, sys->rh, sys->n_rh, s);
+            double* eps = eps_out ? eps_out : ar.take<double>((size_t)nk * nW);
+            cd* U = ar.take<cd>((size_t)nk * nW * nW);
+            int32_t* bad = ar.take<int32_t>(1);
+            Arena a1 = ar, a2 = ar;
+            electron_bands_dev(h, a1, sys, rh, k_frac, nullptr, Mesh{1, 1, 1}, nk, eps, U, s);
+            velocity_dev(h, a2, sys, rh, k_frac, Mesh{1, 1, 1}, nk, eps, U, false, v_out, bad, s);
+            ar.used = std::max(a1.used, a2.used);
+            if (!ar.base) return;
+            int32_t b = 0;
+            HIPCHK(h, hipMemcpyAsync(&b, bad, sizeof b, hipMemcpyDeviceToHost, s));
+            HIPCHK(h, hipStreamSynchronize(s));
+            if (b) {
+                set_err(h, "a degenerate group of more than 8 bands in the velocity operator");
+                throw Fail{PHOEBE_E_UNSUPPORTED};
+            }
+        };
+        Arena dry(nullptr);
+        plan(dry);
+        ensure_ws(h, dry.used);
+        Arena ar(h->ws, h->ws_cap);
+        plan(ar);
+        HIPCHK(h, hipGetLastError());
+        HIPCHK(h, hipStreamSynchronize(s));
+        flush_timing(h, s);
+    });
+}
+
+phoebe_status phoebe_gpu_polar_factor(void* handle, const phoebe_system* sys, const double* q_frac,
+                                      int64_t nq, double omega_min, phoebe_c128* l_out,
+                                      void* stream) {
+    if (!handle) return PHOEBE_E_INVALID;
+    Handle* h = static_cast<Handle*>(handle);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return run(h, [&] {
+        check_system(h, sys, false, true, false);
+        REQUIRE(h, sys->polar != nullptr, "the system has no polar data");
+        check_polar(h, sys);
+        REQUIRE(h, nq >= 0, "nq < 0");
+        REQUIRE(h, std::isfinite(omega_min) && omega_min >= 0.0, "omega_min must be >= 0");
+        if (nq == 0) return;
+        REQUIRE(h, q_frac && l_out, "q_frac/l_out is NULL");
+        HIPCHK(h, hipSetDevice(h->device));
+        scan_finite(h, sys, false, true, false, s);
+        const int nm = 3 * sys->n_atoms;
+        auto plan = [&](Arena& ar) {
+            int32_t* rd = upload_r(h, ar, sys->rd, sys->n_rd, s);
+            double* born = ar.take<double>((size_t)9 * sys->n_atoms);
+            double* om = ar.take<double>((size_t)nq * nm);
+            cd* E = ar.take<cd>((size_t)nq * nm * nm);
+            phonon_dev(h, ar, sys, rd, q_frac, nullptr, Mesh{1, 1, 1}, nq, omega_min, 0.0, om, E,
+                       nullptr, nullptr, s);
+            if (!ar.base) return;
+            HIPCHK(h, hipMemcpyAsync(born, sys->polar->born, sizeof(double) * 9 * sys->n_atoms,
+                                     hipMemcpyHostToDevice, s));
+            HIPCHK(h, launch_polar_factor(q_frac, Mesh{1, 1, 1}, nq, E, nm, polar_dev(sys, born),
+                                          reinterpret_cast<cd*>(l_out), s));
+        };
+        Arena dry(nullptr);
+        plan(dry);
+        ensure_ws(h, dry.used);
+        Arena ar(h->ws, h->ws_cap);
+        plan(ar);
+        HIPCHK(h, hipGetLastError());
+        HIPCHK(h, hipStreamSynchronize(s));
+    });
 }
 
 phoebe_status phoebe_gpu_rate_terms(void* handle, const phoebe_system* sys, const int32_t mesh[3],
@@ -986,9 +1248,9 @@ phoebe_status phoebe_gpu_rate_terms(void* handle, const phoebe_system* sys, cons
         static_cast<Handle*>(handle)->err = "terms is NULL";
         return PHOEBE_E_INVALID;
     }
-    return scatter_rates_impl(handle, sys, mesh, k_idx, nk, nullptr, nullptr, nullptr, par,
-                              PHOEBE_FP64, gamma_out, nullptr, nullptr, nullptr, terms, st_row,
-                              st_band, n_states, dweights, true, max_states, stream);
+    return scatter_rates_impl(handle, sys, mesh, nullptr, nullptr, k_idx, nk, nullptr, nullptr,
+                              nullptr, par, PHOEBE_FP64, gamma_out, nullptr, nullptr, nullptr, terms,
+                              st_row, st_band, n_states, dweights, true, max_states, stream);
 }
 
 phoebe_status phoebe_gpu_delta_weights(void* handle, const phoebe_system* sys,
@@ -1001,9 +1263,10 @@ phoebe_status phoebe_gpu_delta_weights(void* handle, const phoebe_system* sys,
         static_cast<Handle*>(handle)->err = "dweights is NULL";
         return PHOEBE_E_INVALID;
     }
-    return scatter_rates_impl(handle, sys, mesh, k_idx, nk, nullptr, nullptr, nullptr, par,
-                              PHOEBE_FP64, gamma_scratch, nullptr, nullptr, nullptr, nullptr,
-                              st_row, st_band, n_states, dweights, false, max_states, stream);
+    return scatter_rates_impl(handle, sys, mesh, nullptr, nullptr, k_idx, nk, nullptr, nullptr,
+                              nullptr, par, PHOEBE_FP64, gamma_scratch, nullptr, nullptr, nullptr,
+                              nullptr, st_row, st_band, n_states, dweights, false, max_states,
+                              stream);
 }
 
 }  // extern "C"

@@ -192,6 +192,10 @@ phoebe_status phoebe_gpu_batched_plan(void* handle, const phoebe_system* systems
             const phoebe_system* sys = &systems[i];
             check_system(h, sys, true, true, true);
             const phoebe_rate_params* par = &params[i];
+            if (sys->polar || par->smearing != PHOEBE_SMEAR_GAUSSIAN) {
+                set_err(h, "system %d: the batched form takes non-polar systems with a fixed width", i);
+                throw Fail{PHOEBE_E_UNSUPPORTED};
+            }
             REQUIRE(h, std::isfinite(par->sigma) && par->sigma > 0.0, "system %d: sigma must be > 0", i);
             REQUIRE(h, std::isfinite(par->kT) && par->kT > 0.0, "system %d: kT must be > 0", i);
             REQUIRE(h, std::isfinite(par->omega_min) && par->omega_min >= 0.0, "system %d: omega_min", i);

@@ -67,7 +67,7 @@ void grad_impl(Handle* h, const Net& net, const T* P, const T* X, const T* targe
     Arena dry(nullptr);
     plan(dry, Z, A, dZ, dA, sums);
     ensure_ws(h, dry.used + 256);
-    Arena ar(h->ws);
+    Arena ar(h->ws, h->ws_cap);
     plan(ar, Z, A, dZ, dA, sums);
     forward_impl<T>(h, net, P, X, B, nullptr, Z, A, s);
     const int nblk = (int)std::min<int64_t>(256, (B + 255) / 256);
@@ -138,7 +138,7 @@ phoebe_status phoebe_gpu_mlp_forward(void* handle, phoebe_precision prec, const 
             Arena dry(nullptr);
             plan(dry);
             ensure_ws(h, dry.used + 256);
-            Arena ar(h->ws);
+            Arena ar(h->ws, h->ws_cap);
             plan(ar);
             forward_impl<T>(h, net, (const T*)params, (const T*)X, batch, (T*)out, Z, A, s);
         };
@@ -272,7 +272,7 @@ phoebe_status phoebe_gpu_propose_q(void* handle, const int32_t mesh[3], int32_t 
         Arena dry(nullptr);
         plan(dry);
         ensure_ws(h, dry.used + 256);
-        Arena ar(h->ws);
+        Arena ar(h->ws, h->ws_cap);
         plan(ar);
         std::vector<int64_t> offs(nk + 1);
         for (int64_t i = 0; i <= nk; ++i) offs[i] = i * S;

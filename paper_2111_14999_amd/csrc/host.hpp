@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 
+#include "ext.hpp"
 #include "kernels.hpp"
 #include "lowp.hpp"
 
@@ -44,6 +45,8 @@ struct Handle {
     std::string err;
     bool timing = false;
     int mesh_sum = 0;  // PHOEBE_MESH_SUM_AUTO / _DIRECT / _FACTORED
+    bool check_finite = false;
+    int32_t* dflag = nullptr;  // one device word for the finiteness scan (allocated on first use)
     std::vector<TimedLaunch> pending;
     std::vector<KernelStat> stats;
 };
@@ -53,16 +56,19 @@ struct Fail {
 };
 
 // Bump allocation over the handle's workspace.  A first pass with base ==
-// nullptr only sizes the request.
+// nullptr only sizes the request.  A take beyond the capacity of a real pass
+// (a sizing mistake) fails the call instead of handing out memory past the end.
 struct Arena {
     char* base;
     size_t used = 0;
-    explicit Arena(char* b) : base(b) {}
+    size_t cap = SIZE_MAX;
+    explicit Arena(char* b, size_t c = SIZE_MAX) : base(b), cap(c) {}
     template <class T>
     T* take(size_t count) {
         used = (used + 255) & ~(size_t)255;
         T* p = base ? reinterpret_cast<T*>(base + used) : nullptr;
         used += count * sizeof(T);
+        if (base && used > cap) throw Fail{PHOEBE_E_NOMEM};
         return p;
     }
 };
@@ -242,12 +248,80 @@ inline void phonon_dev(Handle* h, Arena& ar, const phoebe_system* sys, const int
                                  s));
 }
 
+inline void check_polar(Handle* h, const phoebe_system* sys) {
+    const phoebe_polar* p = sys->polar;
+    REQUIRE(h, p->born != nullptr, "polar: Born charges are NULL");
+    REQUIRE(h, std::isfinite(p->alpha) && p->alpha > 0.0, "polar: alpha must be > 0");
+    REQUIRE(h, p->g_max >= 0 && p->g_max <= 8, "polar: g_max must be in [0, 8]");
+    REQUIRE(h, sys->n_atoms <= 10, "polar: at most 10 atoms");
+    for (int i = 0; i < 9; ++i) REQUIRE(h, std::isfinite(p->eps_inf[i]), "polar: eps_inf not finite");
+    for (int i = 0; i < 9 * sys->n_atoms; ++i)
+        REQUIRE(h, std::isfinite(p->born[i]), "polar: Born charges not finite");
+}
+
+inline PolarDev polar_dev(const phoebe_system* sys, const double* born_dev) {
+    PolarDev d{};
+    d.born = born_dev;
+    for (int i = 0; i < 9; ++i) d.eps[i] = sys->polar->eps_inf[i];
+    d.alpha = sys->polar->alpha;
+    d.g_max = sys->polar->g_max;
+    d.nat = sys->n_atoms;
+    return d;
+}
+
+// Group velocities at points (fractional or mesh): the phase table, its
+// k-derivative form, dH/dk_a on MFMA and the projection with the eigenvectors
+// U (u_transposed: U[p, band, orbital], else columns).
+inline void velocity_dev(Handle* h, Arena& ar, const phoebe_system* sys, const int32_t* rh_d,
+                         const double* frac, Mesh m, int64_t np, const double* eps, const cd* U,
+                         bool u_transposed, double* v, int32_t* bad, hipStream_t s) {
+    const int nW = sys->n_wannier, nR = sys->n_rh;
+    cd* P = ar.take<cd>((size_t)np * nR);
+    cd* Pv = ar.take<cd>((size_t)np * 3 * nR);
+    cd* dH = ar.take<cd>((size_t)np * 3 * nW * nW);
+    if (!ar.base) return;
+    HIPCHK(h, launch_phase_table(frac, nullptr, m, np, rh_d, nR, P, nR, s));
+    HIPCHK(h, launch_velocity_phases(P, np, rh_d, nR, Pv, s));
+    HIPCHK(h, launch_zgemm(Pv, nR, reinterpret_cast<const cd*>(sys->h_r), (int64_t)nW * nW, dH,
+                           (int64_t)nW * nW, np * 3, (int64_t)nW * nW, nR, s));
+    HIPCHK(h, launch_zero(bad, sizeof(int32_t), s));
+    HIPCHK(h, launch_group_velocities(dH, U, u_transposed, eps, np, nW, 1e-6, v, bad, s));
+}
+
+// Optional finiteness scan of a system's tensors (phoebe_gpu_set_check_finite).
+inline void scan_finite(Handle* h, const phoebe_system* sys, bool hh, bool ph, bool g,
+                        hipStream_t s) {
+    if (!h->check_finite) return;
+    if (!h->dflag) HIPCHK(h, hipMalloc(reinterpret_cast<void**>(&h->dflag), sizeof(int32_t)));
+    int32_t* flag = h->dflag;
+    int32_t bad = 0;
+    {
+        HIPCHK(h, launch_zero(flag, sizeof(int32_t), s));
+        const int nW = sys->n_wannier, nm = 3 * sys->n_atoms;
+        if (hh) HIPCHK(h, launch_nonfinite(reinterpret_cast<const double*>(sys->h_r),
+                                           (int64_t)sys->n_rh * nW * nW * 2, flag, s));
+        if (ph) {
+            HIPCHK(h, launch_nonfinite(sys->phi_r, (int64_t)sys->n_rd * nm * nm, flag, s));
+            HIPCHK(h, launch_nonfinite(sys->mass, sys->n_atoms, flag, s));
+        }
+        if (g) HIPCHK(h, launch_nonfinite(reinterpret_cast<const double*>(sys->g_rr),
+                                          (int64_t)sys->n_re * sys->n_rp * nm * nW * nW * 2, flag, s));
+        HIPCHK(h, hipMemcpyAsync(&bad, flag, sizeof bad, hipMemcpyDeviceToHost, s));
+        HIPCHK(h, hipStreamSynchronize(s));
+    }
+    if (bad) {
+        set_err(h, "an input tensor holds NaN or infinity");
+        throw Fail{PHOEBE_E_NUMERIC};
+    }
+}
+
 inline phoebe_status run(Handle* h, const std::function<void()>& body) {
     try {
         h->err.clear();
         body();
         return PHOEBE_OK;
     } catch (const Fail& f) {
+        if (h->err.empty()) h->err = "workspace sizing error (internal)";
         return f.st;
     } catch (const std::bad_alloc&) {
         set_err(h, "host allocation failed");

@@ -98,6 +98,14 @@ struct RateArgs {
     const double* wmax;        // device scalar: largest phonon energy on the mesh
     const uint32_t* live;        // [nst, N1*N2, N0] live final bands of every point (line_live)
     const uint32_t* line_bands;  // [nst, N1*N2] union of a line's live bands, 0: none
+    // extensions, FP64 forms only (all null/unused in the plain rate sum):
+    const cd* Lpol;            // nullable [Nq, nm]: polar factor, g += i L(q,nu) [U_k^dag U_{k+q}]_nm
+    const double* vel;         // nullable [Nk, nW, 3]: adaptive smearing from the group velocities,
+                               // sigma_t = max(sigma, |ad_c . (v_nk - v_m,k+q)|), terms carry 1/sigma_t
+    double ad_c[3];            // (A / sqrt 12) 2 pi / N_d per axis
+    double* lw;                // nullable: phonon-linewidth partials of the launch's states
+                               // (line kernel [st, line, q0, nu]; direct kernel [st, q, nu], zeroed)
+    double inv_kT;             // 1 / kT (linewidth weight f (1 - f) / kT)
 };
 
 // Fused stage 2 (sum over Rp on MFMA) + rotations + rate terms.
@@ -170,7 +178,7 @@ hipError_t launch_line_live(const RateArgs& a, int nst, uint32_t* live, uint32_t
                             uint32_t* n_live, hipStream_t s);
 hipError_t launch_line_rates(const RateArgs& a, int nst, hipStream_t s);
 hipError_t launch_line_rates_f32(const RateArgs& a, int nst, hipStream_t s);
-size_t line_rates_lds(int W, int N0, int nm, bool f32);
+size_t line_rates_lds(int W, int N0, int nm, bool f32, bool lw = false);
 int line_rates_ncpad(int nm, int nW);  // -1 where the form does not apply
 
 // gamma[row, band] = scale * sum_t partial[st, t]

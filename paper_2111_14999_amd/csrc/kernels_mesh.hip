@@ -728,10 +728,26 @@ __global__ __launch_bounds__(256, 8) void line_live_kernel(RateArgs a, uint32_t*
         // band values two at a time (16-byte loads from an even band; rows are
         // nW doubles, nW even here); masks four at a time where N0 % 4 == 0
         const bool pairs = (nW & 1) == 0;
+        // adaptive smearing: each band's limit uses its own width at the point
+        const double* vn = a.vel ? a.vel + ((int64_t)kmesh * nW + a.st_band[st]) * 3 : nullptr;
         auto bits_of = [&](int q0) {
-            const double* ek = a.eps + ((int64_t)((k0i + q0) % N0) * NL + kq12) * nW;
+            const int64_t kq = (int64_t)((k0i + q0) % N0) * NL + kq12;
+            const double* ek = a.eps + kq * nW;
             uint32_t bits = 0;
-            if (pairs) {
+            if (vn) {
+                const double wm = *a.wmax;
+                for (int m = mlo; m <= mhi; ++m) {
+                    const double* vm = a.vel + (kq * nW + m) * 3;
+                    double s2 = 0.0;
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        const double t = a.ad_c[d] * (vn[d] - vm[d]);
+                        s2 += t * t;
+                    }
+                    const double sg = fmax(a.sigma, sqrt(s2));
+                    bits |= (uint32_t)(fabs(eps_n - ek[m]) <= 27.5 * sg + wm) << m;
+                }
+            } else if (pairs) {
                 for (int m = mlo & ~1; m <= mhi; m += 2) {
                     const double2 e2 = *reinterpret_cast<const double2*>(ek + m);
                     bits |= (uint32_t)(m >= mlo && fabs(eps_n - e2.x) <= lim) << m;
@@ -812,7 +828,9 @@ __device__ inline f4 mfma16(float x, float y, f4 c) {
 // building and the unit's gathers overlap them; KS = 0 loads them per K step.
 constexpr int kTP = 2;  // column tiles per MFMA pass
 
-template <int TN, int KS, class C>
+// EXT (FP64 only): the optional polar term, adaptive widths and linewidth
+// partials (RateArgs.Lpol / vel / lw), each switched on by its pointer.
+template <int TN, int KS, class C, bool EXT>
 __global__ __launch_bounds__(256, 4) void line_rates_kernel(RateArgs a) {
     using R = decltype(C::x);
     constexpr bool F64 = sizeof(R) == 8;
@@ -828,8 +846,11 @@ __global__ __launch_bounds__(256, 4) void line_rates_kernel(RateArgs a) {
     C* sY = sP + (N0 + 1) * Wp;                                // [16][nm]
     uint32_t* sPm = reinterpret_cast<uint32_t*>(sY + 16 * nm);  // [N0] live bands per point
     int* sList = reinterpret_cast<int*>(sPm + N0);             // [N0] live points of a band
+    // EXT: [N0][nm] linewidth partials of the work-group (8-byte aligned: N0 ints above)
+    double* sLW = reinterpret_cast<double*>(sList + N0 + (N0 & 1));
     __shared__ double sRed[4];
     __shared__ int sCount;
+    __shared__ cd sO[16];  // EXT: overlap [U_k^dagger U_{k+q}]_{n m} at the unit's points
 
     // XCD-aware order: work-groups are dealt to the 8 XCDs round-robin, so
     // with id = 8 j + x every state of a line lands on XCD x, one after
@@ -858,6 +879,24 @@ __global__ __launch_bounds__(256, 4) void line_rates_kernel(RateArgs a) {
     // |y| > 27.5 sigma: y^2/sigma^2 > 756 and exp(-756) is below the smallest
     // FP64 subnormal, so such a Gaussian is exactly 0
     const double cut = 27.5 * a.sigma;
+    // EXT per-state values: U_k column n (lane rows 4 lg + v), v_nk, f (1 - f) / kT
+    cd ukn[4] = {};
+    double vn[3] = {0.0, 0.0, 0.0};
+    double mdf = 0.0;
+    if constexpr (EXT) {
+        if (a.Lpol) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                if (4 * lg + v < nW) ukn[v] = a.U[((int64_t)kmesh * nW + nband) * nW + 4 * lg + v];
+        }
+        if (a.vel)
+            for (int d = 0; d < 3; ++d) vn[d] = a.vel[((int64_t)kmesh * nW + nband) * 3 + d];
+        if (a.lw) {
+            const double fn = a.focc[(int64_t)kmesh * nW + nband];
+            mdf = fn * (1.0 - fn) * a.inv_kT;
+            for (int i = tid; i < N0 * nm; i += 256) sLW[i] = 0.0;
+        }
+    }
     // tile row li loads column b = perm(li), see above
     const int bcol = F64 ? (((li & 3) << 2) | (li >> 2)) : li;
     const C* Tst = reinterpret_cast<const C*>(a.T2) + (int64_t)st * W * NL * ldf +
@@ -931,21 +970,49 @@ __global__ __launch_bounds__(256, 4) void line_rates_kernel(RateArgs a) {
     };
     // rate term of one item; E_q is read only for terms that survive the test
     double gacc = 0.0;
-    auto item_term = [&](int q0, int c, int nu, double em, double fm, double w, double nbq) {
+    auto item_term = [&](int q0, int c, int nu, double em, double fm, double w, double nbq, int m) {
         const double x = eps_n - em;
         const double y1 = x - w, y2 = x + w;
+        double is2 = inv_s2, cutv = cut, wt = 1.0;
+        if constexpr (EXT) {
+            if (a.vel) {  // adaptive width of the transition (k n) -> (k+q m)
+                const double* vm = a.vel + (kq_of(q0) * nW + m) * 3;
+                double s2 = 0.0;
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const double t = a.ad_c[d] * (vn[d] - vm[d]);
+                    s2 += t * t;
+                }
+                const double sg = fmax(a.sigma, sqrt(s2));
+                is2 = 1.0 / (sg * sg);
+                cutv = 27.5 * sg;
+                wt = 1.0 / sg;
+            }
+        }
         // both Gaussians underflow to exactly 0: the term is 0
-        if (fabs(y1) > cut && fabs(y2) > cut) return;
+        if (fabs(y1) > cutv && fabs(y2) > cutv) return;
         const int64_t q = (int64_t)q0 * NL + q12;
         const C* Yr = sY + c * nm;
         const cd* Eq = a.E + (q * nm + nu) * nm;
         C z = {0, 0};
         for (int sa = 0; sa < nm; ++sa) z = cfma(to_c<C>(Eq[sa]), Yr[sa], z);
-        const double g1 = exp(-y1 * y1 * inv_s2), g2 = exp(-y2 * y2 * inv_s2);
-        const double term = cabs2(z) * ((nbq + 1.0 - fm) * g1 + (nbq + fm) * g2);
+        if constexpr (EXT) {
+            if (a.Lpol) {  // + i L(q, nu) O_nm
+                const cd l = a.Lpol[q * nm + nu];
+                const cd o = sO[c];
+                z.x -= l.x * o.y + l.y * o.x;
+                z.y += l.x * o.x - l.y * o.y;
+            }
+        }
+        const double g1 = wt * exp(-y1 * y1 * is2), g2 = wt * exp(-y2 * y2 * is2);
+        const double z2 = cabs2(z);
+        const double term = z2 * ((nbq + 1.0 - fm) * g1 + (nbq + fm) * g2);
         gacc += term;
         if (a.terms)
             atomicAdd(&a.terms[((int64_t)st * a.nq_mesh + q) * nm + nu], a.terms_scale * term);
+        if constexpr (EXT) {
+            if (a.lw) sLW[q0 * nm + nu] += mdf * z2 * g1;  // one thread per (q0, nu) per unit
+        }
     };
 
     __syncthreads();  // sPm, sP
@@ -1039,9 +1106,21 @@ __global__ __launch_bounds__(256, 4) void line_rates_kernel(RateArgs a) {
                         reinterpret_cast<R*>(sY + li * nm + sa)[lg >> 1] = y;
                 }
             }
+            if constexpr (EXT) {
+                if (a.Lpol) {  // O at point li: sum over the lane's four b, then over the rows
+                    cd o = {0.0, 0.0};
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) o = cfmac(ukn[v], cd{(double)d.u[v].x, (double)d.u[v].y}, o);
+                    o.x += __shfl_xor(o.x, 16, 64);
+                    o.y += __shfl_xor(o.y, 16, 64);
+                    o.x += __shfl_xor(o.x, 32, 64);
+                    o.y += __shfl_xor(o.y, 32, 64);
+                    if (wave == 0 && lg == 0) sO[li] = o;
+                }
+            }
             __syncthreads();
             // Z[c, nu] = sum_sa E_q[sa, nu] Y[c, sa] and the rate terms
-            if (pc >= 0) item_term(pc, ic, inu, d.em, d.fm, d.om, d.nbq);
+            if (pc >= 0) item_term(pc, ic, inu, d.em, d.fm, d.om, d.nbq, m);
             for (int it = tid + 256; it < 16 * nm; it += 256) {
                 const int c = it / nm, nu = it - c * nm;
                 if (g + c >= cnt) continue;
@@ -1049,7 +1128,7 @@ __global__ __launch_bounds__(256, 4) void line_rates_kernel(RateArgs a) {
                 const int64_t q = (int64_t)q0 * NL + q12;
                 const int64_t kq = kq_of(q0);
                 item_term(q0, c, nu, a.eps[kq * nW + m], a.focc[kq * nW + m], a.omega[q * nm + nu],
-                          a.nb[q * nm + nu]);
+                          a.nb[q * nm + nu], m);
             }
             __syncthreads();  // sY (and the list, after a band's last unit) are rewritten
         }
@@ -1059,12 +1138,19 @@ __global__ __launch_bounds__(256, 4) void line_rates_kernel(RateArgs a) {
     if (lane == 0) sRed[wave] = gacc;
     __syncthreads();
     if (tid == 0) a.partial[(int64_t)st * a.n_qtiles + line] = (sRed[0] + sRed[1]) + (sRed[2] + sRed[3]);
+    if constexpr (EXT) {
+        if (a.lw) {  // (the last __syncthreads above ordered every sLW update)
+            double* o = a.lw + ((int64_t)st * NL + line) * N0 * nm;
+            for (int i = tid; i < N0 * nm; i += 256) o[i] = sLW[i];
+        }
+    }
 }
 
-size_t line_rates_lds(int W, int N0, int nm, bool f32) {
+size_t line_rates_lds(int W, int N0, int nm, bool f32, bool lw) {
     const int Wp = (W + 3) & ~3;
     return ((size_t)(N0 + 1) * Wp + 16 * (size_t)nm) * (f32 ? sizeof(cf) : sizeof(cd)) +
-           2 * (size_t)N0 * sizeof(uint32_t);
+           2 * (size_t)N0 * sizeof(uint32_t) +
+           (lw ? sizeof(uint32_t) * (size_t)(N0 & 1) + (size_t)N0 * nm * sizeof(double) : 0);
 }
 
 // Columns of the factorised form: one 16-wide tile per mode index, 4 waves x TN tiles.
@@ -1074,11 +1160,11 @@ int line_rates_ncpad(int nm, int nW) {
     return 64 * (tn == 5 ? 6 : (tn == 7 ? 8 : tn));
 }
 
-template <int TN, int KS, class C>
+template <int TN, int KS, class C, bool EXT>
 static hipError_t go_line(const RateArgs& a, int nst, hipStream_t s) {
-    const size_t shm = line_rates_lds(a.W, a.mesh.n0, a.nm, sizeof(C) == sizeof(cf));
+    const size_t shm = line_rates_lds(a.W, a.mesh.n0, a.nm, sizeof(C) == sizeof(cf), a.lw != nullptr);
     if (shm > 64 * 1024) return hipErrorInvalidValue;
-    hipError_t e = hipFuncSetAttribute((const void*)line_rates_kernel<TN, KS, C>,
+    hipError_t e = hipFuncSetAttribute((const void*)line_rates_kernel<TN, KS, C, EXT>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) return e;
     const int64_t NL = (int64_t)a.mesh.n1 * a.mesh.n2;
@@ -1097,9 +1183,10 @@ static hipError_t go_line(const RateArgs& a, int nst, hipStream_t s) {
         if (a.terms) b.terms = a.terms + (int64_t)s0 * a.nq_mesh * a.nm;
         b.live = a.live + (int64_t)s0 * a.mesh.n0 * NL;
         b.line_bands = a.line_bands + (int64_t)s0 * NL;
+        if (a.lw) b.lw = a.lw + (int64_t)s0 * NL * a.mesh.n0 * a.nm;
         b.n_states = ns;
-        hipLaunchKernelGGL((line_rates_kernel<TN, KS, C>), dim3((unsigned)(groups * 8 * ns)), dim3(256),
-                           shm, s, b);
+        hipLaunchKernelGGL((line_rates_kernel<TN, KS, C, EXT>), dim3((unsigned)(groups * 8 * ns)),
+                           dim3(256), shm, s, b);
     }
     return hipGetLastError();
 }
@@ -1111,13 +1198,29 @@ static hipError_t line_rates(const RateArgs& a, int nst, hipStream_t s) {
         line_rates_ncpad(a.nm, a.nW) != a.nc_pad || !a.live || !a.line_bands)
         return hipErrorInvalidValue;
     const bool pre = a.W <= 8;  // T2 rows fit two K steps: registers
+    const bool ext = a.Lpol || a.vel || a.lw;
+    if constexpr (sizeof(C) == sizeof(cd)) {
+        if (ext) {
+            switch (a.nc_pad / 64) {
+                case 1: return pre ? go_line<1, 2, C, true>(a, nst, s) : go_line<1, 0, C, true>(a, nst, s);
+                case 2: return pre ? go_line<2, 2, C, true>(a, nst, s) : go_line<2, 0, C, true>(a, nst, s);
+                case 3: return pre ? go_line<3, 2, C, true>(a, nst, s) : go_line<3, 0, C, true>(a, nst, s);
+                case 4: return pre ? go_line<4, 2, C, true>(a, nst, s) : go_line<4, 0, C, true>(a, nst, s);
+                case 6: return go_line<6, 0, C, true>(a, nst, s);
+                case 8: return go_line<8, 0, C, true>(a, nst, s);
+                default: return hipErrorInvalidValue;
+            }
+        }
+    } else {
+        if (ext) return hipErrorInvalidValue;  // the extensions are FP64 only
+    }
     switch (a.nc_pad / 64) {
-        case 1: return pre ? go_line<1, 2, C>(a, nst, s) : go_line<1, 0, C>(a, nst, s);
-        case 2: return pre ? go_line<2, 2, C>(a, nst, s) : go_line<2, 0, C>(a, nst, s);
-        case 3: return pre ? go_line<3, 2, C>(a, nst, s) : go_line<3, 0, C>(a, nst, s);
-        case 4: return pre ? go_line<4, 2, C>(a, nst, s) : go_line<4, 0, C>(a, nst, s);
-        case 6: return go_line<6, 0, C>(a, nst, s);
-        case 8: return go_line<8, 0, C>(a, nst, s);
+        case 1: return pre ? go_line<1, 2, C, false>(a, nst, s) : go_line<1, 0, C, false>(a, nst, s);
+        case 2: return pre ? go_line<2, 2, C, false>(a, nst, s) : go_line<2, 0, C, false>(a, nst, s);
+        case 3: return pre ? go_line<3, 2, C, false>(a, nst, s) : go_line<3, 0, C, false>(a, nst, s);
+        case 4: return pre ? go_line<4, 2, C, false>(a, nst, s) : go_line<4, 0, C, false>(a, nst, s);
+        case 6: return go_line<6, 0, C, false>(a, nst, s);
+        case 8: return go_line<8, 0, C, false>(a, nst, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -241,6 +241,16 @@ __global__ __launch_bounds__(256, (TN >= 12 ? 1 : 2)) void stage2_rates_kernel(R
     const double eps_n = a.eps[(int64_t)kmesh * nW + nband];
     const double inv_s2 = 1.0 / (a.sigma * a.sigma);
     double gacc = 0.0;
+    // extensions (FP64): v_nk for adaptive widths, f (1 - f) / kT for the linewidth
+    double vn[3] = {0.0, 0.0, 0.0};
+    if (a.vel)
+        for (int d = 0; d < 3; ++d) vn[d] = a.vel[((int64_t)kmesh * nW + nband) * 3 + d];
+    double mdf = 0.0;
+    if (a.lw) {
+        const double fn = a.focc[(int64_t)kmesh * nW + nband];
+        mdf = fn * (1.0 - fn) * a.inv_kT;
+    }
+    const cd* Ukn = a.U + ((int64_t)kmesh * nW + nband) * nW;  // U_k column n (transposed table)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         __syncthreads();
@@ -299,15 +309,37 @@ __global__ __launch_bounds__(256, (TN >= 12 ? 1 : 2)) void stage2_rates_kernel(R
                 cd z = {0.0, 0.0};
                 for (int sa = 0; sa < nm; ++sa) z = cfma(Eq[sa], Yr[sa], z);
                 const int m = m0 + mb;
+                if (a.Lpol) {  // + i L(q, nu) [U_k^dagger U_{k+q}]_{n m}
+                    const cd* Ukq = a.U + ((int64_t)kq * nW + m) * nW;
+                    cd o = {0.0, 0.0};
+                    for (int b = 0; b < nW; ++b) o = cfmac(Ukn[b], Ukq[b], o);
+                    const cd l = a.Lpol[q * nm + nu];
+                    z.x -= l.x * o.y + l.y * o.x;
+                    z.y += l.x * o.x - l.y * o.y;
+                }
+                double is2 = inv_s2, wt = 1.0;
+                if (a.vel) {  // adaptive width of the transition
+                    const double* vm = a.vel + ((int64_t)kq * nW + m) * 3;
+                    double s2 = 0.0;
+                    for (int d = 0; d < 3; ++d) {
+                        const double t = a.ad_c[d] * (vn[d] - vm[d]);
+                        s2 += t * t;
+                    }
+                    const double sg = fmax(a.sigma, sqrt(s2));
+                    is2 = 1.0 / (sg * sg);
+                    wt = 1.0 / sg;
+                }
                 const double x = eps_n - a.eps[(int64_t)kq * nW + m];
                 const double fm = a.focc[(int64_t)kq * nW + m];
                 const double w = a.omega[q * nm + nu], nbq = a.nb[q * nm + nu];
                 const double y1 = x - w, y2 = x + w;
-                const double g1 = exp(-y1 * y1 * inv_s2), g2 = exp(-y2 * y2 * inv_s2);
-                const double term = cabs2(z) * ((nbq + 1.0 - fm) * g1 + (nbq + fm) * g2);
+                const double g1 = wt * exp(-y1 * y1 * is2), g2 = wt * exp(-y2 * y2 * is2);
+                const double z2 = cabs2(z);
+                const double term = z2 * ((nbq + 1.0 - fm) * g1 + (nbq + fm) * g2);
                 gacc += sWq[c] * term;
                 if (a.terms)
                     atomicAdd(&a.terms[((int64_t)st * a.nq_mesh + q) * nm + nu], a.terms_scale * term);
+                if (a.lw) atomicAdd(&a.lw[((int64_t)st * a.nq_mesh + q) * nm + nu], mdf * z2 * g1);
             }
             __syncthreads();
         }
@@ -347,6 +379,7 @@ static hipError_t go_stage2(const RateArgs& a, int nst, hipStream_t s) {
         b.st_mhi += s0;
         b.partial = a.partial + (int64_t)s0 * a.n_qtiles;
         if (a.terms) b.terms = a.terms + (int64_t)s0 * a.nq_mesh * a.nm;
+        if (a.lw) b.lw = a.lw + (int64_t)s0 * a.nq_mesh * a.nm;
         hipLaunchKernelGGL((stage2_rates_kernel<TQ, TN>), dim3(a.n_qtiles, ns), dim3(256), shm, s,
                            b);
     }

@@ -1,0 +1,426 @@
+"""GPU parity of the observables beyond the plain rates, through the C ABI.
+
+* phonon linewidth P^{el-ph}_{q nu} (Transport Methods, phonon BTE) against
+  ``oracle.linewidth`` in both mesh-sum forms, bitwise repeatable;
+* polar long-range coupling (Electron Properties, g = g^S + g^L): L(q, nu),
+  the interpolated g and the rates against ``oracle.polar`` / ``coupling`` / ``rates``;
+* group velocities (Velocity) and adaptive smearing (Dirac delta and
+  Smearing) against ``oracle.velocity`` / ``rates``;
+* the 3-phonon coupling V3 (Phonon Properties) against ``oracle.phonon3``;
+* Philox streams, network initialisation, the training-set builder and the
+  row gather against ``oracle.rng`` / ``oracle.mlp``;
+* the finiteness scan (PHOEBE_E_NUMERIC) and a too-small workspace budget
+  (PHOEBE_E_NOMEM).
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_common import rel_err, torch_cuda, workload_params
+from helpers import group_sum_g2
+from oracle import constants, coupling, linewidth, mlp, phonon3, polar, rates, rng, velocity
+
+pytestmark = pytest.mark.gpu
+
+P_BOUND = 1e-9       # linewidth and rates, FP64 (entries above 1e-10 of the maximum)
+G2_BOUND = 1e-11     # degenerate-group |g|^2 relative to the pair's maximum
+V_BOUND = 1e-10      # velocities relative to max |v|
+V3_BOUND = 1e-11     # |V3| relative to max |V3|
+
+
+@pytest.fixture(scope="module")
+def lib():
+    torch_cuda()
+    from paper_2111_14999_amd import Library
+    L = Library(0)
+    yield L
+    L.close()
+
+
+def _params(s, mesh, width=0.8, sigma=0.05):
+    t = rates.mesh_tables(s, mesh)
+    mu = float(np.median(t["eps"]))
+    par = dict(mu=mu, kT=constants.kT_of(300.0), sigma=sigma, win_lo=mu - width,
+               win_hi=mu + width, omega_min=1e-4)
+    return t, par
+
+
+def _lw(lib, ds, mesh, par, nm):
+    torch = torch_cuda()
+    P = torch.full((int(np.prod(mesh)), nm), -1.0, dtype=torch.float64, device="cuda")
+    n = lib.phonon_linewidth(ds, mesh, par, P)
+    torch.cuda.synchronize()
+    return n, P.cpu().numpy()
+
+
+# ---------------------------------------------------------------------------
+# phonon linewidth
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("case", ["toy", "nW5-3x4x5", "nW16-2x3x4"])
+@pytest.mark.parametrize("form", ["direct", "factored"])
+def test_linewidth_matches_oracle(lib, case, form):
+    from paper_2111_14999_amd import DeviceSystem
+    if case == "toy":
+        s = synth.config_c1()
+        p = workload_params()["toy"]
+        mesh = tuple(p["mesh"])
+        par = dict(mu=p["mu"], kT=p["kT"], sigma=p["sigma"], win_lo=p["win_lo"],
+                   win_hi=p["win_hi"], omega_min=p["omega_min"])
+        t = rates.mesh_tables(s, mesh)
+    else:
+        nW, mesh = (5, (3, 4, 5)) if case == "nW5-3x4x5" else (16, (2, 3, 4))
+        s = synth.small_system(81, n_wannier=nW, n_atoms=2 if nW == 5 else 5, r=1)
+        s.h_r *= 0.3
+        t, par = _params(s, mesh)
+    print(f"[linewidth {case} {form}] mesh {mesh}", flush=True)
+    ref = linewidth.phonon_linewidth(s, mesh, tables=t, **par)
+    ds = DeviceSystem.from_host(s)
+    try:
+        lib.set_mesh_sum(form)
+        n, P = _lw(lib, ds, mesh, par, s.n_modes)
+        n2, P2 = _lw(lib, ds, mesh, par, s.n_modes)
+    finally:
+        lib.set_mesh_sum("auto")
+    assert n == len(ref["k_idx"])
+    assert np.array_equal(P, P2), "two calls differ"
+    mx, med, ab = rel_err(P, ref["P"])
+    print(f"  P rel err max {mx:.3e} median {med:.3e} (abs below floor {ab:.1e})", flush=True)
+    assert np.max(ref["P"]) > 0
+    assert mx < P_BOUND
+    assert ab < 1e-10 * np.max(ref["P"])
+
+
+def test_linewidth_gamma_by_product_and_errors(lib):
+    torch = torch_cuda()
+    from paper_2111_14999_amd import DeviceSystem, PhoebeError
+    s = synth.small_system(82, n_wannier=4, n_atoms=2, r=1)
+    s.h_r *= 0.3
+    mesh = (3, 3, 4)
+    t, par = _params(s, mesh)
+    ds = DeviceSystem.from_host(s)
+    N = int(np.prod(mesh))
+    P = torch.zeros((N, s.n_modes), dtype=torch.float64, device="cuda")
+    G = torch.zeros((N, s.n_wannier), dtype=torch.float64, device="cuda")
+    n = lib.phonon_linewidth(ds, mesh, par, P, gamma_out=G)
+    torch.cuda.synchronize()
+    ref = rates.scattering_rates(s, mesh, tables=t, **par)
+    mx, _, _ = rel_err(G.cpu().numpy()[:n], ref["gamma"])
+    assert mx < P_BOUND
+    for prec in ("fp32", "bf16x3"):
+        with pytest.raises(PhoebeError) as e:
+            lib.phonon_linewidth(ds, mesh, par, P, precision=prec)
+        assert e.value.status == -4
+    with pytest.raises(PhoebeError) as e:
+        lib.phonon_linewidth(ds, mesh, par, P, q_mesh=(3, 3, 5))
+    assert e.value.status == -4
+
+
+# ---------------------------------------------------------------------------
+# polar long-range coupling
+# ---------------------------------------------------------------------------
+def _polar_system(seed=91, nW=4, nat=2):
+    s = synth.small_system(seed, n_wannier=nW, n_atoms=nat, r=1)
+    s.h_r *= 0.3
+    return synth.add_polar(s, seed, alpha=3.0, g_max=3)
+
+
+def test_polar_factor_matches_oracle(lib):
+    torch = torch_cuda()
+    from paper_2111_14999_amd import DeviceSystem
+    from oracle.bands import phonon_modes
+    s = _polar_system()
+    q = np.random.default_rng(3).uniform(-1, 1, size=(40, 3))
+    w, z, _ = phonon_modes(q, s.rd, s.phi_r, s.mass)
+    l = coupling.phonon_length(w, s.mass, 1e-4)
+    ref = polar.polar_factor(q, z, l, s.born, s.eps_inf, s.ewald_alpha, s.g_max)
+    ds = DeviceSystem.from_host(s)
+    L = torch.zeros((40, s.n_modes), dtype=torch.complex128, device="cuda")
+    lib.polar_factor(ds, torch.from_numpy(q).cuda(), L)
+    torch.cuda.synchronize()
+    got = L.cpu().numpy()
+    # L carries the phase of each eigenvector: compare |L| (generic q, no degenerate modes)
+    err = np.max(np.abs(np.abs(got) - np.abs(ref))) / np.max(np.abs(ref))
+    print(f"[polar L] max ||L| - |L_ref|| / max |L| = {err:.2e}", flush=True)
+    assert err < 1e-12
+
+
+def test_polar_coupling_matches_oracle(lib):
+    torch = torch_cuda()
+    from paper_2111_14999_amd import DeviceSystem
+    s = _polar_system(92)
+    rng_ = np.random.default_rng(5)
+    k = rng_.uniform(-1, 1, size=(3, 3))
+    q = rng_.uniform(-1, 1, size=(20, 3))
+    ref = coupling.coupling(k, q, s)
+    ds = DeviceSystem.from_host(s)
+    nk, nq, nW, nm = 3, 20, s.n_wannier, s.n_modes
+    g = torch.empty((nk, nq, nm, nW, nW), dtype=torch.complex128, device="cuda")
+    lib.interp_g(ds, torch.from_numpy(k).cuda(), torch.from_numpy(q).cuda(), g)
+    torch.cuda.synchronize()
+    g = g.cpu().numpy()
+    worst = 0.0
+    for i in range(nk):
+        for j in range(nq):
+            a = group_sum_g2(g[i, j], ref["eps_k"][i], ref["eps_kq"][i, j], ref["omega_q"][j])
+            b = group_sum_g2(ref["g"][i, j], ref["eps_k"][i], ref["eps_kq"][i, j], ref["omega_q"][j])
+            worst = max(worst, np.max(np.abs(a - b)) / np.max(b))
+    print(f"[polar g] worst group |g|^2 err / pair max = {worst:.2e}", flush=True)
+    assert worst < G2_BOUND
+
+
+@pytest.mark.parametrize("form", ["direct", "factored"])
+def test_polar_rates_match_oracle(lib, form):
+    torch = torch_cuda()
+    from paper_2111_14999_amd import DeviceSystem
+    s = _polar_system(93, nW=5, nat=2)
+    mesh = (3, 4, 4)
+    t, par = _params(s, mesh)
+    ref = rates.scattering_rates(s, mesh, tables=t, **par)
+    ds = DeviceSystem.from_host(s)
+    N = int(np.prod(mesh))
+    gam = torch.zeros((N, s.n_wannier), dtype=torch.float64, device="cuda")
+    try:
+        lib.set_mesh_sum(form)
+        n = lib.scatter_rates(ds, mesh, par, gam)
+        P = torch.zeros((N, s.n_modes), dtype=torch.float64, device="cuda")
+        lib.phonon_linewidth(ds, mesh, par, P)
+    finally:
+        lib.set_mesh_sum("auto")
+    torch.cuda.synchronize()
+    assert n == len(ref["k_idx"])
+    mx, med, _ = rel_err(gam.cpu().numpy()[:n], ref["gamma"])
+    refP = linewidth.phonon_linewidth(s, mesh, tables=t, **par)["P"]
+    mp, _, _ = rel_err(P.cpu().numpy(), refP)
+    # the polar term matters here: the rates without it differ
+    s0 = synth.small_system(93, n_wannier=5, n_atoms=2, r=1)
+    s0.h_r *= 0.3
+    plain = rates.scattering_rates(s0, mesh, tables=t, **par)["gamma"]
+    diff, _, _ = rel_err(plain, ref["gamma"])
+    print(f"[polar rates {form}] Gamma err {mx:.2e} (median {med:.2e}), P err {mp:.2e}; "
+          f"without the polar term {diff:.2e}", flush=True)
+    assert diff > 1e-3
+    assert mx < P_BOUND and mp < P_BOUND
+
+
+# ---------------------------------------------------------------------------
+# velocities and adaptive smearing
+# ---------------------------------------------------------------------------
+def test_velocities_match_oracle(lib):
+    torch = torch_cuda()
+    from paper_2111_14999_amd import DeviceSystem
+    s = synth.small_system(61, n_wannier=6, n_atoms=2, r=2)
+    k = np.random.default_rng(3).uniform(-1, 1, size=(50, 3))
+    eps, v = velocity.group_velocities(k, s.rh, s.h_r)
+    ds = DeviceSystem.from_host(s)
+    V = torch.zeros((50, s.n_wannier, 3), dtype=torch.float64, device="cuda")
+    E = torch.zeros((50, s.n_wannier), dtype=torch.float64, device="cuda")
+    lib.velocities(ds, torch.from_numpy(k).cuda(), V, eps_out=E)
+    torch.cuda.synchronize()
+    err = np.max(np.abs(V.cpu().numpy() - v)) / np.max(np.abs(v))
+    print(f"[velocity] max |v - v_ref| / max |v| = {err:.2e}", flush=True)
+    assert err < V_BOUND
+    assert np.max(np.abs(E.cpu().numpy() - eps)) < 1e-12 * np.max(np.abs(eps))
+
+
+def test_velocities_degenerate_pair(lib):
+    """Two orbitals degenerate on the k_x = k_y plane: the 2x2 velocity block is
+    diagonalised per direction (closed form, and the oracle)."""
+    torch = torch_cuda()
+    from paper_2111_14999_amd import DeviceSystem
+    R = synth.box_vectors(1)
+    h = np.zeros((27, 2, 2), dtype=np.complex128)
+    idx = {tuple(r): i for i, r in enumerate(R)}
+    t = 0.7
+    h[idx[(1, 0, 0)], 0, 0] = h[idx[(-1, 0, 0)], 0, 0] = t
+    h[idx[(0, 1, 0)], 1, 1] = h[idx[(0, -1, 0)], 1, 1] = t
+    rng_ = np.random.default_rng(0)
+    a = (rng_.standard_normal((2, 2)) + 1j * rng_.standard_normal((2, 2)))
+    W, _ = np.linalg.qr(a)
+    h = np.conj(W.T)[None] @ h @ W[None]   # a Wannier rotation mixes the two orbitals
+    s = synth.small_system(1, n_wannier=2, n_atoms=1, r=1)
+    s.rh, s.h_r = R, np.ascontiguousarray(h)
+    kap = 0.13
+    k = np.array([[kap, kap, 0.3], [0.21, 0.21, -0.4]])
+    eps, v = velocity.group_velocities(k, s.rh, s.h_r)
+    ds = DeviceSystem.from_host(s)
+    V = torch.zeros((2, 2, 3), dtype=torch.float64, device="cuda")
+    lib.velocities(ds, torch.from_numpy(k).cuda(), V)
+    torch.cuda.synchronize()
+    got = V.cpu().numpy()
+    vx = -2 * t * np.sin(2 * np.pi * kap)
+    closed = np.array([sorted([vx, 0.0]), sorted([vx, 0.0]), [0.0, 0.0]]).T   # [band, alpha]
+    assert np.max(np.abs(got[0] - closed)) < 1e-12
+    assert np.max(np.abs(got - v)) < 1e-12
+
+
+@pytest.mark.parametrize("form", ["direct", "factored"])
+def test_adaptive_rates_and_linewidth_match_oracle(lib, form):
+    torch = torch_cuda()
+    from paper_2111_14999_amd import DeviceSystem
+    s = synth.small_system(94, n_wannier=5, n_atoms=2, r=1)
+    s.h_r *= 0.3
+    mesh = (4, 3, 4)
+    t, par = _params(s, mesh, sigma=0.02)
+    ad = dict(sigma_min=0.02, prefactor=1.3)
+    ref = rates.scattering_rates(s, mesh, tables=t, adaptive=ad, **par)
+    refP = linewidth.phonon_linewidth(s, mesh, tables=t, adaptive=ad, **par)["P"]
+    ds = DeviceSystem.from_host(s)
+    par_g = dict(par, smearing="adaptive", adaptive_scale=1.3)
+    N = int(np.prod(mesh))
+    gam = torch.zeros((N, s.n_wannier), dtype=torch.float64, device="cuda")
+    P = torch.zeros((N, s.n_modes), dtype=torch.float64, device="cuda")
+    try:
+        lib.set_mesh_sum(form)
+        n = lib.scatter_rates(ds, mesh, par_g, gam)
+        lib.phonon_linewidth(ds, mesh, par_g, P)
+    finally:
+        lib.set_mesh_sum("auto")
+    torch.cuda.synchronize()
+    assert n == len(ref["k_idx"])
+    mx, med, _ = rel_err(gam.cpu().numpy()[:n], ref["gamma"])
+    mp, _, _ = rel_err(P.cpu().numpy(), refP)
+    fixed = rates.scattering_rates(s, mesh, tables=t, **par)["gamma"]
+    diff, _, _ = rel_err(fixed, ref["gamma"])
+    print(f"[adaptive {form}] Gamma err {mx:.2e} (median {med:.2e}), P err {mp:.2e}; "
+          f"fixed width differs by {diff:.2e}", flush=True)
+    assert diff > 1e-3
+    assert mx < P_BOUND and mp < P_BOUND
+
+
+# ---------------------------------------------------------------------------
+# 3-phonon coupling
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("nat", [1, 2])
+def test_v3_matches_oracle(lib, nat):
+    torch = torch_cuda()
+    from paper_2111_14999_amd import DeviceSystem3
+    s = synth.small_system(5 + nat, n_wannier=1, n_atoms=nat, r=1)
+    r, phi3 = synth.third_order_constants(5 + nat, nat)
+    s.r1, s.r2, s.phi3 = r, r, phi3
+    g = np.random.default_rng(nat)
+    q = g.uniform(-1, 1, size=(3, 3))
+    qp = g.uniform(-1, 1, size=(7, 3))
+    ref = phonon3.interp_v3(q, qp, s)
+    d3 = DeviceSystem3.from_host(s, r, phi3)
+    nm = 3 * nat
+    V = torch.zeros((3, 7, nm, nm, nm), dtype=torch.complex128, device="cuda")
+    W3 = torch.zeros((3, 7, nm), dtype=torch.float64, device="cuda")
+    lib.interp_v3(d3, torch.from_numpy(q).cuda(), torch.from_numpy(qp).cuda(), V, omega_qpp=W3)
+    torch.cuda.synchronize()
+    got = V.cpu().numpy()
+    err = np.max(np.abs(np.abs(got) - np.abs(ref["v3"]))) / np.max(np.abs(ref["v3"]))
+    werr = np.max(np.abs(W3.cpu().numpy() - ref["omega_qpp"])) / np.max(ref["omega_qpp"])
+    print(f"[V3 nat={nat}] max ||V3| - ref| / max = {err:.2e}; omega'' err {werr:.1e}", flush=True)
+    assert err < V3_BOUND
+    assert werr < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# Philox streams, initialisation, training set, gather
+# ---------------------------------------------------------------------------
+def test_philox_streams_bit_exact(lib):
+    torch = torch_cuda()
+    u = torch.zeros(100_003, dtype=torch.float64, device="cuda")
+    lib.philox_uniform(1234, 77, u)
+    r = torch.zeros(50_001, dtype=torch.int32, device="cuda")
+    lib.philox_randint(99, 5, 64_000, r)
+    torch.cuda.synchronize()
+    assert np.array_equal(u.cpu().numpy(), rng.uniform(1234, 77, 100_003))
+    assert np.array_equal(r.cpu().numpy().astype(np.int64), rng.randint(99, 5, 50_001, 64_000))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16"])
+def test_mlp_init_bit_exact(lib, precision):
+    torch = torch_cuda()
+    n_in, width, depth = 22, 32, 3
+    n = lib.mlp_param_count(n_in, width, depth)
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    th = torch.full((n,), 7.0, dtype=dt, device="cuda")
+    lib.mlp_init(th, n_in, width, depth, seed=17, precision=precision)
+    torch.cuda.synchronize()
+    ref = mlp.init_params_philox(17, n_in, width, depth)
+    got = th.cpu().numpy()
+    if precision == "fp64":
+        assert np.array_equal(got, ref)
+    else:
+        assert np.array_equal(got, ref.astype(np.float32))
+
+
+def test_training_set_matches_oracle(lib):
+    torch = torch_cuda()
+    g = np.random.default_rng(4)
+    ns, nq, nm = 5, 301, 6
+    D = g.exponential(size=(ns, nq, nm)) * (g.uniform(size=(ns, nq, nm)) > 0.3)
+    T = D * g.lognormal(size=D.shape)
+    Tt, Dt = torch.from_numpy(T).cuda(), torch.from_numpy(D).cuda()
+    for max_samples in (10 ** 9, 1500):
+        cap = 20_000
+        o_s = torch.zeros(cap, dtype=torch.int32, device="cuda")
+        o_q = torch.zeros_like(o_s)
+        o_v = torch.zeros_like(o_s)
+        o_y = torch.zeros(cap, dtype=torch.float32, device="cuda")
+        n, c = lib.training_set(Tt, Dt, ns, 0.05, 1e-3, max_samples, 11, o_s, o_q, o_v, o_y)
+        torch.cuda.synchronize()
+        st, q, nu, y, c_ref = mlp.training_set(T, D, 0.05, 1e-3, max_samples, 11)
+        assert n == len(st)
+        assert np.array_equal(o_s.cpu().numpy()[:n], st)
+        assert np.array_equal(o_q.cpu().numpy()[:n], q)
+        assert np.array_equal(o_v.cpu().numpy()[:n], nu)
+        assert abs(c - c_ref) <= 1e-13 * abs(c_ref)
+        assert np.max(np.abs(o_y.cpu().numpy()[:n] - y) / np.maximum(np.abs(y), 1.0)) < 1e-6
+
+
+def test_gather_rows_bit_exact(lib):
+    torch = torch_cuda()
+    from paper_2111_14999_amd import PhoebeError
+    X = torch.randn(1000, 37, device="cuda", dtype=torch.float32)
+    idx = torch.from_numpy(np.random.default_rng(2).integers(0, 1000, 4096).astype(np.int32)).cuda()
+    out = torch.zeros(4096, 37, device="cuda", dtype=torch.float32)
+    lib.gather_rows(X, idx, out)
+    torch.cuda.synchronize()
+    assert torch.equal(out, X[idx.long()])
+    bad = idx.clone()
+    bad[7] = 1000
+    with pytest.raises(PhoebeError) as e:
+        lib.gather_rows(X, bad, out)
+    assert e.value.status == -1
+
+
+# ---------------------------------------------------------------------------
+# validation: non-finite inputs and a too-small budget
+# ---------------------------------------------------------------------------
+def test_check_finite_and_nomem():
+    torch = torch_cuda()
+    from paper_2111_14999_amd import DeviceSystem, Library, PhoebeError
+    s = synth.small_system(83, n_wannier=4, n_atoms=2, r=1)
+    mesh = (3, 3, 3)
+    t, par = _params(s, mesh)
+    L = Library(0)
+    try:
+        ds = DeviceSystem.from_host(s)
+        gam = torch.zeros((27, 4), dtype=torch.float64, device="cuda")
+        L.set_check_finite(True)
+        L.scatter_rates(ds, mesh, par, gam)          # finite inputs pass
+        ds.g_rr[3, 5, 1, 2, 0] = complex(float("nan"), 0.0)
+        with pytest.raises(PhoebeError) as e:
+            L.scatter_rates(ds, mesh, par, gam)
+        assert e.value.status == -5
+        ds.g_rr[3, 5, 1, 2, 0] = 0.0
+        ds.h_r[0, 0, 0] = complex(float("inf"), 0.0)
+        with pytest.raises(PhoebeError) as e:
+            L.electron_bands(ds, torch.zeros((2, 3), dtype=torch.float64, device="cuda"),
+                             torch.zeros((2, 4), dtype=torch.float64, device="cuda"))
+        assert e.value.status == -5
+    finally:
+        L.close()
+    small = Library(0, workspace_budget=1 << 16)
+    try:
+        ds = DeviceSystem.from_host(s)
+        gam = torch.zeros((27, 4), dtype=torch.float64, device="cuda")
+        with pytest.raises(PhoebeError) as e:
+            small.scatter_rates(ds, mesh, par, gam)
+        assert e.value.status == -2
+        assert "budget" in str(e.value)
+    finally:
+        small.close()

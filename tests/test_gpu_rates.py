@@ -144,11 +144,27 @@ def test_argument_errors(lib, toy):
     from paper_2111_14999_amd import binding
     c = ds.c_struct()
     m = (ctypes.c_int32 * 3)(*mesh)
-    p = binding.CRateParams(par["mu"], par["kT"], par["sigma"], par["win_lo"], par["win_hi"], 1e-4)
-    st = lib.lib.phoebe_gpu_scatter_rates(lib.handle, ctypes.byref(c), m, None, 0, None, None, None,
-                                          ctypes.byref(p), 7, gamma.data_ptr(), None, None, None,
-                                          None)
+    p = binding.rate_params(par)
+    st = lib.lib.phoebe_gpu_scatter_rates(lib.handle, ctypes.byref(c), m, m, None, 0, None, None,
+                                          None, ctypes.byref(p), 7, gamma.data_ptr(), None, None,
+                                          None, None)
     assert st == -1
+    # smearing enum out of range; adaptive scale <= 0; a q mesh other than the k mesh
+    with pytest.raises(PhoebeError) as e:
+        lib.scatter_rates(ds, mesh, dict(par, smearing="adaptive", adaptive_scale=0.0), gamma)
+    assert e.value.status == -1
+    p.smearing = 5
+    st = lib.lib.phoebe_gpu_scatter_rates(lib.handle, ctypes.byref(c), m, m, None, 0, None, None,
+                                          None, ctypes.byref(p), 0, gamma.data_ptr(), None, None,
+                                          None, None)
+    assert st == -1
+    with pytest.raises(PhoebeError) as e:
+        lib.scatter_rates(ds, mesh, par, gamma, q_mesh=(mesh[0] * 2, mesh[1], mesh[2]))
+    assert e.value.status == -4
+    # the extensions are FP64 only
+    with pytest.raises(PhoebeError) as e:
+        lib.scatter_rates(ds, mesh, dict(par, smearing="adaptive"), gamma, precision="fp32")
+    assert e.value.status == -4
 
 
 # ---------------------------------------------------------------------------
