@@ -65,20 +65,47 @@ def silu_prime(z):
     return s * (1.0 + z * (1.0 - s))
 
 
-def forward(theta, X, n_in, width, depth, n_out=1):
-    """Network output [B, n_out] and the pre-activations of every layer."""
+def round_bf16(x):
+    """Nearest bfloat16 value of each entry (8 significant bits, ties to even).
+
+    The entries are first taken to float32, the storage of the BF16 network's
+    operands; x = m 2^e with m in [0.5, 1) is rounded at 2^(e-8) by numpy's
+    round-half-to-even.  Used to state the BF16 arithmetic exactly: operands
+    of every matrix product rounded to BF16, products and sums exact.
+    """
+    f = np.asarray(x, dtype=np.float32).astype(np.float64)
+    m, e = np.frexp(f)
+    return np.ldexp(np.rint(np.ldexp(m, 8)), e - 8)
+
+
+def _ident(x):
+    return x
+
+
+def forward(theta, X, n_in, width, depth, n_out=1, operand=None):
+    """Network output [B, n_out] and the pre-activations of every layer.
+
+    ``operand`` (default: none) is applied to both inputs of every matrix
+    product, e.g. ``round_bf16`` for the BF16 arithmetic.
+    """
+    op = operand or _ident
     layers = unpack(np.asarray(theta, dtype=np.float64), n_in, width, depth, n_out)
     a = np.asarray(X, dtype=np.float64)
     zs = []
     for li, (W, b) in enumerate(layers):
-        z = a @ W.T + b
+        z = op(a) @ op(W).T + b
         zs.append(z)
         a = z if li == len(layers) - 1 else silu(z)
     return a, zs
 
 
-def loss_and_grad(theta, X, t, n_in, width, depth, n_out=1):
-    """MSE loss and its gradient with respect to the packed parameters."""
+def loss_and_grad(theta, X, t, n_in, width, depth, n_out=1, operand=None):
+    """MSE loss and its gradient with respect to the packed parameters.
+
+    ``operand`` as in ``forward``: applied to both inputs of every matrix
+    product of the forward and backward passes.
+    """
+    op = operand or _ident
     X = np.asarray(X, dtype=np.float64)
     t = np.asarray(t, dtype=np.float64).reshape(X.shape[0], n_out)
     layers = unpack(np.asarray(theta, dtype=np.float64), n_in, width, depth, n_out)
@@ -86,7 +113,7 @@ def loss_and_grad(theta, X, t, n_in, width, depth, n_out=1):
     zs = []
     a = X
     for li, (W, b) in enumerate(layers):
-        z = a @ W.T + b
+        z = op(a) @ op(W).T + b
         zs.append(z)
         a = z if li == len(layers) - 1 else silu(z)
         acts.append(a)
@@ -97,11 +124,11 @@ def loss_and_grad(theta, X, t, n_in, width, depth, n_out=1):
     dz = 2.0 * (y - t) / B                     # dL/dz_L (linear output)
     for li in range(len(layers) - 1, -1, -1):
         W, _ = layers[li]
-        dW = dz.T @ acts[li]                   # [out, in]
+        dW = op(dz).T @ op(acts[li])           # [out, in]
         db = dz.sum(axis=0)
         grads.append((dW, db))
         if li > 0:
-            da = dz @ W                        # dL/da_{l-1}
+            da = op(dz) @ op(W)                # dL/da_{l-1}
             dz = da * silu_prime(zs[li - 1])
     grads.reverse()
     flat = np.concatenate([np.concatenate([dW.ravel(), db]) for dW, db in grads])

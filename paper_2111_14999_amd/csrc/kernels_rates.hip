@@ -129,6 +129,10 @@ __global__ __launch_bounds__(256, (TN >= 12 ? 1 : 2)) void stage2_rates_kernel(R
     off = (off + 15) & ~(size_t)15;
     cd* sX = reinterpret_cast<cd*>(smem_raw + off);           // [CQ][nc_pad]
     cd* sY = sX + CQ * a.nc_pad;                              // [CQ][kMB][nm]
+    // per-term outputs (terms or linewidth, never both): [CQ][kMB][nm], summed
+    // over the bands of a pass in order by one thread per (q, mode)
+    double* sT = reinterpret_cast<double*>(sY + CQ * kMB * nm);
+    double* const tout = a.terms ? a.terms : a.lw;
     __shared__ double sRed[4];
     __shared__ int sKq[CQ];
     __shared__ int sQ[CQ];
@@ -337,11 +341,19 @@ __global__ __launch_bounds__(256, (TN >= 12 ? 1 : 2)) void stage2_rates_kernel(R
                 const double z2 = cabs2(z);
                 const double term = z2 * ((nbq + 1.0 - fm) * g1 + (nbq + fm) * g2);
                 gacc += sWq[c] * term;
-                if (a.terms)
-                    atomicAdd(&a.terms[((int64_t)st * a.nq_mesh + q) * nm + nu], a.terms_scale * term);
-                if (a.lw) atomicAdd(&a.lw[((int64_t)st * a.nq_mesh + q) * nm + nu], mdf * z2 * g1);
+                if (tout) sT[(c * kMB + mb) * nm + nu] = a.terms ? a.terms_scale * term : mdf * z2 * g1;
             }
             __syncthreads();
+            if (tout) {  // (state, q) belongs to this work-group alone: plain adds, fixed order
+                for (int it = tid; it < CQ * nm; it += 256) {
+                    const int c = it / nm, nu = it - c * nm;
+                    if (sKq[c] < 0) continue;
+                    double sum = 0.0;
+                    for (int mb = 0; mb < nmb; ++mb) sum += sT[(c * kMB + mb) * nm + nu];
+                    tout[((int64_t)st * a.nq_mesh + sQ[c]) * nm + nu] += sum;
+                }
+                __syncthreads();
+            }
         }
     }
     // fixed-order reduction of the work-group's partial sum
@@ -353,17 +365,19 @@ __global__ __launch_bounds__(256, (TN >= 12 ? 1 : 2)) void stage2_rates_kernel(R
         a.partial[(int64_t)st * a.n_qtiles + qt] = (sRed[0] + sRed[1]) + (sRed[2] + sRed[3]);
 }
 
-static size_t stage2_lds(int TQ, int rmax, int rp_pad, int nc_pad, int nm) {
+static size_t stage2_lds(int TQ, int rmax, int rp_pad, int nc_pad, int nm, bool per_term) {
     const int BQ = 16 * TQ, CQ = 4 * TQ, W = 2 * rmax + 1;
     size_t shm = (size_t)BQ * 3 * W * sizeof(cd) + (size_t)rp_pad * sizeof(int);
     shm = (shm + 15) & ~(size_t)15;
     shm += (size_t)CQ * nc_pad * sizeof(cd) + (size_t)CQ * kMB * nm * sizeof(cd);
+    if (per_term) shm += (size_t)CQ * kMB * nm * sizeof(double);
     return shm;
 }
 
 template <int TQ, int TN>
 static hipError_t go_stage2(const RateArgs& a, int nst, hipStream_t s) {
-    const size_t shm = stage2_lds(TQ, a.rmax, a.rp_pad, a.nc_pad, a.nm);
+    if (a.terms && a.lw) return hipErrorInvalidValue;
+    const size_t shm = stage2_lds(TQ, a.rmax, a.rp_pad, a.nc_pad, a.nm, a.terms || a.lw);
     if (shm > 160 * 1024 - 1024) return hipErrorInvalidValue;
     hipError_t e = hipFuncSetAttribute((const void*)stage2_rates_kernel<TQ, TN>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);

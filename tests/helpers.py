@@ -28,6 +28,9 @@ def group_sum_g2(g, eps_n, eps_m, omega, tol=1e-6):
     ln = degenerate_groups(eps_n, tol)
     lm = degenerate_groups(eps_m, tol)
     lv = degenerate_groups(omega, tol)
+    if len(np.unique(ln)) == len(ln) and len(np.unique(lm)) == len(lm) and \
+            len(np.unique(lv)) == len(lv):
+        return g2  # no degeneracy: every group is one entry
     out = np.zeros_like(g2)
     for a in np.unique(lv):
         va = lv == a

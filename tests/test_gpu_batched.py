@@ -67,7 +67,7 @@ def test_graph_replays_match_oracle(setup, tmp_path):
             mx, med, ab = rel_err(g, r["gamma"])
             print(f"  system {i}: {plan.info(i)} Gamma rel err max {mx:.2e} median {med:.2e}",
                   flush=True)
-            assert mx < 1e-4
+            assert mx < 1e-6
         if first is None:
             first = got
         else:

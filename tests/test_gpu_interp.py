@@ -84,3 +84,42 @@ def test_shapes(lib, nW, nat, r):
     ref = coupling.coupling(k, q, s)
     got = _run(lib, s, k, q)
     _compare(got, ref, 1e-11)
+
+
+def test_realistic_size_bench_launch(lib):
+    """Realistic system (nW 16, 15 modes, 343 Re and Rp) in the launch bench times.
+
+    Two mesh k points against the whole 40^3 q mesh in one call, as bench.py
+    times it; 64 seeded q of the result are checked against the oracle, which
+    evaluates those pairs one by one.
+    """
+    torch = torch_cuda()
+    from paper_2111_14999_amd import DeviceSystem
+    s = synth.config_c2()
+    mesh = (40, 40, 40)
+    N = int(np.prod(mesh))
+    rng = np.random.default_rng(31)
+    ik = np.sort(rng.choice(N, size=2, replace=False))
+    iq = np.sort(rng.choice(N, size=64, replace=False))
+
+    def frac(idx):
+        i0, r = np.divmod(idx, mesh[1] * mesh[2])
+        i1, i2 = np.divmod(r, mesh[2])
+        return np.stack([i0 / mesh[0], i1 / mesh[1], i2 / mesh[2]], axis=1)
+
+    k = frac(ik)
+    q_all = frac(np.arange(N))
+    ds = DeviceSystem.from_host(s)
+    nW, nm = s.n_wannier, s.n_modes
+    g = torch.empty((2, N, nm, nW, nW), dtype=torch.complex128, device="cuda")
+    ek = torch.empty((2, nW), dtype=torch.float64, device="cuda")
+    ekq = torch.empty((2, N, nW), dtype=torch.float64, device="cuda")
+    lib.interp_g(ds, torch.from_numpy(k).cuda(), torch.from_numpy(q_all).cuda(), g,
+                 omega_min=1e-4, eps_k=ek, eps_kq=ekq)
+    torch.cuda.synchronize()
+    sel = torch.from_numpy(iq).cuda()
+    got = dict(g=g[:, sel].cpu().numpy(), eps_k=ek.cpu().numpy(), eps_kq=ekq[:, sel].cpu().numpy())
+    del g, ekq, ds
+    print("GPU done", flush=True)
+    ref = coupling.coupling(k, q_all[iq], s)
+    _compare(got, ref, 1e-11)

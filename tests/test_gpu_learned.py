@@ -3,7 +3,8 @@ and the importance-sampled rate estimate (unbiasedness and gain).
 
 * gradients and outputs of the FP64 kernel path match the oracle's hand-written
   backpropagation to 1e-10; the BF16 path (BF16 operands, FP32 accumulation)
-  to the stated BF16 bound;
+  matches, entry by entry, the same backpropagation with every product's
+  operands rounded to BF16;
 * one Adam step matches the oracle's update;
 * the per-(q, mode) terms sum to the rate the plain path returns;
 * importance sampling with the trained proposal: its mean over seeds is the
@@ -70,16 +71,32 @@ def test_bf16_gradients_and_adam(lib):
     t32 = t.astype(np.float32)
     loss_ref, g_ref = mlp.loss_and_grad(theta32.astype(np.float64), X32.astype(np.float64),
                                         t32.astype(np.float64), n_in, width, depth)
+    # the BF16 arithmetic stated exactly: every product's operands rounded to BF16
+    loss_b, g_b = mlp.loss_and_grad(theta32.astype(np.float64), X32.astype(np.float64),
+                                    t32.astype(np.float64), n_in, width, depth,
+                                    operand=mlp.round_bf16)
     P = torch.from_numpy(theta32).cuda()
     g = torch.zeros_like(P)
     loss = lib.mlp_grad(P, torch.from_numpy(X32).cuda(), torch.from_numpy(t32).cuda(), g, n_in,
                         width, depth, precision="bf16")
     torch.cuda.synchronize()
     gg = g.cpu().numpy().astype(np.float64)
-    rel = np.linalg.norm(gg - g_ref) / np.linalg.norm(g_ref)
-    print(f"bf16 loss {loss:.6f} vs {loss_ref:.6f}; grad rel L2 err {rel:.2e}", flush=True)
-    assert abs(loss - loss_ref) < 2e-2 * loss_ref
-    assert rel < 5e-2
+    # entry by entry: FP32 accumulation and FP32 activations differ from the oracle's
+    # FP64 ones by ~1e-7 relative; an activation that lands on the other side of a
+    # BF16 rounding boundary moves a few entries by up to ~0.5 % of one product
+    gmax = np.max(np.abs(g_b))
+    dif = np.abs(gg - g_b)
+    big = np.abs(g_b) > 1e-3 * gmax
+    rel = dif[big] / np.abs(g_b[big])
+    rel_plain = np.linalg.norm(gg - g_ref) / np.linalg.norm(g_ref)
+    print(f"bf16 loss {loss:.6f} vs {loss_b:.6f} (FP64 {loss_ref:.6f}); grad vs BF16 oracle: "
+          f"max rel {rel.max():.2e}, median {np.median(rel):.2e}, frac > 1e-3 "
+          f"{np.mean(rel > 1e-3):.2e}, max abs/max {dif.max() / gmax:.2e}; "
+          f"vs FP64 rel L2 {rel_plain:.2e}", flush=True)
+    assert abs(loss - loss_b) < 1e-5 * loss_b
+    assert np.all(dif <= 1e-3 * np.abs(g_b) + 3e-5 * gmax)
+    assert np.mean(rel > 1e-3) < 1e-2
+    assert np.median(rel) < 1e-5
     # one Adam step from zero moments, on the oracle's gradient
     gm = torch.from_numpy(g_ref.astype(np.float32)).cuda()
     m = torch.zeros_like(P)
@@ -204,38 +221,49 @@ def test_features_match_definition(lib):
         assert np.max(np.abs(X.cpu().numpy() - ref)) < 1e-14
 
 
-def _train_proposal(lib, torch, T, D, kk_of_state, eps_of_state, mesh, nm, e0, escale, width,
-                    depth, steps, seed, n_harm, thr=1e-6):
-    """Fit ln(terms / weights + c) on the (state, q, nu) samples with weights > thr x max."""
-    ns, N, _ = T.shape
-    dmax = D.reshape(ns, -1).max(axis=1)
-    sel = D > thr * dmax[:, None, None]
-    si, qi, vi = np.nonzero(sel)
-    ratio = T[si, qi, vi] / D[si, qi, vi]
-    c = 1e-3 * ratio.mean()
-    y = np.log(ratio + c).astype(np.float32)
+def _train_proposal(lib, torch, terms, dw, ns, kk_of_state, eps_of_state, mesh, nm, e0, escale,
+                    width, depth, steps, seed, n_harm, thr=1e-6):
+    """Fit ln(terms / weights + c) on the (state, q, nu) samples with weights > thr x max.
+
+    Every step runs in the library: the training set (selection, targets),
+    the per-sample state tables and features, the parameter initialisation
+    and the minibatch draws (Philox streams) and gathers.
+    """
+    N = terms.shape[1]
+    cap = ns * N * nm
+    o_st = torch.zeros(cap, dtype=torch.int32, device="cuda")
+    o_q = torch.zeros(cap, dtype=torch.int32, device="cuda")
+    o_nu = torch.zeros(cap, dtype=torch.int32, device="cuda")
+    o_y = torch.zeros(cap, dtype=torch.float32, device="cuda")
+    B, c = lib.training_set(terms, dw, ns, thr, 1e-3, cap, seed, o_st, o_q, o_nu, o_y)
+    kk_s = torch.zeros((B, 1), dtype=torch.int32, device="cuda")
+    e_s = torch.zeros((B, 1), dtype=torch.float64, device="cuda")
+    lib.gather_rows(torch.from_numpy(kk_of_state.astype(np.int32)[:, None].copy()).cuda(), o_st[:B],
+                    kk_s)
+    lib.gather_rows(torch.from_numpy(eps_of_state[:, None].copy()).cuda(), o_st[:B], e_s)
     n_in = lib.mlp_feature_count(nm, n_harm)
-    B = len(si)
     X = torch.zeros((B, n_in), dtype=torch.float32, device="cuda")
-    lib.mlp_features(mesh, nm, torch.from_numpy(kk_of_state[si].astype(np.int32)).cuda(),
-                     torch.from_numpy(eps_of_state[si]).cuda(),
-                     torch.from_numpy(qi.astype(np.int32)).cuda(),
-                     torch.from_numpy(vi.astype(np.int32)).cuda(), X, e0, escale, n_harm=n_harm)
-    Y = torch.from_numpy(y).cuda()
-    theta = torch.from_numpy(mlp.init_params(np.random.default_rng(seed), n_in, width,
-                                             depth).astype(np.float32)).cuda()
+    lib.mlp_features(mesh, nm, kk_s[:, 0].contiguous(), e_s[:, 0].contiguous(), o_q[:B],
+                     o_nu[:B], X, e0, escale, n_harm=n_harm)
+    Y = o_y[:B].contiguous()
+    theta = torch.zeros(lib.mlp_param_count(n_in, width, depth), dtype=torch.float32,
+                        device="cuda")
+    lib.mlp_init(theta, n_in, width, depth, seed=seed, precision="bf16")
     g = torch.zeros_like(theta)
     m = torch.zeros_like(theta)
     v = torch.zeros_like(theta)
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(seed)
+    bs = min(2048, B)
+    idx = torch.zeros(bs, dtype=torch.int32, device="cuda")
+    Xb = torch.zeros((bs, n_in), dtype=torch.float32, device="cuda")
+    Yb = torch.zeros(bs, dtype=torch.float32, device="cuda")
     losses = []
     for step in range(1, steps + 1):
-        idx = torch.randint(0, B, (min(2048, B),), device="cuda", generator=gen)
-        losses.append(lib.mlp_grad(theta, X[idx].contiguous(), Y[idx].contiguous(), g, n_in,
-                                   width, depth, precision="bf16"))
+        lib.philox_randint(seed + 1, (step - 1) * bs, B, idx)
+        lib.gather_rows(X, idx, Xb)
+        lib.gather_rows(Y[:, None], idx, Yb[:, None])
+        losses.append(lib.mlp_grad(theta, Xb, Yb, g, n_in, width, depth, precision="bf16"))
         lib.mlp_adam(theta, g, m, v, step, 3e-3 if step < steps // 2 else 1e-3)
-    return theta, losses, float(np.var(y))
+    return theta, losses, float(np.var(Y.cpu().numpy().astype(np.float64)))
 
 
 def test_importance_sampling_unbiased_with_gain(lib):
@@ -268,15 +296,14 @@ def test_importance_sampling_unbiased_with_gain(lib):
     ns = lib.rate_terms(ds, mesh, par, torch.from_numpy(train_k).cuda(), gam, terms, dweights=dw,
                         st_row=strow, st_band=stband)
     torch.cuda.synchronize()
-    T, D = terms[:ns].cpu().numpy(), dw[:ns].cpu().numpy()
     rows, bands = strow[:ns].cpu().numpy(), stband[:ns].cpu().numpy()
     kk = train_k[rows]
     width, depth, H = 64, 3, 2
-    theta, losses, yvar = _train_proposal(lib, torch, T, D, kk, t["eps"][kk, bands], mesh, nm, mu,
-                                          1.0, width, depth, 2000, 11, H)
+    theta, losses, yvar = _train_proposal(lib, torch, terms, dw, ns, kk, t["eps"][kk, bands], mesh,
+                                          nm, mu, 1.0, width, depth, 2000, 11, H)
     print(f"training loss {losses[0]:.3f} -> {np.mean(losses[-20:]):.3f} (target var {yvar:.3f})",
           flush=True)
-    assert np.mean(losses[-20:]) < 0.8 * yvar
+    assert np.mean(losses[-20:]) < 0.5 * yvar
 
     # held-out kept k, the lowest band in the window of each
     test_k = np.array([k for k in kept if k not in set(train_k)][:6], dtype=np.int32)
@@ -296,10 +323,11 @@ def test_importance_sampling_unbiased_with_gain(lib):
     full = rates.scattering_rates(s, mesh, k_idx=test_k, tables=t, **par)["gamma"][np.arange(nk), tb]
     S, seeds = 48, 40
     est = {"learned": [], "smearing": [], "uniform": []}
-    ugen = np.random.default_rng(99)
     lists0 = None
+    u = torch.zeros(nk * S, dtype=torch.float64, device="cuda")
+    qu_d = torch.zeros(nk * S, dtype=torch.int32, device="cuda")
     for sd in range(seeds):
-        u = torch.from_numpy(ugen.uniform(0, 1, size=nk * S)).cuda()
+        lib.philox_uniform(99, sd * nk * S, u)
         for name, prm in (("learned", theta), ("smearing", None)):
             q_off = torch.zeros(nk + 1, dtype=torch.int64, device="cuda")
             q_idx = torch.zeros(nk * S, dtype=torch.int32, device="cuda")
@@ -313,11 +341,10 @@ def test_importance_sampling_unbiased_with_gain(lib):
             if lists0 is None:
                 lists0 = (q_off.cpu().numpy(), q_idx.cpu().numpy(), q_w.cpu().numpy(),
                           est[name][-1].copy())
-        qu = ugen.integers(0, N, size=nk * S).astype(np.int32)
-        wu = np.full(nk * S, 1.0 / S)  # uniform p = 1/N: w = 1/(N S p) = 1/S
+        lib.philox_randint(199, sd * nk * S, N, qu_d)
+        wu = torch.full((nk * S,), 1.0 / S, dtype=torch.float64, device="cuda")  # w = 1/(N S p)
         gu = torch.zeros((nk, nW), dtype=torch.float64, device="cuda")
-        lib.scatter_rates(ds, mesh, par, gu, k_idx=kd,
-                          q_lists=(q_off, torch.from_numpy(qu).cuda(), torch.from_numpy(wu).cuda()))
+        lib.scatter_rates(ds, mesh, par, gu, k_idx=kd, q_lists=(q_off, qu_d, wu))
         torch.cuda.synchronize()
         est["uniform"].append(gu.cpu().numpy()[np.arange(nk), tb])
     est = {k: np.array(v) for k, v in est.items()}

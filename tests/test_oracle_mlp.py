@@ -6,10 +6,12 @@
 * Adam: the first step moves each parameter by lr * sign(g) (bias correction);
 * importance sampling: the exact expectation of sum_j w_j t(q_j) over the
   proposal equals the mesh average, for any proposal with full support;
-* inverse CDF against a brute-force scan.
+* inverse CDF against a brute-force scan;
+* BF16 rounding: ties to even at known points and torch's CPU bfloat16 cast.
 """
 
 import numpy as np
+import pytest
 
 from oracle import mlp
 
@@ -86,3 +88,38 @@ def test_inverse_cdf_brute_force():
             j += 1
         assert gj == j
         assert p[gj] > 0
+
+
+def test_round_bf16_ties_and_library():
+    """Round to nearest even at 8 significant bits; agrees with torch's CPU bfloat16 cast."""
+    torch = pytest.importorskip("torch")
+    one = 1.0
+    assert mlp.round_bf16(one + 2.0 ** -8) == 1.0                      # tie -> even (down)
+    assert mlp.round_bf16(one + 3 * 2.0 ** -8) == 1.0 + 2.0 ** -6      # tie -> even (up)
+    assert mlp.round_bf16(one + 2.0 ** -8 + 2.0 ** -20) == 1.0 + 2.0 ** -7
+    assert mlp.round_bf16(-3.0) == -3.0 and mlp.round_bf16(0.0) == 0.0
+    rng = np.random.default_rng(3)
+    x = (rng.standard_normal(50_000) * 10.0 ** rng.integers(-6, 6, 50_000)).astype(np.float32)
+    ref = torch.from_numpy(x).to(torch.bfloat16).float().numpy().astype(np.float64)
+    assert np.array_equal(mlp.round_bf16(x), ref)
+
+
+def test_operand_rounding_reaches_every_product():
+    """With BF16-exact parameters and inputs the first product is exact; rounding the
+    operands changes the gradient of every layer (it reaches the backward products)."""
+    rng = np.random.default_rng(4)
+    n_in, width, depth, B = 5, 7, 2, 9
+    theta = mlp.round_bf16(mlp.init_params(rng, n_in, width, depth))
+    X = mlp.round_bf16(rng.standard_normal((B, n_in)))
+    t = rng.standard_normal(B)
+    y0, z0 = mlp.forward(theta, X, n_in, width, depth)
+    y1, z1 = mlp.forward(theta, X, n_in, width, depth, operand=mlp.round_bf16)
+    assert np.allclose(z0[0], z1[0], rtol=0, atol=1e-15)
+    _, g0 = mlp.loss_and_grad(theta, X, t, n_in, width, depth)
+    _, g1 = mlp.loss_and_grad(theta, X, t, n_in, width, depth, operand=mlp.round_bf16)
+    off = 0
+    for o, i in mlp.layer_shapes(n_in, width, depth):
+        dw0, dw1 = g0[off:off + o * i], g1[off:off + o * i]
+        assert np.max(np.abs(dw0 - dw1)) > 0
+        assert np.max(np.abs(dw0 - dw1)) < 2e-2 * np.max(np.abs(dw0))
+        off += o * i + o
