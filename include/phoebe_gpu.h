@@ -242,6 +242,32 @@ phoebe_status phoebe_gpu_scatter_rates(void *handle, const phoebe_system *sys,
                                        int32_t *kept_k_out, int64_t *n_kept_out,
                                        void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): phoebe_gpu_scatter_rates
+ * with the same arguments, results and errors, whose workspace is a static
+ * device array of phoebe_gpu_noalloc_scratch_bytes() bytes (256 MiB less one
+ * flag block) instead of the handle's workspace.  The call performs no device
+ * allocation or free (and takes no timing records).  A problem whose workspace
+ * does not fit fails with PHOEBE_E_NOMEM before any launch; the planner sizes
+ * its batches to the scratch, so moderate meshes fit (the tables of a 40^3
+ * mesh with nW = 16 alone do not).  Every call on one device shares that
+ * device's array and leaves its contents behind: calls that overlap on one
+ * device (two streams, two threads, two handles) race and must be ordered by
+ * the caller.  The array's address is resolved once per device when the first
+ * handle on that device is created. */
+phoebe_status phoebe_gpu_scatter_rates_noalloc(void *handle, const phoebe_system *sys,
+                                               const int32_t k_mesh[3], const int32_t q_mesh[3],
+                                               const int32_t *k_idx, int64_t nk,
+                                               const int64_t *q_off, const int32_t *q_idx,
+                                               const double *q_w,
+                                               const phoebe_rate_params *par,
+                                               phoebe_precision prec, double *gamma_out,
+                                               uint8_t *band_mask, int32_t *kept_k_out,
+                                               int64_t *n_kept_out, void *stream);
+
+/* Usable bytes of the static scratch of phoebe_gpu_scatter_rates_noalloc. */
+size_t phoebe_gpu_noalloc_scratch_bytes(void);
+
 /* Batched form: many independent systems (different nW, nModes, lattice-vector
  * sets and meshes) evaluated together (Transport Methods, electron lifetime,
  * per system exactly as phoebe_gpu_scatter_rates over the full q mesh with

@@ -39,7 +39,8 @@ EXPORTS = (
     "phoebe_gpu_phonon_linewidth", "phoebe_gpu_velocities", "phoebe_gpu_polar_factor",
     "phoebe_gpu_interp_v3", "phoebe_gpu_philox_uniform", "phoebe_gpu_philox_randint",
     "phoebe_gpu_mlp_init", "phoebe_gpu_training_set", "phoebe_gpu_gather_rows",
-    "phoebe_gpu_set_check_finite",
+    "phoebe_gpu_set_check_finite", "phoebe_gpu_scatter_rates_noalloc",
+    "phoebe_gpu_noalloc_scratch_bytes",
 )
 
 SMEARING = {"gaussian": 0, "adaptive": 1}
@@ -120,6 +121,9 @@ def load(path: str = LIB_PATH):
                                              ctypes.POINTER(i32), ctypes.POINTER(i32), vp, i64,
                                              vp, vp, vp, ctypes.POINTER(CRateParams), ctypes.c_int,
                                              vp, vp, vp, ctypes.POINTER(i64), vp]
+    lib.phoebe_gpu_scatter_rates_noalloc.argtypes = lib.phoebe_gpu_scatter_rates.argtypes
+    lib.phoebe_gpu_noalloc_scratch_bytes.restype = ctypes.c_size_t
+    lib.phoebe_gpu_noalloc_scratch_bytes.argtypes = []
     lib.phoebe_gpu_phonon_linewidth.argtypes = [vp, ctypes.POINTER(CSystem), ctypes.POINTER(i32),
                                                 ctypes.POINTER(i32), ctypes.POINTER(CRateParams),
                                                 ctypes.c_int, vp, vp, ctypes.POINTER(i64), vp]
@@ -177,7 +181,7 @@ def load(path: str = LIB_PATH):
                                          ctypes.c_double, i32, vp, vp, vp, vp, vp]
     for name in EXPORTS:
         if name not in ("phoebe_gpu_abi_version", "phoebe_gpu_last_error",
-                        "phoebe_gpu_mlp_param_count"):
+                        "phoebe_gpu_mlp_param_count", "phoebe_gpu_noalloc_scratch_bytes"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -374,6 +378,29 @@ class Library:
             _ptr(q_w), ctypes.byref(p), PRECISIONS[precision], _ptr(gamma_out), _ptr(band_mask),
             _ptr(kept_k_out), ctypes.byref(n_kept), _stream(stream)))
         return int(n_kept.value)
+
+    def scatter_rates_noalloc(self, sys: DeviceSystem, mesh, params: dict, gamma_out,
+                              k_idx=None, q_lists=None, precision="fp64", band_mask=None,
+                              kept_k_out=None, stream=None, q_mesh=None) -> int:
+        """scatter_rates with the library's static device scratch (no device allocation)."""
+        c = sys.c_struct()
+        m = (ctypes.c_int32 * 3)(*[int(x) for x in mesh])
+        mq = (ctypes.c_int32 * 3)(*[int(x) for x in (mesh if q_mesh is None else q_mesh)])
+        p = rate_params(params)
+        nk = 0 if k_idx is None else int(k_idx.shape[0])
+        q_off = q_idx = q_w = None
+        if q_lists is not None:
+            q_off, q_idx, q_w = q_lists
+        n_kept = ctypes.c_int64(0)
+        self._check(self.lib.phoebe_gpu_scatter_rates_noalloc(
+            self.handle, ctypes.byref(c), m, mq, _ptr(k_idx), nk, _ptr(q_off), _ptr(q_idx),
+            _ptr(q_w), ctypes.byref(p), PRECISIONS[precision], _ptr(gamma_out), _ptr(band_mask),
+            _ptr(kept_k_out), ctypes.byref(n_kept), _stream(stream)))
+        return int(n_kept.value)
+
+    @staticmethod
+    def noalloc_scratch_bytes() -> int:
+        return int(load().phoebe_gpu_noalloc_scratch_bytes())
 
     def phonon_linewidth(self, sys: DeviceSystem, mesh, params: dict, p_out, gamma_out=None,
                          precision="fp64", stream=None, q_mesh=None) -> int:

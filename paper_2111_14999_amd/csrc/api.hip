@@ -52,6 +52,9 @@ phoebe_status phoebe_gpu_create(int device, size_t budget, void** handle) {
     }
     h->device = device;
     h->budget = budget;
+    // the static scratch of phoebe_gpu_scatter_rates_noalloc on this device; a failed
+    // lookup leaves it NULL and only that entry point reports it
+    if (noalloc_scratch_init(device, &h->scratch) != hipSuccess) h->scratch = nullptr;
     *handle = h;
     g_create_error.clear();
     return PHOEBE_OK;

@@ -19,6 +19,10 @@ namespace phx {
 
 extern std::string g_create_error;
 
+// Device address of the non-allocating entry point's static scratch on `device`
+// (the current device), resolved once per device; hipSuccess or the lookup's error.
+hipError_t noalloc_scratch_init(int device, char** ptr);
+
 
 
 struct TimedLaunch {
@@ -47,6 +51,8 @@ struct Handle {
     int mesh_sum = 0;  // PHOEBE_MESH_SUM_AUTO / _DIRECT / _FACTORED
     bool check_finite = false;
     int32_t* dflag = nullptr;  // one device word for the finiteness scan (allocated on first use)
+    char* scratch = nullptr;   // the device's static scratch of the non-allocating entry point
+    bool fixed_ws = false;     // during such a call: ws is that scratch and is never reallocated
     std::vector<TimedLaunch> pending;
     std::vector<KernelStat> stats;
 };
@@ -102,6 +108,11 @@ inline void set_err(Handle* h, const char* fmt, ...) {
 
 inline void ensure_ws(Handle* h, size_t bytes) {
     if (bytes <= h->ws_cap) return;
+    if (h->fixed_ws) {
+        set_err(h, "workspace of %zu bytes exceeds the %zu-byte static scratch of the "
+                   "non-allocating entry point", bytes, h->ws_cap);
+        throw Fail{PHOEBE_E_NOMEM};
+    }
     if (bytes > h->budget) {
         set_err(h, "workspace of %zu bytes exceeds the budget of %zu bytes", bytes, h->budget);
         throw Fail{PHOEBE_E_NOMEM};
@@ -292,6 +303,10 @@ inline void velocity_dev(Handle* h, Arena& ar, const phoebe_system* sys, const i
 inline void scan_finite(Handle* h, const phoebe_system* sys, bool hh, bool ph, bool g,
                         hipStream_t s) {
     if (!h->check_finite) return;
+    if (!h->dflag && h->fixed_ws) {
+        set_err(h, "no flag word for the finiteness scan");
+        throw Fail{PHOEBE_E_DEVICE};
+    }
     if (!h->dflag) HIPCHK(h, hipMalloc(reinterpret_cast<void**>(&h->dflag), sizeof(int32_t)));
     int32_t* flag = h->dflag;
     int32_t bad = 0;
