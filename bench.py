@@ -219,6 +219,7 @@ def main():
 
     # interp_g element rate (all (nu, n, m) of nk kept k x the full q mesh)
     gel = None
+    gerr = None
     if args.interp_k > 0 and n_kept > 0:
         kf = torch.from_numpy(mesh_points_frac(mesh, kidx[:args.interp_k])).cuda()
         qf = torch.from_numpy(mesh_points_frac(mesh, np.arange(N))).cuda()
@@ -231,8 +232,11 @@ def main():
         torch.cuda.synchronize()
         ti = time.perf_counter() - t1
         gel = nk_i * N * nm * nW * nW / ti
-        del gout
         log(f"interp_g: {nk_i} k x {N} q in {ti * 1e3:.1f} ms = {gel:.3e} elements/s")
+        if not args.no_cpu_baseline:
+            gerr = interp_error(s, kf.cpu().numpy(), qf.cpu().numpy(), gout, n_q=16)
+            log(f"interp_g vs oracle on {gerr['sample']}: |g|^2 err / pair max {gerr['max']:.3e}")
+        del gout
 
     # oracle on a bounded sample: error of the GPU result and the CPU baseline rate
     err = None
@@ -283,6 +287,7 @@ def main():
             "kept_k": n_kept, "states": n_states, "q_points": N,
         },
         "g_elements_per_s": gel,
+        "g_err_vs_oracle": gerr,
         "err_vs_oracle": err,
         "roofline": roofline,
         "kernels": kernels,
@@ -291,6 +296,43 @@ def main():
     }
     print(json.dumps(out), flush=True)
     lib.close()
+
+
+def _groups(e, tol=1e-6):
+    """Labels of degenerate groups of an ascending energy vector."""
+    return np.concatenate([[0], np.cumsum(np.diff(e) >= tol)])
+
+
+def _group_g2(g, eps_n, eps_m, omega):
+    """|g[nu, n, m]|^2 summed over degenerate groups of nu, n and m (gauge-free)."""
+    lv, ln, lm = _groups(omega), _groups(eps_n), _groups(eps_m)
+    sums = np.zeros((lv[-1] + 1, ln[-1] + 1, lm[-1] + 1))
+    np.add.at(sums, (lv[:, None, None], ln[None, :, None], lm[None, None, :]), np.abs(g) ** 2)
+    return sums
+
+
+def interp_error(s, kf, qf, gout, n_q):
+    """Error of interp_g's |g|^2 group sums against the oracle on n_q seeded q of each k."""
+    from oracle import coupling
+    iq = np.sort(np.random.default_rng(777).choice(qf.shape[0], size=n_q, replace=False))
+    ref = coupling.coupling(kf, qf[iq], s)
+    got = gout[:, torch_index(iq, gout.device)].cpu().numpy()
+    worst = 0.0
+    for i in range(kf.shape[0]):
+        for j in range(n_q):
+            order = np.argsort(ref["omega_q"][j], kind="stable")
+            a = _group_g2(got[i, j][order], ref["eps_k"][i], ref["eps_kq"][i, j],
+                          ref["omega_q"][j][order])
+            b = _group_g2(ref["g"][i, j][order], ref["eps_k"][i], ref["eps_kq"][i, j],
+                          ref["omega_q"][j][order])
+            worst = max(worst, float(np.max(np.abs(a - b)) / np.max(b)))
+    return dict(max=worst, unit="|g|^2 group-sum error / largest |g|^2 of its (k, q) pair",
+                sample=f"{kf.shape[0]} k x {n_q} seeded q")
+
+
+def torch_index(idx, device):
+    import torch
+    return torch.from_numpy(np.asarray(idx, dtype=np.int64)).to(device)
 
 
 def bench_batched(args):
@@ -431,65 +473,69 @@ def bench_learned(args):
                         dweights=dws, st_row=strow, st_band=stband)
     torch.cuda.synchronize()
     t_terms = time.perf_counter() - t0
-    T, D = terms[:ns], dws[:ns]
+    # training set built by the library: selection D > thr max D per state, targets
+    # ln(T/D + c), a Philox-drawn subset of at most 2M samples, in flat-index order
     thr = 1e-6
-    sel = D > thr * D.reshape(ns, -1).amax(dim=1)[:, None, None]
-    si_all, qi_all, vi_all = torch.nonzero(sel, as_tuple=True)
-    ratio = T[si_all, qi_all, vi_all] / D[si_all, qi_all, vi_all]
-    c_floor = float(1e-3 * ratio.mean().item())
-    n_samp = min(2_000_000, int(si_all.numel()))
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(5)
-    pick = torch.randperm(int(si_all.numel()), device="cuda", generator=gen)[:n_samp]
-    si, qi, vi = si_all[pick], qi_all[pick], vi_all[pick]
-    y = torch.log(ratio[pick] + c_floor).float().contiguous()
-    y_var = float(y.var().item())
-    rows = strow[:ns].long()[si]
-    bands = stband[:ns].long()[si]
-    kk = torch.from_numpy(kidx[tr]).cuda()[rows].int().contiguous()
+    cap = 2_000_000
+    o_st = torch.zeros(cap, dtype=torch.int32, device="cuda")
+    o_q = torch.zeros(cap, dtype=torch.int32, device="cuda")
+    o_nu = torch.zeros(cap, dtype=torch.int32, device="cuda")
+    y = torch.zeros(cap, dtype=torch.float32, device="cuda")
+    n_samp, c_floor = lib.training_set(terms, dws, ns, thr, 1e-3, cap, 5, o_st, o_q, o_nu, y)
+    y_var = float(np.var(y[:n_samp].cpu().numpy().astype(np.float64)))
+    # per-sample k point and band energy: rows of per-state tables gathered by state
     kf = torch.from_numpy(mesh_points_frac(mesh, kidx[tr])).cuda()
     ek = torch.zeros((n_train, nW), dtype=torch.float64, device="cuda")
     lib.electron_bands(ds, kf, ek, None)
-    ee = ek[rows, bands].contiguous()
+    st_k = torch.zeros((ns, 1), dtype=torch.int32, device="cuda")
+    st_e = torch.zeros((ns, 1), dtype=torch.float64, device="cuda")
+    lib.gather_rows(torch.from_numpy(kidx[tr][:, None].astype(np.int32)).cuda(), strow[:ns], st_k)
+    st_idx = strow[:ns].cpu().numpy() * nW + stband[:ns].cpu().numpy()  # flat index into ek
+    lib.gather_rows(ek.reshape(-1, 1), torch.from_numpy(st_idx.astype(np.int32)).cuda(), st_e)
+    kk = torch.zeros((n_samp, 1), dtype=torch.int32, device="cuda")
+    ee = torch.zeros((n_samp, 1), dtype=torch.float64, device="cuda")
+    lib.gather_rows(st_k, o_st[:n_samp], kk)
+    lib.gather_rows(st_e, o_st[:n_samp], ee)
     n_in, width, depth = lib.mlp_feature_count(nm, args.n_harm), 256, 4
     escale = 0.3
     X = torch.zeros((n_samp, n_in), dtype=torch.float32, device="cuda")
-    lib.mlp_features(mesh, nm, kk, ee, qi.int().contiguous(), vi.int().contiguous(), X, par["mu"],
-                     escale, n_harm=args.n_harm)
-    del T, D, terms, dws, sel, si_all, qi_all, vi_all, ratio
-    # parameters: U(-1/sqrt(in), 1/sqrt(in)) weights, zero biases, packed per layer
-    prng = np.random.default_rng(17)
-    parts, prev = [], n_in
-    for l in range(depth + 1):
-        out_d = 1 if l == depth else width
-        parts.append(prng.uniform(-1 / np.sqrt(prev), 1 / np.sqrt(prev), size=out_d * prev))
-        parts.append(np.zeros(out_d))
-        prev = out_d
-    theta = torch.from_numpy(np.concatenate(parts).astype(np.float32)).cuda()
-    assert theta.numel() == lib.mlp_param_count(n_in, width, depth)
+    lib.mlp_features(mesh, nm, kk[:, 0].contiguous(), ee[:, 0].contiguous(), o_q[:n_samp],
+                     o_nu[:n_samp], X, par["mu"], escale, n_harm=args.n_harm)
+    del terms, dws, kk, ee
+    # parameters: the library's Philox initialisation (U(-1/sqrt(in), 1/sqrt(in)) weights,
+    # zero biases, packed per layer)
+    theta = torch.zeros(lib.mlp_param_count(n_in, width, depth), dtype=torch.float32,
+                        device="cuda")
+    lib.mlp_init(theta, n_in, width, depth, seed=17, precision="bf16")
     gbuf = torch.zeros_like(theta)
     mom1 = torch.zeros_like(theta)
     mom2 = torch.zeros_like(theta)
     bs, epochs = 4096, 2
     steps = epochs * n_samp // bs
+    idx = torch.zeros(bs, dtype=torch.int32, device="cuda")
+    Xb = torch.zeros((bs, n_in), dtype=torch.float32, device="cuda")
+    yb = torch.zeros(bs, dtype=torch.float32, device="cuda")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     losses = []
     for step in range(1, steps + 1):
-        idx = torch.randint(0, n_samp, (bs,), device="cuda", generator=gen)
-        loss = lib.mlp_grad(theta, X[idx].contiguous(), y[idx].contiguous(), gbuf, n_in, width,
-                            depth, precision="bf16")
+        # minibatch: Philox integers in [0, n_samp), rows gathered by the library
+        lib.philox_randint(6, (step - 1) * bs, n_samp, idx)
+        lib.gather_rows(X, idx, Xb)
+        lib.gather_rows(y[:, None], idx, yb[:, None])
+        loss = lib.mlp_grad(theta, Xb, yb, gbuf, n_in, width, depth, precision="bf16")
         lib.mlp_adam(theta, gbuf, mom1, mom2, step, 1e-3 if step < steps // 2 else 3e-4)
         if step == 1 or step % 100 == 0:
             losses.append(loss)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    log(f"terms of {ns} training states in {t_terms:.2f} s; {steps} Adam steps in {t_train:.1f} s, "
-        f"loss {losses[0]:.3f} -> {losses[-1]:.3f} (target variance {y_var:.3f})")
-    del X, y
+    log(f"terms of {ns} training states in {t_terms:.2f} s; {n_samp} samples (c = {c_floor:.3e}); "
+        f"{steps} Adam steps in {t_train:.1f} s, loss {losses[0]:.3f} -> {losses[-1]:.3f} "
+        f"(target variance {y_var:.3f})")
+    del X, y, Xb, yb
 
     # test k: full-mesh plain rates (the reference result) vs importance sampling
-    S, seeds = 4096, 8
+    S, seeds = 4096, 32
     test_k = kidx[te]
     kd = torch.from_numpy(test_k.astype(np.int32)).cuda()
     # plain form on exactly these k, timed
@@ -521,12 +567,14 @@ def bench_learned(args):
     lib.electron_bands(ds, kf, ek, None)
     eps_k = ek.cpu().numpy()[np.arange(n_test), tb]
     full = g_full[te, tb]
-    ugen = torch.Generator(device="cuda")
-    ugen.manual_seed(77)
     est = {"learned": [], "smearing": [], "uniform": []}
     t_prop, t_is = 0.0, 0.0
+    u = torch.zeros(n_test * S, dtype=torch.float64, device="cuda")
+    qu = torch.zeros(n_test * S, dtype=torch.int32, device="cuda")
+    wu = torch.full((n_test * S,), 1.0 / S, dtype=torch.float64, device="cuda")  # 1/(N S p), p=1/N
     for sd in range(seeds):
-        u = torch.rand(n_test * S, dtype=torch.float64, device="cuda", generator=ugen)
+        # sampler uniforms: Philox stream 77 at offset sd * n_test * S
+        lib.philox_uniform(77, sd * n_test * S, u)
         for name, prm in (("learned", theta), ("smearing", None)):
             q_off = torch.zeros(n_test + 1, dtype=torch.int64, device="cuda")
             q_idx = torch.zeros(n_test * S, dtype=torch.int32, device="cuda")
@@ -545,8 +593,7 @@ def bench_learned(args):
                 t_prop += t1 - t0
                 t_is += t2 - t1
             est[name].append(gl.cpu().numpy()[np.arange(n_test), tb])
-        qu = torch.randint(0, N, (n_test * S,), device="cuda", generator=ugen).int()
-        wu = torch.full((n_test * S,), 1.0 / S, dtype=torch.float64, device="cuda")
+        lib.philox_randint(78, sd * n_test * S, N, qu)
         gu = torch.zeros((n_test, nW), dtype=torch.float64, device="cuda")
         lib.scatter_rates(ds, mesh, par, gu, k_idx=kd, q_lists=(q_off, qu, wu))
         torch.cuda.synchronize()
@@ -557,8 +604,9 @@ def bench_learned(args):
     t_step = t_dw + t_prop + t_is
     rel = {k: np.abs(v - full[None]) / full[None] for k, v in est.items()}
     cv = {k: v.std(axis=0, ddof=1) / full for k, v in est.items()}
-    bias = np.abs(est["learned"].mean(axis=0) - full) / (est["learned"].std(axis=0, ddof=1)
-                                                         / np.sqrt(seeds))
+    z = (est["learned"].mean(axis=0) - full) / (est["learned"].std(axis=0, ddof=1)
+                                                / np.sqrt(seeds))
+    bias = np.abs(z)
     log(f"plain {n_test} k in {t_plain * 1e3:.1f} ms; learned: weights {t_dw * 1e3:.1f} ms + "
         f"proposal {t_prop * 1e3:.1f} ms + IS rates {t_is * 1e3:.1f} ms; median rel err learned "
         f"{np.median(rel['learned']):.3e}, smearing-only {np.median(rel['smearing']):.3e}, uniform "
@@ -594,6 +642,8 @@ def bench_learned(args):
         "variance_ratio_vs_uniform_median": {
             k: float(np.median((cv[k] / cv["uniform"]) ** 2)) for k in ("learned", "smearing")},
         "bias_in_std_errors_max": float(bias.max()),
+        "bias_in_std_errors_mean_square": float(np.mean(z ** 2)),
+        "bias_beyond_3_std_errors": int(np.sum(bias > 3.0)),
         "training_loss": [round(x, 4) for x in losses],
         "target_variance": round(y_var, 4),
     }
