@@ -30,7 +30,7 @@ import numpy as np
 
 from .bands import bose_einstein, fermi_dirac
 from .coupling import coupling_k_rp, phonon_length, polar_params
-from .mesh import sum_index_table
+from .mesh import mesh_triples, sum_index_table
 from .polar import polar_factor
 from .rates import gaussian_delta, kept_points, mesh_tables, transition_sigma, window_mask
 from .velocity import group_velocities
@@ -92,3 +92,61 @@ def phonon_linewidth(system, mesh, mu, kT, sigma, win_lo, win_hi, omega_min=1e-4
     nb = np.where(active, bose_einstein(np.where(active, omega, 1.0), kT), 0.0)
     P = np.where(active, (2.0 * np.pi / N) * nb * (nb + 1.0) * omega * S, 0.0)
     return dict(P=P, k_idx=k_idx, tables=tables)
+
+
+def phonon_linewidth_at(system, mesh, q_idx, mu, kT, sigma, win_lo, win_hi, omega_min=1e-4,
+                        tables=None, k_chunk=512):
+    """P^{el-ph}_{q nu} at the given mesh points q only, same definition as
+    ``phonon_linewidth`` (fixed Gaussian width).
+
+    The double lattice sum is taken in the other order: at each q the sum over Rp
+    first, g_q(Re) = sum_Rp e^{i 2 pi q.Rp} g(Re, Rp), then the sum over Re at
+    every kept k.  Each q costs one pass over g(Re, Rp) and one product with the
+    kept-k phases, so a few q of a large mesh are cheap.  Returns P [len(q_idx), nModes].
+    """
+    if tables is None:
+        tables = mesh_tables(system, mesh)
+    eps, U, omega, z = tables["eps"], tables["U"], tables["omega"], tables["z"]
+    pts = tables["points"]
+    N = pts.shape[0]
+    nm, nW = system.n_modes, system.n_wannier
+    mask_all = window_mask(eps, win_lo, win_hi)
+    k_idx = kept_points(mask_all)
+    f_all = fermi_dirac(eps, mu, kT)
+    mdf = f_all * (1.0 - f_all) / kT
+    re = np.asarray(system.re, dtype=np.float64)
+    rp = np.asarray(system.rp, dtype=np.float64)
+    g_flat = system.g_rr.reshape(re.shape[0], rp.shape[0], -1)       # [Re, Rp, sa a b]
+    pp = polar_params(system)
+    q_idx = np.asarray(q_idx, dtype=np.int64)
+    P = np.zeros((q_idx.size, nm))
+    for iq, q in enumerate(q_idx):
+        w = omega[q]
+        active = w >= omega_min
+        l = phonon_length(omega[q:q + 1], system.mass, omega_min)[0]   # [nat, nu]
+        zl = z[q] * np.repeat(l, 3, axis=0)                             # [sa, nu]
+        L = polar_factor(pts[q:q + 1], z[q:q + 1], l[None], *pp)[0] if pp is not None else None
+        ph_q = np.exp(2j * np.pi * (rp @ pts[q]))                       # [Rp]
+        gq = np.einsum("p,epc->ec", ph_q, g_flat)                       # [Re, sa a b]
+        tri = mesh_triples(mesh)
+        nn = np.asarray(mesh, dtype=np.int64)
+        s3 = (tri[k_idx] + tri[q][None, :]) % nn[None, :]
+        kq_all = (s3[:, 0] * nn[1] + s3[:, 1]) * nn[2] + s3[:, 2]      # k + q of every kept k
+        S = np.zeros(nm)
+        for c0 in range(0, k_idx.size, k_chunk):
+            ks = k_idx[c0:c0 + k_chunk]
+            kq = kq_all[c0:c0 + k_chunk]
+            ph_k = np.exp(2j * np.pi * (pts[ks] @ re.T))                # [k, Re]
+            G = (ph_k @ gq).reshape(ks.size, nm, nW, nW)                # [k, sa, a, b]
+            Y = np.conj(np.swapaxes(U[ks], -1, -2))[:, None] @ G @ U[kq][:, None]   # [k, sa, n, m]
+            g = np.einsum("ksnm,sv->knvm", Y, zl)                       # [k, n, nu, m]
+            if L is not None:
+                O = np.conj(np.swapaxes(U[ks], -1, -2)) @ U[kq]         # [k, n, m]
+                g = g + 1j * L[None, None, :, None] * O[:, :, None, :]
+            g2 = (g * np.conj(g)).real
+            x = eps[ks][:, :, None, None] - eps[kq][:, None, None, :] - w[None, None, :, None]
+            wgt = mdf[ks] * mask_all[ks]                                # kept states only
+            S += np.einsum("kn,knvm->v", wgt, g2 * gaussian_delta(x, sigma))
+        nb = np.where(active, bose_einstein(np.where(active, w, 1.0), kT), 0.0)
+        P[iq] = np.where(active, (2.0 * np.pi / N) * nb * (nb + 1.0) * w * S, 0.0)
+    return P

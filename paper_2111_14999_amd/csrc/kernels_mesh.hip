@@ -152,12 +152,14 @@ __global__ __launch_bounds__(64 * kAxisWaves, 6) void axis_fused_kernel(const C*
                                                          Mesh m, const cd* __restrict__ P1,
                                                          const cd* __restrict__ P2,
                                                          const uint32_t* __restrict__ line_any,
-                                                         C* __restrict__ T2) {
+                                                         int qsplit, C* __restrict__ T2) {
     constexpr int W = WT;
     extern __shared__ char smem_raw[];
     C* sF = reinterpret_cast<C*>(smem_raw);  // [W * W][64]
     const int ncb = nc_pad / 64;
     int64_t b = blockIdx.x;
+    const int qs = (int)(b % qsplit);  // this work-group's share of the q2 values
+    b /= qsplit;
     const int cb = (int)(b % ncb);
     b /= ncb;
     const int r0 = (int)(b % W);
@@ -173,7 +175,7 @@ __global__ __launch_bounds__(64 * kAxisWaves, 6) void axis_fused_kernel(const C*
     const int N1 = m.n1, N2 = m.n2, NL = N1 * N2;
     const uint32_t* fl = line_any + (int64_t)st * NL;
     C* out = T2 + ((int64_t)st * W + r0) * NL * nc_pad + c;
-    for (int q2 = g; q2 < N2; q2 += kAxisWaves) {
+    for (int q2 = g + kAxisWaves * qs; q2 < N2; q2 += kAxisWaves * qsplit) {
         // the slab is read from LDS per q2, not held in registers across the loop
         asm volatile("" ::: "memory");
         C t1[W];
@@ -209,11 +211,17 @@ static hipError_t go_axes(const C* F, int rp_pad, int nc_pad, const int32_t* box
             hipError_t e = hipFuncSetAttribute((const void*)axis_fused_kernel<WT, C>,
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
             if (e != hipSuccess) return e;
-            const int64_t groups = (int64_t)nst * WT * (nc_pad / 64);
+            // a few states make few work-groups: split the q2 values of a slab over up to
+            // ceil(N2 / waves) work-groups (each reloads the slab) until the grid fills the chip
+            const int64_t base = (int64_t)nst * WT * (nc_pad / 64);
+            const int qmax = (m.n2 + kAxisWaves - 1) / kAxisWaves;
+            int qsplit = 1;
+            while (qsplit < qmax && base * qsplit < 2048) ++qsplit;
+            const int64_t groups = base * qsplit;
             if (groups > 2147483647LL) return hipErrorInvalidValue;
             hipLaunchKernelGGL((axis_fused_kernel<WT, C>), dim3((unsigned)groups), dim3(64 * kAxisWaves),
                                shm, s,
-                               F, rp_pad, nc_pad, box_rp, m, P1, P2, line_any, T2);
+                               F, rp_pad, nc_pad, box_rp, m, P1, P2, line_any, qsplit, T2);
             return hipGetLastError();
         }
     }
