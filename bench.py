@@ -72,7 +72,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="realistic",
-                    choices=["realistic", "toy", "batched", "learned"])
+                    choices=["realistic", "toy", "batched", "learned", "linewidth", "adaptive",
+                             "polar", "v3"])
     ap.add_argument("--tune-cache", default=None, help="JSON tile cache of the batched form")
     ap.add_argument("--cpu-sample", type=int, default=6, help="kept k points timed on the oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -114,13 +115,25 @@ def main():
         return bench_batched(args)
     if args.workload == "learned":
         return bench_learned(args)
-    p = load_params(args.workload)
+    if args.workload == "v3":
+        return bench_v3(args)
+    # the extension legs run on the realistic system and meshes
+    ext = args.workload in ("linewidth", "adaptive", "polar")
+    p = load_params("realistic" if ext else args.workload)
     mesh = tuple(p["mesh"])
     N = int(np.prod(mesh))
     par = dict(mu=p["mu"], kT=p["kT"], sigma=p["sigma"], win_lo=p["win_lo"], win_hi=p["win_hi"],
                omega_min=p["omega_min"])
     t0 = time.perf_counter()
-    s = synth.config_c2() if args.workload == "realistic" else synth.config_c1()
+    s = synth.config_c1() if args.workload == "toy" else synth.config_c2()
+    if args.workload == "polar":
+        synth.add_polar(s, 7)  # Born charges and dielectric tensor: g = g^S + g^L
+    par_run = dict(par)
+    if args.workload == "adaptive":  # per-transition widths from the group velocities
+        par_run.update(smearing="adaptive", adaptive_scale=1.0)
+    if ext:
+        args.interp_k = 0
+        args.cpu_sample = min(args.cpu_sample, 2)
     log(f"inputs generated in {time.perf_counter() - t0:.1f} s (g(Re,Rp) {s.g_rr.nbytes / 1e9:.2f} GB)")
     ds = DeviceSystem.from_host(s)
     torch.cuda.synchronize()
@@ -131,8 +144,14 @@ def main():
     mask = torch.zeros((N, nW), dtype=torch.uint8, device="cuda")
     kept = torch.zeros((N,), dtype=torch.int32, device="cuda")
 
+    pw = (torch.zeros((N, nm), dtype=torch.float64, device="cuda")
+          if args.workload == "linewidth" else None)
+
     def step():
-        return lib.scatter_rates(ds, mesh, par, gamma, band_mask=mask, kept_k_out=kept,
+        if args.workload == "linewidth":
+            # P^{el-ph} on every (q, mode) of the mesh, with the electron rates of the same pass
+            return lib.phonon_linewidth(ds, mesh, par_run, pw, gamma_out=gamma)
+        return lib.scatter_rates(ds, mesh, par_run, gamma, band_mask=mask, kept_k_out=kept,
                                  precision=args.precision)
 
     for i in range(args.warmup):
@@ -149,6 +168,12 @@ def main():
     dt = (time.perf_counter() - t0) / args.steps
     lib.set_timing(False)
     log(f"{args.steps} timed steps, {dt * 1e3:.1f} ms/step")
+    if args.workload == "linewidth":  # window masks and kept list (untimed)
+        gl = gamma.clone()
+        lib.scatter_rates(ds, mesh, par, gamma, band_mask=mask, kept_k_out=kept)
+        torch.cuda.synchronize()
+        log(f"linewidth pass rates vs plain path: max |diff| "
+            f"{float((gl - gamma).abs().max()):.3e}")
     g = gamma.cpu().numpy()[:n_kept]
     m = mask.cpu().numpy()[:n_kept]
     kidx = kept.cpu().numpy()[:n_kept]
@@ -241,7 +266,28 @@ def main():
     # oracle on a bounded sample: error of the GPU result and the CPU baseline rate
     err = None
     cpu = None
-    if not args.no_cpu_baseline and n_kept > 0:
+    if not args.no_cpu_baseline and n_kept > 0 and args.workload == "linewidth":
+        from oracle import linewidth, rates
+        t1 = time.perf_counter()
+        tables = rates.mesh_tables(s, mesh)
+        t_tab = time.perf_counter() - t1
+        qs = np.sort(np.random.default_rng(12345).choice(N, size=2, replace=False))
+        t1 = time.perf_counter()
+        refP = linewidth.phonon_linewidth_at(s, mesh, qs, tables=tables, **par)
+        t_q = time.perf_counter() - t1
+        per_q = t_q / len(qs) + t_tab / N
+        cpu = dict(value=round(1.0 / per_q, 4), unit="q-pts/s", cores=os.cpu_count(),
+                   kind="oracle",
+                   sample=f"{len(qs)} seeded q of {N}, each summed over all {n_kept} kept k "
+                          f"({t_q:.1f} s) + band/phonon tables on the mesh ({t_tab:.1f} s) "
+                          f"pro-rated per q; NumPy/OpenBLAS threads = host cores")
+        got = pw.cpu().numpy()[qs]
+        sel = refP > 1e-10 * refP.max()
+        rel = np.abs(got[sel] - refP[sel]) / refP[sel]
+        err = dict(max_rel=float(rel.max()), median_rel=float(np.median(rel)),
+                   entries=int(sel.sum()), sample=f"P of {len(qs)} seeded q, all modes")
+        log(f"oracle sample: max rel err of P {rel.max():.3e}, cpu {cpu['value']} q-pts/s")
+    elif not args.no_cpu_baseline and n_kept > 0:
         from oracle import rates
         rng = np.random.default_rng(12345)
         sample = np.sort(rng.choice(n_kept, size=min(args.cpu_sample, n_kept), replace=False))
@@ -249,7 +295,9 @@ def main():
         tables = rates.mesh_tables(s, mesh)
         t_tab = time.perf_counter() - t1
         t1 = time.perf_counter()
-        ref = rates.scattering_rates(s, mesh, k_idx=kidx[sample], tables=tables, **par)
+        kw = dict(adaptive=dict(sigma_min=par["sigma"], prefactor=1.0)) \
+            if args.workload == "adaptive" else {}
+        ref = rates.scattering_rates(s, mesh, k_idx=kidx[sample], tables=tables, **kw, **par)
         t_k = time.perf_counter() - t1
         per_k = t_k / len(sample) + t_tab / n_kept
         cpu = dict(value=round(1.0 / per_k, 4), unit="k-pts/s", cores=os.cpu_count(),
@@ -265,10 +313,18 @@ def main():
                    states=int(sel.sum()), sample=f"{len(sample)} kept k")
         log(f"oracle sample: max rel err {rel.max():.3e}, cpu {cpu['value']} k-pts/s")
 
+    metric, value, unit = METRIC, round(n_kept / dt, 3), "k-pts/s"
+    if args.workload == "linewidth":
+        metric = ("phonon el-ph linewidth P_q,nu q-pts/s (every q and mode of the mesh, summed "
+                  "over every kept k) at stated err vs FP64 oracle, 1 GPU")
+        value, unit = round(N / dt, 3), "q-pts/s"
+    elif args.workload in ("adaptive", "polar"):
+        metric = (f"Γ_nk k-pts/s with {'adaptive Gaussian smearing' if args.workload == 'adaptive' else 'the polar long-range coupling g^L'}"
+                  " at stated err vs FP64 oracle, 1 GPU")
     out = {
-        "metric": METRIC,
-        "value": round(n_kept / dt, 3),
-        "unit": "k-pts/s",
+        "metric": metric,
+        "value": value,
+        "unit": unit,
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -280,7 +336,8 @@ def main():
                   "bf16x6": "bf16x6+f32acc"}[args.precision],
         "data": "synthetic",
         "config": {
-            "workload": (f"{args.workload}: {s.n_atoms} atoms ({nm} modes), nW={nW}, "
+            "workload": (f"{args.workload}{' (realistic system)' if ext else ''}: "
+                         f"{s.n_atoms} atoms ({nm} modes), nW={nW}, "
                          f"|Re|=|Rp|={n_rp}, k and q mesh {mesh[0]}x{mesh[1]}x{mesh[2]}, "
                          f"window ({par['win_lo']:.4f}, {par['win_hi']:.4f}) eV -> {n_kept} kept k, "
                          f"{n_states} states, sigma {par['sigma']} eV, kT {par['kT']:.6f} eV"),
@@ -333,6 +390,90 @@ def interp_error(s, kf, qf, gout, n_q):
 def torch_index(idx, device):
     import torch
     return torch.from_numpy(np.asarray(idx, dtype=np.int64)).to(device)
+
+
+def bench_v3(args):
+    """3-phonon coupling V3(q, q', q'') of the realistic perovskite (15 modes), third-order
+    constants on [-2, 2]^3 for both displacements: 16 q x 4096 q' per call."""
+    import torch
+
+    import synth
+    from paper_2111_14999_amd import DeviceSystem3, Library
+
+    t0 = time.perf_counter()
+    s = synth.config_c2(with_coupling=False)
+    r, phi3 = synth.third_order_constants(11, s.n_atoms)
+    s.r1, s.r2, s.phi3 = r, r, phi3
+    log(f"inputs generated in {time.perf_counter() - t0:.1f} s (Phi3 {phi3.nbytes / 1e9:.2f} GB)")
+    g = np.random.default_rng(12)
+    nq, nqp = 16, 4096
+    q = g.uniform(-1, 1, size=(nq, 3))
+    qp = g.uniform(-1, 1, size=(nqp, 3))
+    nm, n1, n2 = s.n_modes, r.shape[0], r.shape[0]
+    lib = Library(0)
+    d3 = DeviceSystem3.from_host(s, r, phi3)
+    qd, qpd = torch.from_numpy(q).cuda(), torch.from_numpy(qp).cuda()
+    V = torch.zeros((nq, nqp, nm, nm, nm), dtype=torch.complex128, device="cuda")
+    for _ in range(args.warmup):
+        lib.interp_v3(d3, qd, qpd, V)
+    torch.cuda.synchronize()
+    lib.set_timing(True)
+    lib.reset_timing()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        lib.interp_v3(d3, qd, qpd, V)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    lib.set_timing(False)
+    m3 = nm ** 3
+    kernels = {}
+    # complex GEMMs on FP64 MFMA: stage 1 (sum over R per batch of q), stage 2 (sum over R'
+    # per q), 8 flops per complex multiply-add
+    for name, flops in (("v3_stage1", 8.0 * nq * n1 * n2 * m3),
+                        ("v3_stage2", 8.0 * nq * nqp * n2 * m3)):
+        n_l, ms = lib.kernel_time(name)
+        if n_l == 0:
+            continue
+        lps = n_l / args.steps
+        avg = ms / n_l
+        per = flops / lps
+        ach = per / (avg * 1e-3) / 1e12
+        kernels[name] = dict(bound="mfma", achieved=round(ach, 3), peak=PEAK_FP64_TFLOPS,
+                             unit="TFLOP/s", frac=round(ach / PEAK_FP64_TFLOPS, 4),
+                             launches_per_step=lps, avg_launch_ms=round(avg, 4),
+                             ms_per_step=round(ms / args.steps, 3), work_per_launch=per)
+        log(f"{name}: {n_l} launches, avg {avg:.3f} ms, {ach:.2f} TFLOP/s, {ms / args.steps:.1f} ms/step")
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"]) if kernels else None
+    roofline = dict(kernels[dom], kernel=dom, traffic=None) if dom else None
+    iq = np.array([3, 12])
+    jq = np.sort(g.choice(nqp, size=24, replace=False))
+    got = V[torch.from_numpy(iq).cuda()][:, torch.from_numpy(jq).cuda()].cpu().numpy()
+    err = cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import phonon3
+        t1 = time.perf_counter()
+        ref = phonon3.interp_v3(q[iq], qp[jq], s)["v3"]
+        t_o = time.perf_counter() - t1
+        e = np.max(np.abs(np.abs(got) - np.abs(ref))) / np.max(np.abs(ref))
+        err = dict(max_rel_to_max=float(e), sample=f"|V3| of {len(iq)} q x {len(jq)} seeded q'")
+        cpu = dict(value=round(len(iq) * len(jq) * m3 / t_o, 1), unit="V3 elements/s",
+                   cores=os.cpu_count(), kind="oracle",
+                   sample=f"{len(iq)} q x {len(jq)} q' ({t_o:.1f} s)")
+        log(f"oracle sample: max ||V3| - ref| / max {e:.3e}, cpu {cpu['value']} elements/s")
+    out = {
+        "metric": "3-phonon coupling V3(q,q',q'') elements/s at stated err vs FP64 oracle, 1 GPU",
+        "value": round(nq * nqp * m3 / dt, 1),
+        "unit": "V3 elements/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(dt * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": (f"v3: perovskite {s.n_atoms} atoms ({nm} modes), third-order "
+                                f"constants on {n1} x {n2} lattice vectors, {nq} q x {nqp} q' "
+                                f"(q'' = -q - q'), phonon eigenvectors of all three")},
+        "err_vs_oracle": err, "roofline": roofline, "kernels": kernels, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    lib.close()
 
 
 def bench_batched(args):
@@ -405,10 +546,18 @@ def bench_batched(args):
     for inf in info:
         key = f"tq{inf['tq']}_tn{inf['tn']}"
         tiles[key] = tiles.get(key, 0) + 1
+    metric, value, unit = METRIC, round(n_kept / dt, 3), "k-pts/s"
+    if args.workload == "linewidth":
+        metric = ("phonon el-ph linewidth P_q,nu q-pts/s (every q and mode of the mesh, summed "
+                  "over every kept k) at stated err vs FP64 oracle, 1 GPU")
+        value, unit = round(N / dt, 3), "q-pts/s"
+    elif args.workload in ("adaptive", "polar"):
+        metric = (f"Γ_nk k-pts/s with {'adaptive Gaussian smearing' if args.workload == 'adaptive' else 'the polar long-range coupling g^L'}"
+                  " at stated err vs FP64 oracle, 1 GPU")
     out = {
-        "metric": METRIC,
-        "value": round(n_kept / dt, 3),
-        "unit": "k-pts/s",
+        "metric": metric,
+        "value": value,
+        "unit": unit,
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,

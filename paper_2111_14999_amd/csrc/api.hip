@@ -592,7 +592,7 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                                                    2 * (size_t)(rows_cap * nW + rows_cap + 1) *
                                                        sizeof(uint32_t) + 512
                                              : 0) +
-                                   (re_fact ? (size_t)rows_cap * 168 * sizeof(int32_t) + 1024
+                                   (re_fact ? (size_t)rows_cap * 176 * sizeof(int32_t) + 1024
                                             : 0) +
                                    (lw_out ? (factored ? (size_t)nsb * NL * n0_line
                                                        : (size_t)max_states * N) *
@@ -753,7 +753,7 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
         // distinct (k0, k1), with the grouping lists the axis kernels use.
         std::vector<std::pair<int64_t, int64_t>> batches;
         std::vector<int32_t> rbh;          // grouping lists of every batch, one array
-        std::vector<std::array<int64_t, 10>> rbo;  // per batch: d0, d01, offsets of the 8 lists
+        std::vector<std::array<int64_t, 11>> rbo;  // per batch: d0, d01, offsets of the 8 lists
         std::vector<int32_t> planes;               // every distinct k0 of the call, ascending
         if (!re_fact) {
             for (int64_t r0 = 0; r0 < rows; r0 += BK) batches.push_back({r0, std::min<int64_t>(BK, rows - r0)});
@@ -787,7 +787,7 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                 std::sort(prs.begin(), prs.end());
                 const int d0 = (int)k0s.size(), d01 = (int)prs.size();
                 const int64_t nb = e - r;
-                std::array<int64_t, 10> o{};
+                std::array<int64_t, 11> o{};
                 o[0] = d0;
                 o[1] = d01;
                 // d_k0
@@ -834,22 +834,34 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                                              : 0);
                 // row_st: first state (batch-local) of every batch row, and the end
                 o[9] = (int64_t)rbh.size();
+                std::vector<int32_t> rst(nb + 1);
                 {
                     const int64_t s0 = std::lower_bound(strow.begin(), strow.end(), (int32_t)r) -
                                        strow.begin();
                     for (int64_t i = r; i <= e; ++i)
-                        rbh.push_back((int32_t)(std::lower_bound(strow.begin(), strow.end(),
-                                                                 (int32_t)i) - strow.begin() - s0));
+                        rst[i - r] = (int32_t)(std::lower_bound(strow.begin(), strow.end(),
+                                                                (int32_t)i) - strow.begin() - s0);
+                    rbh.insert(rbh.end(), rst.begin(), rst.end());
                 }
+                // k_ent: per entry of k_row, (k2, first state, end of states, 0), 16-byte aligned
+                while (rbh.size() % 4) rbh.push_back(0);
+                o[10] = (int64_t)rbh.size();
+                for (int pp = 0; pp < d01; ++pp)
+                    for (int32_t lr : byp[pp]) {
+                        rbh.push_back((int32_t)(kh[r + lr] % mesh.n2));
+                        rbh.push_back(rst[lr]);
+                        rbh.push_back(rst[lr + 1]);
+                        rbh.push_back(0);
+                    }
                 rbo.push_back(o);
                 batches.push_back({r, nb});
                 r = e;
             }
             if (all_planes) {  // the plane list itself, after the batch lists
-                rbo.push_back({(int64_t)planes.size(), 0, (int64_t)rbh.size(), 0, 0, 0, 0, 0, 0, 0});
+                rbo.push_back({(int64_t)planes.size(), 0, (int64_t)rbh.size(), 0, 0, 0, 0, 0, 0, 0, 0});
                 rbh.insert(rbh.end(), planes.begin(), planes.end());
             }
-            REQUIRE(h, rbh.size() <= (size_t)rows_cap * 168, "stage-1 grouping lists too long");
+            REQUIRE(h, rbh.size() <= (size_t)rows_cap * 176, "stage-1 grouping lists too long");
         }
         int32_t* rbd = re_fact ? ar.take<int32_t>(std::max<size_t>(rbh.size(), 1)) : nullptr;
         if (re_fact)
@@ -914,7 +926,8 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
             if (re_fact) {
                 const auto& o = rbo[bi];
                 ReBatch rb{(int)o[0], (int)o[1], rbd + o[2], rbd + o[3], rbd + o[4],
-                           rbd + o[5], rbd + o[6], rbd + o[7], all_planes ? rbd + o[8] : nullptr};
+                           rbd + o[5], rbd + o[6], rbd + o[7], all_planes ? rbd + o[8] : nullptr,
+                           rbd + o[10]};
                 FoldOut fo{rbd + o[9], T.st_kmesh + sbeg, T.st_band + sbeg, T.U,
                            nW, nm, n_rp, rp_pad, nc_pad, Fbuf};
                 const FoldOut* fop = fold_fused ? &fo : nullptr;

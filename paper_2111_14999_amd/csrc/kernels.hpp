@@ -133,6 +133,8 @@ struct ReBatch {
     int d0, d01;
     const int32_t *d_k0, *pair_k1, *pair_off, *kp_off, *k_row, *k_k2;
     const int32_t* d_plane;  // T0 plane of each distinct k0 (all planes resident), else null
+    // per row of k_row (16-byte aligned): k2, first state, end of the row's states, 0
+    const int32_t* k_ent;
 };
 // With fo set (nW = 16), the pair and k steps apply the U_k fold of the rates at
 // once and write F [states of the batch, rp_pad, nc_pad] (columns sa*16 + b)

@@ -398,17 +398,19 @@ __global__ __launch_bounds__(256) void re_axis12_kernel(const C* __restrict__ T0
 
 // 16-lane row sum by DPP (quad_perm 1,0,3,2 and 2,3,0,1, row_half_mirror,
 // row_mirror), left in every lane of the row.
+// Every lane of the row reads a lane of the same row for these controls, so the
+// moves take no old value (no zeroing instructions before them).
 template <int CTRL>
 __device__ inline double dpp_f64(double x) {
     const uint64_t b = __builtin_bit_cast(uint64_t, x);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)b, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, true);
     return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 template <int CTRL>
 __device__ inline float dpp_f32(float x) {
     return __builtin_bit_cast(
-        float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
+        float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), CTRL, 0xF, 0xF, true));
 }
 template <class R>
 __device__ inline R row16_sum(R x) {
@@ -447,7 +449,8 @@ __global__ __launch_bounds__(64 * kFoldWaves, fold_waves_per_simd<WT>()) void re
     const cd* __restrict__ P2, const int32_t* __restrict__ pair_k1,
     const int32_t* __restrict__ pair_off, const int32_t* __restrict__ kp_off,
     const int32_t* __restrict__ k_row, const int32_t* __restrict__ k_k2,
-    const int32_t* __restrict__ d_plane, int64_t ncb, FoldOut fo) {
+    const int32_t* __restrict__ d_plane, const int4* __restrict__ k_ent, int64_t ncb,
+    FoldOut fo) {
     using R = decltype(C::x);
     constexpr int NV = WT > 0 ? WT : kMaxW;
     const int W = WT > 0 ? WT : Wr;
@@ -490,25 +493,39 @@ __global__ __launch_bounds__(64 * kFoldWaves, fold_waves_per_simd<WT>()) void re
                     tb[r2] = cfma(pbv, v, tb[r2]);
                 }
         }
+        // this lane's G[k, Rp r, sa, a = li, b], folded into every state of row k:
+        // F = sum over the 16 lanes of the row of conj(U_k[a, n]) G
+        auto fold = [&](const C& acc, int st) {
+            const C u =
+                to_c<C>(fo.U[((int64_t)fo.st_kmesh[st] * 16 + fo.st_band[st]) * 16 + li]);
+            const R fr = row16_sum(u.x * acc.x + u.y * acc.y);
+            const R fi = row16_sum(u.x * acc.y - u.y * acc.x);
+            if (li == 0) Fo[st * fst] = C{fr, fi};
+        };
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             if (h == 1 && !two) break;
             const int p = pp + kFoldWaves * h;
-            for (int i = kp_off[p]; i < kp_off[p + 1]; ++i) {
-                const cd* Pk2 = P2 + (int64_t)k_k2[i] * W;
-                C acc = {0, 0};
+            const int iend = kp_off[p + 1];
+            // two k of the pair at a time: one record each (k2, first state, end of its
+            // states), so their loads are issued together and the chains overlap
+            for (int i = kp_off[p]; i < iend; i += 2) {
+                const bool second = i + 1 < iend;
+                const int4 ea = k_ent[i];
+                const int4 eb = k_ent[second ? i + 1 : i];
+                const cd* Pa = P2 + (int64_t)ea.x * W;
+                const cd* Pb = P2 + (int64_t)eb.x * W;
+                C aa = {0, 0}, ab = {0, 0};
 #pragma unroll
                 for (int r2 = 0; r2 < NV; ++r2)
-                    if (r2 < W) acc = cfma(to_c<C>(Pk2[r2]), h ? tb[r2] : ta[r2], acc);
-                // this lane's G[k, Rp r, sa, a = li, b]; fold it into every state of row k
-                const int krow = k_row[i];
-                for (int st = fo.row_st[krow]; st < fo.row_st[krow + 1]; ++st) {
-                    const C u = to_c<C>(
-                        fo.U[((int64_t)fo.st_kmesh[st] * 16 + fo.st_band[st]) * 16 + li]);
-                    const R fr = row16_sum(u.x * acc.x + u.y * acc.y);
-                    const R fi = row16_sum(u.x * acc.y - u.y * acc.x);
-                    if (li == 0) Fo[st * fst] = C{fr, fi};
-                }
+                    if (r2 < W) {
+                        const C t = h ? tb[r2] : ta[r2];
+                        aa = cfma(to_c<C>(Pa[r2]), t, aa);
+                        ab = cfma(to_c<C>(Pb[r2]), t, ab);
+                    }
+                for (int st = ea.y; st < ea.z; ++st) fold(aa, st);
+                if (second)
+                    for (int st = eb.y; st < eb.z; ++st) fold(ab, st);
             }
         }
     }
@@ -535,11 +552,12 @@ static hipError_t go_re_axis12(const C* T0, int64_t NC, int W, Mesh m, const cd*
     if (e != hipSuccess) return e;
     const int64_t ncb = (NC + 63) / 64;
     if ((int64_t)b.d0 * ncb > 2147483647LL) return hipErrorInvalidValue;
+    if (fo && (!b.k_ent || (reinterpret_cast<uintptr_t>(b.k_ent) & 15))) return hipErrorInvalidValue;
     if (fo)
         hipLaunchKernelGGL((re_axis12_fold_kernel<WT, C>), dim3((unsigned)(b.d0 * ncb)),
                            dim3(64 * kFoldWaves),
                            shm, s, T0, NC, W, P1, P2, b.pair_k1, b.pair_off, b.kp_off, b.k_row,
-                           b.k_k2, b.d_plane, ncb, *fo);
+                           b.k_k2, b.d_plane, reinterpret_cast<const int4*>(b.k_ent), ncb, *fo);
     else
         hipLaunchKernelGGL((re_axis12_kernel<WT, C>), dim3((unsigned)(b.d0 * ncb)), dim3(256), shm,
                            s, T0, NC, W, P1, P2, b.pair_k1, b.pair_off, b.kp_off, b.k_row, b.k_k2,
