@@ -265,6 +265,19 @@ phoebe_status phoebe_gpu_scatter_rates_noalloc(void *handle, const phoebe_system
                                                uint8_t *band_mask, int32_t *kept_k_out,
                                                int64_t *n_kept_out, void *stream);
 
+/* Table cache of the rate path (off by default).  With it on, the electron
+ * bands and eigenvectors and the phonon frequencies, eigenvectors and Bose
+ * occupations that a rate call (phoebe_gpu_scatter_rates, _rate_terms,
+ * _delta_weights, _phonon_linewidth) builds on its mesh are kept in a device
+ * buffer of the handle (N (16 nW^2 + 8 nW + 16 nModes^2 + 16 nModes) bytes),
+ * and a later call reuses them instead of rebuilding them when the system's
+ * h_r, phi_r and mass pointers, its lattice lists, nW, n_atoms, the mesh,
+ * omega_min and kT are all the same (results are bitwise the same as without
+ * the cache).  The match is on pointers: a caller that rewrites those arrays
+ * in place must turn the cache off (which frees it) or back on (which empties
+ * it) before the next call.  Not used by phoebe_gpu_scatter_rates_noalloc. */
+phoebe_status phoebe_gpu_set_table_cache(void *handle, int enable);
+
 /* Usable bytes of the static scratch of phoebe_gpu_scatter_rates_noalloc. */
 size_t phoebe_gpu_noalloc_scratch_bytes(void);
 
@@ -393,7 +406,11 @@ phoebe_status phoebe_gpu_mlp_features(void *handle, phoebe_precision prec, const
  * possible, which keeps the estimate unbiased.  S points are drawn by inverse
  * CDF of the given uniforms (device [nk, S] in [0, 1)) and weighted
  * w = 1 / (N_q S p(q)): q_off device int64 [nk+1], q_idx device int32 [nk S],
- * q_w device [nk S], ready for phoebe_gpu_scatter_rates.  Synchronises. */
+ * q_w device [nk S], ready for phoebe_gpu_scatter_rates.  Every k is handled
+ * in the same pass (one selection over all rows, the network over the listed
+ * entries of every k in batches, one sampler work-group per k); nk N_q nModes
+ * must stay below 2^31 (else PHOEBE_E_INVALID: split the k list).
+ * Synchronises once. */
 phoebe_status phoebe_gpu_propose_q(void *handle, const int32_t mesh[3], int32_t n_modes,
                                    int32_t n_harm, const int32_t *k_idx, const double *eps_k, int64_t nk,
                                    const double *dweights, const float *params, int32_t width,

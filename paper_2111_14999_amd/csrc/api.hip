@@ -71,6 +71,7 @@ phoebe_status phoebe_gpu_destroy(void* handle) {
     }
     if (h->ws) (void)hipFree(h->ws);
     if (h->dflag) (void)hipFree(h->dflag);
+    if (h->tc.mem) (void)hipFree(h->tc.mem);
     delete h;
     return PHOEBE_OK;
 }
@@ -646,12 +647,75 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
             HIPCHK(h, hipStreamSynchronize(s));
         }
         {
-            Arena b1 = ar, b2 = ar;
-            electron_bands_dev(h, b1, sys, T.rh, nullptr, nullptr, mesh, N, T.eps, T.U, s);
-            // the rate kernels read each eigenvector contiguously
-            HIPCHK(h, launch_transpose_batch(T.U, N, nW, s));
-            phonon_dev(h, b2, sys, T.rd, nullptr, nullptr, mesh, N, par->omega_min, par->kT,
-                       T.omega, T.E, T.nb, nullptr, s);
+            // band and phonon tables: from the table cache when it holds this system's
+            // tables on this mesh (same inputs, omega_min and kT), else built here
+            const size_t b_eps = sizeof(double) * N * nW, b_U = sizeof(cd) * N * nW * nW,
+                         b_om = sizeof(double) * N * nm, b_E = sizeof(cd) * N * nm * nm;
+            const size_t tc_bytes = b_eps + b_U + 2 * b_om + b_E;
+            TableCache& tc = h->tc;
+            const bool use_cache = h->table_cache && !h->fixed_ws;
+            const std::vector<int32_t> rh_v(sys->rh, sys->rh + 3 * sys->n_rh),
+                rd_v(sys->rd, sys->rd + 3 * sys->n_rd);
+            const bool hit = use_cache && tc.valid && tc.h_r == sys->h_r &&
+                             tc.phi_r == sys->phi_r && tc.mass == sys->mass && tc.nW == nW &&
+                             tc.nat == sys->n_atoms && tc.n0 == mesh.n0 && tc.n1 == mesh.n1 &&
+                             tc.n2 == mesh.n2 && tc.omega_min == par->omega_min &&
+                             tc.kT == par->kT && tc.rh == rh_v && tc.rd == rd_v;
+            char* const parts[5] = {(char*)T.eps, (char*)T.U, (char*)T.omega, (char*)T.E,
+                                    (char*)T.nb};
+            const size_t sizes[5] = {b_eps, b_U, b_om, b_E, b_om};
+            if (hit) {
+                size_t o = 0;
+                for (int i = 0; i < 5; ++i) {
+                    HIPCHK(h, hipMemcpyAsync(parts[i], tc.mem + o, sizes[i],
+                                             hipMemcpyDeviceToDevice, s));
+                    o += sizes[i];
+                }
+            } else {
+                Arena b1 = ar, b2 = ar;
+                electron_bands_dev(h, b1, sys, T.rh, nullptr, nullptr, mesh, N, T.eps, T.U, s);
+                // the rate kernels read each eigenvector contiguously
+                HIPCHK(h, launch_transpose_batch(T.U, N, nW, s));
+                phonon_dev(h, b2, sys, T.rd, nullptr, nullptr, mesh, N, par->omega_min, par->kT,
+                           T.omega, T.E, T.nb, nullptr, s);
+                if (use_cache) {
+                    tc.valid = false;
+                    if (tc.bytes < tc_bytes) {
+                        if (tc.mem) {
+                            HIPCHK(h, hipStreamSynchronize(s));
+                            HIPCHK(h, hipFree(tc.mem));
+                            tc.mem = nullptr;
+                            tc.bytes = 0;
+                        }
+                        if (hipMalloc(&tc.mem, tc_bytes) != hipSuccess) {
+                            tc.mem = nullptr;
+                            set_err(h, "hipMalloc of %zu bytes for the table cache failed",
+                                    tc_bytes);
+                            throw Fail{PHOEBE_E_NOMEM};
+                        }
+                        tc.bytes = tc_bytes;
+                    }
+                    size_t o = 0;
+                    for (int i = 0; i < 5; ++i) {
+                        HIPCHK(h, hipMemcpyAsync(tc.mem + o, parts[i], sizes[i],
+                                                 hipMemcpyDeviceToDevice, s));
+                        o += sizes[i];
+                    }
+                    tc.h_r = sys->h_r;
+                    tc.phi_r = sys->phi_r;
+                    tc.mass = sys->mass;
+                    tc.rh = rh_v;
+                    tc.rd = rd_v;
+                    tc.nW = nW;
+                    tc.nat = sys->n_atoms;
+                    tc.n0 = mesh.n0;
+                    tc.n1 = mesh.n1;
+                    tc.n2 = mesh.n2;
+                    tc.omega_min = par->omega_min;
+                    tc.kT = par->kT;
+                    tc.valid = true;
+                }
+            }
         }
         HIPCHK(h, launch_fermi(T.eps, N * nW, par->mu, par->kT, T.focc, s));
         HIPCHK(h, launch_band_extrema(T.eps, N, nW, T.omega, N, nm, T.bmin, T.bmax, T.wmax, s));
@@ -1162,6 +1226,21 @@ phoebe_status phoebe_gpu_phonon_linewidth(void* handle, const phoebe_system* sys
         (void)hipFree(g);
     }
     return st;
+}
+
+phoebe_status phoebe_gpu_set_table_cache(void* handle, int enable) {
+    if (!handle) return PHOEBE_E_INVALID;
+    Handle* h = static_cast<Handle*>(handle);
+    h->table_cache = enable != 0;
+    h->tc.valid = false;  // on or off, the next call builds its tables
+    if (!enable && h->tc.mem) {
+        (void)hipSetDevice(h->device);
+        (void)hipDeviceSynchronize();
+        (void)hipFree(h->tc.mem);
+        h->tc.mem = nullptr;
+        h->tc.bytes = 0;
+    }
+    return PHOEBE_OK;
 }
 
 phoebe_status phoebe_gpu_set_check_finite(void* handle, int enable) {

@@ -1,6 +1,7 @@
 // C ABI of the learned q-proposal: MLP forward/gradient/Adam, input features,
 // and the proposal sampler that writes weighted per-k q lists for
 // phoebe_gpu_scatter_rates.
+#include "ext.hpp"
 #include "host.hpp"
 #include "mlp.hpp"
 
@@ -248,19 +249,27 @@ phoebe_status phoebe_gpu_propose_q(void* handle, const int32_t mesh[3], int32_t 
         REQUIRE(h, NR < ((int64_t)1 << 31), "mesh x modes too large");
         for (int64_t i = 0; i < nk; ++i)
             REQUIRE(h, k_idx[i] >= 0 && k_idx[i] < N, "k_idx[%lld] not a mesh index", (long long)i);
-        const int64_t chunk = std::min<int64_t>(NR, 262144);
+        REQUIRE(h, nk * NR < ((int64_t)1 << 31), "k count x mesh x modes too large for one call");
+        // every k at once: the selection over all rows, the network in batches of at most
+        // `chunk` listed entries, then one sampler work-group per k
+        const int64_t chunk = 262144;
         const Net net(n_in, params ? width : 1, params ? depth : 0);
         std::vector<float*> Z(net.shape.size()), A(net.shape.size());
         float *X = nullptr, *y = nullptr;
-        double *p = nullptr, *E = nullptr, *dmax = nullptr;
-        int32_t *list = nullptr, *count = nullptr;
+        double *p = nullptr, *E = nullptr, *dmax = nullptr, *ek = nullptr;
+        int32_t *list = nullptr, *counts = nullptr, *kd = nullptr;
+        int64_t* total = nullptr;
+        const int64_t nch = select_rows_chunks(nk, NR);
         auto plan = [&](Arena& ar) {
-            p = ar.take<double>((size_t)N);
-            E = ar.take<double>((size_t)NR);
-            dmax = ar.take<double>(1);
-            count = ar.take<int32_t>(2);
-            list = ar.take<int32_t>((size_t)NR);
+            p = ar.take<double>((size_t)nk * N);
+            kd = ar.take<int32_t>((size_t)nk);
+            ek = ar.take<double>((size_t)nk);
             if (params) {
+                E = ar.take<double>((size_t)nk * NR);
+                dmax = ar.take<double>((size_t)nk);
+                counts = ar.take<int32_t>((size_t)nch);
+                total = ar.take<int64_t>(1);
+                list = ar.take<int32_t>((size_t)nk * NR);
                 X = ar.take<float>((size_t)chunk * n_in);
                 for (size_t l = 0; l < net.shape.size(); ++l) {
                     Z[l] = ar.take<float>((size_t)chunk * net.shape[l].first);
@@ -277,32 +286,30 @@ phoebe_status phoebe_gpu_propose_q(void* handle, const int32_t mesh[3], int32_t 
         std::vector<int64_t> offs(nk + 1);
         for (int64_t i = 0; i <= nk; ++i) offs[i] = i * S;
         HIPCHK(h, hipMemcpyAsync(q_off, offs.data(), sizeof(int64_t) * (nk + 1), hipMemcpyHostToDevice, s));
-        for (int64_t i = 0; i < nk; ++i) {
-            Timer t(h, s, "mlp_proposal");
-            const double* D = dweights + i * NR;
-            if (!params) {
-                HIPCHK(h, launch_sum_modes(D, N, n_modes, p, s));
-            } else {
-                // evaluate the network only where the smearing weight matters
-                HIPCHK(h, launch_rowmax(D, NR, dmax, s));
-                HIPCHK(h, launch_zero(count, 8, s));
-                HIPCHK(h, launch_select(D, NR, dmax, d_threshold, list, count, s));
-                HIPCHK(h, launch_zero(E, (size_t)NR * sizeof(double), s));
-                int32_t cnt = 0;
-                HIPCHK(h, hipMemcpyAsync(&cnt, count, 4, hipMemcpyDeviceToHost, s));
-                HIPCHK(h, hipStreamSynchronize(s));
-                for (int64_t c0 = 0; c0 < cnt; c0 += chunk) {
-                    const int64_t nc = std::min<int64_t>(chunk, cnt - c0);
-                    HIPCHK(h, launch_features_list(k_idx[i], eps_k[i], list + c0, nc, m, n_modes,
-                                                   n_harm, e0, escale, X, s));
-                    forward_impl<float>(h, net, params, X, nc, y, Z, A, s);
-                    HIPCHK(h, launch_weight_list(D, list + c0, y, nc, E, s));
-                }
-                HIPCHK(h, launch_sum_modes(E, N, n_modes, p, s));
+        Timer t(h, s, "mlp_proposal");
+        if (!params) {
+            HIPCHK(h, launch_sum_modes(dweights, nk * N, n_modes, p, s));
+        } else {
+            HIPCHK(h, hipMemcpyAsync(kd, k_idx, sizeof(int32_t) * nk, hipMemcpyHostToDevice, s));
+            HIPCHK(h, hipMemcpyAsync(ek, eps_k, sizeof(double) * nk, hipMemcpyHostToDevice, s));
+            // evaluate the network only where the smearing weight matters
+            HIPCHK(h, launch_ts_state_max(dweights, nk, NR, dmax, s));
+            HIPCHK(h, launch_select_rows(dweights, dmax, nk, NR, d_threshold, counts, total, list, s));
+            HIPCHK(h, launch_zero(E, (size_t)nk * NR * sizeof(double), s));
+            int64_t cnt = 0;
+            HIPCHK(h, hipMemcpyAsync(&cnt, total, sizeof cnt, hipMemcpyDeviceToHost, s));
+            HIPCHK(h, hipStreamSynchronize(s));
+            for (int64_t c0 = 0; c0 < cnt; c0 += chunk) {
+                const int64_t nc = std::min<int64_t>(chunk, cnt - c0);
+                HIPCHK(h, launch_features_flat(kd, ek, list + c0, nc, NR, m, n_modes, n_harm, e0,
+                                               escale, X, s));
+                forward_impl<float>(h, net, params, X, nc, y, Z, A, s);
+                HIPCHK(h, launch_weight_list(dweights, list + c0, y, nc, E, s));
             }
-            HIPCHK(h, launch_sample(p, N, mix, uniforms + i * S, S, q_idx + i * S, q_w + i * S, s));
-            t.done();
+            HIPCHK(h, launch_sum_modes(E, nk * N, n_modes, p, s));
         }
+        HIPCHK(h, launch_sample(p, N, mix, uniforms, S, q_idx, q_w, nk, s));
+        t.done();
         HIPCHK(h, hipStreamSynchronize(s));  // host offsets are read before return
         flush_timing(h, s);
     });

@@ -41,6 +41,18 @@ struct KernelStat {
     double bytes = 0.0;
 };
 
+// Band and phonon tables of the last (system, mesh) the rate path built, kept
+// while the table cache is on (phoebe_gpu_set_table_cache).
+struct TableCache {
+    bool valid = false;
+    const void *h_r = nullptr, *phi_r = nullptr, *mass = nullptr;
+    std::vector<int32_t> rh, rd;
+    int nW = 0, nat = 0, n0 = 0, n1 = 0, n2 = 0;
+    double omega_min = 0.0, kT = 0.0;
+    char* mem = nullptr;
+    size_t bytes = 0;
+};
+
 struct Handle {
     int device = 0;
     size_t budget = 0;
@@ -53,6 +65,8 @@ struct Handle {
     int32_t* dflag = nullptr;  // one device word for the finiteness scan (allocated on first use)
     char* scratch = nullptr;   // the device's static scratch of the non-allocating entry point
     bool fixed_ws = false;     // during such a call: ws is that scratch and is never reallocated
+    bool table_cache = false;  // reuse band and phonon tables across rate calls
+    TableCache tc;
     std::vector<TimedLaunch> pending;
     std::vector<KernelStat> stats;
 };

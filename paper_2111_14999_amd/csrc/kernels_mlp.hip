@@ -8,6 +8,7 @@
 // (double storage) used to check gradients against the FP64 oracle.
 #include <algorithm>
 
+#include "ext.hpp"
 #include "mlp.hpp"
 
 namespace phx {
@@ -381,53 +382,6 @@ hipError_t launch_proposal_raw(const float* y, int64_t nq, int nm, double c, dou
     return hipGetLastError();
 }
 
-// max of a non-negative array: block maxima combined by an atomic max on the
-// IEEE bit patterns (ordered like the values for non-negative doubles); *out
-// must hold +0.0 before the launch
-__global__ __launch_bounds__(256) void rowmax_kernel(const double* x, int64_t n,
-                                                     unsigned long long* out) {
-    __shared__ double sh[256];
-    double m = 0.0;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        m = fmax(m, x[i]);
-    sh[threadIdx.x] = m;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) atomicMax(out, (unsigned long long)__double_as_longlong(sh[0]));
-}
-
-// list (in any order) of the entries with D > thr * max; count[0] must start at 0
-__global__ void select_kernel(const double* D, int64_t n, const double* dmax, double thr,
-                              int32_t* list, int32_t* count) {
-    const double cut = thr * *dmax;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        if (D[i] > cut) list[atomicAdd(count, 1)] = (int32_t)i;
-}
-
-// features of listed (q, nu) entries r = q nm + nu for one k
-__global__ void features_list_kernel(int32_t kmesh, double eps, const int32_t* list, int64_t n,
-                                     Mesh mesh, int nm, int n_harm, double e0, double escale,
-                                     float* X) {
-    const int nin = n_features(nm, n_harm);
-    int k0, k1, k2;
-    mesh_triple(kmesh, mesh, k0, k1, k2);
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r = list[i];
-        const int64_t q = r / nm;
-        const int nu = (int)(r % nm);
-        int a0, a1, a2;
-        mesh_triple(q, mesh, a0, a1, a2);
-        write_features<float>(X + i * nin, k0, k1, k2, a0, a1, a2, nu, (eps - e0) / escale, mesh,
-                              nm, n_harm);
-    }
-}
-
 // E[list[i]] = D[list[i]] exp(y[i])
 __global__ void weight_list_kernel(const double* D, const int32_t* list, const float* y, int64_t n,
                                    double* E) {
@@ -448,27 +402,6 @@ __global__ void sum_modes_kernel(const double* E, int64_t N, int nm, double* p) 
     }
 }
 
-hipError_t launch_rowmax(const double* x, int64_t n, double* out, hipStream_t s) {
-    hipError_t e = hipMemsetAsync(out, 0, sizeof(double), s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(rowmax_kernel, dim3(std::min<int64_t>(gridm(n, 256), 1024)), dim3(256), 0, s,
-                       x, n, reinterpret_cast<unsigned long long*>(out));
-    return hipGetLastError();
-}
-hipError_t launch_select(const double* D, int64_t n, const double* dmax, double thr, int32_t* list,
-                         int32_t* count, hipStream_t s) {
-    hipLaunchKernelGGL(select_kernel, dim3(gridm(n, 256)), dim3(256), 0, s, D, n, dmax, thr, list,
-                       count);
-    return hipGetLastError();
-}
-hipError_t launch_features_list(int32_t kmesh, double eps, const int32_t* list, int64_t n,
-                                Mesh mesh, int nm, int n_harm, double e0, double escale, float* X,
-                                hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(features_list_kernel, dim3(gridm(n, 256)), dim3(256), 0, s, kmesh, eps, list,
-                       n, mesh, nm, n_harm, e0, escale, X);
-    return hipGetLastError();
-}
 hipError_t launch_weight_list(const double* D, const int32_t* list, const float* y, int64_t n,
                               double* E, hipStream_t s) {
     if (n <= 0) return hipSuccess;
@@ -480,12 +413,109 @@ hipError_t launch_sum_modes(const double* E, int64_t N, int nm, double* p, hipSt
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// The proposal for many k at once: entries f = k NR + (q nm + nu) of D [nk, NR]
+// with D > thr x max over the k's row are listed in flat order (per-chunk
+// counts, an exclusive scan, then the writes), so the network runs over the
+// listed entries of every k in a few large batches.
+// ---------------------------------------------------------------------------
+constexpr int kSelChunk = 4096;
+
+__global__ __launch_bounds__(256) void sel_count_kernel(const double* D, const double* dmax,
+                                                        int64_t total, int64_t NR, double thr,
+                                                        int32_t* counts) {
+    __shared__ int sm[4];
+    const int64_t c0 = (int64_t)blockIdx.x * kSelChunk;
+    int n = 0;
+    for (int i = threadIdx.x; i < kSelChunk; i += 256) {
+        const int64_t f = c0 + i;
+        if (f < total && D[f] > thr * dmax[f / NR]) ++n;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o, 64);
+    if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = n;
+    __syncthreads();
+    if (threadIdx.x == 0) counts[blockIdx.x] = sm[0] + sm[1] + sm[2] + sm[3];
+}
+
+__global__ __launch_bounds__(256) void sel_write_kernel(const double* D, const double* dmax,
+                                                        int64_t total, int64_t NR, double thr,
+                                                        const int32_t* offsets, int32_t* list) {
+    __shared__ int wsum[4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t c0 = (int64_t)blockIdx.x * kSelChunk;
+    int64_t base = offsets[blockIdx.x];
+    for (int i0 = 0; i0 < kSelChunk; i0 += 256) {
+        const int64_t f = c0 + i0 + tid;
+        const bool keep = f < total && D[f] > thr * dmax[f / NR];
+        const uint64_t bal = __ballot(keep);
+        if (lane == 0) wsum[wave] = __popcll(bal);
+        __syncthreads();
+        int before = 0;
+        for (int w = 0; w < wave; ++w) before += wsum[w];
+        if (keep) list[base + before + __popcll(bal & ((1ull << lane) - 1ull))] = (int32_t)f;
+        base += wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        __syncthreads();
+    }
+}
+
+hipError_t launch_select_rows(const double* D, const double* dmax, int64_t nk, int64_t NR,
+                              double thr, int32_t* counts, int64_t* total_out, int32_t* list,
+                              hipStream_t s) {
+    const int64_t total = nk * NR;
+    const int64_t nch = (total + kSelChunk - 1) / kSelChunk;
+    if (nch <= 0) return hipSuccess;
+    if (nch > 2147483647LL || total > 2147483647LL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(sel_count_kernel, dim3((unsigned)nch), dim3(256), 0, s, D, dmax, total, NR,
+                       thr, counts);
+    hipError_t e = launch_exclusive_scan(counts, nch, total_out, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sel_write_kernel, dim3((unsigned)nch), dim3(256), 0, s, D, dmax, total, NR,
+                       thr, counts, list);
+    return hipGetLastError();
+}
+int64_t select_rows_chunks(int64_t nk, int64_t NR) { return (nk * NR + kSelChunk - 1) / kSelChunk; }
+
+// features of listed flat entries f = k NR + q nm + nu; k's mesh index and band
+// energy from per-k device arrays
+__global__ void features_flat_kernel(const int32_t* kmesh, const double* epsk, const int32_t* list,
+                                     int64_t n, int64_t NR, Mesh mesh, int nm, int n_harm,
+                                     double e0, double escale, float* X) {
+    const int nin = n_features(nm, n_harm);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t f = list[i];
+        const int64_t kl = f / NR, r = f - kl * NR;
+        const int64_t q = r / nm;
+        const int nu = (int)(r - q * nm);
+        int k0, k1, k2, a0, a1, a2;
+        mesh_triple(kmesh[kl], mesh, k0, k1, k2);
+        mesh_triple(q, mesh, a0, a1, a2);
+        write_features<float>(X + i * nin, k0, k1, k2, a0, a1, a2, nu, (epsk[kl] - e0) / escale,
+                              mesh, nm, n_harm);
+    }
+}
+
+hipError_t launch_features_flat(const int32_t* kmesh, const double* epsk, const int32_t* list,
+                                int64_t n, int64_t NR, Mesh mesh, int nm, int n_harm, double e0,
+                                double escale, float* X, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(features_flat_kernel, dim3(gridm(n, 256)), dim3(256), 0, s, kmesh, epsk,
+                       list, n, NR, mesh, nm, n_harm, e0, escale, X);
+    return hipGetLastError();
+}
+
 // One work-group per k: normalise p_raw (mixed with the uniform distribution),
 // build the CDF by an ordered FP64 scan, draw S points by inverse CDF of the
 // given uniforms and write the importance weights 1 / (N S p(q)).
 __global__ __launch_bounds__(1024) void sample_kernel(double* p, int64_t N, double mix,
                                                       const double* u, int S, int32_t* q_idx,
                                                       double* q_w) {
+    // work-group j samples for the j-th k: its row of p and its S uniforms and outputs
+    p += (int64_t)blockIdx.x * N;
+    u += (int64_t)blockIdx.x * S;
+    q_idx += (int64_t)blockIdx.x * S;
+    q_w += (int64_t)blockIdx.x * S;
     __shared__ double wsum[16];
     __shared__ double base_sh;
     __shared__ double total_sh;
@@ -544,8 +574,11 @@ __global__ __launch_bounds__(1024) void sample_kernel(double* p, int64_t N, doub
 }
 
 hipError_t launch_sample(double* p, int64_t N, double mix, const double* u, int S, int32_t* q_idx,
-                         double* q_w, hipStream_t s) {
-    hipLaunchKernelGGL(sample_kernel, dim3(1), dim3(1024), 0, s, p, N, mix, u, S, q_idx, q_w);
+                         double* q_w, int64_t nk, hipStream_t s) {
+    if (nk <= 0) return hipSuccess;
+    if (nk > 2147483647LL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(sample_kernel, dim3((unsigned)nk), dim3(1024), 0, s, p, N, mix, u, S, q_idx,
+                       q_w);
     return hipGetLastError();
 }
 

@@ -27,16 +27,19 @@ hipError_t launch_features(const int32_t* k_idx, const double* eps, const int32_
 int feature_count(int nm, int n_harm);
 hipError_t launch_proposal_raw(const float* y, int64_t nq, int nm, double c, double* p,
                                hipStream_t s);
-hipError_t launch_rowmax(const double* x, int64_t n, double* out, hipStream_t s);
-hipError_t launch_select(const double* D, int64_t n, const double* dmax, double thr, int32_t* list,
-                         int32_t* count, hipStream_t s);
-hipError_t launch_features_list(int32_t kmesh, double eps, const int32_t* list, int64_t n,
-                                Mesh mesh, int nm, int n_harm, double e0, double escale, float* X,
-                                hipStream_t s);
 hipError_t launch_weight_list(const double* D, const int32_t* list, const float* y, int64_t n,
                               double* E, hipStream_t s);
 hipError_t launch_sum_modes(const double* E, int64_t N, int nm, double* p, hipStream_t s);
 hipError_t launch_sample(double* p, int64_t N, double mix, const double* u, int S, int32_t* q_idx,
-                         double* q_w, hipStream_t s);
+                         double* q_w, int64_t nk, hipStream_t s);
+// entries f = k NR + r of D [nk, NR] with D > thr dmax[k], in flat order; counts has
+// select_rows_chunks(nk, NR) entries, total_out one (device)
+hipError_t launch_select_rows(const double* D, const double* dmax, int64_t nk, int64_t NR,
+                              double thr, int32_t* counts, int64_t* total_out, int32_t* list,
+                              hipStream_t s);
+int64_t select_rows_chunks(int64_t nk, int64_t NR);
+hipError_t launch_features_flat(const int32_t* kmesh, const double* epsk, const int32_t* list,
+                                int64_t n, int64_t NR, Mesh mesh, int nm, int n_harm, double e0,
+                                double escale, float* X, hipStream_t s);
 
 }  // namespace phx

@@ -278,3 +278,42 @@ def test_mesh_sum_mode_errors(lib, toy):
         assert e.value.status == -4
     finally:
         lib.set_mesh_sum("auto")
+
+
+def test_table_cache_bitwise_and_keyed():
+    """Rates with the table cache on: the second call reuses the tables and gives the
+    same bits as a call without the cache; a different kT, mesh or system rebuilds."""
+    torch = torch_cuda()
+    from paper_2111_14999_amd import DeviceSystem, Library
+    lib = Library(0)
+    s = synth.small_system(17, n_wannier=5, n_atoms=2, r=1)
+    s.h_r *= 0.3
+    mesh = (4, 3, 5)
+    t = rates.mesh_tables(s, mesh)
+    mu = float(np.median(t["eps"]))
+    par = dict(mu=mu, kT=constants.kT_of(300.0), sigma=0.05, win_lo=mu - 0.8, win_hi=mu + 0.8,
+               omega_min=1e-4)
+    ds = DeviceSystem.from_host(s)
+    N = int(np.prod(mesh))
+
+    def run(p, m=mesh):
+        g = torch.zeros((int(np.prod(m)), s.n_wannier), dtype=torch.float64, device="cuda")
+        n = lib.scatter_rates(ds, m, p, g)
+        torch.cuda.synchronize()
+        return g.cpu().numpy()[:n]
+
+    ref = run(par)
+    par2 = dict(par, kT=constants.kT_of(400.0))
+    ref2 = run(par2)
+    ref3 = run(par, (3, 3, 3))
+    lib.set_table_cache(True)
+    for _ in range(2):  # build, then reuse
+        assert np.array_equal(run(par), ref)
+    assert np.array_equal(run(par2), ref2)        # kT changed: rebuilt
+    assert np.array_equal(run(par, (3, 3, 3)), ref3)
+    assert np.array_equal(run(par), ref)
+    lib.set_table_cache(False)
+    assert np.array_equal(run(par), ref)
+    o = rates.scattering_rates(s, mesh, tables=t, **par)
+    assert np.max(np.abs(ref - o["gamma"])) < 1e-9 * np.max(o["gamma"])
+    lib.close()
