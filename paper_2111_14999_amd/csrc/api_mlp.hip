@@ -40,11 +40,11 @@ void forward_impl(Handle* h, const Net& net, const T* P, const T* X, int64_t B, 
         const T* b = P + off + (int64_t)o * i;
         off += (int64_t)o * i + o;
         T* z = (l + 1 == net.shape.size() && out) ? out : Z[l];
-        HIPCHK(h, launch_mlp_gemm<T>(false, true, a, i, W, i, z, o, B, o, i, b, 0, s));
-        if (l + 1 < net.shape.size()) {
-            HIPCHK(h, launch_silu_fwd<T>(z, A[l], B * o, s));
-            a = A[l];
-        }
+        const bool hidden = l + 1 < net.shape.size();
+        // hidden layers: z and silu(z) from the same pass
+        HIPCHK(h, launch_mlp_gemm<T>(false, true, a, i, W, i, z, o, B, o, i, b, 0, s,
+                                     hidden ? A[l] : nullptr));
+        if (hidden) a = A[l];
     }
 }
 

@@ -97,6 +97,95 @@ __global__ __launch_bounds__(256) void mlp_gemm_bf16(const float* __restrict__ A
             }
 }
 
+// The same BF16 product, LDS-tiled: a work-group of 4 waves owns a 128 x 128 tile
+// of C (each wave 64 x 64: 4 x 4 MFMA tiles); per 32-wide K step the A and B tiles
+// are converted to BF16 once, staged in LDS (rows padded to 40 BF16 so the 16-byte
+// fragment reads of a 16-lane group hit distinct banks) and read from there by
+// every wave.  The K steps, the MFMA and the epilogue are those of mlp_gemm_bf16,
+// so the results are the same bits.  With act set, silu(C) is written there too.
+constexpr int kGT = 128;   // tile rows and columns
+constexpr int kGK = 32;    // K step
+constexpr int kGLd = 40;   // LDS row stride (BF16 elements)
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void mlp_gemm_bf16_tiled(
+    const float* __restrict__ A, int64_t lda, const float* __restrict__ B, int64_t ldb,
+    float* __restrict__ C, int64_t ldc, int64_t M, int64_t N, int64_t K,
+    const float* __restrict__ bias, int accumulate, float* __restrict__ act) {
+    __shared__ __align__(16) uint16_t sA[kGT * kGLd];
+    __shared__ __align__(16) uint16_t sB[kGT * kGLd];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int64_t m0 = (int64_t)blockIdx.y * kGT, n0 = (int64_t)blockIdx.x * kGT;
+    f4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[i][t] = f4{0, 0, 0, 0};
+    // element (row r of the tile, k) of op(A) and (k, column c) of op(B)
+    auto a_at = [&](int64_t row, int64_t k) -> float {
+        return (row < M && k < K) ? (TA ? A[k * lda + row] : A[row * lda + k]) : 0.f;
+    };
+    auto b_at = [&](int64_t col, int64_t k) -> float {
+        return (col < N && k < K) ? (TB ? B[col * ldb + k] : B[k * ldb + col]) : 0.f;
+    };
+    for (int64_t k0 = 0; k0 < K; k0 += kGK) {
+        // stage: each thread converts 8 (row, k pair) entries of each tile; pairs
+        // along k for row-major operands, along the rows for transposed ones, so
+        // that neighbouring threads read neighbouring addresses
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int e = tid + 256 * j;
+            const int r = TA ? (e & (kGT - 1)) : (e >> 4);
+            const int kp = TA ? (e >> 7) : (e & 15);
+            const int64_t row = m0 + r, k = k0 + 2 * kp;
+            const uint32_t v = (uint32_t)f2bf(a_at(row, k)) | ((uint32_t)f2bf(a_at(row, k + 1)) << 16);
+            *reinterpret_cast<uint32_t*>(&sA[r * kGLd + 2 * kp]) = v;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int e = tid + 256 * j;
+            const int c = TB ? (e >> 4) : (e & (kGT - 1));
+            const int kp = TB ? (e & 15) : (e >> 7);
+            const int64_t col = n0 + c, k = k0 + 2 * kp;
+            const uint32_t v = (uint32_t)f2bf(b_at(col, k)) | ((uint32_t)f2bf(b_at(col, k + 1)) << 16);
+            *reinterpret_cast<uint32_t*>(&sB[c * kGLd + 2 * kp]) = v;
+        }
+        __syncthreads();
+        s8m a[4], b[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            a[i] = *reinterpret_cast<const s8m*>(&sA[(64 * wm + 16 * i + li) * kGLd + 8 * lk]);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            b[t] = *reinterpret_cast<const s8m*>(&sB[(64 * wn + 16 * t + li) * kGLd + 8 * lk]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    __builtin_bit_cast(bf8m, a[i]), __builtin_bit_cast(bf8m, b[t]), acc[i][t], 0, 0, 0);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t row = m0 + 64 * wm + 16 * i + 4 * lk + v;
+                const int64_t col = n0 + 64 * wn + 16 * t + li;
+                if (row < M && col < N) {
+                    float r = acc[i][t][v];
+                    if (bias) r += bias[col];
+                    if (accumulate) r += C[row * ldc + col];
+                    C[row * ldc + col] = r;
+                    if (act) act[row * ldc + col] = r / (1.0f + exp(-r));
+                }
+            }
+}
+
 template <bool TA, bool TB>
 __global__ __launch_bounds__(256) void mlp_gemm_f64(const double* __restrict__ A, int64_t lda,
                                                     const double* __restrict__ B, int64_t ldb,
@@ -153,8 +242,31 @@ __global__ __launch_bounds__(256) void mlp_gemm_f64(const double* __restrict__ A
 template <class T>
 hipError_t launch_mlp_gemm(bool ta, bool tb, const T* A, int64_t lda, const T* B, int64_t ldb, T* C,
                            int64_t ldc, int64_t M, int64_t N, int64_t K, const T* bias, int acc,
-                           hipStream_t s) {
+                           hipStream_t s, T* act) {
     if (M <= 0 || N <= 0) return hipSuccess;
+    if constexpr (sizeof(T) == 4) {
+        // large products (the network over many samples) on the tiled kernel, where its
+        // 128 x 128 tiles still make enough work-groups to fill the chip
+        if (N >= 64 && ((M + kGT - 1) / kGT) * ((N + kGT - 1) / kGT) >= 512) {
+            dim3 g((unsigned)((N + kGT - 1) / kGT), (unsigned)((M + kGT - 1) / kGT));
+            if (g.y > 65535) return hipErrorInvalidValue;
+#define PHX_GT(TAv, TBv)                                                                         \
+            if (ta == TAv && tb == TBv) {                                                        \
+                hipLaunchKernelGGL((mlp_gemm_bf16_tiled<TAv, TBv>), g, dim3(256), 0, s,          \
+                                   (const float*)A, lda, (const float*)B, ldb, (float*)C, ldc,   \
+                                   M, N, K, (const float*)bias, acc, (float*)act);               \
+                return hipGetLastError();                                                        \
+            }
+            PHX_GT(false, false) PHX_GT(false, true) PHX_GT(true, false) PHX_GT(true, true)
+#undef PHX_GT
+        }
+    }
+    if (act) {  // the small products: the activation as its own pass
+        hipError_t e = launch_mlp_gemm<T>(ta, tb, A, lda, B, ldb, C, ldc, M, N, K, bias, acc, s);
+        if (e != hipSuccess) return e;
+        if (ldc != N) return hipErrorInvalidValue;
+        return launch_silu_fwd<T>(C, act, M * N, s);
+    }
     dim3 grid((unsigned)((N + 127) / 128), (unsigned)((M + 31) / 32));
     if (grid.y > 65535) return hipErrorInvalidValue;
 #define PHX_GO(TAv, TBv)                                                                        \
@@ -175,10 +287,10 @@ hipError_t launch_mlp_gemm(bool ta, bool tb, const T* A, int64_t lda, const T* B
 }
 template hipError_t launch_mlp_gemm<float>(bool, bool, const float*, int64_t, const float*, int64_t,
                                            float*, int64_t, int64_t, int64_t, int64_t, const float*,
-                                           int, hipStream_t);
+                                           int, hipStream_t, float*);
 template hipError_t launch_mlp_gemm<double>(bool, bool, const double*, int64_t, const double*,
                                             int64_t, double*, int64_t, int64_t, int64_t, int64_t,
-                                            const double*, int, hipStream_t);
+                                            const double*, int, hipStream_t, double*);
 
 // ---------------------------------------------------------------------------
 // elementwise pieces

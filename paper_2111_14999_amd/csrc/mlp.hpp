@@ -5,10 +5,11 @@
 
 namespace phx {
 
+// with act set, silu(C) is also written to act (same leading dimension)
 template <class T>
 hipError_t launch_mlp_gemm(bool ta, bool tb, const T* A, int64_t lda, const T* B, int64_t ldb, T* C,
                            int64_t ldc, int64_t M, int64_t N, int64_t K, const T* bias, int acc,
-                           hipStream_t s);
+                           hipStream_t s, T* act = nullptr);
 template <class T>
 hipError_t launch_silu_fwd(const T* z, T* a, int64_t n, hipStream_t s);
 template <class T>
