@@ -1149,8 +1149,8 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                     // points of every unit
                     tl.done(0.0, nl, (double)g_elem * Wbox * nm * nW, nl + 1, 16.0 * nW * sizeof(cd));
                     if (lwbuf)
-                        HIPCHK(h, launch_lw_reduce_lines(lwbuf, lineany, nn, (int)NL, mesh.n0, nm,
-                                                         T.lwacc, s));
+                        HIPCHK(h, launch_lw_reduce_lines(lwbuf, lineany, livebuf, nn, (int)NL,
+                                                         mesh.n0, nm, T.lwacc, s));
                 }
             }
             HIPCHK(h, launch_reduce_partials(partial, ns, n_qtiles, T.st_row + sbeg,

@@ -43,8 +43,9 @@ hipError_t launch_velocity_max(const double* v, int64_t np, int nW, double* vmax
 // Linewidth partials -> acc[q, nu] (+=), states in order.  Factorised layout:
 // lw[st, line, q0, nu] for the (state, line) pairs with line_bands != 0, q = q0 NL +
 // line.  Direct layout: lw[st, q, nu].
-hipError_t launch_lw_reduce_lines(const double* lw, const uint32_t* line_bands, int nst, int NL,
-                                  int N0, int nm, double* acc, hipStream_t s);
+hipError_t launch_lw_reduce_lines(const double* lw, const uint32_t* line_bands,
+                                  const uint32_t* live, int nst, int NL, int N0, int nm,
+                                  double* acc, hipStream_t s);
 hipError_t launch_lw_reduce_dense(const double* lw, int nst, int64_t N, int nm, double* acc,
                                   hipStream_t s);
 // P = scale n (n + 1) omega acc for omega >= omega_min, else 0.

@@ -264,8 +264,9 @@ hipError_t launch_velocity_max(const double* v, int64_t np, int nW, double* vmax
 // ---------------------------------------------------------------------------
 // Phonon linewidth (Transport Methods, phonon BTE): sums over states in order
 // ---------------------------------------------------------------------------
-__global__ void lw_reduce_lines_kernel(const double* lw, const uint32_t* line_bands, int nst,
-                                       int NL, int N0, int nm, double* acc) {
+__global__ void lw_reduce_lines_kernel(const double* lw, const uint32_t* line_bands,
+                                       const uint32_t* live, int nst, int NL, int N0, int nm,
+                                       double* acc) {
     const int64_t per = (int64_t)N0 * nm;
     const int64_t total = (int64_t)NL * per;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
@@ -273,18 +274,21 @@ __global__ void lw_reduce_lines_kernel(const double* lw, const uint32_t* line_ba
         const int line = (int)(t / per);
         const int64_t j = t - line * per;  // q0 nm + nu
         double s = 0.0;
-        for (int st = 0; st < nst; ++st)
-            if (line_bands[(int64_t)st * NL + line]) s += lw[((int64_t)st * NL + line) * per + j];
         const int q0 = (int)(j / nm), nu = (int)(j - (int64_t)q0 * nm);
+        // a (state, line) pair's partials exist at its live points only
+        for (int st = 0; st < nst; ++st)
+            if (line_bands[(int64_t)st * NL + line] && live[((int64_t)st * NL + line) * N0 + q0])
+                s += lw[((int64_t)st * NL + line) * per + j];
         acc[((int64_t)q0 * NL + line) * nm + nu] += s;
     }
 }
 
-hipError_t launch_lw_reduce_lines(const double* lw, const uint32_t* line_bands, int nst, int NL,
-                                  int N0, int nm, double* acc, hipStream_t s) {
+hipError_t launch_lw_reduce_lines(const double* lw, const uint32_t* line_bands,
+                                  const uint32_t* live, int nst, int NL, int N0, int nm,
+                                  double* acc, hipStream_t s) {
     if (nst <= 0) return hipSuccess;
     hipLaunchKernelGGL(lw_reduce_lines_kernel, dim3(grid_n((int64_t)NL * N0 * nm, 256)), dim3(256),
-                       0, s, lw, line_bands, nst, NL, N0, nm, acc);
+                       0, s, lw, line_bands, live, nst, NL, N0, nm, acc);
     return hipGetLastError();
 }
 

@@ -854,10 +854,21 @@ __device__ inline f4 mfma16(float x, float y, f4 c) {
 // building and the unit's gathers overlap them; KS = 0 loads them per K step.
 constexpr int kTP = 2;  // column tiles per MFMA pass
 
-// EXT (FP64 only): the optional polar term, adaptive widths and linewidth
+// FEAT (FP64 only, a bit set; 0 for the plain rates): kLineLW linewidth
+// partials, kLinePol the polar term, kLineVel adaptive widths.  Each variant
+// carries only the registers of its own terms.
 // partials (RateArgs.Lpol / vel / lw), each switched on by its pointer.
-template <int TN, int KS, class C, bool EXT>
-__global__ __launch_bounds__(256, 4) void line_rates_kernel(RateArgs a) {
+// Waves per SIMD the line kernel is compiled for: four for the plain rates; the
+// extension terms need more registers, and at four waves they would spill.
+constexpr int kLineLW = 1, kLinePol = 2, kLineVel = 4;
+template <int FEAT>
+constexpr int line_waves_per_simd() {
+    return FEAT == 0 || FEAT == kLineLW ? 4 : 3;
+}
+
+template <int TN, int KS, class C, int FEAT>
+__global__ __launch_bounds__(256, line_waves_per_simd<FEAT>()) void line_rates_kernel(RateArgs a) {
+    constexpr bool LW = FEAT & kLineLW, POL = FEAT & kLinePol, VEL = FEAT & kLineVel;
     using R = decltype(C::x);
     constexpr bool F64 = sizeof(R) == 8;
     using V4 = std::conditional_t<F64, d4, f4>;
@@ -872,11 +883,11 @@ __global__ __launch_bounds__(256, 4) void line_rates_kernel(RateArgs a) {
     C* sY = sP + (N0 + 1) * Wp;                                // [16][nm]
     uint32_t* sPm = reinterpret_cast<uint32_t*>(sY + 16 * nm);  // [N0] live bands per point
     int* sList = reinterpret_cast<int*>(sPm + N0);             // [N0] live points of a band
-    // EXT: [N0][nm] linewidth partials of the work-group (8-byte aligned: N0 ints above)
+    // LW: [N0][nm] linewidth partials of the work-group (8-byte aligned: N0 ints above)
     double* sLW = reinterpret_cast<double*>(sList + N0 + (N0 & 1));
     __shared__ double sRed[4];
     __shared__ int sCount;
-    __shared__ cd sO[16];  // EXT: overlap [U_k^dagger U_{k+q}]_{n m} at the unit's points
+    __shared__ cd sO[16];  // POL: overlap [U_k^dagger U_{k+q}]_{n m} at the unit's points
 
     // XCD-aware order: work-groups are dealt to the 8 XCDs round-robin, so
     // with id = 8 j + x every state of a line lands on XCD x, one after
@@ -905,19 +916,19 @@ __global__ __launch_bounds__(256, 4) void line_rates_kernel(RateArgs a) {
     // |y| > 27.5 sigma: y^2/sigma^2 > 756 and exp(-756) is below the smallest
     // FP64 subnormal, so such a Gaussian is exactly 0
     const double cut = 27.5 * a.sigma;
-    // EXT per-state values: U_k column n (lane rows 4 lg + v), v_nk, f (1 - f) / kT
+    // per-state values of the extensions: U_k column n (lane rows 4 lg + v), v_nk, f (1 - f) / kT
     cd ukn[4] = {};
     double vn[3] = {0.0, 0.0, 0.0};
     double mdf = 0.0;
-    if constexpr (EXT) {
-        if (a.Lpol) {
+    if constexpr (POL || VEL || LW) {
+        if (POL && a.Lpol) {
 #pragma unroll
             for (int v = 0; v < 4; ++v)
                 if (4 * lg + v < nW) ukn[v] = a.U[((int64_t)kmesh * nW + nband) * nW + 4 * lg + v];
         }
-        if (a.vel)
+        if (VEL && a.vel)
             for (int d = 0; d < 3; ++d) vn[d] = a.vel[((int64_t)kmesh * nW + nband) * 3 + d];
-        if (a.lw) {
+        if (LW && a.lw) {
             const double fn = a.focc[(int64_t)kmesh * nW + nband];
             mdf = fn * (1.0 - fn) * a.inv_kT;
             for (int i = tid; i < N0 * nm; i += 256) sLW[i] = 0.0;
@@ -1000,7 +1011,7 @@ __global__ __launch_bounds__(256, 4) void line_rates_kernel(RateArgs a) {
         const double x = eps_n - em;
         const double y1 = x - w, y2 = x + w;
         double is2 = inv_s2, cutv = cut, wt = 1.0;
-        if constexpr (EXT) {
+        if constexpr (VEL) {
             if (a.vel) {  // adaptive width of the transition (k n) -> (k+q m)
                 const double* vm = a.vel + (kq_of(q0) * nW + m) * 3;
                 double s2 = 0.0;
@@ -1022,7 +1033,7 @@ __global__ __launch_bounds__(256, 4) void line_rates_kernel(RateArgs a) {
         const cd* Eq = a.E + (q * nm + nu) * nm;
         C z = {0, 0};
         for (int sa = 0; sa < nm; ++sa) z = cfma(to_c<C>(Eq[sa]), Yr[sa], z);
-        if constexpr (EXT) {
+        if constexpr (POL) {
             if (a.Lpol) {  // + i L(q, nu) O_nm
                 const cd l = a.Lpol[q * nm + nu];
                 const cd o = sO[c];
@@ -1036,7 +1047,7 @@ __global__ __launch_bounds__(256, 4) void line_rates_kernel(RateArgs a) {
         gacc += term;
         if (a.terms)
             atomicAdd(&a.terms[((int64_t)st * a.nq_mesh + q) * nm + nu], a.terms_scale * term);
-        if constexpr (EXT) {
+        if constexpr (LW) {
             if (a.lw) sLW[q0 * nm + nu] += mdf * z2 * g1;  // one thread per (q0, nu) per unit
         }
     };
@@ -1132,7 +1143,7 @@ __global__ __launch_bounds__(256, 4) void line_rates_kernel(RateArgs a) {
                         reinterpret_cast<R*>(sY + li * nm + sa)[lg >> 1] = y;
                 }
             }
-            if constexpr (EXT) {
+            if constexpr (POL) {
                 if (a.Lpol) {  // O at point li: sum over the lane's four b, then over the rows
                     cd o = {0.0, 0.0};
 #pragma unroll
@@ -1164,10 +1175,12 @@ __global__ __launch_bounds__(256, 4) void line_rates_kernel(RateArgs a) {
     if (lane == 0) sRed[wave] = gacc;
     __syncthreads();
     if (tid == 0) a.partial[(int64_t)st * a.n_qtiles + line] = (sRed[0] + sRed[1]) + (sRed[2] + sRed[3]);
-    if constexpr (EXT) {
+    if constexpr (LW) {
         if (a.lw) {  // (the last __syncthreads above ordered every sLW update)
+            // only the live points' partials: the reduction reads those alone
             double* o = a.lw + ((int64_t)st * NL + line) * N0 * nm;
-            for (int i = tid; i < N0 * nm; i += 256) o[i] = sLW[i];
+            for (int i = tid; i < N0 * nm; i += 256)
+                if (sPm[i / nm]) o[i] = sLW[i];
         }
     }
 }
@@ -1186,11 +1199,11 @@ int line_rates_ncpad(int nm, int nW) {
     return 64 * (tn == 5 ? 6 : (tn == 7 ? 8 : tn));
 }
 
-template <int TN, int KS, class C, bool EXT>
+template <int TN, int KS, class C, int FEAT>
 static hipError_t go_line(const RateArgs& a, int nst, hipStream_t s) {
     const size_t shm = line_rates_lds(a.W, a.mesh.n0, a.nm, sizeof(C) == sizeof(cf), a.lw != nullptr);
     if (shm > 64 * 1024) return hipErrorInvalidValue;
-    hipError_t e = hipFuncSetAttribute((const void*)line_rates_kernel<TN, KS, C, EXT>,
+    hipError_t e = hipFuncSetAttribute((const void*)line_rates_kernel<TN, KS, C, FEAT>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) return e;
     const int64_t NL = (int64_t)a.mesh.n1 * a.mesh.n2;
@@ -1211,7 +1224,7 @@ static hipError_t go_line(const RateArgs& a, int nst, hipStream_t s) {
         b.line_bands = a.line_bands + (int64_t)s0 * NL;
         if (a.lw) b.lw = a.lw + (int64_t)s0 * NL * a.mesh.n0 * a.nm;
         b.n_states = ns;
-        hipLaunchKernelGGL((line_rates_kernel<TN, KS, C, EXT>), dim3((unsigned)(groups * 8 * ns)),
+        hipLaunchKernelGGL((line_rates_kernel<TN, KS, C, FEAT>), dim3((unsigned)(groups * 8 * ns)),
                            dim3(256), shm, s, b);
     }
     return hipGetLastError();
@@ -1224,29 +1237,34 @@ static hipError_t line_rates(const RateArgs& a, int nst, hipStream_t s) {
         line_rates_ncpad(a.nm, a.nW) != a.nc_pad || !a.live || !a.line_bands)
         return hipErrorInvalidValue;
     const bool pre = a.W <= 8;  // T2 rows fit two K steps: registers
-    const bool ext = a.Lpol || a.vel || a.lw;
-    if constexpr (sizeof(C) == sizeof(cd)) {
-        if (ext) {
-            switch (a.nc_pad / 64) {
-                case 1: return pre ? go_line<1, 2, C, true>(a, nst, s) : go_line<1, 0, C, true>(a, nst, s);
-                case 2: return pre ? go_line<2, 2, C, true>(a, nst, s) : go_line<2, 0, C, true>(a, nst, s);
-                case 3: return pre ? go_line<3, 2, C, true>(a, nst, s) : go_line<3, 0, C, true>(a, nst, s);
-                case 4: return pre ? go_line<4, 2, C, true>(a, nst, s) : go_line<4, 0, C, true>(a, nst, s);
-                case 6: return go_line<6, 0, C, true>(a, nst, s);
-                case 8: return go_line<8, 0, C, true>(a, nst, s);
-                default: return hipErrorInvalidValue;
+    const int feat = (a.lw ? kLineLW : 0) | (a.Lpol ? kLinePol : 0) | (a.vel ? kLineVel : 0);
+    if (feat && sizeof(C) != sizeof(cd)) return hipErrorInvalidValue;  // the extensions are FP64 only
+    auto with_feat = [&](auto tn, auto ks) -> hipError_t {
+        constexpr int TN = decltype(tn)::value, KS = decltype(ks)::value;
+        if constexpr (sizeof(C) == sizeof(cd)) {
+            switch (feat) {
+                case 0: return go_line<TN, KS, C, 0>(a, nst, s);
+                case kLineLW: return go_line<TN, KS, C, kLineLW>(a, nst, s);
+                case kLinePol: return go_line<TN, KS, C, kLinePol>(a, nst, s);
+                case kLineVel: return go_line<TN, KS, C, kLineVel>(a, nst, s);
+                default: return go_line<TN, KS, C, kLineLW | kLinePol | kLineVel>(a, nst, s);
             }
+        } else {
+            return go_line<TN, KS, C, 0>(a, nst, s);
         }
-    } else {
-        if (ext) return hipErrorInvalidValue;  // the extensions are FP64 only
-    }
+    };
+    using std::integral_constant;
     switch (a.nc_pad / 64) {
-        case 1: return pre ? go_line<1, 2, C, false>(a, nst, s) : go_line<1, 0, C, false>(a, nst, s);
-        case 2: return pre ? go_line<2, 2, C, false>(a, nst, s) : go_line<2, 0, C, false>(a, nst, s);
-        case 3: return pre ? go_line<3, 2, C, false>(a, nst, s) : go_line<3, 0, C, false>(a, nst, s);
-        case 4: return pre ? go_line<4, 2, C, false>(a, nst, s) : go_line<4, 0, C, false>(a, nst, s);
-        case 6: return go_line<6, 0, C, false>(a, nst, s);
-        case 8: return go_line<8, 0, C, false>(a, nst, s);
+        case 1: return pre ? with_feat(integral_constant<int, 1>{}, integral_constant<int, 2>{})
+                           : with_feat(integral_constant<int, 1>{}, integral_constant<int, 0>{});
+        case 2: return pre ? with_feat(integral_constant<int, 2>{}, integral_constant<int, 2>{})
+                           : with_feat(integral_constant<int, 2>{}, integral_constant<int, 0>{});
+        case 3: return pre ? with_feat(integral_constant<int, 3>{}, integral_constant<int, 2>{})
+                           : with_feat(integral_constant<int, 3>{}, integral_constant<int, 0>{});
+        case 4: return pre ? with_feat(integral_constant<int, 4>{}, integral_constant<int, 2>{})
+                           : with_feat(integral_constant<int, 4>{}, integral_constant<int, 0>{});
+        case 6: return with_feat(integral_constant<int, 6>{}, integral_constant<int, 0>{});
+        case 8: return with_feat(integral_constant<int, 8>{}, integral_constant<int, 0>{});
         default: return hipErrorInvalidValue;
     }
 }
