@@ -305,6 +305,18 @@ def main():
                    sample=f"{len(sample)} seeded kept k of {n_kept} over the full {N}-q mesh "
                           f"({t_k:.1f} s) + band/phonon tables on the mesh ({t_tab:.1f} s) "
                           f"pro-rated per kept k; NumPy/OpenBLAS threads = host cores")
+        # the same oracle on one thread (one kept k)
+        try:
+            from threadpoolctl import threadpool_limits
+            with threadpool_limits(limits=1):
+                t1 = time.perf_counter()
+                rates.scattering_rates(s, mesh, k_idx=kidx[sample[:1]], tables=tables, **kw, **par)
+                t_1 = time.perf_counter() - t1
+            cpu["value_1thread"] = round(1.0 / (t_1 + t_tab / n_kept), 4)
+            cpu["sample_1thread"] = (f"1 kept k over the full mesh on one BLAS thread ({t_1:.1f} s), "
+                                     f"tables pro-rated as above")
+        except ImportError:
+            pass
         got = g[sample]
         rm = ref["gamma"]
         sel = rm > 1e-10 * rm.max()

@@ -278,6 +278,14 @@ phoebe_status phoebe_gpu_scatter_rates_noalloc(void *handle, const phoebe_system
  * it) before the next call.  Not used by phoebe_gpu_scatter_rates_noalloc. */
 phoebe_status phoebe_gpu_set_table_cache(void *handle, int enable);
 
+/* Testing aid for callers' error handling: with at > 0, the at-th HIP runtime
+ * call the library checks from now on (on this handle) is reported as failed
+ * although it succeeded; the call in progress then waits for the device and
+ * returns PHOEBE_E_DEVICE with a last-error message ending in "(injected)".  The
+ * injection fires once; the handle stays usable.  at = 0 disarms it, at < 0 is
+ * PHOEBE_E_INVALID. */
+phoebe_status phoebe_gpu_set_fault_injection(void *handle, int64_t at);
+
 /* Usable bytes of the static scratch of phoebe_gpu_scatter_rates_noalloc. */
 size_t phoebe_gpu_noalloc_scratch_bytes(void);
 

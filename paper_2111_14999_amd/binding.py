@@ -41,6 +41,7 @@ EXPORTS = (
     "phoebe_gpu_mlp_init", "phoebe_gpu_training_set", "phoebe_gpu_gather_rows",
     "phoebe_gpu_set_check_finite", "phoebe_gpu_scatter_rates_noalloc",
     "phoebe_gpu_noalloc_scratch_bytes", "phoebe_gpu_set_table_cache",
+    "phoebe_gpu_set_fault_injection",
 )
 
 SMEARING = {"gaussian": 0, "adaptive": 1}
@@ -143,6 +144,7 @@ def load(path: str = LIB_PATH):
     lib.phoebe_gpu_gather_rows.argtypes = [vp, vp, i64, i64, vp, i64, vp, vp]
     lib.phoebe_gpu_set_check_finite.argtypes = [vp, ctypes.c_int]
     lib.phoebe_gpu_set_table_cache.argtypes = [vp, ctypes.c_int]
+    lib.phoebe_gpu_set_fault_injection.argtypes = [vp, i64]
     lib.phoebe_gpu_set_timing.argtypes = [vp, ctypes.c_int]
     lib.phoebe_gpu_set_mesh_sum.argtypes = [vp, i32]
     lib.phoebe_gpu_kernel_bytes.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double)]
@@ -468,6 +470,10 @@ class Library:
         self._check(self.lib.phoebe_gpu_gather_rows(
             self.handle, _ptr(src), int(src.shape[0]), row_bytes, _ptr(idx), int(idx.shape[0]),
             _ptr(dst), _stream(stream)))
+
+    def set_fault_injection(self, at: int):
+        """Report the at-th checked HIP call from now on as failed (0: off); for testing."""
+        self._check(self.lib.phoebe_gpu_set_fault_injection(self.handle, int(at)))
 
     def set_table_cache(self, on: bool):
         """Reuse band and phonon tables across rate calls on the same system and mesh."""

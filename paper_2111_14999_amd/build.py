@@ -68,7 +68,9 @@ def build(verbose: bool = False) -> str:
                 sys.stderr.write("\n".join(warns) + "\n")
             objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = [cc, "-shared", "-fPIC", f"--offload-arch={ARCH}"] + objs + ["-o", tmp]
+    # roctx: named ranges per entry point for tracing tools
+    cmd = [cc, "-shared", "-fPIC", f"--offload-arch={ARCH}"] + objs + [
+        "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib", "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)

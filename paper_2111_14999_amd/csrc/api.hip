@@ -133,7 +133,7 @@ phoebe_status phoebe_gpu_electron_bands(void* handle, const phoebe_system* sys,
     if (!handle) return PHOEBE_E_INVALID;
     Handle* h = static_cast<Handle*>(handle);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    return run(h, [&] {
+    return run(h, __func__, [&] {
         check_system(h, sys, true, false, false);
         REQUIRE(h, nk >= 0, "nk < 0");
         if (nk == 0) return;
@@ -164,7 +164,7 @@ phoebe_status phoebe_gpu_phonon_modes(void* handle, const phoebe_system* sys,
     if (!handle) return PHOEBE_E_INVALID;
     Handle* h = static_cast<Handle*>(handle);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    return run(h, [&] {
+    return run(h, __func__, [&] {
         check_system(h, sys, false, true, false);
         REQUIRE(h, nq >= 0, "nq < 0");
         if (nq == 0) return;
@@ -194,7 +194,7 @@ phoebe_status phoebe_gpu_interp_g(void* handle, const phoebe_system* sys, const 
     if (!handle) return PHOEBE_E_INVALID;
     Handle* h = static_cast<Handle*>(handle);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    return run(h, [&] {
+    return run(h, __func__, [&] {
         check_system(h, sys, true, true, true);
         REQUIRE(h, nk >= 0 && nq >= 0, "negative nk or nq");
         REQUIRE(h, prec >= PHOEBE_FP64 && prec <= PHOEBE_BF16X6, "precision enum out of range");
@@ -337,7 +337,7 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
     if (!handle) return PHOEBE_E_INVALID;
     Handle* h = static_cast<Handle*>(handle);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    return run(h, [&] {
+    return run(h, __func__, [&] {
         check_system(h, sys, true, true, true);
         REQUIRE(h, mesh_in != nullptr, "mesh is NULL");
         REQUIRE(h, mesh_in[0] >= 1 && mesh_in[1] >= 1 && mesh_in[2] >= 1, "mesh must be >= 1");
@@ -683,9 +683,10 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
                     if (tc.bytes < tc_bytes) {
                         if (tc.mem) {
                             HIPCHK(h, hipStreamSynchronize(s));
-                            HIPCHK(h, hipFree(tc.mem));
+                            char* old = tc.mem;  // forgotten before the free is checked
                             tc.mem = nullptr;
                             tc.bytes = 0;
+                            HIPCHK(h, hipFree(old));
                         }
                         if (hipMalloc(&tc.mem, tc_bytes) != hipSuccess) {
                             tc.mem = nullptr;
@@ -1228,6 +1229,12 @@ phoebe_status phoebe_gpu_phonon_linewidth(void* handle, const phoebe_system* sys
     return st;
 }
 
+phoebe_status phoebe_gpu_set_fault_injection(void* handle, int64_t at) {
+    if (!handle || at < 0) return PHOEBE_E_INVALID;
+    static_cast<Handle*>(handle)->inject_at = at;
+    return PHOEBE_OK;
+}
+
 phoebe_status phoebe_gpu_set_table_cache(void* handle, int enable) {
     if (!handle) return PHOEBE_E_INVALID;
     Handle* h = static_cast<Handle*>(handle);
@@ -1254,7 +1261,7 @@ phoebe_status phoebe_gpu_velocities(void* handle, const phoebe_system* sys, cons
     if (!handle) return PHOEBE_E_INVALID;
     Handle* h = static_cast<Handle*>(handle);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    return run(h, [&] {
+    return run(h, __func__, [&] {
         check_system(h, sys, true, false, false);
         REQUIRE(h, nk >= 0, "nk < 0");
         if (nk == 0) return;
@@ -1298,7 +1305,7 @@ phoebe_status phoebe_gpu_polar_factor(void* handle, const phoebe_system* sys, co
     if (!handle) return PHOEBE_E_INVALID;
     Handle* h = static_cast<Handle*>(handle);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    return run(h, [&] {
+    return run(h, __func__, [&] {
         check_system(h, sys, false, true, false);
         REQUIRE(h, sys->polar != nullptr, "the system has no polar data");
         check_polar(h, sys);

@@ -175,7 +175,7 @@ phoebe_status phoebe_gpu_batched_plan(void* handle, const phoebe_system* systems
     Handle* h = static_cast<Handle*>(handle);
     hipStream_t s = static_cast<hipStream_t>(stream);
     Plan* P = nullptr;
-    const phoebe_status st = run(h, [&] {
+    const phoebe_status st = run(h, __func__, [&] {
         REQUIRE(h, plan_out != nullptr, "plan out-pointer is NULL");
         *plan_out = nullptr;
         REQUIRE(h, systems && meshes && params && n_sys >= 1, "systems/meshes/params missing");
@@ -471,11 +471,12 @@ phoebe_status phoebe_gpu_batched_plan(void* handle, const phoebe_system* systems
             set_err(h, "hipMalloc of %zu bytes for the batched plan failed", P->mem_bytes + run_bytes);
             throw Fail{PHOEBE_E_NOMEM};
         }
-        HIPCHK(h, hipStreamSynchronize(s));
-        HIPCHK(h, hipMemcpy(mem2, P->mem, P->mem_bytes, hipMemcpyDeviceToDevice));
-        const ptrdiff_t shift = mem2 - P->mem;
-        HIPCHK(h, hipFree(P->mem));
+        char* old = P->mem;  // the plan owns the new block from here on
         P->mem = mem2;
+        HIPCHK(h, hipStreamSynchronize(s));
+        HIPCHK(h, hipMemcpy(mem2, old, P->mem_bytes, hipMemcpyDeviceToDevice));
+        const ptrdiff_t shift = mem2 - old;
+        HIPCHK(h, hipFree(old));
         auto mv = [&](auto*& ptr) {
             if (ptr) ptr = reinterpret_cast<std::remove_reference_t<decltype(ptr)>>(reinterpret_cast<char*>(ptr) + shift);
         };
@@ -544,7 +545,7 @@ phoebe_status phoebe_gpu_batched_run(void* plan, double* const* gamma_out, void*
     if (!P) return PHOEBE_E_INVALID;
     Handle* h = P->h;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    return run(h, [&] {
+    return run(h, __func__, [&] {
         HIPCHK(h, hipSetDevice(h->device));
         HIPCHK(h, hipGraphLaunch(P->exec, s));
         if (gamma_out) {

@@ -13,7 +13,7 @@ phoebe_status phoebe_gpu_interp_v3(void* handle, const phoebe_system3* sys, cons
     if (!handle) return PHOEBE_E_INVALID;
     Handle* h = static_cast<Handle*>(handle);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    return run(h, [&] {
+    return run(h, __func__, [&] {
         REQUIRE(h, sys != nullptr, "system is NULL");
         REQUIRE(h, sys->n_atoms >= 1, "n_atoms must be >= 1");
         REQUIRE(h, sys->n_rd >= 1 && sys->rd && sys->phi_r && sys->mass, "force constants missing");
@@ -115,7 +115,7 @@ phoebe_status phoebe_gpu_philox_uniform(void* handle, uint64_t seed, uint64_t of
     if (!handle) return PHOEBE_E_INVALID;
     Handle* h = static_cast<Handle*>(handle);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    return run(h, [&] {
+    return run(h, __func__, [&] {
         REQUIRE(h, n >= 0, "n < 0");
         if (n == 0) return;
         REQUIRE(h, out != nullptr, "out is NULL");
@@ -129,7 +129,7 @@ phoebe_status phoebe_gpu_philox_randint(void* handle, uint64_t seed, uint64_t of
     if (!handle) return PHOEBE_E_INVALID;
     Handle* h = static_cast<Handle*>(handle);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    return run(h, [&] {
+    return run(h, __func__, [&] {
         REQUIRE(h, n >= 0, "n < 0");
         REQUIRE(h, hi >= 1 && hi <= 2147483647LL, "hi must be in [1, 2^31 - 1]");
         if (n == 0) return;
@@ -144,7 +144,7 @@ phoebe_status phoebe_gpu_mlp_init(void* handle, phoebe_precision prec, void* par
     if (!handle) return PHOEBE_E_INVALID;
     Handle* h = static_cast<Handle*>(handle);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    return run(h, [&] {
+    return run(h, __func__, [&] {
         REQUIRE(h, prec == PHOEBE_BF16 || prec == PHOEBE_FP64, "precision must be BF16 or FP64");
         REQUIRE(h, n_in >= 1 && width >= 1 && depth >= 0 && depth <= 16 && width <= 4096,
                 "network shape out of range");
@@ -174,7 +174,7 @@ phoebe_status phoebe_gpu_training_set(void* handle, const double* terms, const d
     if (!handle) return PHOEBE_E_INVALID;
     Handle* h = static_cast<Handle*>(handle);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    return run(h, [&] {
+    return run(h, __func__, [&] {
         REQUIRE(h, n_states >= 0 && n_q >= 1 && n_modes >= 1, "shape out of range");
         REQUIRE(h, std::isfinite(d_threshold) && d_threshold >= 0.0, "d_threshold must be >= 0");
         REQUIRE(h, std::isfinite(c_frac) && c_frac >= 0.0, "c_frac must be >= 0");
@@ -233,7 +233,7 @@ phoebe_status phoebe_gpu_gather_rows(void* handle, const void* src, int64_t n_sr
     if (!handle) return PHOEBE_E_INVALID;
     Handle* h = static_cast<Handle*>(handle);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    return run(h, [&] {
+    return run(h, __func__, [&] {
         REQUIRE(h, n >= 0 && n_src >= 0, "negative count");
         REQUIRE(h, row_bytes >= 4 && row_bytes % 4 == 0, "row_bytes must be a positive multiple of 4");
         if (n == 0) return;

@@ -119,7 +119,7 @@ phoebe_status phoebe_gpu_mlp_forward(void* handle, phoebe_precision prec, const 
     if (!handle) return PHOEBE_E_INVALID;
     Handle* h = static_cast<Handle*>(handle);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    return run(h, [&] {
+    return run(h, __func__, [&] {
         check_net(h, n_in, width, depth);
         REQUIRE(h, prec == PHOEBE_FP64 || prec == PHOEBE_BF16, "MLP precision must be FP64 or BF16");
         REQUIRE(h, batch >= 0, "batch < 0");
@@ -158,7 +158,7 @@ phoebe_status phoebe_gpu_mlp_grad(void* handle, phoebe_precision prec, const voi
     if (!handle) return PHOEBE_E_INVALID;
     Handle* h = static_cast<Handle*>(handle);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    return run(h, [&] {
+    return run(h, __func__, [&] {
         check_net(h, n_in, width, depth);
         REQUIRE(h, prec == PHOEBE_FP64 || prec == PHOEBE_BF16, "MLP precision must be FP64 or BF16");
         REQUIRE(h, batch >= 1, "batch < 1");
@@ -181,7 +181,7 @@ phoebe_status phoebe_gpu_mlp_adam(void* handle, float* params, const float* grad
     if (!handle) return PHOEBE_E_INVALID;
     Handle* h = static_cast<Handle*>(handle);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    return run(h, [&] {
+    return run(h, __func__, [&] {
         REQUIRE(h, params && grad && m && v && n >= 0 && step >= 1, "bad Adam arguments");
         REQUIRE(h, beta1 >= 0 && beta1 < 1 && beta2 >= 0 && beta2 < 1 && eps >= 0 && lr >= 0,
                 "Adam hyper-parameters out of range");
@@ -203,7 +203,7 @@ phoebe_status phoebe_gpu_mlp_features(void* handle, phoebe_precision prec, const
     if (!handle) return PHOEBE_E_INVALID;
     Handle* h = static_cast<Handle*>(handle);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    return run(h, [&] {
+    return run(h, __func__, [&] {
         REQUIRE(h, mesh && mesh[0] >= 1 && mesh[1] >= 1 && mesh[2] >= 1, "bad mesh");
         REQUIRE(h, n_modes >= 1 && escale > 0.0, "n_modes >= 1 and escale > 0 required");
         REQUIRE(h, n_harm >= 0 && n_harm <= 16, "n_harm must be in [0, 16]");
@@ -230,7 +230,7 @@ phoebe_status phoebe_gpu_propose_q(void* handle, const int32_t mesh[3], int32_t 
     if (!handle) return PHOEBE_E_INVALID;
     Handle* h = static_cast<Handle*>(handle);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    return run(h, [&] {
+    return run(h, __func__, [&] {
         REQUIRE(h, mesh && mesh[0] >= 1 && mesh[1] >= 1 && mesh[2] >= 1, "bad mesh");
         REQUIRE(h, n_modes >= 1 && escale > 0.0 && S >= 1, "n_modes >= 1, escale > 0, S >= 1");
         REQUIRE(h, mix > 0.0 && mix <= 1.0, "mix must be in (0, 1]: the uniform share keeps the "

@@ -11,6 +11,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "ext.hpp"
 #include "kernels.hpp"
 #include "lowp.hpp"
@@ -66,6 +68,7 @@ struct Handle {
     char* scratch = nullptr;   // the device's static scratch of the non-allocating entry point
     bool fixed_ws = false;     // during such a call: ws is that scratch and is never reallocated
     bool table_cache = false;  // reuse band and phonon tables across rate calls
+    int64_t inject_at = 0;     // testing: report the n-th successful HIP check as failed
     TableCache tc;
     std::vector<TimedLaunch> pending;
     std::vector<KernelStat> stats;
@@ -111,11 +114,21 @@ inline void set_err(Handle* h, const char* fmt, ...) {
         }                                        \
     } while (0)
 
+// A failed HIP call ends the entry point with PHOEBE_E_DEVICE.  With fault
+// injection armed (phoebe_gpu_set_fault_injection) the n-th successful check is
+// reported as failed instead, after the device has finished the work in flight.
 #define HIPCHK(h, expr)                                                                   \
     do {                                                                                  \
         hipError_t e_ = (expr);                                                           \
+        bool inj_ = false;                                                                \
+        if (e_ == hipSuccess && (h)->inject_at > 0 && --(h)->inject_at == 0) {            \
+            (void)hipDeviceSynchronize();                                                 \
+            e_ = hipErrorUnknown;                                                         \
+            inj_ = true;                                                                  \
+        }                                                                                 \
         if (e_ != hipSuccess) {                                                           \
-            set_err((h), "HIP error %s at %s:%d", hipGetErrorString(e_), __FILE__, __LINE__); \
+            set_err((h), "HIP error %s at %s:%d%s", hipGetErrorString(e_), __FILE__, __LINE__, \
+                    inj_ ? " (injected)" : "");                                           \
             throw Fail{PHOEBE_E_DEVICE};                                                  \
         }                                                                                 \
     } while (0)
@@ -133,9 +146,10 @@ inline void ensure_ws(Handle* h, size_t bytes) {
     }
     if (h->ws) {
         HIPCHK(h, hipDeviceSynchronize());
-        HIPCHK(h, hipFree(h->ws));
+        char* old = h->ws;  // forgotten before the free is checked: never reused
         h->ws = nullptr;
         h->ws_cap = 0;
+        HIPCHK(h, hipFree(old));
     }
     hipError_t e = hipMalloc(&h->ws, bytes);
     if (e != hipSuccess) {
@@ -321,7 +335,12 @@ inline void scan_finite(Handle* h, const phoebe_system* sys, bool hh, bool ph, b
         set_err(h, "no flag word for the finiteness scan");
         throw Fail{PHOEBE_E_DEVICE};
     }
-    if (!h->dflag) HIPCHK(h, hipMalloc(reinterpret_cast<void**>(&h->dflag), sizeof(int32_t)));
+    if (!h->dflag) {
+        int32_t* p = nullptr;
+        const hipError_t e = hipMalloc(reinterpret_cast<void**>(&p), sizeof(int32_t));
+        if (e == hipSuccess) h->dflag = p;  // kept (and freed with the handle) once allocated
+        HIPCHK(h, e);
+    }
     int32_t* flag = h->dflag;
     int32_t bad = 0;
     {
@@ -344,7 +363,14 @@ inline void scan_finite(Handle* h, const phoebe_system* sys, bool hh, bool ph, b
     }
 }
 
-inline phoebe_status run(Handle* h, const std::function<void()>& body) {
+// Marks the entry point as a named range for tracing tools (rocprofv3 --marker-trace).
+struct TraceRange {
+    explicit TraceRange(const char* name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+};
+
+inline phoebe_status run(Handle* h, const char* name, const std::function<void()>& body) {
+    TraceRange range(name);
     try {
         h->err.clear();
         body();

@@ -317,3 +317,37 @@ def test_table_cache_bitwise_and_keyed():
     o = rates.scattering_rates(s, mesh, tables=t, **par)
     assert np.max(np.abs(ref - o["gamma"])) < 1e-9 * np.max(o["gamma"])
     lib.close()
+
+
+def test_injected_device_error_and_recovery():
+    """A HIP failure inside the rate call (forced from the host: the n-th checked HIP
+    call is reported as failed) returns PHOEBE_E_DEVICE with its message; the handle
+    then runs the same call to the oracle's result."""
+    torch = torch_cuda()
+    from paper_2111_14999_amd import DeviceSystem, Library, PhoebeError
+    lib = Library(0)
+    s = synth.config_c1()
+    p = workload_params()["toy"]
+    mesh = tuple(p["mesh"])
+    par = dict(mu=p["mu"], kT=p["kT"], sigma=p["sigma"], win_lo=p["win_lo"], win_hi=p["win_hi"],
+               omega_min=p["omega_min"])
+    ds = DeviceSystem.from_host(s)
+    N = int(np.prod(mesh))
+    ref = rates.scattering_rates(s, mesh, **par)
+    for at in (1, 3, 10, 40):
+        g = torch.zeros((N, s.n_wannier), dtype=torch.float64, device="cuda")
+        lib.set_fault_injection(at)
+        with pytest.raises(PhoebeError) as e:
+            lib.scatter_rates(ds, mesh, par, g)
+        assert e.value.status == -3
+        assert "(injected)" in str(e.value)
+        torch.cuda.synchronize()
+        n = lib.scatter_rates(ds, mesh, par, g)   # disarmed after firing once
+        torch.cuda.synchronize()
+        got = g.cpu().numpy()[:n]
+        assert np.max(np.abs(got - ref["gamma"])) < 1e-9 * np.max(ref["gamma"])
+    lib.set_fault_injection(10 ** 9)   # armed beyond the call's checks: no effect
+    g = torch.zeros((N, s.n_wannier), dtype=torch.float64, device="cuda")
+    lib.scatter_rates(ds, mesh, par, g)
+    lib.set_fault_injection(0)
+    lib.close()
