@@ -299,7 +299,12 @@ size_t phoebe_gpu_noalloc_scratch_bytes(void);
  * hipGraph: stage 1 and the U_k fold of every system, then one persistent
  * kernel that drains a work queue of (system, state, q tile) tasks, then the
  * per-system reductions.  Only PHOEBE_FP32 contractions (complex64) are
- * offered; tables, eigensolves, occupations and rate sums are FP64.
+ * offered; tables, eigensolves, occupations and rate sums are FP64.  Unless
+ * the handle's mesh-sum mode is PHOEBE_MESH_SUM_DIRECT, every system of at most
+ * 16 Wannier functions (its full q mesh is what the plan sums) is taken out of
+ * the graph and run by phoebe_gpu_batched_run as one plain rate call (FP32, the
+ * factorised mesh sums, the handle's workspace) after the graph; such systems
+ * report tq = tn = 0 in phoebe_gpu_batched_info.
  *   systems   host [n_sys] (their tensors are device pointers, used until the
  *             plan is destroyed)
  *   meshes    host [n_sys, 3];  params host [n_sys]

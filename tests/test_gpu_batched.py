@@ -49,11 +49,25 @@ def setup():
     lib.close()
 
 
-def test_graph_replays_match_oracle(setup, tmp_path):
+@pytest.mark.parametrize("mode", ["direct", "auto"])
+def test_graph_replays_match_oracle(setup, tmp_path, mode):
+    """mode "direct": every system in the graph's persistent kernel; "auto": systems of
+    at most 16 bands run as plain calls (factorised sums) after the graph."""
     torch = torch_cuda()
     lib, systems, dsys, meshes, pars, refs = setup
     cache = str(tmp_path / "tiles.json")
+    lib.set_mesh_sum(mode)
+    try:
+        _replays(lib, systems, dsys, meshes, pars, refs, cache, mode)
+    finally:
+        lib.set_mesh_sum("auto")
+
+
+def _replays(lib, systems, dsys, meshes, pars, refs, cache, mode):
+    torch = torch_cuda()
     plan = lib.batched_plan(dsys, meshes, pars, precision="fp32", tune_cache=cache)
+    routed = [plan.info(i)["tq"] == 0 for i in range(len(systems))]
+    assert routed == [mode == "auto" and s.n_wannier <= 16 for s in systems]
     assert plan.n_kept == [len(r["k_idx"]) for r in refs]
     outs = [torch.full((max(n, 1), s.n_wannier), -1.0, dtype=torch.float64, device="cuda")
             for n, s in zip(plan.n_kept, systems)]
@@ -83,7 +97,7 @@ def test_graph_replays_match_oracle(setup, tmp_path):
     tiles = [(plan.info(i)["tq"], plan.info(i)["tn"]) for i in range(len(systems))]
     plan.close()
     doc = json.load(open(cache))
-    assert len(doc["entries"]) == len(systems)
+    assert len(doc["entries"]) == len(systems) - sum(routed)
     plan2 = lib.batched_plan(dsys, meshes, pars, precision="fp32", tune_cache=cache)
     assert [(plan2.info(i)["tq"], plan2.info(i)["tn"]) for i in range(len(systems))] == tiles
     plan2.close()
