@@ -75,6 +75,9 @@ def main():
                     choices=["realistic", "toy", "batched", "learned", "linewidth", "adaptive",
                              "polar", "v3"])
     ap.add_argument("--tune-cache", default=None, help="JSON tile cache of the batched form")
+    ap.add_argument("--plan-only", action="store_true",
+                    help="batched form: time the plan's replays only (no plain or all-graph "
+                         "comparison runs), e.g. under a kernel trace")
     ap.add_argument("--cpu-sample", type=int, default=6, help="kept k points timed on the oracle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--interp-k", type=int, default=2, help="k points of the interp_g rate run")
@@ -535,6 +538,12 @@ def bench_batched(args):
         flops += 8.0 * inf["states"] * p["mesh"] ** 3 * s.rp.shape[0] * s.n_modes * s.n_wannier
     log(f"graph replay {dt * 1e3:.1f} ms: {n_kept / dt:.1f} kept k/s, "
         f"{flops / dt / 1e12:.1f} TFLOP/s (stage-2 algorithmic, whole graph)")
+    if args.plan_only:
+        print(json.dumps({"workload": "batched plan replays only", "ms_per_replay": round(dt * 1e3, 3),
+                          "kept_k": n_kept}), flush=True)
+        plan.close()
+        lib.close()
+        return
     # the plain form on the same systems, one phoebe_gpu_scatter_rates call each (FP32
     # contractions, the library's choice of mesh sum), and its agreement with the graph
     plain_outs = [torch.zeros_like(o) for o in outs]
@@ -555,6 +564,13 @@ def bench_batched(args):
             dmax = max(dmax, float(np.max(np.abs(a[sel] - b[sel]) / b[sel])))
     log(f"plain form, 32 calls: {dt_plain * 1e3:.1f} ms ({n_kept / dt_plain:.1f} kept k/s); "
         f"plan vs plain max rel diff {dmax:.2e}")
+    for i, (p, s, inf) in enumerate(zip(plist, systems, info)):
+        t1 = time.perf_counter()
+        lib.scatter_rates(dsys[i], meshes[i], pars[i], plain_outs[i], precision="fp32")
+        torch.cuda.synchronize()
+        log(f"  system {i}: nW {s.n_wannier} nModes {s.n_modes} |Rp| {s.rp.shape[0]} mesh "
+            f"{p['mesh']}^3 states {inf['states']} tile ({inf['tq']},{inf['tn']}) plain call "
+            f"{(time.perf_counter() - t1) * 1e3:.2f} ms")
     # every system in the graph's persistent kernel (the direct contraction), for reference
     lib.set_mesh_sum("direct")
     plan_d = lib.batched_plan(dsys, meshes, pars, precision="fp32", tune_cache=cache)
@@ -607,7 +623,8 @@ def bench_batched(args):
             "workload": (f"batched: {len(plist)} systems, nW 4..24, nModes 6..30, |R| 125..729, "
                          f"meshes 16^3..32^3, +-0.3 eV windows; one plan: systems of at most 16 "
                          f"bands as plain calls (factorised sums), the others in one captured "
-                         f"graph with the persistent multi-system kernel (complex64 contractions)"),
+                         f"graph with persistent multi-system kernels, one per tile shape "
+                         f"(complex64 contractions)"),
             "kept_k": n_kept, "plan_s": round(t_plan, 2), "tiles": tiles,
         },
         "stage2_tflops_whole_graph": round(flops / dt / 1e12, 3),

@@ -229,7 +229,8 @@ phoebe_status phoebe_gpu_interp_g(void *handle, const phoebe_system *sys,
  * same bit for bit.
  * Errors: PHOEBE_E_INVALID (mesh < 1, sigma <= 0, kT <= 0, enum, pointers),
  * PHOEBE_E_NOMEM, PHOEBE_E_UNSUPPORTED (nW > 32, nModes > 32, q_mesh != k_mesh,
- * polar or adaptive smearing with another precision than FP64),
+ * polar or adaptive smearing with another precision than FP64, split-BF16 with
+ * nModes*nW > 512),
  * PHOEBE_E_NUMERIC (finiteness checks on, see phoebe_gpu_set_check_finite),
  * PHOEBE_E_DEVICE. */
 phoebe_status phoebe_gpu_scatter_rates(void *handle, const phoebe_system *sys,

@@ -429,6 +429,10 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
         const int n_re = sys->n_re, n_rp = sys->n_rp;
         // K padding of the stage-2 operand: 4 (K of the f64/f32 MFMA) or 32 (bf16)
         const bool bf16 = prec == PHOEBE_BF16X3 || prec == PHOEBE_BF16X6;
+        if (bf16 && tn > 8) {
+            set_err(h, "split-BF16 contractions take nModes*nW <= 512 (here %d)", nm * nW);
+            throw Fail{PHOEBE_E_UNSUPPORTED};
+        }
         const int rp_pad = bf16 ? (n_rp + 31) & ~31 : (n_rp + 3) & ~3;
         const int64_t NC2 = (int64_t)n_rp * nm * nW * nW;
         // bytes of one stage-1 element and of one stage-2 operand element
@@ -646,7 +650,14 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
             // the host vector must outlive the copy
             HIPCHK(h, hipStreamSynchronize(s));
         }
-        {
+        if (h->preset) {
+            // tables lent by a batched plan for this call (built there with the same routines)
+            T.eps = h->preset->eps;
+            T.U = h->preset->U;
+            T.omega = h->preset->omega;
+            T.E = h->preset->E;
+            T.nb = h->preset->nb;
+        } else {
             // band and phonon tables: from the table cache when it holds this system's
             // tables on this mesh (same inputs, omega_min and kT), else built here
             const size_t b_eps = sizeof(double) * N * nW, b_U = sizeof(cd) * N * nW * nW,

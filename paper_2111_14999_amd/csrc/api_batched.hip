@@ -1,6 +1,7 @@
 // C ABI of the batched form: many independent systems, band tables and windows
 // built once per plan, then one captured hipGraph whose core is the persistent
-// multi-system rate kernel (FP32 contractions, FP64 tables and rates).  Tile
+// multi-system rate kernel (FP32 contractions, FP64 tables and rates), one
+// launch per tile shape in use, each draining the queue of its shape's tasks.  Tile
 // shapes per system come from an autotuner that times the candidates and can
 // keep its choices in a small JSON cache file.
 #include <chrono>
@@ -60,8 +61,11 @@ struct Plan {
     int* d_head = nullptr;
     cf* G = nullptr;
     int n_tasks = 0;
-    int n_wg = 256;
-    size_t lds = 0;
+    // tasks, dynamic LDS and work-groups of each shape's persistent kernel; the
+    // task list holds the shapes' queues one after the other
+    int n_tasks_shape[kBatchedShapes] = {};
+    size_t lds_shape[kBatchedShapes] = {};
+    int n_wg_shape[kBatchedShapes] = {};
     hipStream_t cs = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -116,32 +120,50 @@ void save_cache(const char* path, const std::map<std::string, std::pair<int, int
     f << "]}\n";
 }
 
+// smallest TN whose 64*TN columns hold the system's nModes*nW in one pass
+int tn_for(int nc) {
+    static const int tns[] = {1, 2, 3, 4, 6, 8, 12, 16};
+    for (int tn : tns)
+        if (64 * tn >= nc) return tn;
+    return 0;
+}
+
 void fill_desc(const SysPlan& p, SysDesc& d) {
-    d.F = p.F;
-    d.rp_pad = p.rp_pad;
-    d.nc_pad = p.nc_pad;
-    d.n_rp = p.n_rp;
-    d.rmax = p.rmax;
-    d.nW = p.nW;
-    d.nm = p.nm;
+    RateArgsLP& a = d.a;
+    a = RateArgsLP{};
+    a.F = p.F;
+    a.rp_pad = p.rp_pad;
+    a.nc_pad = p.nc_pad;
+    a.n_rp = p.n_rp;
+    a.rp_packed = p.rp_packed;
+    a.rmax = p.rmax;
+    a.mesh = p.mesh;
+    a.nq_mesh = p.N;
+    a.st_kmesh = p.st_kmesh;
+    a.st_band = p.st_band;
+    a.st_row = p.st_row;
+    a.st_mlo = p.st_mlo;
+    a.st_mhi = p.st_mhi;
+    a.eps = p.eps;
+    a.focc = p.focc;
+    a.U = p.U;
+    a.omega = p.omega;
+    a.nb = p.nb;
+    a.E = p.E;
+    a.nW = p.nW;
+    a.nm = p.nm;
+    a.sigma = p.sigma;
+    a.partial = p.partial;
+    a.n_qtiles = p.n_qtiles;
     d.tq = p.tq;
     d.tn = p.tn;
-    d.rp_packed = p.rp_packed;
-    d.mesh = p.mesh;
-    d.nq = p.N;
-    d.st_kmesh = p.st_kmesh;
-    d.st_band = p.st_band;
-    d.st_mlo = p.st_mlo;
-    d.st_mhi = p.st_mhi;
-    d.eps = p.eps;
-    d.focc = p.focc;
-    d.omega = p.omega;
-    d.nb = p.nb;
-    d.U = p.U;
-    d.E = p.E;
-    d.sigma = p.sigma;
-    d.partial = p.partial;
-    d.n_qtiles = p.n_qtiles;
+}
+
+// work-groups of a persistent launch: as many per CU as the LDS of its largest
+// tile allows, at most 8 (those beyond what the registers allow start when
+// others end; a queue task never waits on another)
+int persistent_wgs(size_t lds) {
+    return 256 * std::max(1, std::min(8, (int)((160 * 1024) / std::max<size_t>(lds, 1))));
 }
 
 // stage 1 + fold of states [s0, s1) of one system into F (rows of those states)
@@ -364,12 +386,9 @@ phoebe_status phoebe_gpu_batched_plan(void* handle, const phoebe_system* systems
         const auto t_tune0 = std::chrono::steady_clock::now();
         auto cache = load_cache(tune_cache);
         std::map<std::string, double> cache_us;
-        static const int cands[][2] = {{2, 1}, {2, 2}, {2, 4}, {1, 1}, {1, 2}, {1, 4}};
-        int max_tune_states = 0;
-        for (auto& p : P->sp) max_tune_states = std::max(max_tune_states, std::min(p.states, 4));
         size_t tune_f = 0;
         for (auto& p : P->sp)
-            tune_f = std::max(tune_f, (size_t)4 * p.rp_pad * nc_pad_for(p.nm * p.nW, 4));
+            tune_f = std::max(tune_f, (size_t)4 * p.rp_pad * 64 * std::max(1, tn_for(p.nm * p.nW)));
         {
             // workspace: G, F of the tuning states, partials, one descriptor, tasks, head
             const size_t need = (size_t)g_max * sizeof(cf) + tune_f * sizeof(cf) + 1024 * 1024 * 8;
@@ -379,7 +398,8 @@ phoebe_status phoebe_gpu_batched_plan(void* handle, const phoebe_system* systems
             if (!in_graph(p)) continue;
             const std::string key = tune_key(p);
             auto it = cache.find(key);
-            if (it != cache.end() && batched_tile_supported(it->second.first, it->second.second) &&
+            if (it != cache.end() &&
+                batched_tile_supported(it->second.first, it->second.second, p.nm * p.nW) &&
                 batched_lds(it->second.first, p.rmax, p.rp_pad, nc_pad_for(p.nm * p.nW, it->second.second), p.nm) <= 150 * 1024) {
                 p.tq = it->second.first;
                 p.tn = it->second.second;
@@ -388,8 +408,12 @@ phoebe_status phoebe_gpu_batched_plan(void* handle, const phoebe_system* systems
             const int ns = std::min(p.states, 4);
             double best = 1e300;
             int btq = 0, btn = 0;
+            // the one-pass TN at both q-tile heights
+            const int tn1 = tn_for(p.nm * p.nW);
+            const int cands[2][2] = {{2, tn1}, {1, tn1}};
             for (auto& c : cands) {
                 const int tq = c[0], tn = c[1];
+                if (!batched_tile_supported(tq, tn, p.nm * p.nW)) continue;
                 const int ncp = nc_pad_for(p.nm * p.nW, tn);
                 const size_t lds = batched_lds(tq, p.rmax, p.rp_pad, ncp, p.nm);
                 if (lds > 150 * 1024) continue;
@@ -417,7 +441,6 @@ phoebe_status phoebe_gpu_batched_plan(void* handle, const phoebe_system* systems
                     for (int t = 0; t < nqt; ++t) tv.push_back(BTask{0, a, t, 0});
                 HIPCHK(h, hipMemcpyAsync(dd, &d, sizeof d, hipMemcpyHostToDevice, s));
                 HIPCHK(h, hipMemcpyAsync(tk, tv.data(), sizeof(BTask) * tv.size(), hipMemcpyHostToDevice, s));
-                const int per_cu = std::max(1, std::min(2, (int)(160 * 1024 / std::max<size_t>(lds, 1))));
                 double t_best = 1e300;
                 for (int rep = 0; rep < 2; ++rep) {
                     hipEvent_t e0, e1;
@@ -425,7 +448,8 @@ phoebe_status phoebe_gpu_batched_plan(void* handle, const phoebe_system* systems
                     HIPCHK(h, hipEventCreate(&e1));
                     HIPCHK(h, launch_zero(head, 8, s));
                     HIPCHK(h, hipEventRecord(e0, s));
-                    HIPCHK(h, launch_batched_rates(dd, tk, (int)tv.size(), head, 256 * per_cu, lds, s));
+                    HIPCHK(h, launch_batched_rates(batched_shape(tq, tn), dd, tk, (int)tv.size(),
+                                                   head, persistent_wgs(lds), lds, s));
                     HIPCHK(h, hipEventRecord(e1, s));
                     HIPCHK(h, hipEventSynchronize(e1));
                     float ms = 0.f;
@@ -456,7 +480,6 @@ phoebe_status phoebe_gpu_batched_plan(void* handle, const phoebe_system* systems
         P->tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_tune0).count();
 
         // ---- plan memory, part 2: F, partials, descriptors, tasks ----
-        size_t lds = 0;
         std::vector<BTask> tasks;
         std::vector<int> order;
         for (int i = 0; i < n_sys; ++i)
@@ -474,15 +497,18 @@ phoebe_status phoebe_gpu_batched_plan(void* handle, const phoebe_system* systems
             p.n_qtiles = (int)((p.N + 16 * p.tq - 1) / (16 * p.tq));
             f_total += (size_t)p.states * p.rp_pad * p.nc_pad;
             part_total += (size_t)p.states * p.n_qtiles;
-            lds = std::max(lds, batched_lds(p.tq, p.rmax, p.rp_pad, p.nc_pad, p.nm));
+            const int sh = batched_shape(p.tq, p.tn);
+            P->lds_shape[sh] = std::max(P->lds_shape[sh], batched_lds(p.tq, p.rmax, p.rp_pad, p.nc_pad, p.nm));
         }
-        for (int i : order) {
-            const SysPlan& p = P->sp[i];
-            for (int a = 0; a < p.states; ++a)
-                for (int t = 0; t < p.n_qtiles; ++t) tasks.push_back(BTask{i, a, t, 0});
-        }
+        for (int sh = 0; sh < kBatchedShapes; ++sh)
+            for (int i : order) {
+                const SysPlan& p = P->sp[i];
+                if (batched_shape(p.tq, p.tn) != sh) continue;
+                for (int a = 0; a < p.states; ++a)
+                    for (int t = 0; t < p.n_qtiles; ++t) tasks.push_back(BTask{i, a, t, 0});
+                P->n_tasks_shape[sh] += p.states * p.n_qtiles;
+            }
         P->n_tasks = (int)tasks.size();
-        P->lds = lds;
         const size_t run_bytes = f_total * sizeof(cf) + part_total * sizeof(double) +
                                  (size_t)n_sys * sizeof(SysDesc) + tasks.size() * sizeof(BTask) +
                                  (size_t)g_max * sizeof(cf) + 16 * 256;
@@ -521,7 +547,7 @@ phoebe_status phoebe_gpu_batched_plan(void* handle, const phoebe_system* systems
         }
         P->d_desc = rar.take<SysDesc>(n_sys);
         P->d_tasks = rar.take<BTask>(tasks.size());
-        P->d_head = rar.take<int>(4);
+        P->d_head = rar.take<int>(kBatchedShapes);
         P->G = rar.take<cf>(g_max);
         std::vector<SysDesc> desc(n_sys);
         for (int i = 0; i < n_sys; ++i) fill_desc(P->sp[i], desc[i]);
@@ -529,9 +555,12 @@ phoebe_status phoebe_gpu_batched_plan(void* handle, const phoebe_system* systems
         if (!tasks.empty())
             HIPCHK(h, hipMemcpy(P->d_tasks, tasks.data(), sizeof(BTask) * tasks.size(),
                                 hipMemcpyHostToDevice));
-        const int per_cu = std::max(1, std::min(2, (int)(160 * 1024 / std::max<size_t>(lds, 1))));
-        P->n_wg = 256 * per_cu;
-        HIPCHK(h, prepare_batched_rates(P->lds));  // kernel attribute set outside the capture
+        for (int sh = 0; sh < kBatchedShapes; ++sh) {
+            if (!P->n_tasks_shape[sh]) continue;
+            P->n_wg_shape[sh] = persistent_wgs(P->lds_shape[sh]);
+            // kernel attribute set outside the capture
+            HIPCHK(h, prepare_batched_rates(sh, P->lds_shape[sh]));
+        }
 
         // ---- capture: stage 1 + folds, persistent rate kernel, reductions ----
         HIPCHK(h, hipStreamCreate(&P->cs));
@@ -540,9 +569,12 @@ phoebe_status phoebe_gpu_batched_plan(void* handle, const phoebe_system* systems
             if (!in_graph(p)) continue;
             enqueue_stage1(h, p, P->G, 0, p.states, p.F, p.nc_pad, P->cs);
         }
-        HIPCHK(h, launch_zero(P->d_head, 16, P->cs));
-        HIPCHK(h, launch_batched_rates(P->d_desc, P->d_tasks, P->n_tasks, P->d_head, P->n_wg, P->lds,
-                                       P->cs));
+        HIPCHK(h, launch_zero(P->d_head, sizeof(int) * kBatchedShapes, P->cs));
+        for (int sh = 0, t0 = 0; sh < kBatchedShapes; t0 += P->n_tasks_shape[sh++])
+            if (P->n_tasks_shape[sh])
+                HIPCHK(h, launch_batched_rates(sh, P->d_desc, P->d_tasks + t0, P->n_tasks_shape[sh],
+                                               P->d_head + sh, P->n_wg_shape[sh],
+                                               P->lds_shape[sh], P->cs));
         for (auto& p : P->sp) {
             if (!in_graph(p)) continue;
             const double scale = 2.0 * kPi / (std::sqrt(kPi) * p.sigma) / (double)p.N;
@@ -576,13 +608,17 @@ phoebe_status phoebe_gpu_batched_run(void* plan, double* const* gamma_out, void*
         for (int i = 0; i < P->n_sys; ++i) {
             SysPlan& p = P->sp[i];
             if (!p.plain || p.rows == 0) continue;
-            // the plain rate call (its factorised mesh sums) straight into the caller's rows
+            // the plain rate call (its factorised mesh sums) straight into the caller's rows,
+            // on the band and phonon tables the plan built
             double* dst = gamma_out && gamma_out[i] ? gamma_out[i] : p.gamma;
             const int32_t m[3] = {p.mesh.n0, p.mesh.n1, p.mesh.n2};
             int64_t nk = 0;
+            const PresetTables pt{p.eps, p.U, p.omega, p.E, p.nb};
+            h->preset = &pt;
             const phoebe_status st2 =
                 phoebe_gpu_scatter_rates(h, p.sys, m, m, nullptr, 0, nullptr, nullptr, nullptr,
                                          &p.par, PHOEBE_FP32, dst, nullptr, nullptr, &nk, s);
+            h->preset = nullptr;
             if (st2 != PHOEBE_OK) throw Fail{st2};
             REQUIRE(h, nk == p.rows, "system %d: %lld kept k, the plan found %lld", i,
                     (long long)nk, (long long)p.rows);

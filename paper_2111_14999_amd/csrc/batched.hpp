@@ -5,39 +5,28 @@
 
 namespace phx {
 
-constexpr int kMBB = 8;  // final bands per rotation pass
-
-// Everything one system's tasks read (device pointers).
+// One system of the batched form: the arguments of its rate tiles (device
+// pointers: F [states][rp_pad][nc_pad], tables, state lists, partials) and the
+// tile shape (TQ, TN) the autotuner chose for it.
 struct SysDesc {
-    const cf* F;               // [states][rp_pad][nc_pad]
-    int rp_pad, nc_pad, n_rp, rmax;
-    int nW, nm, tq, tn;
-    const int32_t* rp_packed;  // [n_rp]
-    Mesh mesh;
-    int64_t nq;
-    const int32_t* st_kmesh;
-    const int32_t* st_band;
-    const int32_t* st_mlo;
-    const int32_t* st_mhi;
-    const double* eps;
-    const double* focc;
-    const double* omega;
-    const double* nb;
-    const cd* U;  // transposed: U[k, band, orbital]
-    const cd* E;
-    double sigma;
-    double* partial;           // [states][n_qtiles]
-    int n_qtiles;
+    RateArgsLP a;
+    int tq, tn;
 };
 
 struct BTask {
     int sys, state, qtile, pad;
 };
 
-bool batched_tile_supported(int tq, int tn);
+// The tile shapes (TQ, TN) of the persistent kernels, one kernel per shape;
+// shape index of (tq, tn), or -1.  nc = nModes*nW stage-2 columns fit one
+// column pass when 64*TN >= nc.
+constexpr int kBatchedShapes = 12;
+int batched_shape(int tq, int tn);
+bool batched_tile_supported(int tq, int tn, int nc);
 size_t batched_lds(int tq, int rmax, int rp_pad, int nc_pad, int nm);
-hipError_t prepare_batched_rates(size_t lds);
-hipError_t launch_batched_rates(const SysDesc* sys, const BTask* tasks, int n_tasks, int* head,
-                                int n_wg, size_t lds, hipStream_t s);
+// sets the kernel's dynamic LDS limit (outside a stream capture)
+hipError_t prepare_batched_rates(int shape, size_t lds);
+hipError_t launch_batched_rates(int shape, const SysDesc* sys, const BTask* tasks, int n_tasks,
+                                int* head, int n_wg, size_t lds, hipStream_t s);
 
 }  // namespace phx

@@ -55,6 +55,17 @@ struct TableCache {
     size_t bytes = 0;
 };
 
+// Band and phonon tables of the system of the current rate call, built by a
+// batched plan (same routines, same omega_min and kT) and lent to the plain calls
+// it makes on replay; the rate path reads them in place of building its own.
+struct PresetTables {
+    double* eps;    // [N, nW]
+    cd* U;          // [N, band, orbital] (transposed eigenvectors)
+    double* omega;  // [N, nModes]
+    cd* E;          // [N, nModes, nModes]
+    double* nb;     // [N, nModes]
+};
+
 struct Handle {
     int device = 0;
     size_t budget = 0;
@@ -70,6 +81,7 @@ struct Handle {
     bool table_cache = false;  // reuse band and phonon tables across rate calls
     int64_t inject_at = 0;     // testing: report the n-th successful HIP check as failed
     TableCache tc;
+    const PresetTables* preset = nullptr;  // set only for the duration of a plan's plain call
     std::vector<TimedLaunch> pending;
     std::vector<KernelStat> stats;
 };
