@@ -65,6 +65,23 @@ __device__ inline cd expi2pi(double t) {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
+typedef float f2 __attribute__((ext_vector_type(2)));
+
+// One complex element of an LDS (or global) array whose elements sit at their
+// natural vector alignment (16 bytes for cd, 8 for cf): one 128-bit (64-bit)
+// access per lane instead of two halves.  The structs themselves only promise
+// the alignment of their scalar members.
+__device__ inline cd ld_vec(const cd* p) {
+    const d2 v = *reinterpret_cast<const d2*>(p);
+    return cd{v.x, v.y};
+}
+__device__ inline cf ld_vec(const cf* p) {
+    const f2 v = *reinterpret_cast<const f2*>(p);
+    return cf{v.x, v.y};
+}
+__device__ inline void st_vec(cd* p, cd v) { *reinterpret_cast<d2*>(p) = d2{v.x, v.y}; }
+__device__ inline void st_vec(cf* p, cf v) { *reinterpret_cast<f2*>(p) = f2{v.x, v.y}; }
 
 // Mesh helpers: linear index (i0 N1 + i1) N2 + i2
 struct Mesh {

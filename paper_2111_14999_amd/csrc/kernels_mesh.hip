@@ -169,7 +169,7 @@ __global__ __launch_bounds__(64 * kAxisWaves, 6) void axis_fused_kernel(const C*
     const C* Fs = F + (int64_t)st * rp_pad * nc_pad + c;
     for (int i = g; i < W * W; i += kAxisWaves) {
         const int row = box_rp[r0 * W * W + i];
-        sF[i * 64 + cc] = row >= 0 ? Fs[(int64_t)row * nc_pad] : C{0, 0};
+        st_vec(sF + i * 64 + cc, row >= 0 ? ld_vec(Fs + (int64_t)row * nc_pad) : C{0, 0});
     }
     __syncthreads();
     const int N1 = m.n1, N2 = m.n2, NL = N1 * N2;
@@ -184,7 +184,8 @@ __global__ __launch_bounds__(64 * kAxisWaves, 6) void axis_fused_kernel(const C*
         for (int r1 = 0; r1 < W; ++r1) {
             C acc = {0, 0};
 #pragma unroll
-            for (int r2 = 0; r2 < W; ++r2) acc = cfma(to_c<C>(Pq[r2]), sF[(r1 * W + r2) * 64 + cc], acc);
+            for (int r2 = 0; r2 < W; ++r2)
+                acc = cfma(to_c<C>(Pq[r2]), ld_vec(sF + (r1 * W + r2) * 64 + cc), acc);
             t1[r1] = acc;
         }
         for (int q1 = 0; q1 < N1; ++q1) {
@@ -194,7 +195,7 @@ __global__ __launch_bounds__(64 * kAxisWaves, 6) void axis_fused_kernel(const C*
             C acc = {0, 0};
 #pragma unroll
             for (int r1 = 0; r1 < W; ++r1) acc = cfma(to_c<C>(Pn[r1]), t1[r1], acc);
-            out[(int64_t)line * nc_pad] = acc;
+            st_vec(out + (int64_t)line * nc_pad, acc);
         }
     }
 }
@@ -463,7 +464,7 @@ __global__ __launch_bounds__(64 * kFoldWaves, fold_waves_per_simd<WT>()) void re
     const int plane = d_plane ? d_plane[d] : d;
     const C* src = T0 + (int64_t)plane * W * W * NC + c0;
     for (int i = tid; i < W * W * 64; i += 64 * kFoldWaves)
-        sT[i] = src[(int64_t)(i >> 6) * NC + (i & 63)];
+        st_vec(sT + i, ld_vec(src + (int64_t)(i >> 6) * NC + (i & 63)));
     __syncthreads();
     const int cc = tid & 63, tg = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int li = cc & 15, lg = cc >> 4;
@@ -488,7 +489,7 @@ __global__ __launch_bounds__(64 * kFoldWaves, fold_waves_per_simd<WT>()) void re
 #pragma unroll
             for (int r2 = 0; r2 < NV; ++r2)
                 if (r2 < W) {
-                    const C v = row[r2 * 64];
+                    const C v = ld_vec(row + r2 * 64);
                     ta[r2] = cfma(pa, v, ta[r2]);
                     tb[r2] = cfma(pbv, v, tb[r2]);
                 }
@@ -879,8 +880,11 @@ __global__ __launch_bounds__(256, line_waves_per_simd<FEAT>()) void line_rates_k
     const Mesh mesh = a.mesh;
     const int N0 = mesh.n0;
     const int ldf = a.nc_pad;
-    C* sP = reinterpret_cast<C*>(smem_raw);                    // [N0 + 1][Wp], row N0 zero
-    C* sY = sP + (N0 + 1) * Wp;                                // [16][nm]
+    // phase table rows are Wp + 1 elements apart: the 16 rows an MFMA step reads then
+    // start on different LDS banks (Wp apart, every other row would share banks)
+    const int Ws = Wp + 1;
+    C* sP = reinterpret_cast<C*>(smem_raw);                    // [N0 + 1][Ws], row N0 zero
+    C* sY = sP + (N0 + 1) * Ws;                                // [16][nm]
     uint32_t* sPm = reinterpret_cast<uint32_t*>(sY + 16 * nm);  // [N0] live bands per point
     int* sList = reinterpret_cast<int*>(sPm + N0);             // [N0] live points of a band
     // LW: [N0][nm] linewidth partials of the work-group (8-byte aligned: N0 ints above)
@@ -941,9 +945,9 @@ __global__ __launch_bounds__(256, line_waves_per_simd<FEAT>()) void line_rates_k
     const int64_t Tk = (int64_t)NL * ldf;  // stride of R0 in T2
 
     const uint32_t* lv = a.live + ((int64_t)st * NL + line) * N0;
-    const int nP = (N0 + 1) * Wp;
+    const int nP = (N0 + 1) * Ws;
     auto p0_at = [&](int i) {
-        const int q0 = i / Wp, r = i - q0 * Wp;
+        const int q0 = i / Ws, r = i - q0 * Ws;
         return (q0 < N0 && r < W) ? to_c<C>(a.P0[q0 * W + r]) : C{0, 0};
     };
     // The first mask and table elements and the T2 fragments are loaded
@@ -952,7 +956,7 @@ __global__ __launch_bounds__(256, line_waves_per_simd<FEAT>()) void line_rates_k
     // from row W - 1 and meets a zero phase (the table is zero beyond W).
     const int i0 = min(tid, nP - 1), i1 = min(tid + 256, nP - 1);
     auto p0_src = [&](int i) {
-        const int q0 = i / Wp, r = i - q0 * Wp;
+        const int q0 = i / Ws, r = i - q0 * Ws;
         return a.P0[min(q0, N0 - 1) * W + min(r, W - 1)];
     };
     const uint32_t pm0 = lv[min(tid, N0 - 1)];
@@ -968,7 +972,7 @@ __global__ __launch_bounds__(256, line_waves_per_simd<FEAT>()) void line_rates_k
         }
     }
     auto p0_keep = [&](int i) {
-        const int q0 = i / Wp, r = i - q0 * Wp;
+        const int q0 = i / Ws, r = i - q0 * Ws;
         return q0 < N0 && r < W;
     };
     if (tid < N0) sPm[tid] = pm0;
@@ -1076,7 +1080,7 @@ __global__ __launch_bounds__(256, line_waves_per_simd<FEAT>()) void line_rates_k
             const int pc = has_item && g + ic < cnt ? sList[g + ic] : -1;
             Unit d;
             load_unit(pl, pc, m, d);
-            const int prow = (pl >= 0 ? pl : N0) * Wp;
+            const int prow = (pl >= 0 ? pl : N0) * Ws;
             // X^T tiles of the unit's points and Y, two column tiles at a time
 #pragma unroll
             for (int t0 = 0; t0 < TN; t0 += kTP) {
@@ -1106,7 +1110,7 @@ __global__ __launch_bounds__(256, line_waves_per_simd<FEAT>()) void line_rates_k
                         C bc[P];
 #pragma unroll
                         for (int t = 0; t < P; ++t) bc[t] = t0 + t < TN ? tb[ks * TN + t0 + t] : C{0, 0};
-                        kstep(bc, sP[prow + 4 * ks + lg]);
+                        kstep(bc, ld_vec(sP + prow + 4 * ks + lg));
                     }
                 } else {
                     for (int k0 = 0; k0 < Wp; k0 += 4) {
@@ -1115,7 +1119,7 @@ __global__ __launch_bounds__(256, line_waves_per_simd<FEAT>()) void line_rates_k
 #pragma unroll
                         for (int t = 0; t < P; ++t)
                             bc[t] = (k < W && t0 + t < TN) ? Tst[k * Tk + (t0 + t) * 16] : C{0, 0};
-                        kstep(bc, sP[prow + k]);
+                        kstep(bc, ld_vec(sP + prow + k));
                     }
                 }
                 // Y[slot li, sa] = sum_b X[slot li, sa, b] U_{k+q}[b, m]: products over
@@ -1187,7 +1191,7 @@ __global__ __launch_bounds__(256, line_waves_per_simd<FEAT>()) void line_rates_k
 
 size_t line_rates_lds(int W, int N0, int nm, bool f32, bool lw) {
     const int Wp = (W + 3) & ~3;
-    return ((size_t)(N0 + 1) * Wp + 16 * (size_t)nm) * (f32 ? sizeof(cf) : sizeof(cd)) +
+    return ((size_t)(N0 + 1) * (Wp + 1) + 16 * (size_t)nm) * (f32 ? sizeof(cf) : sizeof(cd)) +
            2 * (size_t)N0 * sizeof(uint32_t) +
            (lw ? sizeof(uint32_t) * (size_t)(N0 & 1) + (size_t)N0 * nm * sizeof(double) : 0);
 }
