@@ -440,7 +440,7 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
         const size_t f_elem = prec == PHOEBE_FP64 ? sizeof(cd)
                               : prec == PHOEBE_FP32 ? sizeof(cf)
                               : prec == PHOEBE_BF16X3 ? 4 * sizeof(uint16_t) : 6 * sizeof(uint16_t);
-        if (lowp && stage2_lp_lds(prec, tq, rmax_p, rp_pad, nc_pad, nm) > 159 * 1024) {
+        if (lowp && stage2_lp_lds(prec, tq, rmax_p, rp_pad, nc_pad, nm, nW, false) > 159 * 1024) {
             set_err(h, "stage-2 tile does not fit in LDS");
             throw Fail{PHOEBE_E_UNSUPPORTED};
         }

@@ -34,6 +34,7 @@ struct SysPlan {
     int states = 0;
     int nW = 0, nm = 0, n_re = 0, n_rp = 0, rmax = 0, rp_pad = 0;
     int tq = 2, tn = 1, nc_pad = 64, n_qtiles = 0;
+    int stage = 0;  // the tile stages its rotation operands in LDS (chosen per tile shape)
     double sigma = 0.0;
     std::vector<int32_t> strow;
     const phoebe_system* sys = nullptr;
@@ -155,6 +156,7 @@ void fill_desc(const SysPlan& p, SysDesc& d) {
     a.sigma = p.sigma;
     a.partial = p.partial;
     a.n_qtiles = p.n_qtiles;
+    a.stage = p.stage;
     d.tq = p.tq;
     d.tn = p.tn;
 }
@@ -400,7 +402,7 @@ phoebe_status phoebe_gpu_batched_plan(void* handle, const phoebe_system* systems
             auto it = cache.find(key);
             if (it != cache.end() &&
                 batched_tile_supported(it->second.first, it->second.second, p.nm * p.nW) &&
-                batched_lds(it->second.first, p.rmax, p.rp_pad, nc_pad_for(p.nm * p.nW, it->second.second), p.nm) <= 150 * 1024) {
+                batched_lds(it->second.first, p.rmax, p.rp_pad, nc_pad_for(p.nm * p.nW, it->second.second), p.nm, p.nW, false) <= 150 * 1024) {
                 p.tq = it->second.first;
                 p.tn = it->second.second;
                 continue;
@@ -415,8 +417,11 @@ phoebe_status phoebe_gpu_batched_plan(void* handle, const phoebe_system* systems
                 const int tq = c[0], tn = c[1];
                 if (!batched_tile_supported(tq, tn, p.nm * p.nW)) continue;
                 const int ncp = nc_pad_for(p.nm * p.nW, tn);
-                const size_t lds = batched_lds(tq, p.rmax, p.rp_pad, ncp, p.nm);
-                if (lds > 150 * 1024) continue;
+                const size_t lds0 = batched_lds(tq, p.rmax, p.rp_pad, ncp, p.nm, p.nW, false);
+                const size_t lds1 = batched_lds(tq, p.rmax, p.rp_pad, ncp, p.nm, p.nW, true);
+                if (lds0 > 150 * 1024) continue;
+                const bool stg = batched_stage_pays(batched_shape(tq, tn), lds0, lds1);
+                const size_t lds = stg ? lds1 : lds0;
                 Arena wa(h->ws);
                 cf* G = wa.take<cf>(g_max);
                 cf* F = wa.take<cf>((size_t)ns * p.rp_pad * ncp);
@@ -434,6 +439,7 @@ phoebe_status phoebe_gpu_batched_plan(void* handle, const phoebe_system* systems
                 q.F = F;
                 q.partial = part;
                 q.n_qtiles = nqt;
+                q.stage = stg ? 1 : 0;
                 SysDesc d{};
                 fill_desc(q, d);
                 std::vector<BTask> tv;
@@ -491,6 +497,9 @@ phoebe_status phoebe_gpu_batched_plan(void* handle, const phoebe_system* systems
         });
         Arena dry(nullptr);
         size_t f_total = 0, part_total = 0;
+        // per shape: the largest LDS block of its systems, without and with staging;
+        // staging is chosen for the whole shape (one kernel, one LDS size)
+        size_t lds0[kBatchedShapes] = {}, lds1[kBatchedShapes] = {};
         for (auto& p : P->sp) {
             if (!in_graph(p)) continue;
             p.nc_pad = nc_pad_for(p.nm * p.nW, p.tn);
@@ -498,7 +507,15 @@ phoebe_status phoebe_gpu_batched_plan(void* handle, const phoebe_system* systems
             f_total += (size_t)p.states * p.rp_pad * p.nc_pad;
             part_total += (size_t)p.states * p.n_qtiles;
             const int sh = batched_shape(p.tq, p.tn);
-            P->lds_shape[sh] = std::max(P->lds_shape[sh], batched_lds(p.tq, p.rmax, p.rp_pad, p.nc_pad, p.nm));
+            lds0[sh] = std::max(lds0[sh], batched_lds(p.tq, p.rmax, p.rp_pad, p.nc_pad, p.nm, p.nW, false));
+            lds1[sh] = std::max(lds1[sh], batched_lds(p.tq, p.rmax, p.rp_pad, p.nc_pad, p.nm, p.nW, true));
+        }
+        for (int sh = 0; sh < kBatchedShapes; ++sh) {
+            if (!lds0[sh]) continue;
+            const bool stg = batched_stage_pays(sh, lds0[sh], lds1[sh]);
+            P->lds_shape[sh] = stg ? lds1[sh] : lds0[sh];
+            for (auto& p : P->sp)
+                if (in_graph(p) && batched_shape(p.tq, p.tn) == sh) p.stage = stg ? 1 : 0;
         }
         for (int sh = 0; sh < kBatchedShapes; ++sh)
             for (int i : order) {

@@ -23,7 +23,10 @@ struct BTask {
 constexpr int kBatchedShapes = 12;
 int batched_shape(int tq, int tn);
 bool batched_tile_supported(int tq, int tn, int nc);
-size_t batched_lds(int tq, int rmax, int rp_pad, int nc_pad, int nm);
+// dynamic LDS of a system's tiles, with or without the staged rotation operands
+size_t batched_lds(int tq, int rmax, int rp_pad, int nc_pad, int nm, int nW, bool stage);
+// staging pays for the shape's kernel at these LDS sizes (see lp_stage_pays)
+bool batched_stage_pays(int shape, size_t lds0, size_t lds1);
 // sets the kernel's dynamic LDS limit (outside a stream capture)
 hipError_t prepare_batched_rates(int shape, size_t lds);
 hipError_t launch_batched_rates(int shape, const SysDesc* sys, const BTask* tasks, int n_tasks,

@@ -13,6 +13,10 @@
 
 namespace phx {
 
+// Waves per SIMD a shape's kernel is compiled for: three where its registers fit
+// without spills, two for the widest tiles.
+constexpr int batched_waves_per_simd(int tq, int tn) { return tn >= 8 || tq * tn >= 8 ? 2 : 3; }
+
 // Every work-group loops: take the next task index from the queue head, run
 // it, stop when the queue is exhausted (every wave reaches the exit).
 //
@@ -22,7 +26,7 @@ namespace phx {
 // end of one task with the fetch of the next into one thread-divergent path,
 // which would put the work-group's barriers under a divergent loop.
 template <int TQ, int TN>
-__global__ __launch_bounds__(256, 2) void batched_rates_kernel(const SysDesc* __restrict__ sys,
+__global__ __launch_bounds__(256, batched_waves_per_simd(TQ, TN)) void batched_rates_kernel(const SysDesc* __restrict__ sys,
                                                                const BTask* __restrict__ tasks,
                                                                int n_tasks, int* head) {
     extern __shared__ char smem_raw[];
@@ -92,8 +96,13 @@ bool batched_tile_supported(int tq, int tn, int nc) {
     return 64 * tn >= nc && batched_shape(tq, tn) >= 0;
 }
 
-size_t batched_lds(int tq, int rmax, int rp_pad, int nc_pad, int nm) {
-    return stage2_lp_lds(PHOEBE_FP32, tq, rmax, rp_pad, nc_pad, nm);
+size_t batched_lds(int tq, int rmax, int rp_pad, int nc_pad, int nm, int nW, bool stage) {
+    return stage2_lp_lds(PHOEBE_FP32, tq, rmax, rp_pad, nc_pad, nm, nW, stage);
+}
+
+bool batched_stage_pays(int shape, size_t lds0, size_t lds1) {
+    const void* fn = kernel_of(shape);
+    return fn && lp_stage_pays(fn, lds0, lds1);
 }
 
 hipError_t prepare_batched_rates(int shape, size_t lds) {

@@ -308,11 +308,14 @@ __global__ __launch_bounds__(256, 2) void stage2_rates_lp_kernel(RateArgsLP a) {
     stage2_lp_tile<PREC, TQ, TN>(a, blockIdx.y, blockIdx.x, smem_raw, sh);
 }
 
-size_t stage2_lp_lds(int prec, int tq, int rmax, int rp_pad, int nc_pad, int nm) {
+size_t stage2_lp_lds(int prec, int tq, int rmax, int rp_pad, int nc_pad, int nm, int nW,
+                     bool stage) {
     const int BQ = 16 * tq, CQ = 4 * tq, W = 2 * rmax + 1;
     size_t shm = (size_t)BQ * 3 * W * sizeof(cd) + (size_t)rp_pad * sizeof(int);
     shm = (shm + 15) & ~(size_t)15;
     shm += (size_t)CQ * nc_pad * sizeof(cf) + (size_t)CQ * kMBLP * nm * sizeof(cf);
+    // staged U_{k+q} rows [CQ][MB][nW] and E_q [CQ][nm][nm]
+    if (stage) shm += (size_t)CQ * kMBLP * nW * sizeof(cf) + (size_t)CQ * nm * nm * sizeof(cf);
     shm = (shm + 15) & ~(size_t)15;
     // split-BF16: two buffers of NP pieces x (re, im) x TQ x 64 lanes x 8 BF16
     const int np = prec == PHOEBE_BF16X3 ? 2 : (prec == PHOEBE_BF16X6 ? 3 : 0);
@@ -320,12 +323,28 @@ size_t stage2_lp_lds(int prec, int tq, int rmax, int rp_pad, int nc_pad, int nm)
     return shm;
 }
 
+bool lp_stage_pays(const void* kern, size_t shm0, size_t shm1) {
+    if (shm1 > 160 * 1024 - 1024) return false;
+    if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm1) !=
+        hipSuccess)
+        return false;
+    int n0 = 0, n1 = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n0, kern, 256, shm0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&n1, kern, 256, shm1) != hipSuccess)
+        return false;
+    return n1 >= n0;
+}
+
 template <int PREC, int TQ, int TN>
-static hipError_t go_stage2_lp(const RateArgsLP& a, int nst, hipStream_t s) {
-    const size_t shm = stage2_lp_lds(PREC, TQ, a.rmax, a.rp_pad, a.nc_pad, a.nm);
-    if (shm > 160 * 1024 - 1024) return hipErrorInvalidValue;
-    hipError_t e = hipFuncSetAttribute((const void*)stage2_rates_lp_kernel<PREC, TQ, TN>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+static hipError_t go_stage2_lp(const RateArgsLP& a0, int nst, hipStream_t s) {
+    const void* kern = (const void*)stage2_rates_lp_kernel<PREC, TQ, TN>;
+    const size_t shm0 = stage2_lp_lds(PREC, TQ, a0.rmax, a0.rp_pad, a0.nc_pad, a0.nm, a0.nW, false);
+    const size_t shm1 = stage2_lp_lds(PREC, TQ, a0.rmax, a0.rp_pad, a0.nc_pad, a0.nm, a0.nW, true);
+    if (shm0 > 160 * 1024 - 1024) return hipErrorInvalidValue;
+    RateArgsLP a = a0;
+    a.stage = lp_stage_pays(kern, shm0, shm1) ? 1 : 0;
+    const size_t shm = a.stage ? shm1 : shm0;
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) return e;
     const size_t fbytes = (PREC == PHOEBE_FP32 ? sizeof(cf)
                                                : (PREC == PHOEBE_BF16X3 ? 4 : 6) * sizeof(uint16_t)) *

@@ -33,6 +33,9 @@ struct RateArgsLP {
     double sigma;
     double* partial;
     int n_qtiles;
+    // stage each rotation chunk's U_{k+q} rows and E_q in LDS (set by the launcher
+    // where the larger LDS block costs no occupancy)
+    int stage;
 };
 
 // C (cf) = A (cd phases) * B in the given precision (FP32, BF16X3, BF16X6).
@@ -45,7 +48,11 @@ hipError_t launch_fold_uk_lp(int prec, const cf* G, int64_t ldg, const cd* U,
                              const int32_t* st_band, int nst, int n_rp, int nm, int nW, int cw,
                              int rp_pad, int nc_pad, void* F, hipStream_t s);
 hipError_t launch_stage2_rates_lp(int prec, const RateArgsLP& a, int nst, hipStream_t s);
-size_t stage2_lp_lds(int prec, int tq, int rmax, int rp_pad, int nc_pad, int nm);
+size_t stage2_lp_lds(int prec, int tq, int rmax, int rp_pad, int nc_pad, int nm, int nW,
+                     bool stage);
+// staging in LDS pays for a kernel when its larger LDS block (shm1) allows as many
+// resident work-groups per CU as the smaller one (shm0)
+bool lp_stage_pays(const void* kern, size_t shm0, size_t shm1);
 int stage2_lp_config(int nm, int nW, int* tq_out, int* tn_out);
 hipError_t launch_fold_all_lp(const cf* G, const cd* U, int n_rp, int nm, int nW, cf* F,
                               hipStream_t s);

@@ -88,6 +88,12 @@ __device__ __forceinline__ void stage2_lp_tile(const RateArgsLP& a, int st, int 
     off = (off + 15) & ~(size_t)15;
     cf* sX = reinterpret_cast<cf*>(smem_raw + off);            // [CQ][nc_pad]
     cf* sY = sX + CQ * a.nc_pad;                               // [CQ][MB][nm]
+    // with a.stage, a rotation chunk's operands are staged once (coalesced) instead
+    // of read per item: U_{k+q} rows of the pass' final bands and E_q of the chunk's
+    // q points (FP32)
+    const bool stg = a.stage != 0;
+    cf* sU = sY + CQ * kMBLP * nm;                             // [CQ][MB][nW]
+    cf* sE = sU + (stg ? CQ * kMBLP * nW : 0);                 // [CQ][nm][nm]
     double* sRed = sh.red;
     int* sKq = sh.kq;
     int* sQ = sh.q;
@@ -196,7 +202,7 @@ __device__ __forceinline__ void stage2_lp_tile(const RateArgsLP& a, int st, int 
         // The A fragments (phase pieces) are the same for the four waves: the
         // work-group forms each once per K step into LDS (double-buffered,
         // [buf][piece][re, im][i][lane] slots of 8 BF16), TPS threads per slot.
-        s8v* sAf = reinterpret_cast<s8v*>(sY + CQ * kMBLP * nm);
+        s8v* sAf = reinterpret_cast<s8v*>(sE + (stg ? CQ * nm * nm : 0));
         constexpr int SLOTS = TQ * 64;
         constexpr int TPS = 256 / SLOTS;  // threads per slot
         constexpr int JPT = 8 / TPS;      // phases per thread
@@ -300,6 +306,37 @@ __device__ __forceinline__ void stage2_lp_tile(const RateArgsLP& a, int st, int 
             sWq[cc] = w;
         }
         __syncthreads();
+        // the chunk's E_q and the first pass' U_{k+q} rows (zero rows where the q is
+        // beyond the list: no item reads them)
+        auto stage_u = [&](int m0) {
+            if (!stg) return;
+            const int nmb = min(kMBLP, mhi - m0 + 1);
+            for (int i = tid; i < CQ * nmb * nW; i += 256) {
+                const int cc = i / (nmb * nW);
+                const int r = i - cc * nmb * nW;
+                const int mb = r / nW, b = r - mb * nW;
+                const int kq = sKq[cc];
+                cf v = {0.f, 0.f};
+                if (kq >= 0) {
+                    const cd u = a.U[((int64_t)kq * nW + m0 + mb) * nW + b];  // eigenvector m
+                    v = cf{(float)u.x, (float)u.y};
+                }
+                sU[(cc * kMBLP + mb) * nW + b] = v;
+            }
+        };
+        for (int i = tid; stg && i < CQ * nm * nm; i += 256) {
+            const int cc = i / (nm * nm);
+            const int r = i - cc * nm * nm;
+            const int kq = sKq[cc];
+            cf v = {0.f, 0.f};
+            if (kq >= 0) {
+                const cd e = a.E[(int64_t)sQ[cc] * nm * nm + r];
+                v = cf{(float)e.x, (float)e.y};
+            }
+            sE[i] = v;
+        }
+        stage_u(mlo);
+        __syncthreads();
         for (int m0 = mlo; m0 <= mhi; m0 += kMBLP) {
             const int nmb = min(kMBLP, mhi - m0 + 1);
             for (int it = tid; it < CQ * nmb * nm; it += 256) {
@@ -310,13 +347,23 @@ __device__ __forceinline__ void stage2_lp_tile(const RateArgsLP& a, int st, int 
                 float yr = 0.f, yi = 0.f;
                 if (kq >= 0) {
                     const cf* Xr = sX + cc * ldf + sa * nW;
-                    const cd* Um = a.U + ((int64_t)kq * nW + m0 + mb) * nW;  // eigenvector m
-                    for (int b = 0; b < nW; ++b) {
-                        const cf x = Xr[b];
-                        const cd u = Um[b];
-                        const float ur = (float)u.x, ui = (float)u.y;
-                        yr = fmaf(x.x, ur, fmaf(-x.y, ui, yr));
-                        yi = fmaf(x.x, ui, fmaf(x.y, ur, yi));
+                    if (stg) {
+                        const cf* Ur = sU + (cc * kMBLP + mb) * nW;
+                        for (int b = 0; b < nW; ++b) {
+                            const cf x = Xr[b];
+                            const cf u = Ur[b];
+                            yr = fmaf(x.x, u.x, fmaf(-x.y, u.y, yr));
+                            yi = fmaf(x.x, u.y, fmaf(x.y, u.x, yi));
+                        }
+                    } else {
+                        const cd* Um = a.U + ((int64_t)kq * nW + m0 + mb) * nW;  // eigenvector m
+                        for (int b = 0; b < nW; ++b) {
+                            const cf x = Xr[b];
+                            const cd u = Um[b];
+                            const float ur = (float)u.x, ui = (float)u.y;
+                            yr = fmaf(x.x, ur, fmaf(-x.y, ui, yr));
+                            yi = fmaf(x.x, ui, fmaf(x.y, ur, yi));
+                        }
                     }
                 }
                 sY[(cc * kMBLP + mb) * nm + sa] = cf{yr, yi};
@@ -329,25 +376,40 @@ __device__ __forceinline__ void stage2_lp_tile(const RateArgsLP& a, int st, int 
                 const int kq = sKq[cc];
                 if (kq < 0) continue;
                 const int64_t q = sQ[cc];
-                const cf* Yr = sY + (cc * kMBLP + mb) * nm;
-                const cd* Eq = a.E + (q * nm + nu) * nm;
-                float zr = 0.f, zi = 0.f;
-                for (int sa = 0; sa < nm; ++sa) {
-                    const cd e = Eq[sa];
-                    const float er = (float)e.x, ei = (float)e.y;
-                    const cf y = Yr[sa];
-                    zr = fmaf(er, y.x, fmaf(-ei, y.y, zr));
-                    zi = fmaf(er, y.y, fmaf(ei, y.x, zi));
-                }
                 const int m = m0 + mb;
                 const double x = eps_n - a.eps[(int64_t)kq * nW + m];
-                const double fm = a.focc[(int64_t)kq * nW + m];
-                const double w = a.omega[q * nm + nu], nbq = a.nb[q * nm + nu];
+                const double w = a.omega[q * nm + nu];
                 const double y1 = x - w, y2 = x + w;
+                // both Gaussians underflow to exactly 0 beyond 27.5 sigma: the term is 0
+                if (fabs(y1) > 27.5 * a.sigma && fabs(y2) > 27.5 * a.sigma) continue;
+                const cf* Yr = sY + (cc * kMBLP + mb) * nm;
+                float zr = 0.f, zi = 0.f;
+                if (stg) {
+                    const cf* Er = sE + (cc * nm + nu) * nm;
+                    for (int sa = 0; sa < nm; ++sa) {
+                        const cf e = Er[sa];
+                        const cf y = Yr[sa];
+                        zr = fmaf(e.x, y.x, fmaf(-e.y, y.y, zr));
+                        zi = fmaf(e.x, y.y, fmaf(e.y, y.x, zi));
+                    }
+                } else {
+                    const cd* Eq = a.E + (q * nm + nu) * nm;
+                    for (int sa = 0; sa < nm; ++sa) {
+                        const cd e = Eq[sa];
+                        const float er = (float)e.x, ei = (float)e.y;
+                        const cf y = Yr[sa];
+                        zr = fmaf(er, y.x, fmaf(-ei, y.y, zr));
+                        zi = fmaf(er, y.y, fmaf(ei, y.x, zi));
+                    }
+                }
+                const double fm = a.focc[(int64_t)kq * nW + m];
+                const double nbq = a.nb[q * nm + nu];
                 const double g1 = exp(-y1 * y1 * inv_s2), g2 = exp(-y2 * y2 * inv_s2);
                 const double z2 = (double)zr * zr + (double)zi * zi;
                 gacc += sWq[cc] * z2 * ((nbq + 1.0 - fm) * g1 + (nbq + fm) * g2);
             }
+            // the next pass' U_{k+q} rows (this pass' Y loop, their only reader, is done)
+            if (m0 + kMBLP <= mhi) stage_u(m0 + kMBLP);
             __syncthreads();
         }
     }
