@@ -244,6 +244,24 @@ def main():
                     frac=d["frac"], traffic=traffic, traffic_unit="B/launch", kernel=dom,
                     launches_per_step=d["launches_per_step"], avg_launch_ms=d["avg_launch_ms"],
                     work_per_launch=d["work_per_launch"])
+    # HBM bytes of one step: compulsory (g(Re,Rp) read once, the band and phonon tables
+    # written once) against what the HBM-bound kernels move by their algorithmic
+    # accounting and, where the committed counter summary matches every kernel's
+    # source, by the calibrated FETCH_SIZE + WRITE_SIZE counters
+    ew = 16.0 if args.precision == "fp64" else 8.0
+    tables = N * (8.0 * nW + 16.0 * nW * nW + 16.0 * nm + 16.0 * nm * nm)
+    hbm_k = [k for k, v in kernels.items() if v["bound"] == "hbm"]
+    counted = None
+    if args.workload == "realistic" and args.precision == "fp64" and hbm_k:
+        per = [measured_traffic(k) for k in hbm_k]
+        if all(x is not None for x in per):
+            counted = sum(x * kernels[k]["launches_per_step"] for x, k in zip(per, hbm_k))
+    step_bytes = dict(compulsory=g_bytes + tables,
+                      algorithmic=sum(kernels[k]["work_per_launch"] * kernels[k]["launches_per_step"]
+                                      for k in hbm_k),
+                      counted=counted, kernels=hbm_k,
+                      note=f"compulsory: g(Re,Rp) once ({g_bytes:.3e} B) + tables once; the rest "
+                           f"are the factorised sums' intermediates ({ew:.0f}-byte elements)")
 
     # interp_g element rate (all (nu, n, m) of nk kept k x the full q mesh)
     gel = None
@@ -363,6 +381,7 @@ def main():
         "err_vs_oracle": err,
         "roofline": roofline,
         "kernels": kernels,
+        "step_hbm_bytes": step_bytes,
         "mesh_sum": args.mesh_sum,
         "cpu_baseline": cpu,
     }
