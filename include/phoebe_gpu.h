@@ -297,15 +297,17 @@ size_t phoebe_gpu_noalloc_scratch_bytes(void);
  * and kept-state lists, picks each system's tile shape with an autotuner (the
  * candidates are timed on the device; choices are read from and written to
  * tune_cache, a small JSON file, when it is not NULL), and captures one
- * hipGraph: stage 1 and the U_k fold of every system, then one persistent
- * kernel that drains a work queue of (system, state, q tile) tasks, then the
- * per-system reductions.  Only PHOEBE_FP32 contractions (complex64) are
- * offered; tables, eigensolves, occupations and rate sums are FP64.  Unless
- * the handle's mesh-sum mode is PHOEBE_MESH_SUM_DIRECT, every system of at most
- * 16 Wannier functions (its full q mesh is what the plan sums) is taken out of
- * the graph and run by phoebe_gpu_batched_run as one plain rate call (FP32, the
- * factorised mesh sums, the handle's workspace) after the graph; such systems
- * report tq = tn = 0 in phoebe_gpu_batched_info.
+ * hipGraph: stage 1 and the U_k fold of every system, then persistent
+ * kernels (one per tile shape in use) that drain work queues of (system,
+ * state, q tile) tasks, then the per-system reductions.  Only PHOEBE_FP32
+ * contractions (complex64) are offered; tables, eigensolves, occupations and
+ * rate sums are FP64.  Unless the handle's mesh-sum mode is
+ * PHOEBE_MESH_SUM_DIRECT, every system that phoebe_gpu_scatter_rates would sum
+ * in the factorised form (the automatic rule of phoebe_gpu_set_mesh_sum on its
+ * full q mesh) is taken out of the graph and run by phoebe_gpu_batched_run as
+ * one plain rate call (FP32, the handle's workspace, the band and phonon tables
+ * the plan built) after the graph; such systems report tq = tn = 0 in
+ * phoebe_gpu_batched_info.
  *   systems   host [n_sys] (their tensors are device pointers, used until the
  *             plan is destroyed)
  *   meshes    host [n_sys, 3];  params host [n_sys]
@@ -568,7 +570,8 @@ phoebe_status phoebe_gpu_set_check_finite(void *handle, int enable);
  * three per-axis factors on a full mesh, so the sum is taken one axis at a
  * time over the box [-rmax, rmax]^3 holding the Rp list (zero where the list
  * has no vector); the result is the same sum up to the order of additions.
- * Needs FP64 or FP32, the full q mesh, |Rp components| <= 15, nW <= 16,
+ * Needs FP64 or FP32, the full q mesh, |Rp components| <= 15, nW <= 32 (16
+ * with the polar or adaptive terms and for phoebe_gpu_phonon_linewidth),
  * nModes <= 32, N0 <= 1024 and N1*N2 <= 65535.
  * AUTO (the default) takes FACTORED where it applies and the box width is at
  * most half the number of Rp vectors (the sum over Re is then factorised the

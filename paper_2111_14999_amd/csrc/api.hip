@@ -408,13 +408,16 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
         const int Wbox = 2 * rmax_p + 1;
         const int nc_line = line_rates_ncpad(nm, nW);
         const int64_t NL = (int64_t)mesh.n1 * mesh.n2;
+        // (16 < nW <= 32: the plain rates; the extension terms need nW <= 16)
         const bool can_factor = (prec == PHOEBE_FP64 || prec == PHOEBE_FP32) && q_off == nullptr &&
                                 Wbox <= 31 && nc_line > 0 && NL <= 65535 && mesh.n0 <= 1024 &&
+                                (nW <= 16 || !ext) &&
                                 line_rates_lds(Wbox, mesh.n0, nm, lowp, lw_out != nullptr) <=
                                     64 * 1024;
         if (h->mesh_sum == PHOEBE_MESH_SUM_FACTORED && !can_factor) {
             set_err(h, "the factorised mesh sum needs FP64 or FP32, the full q mesh, |Rp| <= 15, "
-                       "nW <= 16, nModes <= 32, N0 <= 1024 and N1*N2 <= 65535");
+                       "nW <= 32 (16 with linewidth, polar or adaptive terms), nModes <= 32, "
+                       "N0 <= 1024 and N1*N2 <= 65535");
             throw Fail{PHOEBE_E_UNSUPPORTED};
         }
         HIPCHK(h, hipSetDevice(h->device));
@@ -422,9 +425,10 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
         const bool factored = can_factor && (h->mesh_sum == PHOEBE_MESH_SUM_FACTORED ||
                                              (h->mesh_sum == PHOEBE_MESH_SUM_AUTO &&
                                               2 * Wbox <= sys->n_rp));
-        // stage-2 operand columns: sa*nW + b (direct), sa*16 + b (factorised)
+        // stage-2 operand columns: sa*nW + b (direct), sa*16 + b (factorised, nW <= 16) or
+        // sa*32 + b (factorised, nW <= 32)
         const int nc_pad = factored ? nc_line : nc_direct;
-        const int cw = factored ? 16 : nW;
+        const int cw = factored ? (nW <= 16 ? 16 : 32) : nW;
         HIPCHK(h, hipSetDevice(h->device));
         const int n_re = sys->n_re, n_rp = sys->n_rp;
         // K padding of the stage-2 operand: 4 (K of the f64/f32 MFMA) or 32 (bf16)

@@ -375,9 +375,15 @@ phoebe_status phoebe_gpu_batched_plan(void* handle, const phoebe_system* systems
             HIPCHK(h, hipMemcpyAsync(p.strow.data(), p.st_row, 4 * (size_t)p.states,
                                      hipMemcpyDeviceToHost, s));
             HIPCHK(h, hipStreamSynchronize(s));
-            // full meshes of at most 16 bands: the plain path's factorised sums do about 40x
-            // fewer operations than the direct contraction of the persistent kernel
-            p.plain = h->mesh_sum != PHOEBE_MESH_SUM_DIRECT && p.nW <= 16;
+            // where the plain rate call takes the factorised sums (its automatic rule: the
+            // full mesh, nW <= 32, an Rp box at most 31 wide and half the Rp count), they
+            // do tens of times fewer operations than the persistent kernel's direct
+            // contraction, so the system runs as such a call
+            const int wbox = 2 * p.rmax + 1;
+            p.plain = h->mesh_sum != PHOEBE_MESH_SUM_DIRECT && line_rates_ncpad(p.nm, p.nW) > 0 &&
+                      wbox <= 31 && 2 * wbox <= p.n_rp && p.mesh.n0 <= 1024 &&
+                      (int64_t)p.mesh.n1 * p.mesh.n2 <= 65535 &&
+                      line_rates_lds(wbox, p.mesh.n0, p.nm, true) <= 64 * 1024;
             if (p.plain) p.tq = p.tn = 0;
         }
 

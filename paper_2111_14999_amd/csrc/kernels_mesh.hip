@@ -750,7 +750,7 @@ __global__ __launch_bounds__(256, 8) void line_live_kernel(RateArgs a, uint32_t*
         const int64_t kq12 = ((k1i + q1) % mesh.n1) * mesh.n2 + (k2i + q2) % mesh.n2;
         const double eps_n = a.eps[(int64_t)kmesh * nW + a.st_band[st]];
         const double lim = 27.5 * a.sigma + *a.wmax;
-        uint32_t cnt2[8] = {};  // live points per band, two 16-bit counts a word (N0 <= 1024)
+        uint32_t cnt2[16] = {};  // live points per band, two 16-bit counts a word (N0 <= 1024)
         uint32_t* out = live + i * N0;
         // band values two at a time (16-byte loads from an even band; rows are
         // nW doubles, nW even here); masks four at a time where N0 % 4 == 0
@@ -785,7 +785,7 @@ __global__ __launch_bounds__(256, 8) void line_live_kernel(RateArgs a, uint32_t*
             }
             u |= bits;
 #pragma unroll
-            for (int m = 0; m < 16; ++m) cnt2[m >> 1] += ((bits >> m) & 1u) << (16 * (m & 1));
+            for (int m = 0; m < 32; ++m) cnt2[m >> 1] += ((bits >> m) & 1u) << (16 * (m & 1));
             return bits;
         };
         if ((N0 & 3) == 0) {
@@ -804,7 +804,7 @@ __global__ __launch_bounds__(256, 8) void line_live_kernel(RateArgs a, uint32_t*
         line_bands[i] = u;
         if (!u) a.partial[(int64_t)st * a.n_qtiles + line] = 0.0;  // the line kernel skips the pair
 #pragma unroll
-        for (int m = 0; m < 16; ++m) units += (((cnt2[m >> 1] >> (16 * (m & 1))) & 0xFFFFu) + 15) / 16;
+        for (int m = 0; m < 32; ++m) units += (((cnt2[m >> 1] >> (16 * (m & 1))) & 0xFFFFu) + 15) / 16;
     }
     const uint64_t bal = __ballot(u != 0);
 #pragma unroll
@@ -818,7 +818,7 @@ __global__ __launch_bounds__(256, 8) void line_live_kernel(RateArgs a, uint32_t*
 hipError_t launch_line_live(const RateArgs& a, int nst, uint32_t* live, uint32_t* line_bands,
                             uint32_t* n_live, hipStream_t s) {
     if (nst <= 0) return hipSuccess;
-    if (a.nW > 16 || !live || !line_bands || !n_live || !a.partial ||
+    if (a.nW > 32 || !live || !line_bands || !n_live || !a.partial ||
         a.n_qtiles != a.mesh.n1 * a.mesh.n2)
         return hipErrorInvalidValue;
     RateArgs b = a;
@@ -860,15 +860,21 @@ constexpr int kTP = 2;  // column tiles per MFMA pass
 // carries only the registers of its own terms.
 // partials (RateArgs.Lpol / vel / lw), each switched on by its pointer.
 // Waves per SIMD the line kernel is compiled for: four for the plain rates; the
-// extension terms need more registers, and at four waves they would spill.
+// extension terms, and the FP64 form with two tiles per mode (its U_{k+q} values
+// of both halves), need more registers, and at four waves they would spill.
 constexpr int kLineLW = 1, kLinePol = 2, kLineVel = 4;
-template <int FEAT>
+template <int FEAT, int H, bool F64>
 constexpr int line_waves_per_simd() {
-    return FEAT == 0 || FEAT == kLineLW ? 4 : 3;
+    return (H == 2 && F64) ? 3 : (FEAT == 0 || FEAT == kLineLW ? 4 : 3);
 }
 
-template <int TN, int KS, class C, int FEAT>
-__global__ __launch_bounds__(256, line_waves_per_simd<FEAT>()) void line_rates_kernel(RateArgs a) {
+// H: column tiles per mode, 1 (nW <= 16: column sa*16 + b) or 2 (nW <= 32: column
+// sa*32 + b, the tiles of a mode being its halves b < 16 and b >= 16, one MFMA pass).
+template <int TN, int KS, class C, int FEAT, int H = 1>
+__global__ __launch_bounds__(256, (line_waves_per_simd<FEAT, H, sizeof(C) == sizeof(cd)>())) void
+line_rates_kernel(RateArgs a) {
+    static_assert(H == 1 || (H == 2 && FEAT == 0 && TN % 2 == 0 && kTP == 2),
+                  "two tiles per mode: plain rates, whole modes per wave and per pass");
     constexpr bool LW = FEAT & kLineLW, POL = FEAT & kLinePol, VEL = FEAT & kLineVel;
     using R = decltype(C::x);
     constexpr bool F64 = sizeof(R) == 8;
@@ -987,7 +993,7 @@ __global__ __launch_bounds__(256, line_waves_per_simd<FEAT>()) void line_rates_k
     // at k+q and omega and n of (q, nu).  Items beyond the first of a thread
     // (nm > 16) read theirs in place.
     struct Unit {
-        C u[4];
+        C u[4 * H];  // U_{k+q}[b, m] at b = 16 h + 4 lg + v, entry 4 h + v
         double em, fm, om, nbq;
     };
     const bool has_item = tid < 16 * nm;
@@ -998,7 +1004,11 @@ __global__ __launch_bounds__(256, line_waves_per_simd<FEAT>()) void line_rates_k
         const int64_t kql = pl >= 0 ? kq_of(pl) : 0;
         const cd* Ur = a.U + (kql * nW + m) * nW + 4 * lg;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) d.u[v] = (pl >= 0 && 4 * lg + v < nW) ? to_c<C>(Ur[v]) : C{0, 0};
+        for (int h = 0; h < H; ++h)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                d.u[4 * h + v] =
+                    (pl >= 0 && 16 * h + 4 * lg + v < nW) ? to_c<C>(Ur[16 * h + v]) : C{0, 0};
         d.em = d.fm = d.om = d.nbq = 0.0;
         if (has_item && pc >= 0) {
             const int64_t q = (int64_t)pc * NL + q12;
@@ -1128,23 +1138,31 @@ __global__ __launch_bounds__(256, line_waves_per_simd<FEAT>()) void line_rates_k
                 R pr[P], pi[P];
 #pragma unroll
                 for (int t = 0; t < P; ++t) {
+                    const C* uu = d.u + (H == 2 ? 4 * t : 0);  // H = 2: tile t is half t
                     R xr = 0, xi = 0;
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        xr += cr[t][v] * d.u[v].x - ci[t][v] * d.u[v].y;
-                        xi += cr[t][v] * d.u[v].y + ci[t][v] * d.u[v].x;
+                        xr += cr[t][v] * uu[v].x - ci[t][v] * uu[v].y;
+                        xi += cr[t][v] * uu[v].y + ci[t][v] * uu[v].x;
                     }
                     pr[t] = xr;
                     pi[t] = xi;
                 }
+                if constexpr (H == 1) {
 #pragma unroll
-                for (int t = 0; t < P; t += 2) {
-                    const R y = rows4_reduce_scatter(pr[t], t + 1 < P ? pr[t + 1] : R(0), pi[t],
-                                                     t + 1 < P ? pi[t + 1] : R(0));
-                    const int tt = t0 + t + (lg & 1);
-                    const int sa = wave * TN + tt;
-                    if (t + (lg & 1) < P && tt < TN && sa < nm)
-                        reinterpret_cast<R*>(sY + li * nm + sa)[lg >> 1] = y;
+                    for (int t = 0; t < P; t += 2) {
+                        const R y = rows4_reduce_scatter(pr[t], t + 1 < P ? pr[t + 1] : R(0), pi[t],
+                                                         t + 1 < P ? pi[t + 1] : R(0));
+                        const int tt = t0 + t + (lg & 1);
+                        const int sa = wave * TN + tt;
+                        if (t + (lg & 1) < P && tt < TN && sa < nm)
+                            reinterpret_cast<R*>(sY + li * nm + sa)[lg >> 1] = y;
+                    }
+                } else {
+                    // both halves of mode sa: Y is their sum; rows 0 and 2 receive Re and Im
+                    const R y = rows4_reduce_scatter(pr[0] + pr[1], R(0), pi[0] + pi[1], R(0));
+                    const int sa = (wave * TN + t0) >> 1;
+                    if (!(lg & 1) && sa < nm) reinterpret_cast<R*>(sY + li * nm + sa)[lg >> 1] = y;
                 }
             }
             if constexpr (POL) {
@@ -1196,18 +1214,23 @@ size_t line_rates_lds(int W, int N0, int nm, bool f32, bool lw) {
            (lw ? sizeof(uint32_t) * (size_t)(N0 & 1) + (size_t)N0 * nm * sizeof(double) : 0);
 }
 
-// Columns of the factorised form: one 16-wide tile per mode index, 4 waves x TN tiles.
+// Columns of the factorised form, 4 waves x TN tiles of 16: one tile per mode index
+// (nW <= 16), or two (16 < nW <= 32: a wave takes TN / 2 whole modes).
 int line_rates_ncpad(int nm, int nW) {
-    if (nW > 16 || nm > 32) return -1;
-    const int tn = (nm + 3) / 4;
-    return 64 * (tn == 5 ? 6 : (tn == 7 ? 8 : tn));
+    if (nW > 32 || nm > 32 || nm < 1 || nW < 1) return -1;
+    if (nW <= 16) {
+        const int tn = (nm + 3) / 4;
+        return 64 * (tn == 5 ? 6 : (tn == 7 ? 8 : tn));
+    }
+    const int tn = 2 * ((nm + 3) / 4);  // even: whole modes per wave
+    return 64 * (tn <= 8 ? tn : (tn <= 12 ? 12 : 16));
 }
 
-template <int TN, int KS, class C, int FEAT>
+template <int TN, int KS, class C, int FEAT, int H = 1>
 static hipError_t go_line(const RateArgs& a, int nst, hipStream_t s) {
     const size_t shm = line_rates_lds(a.W, a.mesh.n0, a.nm, sizeof(C) == sizeof(cf), a.lw != nullptr);
     if (shm > 64 * 1024) return hipErrorInvalidValue;
-    hipError_t e = hipFuncSetAttribute((const void*)line_rates_kernel<TN, KS, C, FEAT>,
+    hipError_t e = hipFuncSetAttribute((const void*)line_rates_kernel<TN, KS, C, FEAT, H>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) return e;
     const int64_t NL = (int64_t)a.mesh.n1 * a.mesh.n2;
@@ -1228,7 +1251,7 @@ static hipError_t go_line(const RateArgs& a, int nst, hipStream_t s) {
         b.line_bands = a.line_bands + (int64_t)s0 * NL;
         if (a.lw) b.lw = a.lw + (int64_t)s0 * NL * a.mesh.n0 * a.nm;
         b.n_states = ns;
-        hipLaunchKernelGGL((line_rates_kernel<TN, KS, C, FEAT>), dim3((unsigned)(groups * 8 * ns)),
+        hipLaunchKernelGGL((line_rates_kernel<TN, KS, C, FEAT, H>), dim3((unsigned)(groups * 8 * ns)),
                            dim3(256), shm, s, b);
     }
     return hipGetLastError();
@@ -1258,6 +1281,18 @@ static hipError_t line_rates(const RateArgs& a, int nst, hipStream_t s) {
         }
     };
     using std::integral_constant;
+    if (a.nW > 16) {  // two tiles per mode: the plain rates only
+        if (feat) return hipErrorInvalidValue;
+        switch (a.nc_pad / 64) {
+            case 2: return pre ? go_line<2, 2, C, 0, 2>(a, nst, s) : go_line<2, 0, C, 0, 2>(a, nst, s);
+            case 4: return pre ? go_line<4, 2, C, 0, 2>(a, nst, s) : go_line<4, 0, C, 0, 2>(a, nst, s);
+            case 6: return go_line<6, 0, C, 0, 2>(a, nst, s);
+            case 8: return go_line<8, 0, C, 0, 2>(a, nst, s);
+            case 12: return go_line<12, 0, C, 0, 2>(a, nst, s);
+            case 16: return go_line<16, 0, C, 0, 2>(a, nst, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (a.nc_pad / 64) {
         case 1: return pre ? with_feat(integral_constant<int, 1>{}, integral_constant<int, 2>{})
                            : with_feat(integral_constant<int, 1>{}, integral_constant<int, 0>{});

@@ -191,12 +191,17 @@ def _sparse_re(s, seed, keep_frac):
 
 @pytest.mark.parametrize("case", ["toy", "ragged-5x6x7", "sparse-rp", "sparse-re", "c2-tiling",
                                   "single-line", "nW16-sparse-re", "axis0-70", "rp-box-9",
-                                  "18-modes"])
+                                  "18-modes", "nW20-15-modes", "nW32-3-modes", "nW18-30-modes",
+                                  "nW17-sparse-rp"])
 def test_mesh_sum_forms_match_oracle(lib, toy, case):
-    """Both full-mesh forms against the oracle.  The last three cases take the line
-    kernel's general path: more than 64 points on axis 0 (point lists in LDS, two
-    ballot chunks), an Rp box 9 wide (T2 read per K step, three K steps) and 18 modes
-    (six column tiles per wave, term items beyond one per thread)."""
+    """Both full-mesh forms against the oracle.  "axis0-70", "rp-box-9" and "18-modes"
+    take the line kernel's general path: more than 64 points on axis 0 (point lists in
+    LDS, two ballot chunks), an Rp box 9 wide (T2 read per K step, three K steps) and 18
+    modes (six column tiles per wave, term items beyond one per thread).  The nW > 16
+    cases take its two-tiles-per-mode form (columns sa*32 + b): 15 modes (eight tiles
+    per wave), 3 modes (two tiles, most of the waves' modes beyond nModes), 30 modes
+    (sixteen tiles per wave) and 17 bands with a sparse Rp list (a half-empty second
+    tile of every mode)."""
     if case == "toy":
         s, mesh, par, ref = toy
     else:
@@ -219,6 +224,14 @@ def test_mesh_sum_forms_match_oracle(lib, toy, case):
         elif case == "18-modes":
             s, mesh = synth.small_system(80, n_wannier=4, n_atoms=6, r=1), (4, 3, 2)
             assert 3 * s.mass.shape[0] == 18
+        elif case == "nW20-15-modes":
+            s, mesh = synth.small_system(86, n_wannier=20, n_atoms=5, r=1), (5, 4, 3)
+        elif case == "nW32-3-modes":
+            s, mesh = synth.small_system(87, n_wannier=32, n_atoms=1, r=1), (3, 5, 4)
+        elif case == "nW18-30-modes":
+            s, mesh = synth.small_system(88, n_wannier=18, n_atoms=10, r=1), (3, 2, 3)
+        elif case == "nW17-sparse-rp":
+            s, mesh = _sparse_rp(synth.small_system(89, n_wannier=17, n_atoms=2, r=2), 9, 0.5), (4, 5, 3)
         else:
             s, mesh = synth.small_system(74, n_wannier=3, n_atoms=1, r=2), (33, 1, 1)
         s.h_r *= 0.3
@@ -351,3 +364,30 @@ def test_injected_device_error_and_recovery():
     lib.scatter_rates(ds, mesh, par, g)
     lib.set_fault_injection(0)
     lib.close()
+
+
+@pytest.mark.parametrize("nW,nat,mesh", [(20, 5, (5, 4, 3)), (32, 1, (3, 5, 4))])
+def test_two_tile_modes_fp32_factored(lib, nW, nat, mesh):
+    """FP32 form of the factorised sums with two column tiles per mode (16 < nW <= 32)
+    against the FP64 oracle at the FP32 bound."""
+    torch = torch_cuda()
+    from paper_2111_14999_amd import DeviceSystem
+    s = synth.small_system(90 + nW, n_wannier=nW, n_atoms=nat, r=1)
+    s.h_r *= 0.3
+    t = rates.mesh_tables(s, mesh)
+    mu = float(np.median(t["eps"]))
+    par = dict(mu=mu, kT=constants.kT_of(300.0), sigma=0.05, win_lo=mu - 0.8,
+               win_hi=mu + 0.8, omega_min=1e-4)
+    ref = rates.scattering_rates(s, mesh, tables=t, **par)
+    N = int(np.prod(mesh))
+    gamma = torch.full((N, nW), -1.0, dtype=torch.float64, device="cuda")
+    lib.set_mesh_sum("factored")
+    try:
+        n = lib.scatter_rates(DeviceSystem.from_host(s), mesh, par, gamma, precision="fp32")
+    finally:
+        lib.set_mesh_sum("auto")
+    torch.cuda.synchronize()
+    assert n == len(ref["k_idx"])
+    mx, med, _ = rel_err(gamma.cpu().numpy()[:n], ref["gamma"])
+    print(f"nW {nW}: FP32 factorised Gamma rel err max {mx:.2e} median {med:.2e}")
+    assert mx < 1e-6
