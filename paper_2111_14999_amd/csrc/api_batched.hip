@@ -300,7 +300,7 @@ phoebe_status phoebe_gpu_batched_plan(void* handle, const phoebe_system* systems
         {
             Arena dry(nullptr);
             for (auto& p : P->sp) carve_tables(dry, p);
-            tables_bytes = dry.used + 4096;
+            tables_bytes = (dry.used + 4096 + 255) & ~(size_t)255;  // part 2 starts aligned
         }
         // band scratch comes from the handle workspace, one system at a time
         size_t scratch = 0;
@@ -324,7 +324,7 @@ phoebe_status phoebe_gpu_batched_plan(void* handle, const phoebe_system* systems
         }
         P->mem = tables_mem;
         P->mem_bytes = tables_bytes;
-        Arena tar(tables_mem);
+        Arena tar(tables_mem, tables_bytes);
         for (int i = 0; i < n_sys; ++i) {
             SysPlan& p = P->sp[i];
             const phoebe_rate_params* par = &params[i];
@@ -342,7 +342,7 @@ phoebe_status phoebe_gpu_batched_plan(void* handle, const phoebe_system* systems
                                      hipMemcpyHostToDevice, s));
             HIPCHK(h, hipStreamSynchronize(s));
             {
-                Arena b1(h->ws), b2(h->ws);
+                Arena b1(h->ws, h->ws_cap), b2(h->ws, h->ws_cap);
                 electron_bands_dev(h, b1, sys, p.rh, nullptr, nullptr, p.mesh, p.N, p.eps, p.U, s);
                 // the rate kernels read each eigenvector contiguously
                 HIPCHK(h, launch_transpose_batch(p.U, p.N, p.nW, s));
@@ -532,9 +532,12 @@ phoebe_status phoebe_gpu_batched_plan(void* handle, const phoebe_system* systems
                 P->n_tasks_shape[sh] += p.states * p.n_qtiles;
             }
         P->n_tasks = (int)tasks.size();
+        // (each take below starts on a 256-byte boundary: two per graph system, four more)
+        size_t n_takes = 4;
+        for (auto& p : P->sp) n_takes += in_graph(p) ? 2 : 0;
         const size_t run_bytes = f_total * sizeof(cf) + part_total * sizeof(double) +
                                  (size_t)n_sys * sizeof(SysDesc) + tasks.size() * sizeof(BTask) +
-                                 (size_t)g_max * sizeof(cf) + 16 * 256;
+                                 (size_t)g_max * sizeof(cf) + (n_takes + 1) * 256;
         if (P->mem_bytes + run_bytes > h->budget) {
             set_err(h, "batched plan needs %zu bytes, over the budget", P->mem_bytes + run_bytes);
             throw Fail{PHOEBE_E_NOMEM};
@@ -561,7 +564,7 @@ phoebe_status phoebe_gpu_batched_plan(void* handle, const phoebe_system* systems
             mv(p.st_row); mv(p.st_band); mv(p.st_kmesh); mv(p.st_mlo); mv(p.st_mhi); mv(p.P1);
             mv(p.gamma);
         }
-        Arena rar(P->mem + P->mem_bytes);
+        Arena rar(P->mem + P->mem_bytes, run_bytes);
         P->mem_bytes += run_bytes;
         for (auto& p : P->sp) {
             if (!in_graph(p)) continue;
