@@ -570,8 +570,7 @@ phoebe_status phoebe_gpu_set_check_finite(void *handle, int enable);
  * three per-axis factors on a full mesh, so the sum is taken one axis at a
  * time over the box [-rmax, rmax]^3 holding the Rp list (zero where the list
  * has no vector); the result is the same sum up to the order of additions.
- * Needs FP64 or FP32, the full q mesh, |Rp components| <= 15, nW <= 32 (16
- * with the polar or adaptive terms and for phoebe_gpu_phonon_linewidth),
+ * Needs FP64 or FP32, the full q mesh, |Rp components| <= 15, nW <= 32,
  * nModes <= 32, N0 <= 1024 and N1*N2 <= 65535.
  * AUTO (the default) takes FACTORED where it applies and the box width is at
  * most half the number of Rp vectors (the sum over Re is then factorised the

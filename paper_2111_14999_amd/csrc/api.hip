@@ -408,16 +408,13 @@ static phoebe_status scatter_rates_impl(void* handle, const phoebe_system* sys,
         const int Wbox = 2 * rmax_p + 1;
         const int nc_line = line_rates_ncpad(nm, nW);
         const int64_t NL = (int64_t)mesh.n1 * mesh.n2;
-        // (16 < nW <= 32: the plain rates; the extension terms need nW <= 16)
         const bool can_factor = (prec == PHOEBE_FP64 || prec == PHOEBE_FP32) && q_off == nullptr &&
                                 Wbox <= 31 && nc_line > 0 && NL <= 65535 && mesh.n0 <= 1024 &&
-                                (nW <= 16 || !ext) &&
                                 line_rates_lds(Wbox, mesh.n0, nm, lowp, lw_out != nullptr) <=
                                     64 * 1024;
         if (h->mesh_sum == PHOEBE_MESH_SUM_FACTORED && !can_factor) {
             set_err(h, "the factorised mesh sum needs FP64 or FP32, the full q mesh, |Rp| <= 15, "
-                       "nW <= 32 (16 with linewidth, polar or adaptive terms), nModes <= 32, "
-                       "N0 <= 1024 and N1*N2 <= 65535");
+                       "nW <= 32, nModes <= 32, N0 <= 1024 and N1*N2 <= 65535");
             throw Fail{PHOEBE_E_UNSUPPORTED};
         }
         HIPCHK(h, hipSetDevice(h->device));

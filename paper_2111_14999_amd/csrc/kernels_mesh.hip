@@ -865,7 +865,8 @@ constexpr int kTP = 2;  // column tiles per MFMA pass
 constexpr int kLineLW = 1, kLinePol = 2, kLineVel = 4;
 template <int FEAT, int H, bool F64>
 constexpr int line_waves_per_simd() {
-    return (H == 2 && F64) ? 3 : (FEAT == 0 || FEAT == kLineLW ? 4 : 3);
+    if (H == 2 && F64) return FEAT == 0 || FEAT == kLineLW ? 3 : 2;
+    return FEAT == 0 || FEAT == kLineLW ? 4 : 3;
 }
 
 // H: column tiles per mode, 1 (nW <= 16: column sa*16 + b) or 2 (nW <= 32: column
@@ -873,8 +874,8 @@ constexpr int line_waves_per_simd() {
 template <int TN, int KS, class C, int FEAT, int H = 1>
 __global__ __launch_bounds__(256, (line_waves_per_simd<FEAT, H, sizeof(C) == sizeof(cd)>())) void
 line_rates_kernel(RateArgs a) {
-    static_assert(H == 1 || (H == 2 && FEAT == 0 && TN % 2 == 0 && kTP == 2),
-                  "two tiles per mode: plain rates, whole modes per wave and per pass");
+    static_assert(H == 1 || (H == 2 && TN % 2 == 0 && kTP == 2),
+                  "two tiles per mode: whole modes per wave and per pass");
     constexpr bool LW = FEAT & kLineLW, POL = FEAT & kLinePol, VEL = FEAT & kLineVel;
     using R = decltype(C::x);
     constexpr bool F64 = sizeof(R) == 8;
@@ -927,14 +928,16 @@ line_rates_kernel(RateArgs a) {
     // FP64 subnormal, so such a Gaussian is exactly 0
     const double cut = 27.5 * a.sigma;
     // per-state values of the extensions: U_k column n (lane rows 4 lg + v), v_nk, f (1 - f) / kT
-    cd ukn[4] = {};
+    cd ukn[4 * H] = {};
     double vn[3] = {0.0, 0.0, 0.0};
     double mdf = 0.0;
     if constexpr (POL || VEL || LW) {
         if (POL && a.Lpol) {
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-                if (4 * lg + v < nW) ukn[v] = a.U[((int64_t)kmesh * nW + nband) * nW + 4 * lg + v];
+                for (int h = 0; h < H; ++h)
+                    if (16 * h + 4 * lg + v < nW)
+                        ukn[4 * h + v] = a.U[((int64_t)kmesh * nW + nband) * nW + 16 * h + 4 * lg + v];
         }
         if (VEL && a.vel)
             for (int d = 0; d < 3; ++d) vn[d] = a.vel[((int64_t)kmesh * nW + nband) * 3 + d];
@@ -1169,7 +1172,8 @@ line_rates_kernel(RateArgs a) {
                 if (a.Lpol) {  // O at point li: sum over the lane's four b, then over the rows
                     cd o = {0.0, 0.0};
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) o = cfmac(ukn[v], cd{(double)d.u[v].x, (double)d.u[v].y}, o);
+                    for (int v = 0; v < 4 * H; ++v)
+                        o = cfmac(ukn[v], cd{(double)d.u[v].x, (double)d.u[v].y}, o);
                     o.x += __shfl_xor(o.x, 16, 64);
                     o.y += __shfl_xor(o.y, 16, 64);
                     o.x += __shfl_xor(o.x, 32, 64);
@@ -1281,15 +1285,30 @@ static hipError_t line_rates(const RateArgs& a, int nst, hipStream_t s) {
         }
     };
     using std::integral_constant;
-    if (a.nW > 16) {  // two tiles per mode: the plain rates only
-        if (feat) return hipErrorInvalidValue;
+    if (a.nW > 16) {  // two tiles per mode
+        auto with_feat2 = [&](auto tn, auto ks) -> hipError_t {
+            constexpr int TN = decltype(tn)::value, KS = decltype(ks)::value;
+            if constexpr (sizeof(C) == sizeof(cd)) {
+                switch (feat) {
+                    case 0: return go_line<TN, KS, C, 0, 2>(a, nst, s);
+                    case kLineLW: return go_line<TN, KS, C, kLineLW, 2>(a, nst, s);
+                    case kLinePol: return go_line<TN, KS, C, kLinePol, 2>(a, nst, s);
+                    case kLineVel: return go_line<TN, KS, C, kLineVel, 2>(a, nst, s);
+                    default: return go_line<TN, KS, C, kLineLW | kLinePol | kLineVel, 2>(a, nst, s);
+                }
+            } else {
+                return go_line<TN, KS, C, 0, 2>(a, nst, s);
+            }
+        };
         switch (a.nc_pad / 64) {
-            case 2: return pre ? go_line<2, 2, C, 0, 2>(a, nst, s) : go_line<2, 0, C, 0, 2>(a, nst, s);
-            case 4: return pre ? go_line<4, 2, C, 0, 2>(a, nst, s) : go_line<4, 0, C, 0, 2>(a, nst, s);
-            case 6: return go_line<6, 0, C, 0, 2>(a, nst, s);
-            case 8: return go_line<8, 0, C, 0, 2>(a, nst, s);
-            case 12: return go_line<12, 0, C, 0, 2>(a, nst, s);
-            case 16: return go_line<16, 0, C, 0, 2>(a, nst, s);
+            case 2: return pre ? with_feat2(integral_constant<int, 2>{}, integral_constant<int, 2>{})
+                               : with_feat2(integral_constant<int, 2>{}, integral_constant<int, 0>{});
+            case 4: return pre ? with_feat2(integral_constant<int, 4>{}, integral_constant<int, 2>{})
+                               : with_feat2(integral_constant<int, 4>{}, integral_constant<int, 0>{});
+            case 6: return with_feat2(integral_constant<int, 6>{}, integral_constant<int, 0>{});
+            case 8: return with_feat2(integral_constant<int, 8>{}, integral_constant<int, 0>{});
+            case 12: return with_feat2(integral_constant<int, 12>{}, integral_constant<int, 0>{});
+            case 16: return with_feat2(integral_constant<int, 16>{}, integral_constant<int, 0>{});
             default: return hipErrorInvalidValue;
         }
     }

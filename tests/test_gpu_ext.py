@@ -57,9 +57,10 @@ def _lw(lib, ds, mesh, par, nm):
 # ---------------------------------------------------------------------------
 # phonon linewidth
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("case", ["toy", "nW5-3x4x5", "nW16-2x3x4"])
+@pytest.mark.parametrize("case", ["toy", "nW5-3x4x5", "nW16-2x3x4", "nW20-3x3x4"])
 @pytest.mark.parametrize("form", ["direct", "factored"])
 def test_linewidth_matches_oracle(lib, case, form):
+    """nW20: the factorised form's two column tiles per mode."""
     from paper_2111_14999_amd import DeviceSystem
     if case == "toy":
         s = synth.config_c1()
@@ -69,8 +70,9 @@ def test_linewidth_matches_oracle(lib, case, form):
                    win_hi=p["win_hi"], omega_min=p["omega_min"])
         t = rates.mesh_tables(s, mesh)
     else:
-        nW, mesh = (5, (3, 4, 5)) if case == "nW5-3x4x5" else (16, (2, 3, 4))
-        s = synth.small_system(81, n_wannier=nW, n_atoms=2 if nW == 5 else 5, r=1)
+        nW, mesh = {"nW5-3x4x5": (5, (3, 4, 5)), "nW16-2x3x4": (16, (2, 3, 4)),
+                    "nW20-3x3x4": (20, (3, 3, 4))}[case]
+        s = synth.small_system(81, n_wannier=nW, n_atoms=5 if nW == 16 else 2, r=1)
         s.h_r *= 0.3
         t, par = _params(s, mesh)
     print(f"[linewidth {case} {form}] mesh {mesh}", flush=True)
@@ -170,10 +172,12 @@ def test_polar_coupling_matches_oracle(lib):
 
 
 @pytest.mark.parametrize("form", ["direct", "factored"])
-def test_polar_rates_match_oracle(lib, form):
+@pytest.mark.parametrize("nW", [5, 20])
+def test_polar_rates_match_oracle(lib, form, nW):
+    """nW 20: the factorised form's two column tiles per mode (the overlap over both)."""
     torch = torch_cuda()
     from paper_2111_14999_amd import DeviceSystem
-    s = _polar_system(93, nW=5, nat=2)
+    s = _polar_system(93, nW=nW, nat=2)
     mesh = (3, 4, 4)
     t, par = _params(s, mesh)
     ref = rates.scattering_rates(s, mesh, tables=t, **par)
@@ -193,11 +197,11 @@ def test_polar_rates_match_oracle(lib, form):
     refP = linewidth.phonon_linewidth(s, mesh, tables=t, **par)["P"]
     mp, _, _ = rel_err(P.cpu().numpy(), refP)
     # the polar term matters here: the rates without it differ
-    s0 = synth.small_system(93, n_wannier=5, n_atoms=2, r=1)
+    s0 = synth.small_system(93, n_wannier=nW, n_atoms=2, r=1)
     s0.h_r *= 0.3
     plain = rates.scattering_rates(s0, mesh, tables=t, **par)["gamma"]
     diff, _, _ = rel_err(plain, ref["gamma"])
-    print(f"[polar rates {form}] Gamma err {mx:.2e} (median {med:.2e}), P err {mp:.2e}; "
+    print(f"[polar rates {form} nW {nW}] Gamma err {mx:.2e} (median {med:.2e}), P err {mp:.2e}; "
           f"without the polar term {diff:.2e}", flush=True)
     assert diff > 1e-3
     assert mx < P_BOUND and mp < P_BOUND
@@ -255,10 +259,11 @@ def test_velocities_degenerate_pair(lib):
 
 
 @pytest.mark.parametrize("form", ["direct", "factored"])
-def test_adaptive_rates_and_linewidth_match_oracle(lib, form):
+@pytest.mark.parametrize("nW", [5, 20])
+def test_adaptive_rates_and_linewidth_match_oracle(lib, form, nW):
     torch = torch_cuda()
     from paper_2111_14999_amd import DeviceSystem
-    s = synth.small_system(94, n_wannier=5, n_atoms=2, r=1)
+    s = synth.small_system(94, n_wannier=nW, n_atoms=2, r=1)
     s.h_r *= 0.3
     mesh = (4, 3, 4)
     t, par = _params(s, mesh, sigma=0.02)
@@ -282,7 +287,7 @@ def test_adaptive_rates_and_linewidth_match_oracle(lib, form):
     mp, _, _ = rel_err(P.cpu().numpy(), refP)
     fixed = rates.scattering_rates(s, mesh, tables=t, **par)["gamma"]
     diff, _, _ = rel_err(fixed, ref["gamma"])
-    print(f"[adaptive {form}] Gamma err {mx:.2e} (median {med:.2e}), P err {mp:.2e}; "
+    print(f"[adaptive {form} nW {nW}] Gamma err {mx:.2e} (median {med:.2e}), P err {mp:.2e}; "
           f"fixed width differs by {diff:.2e}", flush=True)
     assert diff > 1e-3
     assert mx < P_BOUND and mp < P_BOUND
