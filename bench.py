@@ -263,25 +263,38 @@ def main():
                       note=f"compulsory: g(Re,Rp) once ({g_bytes:.3e} B) + tables once; the rest "
                            f"are the factorised sums' intermediates ({ew:.0f}-byte elements)")
 
-    # interp_g element rate (all (nu, n, m) of nk kept k x the full q mesh)
+    # g(k,q) element rate: all (nu, n, m) of nk kept k x the full q mesh, by
+    # phoebe_gpu_interp_g_mesh (the sum over Rp axis by axis) and, for reference, by
+    # phoebe_gpu_interp_g with the mesh as a q list (the dense contraction over Rp)
     gel = None
+    gel_list = None
     gerr = None
     if args.interp_k > 0 and n_kept > 0:
         kf = torch.from_numpy(mesh_points_frac(mesh, kidx[:args.interp_k])).cuda()
         qf = torch.from_numpy(mesh_points_frac(mesh, np.arange(N))).cuda()
         nk_i = kf.shape[0]
         gout = torch.empty((nk_i, N, nm, nW, nW), dtype=torch.complex128, device="cuda")
-        lib.interp_g(ds, kf, qf, gout, omega_min=par["omega_min"], precision=args.precision)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        lib.interp_g(ds, kf, qf, gout, omega_min=par["omega_min"], precision=args.precision)
-        torch.cuda.synchronize()
-        ti = time.perf_counter() - t1
+
+        def timed(call):
+            call()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            call()
+            torch.cuda.synchronize()
+            return time.perf_counter() - t1
+
+        ti_l = timed(lambda: lib.interp_g(ds, kf, qf, gout, omega_min=par["omega_min"],
+                                          precision=args.precision))
+        gel_list = nk_i * N * nm * nW * nW / ti_l
+        ti = timed(lambda: lib.interp_g_mesh(ds, kf, mesh, gout, omega_min=par["omega_min"],
+                                             precision=args.precision))
         gel = nk_i * N * nm * nW * nW / ti
-        log(f"interp_g: {nk_i} k x {N} q in {ti * 1e3:.1f} ms = {gel:.3e} elements/s")
+        log(f"interp_g_mesh: {nk_i} k x {N} q in {ti * 1e3:.1f} ms = {gel:.3e} elements/s "
+            f"(interp_g with the mesh as a q list: {ti_l * 1e3:.1f} ms, {gel_list:.3e}/s)")
         if not args.no_cpu_baseline:
             gerr = interp_error(s, kf.cpu().numpy(), qf.cpu().numpy(), gout, n_q=16)
-            log(f"interp_g vs oracle on {gerr['sample']}: |g|^2 err / pair max {gerr['max']:.3e}")
+            log(f"interp_g_mesh vs oracle on {gerr['sample']}: |g|^2 err / pair max "
+                f"{gerr['max']:.3e}")
         del gout
 
     # oracle on a bounded sample: error of the GPU result and the CPU baseline rate
@@ -377,6 +390,7 @@ def main():
             "kept_k": n_kept, "states": n_states, "q_points": N,
         },
         "g_elements_per_s": gel,
+        "g_elements_per_s_list_form": gel_list,
         "g_err_vs_oracle": gerr,
         "err_vs_oracle": err,
         "roofline": roofline,

@@ -191,6 +191,24 @@ phoebe_status phoebe_gpu_interp_g(void *handle, const phoebe_system *sys,
                                   phoebe_c128 *g_out, double *eps_k, double *eps_kq,
                                   double *omega_q, void *stream);
 
+/* phoebe_gpu_interp_g with the q list the full mesh q_mesh (host [3]): the
+ * nq = N0 N1 N2 points q = (i0/N0, i1/N1, i2/N2) in linear order
+ * (i0 N1 + i1) N2 + i2; g_out, eps_kq and omega_q are indexed by that order.
+ * On the mesh the phase e^{i 2 pi q.Rp} is a product of three per-axis factors
+ * (the Electron Properties interpolation of g, applied one lattice axis at a
+ * time as for phoebe_gpu_scatter_rates' factorised sums), so in FP64 and FP32,
+ * where the Rp box [-rmax, rmax]^3 is at most 31 wide and at most half as wide
+ * as the Rp count, the sum over Rp is taken axis by axis; the result is the same
+ * sum up to the order of the additions.  Otherwise (split-BF16, other Rp lists)
+ * it is the dense contraction of phoebe_gpu_interp_g.
+ * Errors as phoebe_gpu_interp_g; PHOEBE_E_INVALID for q_mesh NULL or below 1. */
+phoebe_status phoebe_gpu_interp_g_mesh(void *handle, const phoebe_system *sys,
+                                       const double *k_frac, int64_t nk,
+                                       const int32_t q_mesh[3], double omega_min,
+                                       phoebe_precision prec, phoebe_c128 *g_out,
+                                       double *eps_k, double *eps_kq, double *omega_q,
+                                       void *stream);
+
 /* Scattering rates Gamma_nk = hbar/tau_nk on a uniform mesh (Transport
  * Methods, electron lifetime; Gaussian smearing; energy window):
  *   Gamma_nk = 2 pi sum_q w_q sum_m sum_nu |g_{nu n m}(k,q)|^2

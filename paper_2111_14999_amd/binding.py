@@ -41,7 +41,7 @@ EXPORTS = (
     "phoebe_gpu_mlp_init", "phoebe_gpu_training_set", "phoebe_gpu_gather_rows",
     "phoebe_gpu_set_check_finite", "phoebe_gpu_scatter_rates_noalloc",
     "phoebe_gpu_noalloc_scratch_bytes", "phoebe_gpu_set_table_cache",
-    "phoebe_gpu_set_fault_injection",
+    "phoebe_gpu_set_fault_injection", "phoebe_gpu_interp_g_mesh",
 )
 
 SMEARING = {"gaussian": 0, "adaptive": 1}
@@ -118,6 +118,9 @@ def load(path: str = LIB_PATH):
     lib.phoebe_gpu_phonon_modes.argtypes = [vp, ctypes.POINTER(CSystem), vp, i64, vp, vp, vp]
     lib.phoebe_gpu_interp_g.argtypes = [vp, ctypes.POINTER(CSystem), vp, i64, vp, i64,
                                         ctypes.c_double, ctypes.c_int, vp, vp, vp, vp, vp]
+    lib.phoebe_gpu_interp_g_mesh.argtypes = [vp, ctypes.POINTER(CSystem), vp, i64,
+                                             ctypes.POINTER(i32), ctypes.c_double, i32, vp, vp,
+                                             vp, vp, vp]
     lib.phoebe_gpu_scatter_rates.argtypes = [vp, ctypes.POINTER(CSystem),
                                              ctypes.POINTER(i32), ctypes.POINTER(i32), vp, i64,
                                              vp, vp, vp, ctypes.POINTER(CRateParams), ctypes.c_int,
@@ -362,6 +365,16 @@ class Library:
             self.handle, ctypes.byref(c), _ptr(k_frac), k_frac.shape[0], _ptr(q_frac),
             q_frac.shape[0], float(omega_min), PRECISIONS[precision], _ptr(g_out),
             _ptr(eps_k), _ptr(eps_kq), _ptr(omega_q), _stream(stream)))
+
+    def interp_g_mesh(self, sys: DeviceSystem, k_frac, q_mesh, g_out, omega_min=1e-4,
+                      precision="fp64", eps_k=None, eps_kq=None, omega_q=None, stream=None):
+        """interp_g with q the full mesh q_mesh in linear order."""
+        c = sys.c_struct()
+        m = (ctypes.c_int32 * 3)(*[int(x) for x in q_mesh])
+        self._check(self.lib.phoebe_gpu_interp_g_mesh(
+            self.handle, ctypes.byref(c), _ptr(k_frac), k_frac.shape[0], m, float(omega_min),
+            PRECISIONS[precision], _ptr(g_out), _ptr(eps_k), _ptr(eps_kq), _ptr(omega_q),
+            _stream(stream)))
 
     # -- rates --------------------------------------------------------------
     def scatter_rates(self, sys: DeviceSystem, mesh, params: dict, gamma_out, k_idx=None,

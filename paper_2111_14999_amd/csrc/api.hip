@@ -187,20 +187,35 @@ phoebe_status phoebe_gpu_phonon_modes(void* handle, const phoebe_system* sys,
     });
 }
 
-phoebe_status phoebe_gpu_interp_g(void* handle, const phoebe_system* sys, const double* k_frac,
-                                  int64_t nk, const double* q_frac, int64_t nq, double omega_min,
-                                  phoebe_precision prec, phoebe_c128* g_out, double* eps_k,
-                                  double* eps_kq, double* omega_q, void* stream) {
-    if (!handle) return PHOEBE_E_INVALID;
-    Handle* h = static_cast<Handle*>(handle);
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    return run(h, __func__, [&] {
+}  // extern "C"
+
+namespace {
+
+// Interpolated g for every (k, q) pair: q_frac (device) a list of nq points, or
+// q_frac = NULL and q_mesh (host) the full mesh, nq = N0 N1 N2 points in linear
+// order.  On the mesh, FP64 and FP32, where the Rp box is at most half as wide as
+// the Rp count, the sum over Rp is taken one axis at a time (the first two by the
+// rate path's axis transforms, the last written out row by row): the same sum
+// up to the order of the additions, without the dense contraction over Rp.
+phoebe_status interp_g_impl(Handle* h, const phoebe_system* sys, const double* k_frac,
+                            int64_t nk, const double* q_frac_in, int64_t nq,
+                            const int32_t* q_mesh, double omega_min, phoebe_precision prec,
+                            phoebe_c128* g_out, double* eps_k, double* eps_kq, double* omega_q,
+                            hipStream_t s, const char* name) {
+    return run(h, name, [&] {
         check_system(h, sys, true, true, true);
         REQUIRE(h, nk >= 0 && nq >= 0, "negative nk or nq");
         REQUIRE(h, prec >= PHOEBE_FP64 && prec <= PHOEBE_BF16X6, "precision enum out of range");
         REQUIRE(h, std::isfinite(omega_min) && omega_min >= 0.0, "omega_min must be >= 0");
+        Mesh qm{1, 1, 1};
+        if (q_mesh) {
+            REQUIRE(h, q_mesh[0] >= 1 && q_mesh[1] >= 1 && q_mesh[2] >= 1, "q_mesh must be >= 1");
+            qm = Mesh{q_mesh[0], q_mesh[1], q_mesh[2]};
+            REQUIRE(h, (int64_t)qm.n0 * qm.n1 * qm.n2 <= (int64_t)1 << 26, "q mesh too large");
+            nq = (int64_t)qm.n0 * qm.n1 * qm.n2;
+        }
         if (nk == 0 || nq == 0) return;
-        REQUIRE(h, k_frac && q_frac && g_out, "k_frac/q_frac/g_out is NULL");
+        REQUIRE(h, k_frac && (q_frac_in || q_mesh) && g_out, "k_frac/q_frac/g_out is NULL");
         REQUIRE(h, nk * nq <= 4000000, "nk * nq above 4e6 pairs: split the call");
         const int nW = sys->n_wannier, nm = 3 * sys->n_atoms;
         if (nW > 32 || nm > 32) {
@@ -216,13 +231,47 @@ phoebe_status phoebe_gpu_interp_g(void* handle, const phoebe_system* sys, const 
         const int n_re = sys->n_re, n_rp = sys->n_rp;
         const int64_t NC3 = (int64_t)nm * nW * nW;
         const int64_t npair = nk * nq;
-        const int64_t qchunk = std::min<int64_t>(nq, 65536);
         const int64_t kb = std::min<int64_t>(nk, 64);
+        // factorised sum over Rp on the mesh (see above)
+        const int rmax_p = rmax_of(sys->rp, n_rp);
+        const int Wbox = 2 * rmax_p + 1;
+        const bool fact = q_mesh && (prec == PHOEBE_FP64 || prec == PHOEBE_FP32) && Wbox <= 31 &&
+                          2 * Wbox <= n_rp;
+        const int64_t NL = (int64_t)qm.n1 * qm.n2;
+        const int64_t ncp = (NC3 + 63) / 64 * 64;  // F and T columns, 64-wide blocks
+        const bool axes_fused = fact && axis_transforms_fused(rmax_p, (int)ncp, lowp);
+        // q rows per rotation chunk (whole q0 planes on the mesh)
+        const int64_t planes = fact ? std::max<int64_t>(1, 65536 / NL) : 0;
+        const int64_t qchunk = fact ? std::min<int64_t>(nq, planes * NL) : std::min<int64_t>(nq, 65536);
+        std::vector<double> qf_h;
+        std::vector<int32_t> box;
+        if (q_mesh) {
+            qf_h.resize((size_t)nq * 3);
+            for (int64_t q = 0; q < nq; ++q) {
+                int i0, i1, i2;
+                mesh_triple(q, qm, i0, i1, i2);
+                qf_h[3 * q] = (double)i0 / qm.n0;
+                qf_h[3 * q + 1] = (double)i1 / qm.n1;
+                qf_h[3 * q + 2] = (double)i2 / qm.n2;
+            }
+        }
+        if (fact) {
+            box.assign((size_t)Wbox * Wbox * Wbox, -1);
+            for (int i = 0; i < n_rp; ++i) {
+                const int64_t b = ((int64_t)(sys->rp[3 * i] + rmax_p) * Wbox +
+                                   (sys->rp[3 * i + 1] + rmax_p)) * Wbox +
+                                  (sys->rp[3 * i + 2] + rmax_p);
+                REQUIRE(h, box[b] < 0, "Rp list holds a vector twice");
+                box[b] = i;
+            }
+        }
         auto plan = [&](Arena& ar) {
             int32_t* rh = upload_r(h, ar, sys->rh, sys->n_rh, s);
             int32_t* rd = upload_r(h, ar, sys->rd, sys->n_rd, s);
             int32_t* re = upload_r(h, ar, sys->re, n_re, s);
             int32_t* rp = upload_r(h, ar, sys->rp, n_rp, s);
+            double* qfd = q_mesh ? ar.take<double>((size_t)nq * 3) : nullptr;
+            const double* q_frac = q_mesh ? qfd : q_frac_in;
             double* ek = eps_k ? eps_k : ar.take<double>((size_t)nk * nW);
             cd* Uk = ar.take<cd>((size_t)nk * nW * nW);
             double* ekq = eps_kq ? eps_kq : ar.take<double>((size_t)npair * nW);
@@ -232,11 +281,20 @@ phoebe_status phoebe_gpu_interp_g(void* handle, const phoebe_system* sys, const 
             cd* E = ar.take<cd>((size_t)nq * nm * nm);
             cd* Pe = ar.take<cd>((size_t)kb * n_re);
             char* G1 = ar.take<char>((size_t)kb * n_rp * NC3 * el);
-            cd* Pp = ar.take<cd>((size_t)nq * n_rp);
-            char* F = ar.take<char>((size_t)n_rp * NC3 * el);
+            cd* Pp = fact ? nullptr : ar.take<cd>((size_t)nq * n_rp);
+            char* F = ar.take<char>((size_t)n_rp * (fact ? ncp : NC3) * el);
             char* X = ar.take<char>((size_t)qchunk * NC3 * el);
             cd* Lq = polar ? ar.take<cd>((size_t)nq * nm) : nullptr;
             double* born = polar ? ar.take<double>((size_t)9 * sys->n_atoms) : nullptr;
+            int32_t* box_d = fact ? ar.take<int32_t>(box.size()) : nullptr;
+            cd* Pax = fact ? ar.take<cd>((size_t)(qm.n0 + qm.n1 + qm.n2) * Wbox) : nullptr;
+            uint32_t* all_lines = fact ? ar.take<uint32_t>((size_t)NL) : nullptr;
+            char* T1 = fact && !axes_fused ? ar.take<char>((size_t)Wbox * Wbox * qm.n2 * ncp * el)
+                                           : nullptr;
+            char* T2 = fact ? ar.take<char>((size_t)Wbox * NL * ncp * el) : nullptr;
+            if (ar.base && q_mesh)
+                HIPCHK(h, hipMemcpyAsync(qfd, qf_h.data(), sizeof(double) * qf_h.size(),
+                                         hipMemcpyHostToDevice, s));
             {
                 Arena sub = ar;  // band scratch, reused after the tables are built
                 electron_bands_dev(h, sub, sys, rh, k_frac, nullptr, Mesh{1, 1, 1}, nk, ek, Uk, s);
@@ -256,7 +314,16 @@ phoebe_status phoebe_gpu_interp_g(void* handle, const phoebe_system* sys, const 
                 HIPCHK(h, launch_polar_factor(q_frac, Mesh{1, 1, 1}, nq, E, nm, polar_dev(sys, born),
                                               Lq, s));
             }
-            HIPCHK(h, launch_phase_table(q_frac, nullptr, Mesh{1, 1, 1}, nq, rp, n_rp, Pp, n_rp, s));
+            if (fact) {
+                HIPCHK(h, hipMemcpyAsync(box_d, box.data(), sizeof(int32_t) * box.size(),
+                                         hipMemcpyHostToDevice, s));
+                HIPCHK(h, launch_axis_phases(qm, rmax_p, Pax, s));
+                HIPCHK(h, hipMemsetAsync(all_lines, 0xFF, sizeof(uint32_t) * NL, s));  // every line
+                // the columns beyond nModes nW^2 stay zero (the fold writes the others)
+                if (ncp > NC3) HIPCHK(h, launch_zero(F, (size_t)n_rp * ncp * el, s));
+            } else {
+                HIPCHK(h, launch_phase_table(q_frac, nullptr, Mesh{1, 1, 1}, nq, rp, n_rp, Pp, n_rp, s));
+            }
             for (int64_t k0 = 0; k0 < nk; k0 += kb) {
                 const int64_t nb = std::min(kb, nk - k0);
                 HIPCHK(h, launch_phase_table(k_frac + 3 * k0, nullptr, Mesh{1, 1, 1}, nb, re, n_re,
@@ -273,33 +340,62 @@ phoebe_status phoebe_gpu_interp_g(void* handle, const phoebe_system* sys, const 
                 t1.done();
                 for (int64_t i = 0; i < nb; ++i) {
                     const int64_t k = k0 + i;
+                    const int64_t ldf = fact ? ncp : NC3;
                     if (lowp)
                         HIPCHK(h, launch_fold_all_lp(reinterpret_cast<const cf*>(G1) + i * n_rp * NC3,
                                                      Uk + k * nW * nW, n_rp, nm, nW,
-                                                     reinterpret_cast<cf*>(F), s));
+                                                     reinterpret_cast<cf*>(F), s, ldf));
                     else
                         HIPCHK(h, launch_fold_all(reinterpret_cast<const cd*>(G1) + i * n_rp * NC3,
                                                   Uk + k * nW * nW, n_rp, nm, nW,
-                                                  reinterpret_cast<cd*>(F), s));
+                                                  reinterpret_cast<cd*>(F), s, ldf));
+                    if (fact) {  // first two Rp axes for every line of the mesh
+                        Timer ta(h, s, "interp_axes");
+                        if (lowp)
+                            HIPCHK(h, launch_axis_transforms_f32(
+                                          reinterpret_cast<const cf*>(F), n_rp, (int)ncp, box_d,
+                                          rmax_p, qm, Pax, 1, all_lines, reinterpret_cast<cf*>(T1),
+                                          reinterpret_cast<cf*>(T2), s));
+                        else
+                            HIPCHK(h, launch_axis_transforms(
+                                          reinterpret_cast<const cd*>(F), n_rp, (int)ncp, box_d,
+                                          rmax_p, qm, Pax, 1, all_lines, reinterpret_cast<cd*>(T1),
+                                          reinterpret_cast<cd*>(T2), s));
+                        ta.done();
+                    }
                     for (int64_t q0 = 0; q0 < nq; q0 += qchunk) {
                         const int64_t nqc = std::min(qchunk, nq - q0);
                         cd* gk = reinterpret_cast<cd*>(g_out) + (k * nq + q0) * NC3;
-                        if (lowp) {
+                        if (fact) {  // last axis: X rows of the chunk's q0 planes
+                            Timer tx(h, s, "interp_axis0");
+                            const int pa = (int)(q0 / NL), pb = (int)((q0 + nqc) / NL);
+                            if (lowp)
+                                HIPCHK(h, launch_axis0_out_f32(reinterpret_cast<const cf*>(T2), qm,
+                                                               (int)ncp, (int)NC3, rmax_p, Pax, pa,
+                                                               pb, reinterpret_cast<cf*>(X), NC3, s));
+                            else
+                                HIPCHK(h, launch_axis0_out(reinterpret_cast<const cd*>(T2), qm,
+                                                           (int)ncp, (int)NC3, rmax_p, Pax, pa, pb,
+                                                           reinterpret_cast<cd*>(X), NC3, s));
+                            tx.done();
+                        } else if (lowp) {
                             HIPCHK(h, launch_cgemm_lp_cf(prec, Pp + q0 * n_rp, n_rp,
                                                          reinterpret_cast<const cf*>(F), NC3,
                                                          reinterpret_cast<cf*>(X), NC3, nqc, NC3,
                                                          n_rp, s));
-                            HIPCHK(h, launch_rotate_g_lp(reinterpret_cast<const cf*>(X), nqc,
-                                                         Ukq + (k * nq + q0) * nW * nW,
-                                                         E + q0 * nm * nm, nW, nm, gk, s));
                         } else {
                             HIPCHK(h, launch_zgemm(Pp + q0 * n_rp, n_rp, reinterpret_cast<const cd*>(F),
                                                    NC3, reinterpret_cast<cd*>(X), NC3, nqc, NC3, n_rp,
                                                    s));
+                        }
+                        if (lowp)
+                            HIPCHK(h, launch_rotate_g_lp(reinterpret_cast<const cf*>(X), nqc,
+                                                         Ukq + (k * nq + q0) * nW * nW,
+                                                         E + q0 * nm * nm, nW, nm, gk, s));
+                        else
                             HIPCHK(h, launch_rotate_g(reinterpret_cast<const cd*>(X), nqc,
                                                       Uk + k * nW * nW, Ukq + (k * nq + q0) * nW * nW,
                                                       E + q0 * nm * nm, nW, nm, gk, s));
-                        }
                         if (polar)  // + i L(q, nu) [U_k^dagger U_{k+q}]_{n m}
                             HIPCHK(h, launch_polar_add_g(gk, nqc, Uk + k * nW * nW,
                                                          Ukq + (k * nq + q0) * nW * nW,
@@ -317,6 +413,35 @@ phoebe_status phoebe_gpu_interp_g(void* handle, const phoebe_system* sys, const 
         HIPCHK(h, hipStreamSynchronize(s));  // host lattice lists are read before return
         flush_timing(h, s);
     });
+}
+
+}  // namespace
+
+extern "C" {
+
+phoebe_status phoebe_gpu_interp_g(void* handle, const phoebe_system* sys, const double* k_frac,
+                                  int64_t nk, const double* q_frac, int64_t nq, double omega_min,
+                                  phoebe_precision prec, phoebe_c128* g_out, double* eps_k,
+                                  double* eps_kq, double* omega_q, void* stream) {
+    if (!handle) return PHOEBE_E_INVALID;
+    return interp_g_impl(static_cast<Handle*>(handle), sys, k_frac, nk, q_frac, nq, nullptr,
+                         omega_min, prec, g_out, eps_k, eps_kq, omega_q,
+                         static_cast<hipStream_t>(stream), __func__);
+}
+
+phoebe_status phoebe_gpu_interp_g_mesh(void* handle, const phoebe_system* sys,
+                                       const double* k_frac, int64_t nk, const int32_t q_mesh[3],
+                                       double omega_min, phoebe_precision prec, phoebe_c128* g_out,
+                                       double* eps_k, double* eps_kq, double* omega_q,
+                                       void* stream) {
+    if (!handle) return PHOEBE_E_INVALID;
+    Handle* h = static_cast<Handle*>(handle);
+    if (!q_mesh) {
+        h->err = "q_mesh is NULL";
+        return PHOEBE_E_INVALID;
+    }
+    return interp_g_impl(h, sys, k_frac, nk, nullptr, 0, q_mesh, omega_min, prec, g_out, eps_k,
+                         eps_kq, omega_q, static_cast<hipStream_t>(stream), __func__);
 }
 
 }  // extern "C"

@@ -125,6 +125,12 @@ bool axis_transforms_fused(int rmax, int nc_pad, bool f32);
 hipError_t launch_axis_transforms_f32(const cf* F, int rp_pad, int nc_pad, const int32_t* box_rp,
                                       int rmax, Mesh m, const cd* P, int nst,
                                       const uint32_t* line_any, cf* T1, cf* T2, hipStream_t s);
+// The last axis written out for q0 in [q0a, q0b) of one T2 [W, N1*N2, nc_pad]:
+// X [(q0 - q0a) N1 N2 + line, c] (rows ldx apart, c < nc); P as for the transforms.
+hipError_t launch_axis0_out(const cd* T2, Mesh m, int nc_pad, int nc, int rmax, const cd* P,
+                            int q0a, int q0b, cd* X, int64_t ldx, hipStream_t s);
+hipError_t launch_axis0_out_f32(const cf* T2, Mesh m, int nc_pad, int nc, int rmax, const cd* P,
+                                int q0a, int q0b, cf* X, int64_t ldx, hipStream_t s);
 // Stage 1 factorised over the axes of the Re box for one batch of kept k.
 // Device lists: d_k0 [d0] distinct k0; pair_k1 [d01] and pair_off [d0+1] the
 // distinct (k0, k1) pairs grouped by k0; kp_off [d01+1], k_row, k_k2 [nb] the
@@ -193,8 +199,9 @@ hipError_t launch_rotate_g(const cd* X, int64_t nq, const cd* Uk, const cd* Ukq,
                            int nW, int nm, cd* g, hipStream_t s);
 
 // fold for interp_g (all bands n): F[r, sa, n, b] = sum_a conj(U[a, n]) G[r, sa, a, b]
+// (F rows ldf elements apart; ldf < 0: nm nW^2)
 hipError_t launch_fold_all(const cd* G, const cd* U, int n_rp, int nm, int nW, cd* F,
-                           hipStream_t s);
+                           hipStream_t s, int64_t ldf = -1);
 
 hipError_t launch_gather_rows(const uint8_t* mask, const int32_t* kept, int64_t rows, int nW,
                               int32_t* rowflag, uint8_t* mask_out, int32_t* kept_out,

@@ -398,8 +398,9 @@ hipError_t launch_stage2_rates_lp(int prec, const RateArgsLP& a, int nst, hipStr
 // interp_g in reduced precision: fold (all bands) and rotation in FP32.
 // ---------------------------------------------------------------------------
 __global__ void fold_all_lp_kernel(const cf* __restrict__ G, const cd* __restrict__ U, int n_rp,
-                                   int nm, int nW, cf* __restrict__ F) {
-    const int64_t total = (int64_t)n_rp * nm * nW * nW;
+                                   int nm, int nW, cf* __restrict__ F, int64_t ldf) {
+    const int64_t nc = (int64_t)nm * nW * nW;
+    const int64_t total = (int64_t)n_rp * nc;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
         const int b = (int)(t % nW);
@@ -414,14 +415,18 @@ __global__ void fold_all_lp_kernel(const cf* __restrict__ G, const cd* __restric
             ar = fmaf(ur, g.x, fmaf(ui, g.y, ar));
             ai = fmaf(ur, g.y, fmaf(-ui, g.x, ai));
         }
-        F[t] = cf{ar, ai};
+        const int64_t r = t / nc;
+        F[r * ldf + (t - r * nc)] = cf{ar, ai};
     }
 }
 
 hipError_t launch_fold_all_lp(const cf* G, const cd* U, int n_rp, int nm, int nW, cf* F,
-                              hipStream_t s) {
-    hipLaunchKernelGGL(fold_all_lp_kernel, dim3(gridn((int64_t)n_rp * nm * nW * nW, 256)),
-                       dim3(256), 0, s, G, U, n_rp, nm, nW, F);
+                              hipStream_t s, int64_t ldf) {
+    const int64_t nc = (int64_t)nm * nW * nW;
+    if (ldf < 0) ldf = nc;
+    if (ldf < nc) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(fold_all_lp_kernel, dim3(gridn((int64_t)n_rp * nc, 256)), dim3(256), 0, s,
+                       G, U, n_rp, nm, nW, F, ldf);
     return hipGetLastError();
 }
 

@@ -256,6 +256,66 @@ static hipError_t axis_transforms(const C* F, int rp_pad, int nc_pad, const int3
     }
 }
 
+// The last axis written out, for g on the full mesh (interpolation):
+//   X[(q0 - q0a) NL + line, c] = sum_R0 P0[q0, R0] T2[R0, line, c],  q0 in [q0a, q0b),
+// X rows ldx elements apart, columns c < nc.  A thread takes one (line, c): it
+// reads its W values of T2 once and writes one value per q0 (consecutive threads,
+// consecutive c: coalesced).
+template <int WT, class C>
+__global__ __launch_bounds__(256) void axis0_out_kernel(const C* __restrict__ T2, int64_t NL,
+                                                        int nc_pad, int nc, int Wr,
+                                                        const cd* __restrict__ P0, int q0a, int q0b,
+                                                        C* __restrict__ X, int64_t ldx) {
+    constexpr int NV = WT > 0 ? WT : kMaxW;
+    const int W = WT > 0 ? WT : Wr;
+    const int64_t total = NL * nc;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t line = i / nc;
+        const int c = (int)(i - line * nc);
+        C v[NV];
+#pragma unroll
+        for (int r = 0; r < NV; ++r)
+            if (r < W) v[r] = T2[((int64_t)r * NL + line) * nc_pad + c];
+        for (int q0 = q0a; q0 < q0b; ++q0) {
+            const cd* Pq = P0 + (int64_t)q0 * W;
+            C acc = {0, 0};
+#pragma unroll
+            for (int r = 0; r < NV; ++r)
+                if (r < W) acc = cfma(to_c<C>(Pq[r]), v[r], acc);
+            X[((int64_t)(q0 - q0a) * NL + line) * ldx + c] = acc;
+        }
+    }
+}
+
+template <class C>
+static hipError_t axis0_out(const C* T2, Mesh m, int nc_pad, int nc, int rmax, const cd* P,
+                            int q0a, int q0b, C* X, int64_t ldx, hipStream_t s) {
+    const int W = 2 * rmax + 1;
+    if (W > kMaxW || nc > nc_pad || q0a < 0 || q0b > m.n0 || ldx < nc) return hipErrorInvalidValue;
+    if (q0b <= q0a) return hipSuccess;
+    const int64_t NL = (int64_t)m.n1 * m.n2;
+    const dim3 g(gridm(NL * nc, 256)), b(256);
+    switch (W) {
+        case 1: hipLaunchKernelGGL((axis0_out_kernel<1, C>), g, b, 0, s, T2, NL, nc_pad, nc, W, P, q0a, q0b, X, ldx); break;
+        case 3: hipLaunchKernelGGL((axis0_out_kernel<3, C>), g, b, 0, s, T2, NL, nc_pad, nc, W, P, q0a, q0b, X, ldx); break;
+        case 5: hipLaunchKernelGGL((axis0_out_kernel<5, C>), g, b, 0, s, T2, NL, nc_pad, nc, W, P, q0a, q0b, X, ldx); break;
+        case 7: hipLaunchKernelGGL((axis0_out_kernel<7, C>), g, b, 0, s, T2, NL, nc_pad, nc, W, P, q0a, q0b, X, ldx); break;
+        case 9: hipLaunchKernelGGL((axis0_out_kernel<9, C>), g, b, 0, s, T2, NL, nc_pad, nc, W, P, q0a, q0b, X, ldx); break;
+        default: hipLaunchKernelGGL((axis0_out_kernel<0, C>), g, b, 0, s, T2, NL, nc_pad, nc, W, P, q0a, q0b, X, ldx); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_axis0_out(const cd* T2, Mesh m, int nc_pad, int nc, int rmax, const cd* P,
+                            int q0a, int q0b, cd* X, int64_t ldx, hipStream_t s) {
+    return axis0_out<cd>(T2, m, nc_pad, nc, rmax, P, q0a, q0b, X, ldx, s);
+}
+hipError_t launch_axis0_out_f32(const cf* T2, Mesh m, int nc_pad, int nc, int rmax, const cd* P,
+                                int q0a, int q0b, cf* X, int64_t ldx, hipStream_t s) {
+    return axis0_out<cf>(T2, m, nc_pad, nc, rmax, P, q0a, q0b, X, ldx, s);
+}
+
 bool axis_transforms_fused(int rmax, int nc_pad, bool f32) {
     const int W = 2 * rmax + 1;
     const bool listed = W == 1 || W == 3 || W == 5 || W == 7 || W == 9;  // compile-time widths

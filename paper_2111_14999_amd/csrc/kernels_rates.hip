@@ -578,9 +578,11 @@ hipError_t launch_delta_weights(int nst, int64_t N, Mesh mesh, const int32_t* st
 // interp_g helpers
 // ---------------------------------------------------------------------------
 // F[r, sa, n, b] = sum_a conj(U[a, n]) G[r, sa, a, b]
+// F rows (one per Rp) are ldf elements apart (ldf >= nm nW^2)
 __global__ void fold_all_kernel(const cd* __restrict__ G, const cd* __restrict__ U, int n_rp,
-                                int nm, int nW, cd* __restrict__ F) {
-    const int64_t total = (int64_t)n_rp * nm * nW * nW;
+                                int nm, int nW, cd* __restrict__ F, int64_t ldf) {
+    const int64_t nc = (int64_t)nm * nW * nW;
+    const int64_t total = (int64_t)n_rp * nc;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
         const int b = (int)(t % nW);
@@ -589,14 +591,18 @@ __global__ void fold_all_kernel(const cd* __restrict__ G, const cd* __restrict__
         const cd* Gp = G + rs * nW * nW + b;
         cd acc = {0.0, 0.0};
         for (int a = 0; a < nW; ++a) acc = cfmac(U[a * nW + n], Gp[a * nW], acc);
-        F[t] = acc;
+        const int64_t r = t / nc;
+        F[r * ldf + (t - r * nc)] = acc;
     }
 }
 
 hipError_t launch_fold_all(const cd* G, const cd* U, int n_rp, int nm, int nW, cd* F,
-                           hipStream_t s) {
-    hipLaunchKernelGGL(fold_all_kernel, dim3(grid1((int64_t)n_rp * nm * nW * nW, 256)), dim3(256),
-                       0, s, G, U, n_rp, nm, nW, F);
+                           hipStream_t s, int64_t ldf) {
+    const int64_t nc = (int64_t)nm * nW * nW;
+    if (ldf < 0) ldf = nc;
+    if (ldf < nc) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(fold_all_kernel, dim3(grid1((int64_t)n_rp * nc, 256)), dim3(256), 0, s, G,
+                       U, n_rp, nm, nW, F, ldf);
     return hipGetLastError();
 }
 

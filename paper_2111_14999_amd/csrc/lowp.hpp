@@ -55,7 +55,7 @@ size_t stage2_lp_lds(int prec, int tq, int rmax, int rp_pad, int nc_pad, int nm,
 bool lp_stage_pays(const void* kern, size_t shm0, size_t shm1);
 int stage2_lp_config(int nm, int nW, int* tq_out, int* tn_out);
 hipError_t launch_fold_all_lp(const cf* G, const cd* U, int n_rp, int nm, int nW, cf* F,
-                              hipStream_t s);
+                              hipStream_t s, int64_t ldf = -1);
 hipError_t launch_rotate_g_lp(const cf* X, int64_t nq, const cd* Ukq, const cd* E, int nW, int nm,
                               cd* g, hipStream_t s);
 

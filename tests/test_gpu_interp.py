@@ -123,3 +123,102 @@ def test_realistic_size_bench_launch(lib):
     print("GPU done", flush=True)
     ref = coupling.coupling(k, q_all[iq], s)
     _compare(got, ref, 1e-11)
+
+
+# ---------------------------------------------------------------------------
+# phoebe_gpu_interp_g_mesh: q the full mesh, the sum over Rp axis by axis
+# ---------------------------------------------------------------------------
+def _mesh_frac(mesh, idx=None):
+    N = int(np.prod(mesh))
+    idx = np.arange(N) if idx is None else np.asarray(idx)
+    i0, r = np.divmod(idx, mesh[1] * mesh[2])
+    i1, i2 = np.divmod(r, mesh[2])
+    return np.stack([i0 / mesh[0], i1 / mesh[1], i2 / mesh[2]], axis=1)
+
+
+def _run_mesh(lib, s, k, mesh, precision="fp64", omega_min=1e-4):
+    torch = torch_cuda()
+    from paper_2111_14999_amd import DeviceSystem
+    ds = DeviceSystem.from_host(s)
+    nk, nq, nW, nm = k.shape[0], int(np.prod(mesh)), s.n_wannier, s.n_modes
+    g = torch.empty((nk, nq, nm, nW, nW), dtype=torch.complex128, device="cuda")
+    ek = torch.empty((nk, nW), dtype=torch.float64, device="cuda")
+    ekq = torch.empty((nk, nq, nW), dtype=torch.float64, device="cuda")
+    om = torch.empty((nq, nm), dtype=torch.float64, device="cuda")
+    lib.interp_g_mesh(ds, torch.from_numpy(k).cuda(), mesh, g, omega_min=omega_min,
+                      precision=precision, eps_k=ek, eps_kq=ekq, omega_q=om)
+    torch.cuda.synchronize()
+    return dict(g=g.cpu().numpy(), eps_k=ek.cpu().numpy(), eps_kq=ekq.cpu().numpy(),
+                omega_q=om.cpu().numpy())
+
+
+@pytest.mark.parametrize("nW,nat,r,mesh", [(5, 2, 2, (5, 4, 3)), (16, 5, 1, (3, 4, 5)),
+                                           (9, 1, 2, (7, 1, 2)), (20, 2, 1, (4, 3, 3))])
+def test_mesh_form_matches_oracle_and_list_form(lib, nW, nat, r, mesh):
+    """The factorised sum over Rp on a full (ragged) q mesh against the oracle, and
+    against the dense contraction of phoebe_gpu_interp_g on the same q points (the
+    same bands and modes, so g itself agrees, not only |g|^2)."""
+    s = synth.small_system(60 + nW, n_wannier=nW, n_atoms=nat, r=r)
+    rng = np.random.default_rng(nW)
+    k = rng.uniform(-1, 1, size=(3, 3))
+    q = _mesh_frac(mesh)
+    got = _run_mesh(lib, s, k, mesh)
+    ref = coupling.coupling(k, q, s)
+    _compare(got, ref, 1e-11)
+    lst = _run(lib, s, k, q)
+    scale = np.max(np.abs(lst["g"]))
+    d = np.max(np.abs(got["g"] - lst["g"]))
+    print(f"mesh form vs list form: max |dg| / max |g| = {d / scale:.2e}", flush=True)
+    assert d < 1e-12 * scale
+    assert np.array_equal(got["eps_kq"], lst["eps_kq"])
+
+
+def test_mesh_form_fp32(lib):
+    """FP32 form of the mesh interpolation against the FP64 oracle."""
+    s = synth.small_system(77, n_wannier=8, n_atoms=3, r=2)
+    mesh = (4, 5, 3)
+    k = np.random.default_rng(5).uniform(-1, 1, size=(2, 3))
+    got = _run_mesh(lib, s, k, mesh, precision="fp32")
+    ref = coupling.coupling(k, _mesh_frac(mesh), s)
+    _compare(got, ref, 1e-6)
+
+
+def test_mesh_form_argument_errors(lib):
+    torch = torch_cuda()
+    from paper_2111_14999_amd import DeviceSystem, PhoebeError
+    s = synth.small_system(78, n_wannier=3, n_atoms=1, r=1)
+    ds = DeviceSystem.from_host(s)
+    k = torch.zeros((1, 3), dtype=torch.float64, device="cuda")
+    g = torch.empty((1, 8, 3, 3, 3), dtype=torch.complex128, device="cuda")
+    with pytest.raises(PhoebeError) as e:
+        lib.interp_g_mesh(ds, k, (2, 0, 4), g)
+    assert e.value.status == -1
+
+
+def test_realistic_size_mesh_launch(lib):
+    """Realistic system (nW 16, 15 modes, 343 Re and Rp): two mesh k against the whole
+    40^3 q mesh in one phoebe_gpu_interp_g_mesh call, as bench.py times it; 64 seeded
+    q of the result against the oracle, which evaluates those pairs one by one."""
+    torch = torch_cuda()
+    from paper_2111_14999_amd import DeviceSystem
+    s = synth.config_c2()
+    mesh = (40, 40, 40)
+    N = int(np.prod(mesh))
+    rng = np.random.default_rng(31)
+    ik = np.sort(rng.choice(N, size=2, replace=False))
+    iq = np.sort(rng.choice(N, size=64, replace=False))
+    k = _mesh_frac(mesh, ik)
+    ds = DeviceSystem.from_host(s)
+    nW, nm = s.n_wannier, s.n_modes
+    g = torch.empty((2, N, nm, nW, nW), dtype=torch.complex128, device="cuda")
+    ek = torch.empty((2, nW), dtype=torch.float64, device="cuda")
+    ekq = torch.empty((2, N, nW), dtype=torch.float64, device="cuda")
+    lib.interp_g_mesh(ds, torch.from_numpy(k).cuda(), mesh, g, omega_min=1e-4, eps_k=ek,
+                      eps_kq=ekq)
+    torch.cuda.synchronize()
+    sel = torch.from_numpy(iq).cuda()
+    got = dict(g=g[:, sel].cpu().numpy(), eps_k=ek.cpu().numpy(), eps_kq=ekq[:, sel].cpu().numpy())
+    del g, ekq, ds
+    print("GPU done", flush=True)
+    ref = coupling.coupling(k, _mesh_frac(mesh, iq), s)
+    _compare(got, ref, 1e-11)
