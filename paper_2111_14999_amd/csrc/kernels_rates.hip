@@ -683,10 +683,76 @@ __global__ __launch_bounds__(256) void rotate_g_lds_kernel(const cd* __restrict_
     }
 }
 
+// The rotation on FP64 MFMA (nW, nModes <= 16; indices padded to 16 with zeros),
+// one work-group of four waves per q, wave w taking n = 4w .. 4w + 3.  Per n two
+// 16 x 16 x 16 complex products, each four K steps of v_mfma_f64_16x16x4f64 for
+// every real product:
+//   W^T[b, nu] = sum_sa X[q, sa, n, b] E[q, nu, sa]      (A: lane (i, j) X[4s + j][n][i])
+//   g[nu, n, m] = sum_b W[nu, b] U_{k+q}[b, m]            (A: W, B: lane (i, j) U[4s + j][i])
+// The first product leaves W[nu = i][b = j + 4v] in result v of lane (i, j), which is
+// the A operand of K step s = v of the second: no data moves between the two.  g's
+// row nu = j + 4v, column m = i: four 256-byte runs per store.  The sums are the
+// same as the VALU kernels' up to the order of the additions.
+__device__ inline void cmfma(d4& cr, d4& ci, double ar, double ai, double br, double bi) {
+    cr = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, cr, 0, 0, 0);
+    cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, bi, cr, 0, 0, 0);
+    ci = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, ci, 0, 0, 0);
+    ci = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, ci, 0, 0, 0);
+}
+
+__global__ __launch_bounds__(256) void rotate_g_mfma_kernel(const cd* __restrict__ X,
+                                                            const cd* __restrict__ Ukq,
+                                                            const cd* __restrict__ E, int nW,
+                                                            int nm, cd* __restrict__ g) {
+    const int64_t q = blockIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int64_t nc = (int64_t)nm * nW * nW;
+    const cd* Xq = X + q * nc;
+    const cd* Uq = Ukq + q * nW * nW;
+    const cd* Eq = E + q * nm * nm;
+    const cd z = {0.0, 0.0};
+    cd e[4], u[4];  // B operands: E[nu = i][sa = 4s + j], U[b = 4s + j][m = i]
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int k = 4 * s + lg;
+        e[s] = (li < nm && k < nm) ? Eq[li * nm + k] : z;
+        u[s] = (k < nW && li < nW) ? Uq[k * nW + li] : z;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int n = 4 * wave + t;
+        if (n >= nW) break;  // the same for the whole wave
+        cd x[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int sa = 4 * s + lg;
+            x[s] = (sa < nm && li < nW) ? Xq[((int64_t)sa * nW + n) * nW + li] : z;
+        }
+        d4 wr = {0, 0, 0, 0}, wi = {0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) cmfma(wr, wi, x[s].x, x[s].y, e[s].x, e[s].y);
+        d4 gr = {0, 0, 0, 0}, gi = {0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) cmfma(gr, gi, wr[s], wi[s], u[s].x, u[s].y);
+        cd* go = g + q * nc + (int64_t)n * nW + li;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int nu = lg + 4 * v;
+            if (nu < nm && li < nW) go[(int64_t)nu * nW * nW] = cd{gr[v], gi[v]};
+        }
+    }
+}
+
 hipError_t launch_rotate_g(const cd* X, int64_t nq, const cd* Uk, const cd* Ukq, const cd* E,
                            int nW, int nm, cd* g, hipStream_t s) {
     (void)Uk;
     if (nq <= 0) return hipSuccess;
+    if (nW <= 16 && nm <= 16 && nq <= 2147483647LL) {
+        hipLaunchKernelGGL(rotate_g_mfma_kernel, dim3((unsigned)nq), dim3(256), 0, s, X, Ukq, E,
+                           nW, nm, g);
+        return hipGetLastError();
+    }
     const size_t shm = ((size_t)nm * nW * nW + (size_t)nm * nm) * sizeof(cd);
     if (nW <= 16 && nm <= 32 && shm <= 160 * 1024 && nq <= 2147483647LL) {
         const int block = std::max(64, (nW * nW + 63) / 64 * 64);
