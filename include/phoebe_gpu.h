@@ -200,7 +200,11 @@ phoebe_status phoebe_gpu_interp_g(void *handle, const phoebe_system *sys,
  * where the Rp box [-rmax, rmax]^3 is at most 31 wide and at most half as wide
  * as the Rp count, the sum over Rp is taken axis by axis; the result is the same
  * sum up to the order of the additions.  Otherwise (split-BF16, other Rp lists)
- * it is the dense contraction of phoebe_gpu_interp_g.
+ * it is the dense contraction of phoebe_gpu_interp_g.  When every k is a point
+ * of the mesh (k N_d integral to 1e-9), every k + q is one too: the bands at
+ * the pairs are then the mesh's, one eigensolve per mesh point gathered per pair
+ * (equal to the per-pair eigensolves up to rounding and the eigenvector phases).
+ * k_frac is read back to the host once.
  * Errors as phoebe_gpu_interp_g; PHOEBE_E_INVALID for q_mesh NULL or below 1. */
 phoebe_status phoebe_gpu_interp_g_mesh(void *handle, const phoebe_system *sys,
                                        const double *k_frac, int64_t nk,

@@ -255,6 +255,31 @@ phoebe_status interp_g_impl(Handle* h, const phoebe_system* sys, const double* k
                 qf_h[3 * q + 2] = (double)i2 / qm.n2;
             }
         }
+        // k points on the q mesh: every k + q is a mesh point, so the bands at the pairs
+        // are the mesh's (one eigensolve per mesh point, gathered per pair)
+        std::vector<int32_t> kidx_h;
+        if (q_mesh) {
+            std::vector<double> kh((size_t)nk * 3);
+            HIPCHK(h, hipMemcpyAsync(kh.data(), k_frac, sizeof(double) * kh.size(),
+                                     hipMemcpyDeviceToHost, s));
+            HIPCHK(h, hipStreamSynchronize(s));
+            const int Nd[3] = {qm.n0, qm.n1, qm.n2};
+            kidx_h.resize(nk);
+            for (int64_t i = 0; i < nk && !kidx_h.empty(); ++i) {
+                int id[3];
+                for (int d = 0; d < 3; ++d) {
+                    const double x = kh[3 * i + d] * Nd[d];
+                    const double r = std::nearbyint(x);
+                    if (!(std::fabs(x - r) <= 1e-9 * std::max(1.0, std::fabs(x)))) {
+                        kidx_h.clear();
+                        break;
+                    }
+                    id[d] = (int)(((int64_t)r % Nd[d] + Nd[d]) % Nd[d]);
+                }
+                if (!kidx_h.empty()) kidx_h[i] = (int32_t)mesh_linear(id[0], id[1], id[2], qm);
+            }
+        }
+        const bool k_on_mesh = !kidx_h.empty();
         if (fact) {
             box.assign((size_t)Wbox * Wbox * Wbox, -1);
             for (int i = 0; i < n_rp; ++i) {
@@ -276,7 +301,10 @@ phoebe_status interp_g_impl(Handle* h, const phoebe_system* sys, const double* k
             cd* Uk = ar.take<cd>((size_t)nk * nW * nW);
             double* ekq = eps_kq ? eps_kq : ar.take<double>((size_t)npair * nW);
             cd* Ukq = ar.take<cd>((size_t)npair * nW * nW);
-            double* kqf = ar.take<double>((size_t)npair * 3);
+            double* kqf = k_on_mesh ? nullptr : ar.take<double>((size_t)npair * 3);
+            double* eps_m = k_on_mesh ? ar.take<double>((size_t)nq * nW) : nullptr;
+            cd* U_m = k_on_mesh ? ar.take<cd>((size_t)nq * nW * nW) : nullptr;
+            int32_t* kidx_d = k_on_mesh ? ar.take<int32_t>((size_t)nk) : nullptr;
             double* om = omega_q ? omega_q : ar.take<double>((size_t)nq * nm);
             cd* E = ar.take<cd>((size_t)nq * nm * nm);
             cd* Pe = ar.take<cd>((size_t)kb * n_re);
@@ -299,9 +327,19 @@ phoebe_status interp_g_impl(Handle* h, const phoebe_system* sys, const double* k
                 Arena sub = ar;  // band scratch, reused after the tables are built
                 electron_bands_dev(h, sub, sys, rh, k_frac, nullptr, Mesh{1, 1, 1}, nk, ek, Uk, s);
                 Arena sub2 = ar;
-                if (ar.base) HIPCHK(h, launch_kq_points(k_frac, nk, q_frac, nq, kqf, s));
-                electron_bands_dev(h, sub2, sys, rh, kqf, nullptr, Mesh{1, 1, 1}, npair, ekq, Ukq,
-                                   s);
+                if (k_on_mesh) {
+                    electron_bands_dev(h, sub2, sys, rh, nullptr, nullptr, qm, nq, eps_m, U_m, s);
+                    if (ar.base) {
+                        HIPCHK(h, hipMemcpyAsync(kidx_d, kidx_h.data(), sizeof(int32_t) * nk,
+                                                 hipMemcpyHostToDevice, s));
+                        HIPCHK(h, launch_gather_kq_bands(eps_m, U_m, nW, qm, kidx_d, nk, nq, ekq,
+                                                         Ukq, s));
+                    }
+                } else {
+                    if (ar.base) HIPCHK(h, launch_kq_points(k_frac, nk, q_frac, nq, kqf, s));
+                    electron_bands_dev(h, sub2, sys, rh, kqf, nullptr, Mesh{1, 1, 1}, npair, ekq,
+                                       Ukq, s);
+                }
                 Arena sub3 = ar;
                 phonon_dev(h, sub3, sys, rd, q_frac, nullptr, Mesh{1, 1, 1}, nq, omega_min, 0.0,
                            om, E, nullptr, nullptr, s);

@@ -222,6 +222,11 @@ hipError_t launch_delta_weights(int nst, int64_t N, Mesh mesh, const int32_t* st
 // helpers
 hipError_t launch_kq_points(const double* k, int64_t nk, const double* q, int64_t nq,
                             double* kq, hipStream_t s);
+// eps_kq [nk, nq, nW], Ukq [nk, nq, nW, nW] of k = mesh point k_idx[i] and q = mesh
+// point j from the mesh's eps [N, nW] and U [N, nW, nW]
+hipError_t launch_gather_kq_bands(const double* eps, const cd* U, int nW, Mesh m,
+                                  const int32_t* k_idx, int64_t nk, int64_t nq, double* eps_kq,
+                                  cd* Ukq, hipStream_t s);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 
 }  // namespace phx

@@ -747,6 +747,41 @@ hipError_t launch_kq_points(const double* k, int64_t nk, const double* q, int64_
     return hipGetLastError();
 }
 
+// Bands at k + q for k and q on one mesh: the mesh's bands gathered per pair.
+// Pair (i, j) of k index k_idx[i] and q index j takes mesh point
+// ((k0 + q0) mod N0, (k1 + q1) mod N1, (k2 + q2) mod N2); one thread per (pair, entry).
+__global__ void gather_kq_bands_kernel(const double* __restrict__ eps, const cd* __restrict__ U,
+                                       int nW, Mesh m, const int32_t* __restrict__ k_idx,
+                                       int64_t nk, int64_t nq, double* __restrict__ eps_kq,
+                                       cd* __restrict__ Ukq) {
+    const int64_t per = (int64_t)nW + (int64_t)nW * nW;
+    const int64_t total = nk * nq * per;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t pair = t / per;
+        const int64_t e = t - pair * per;
+        const int64_t i = pair / nq, j = pair - i * nq;
+        int k0, k1, k2, q0, q1, q2;
+        mesh_triple(k_idx[i], m, k0, k1, k2);
+        mesh_triple(j, m, q0, q1, q2);
+        const int64_t kq = mesh_linear((k0 + q0) % m.n0, (k1 + q1) % m.n1, (k2 + q2) % m.n2, m);
+        if (e < nW)
+            eps_kq[pair * nW + e] = eps[kq * nW + e];
+        else
+            Ukq[pair * nW * nW + (e - nW)] = U[kq * nW * nW + (e - nW)];
+    }
+}
+
+hipError_t launch_gather_kq_bands(const double* eps, const cd* U, int nW, Mesh m,
+                                  const int32_t* k_idx, int64_t nk, int64_t nq, double* eps_kq,
+                                  cd* Ukq, hipStream_t s) {
+    if (nk * nq <= 0) return hipSuccess;
+    const int64_t total = nk * nq * ((int64_t)nW + (int64_t)nW * nW);
+    hipLaunchKernelGGL(gather_kq_bands_kernel, dim3(grid_for(total, 256)), dim3(256), 0, s, eps, U,
+                       nW, m, k_idx, nk, nq, eps_kq, Ukq);
+    return hipGetLastError();
+}
+
 // Fill with zeros by a kernel (safe under stream capture).
 __global__ void zero_kernel(uint32_t* p, int64_t n, uint8_t* tail, int ntail) {
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;

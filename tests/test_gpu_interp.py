@@ -173,6 +173,20 @@ def test_mesh_form_matches_oracle_and_list_form(lib, nW, nat, r, mesh):
     assert np.array_equal(got["eps_kq"], lst["eps_kq"])
 
 
+@pytest.mark.parametrize("nW,nat,r,mesh", [(5, 2, 2, (5, 4, 3)), (16, 5, 1, (4, 3, 4))])
+def test_mesh_form_k_on_mesh(lib, nW, nat, r, mesh):
+    """k points on the q mesh (k + q on the mesh: the mesh's bands gathered per pair)
+    against the oracle; a k written as -1/N0 + 1 exercises the wrap to the mesh index."""
+    s = synth.small_system(70 + nW, n_wannier=nW, n_atoms=nat, r=r)
+    N = int(np.prod(mesh))
+    ik = np.array([0, 7 % N, N - 1])
+    k = _mesh_frac(mesh, ik)
+    k[2, 0] -= 1.0  # the same mesh point, one period away
+    got = _run_mesh(lib, s, k, mesh)
+    ref = coupling.coupling(k, _mesh_frac(mesh), s)
+    _compare(got, ref, 1e-11)
+
+
 def test_mesh_form_fp32(lib):
     """FP32 form of the mesh interpolation against the FP64 oracle."""
     s = synth.small_system(77, n_wannier=8, n_atoms=3, r=2)
