@@ -303,12 +303,14 @@ __global__ __launch_bounds__(64) void eig_herm_kernel(cd* __restrict__ Aall, int
                     const double bb2 = cabs2(bpq);
                     if (bb2 > fmax(eps2 * fabs(a * d), skip_abs) && bb2 > 0.0) {
                         rotated = 1;
-                        const double bb = sqrt(bb2);
-                        const double tau = (d - a) / (2.0 * bb);
-                        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                        c = 1.0 / sqrt(1.0 + t * t);
+                        // (one reciprocal square root for 1/|b|, one for c: two
+                        // divisions and a square root fewer on the round's critical path)
+                        const double ib = rsqrt(bb2);
+                        const double tau = (d - a) * (0.5 * ib);
+                        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(fma(tau, tau, 1.0)));
+                        c = rsqrt(fma(t, t, 1.0));
                         s = t * c;
-                        e = cd{bpq.x / bb, bpq.y / bb};
+                        e = cd{bpq.x * ib, bpq.y * ib};
                     }
                 }
                 rc[lane] = c;
@@ -435,12 +437,14 @@ __global__ __launch_bounds__(64) void eig_herm_blk_kernel(cd* __restrict__ Aall,
                     const double bb2 = cabs2(bpq);
                     if (bb2 > fmax(eps2 * fabs(a * d), skip_abs) && bb2 > 0.0) {
                         rotated = 1;
-                        const double bb = sqrt(bb2);
-                        const double tau = (d - a) / (2.0 * bb);
-                        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                        c = 1.0 / sqrt(1.0 + t * t);
+                        // (one reciprocal square root for 1/|b|, one for c: two
+                        // divisions and a square root fewer on the round's critical path)
+                        const double ib = rsqrt(bb2);
+                        const double tau = (d - a) * (0.5 * ib);
+                        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(fma(tau, tau, 1.0)));
+                        c = rsqrt(fma(t, t, 1.0));
                         s = t * c;
-                        e = cd{bpq.x / bb, bpq.y / bb};
+                        e = cd{bpq.x * ib, bpq.y * ib};
                     }
                 }
                 prm[lane][0] = c;
