@@ -240,6 +240,8 @@ phoebe_status interp_g_impl(Handle* h, const phoebe_system* sys, const double* k
         const int64_t NL = (int64_t)qm.n1 * qm.n2;
         const int64_t ncp = (NC3 + 63) / 64 * 64;  // F and T columns, 64-wide blocks
         const bool axes_fused = fact && axis_transforms_fused(rmax_p, (int)ncp, lowp);
+        // FP64 with nW, nModes <= 16: the last axis feeds the rotation in registers
+        const bool fused_rot = fact && !lowp && axis0_rotate_supported(rmax_p, nW, nm);
         // q rows per rotation chunk (whole q0 planes on the mesh)
         const int64_t planes = fact ? std::max<int64_t>(1, 65536 / NL) : 0;
         const int64_t qchunk = fact ? std::min<int64_t>(nq, planes * NL) : std::min<int64_t>(nq, 65536);
@@ -311,7 +313,7 @@ phoebe_status interp_g_impl(Handle* h, const phoebe_system* sys, const double* k
             char* G1 = ar.take<char>((size_t)kb * n_rp * NC3 * el);
             cd* Pp = fact ? nullptr : ar.take<cd>((size_t)nq * n_rp);
             char* F = ar.take<char>((size_t)n_rp * (fact ? ncp : NC3) * el);
-            char* X = ar.take<char>((size_t)qchunk * NC3 * el);
+            char* X = fused_rot ? nullptr : ar.take<char>((size_t)qchunk * NC3 * el);
             cd* Lq = polar ? ar.take<cd>((size_t)nq * nm) : nullptr;
             double* born = polar ? ar.take<double>((size_t)9 * sys->n_atoms) : nullptr;
             int32_t* box_d = fact ? ar.take<int32_t>(box.size()) : nullptr;
@@ -400,6 +402,18 @@ phoebe_status interp_g_impl(Handle* h, const phoebe_system* sys, const double* k
                                           rmax_p, qm, Pax, 1, all_lines, reinterpret_cast<cd*>(T1),
                                           reinterpret_cast<cd*>(T2), s));
                         ta.done();
+                    }
+                    if (fused_rot) {  // last axis and rotation together, every q of this k
+                        cd* gk = reinterpret_cast<cd*>(g_out) + k * nq * NC3;
+                        Timer tx(h, s, "interp_axis0_rotate");
+                        HIPCHK(h, launch_axis0_rotate(reinterpret_cast<const cd*>(T2), qm, (int)ncp,
+                                                      rmax_p, Pax, E, Ukq + k * nq * nW * nW, nW,
+                                                      nm, gk, s));
+                        tx.done();
+                        if (polar)
+                            HIPCHK(h, launch_polar_add_g(gk, nq, Uk + k * nW * nW,
+                                                         Ukq + k * nq * nW * nW, Lq, nW, nm, s));
+                        continue;
                     }
                     for (int64_t q0 = 0; q0 < nq; q0 += qchunk) {
                         const int64_t nqc = std::min(qchunk, nq - q0);

@@ -81,6 +81,15 @@ __device__ inline cf ld_vec(const cf* p) {
     return cf{v.x, v.y};
 }
 __device__ inline void st_vec(cd* p, cd v) { *reinterpret_cast<d2*>(p) = d2{v.x, v.y}; }
+
+// C += A B for complex 16 x 16 x 4 tiles on v_mfma_f64_16x16x4f64: four real
+// products; (ar, ai) this lane's A entry, (br, bi) its B entry
+__device__ inline void cmfma_f64(d4& cr, d4& ci, double ar, double ai, double br, double bi) {
+    cr = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, cr, 0, 0, 0);
+    cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, bi, cr, 0, 0, 0);
+    ci = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, ci, 0, 0, 0);
+    ci = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, ci, 0, 0, 0);
+}
 __device__ inline void st_vec(cf* p, cf v) { *reinterpret_cast<f2*>(p) = f2{v.x, v.y}; }
 
 // Mesh helpers: linear index (i0 N1 + i1) N2 + i2

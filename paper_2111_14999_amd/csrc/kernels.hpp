@@ -131,6 +131,12 @@ hipError_t launch_axis0_out(const cd* T2, Mesh m, int nc_pad, int nc, int rmax, 
                             int q0a, int q0b, cd* X, int64_t ldx, hipStream_t s);
 hipError_t launch_axis0_out_f32(const cf* T2, Mesh m, int nc_pad, int nc, int rmax, const cd* P,
                                 int q0a, int q0b, cf* X, int64_t ldx, hipStream_t s);
+// The last axis and the rotation of g on the full mesh in one pass (FP64, nW and
+// nModes <= 16, box width 1 to 7): g [N, nModes, nW, nW] of one k from its T2
+// [W, N1*N2, ncp] (columns (sa, n, b)), E [N, nModes, nModes], Ukq [N, nW, nW].
+bool axis0_rotate_supported(int rmax, int nW, int nm);
+hipError_t launch_axis0_rotate(const cd* T2, Mesh m, int ncp, int rmax, const cd* P,
+                               const cd* E, const cd* Ukq, int nW, int nm, cd* g, hipStream_t s);
 // Stage 1 factorised over the axes of the Re box for one batch of kept k.
 // Device lists: d_k0 [d0] distinct k0; pair_k1 [d01] and pair_off [d0+1] the
 // distinct (k0, k1) pairs grouped by k0; kp_off [d01+1], k_row, k_k2 [nb] the

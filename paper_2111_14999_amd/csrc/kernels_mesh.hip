@@ -316,6 +316,162 @@ hipError_t launch_axis0_out_f32(const cf* T2, Mesh m, int nc_pad, int nc, int rm
     return axis0_out<cf>(T2, m, nc_pad, nc, rmax, P, q0a, q0b, X, ldx, s);
 }
 
+// The last axis and the rotation of g on the full mesh in one pass (FP64, nW and
+// nModes <= 16, box width WT <= 7): X never reaches memory.  A wave takes one band n
+// of one line (q1, q2) and holds, in the A-operand layout of the rotation's first
+// product, the line's T2 entries T2[R0, line, (sa, n, b)] for sa = 4s + j, b = i
+// (lane (i, j), K step s).  For every q0 of the line it forms
+//   X[q, sa, n, b] = sum_R0 P0[q0, R0] T2[R0, line, (sa, n, b)]
+// in registers and runs the two chained products of rotate_g_mfma_kernel (E_q X,
+// then that times U_{k+q}), writing g[q, nu, n, m].  Each complex product takes
+// three real ones (Gauss: Ar Br, Ai Bi and (Ar + Ai)(Br + Bi)) instead of four.
+// A work-group is four waves (bands 4p .. 4p + 3); the work-groups of one line are
+// dealt to one XCD, so that line's E_q and U_{k+q} come from one L2.
+//
+// Every load and store is a buffer access over the one object it touches (a
+// T2 row, E_q, U_{k+q}, g[q]); a lane outside the matrices (row or column beyond
+// nModes or nW) gets an offset past the object's size, so the hardware range
+// check returns zero or drops the store.  No access sits under a lane branch,
+// which keeps the count of memory operations in flight fixed: E_q and U_{k+q} of
+// the next q0 load while the current products run, and only the loop's end waits
+// for them.
+namespace {
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+constexpr int kOob = 0x7FFFFFF0;  // past every object below (each is < 2 GiB)
+__device__ inline __amdgpu_buffer_rsrc_t rsrc(const void* p, int64_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, (int)bytes, 0x00020000);
+}
+__device__ inline cd bld(__amdgpu_buffer_rsrc_t r, int off) {
+    const u4v v = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+    return __builtin_bit_cast(cd, v);
+}
+__device__ inline void bst(__amdgpu_buffer_rsrc_t r, int off, cd v) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4v, v), r, off, 0, 0);
+}
+struct Bop {  // a complex B operand and the sum of its parts
+    double r, i, s;
+};
+__device__ inline Bop bop(cd v) { return Bop{v.x, v.y, v.x + v.y}; }
+// one K step of a complex product by Gauss's three real products
+__device__ inline void gauss_step(d4& t1, d4& t2, d4& t3, double ar, double ai, const Bop& b) {
+    t1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, b.r, t1, 0, 0, 0);
+    t2 = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, b.i, t2, 0, 0, 0);
+    t3 = __builtin_amdgcn_mfma_f64_16x16x4f64(ar + ai, b.s, t3, 0, 0, 0);
+}
+}  // namespace
+
+template <int WT>
+__global__ __launch_bounds__(256, 2) void axis0_rotate_kernel(
+    const cd* __restrict__ T2, int64_t NL, int ncp, int N0, const cd* __restrict__ P0,
+    const cd* __restrict__ E, const cd* __restrict__ Ukq, int nW, int nm, int nwg_line,
+    cd* __restrict__ g) {
+    const int64_t id = blockIdx.x;
+    const int xcd = (int)(id & 7);
+    const int64_t j = id >> 3;
+    const int64_t line = (j / nwg_line) * 8 + xcd;
+    const int part = (int)(j % nwg_line);
+    if (line >= NL) return;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int li = lane & 15, lg = lane >> 4;
+    const int n = 4 * part + wave;
+    if (n >= nW) return;  // the same for the whole wave; no barriers below
+    const int64_t nc = (int64_t)nm * nW * nW;
+    // lane offsets (bytes) into a T2 row / E_q / U_{k+q} for K step s, into g[q] for row v
+    int ot[4], oe[4], ou[4], og[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int k = 4 * s + lg;
+        ot[s] = (k < nm && li < nW) ? ((k * nW + n) * nW + li) * 16 : kOob;
+        oe[s] = (li < nm && k < nm) ? (li * nm + k) * 16 : kOob;
+        ou[s] = (k < nW && li < nW) ? (k * nW + li) * 16 : kOob;
+        og[s] = (k < nm && li < nW) ? (k * nW * nW + n * nW + li) * 16 : kOob;  // nu = lg + 4v
+    }
+    cd t2[WT][4];
+#pragma unroll
+    for (int r = 0; r < WT; ++r) {
+        const auto rt = rsrc(T2 + ((int64_t)r * NL + line) * ncp, (int64_t)ncp * 16);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) t2[r][s] = bld(rt, ot[s]);
+    }
+    auto load_eu = [&](int q0, cd (&e)[4], cd (&u)[4]) {
+        const int64_t q = (int64_t)q0 * NL + line;
+        const auto re = rsrc(E + q * nm * nm, (int64_t)nm * nm * 16);
+        const auto ru = rsrc(Ukq + q * nW * nW, (int64_t)nW * nW * 16);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            e[s] = bld(re, oe[s]);
+            u[s] = bld(ru, ou[s]);
+        }
+    };
+    Bop be[4], bu[4];
+    {
+        cd e[4], u[4];
+        load_eu(0, e, u);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            be[s] = bop(e[s]);
+            bu[s] = bop(u[s]);
+        }
+    }
+    // T2 and the first operands are in registers before the loop starts, so that the
+    // loop's own waits count only its own accesses
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    for (int q0 = 0; q0 < N0; ++q0) {
+        cd en[4], un[4];
+        load_eu(q0 + 1 < N0 ? q0 + 1 : q0, en, un);  // the last pass reloads its own
+        const cd* Pq = P0 + (int64_t)q0 * WT;
+        cd x[4] = {};
+#pragma unroll
+        for (int r = 0; r < WT; ++r) {
+            const cd p = Pq[r];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) x[s] = cfma(p, t2[r][s], x[s]);
+        }
+        d4 t1 = {0, 0, 0, 0}, tb = {0, 0, 0, 0}, t3 = {0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) gauss_step(t1, tb, t3, x[s].x, x[s].y, be[s]);
+        const d4 wr = t1 - tb, wi = t3 - t1 - tb;
+        t1 = d4{0, 0, 0, 0};
+        tb = d4{0, 0, 0, 0};
+        t3 = d4{0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) gauss_step(t1, tb, t3, wr[s], wi[s], bu[s]);
+        const d4 gr = t1 - tb, gi = t3 - t1 - tb;
+        const auto rg = rsrc(g + ((int64_t)q0 * NL + line) * nc, nc * 16);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) bst(rg, og[v], cd{gr[v], gi[v]});
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            be[s] = bop(en[s]);
+            bu[s] = bop(un[s]);
+        }
+    }
+}
+
+bool axis0_rotate_supported(int rmax, int nW, int nm) {
+    const int W = 2 * rmax + 1;
+    return nW <= 16 && nm <= 16 && (W == 1 || W == 3 || W == 5 || W == 7);
+}
+
+hipError_t launch_axis0_rotate(const cd* T2, Mesh m, int ncp, int rmax, const cd* P,
+                               const cd* E, const cd* Ukq, int nW, int nm, cd* g, hipStream_t s) {
+    const int W = 2 * rmax + 1;
+    if (!axis0_rotate_supported(rmax, nW, nm)) return hipErrorInvalidValue;
+    const int64_t NL = (int64_t)m.n1 * m.n2;
+    const int nwg_line = (nW + 3) / 4;
+    const int64_t groups = (NL + 7) / 8 * 8 * nwg_line;
+    if (groups > 2147483647LL) return hipErrorInvalidValue;
+    const dim3 gr((unsigned)groups), b(256);
+    switch (W) {
+        case 1: hipLaunchKernelGGL(axis0_rotate_kernel<1>, gr, b, 0, s, T2, NL, ncp, m.n0, P, E, Ukq, nW, nm, nwg_line, g); break;
+        case 3: hipLaunchKernelGGL(axis0_rotate_kernel<3>, gr, b, 0, s, T2, NL, ncp, m.n0, P, E, Ukq, nW, nm, nwg_line, g); break;
+        case 5: hipLaunchKernelGGL(axis0_rotate_kernel<5>, gr, b, 0, s, T2, NL, ncp, m.n0, P, E, Ukq, nW, nm, nwg_line, g); break;
+        default: hipLaunchKernelGGL(axis0_rotate_kernel<7>, gr, b, 0, s, T2, NL, ncp, m.n0, P, E, Ukq, nW, nm, nwg_line, g); break;
+    }
+    return hipGetLastError();
+}
+
 bool axis_transforms_fused(int rmax, int nc_pad, bool f32) {
     const int W = 2 * rmax + 1;
     const bool listed = W == 1 || W == 3 || W == 5 || W == 7 || W == 9;  // compile-time widths

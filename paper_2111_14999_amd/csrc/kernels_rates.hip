@@ -693,13 +693,6 @@ __global__ __launch_bounds__(256) void rotate_g_lds_kernel(const cd* __restrict_
 // the A operand of K step s = v of the second: no data moves between the two.  g's
 // row nu = j + 4v, column m = i: four 256-byte runs per store.  The sums are the
 // same as the VALU kernels' up to the order of the additions.
-__device__ inline void cmfma(d4& cr, d4& ci, double ar, double ai, double br, double bi) {
-    cr = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, cr, 0, 0, 0);
-    cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, bi, cr, 0, 0, 0);
-    ci = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, ci, 0, 0, 0);
-    ci = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, ci, 0, 0, 0);
-}
-
 __global__ __launch_bounds__(256) void rotate_g_mfma_kernel(const cd* __restrict__ X,
                                                             const cd* __restrict__ Ukq,
                                                             const cd* __restrict__ E, int nW,
@@ -731,10 +724,10 @@ __global__ __launch_bounds__(256) void rotate_g_mfma_kernel(const cd* __restrict
         }
         d4 wr = {0, 0, 0, 0}, wi = {0, 0, 0, 0};
 #pragma unroll
-        for (int s = 0; s < 4; ++s) cmfma(wr, wi, x[s].x, x[s].y, e[s].x, e[s].y);
+        for (int s = 0; s < 4; ++s) cmfma_f64(wr, wi, x[s].x, x[s].y, e[s].x, e[s].y);
         d4 gr = {0, 0, 0, 0}, gi = {0, 0, 0, 0};
 #pragma unroll
-        for (int s = 0; s < 4; ++s) cmfma(gr, gi, wr[s], wi[s], u[s].x, u[s].y);
+        for (int s = 0; s < 4; ++s) cmfma_f64(gr, gi, wr[s], wi[s], u[s].x, u[s].y);
         cd* go = g + q * nc + (int64_t)n * nW + li;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {

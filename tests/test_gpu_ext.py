@@ -171,6 +171,41 @@ def test_polar_coupling_matches_oracle(lib):
     assert worst < G2_BOUND
 
 
+def test_polar_coupling_mesh_form(lib):
+    """The polar term on the full-mesh form of the interpolation: against the list form
+    on the same q points (same bands and modes, so g itself agrees) and, through the
+    gauge-invariant group sums, against the oracle."""
+    torch = torch_cuda()
+    from paper_2111_14999_amd import DeviceSystem
+    s = _polar_system(94, nW=5, nat=2)
+    mesh = (4, 3, 4)
+    N = int(np.prod(mesh))
+    i0, r = np.divmod(np.arange(N), mesh[1] * mesh[2])
+    i1, i2 = np.divmod(r, mesh[2])
+    q = np.stack([i0 / mesh[0], i1 / mesh[1], i2 / mesh[2]], axis=1)
+    k = np.random.default_rng(6).uniform(-1, 1, size=(2, 3))
+    ds = DeviceSystem.from_host(s)
+    nW, nm = s.n_wannier, s.n_modes
+    gm = torch.empty((2, N, nm, nW, nW), dtype=torch.complex128, device="cuda")
+    gl = torch.empty_like(gm)
+    kd = torch.from_numpy(k).cuda()
+    lib.interp_g_mesh(ds, kd, mesh, gm)
+    lib.interp_g(ds, kd, torch.from_numpy(q).cuda(), gl)
+    torch.cuda.synchronize()
+    gm, gl = gm.cpu().numpy(), gl.cpu().numpy()
+    d = np.max(np.abs(gm - gl)) / np.max(np.abs(gl))
+    ref = coupling.coupling(k, q, s)
+    worst = 0.0
+    for i in range(2):
+        for j in range(N):
+            a = group_sum_g2(gm[i, j], ref["eps_k"][i], ref["eps_kq"][i, j], ref["omega_q"][j])
+            b = group_sum_g2(ref["g"][i, j], ref["eps_k"][i], ref["eps_kq"][i, j], ref["omega_q"][j])
+            worst = max(worst, np.max(np.abs(a - b)) / np.max(b))
+    print(f"[polar g mesh form] vs list form {d:.2e}, group |g|^2 vs oracle {worst:.2e}", flush=True)
+    assert d < 1e-12
+    assert worst < G2_BOUND
+
+
 @pytest.mark.parametrize("form", ["direct", "factored"])
 @pytest.mark.parametrize("nW", [5, 20])
 def test_polar_rates_match_oracle(lib, form, nW):
