@@ -1079,17 +1079,24 @@ constexpr int kTP = 2;  // column tiles per MFMA pass
 // extension terms, and the FP64 form with two tiles per mode (its U_{k+q} values
 // of both halves), need more registers, and at four waves they would spill.
 constexpr int kLineLW = 1, kLinePol = 2, kLineVel = 4;
-template <int FEAT, int H, bool F64>
+template <int FEAT, int H, bool F64, int NWV = 4>
 constexpr int line_waves_per_simd() {
+    if (NWV == 2) return 3;  // two waves per work-group: twice the tiles per wave
     if (H == 2 && F64) return FEAT == 0 || FEAT == kLineLW ? 3 : 2;
     return FEAT == 0 || FEAT == kLineLW ? 4 : 3;
 }
 
 // H: column tiles per mode, 1 (nW <= 16: column sa*16 + b) or 2 (nW <= 32: column
 // sa*32 + b, the tiles of a mode being its halves b < 16 and b >= 16, one MFMA pass).
-template <int TN, int KS, class C, int FEAT, int H = 1>
-__global__ __launch_bounds__(256, (line_waves_per_simd<FEAT, H, sizeof(C) == sizeof(cd)>())) void
+// NWV: waves per work-group, 4, or 2 with twice the tiles per wave: a pair then
+// holds 2 x 159 VGPRs per lane instead of 4 x 127, so six (state, line) pairs are
+// resident per CU instead of four (measured on the realistic workload: 2.45 ms per
+// launch against 2.68 ms; one wave of sixteen tiles, 2.47 ms; two waves loading
+// T2 per K step, 2.73 ms).
+template <int TN, int KS, class C, int FEAT, int H = 1, int NWV = 4>
+__global__ __launch_bounds__(64 * NWV, (line_waves_per_simd<FEAT, H, sizeof(C) == sizeof(cd), NWV>())) void
 line_rates_kernel(RateArgs a) {
+    constexpr int BT = 64 * NWV;  // threads of the work-group
     static_assert(H == 1 || (H == 2 && TN % 2 == 0 && kTP == 2),
                   "two tiles per mode: whole modes per wave and per pass");
     constexpr bool LW = FEAT & kLineLW, POL = FEAT & kLinePol, VEL = FEAT & kLineVel;
@@ -1112,7 +1119,7 @@ line_rates_kernel(RateArgs a) {
     int* sList = reinterpret_cast<int*>(sPm + N0);             // [N0] live points of a band
     // LW: [N0][nm] linewidth partials of the work-group (8-byte aligned: N0 ints above)
     double* sLW = reinterpret_cast<double*>(sList + N0 + (N0 & 1));
-    __shared__ double sRed[4];
+    __shared__ double sRed[NWV];
     __shared__ int sCount;
     __shared__ cd sO[16];  // POL: overlap [U_k^dagger U_{k+q}]_{n m} at the unit's points
 
@@ -1160,7 +1167,7 @@ line_rates_kernel(RateArgs a) {
         if (LW && a.lw) {
             const double fn = a.focc[(int64_t)kmesh * nW + nband];
             mdf = fn * (1.0 - fn) * a.inv_kT;
-            for (int i = tid; i < N0 * nm; i += 256) sLW[i] = 0.0;
+            for (int i = tid; i < N0 * nm; i += BT) sLW[i] = 0.0;
         }
     }
     // tile row li loads column b = perm(li), see above
@@ -1179,7 +1186,7 @@ line_rates_kernel(RateArgs a) {
     // without branches (clamped addresses), so that the LDS stores wait on
     // the first two only and T2 stays in flight.  A T2 row k >= W is read
     // from row W - 1 and meets a zero phase (the table is zero beyond W).
-    const int i0 = min(tid, nP - 1), i1 = min(tid + 256, nP - 1);
+    const int i0 = min(tid, nP - 1), i1 = min(tid + BT, nP - 1);
     auto p0_src = [&](int i) {
         const int q0 = i / Ws, r = i - q0 * Ws;
         return a.P0[min(q0, N0 - 1) * W + min(r, W - 1)];
@@ -1202,9 +1209,9 @@ line_rates_kernel(RateArgs a) {
     };
     if (tid < N0) sPm[tid] = pm0;
     if (tid < nP) sP[tid] = p0_keep(tid) ? to_c<C>(pv0) : C{0, 0};
-    if (tid + 256 < nP) sP[tid + 256] = p0_keep(tid + 256) ? to_c<C>(pv1) : C{0, 0};
-    for (int q0 = tid + 256; q0 < N0; q0 += 256) sPm[q0] = lv[q0];
-    for (int i = tid + 512; i < nP; i += 256) sP[i] = p0_at(i);
+    if (tid + BT < nP) sP[tid + BT] = p0_keep(tid + BT) ? to_c<C>(pv1) : C{0, 0};
+    for (int q0 = tid + BT; q0 < N0; q0 += BT) sPm[q0] = lv[q0];
+    for (int i = tid + 2 * BT; i < nP; i += BT) sP[i] = p0_at(i);
 
     // Values one unit (band m, points list[g .. g+15]) needs: per lane,
     // U_{k+q}[b = 4 lg + v, m] at the lane's point; per thread, for its term
@@ -1400,7 +1407,7 @@ line_rates_kernel(RateArgs a) {
             __syncthreads();
             // Z[c, nu] = sum_sa E_q[sa, nu] Y[c, sa] and the rate terms
             if (pc >= 0) item_term(pc, ic, inu, d.em, d.fm, d.om, d.nbq, m);
-            for (int it = tid + 256; it < 16 * nm; it += 256) {
+            for (int it = tid + BT; it < 16 * nm; it += BT) {
                 const int c = it / nm, nu = it - c * nm;
                 if (g + c >= cnt) continue;
                 const int q0 = sList[g + c];
@@ -1416,12 +1423,19 @@ line_rates_kernel(RateArgs a) {
     for (int o = 32; o > 0; o >>= 1) gacc += __shfl_xor(gacc, o, 64);
     if (lane == 0) sRed[wave] = gacc;
     __syncthreads();
-    if (tid == 0) a.partial[(int64_t)st * a.n_qtiles + line] = (sRed[0] + sRed[1]) + (sRed[2] + sRed[3]);
+    if (tid == 0) {
+        double tot;
+        if constexpr (NWV == 4)
+            tot = (sRed[0] + sRed[1]) + (sRed[2] + sRed[3]);
+        else
+            tot = sRed[0] + sRed[1];
+        a.partial[(int64_t)st * a.n_qtiles + line] = tot;
+    }
     if constexpr (LW) {
         if (a.lw) {  // (the last __syncthreads above ordered every sLW update)
             // only the live points' partials: the reduction reads those alone
             double* o = a.lw + ((int64_t)st * NL + line) * N0 * nm;
-            for (int i = tid; i < N0 * nm; i += 256)
+            for (int i = tid; i < N0 * nm; i += BT)
                 if (sPm[i / nm]) o[i] = sLW[i];
         }
     }
@@ -1434,7 +1448,7 @@ size_t line_rates_lds(int W, int N0, int nm, bool f32, bool lw) {
            (lw ? sizeof(uint32_t) * (size_t)(N0 & 1) + (size_t)N0 * nm * sizeof(double) : 0);
 }
 
-// Columns of the factorised form, 4 waves x TN tiles of 16: one tile per mode index
+// Columns of the factorised form, 4 waves x TN tiles of 16 (or 2 x 2 TN): one tile per mode index
 // (nW <= 16), or two (16 < nW <= 32: a wave takes TN / 2 whole modes).
 int line_rates_ncpad(int nm, int nW) {
     if (nW > 32 || nm > 32 || nm < 1 || nW < 1) return -1;
@@ -1446,11 +1460,11 @@ int line_rates_ncpad(int nm, int nW) {
     return 64 * (tn <= 8 ? tn : (tn <= 12 ? 12 : 16));
 }
 
-template <int TN, int KS, class C, int FEAT, int H = 1>
+template <int TN, int KS, class C, int FEAT, int H = 1, int NWV = 4>
 static hipError_t go_line(const RateArgs& a, int nst, hipStream_t s) {
     const size_t shm = line_rates_lds(a.W, a.mesh.n0, a.nm, sizeof(C) == sizeof(cf), a.lw != nullptr);
     if (shm > 64 * 1024) return hipErrorInvalidValue;
-    hipError_t e = hipFuncSetAttribute((const void*)line_rates_kernel<TN, KS, C, FEAT, H>,
+    hipError_t e = hipFuncSetAttribute((const void*)line_rates_kernel<TN, KS, C, FEAT, H, NWV>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) return e;
     const int64_t NL = (int64_t)a.mesh.n1 * a.mesh.n2;
@@ -1471,8 +1485,8 @@ static hipError_t go_line(const RateArgs& a, int nst, hipStream_t s) {
         b.line_bands = a.line_bands + (int64_t)s0 * NL;
         if (a.lw) b.lw = a.lw + (int64_t)s0 * NL * a.mesh.n0 * a.nm;
         b.n_states = ns;
-        hipLaunchKernelGGL((line_rates_kernel<TN, KS, C, FEAT, H>), dim3((unsigned)(groups * 8 * ns)),
-                           dim3(256), shm, s, b);
+        hipLaunchKernelGGL((line_rates_kernel<TN, KS, C, FEAT, H, NWV>),
+                           dim3((unsigned)(groups * 8 * ns)), dim3(64 * NWV), shm, s, b);
     }
     return hipGetLastError();
 }
@@ -1535,8 +1549,11 @@ static hipError_t line_rates(const RateArgs& a, int nst, hipStream_t s) {
                            : with_feat(integral_constant<int, 2>{}, integral_constant<int, 0>{});
         case 3: return pre ? with_feat(integral_constant<int, 3>{}, integral_constant<int, 2>{})
                            : with_feat(integral_constant<int, 3>{}, integral_constant<int, 0>{});
-        case 4: return pre ? with_feat(integral_constant<int, 4>{}, integral_constant<int, 2>{})
-                           : with_feat(integral_constant<int, 4>{}, integral_constant<int, 0>{});
+        case 4:
+            // the plain rates: two waves of eight tiles, six work-groups per CU
+            if (pre && feat == 0) return go_line<8, 2, C, 0, 1, 2>(a, nst, s);
+            return pre ? with_feat(integral_constant<int, 4>{}, integral_constant<int, 2>{})
+                       : with_feat(integral_constant<int, 4>{}, integral_constant<int, 0>{});
         case 6: return with_feat(integral_constant<int, 6>{}, integral_constant<int, 0>{});
         case 8: return with_feat(integral_constant<int, 8>{}, integral_constant<int, 0>{});
         default: return hipErrorInvalidValue;
