@@ -1092,7 +1092,8 @@ constexpr int line_waves_per_simd() {
 // holds 2 x 159 VGPRs per lane instead of 4 x 127, so six (state, line) pairs are
 // resident per CU instead of four (measured on the realistic workload: 2.45 ms per
 // launch against 2.68 ms; one wave of sixteen tiles, 2.47 ms; two waves loading
-// T2 per K step, 2.73 ms).
+// T2 per K step, 2.73 ms).  The plain rates of two and three tiles per wave take the
+// two-wave form as well (the batched plan of 32 systems: 137.9 -> 133.9 ms).
 template <int TN, int KS, class C, int FEAT, int H = 1, int NWV = 4>
 __global__ __launch_bounds__(64 * NWV, (line_waves_per_simd<FEAT, H, sizeof(C) == sizeof(cd), NWV>())) void
 line_rates_kernel(RateArgs a) {
@@ -1545,10 +1546,14 @@ static hipError_t line_rates(const RateArgs& a, int nst, hipStream_t s) {
     switch (a.nc_pad / 64) {
         case 1: return pre ? with_feat(integral_constant<int, 1>{}, integral_constant<int, 2>{})
                            : with_feat(integral_constant<int, 1>{}, integral_constant<int, 0>{});
-        case 2: return pre ? with_feat(integral_constant<int, 2>{}, integral_constant<int, 2>{})
-                           : with_feat(integral_constant<int, 2>{}, integral_constant<int, 0>{});
-        case 3: return pre ? with_feat(integral_constant<int, 3>{}, integral_constant<int, 2>{})
-                           : with_feat(integral_constant<int, 3>{}, integral_constant<int, 0>{});
+        case 2:
+            if (pre && feat == 0) return go_line<4, 2, C, 0, 1, 2>(a, nst, s);
+            return pre ? with_feat(integral_constant<int, 2>{}, integral_constant<int, 2>{})
+                       : with_feat(integral_constant<int, 2>{}, integral_constant<int, 0>{});
+        case 3:
+            if (pre && feat == 0) return go_line<6, 2, C, 0, 1, 2>(a, nst, s);
+            return pre ? with_feat(integral_constant<int, 3>{}, integral_constant<int, 2>{})
+                       : with_feat(integral_constant<int, 3>{}, integral_constant<int, 0>{});
         case 4:
             // the plain rates: two waves of eight tiles, six work-groups per CU
             if (pre && feat == 0) return go_line<8, 2, C, 0, 1, 2>(a, nst, s);
