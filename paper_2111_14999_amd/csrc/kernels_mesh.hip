@@ -1093,7 +1093,9 @@ constexpr int line_waves_per_simd() {
 // resident per CU instead of four (measured on the realistic workload: 2.45 ms per
 // launch against 2.68 ms; one wave of sixteen tiles, 2.47 ms; two waves loading
 // T2 per K step, 2.73 ms).  The plain rates of two and three tiles per wave take the
-// two-wave form as well (the batched plan of 32 systems: 137.9 -> 133.9 ms).
+// two-wave form as well (the batched plan of 32 systems: 137.9 -> 133.9 ms), and so do
+// the linewidth and adaptive-width variants (163 VGPRs; phonon linewidth 107 -> 101.5 ms,
+// adaptive rates 541 -> 478 ms per step); the polar variant would spill.
 template <int TN, int KS, class C, int FEAT, int H = 1, int NWV = 4>
 __global__ __launch_bounds__(64 * NWV, (line_waves_per_simd<FEAT, H, sizeof(C) == sizeof(cd), NWV>())) void
 line_rates_kernel(RateArgs a) {
@@ -1557,6 +1559,10 @@ static hipError_t line_rates(const RateArgs& a, int nst, hipStream_t s) {
         case 4:
             // the plain rates: two waves of eight tiles, six work-groups per CU
             if (pre && feat == 0) return go_line<8, 2, C, 0, 1, 2>(a, nst, s);
+            if constexpr (sizeof(C) == sizeof(cd)) {
+                if (pre && feat == kLineLW) return go_line<8, 2, C, kLineLW, 1, 2>(a, nst, s);
+                if (pre && feat == kLineVel) return go_line<8, 2, C, kLineVel, 1, 2>(a, nst, s);
+            }
             return pre ? with_feat(integral_constant<int, 4>{}, integral_constant<int, 2>{})
                        : with_feat(integral_constant<int, 4>{}, integral_constant<int, 0>{});
         case 6: return with_feat(integral_constant<int, 6>{}, integral_constant<int, 0>{});
