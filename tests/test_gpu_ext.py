@@ -294,11 +294,13 @@ def test_velocities_degenerate_pair(lib):
 
 
 @pytest.mark.parametrize("form", ["direct", "factored"])
-@pytest.mark.parametrize("nW", [5, 20])
-def test_adaptive_rates_and_linewidth_match_oracle(lib, form, nW):
+@pytest.mark.parametrize("nW,nat", [(5, 2), (20, 2), (16, 5)])
+def test_adaptive_rates_and_linewidth_match_oracle(lib, form, nW, nat):
+    """nW 16 with 15 modes: the factorised line kernel's two-wave, eight-tile form with
+    per-transition widths; nW 20: two column tiles per mode."""
     torch = torch_cuda()
     from paper_2111_14999_amd import DeviceSystem
-    s = synth.small_system(94, n_wannier=nW, n_atoms=2, r=1)
+    s = synth.small_system(94, n_wannier=nW, n_atoms=nat, r=1)
     s.h_r *= 0.3
     mesh = (4, 3, 4)
     t, par = _params(s, mesh, sigma=0.02)
