@@ -332,9 +332,9 @@ hipError_t launch_axis0_out_f32(const cf* T2, Mesh m, int nc_pad, int nc, int rm
 // T2 row, E_q, U_{k+q}, g[q]); a lane outside the matrices (row or column beyond
 // nModes or nW) gets an offset past the object's size, so the hardware range
 // check returns zero or drops the store.  No access sits under a lane branch,
-// which keeps the count of memory operations in flight fixed: E_q and U_{k+q} of
-// the next q0 load while the current products run, and only the loop's end waits
-// for them.
+// which keeps the count of memory operations in flight fixed, so the compiler's
+// waits name exact counts: E_q and U_{k+q} of the next q0 are issued at the top of
+// each pass and first waited for after the current pass's X and its first product.
 namespace {
 typedef unsigned int u4v __attribute__((ext_vector_type(4)));
 constexpr int kOob = 0x7FFFFFF0;  // past every object below (each is < 2 GiB)
