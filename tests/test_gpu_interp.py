@@ -153,11 +153,14 @@ def _run_mesh(lib, s, k, mesh, precision="fp64", omega_min=1e-4):
 
 
 @pytest.mark.parametrize("nW,nat,r,mesh", [(5, 2, 2, (5, 4, 3)), (16, 5, 1, (3, 4, 5)),
-                                           (9, 1, 2, (7, 1, 2)), (20, 2, 1, (4, 3, 3))])
+                                           (9, 1, 2, (7, 1, 2)), (20, 2, 1, (4, 3, 3)),
+                                           (8, 6, 1, (3, 4, 3))])
 def test_mesh_form_matches_oracle_and_list_form(lib, nW, nat, r, mesh):
     """The factorised sum over Rp on a full (ragged) q mesh against the oracle, and
     against the dense contraction of phoebe_gpu_interp_g on the same q points (the
-    same bands and modes, so g itself agrees, not only |g|^2)."""
+    same bands and modes, so g itself agrees, not only |g|^2).  Up to 16 bands and 16
+    modes the last axis and the rotation run in one kernel; 20 bands, or 18 modes,
+    take the two-kernel form."""
     s = synth.small_system(60 + nW, n_wannier=nW, n_atoms=nat, r=r)
     rng = np.random.default_rng(nW)
     k = rng.uniform(-1, 1, size=(3, 3))
@@ -236,3 +239,32 @@ def test_realistic_size_mesh_launch(lib):
     print("GPU done", flush=True)
     ref = coupling.coupling(k, _mesh_frac(mesh, iq), s)
     _compare(got, ref, 1e-11)
+
+
+def test_realistic_size_mesh_launch_fp32(lib):
+    """The FP32 form of phoebe_gpu_interp_g_mesh at the realistic size (nW 16, 15 modes,
+    343 Re and Rp, the whole 40^3 q mesh): 32 seeded q of the result against the FP64
+    oracle at the FP32 bound."""
+    torch = torch_cuda()
+    from paper_2111_14999_amd import DeviceSystem
+    s = synth.config_c2()
+    mesh = (40, 40, 40)
+    N = int(np.prod(mesh))
+    rng = np.random.default_rng(37)
+    ik = np.sort(rng.choice(N, size=1, replace=False))
+    iq = np.sort(rng.choice(N, size=32, replace=False))
+    k = _mesh_frac(mesh, ik)
+    ds = DeviceSystem.from_host(s)
+    nW, nm = s.n_wannier, s.n_modes
+    g = torch.empty((1, N, nm, nW, nW), dtype=torch.complex128, device="cuda")
+    ek = torch.empty((1, nW), dtype=torch.float64, device="cuda")
+    ekq = torch.empty((1, N, nW), dtype=torch.float64, device="cuda")
+    lib.interp_g_mesh(ds, torch.from_numpy(k).cuda(), mesh, g, omega_min=1e-4, precision="fp32",
+                      eps_k=ek, eps_kq=ekq)
+    torch.cuda.synchronize()
+    sel = torch.from_numpy(iq).cuda()
+    got = dict(g=g[:, sel].cpu().numpy(), eps_k=ek.cpu().numpy(), eps_kq=ekq[:, sel].cpu().numpy())
+    del g, ekq, ds
+    print("GPU done", flush=True)
+    ref = coupling.coupling(k, _mesh_frac(mesh, iq), s)
+    _compare(got, ref, 1e-6)
