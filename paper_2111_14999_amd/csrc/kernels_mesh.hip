@@ -613,8 +613,11 @@ __global__ __launch_bounds__(256) void re_axis12_kernel(const C* __restrict__ T0
     }
 }
 
-// 16-lane row sum by DPP (quad_perm 1,0,3,2 and 2,3,0,1, row_half_mirror,
-// row_mirror), left in every lane of the row.
+// Two 16-lane row sums at once by DPP: the first step (quad_perm 1,0,3,2) swaps
+// the values so that each even lane adds the pair's a and each odd lane the pair's
+// b; then quad_perm 2,3,0,1 and row rotations by 4 and by 8 add lanes of the same
+// parity.  Every even lane of the row ends with the sum of a, every odd lane with
+// the sum of b: half the moves and adds of two separate row sums.
 // Every lane of the row reads a lane of the same row for these controls, so the
 // moves take no old value (no zeroing instructions before them).
 template <int CTRL>
@@ -630,17 +633,19 @@ __device__ inline float dpp_f32(float x) {
         float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), CTRL, 0xF, 0xF, true));
 }
 template <class R>
-__device__ inline R row16_sum(R x) {
+__device__ inline R row16_sum2(R a, R b, bool odd) {
+    const R keep = odd ? b : a, send = odd ? a : b;
+    R x;
     if constexpr (sizeof(R) == 8) {
-        x += dpp_f64<0xB1>(x);
+        x = keep + dpp_f64<0xB1>(send);
         x += dpp_f64<0x4E>(x);
-        x += dpp_f64<0x141>(x);
-        x += dpp_f64<0x140>(x);
+        x += dpp_f64<0x124>(x);
+        x += dpp_f64<0x128>(x);
     } else {
-        x += dpp_f32<0xB1>(x);
+        x = keep + dpp_f32<0xB1>(send);
         x += dpp_f32<0x4E>(x);
-        x += dpp_f32<0x141>(x);
-        x += dpp_f32<0x140>(x);
+        x += dpp_f32<0x124>(x);
+        x += dpp_f32<0x128>(x);
     }
     return x;
 }
@@ -715,9 +720,8 @@ __global__ __launch_bounds__(64 * kFoldWaves, fold_waves_per_simd<WT>()) void re
         auto fold = [&](const C& acc, int st) {
             const C u =
                 to_c<C>(fo.U[((int64_t)fo.st_kmesh[st] * 16 + fo.st_band[st]) * 16 + li]);
-            const R fr = row16_sum(u.x * acc.x + u.y * acc.y);
-            const R fi = row16_sum(u.x * acc.y - u.y * acc.x);
-            if (li == 0) Fo[st * fst] = C{fr, fi};
+            const R f = row16_sum2(u.x * acc.x + u.y * acc.y, u.x * acc.y - u.y * acc.x, li & 1);
+            if (li < 2) reinterpret_cast<R*>(Fo + st * fst)[li] = f;  // Re from lane 0, Im from 1
         };
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
