@@ -585,17 +585,28 @@ __global__ __launch_bounds__(256) void re_axis12_kernel(const C* __restrict__ T0
 #pragma unroll
         for (int r2 = 0; r2 < NV; ++r2) ta[r2] = tb[r2] = C{0, 0};
         // one R1 row at a time keeps the register footprint to the 2 W sums
+        if (two) {  // (wave-uniform)
 #pragma unroll 1
-        for (int r1 = 0; r1 < W; ++r1) {
-            const C pa = to_c<C>(Pka[r1]), pb = to_c<C>(Pkb[r1]);
-            const C* row = sT + r1 * W * 64 + cc;
+            for (int r1 = 0; r1 < W; ++r1) {
+                const C pa = to_c<C>(Pka[r1]), pb = to_c<C>(Pkb[r1]);
+                const C* row = sT + r1 * W * 64 + cc;
 #pragma unroll
-            for (int r2 = 0; r2 < NV; ++r2)
-                if (r2 < W) {
-                    const C v = row[r2 * 64];
-                    ta[r2] = cfma(pa, v, ta[r2]);
-                    tb[r2] = cfma(pb, v, tb[r2]);
-                }
+                for (int r2 = 0; r2 < NV; ++r2)
+                    if (r2 < W) {
+                        const C v = row[r2 * 64];
+                        ta[r2] = cfma(pa, v, ta[r2]);
+                        tb[r2] = cfma(pb, v, tb[r2]);
+                    }
+            }
+        } else {  // the wave's last pair alone: no second set of products
+#pragma unroll 1
+            for (int r1 = 0; r1 < W; ++r1) {
+                const C pa = to_c<C>(Pka[r1]);
+                const C* row = sT + r1 * W * 64 + cc;
+#pragma unroll
+                for (int r2 = 0; r2 < NV; ++r2)
+                    if (r2 < W) ta[r2] = cfma(pa, row[r2 * 64], ta[r2]);
+            }
         }
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -703,17 +714,28 @@ __global__ __launch_bounds__(64 * kFoldWaves, fold_waves_per_simd<WT>()) void re
         C ta[NV], tb[NV];
 #pragma unroll
         for (int r2 = 0; r2 < NV; ++r2) ta[r2] = tb[r2] = C{0, 0};
+        if (two) {  // (wave-uniform) both pairs from one read of each slab value
 #pragma unroll 1
-        for (int r1 = 0; r1 < W; ++r1) {
-            const C pa = to_c<C>(Pka[r1]), pbv = to_c<C>(Pkb[r1]);
-            const C* row = sT + r1 * W * 64 + cc;
+            for (int r1 = 0; r1 < W; ++r1) {
+                const C pa = to_c<C>(Pka[r1]), pbv = to_c<C>(Pkb[r1]);
+                const C* row = sT + r1 * W * 64 + cc;
 #pragma unroll
-            for (int r2 = 0; r2 < NV; ++r2)
-                if (r2 < W) {
-                    const C v = ld_vec(row + r2 * 64);
-                    ta[r2] = cfma(pa, v, ta[r2]);
-                    tb[r2] = cfma(pbv, v, tb[r2]);
-                }
+                for (int r2 = 0; r2 < NV; ++r2)
+                    if (r2 < W) {
+                        const C v = ld_vec(row + r2 * 64);
+                        ta[r2] = cfma(pa, v, ta[r2]);
+                        tb[r2] = cfma(pbv, v, tb[r2]);
+                    }
+            }
+        } else {  // the wave's last pair alone: no second set of products
+#pragma unroll 1
+            for (int r1 = 0; r1 < W; ++r1) {
+                const C pa = to_c<C>(Pka[r1]);
+                const C* row = sT + r1 * W * 64 + cc;
+#pragma unroll
+                for (int r2 = 0; r2 < NV; ++r2)
+                    if (r2 < W) ta[r2] = cfma(pa, ld_vec(row + r2 * 64), ta[r2]);
+            }
         }
         // this lane's G[k, Rp r, sa, a = li, b], folded into every state of row k:
         // F = sum over the 16 lanes of the row of conj(U_k[a, n]) G
