@@ -154,13 +154,15 @@ def _run_mesh(lib, s, k, mesh, precision="fp64", omega_min=1e-4):
 
 @pytest.mark.parametrize("nW,nat,r,mesh", [(5, 2, 2, (5, 4, 3)), (16, 5, 1, (3, 4, 5)),
                                            (9, 1, 2, (7, 1, 2)), (20, 2, 1, (4, 3, 3)),
-                                           (8, 6, 1, (3, 4, 3))])
+                                           (8, 6, 1, (3, 4, 3)), (1, 1, 1, (2, 3, 2)),
+                                           (6, 2, 1, (1, 4, 3))])
 def test_mesh_form_matches_oracle_and_list_form(lib, nW, nat, r, mesh):
     """The factorised sum over Rp on a full (ragged) q mesh against the oracle, and
     against the dense contraction of phoebe_gpu_interp_g on the same q points (the
     same bands and modes, so g itself agrees, not only |g|^2).  Up to 16 bands and 16
     modes the last axis and the rotation run in one kernel; 20 bands, or 18 modes,
-    take the two-kernel form."""
+    take the two-kernel form; one band, and a mesh of a single q0 plane, are the edge
+    cases of the fused kernel."""
     s = synth.small_system(60 + nW, n_wannier=nW, n_atoms=nat, r=r)
     rng = np.random.default_rng(nW)
     k = rng.uniform(-1, 1, size=(3, 3))
