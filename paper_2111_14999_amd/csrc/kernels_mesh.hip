@@ -1107,7 +1107,7 @@ constexpr int kTP = 2;  // column tiles per MFMA pass
 constexpr int kLineLW = 1, kLinePol = 2, kLineVel = 4;
 template <int FEAT, int H, bool F64, int NWV = 4>
 constexpr int line_waves_per_simd() {
-    if (NWV == 2) return 3;  // two waves per work-group: twice the tiles per wave
+    if (NWV == 2) return FEAT & kLinePol ? 2 : 3;  // two waves per work-group: twice the tiles per wave
     if (H == 2 && F64) return FEAT == 0 || FEAT == kLineLW ? 3 : 2;
     return FEAT == 0 || FEAT == kLineLW ? 4 : 3;
 }
@@ -1121,7 +1121,8 @@ constexpr int line_waves_per_simd() {
 // T2 per K step, 2.73 ms).  The plain rates of two and three tiles per wave take the
 // two-wave form as well (the batched plan of 32 systems: 137.9 -> 133.9 ms), and so do
 // the linewidth and adaptive-width variants (163 VGPRs; phonon linewidth 107 -> 101.5 ms,
-// adaptive rates 541 -> 478 ms per step); the polar variant would spill.
+// adaptive rates 541 -> 478 ms per step) and, at two waves per SIMD (181 VGPRs; four
+// pairs per CU against three), the polar one (3.29 -> 3.16 ms per launch).
 template <int TN, int KS, class C, int FEAT, int H = 1, int NWV = 4>
 __global__ __launch_bounds__(64 * NWV, (line_waves_per_simd<FEAT, H, sizeof(C) == sizeof(cd), NWV>())) void
 line_rates_kernel(RateArgs a) {
@@ -1587,6 +1588,7 @@ static hipError_t line_rates(const RateArgs& a, int nst, hipStream_t s) {
             if (pre && feat == 0) return go_line<8, 2, C, 0, 1, 2>(a, nst, s);
             if constexpr (sizeof(C) == sizeof(cd)) {
                 if (pre && feat == kLineLW) return go_line<8, 2, C, kLineLW, 1, 2>(a, nst, s);
+                if (pre && feat == kLinePol) return go_line<8, 2, C, kLinePol, 1, 2>(a, nst, s);
                 if (pre && feat == kLineVel) return go_line<8, 2, C, kLineVel, 1, 2>(a, nst, s);
             }
             return pre ? with_feat(integral_constant<int, 4>{}, integral_constant<int, 2>{})

@@ -207,12 +207,13 @@ def test_polar_coupling_mesh_form(lib):
 
 
 @pytest.mark.parametrize("form", ["direct", "factored"])
-@pytest.mark.parametrize("nW", [5, 20])
-def test_polar_rates_match_oracle(lib, form, nW):
-    """nW 20: the factorised form's two column tiles per mode (the overlap over both)."""
+@pytest.mark.parametrize("nW,nat", [(5, 2), (20, 2), (16, 5)])
+def test_polar_rates_match_oracle(lib, form, nW, nat):
+    """nW 20: the factorised form's two column tiles per mode (the overlap over both);
+    nW 16 with 15 modes: the two-wave, eight-tile form of the line kernel."""
     torch = torch_cuda()
     from paper_2111_14999_amd import DeviceSystem
-    s = _polar_system(93, nW=nW, nat=2)
+    s = _polar_system(93, nW=nW, nat=nat)
     mesh = (3, 4, 4)
     t, par = _params(s, mesh)
     ref = rates.scattering_rates(s, mesh, tables=t, **par)
@@ -232,7 +233,7 @@ def test_polar_rates_match_oracle(lib, form, nW):
     refP = linewidth.phonon_linewidth(s, mesh, tables=t, **par)["P"]
     mp, _, _ = rel_err(P.cpu().numpy(), refP)
     # the polar term matters here: the rates without it differ
-    s0 = synth.small_system(93, n_wannier=nW, n_atoms=2, r=1)
+    s0 = synth.small_system(93, n_wannier=nW, n_atoms=nat, r=1)
     s0.h_r *= 0.3
     plain = rates.scattering_rates(s0, mesh, tables=t, **par)["gamma"]
     diff, _, _ = rel_err(plain, ref["gamma"])
