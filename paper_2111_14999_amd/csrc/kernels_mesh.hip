@@ -1122,7 +1122,9 @@ constexpr int line_waves_per_simd() {
 // two-wave form as well (the batched plan of 32 systems: 137.9 -> 133.9 ms), and so do
 // the linewidth and adaptive-width variants (163 VGPRs; phonon linewidth 107 -> 101.5 ms,
 // adaptive rates 541 -> 478 ms per step) and, at two waves per SIMD (181 VGPRs; four
-// pairs per CU against three), the polar one (3.29 -> 3.16 ms per launch).
+// pairs per CU against three), the polar one (3.29 -> 3.16 ms per launch); with two
+// tiles per mode (16 < nW <= 32) the plain rates of one and two modes per wave, the
+// latter in FP32 (batched plan 133.4 -> 132.1 ms).
 template <int TN, int KS, class C, int FEAT, int H = 1, int NWV = 4>
 __global__ __launch_bounds__(64 * NWV, (line_waves_per_simd<FEAT, H, sizeof(C) == sizeof(cd), NWV>())) void
 line_rates_kernel(RateArgs a) {
@@ -1561,10 +1563,15 @@ static hipError_t line_rates(const RateArgs& a, int nst, hipStream_t s) {
             }
         };
         switch (a.nc_pad / 64) {
-            case 2: return pre ? with_feat2(integral_constant<int, 2>{}, integral_constant<int, 2>{})
-                               : with_feat2(integral_constant<int, 2>{}, integral_constant<int, 0>{});
-            case 4: return pre ? with_feat2(integral_constant<int, 4>{}, integral_constant<int, 2>{})
-                               : with_feat2(integral_constant<int, 4>{}, integral_constant<int, 0>{});
+            case 2:
+                if (pre && feat == 0) return go_line<4, 2, C, 0, 2, 2>(a, nst, s);
+                return pre ? with_feat2(integral_constant<int, 2>{}, integral_constant<int, 2>{})
+                           : with_feat2(integral_constant<int, 2>{}, integral_constant<int, 0>{});
+            case 4:
+                // (FP32 only: the FP64 form would spill)
+                if (pre && feat == 0 && sizeof(C) == sizeof(cf)) return go_line<8, 2, C, 0, 2, 2>(a, nst, s);
+                return pre ? with_feat2(integral_constant<int, 4>{}, integral_constant<int, 2>{})
+                           : with_feat2(integral_constant<int, 4>{}, integral_constant<int, 0>{});
             case 6: return with_feat2(integral_constant<int, 6>{}, integral_constant<int, 0>{});
             case 8: return with_feat2(integral_constant<int, 8>{}, integral_constant<int, 0>{});
             case 12: return with_feat2(integral_constant<int, 12>{}, integral_constant<int, 0>{});
