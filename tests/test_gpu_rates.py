@@ -191,13 +191,14 @@ def _sparse_re(s, seed, keep_frac):
 
 @pytest.mark.parametrize("case", ["toy", "ragged-5x6x7", "sparse-rp", "sparse-re", "c2-tiling",
                                   "single-line", "nW16-sparse-re", "axis0-70", "rp-box-9",
-                                  "18-modes", "nW20-15-modes", "nW32-3-modes", "nW18-30-modes",
-                                  "nW17-sparse-rp"])
+                                  "18-modes", "30-modes", "nW20-15-modes", "nW32-3-modes",
+                                  "nW18-30-modes", "nW17-sparse-rp"])
 def test_mesh_sum_forms_match_oracle(lib, toy, case):
     """Both full-mesh forms against the oracle.  "axis0-70", "rp-box-9" and "18-modes"
     take the line kernel's general path: more than 64 points on axis 0 (point lists in
-    LDS, two ballot chunks), an Rp box 9 wide (T2 read per K step, three K steps) and 18
-    modes (six column tiles per wave, term items beyond one per thread).  The nW > 16
+    LDS, two ballot chunks), an Rp box 9 wide (T2 read per K step, three K steps), 18
+    modes (twelve column tiles per wave in two-wave work-groups, term items beyond one per
+    thread) and 30 modes (sixteen tiles per wave).  The nW > 16
     cases take its two-tiles-per-mode form (columns sa*32 + b): 15 modes (eight tiles
     per wave), 3 modes (two tiles, most of the waves' modes beyond nModes), 30 modes
     (sixteen tiles per wave) and 17 bands with a sparse Rp list (a half-empty second
@@ -224,6 +225,8 @@ def test_mesh_sum_forms_match_oracle(lib, toy, case):
         elif case == "18-modes":
             s, mesh = synth.small_system(80, n_wannier=4, n_atoms=6, r=1), (4, 3, 2)
             assert 3 * s.mass.shape[0] == 18
+        elif case == "30-modes":
+            s, mesh = synth.small_system(90, n_wannier=4, n_atoms=10, r=1), (3, 2, 3)
         elif case == "nW20-15-modes":
             s, mesh = synth.small_system(86, n_wannier=20, n_atoms=5, r=1), (5, 4, 3)
         elif case == "nW32-3-modes":
