@@ -1126,7 +1126,7 @@ constexpr int line_waves_per_simd() {
 // tiles per mode (16 < nW <= 32) the plain rates of one and two modes per wave, the
 // latter in FP32 (batched plan 133.4 -> 132.1 ms); and the plain rates of six and eight
 // tiles per wave, whose T2 is read per K step (12 and 16 tiles in two waves: 132.1 ->
-// 129.9 ms).
+// 129.9 ms), with one or two tiles per mode (-> 128.6 ms).
 template <int TN, int KS, class C, int FEAT, int H = 1, int NWV = 4>
 __global__ __launch_bounds__(64 * NWV, (line_waves_per_simd<FEAT, H, sizeof(C) == sizeof(cd), NWV>())) void
 line_rates_kernel(RateArgs a) {
@@ -1574,8 +1574,12 @@ static hipError_t line_rates(const RateArgs& a, int nst, hipStream_t s) {
                 if (pre && feat == 0 && sizeof(C) == sizeof(cf)) return go_line<8, 2, C, 0, 2, 2>(a, nst, s);
                 return pre ? with_feat2(integral_constant<int, 4>{}, integral_constant<int, 2>{})
                            : with_feat2(integral_constant<int, 4>{}, integral_constant<int, 0>{});
-            case 6: return with_feat2(integral_constant<int, 6>{}, integral_constant<int, 0>{});
-            case 8: return with_feat2(integral_constant<int, 8>{}, integral_constant<int, 0>{});
+            case 6:
+                if (feat == 0) return go_line<12, 0, C, 0, 2, 2>(a, nst, s);
+                return with_feat2(integral_constant<int, 6>{}, integral_constant<int, 0>{});
+            case 8:
+                if (feat == 0) return go_line<16, 0, C, 0, 2, 2>(a, nst, s);
+                return with_feat2(integral_constant<int, 8>{}, integral_constant<int, 0>{});
             case 12: return with_feat2(integral_constant<int, 12>{}, integral_constant<int, 0>{});
             case 16: return with_feat2(integral_constant<int, 16>{}, integral_constant<int, 0>{});
             default: return hipErrorInvalidValue;
